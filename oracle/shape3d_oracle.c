@@ -1,0 +1,788 @@
+/*
+ * shape3d_oracle.c -- plain CPU FP64 oracle for the 3D shape-feature path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file's library.  The product
+ * (the HIP library under paper_2510_02894_amd/) never links, calls or reads
+ * anything here, and nothing here reads the product's marching-cubes table:
+ * the per-cube surface is traced from its definition at run time.
+ *
+ * What is computed (paper, Sec. 2 "PyRadiomics-cuda design" and the
+ * "Marching cubes fused parallel kernels" / "Parallel diameter calculation"
+ * paragraphs): a marching-cubes surface of the region of interest, its
+ * surface area and signed-tetrahedron mesh volume, the maximum 3D distance
+ * between mesh vertices and the maximum distance between vertices that share
+ * a plane of each of the three axis-aligned families (the planar diameters).
+ * The method reaches the plain definitions below exactly, so each function
+ * is the definition written out, in FP64, with no blocking or reordering.
+ *
+ * Conventions (readings where the paper is silent; listed in the design notes):
+ *   - volume is C-contiguous with shape (d0, d1, d2); spacing (s0, s1, s2) in
+ *     the same axis order; positions are index * spacing (physical units);
+ *   - voxels outside the array are outside the region (one-voxel zero pad);
+ *   - uint8 input: inside iff value != 0, vertices at edge midpoints;
+ *     float32 input ("soft" mask): inside iff p > 0.5, vertices linearly
+ *     interpolated at the 0.5 level, t = (0.5 - p_u) / (p_b - p_u);
+ *   - one vertex per grid edge (u, u + e_a) whose end points differ in the
+ *     inside test; id = 3 * lin_pad(u) + a with
+ *     lin_pad(u) = ((u0+1)*(d1+2) + (u1+1))*(d2+2) + (u2+1);
+ *   - per-cube surface: faces with two crossings get one segment, faces with
+ *     four crossings (diagonal corners inside) get two segments each cutting
+ *     off one inside corner; segments are oriented so the inside lies on a
+ *     fixed side, chained into loops, and each loop is fan-triangulated from
+ *     its vertex with the smallest cube-edge number, normals pointing from
+ *     inside to outside;
+ *   - MeshVolume = |sum over triangles of a.(b x c) / 6|;
+ *   - planar diameters: vertices share a plane of axis k iff
+ *     key_k = 2*u_k + [a == k] is equal (the plane's coordinate in half
+ *     voxels); Slice = axis 0, Column = axis 1, Row = axis 2;
+ *   - ties of the maximum distance: the pair with the lexicographically
+ *     smallest (id_i, id_j), id_i < id_j.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_EMPTY 1
+#define OR_EINVAL (-1)
+#define OR_ECAPACITY (-4)
+#define OR_ENOMEM (-5)
+#define OR_EINTERNAL (-6)
+
+#define OR_U8 0
+#define OR_F32 1
+
+typedef struct {
+  const void* vol;
+  int dtype;
+  int64_t d[3];
+  double s[3];
+} grid_t;
+
+static int grid_init(grid_t* g, const void* vol, int dtype, const int64_t dims[3],
+                     const double spacing[3]) {
+  if (!vol || !dims || !spacing) return OR_EINVAL;
+  if (dtype != OR_U8 && dtype != OR_F32) return OR_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    if (dims[k] <= 0 || dims[k] > (1 << 20) - 3) return OR_EINVAL;
+    if (!(spacing[k] > 0.0) || !isfinite(spacing[k])) return OR_EINVAL;
+    g->d[k] = dims[k];
+    g->s[k] = spacing[k];
+  }
+  g->vol = vol;
+  g->dtype = dtype;
+  return OR_OK;
+}
+
+static int in_range(const grid_t* g, const int64_t u[3]) {
+  return u[0] >= 0 && u[1] >= 0 && u[2] >= 0 && u[0] < g->d[0] && u[1] < g->d[1] &&
+         u[2] < g->d[2];
+}
+
+static int64_t lin(const grid_t* g, const int64_t u[3]) {
+  return (u[0] * g->d[1] + u[1]) * g->d[2] + u[2];
+}
+
+/* Inside test with the implicit zero pad. */
+static int inside_at(const grid_t* g, const int64_t u[3]) {
+  if (!in_range(g, u)) return 0;
+  if (g->dtype == OR_U8) return ((const uint8_t*)g->vol)[lin(g, u)] != 0;
+  return ((const float*)g->vol)[lin(g, u)] > 0.5f;
+}
+
+/* Probability value (soft input only); 0 in the pad. */
+static double value_at(const grid_t* g, const int64_t u[3]) {
+  if (!in_range(g, u)) return 0.0;
+  return (double)((const float*)g->vol)[lin(g, u)];
+}
+
+static int64_t vertex_id(const grid_t* g, const int64_t u[3], int a) {
+  int64_t l = ((u[0] + 1) * (g->d[1] + 2) + (u[1] + 1)) * (g->d[2] + 2) + (u[2] + 1);
+  return 3 * l + a;
+}
+
+static void decode_id(const grid_t* g, int64_t id, int64_t u[3], int* a) {
+  *a = (int)(id % 3);
+  int64_t l = id / 3;
+  u[2] = l % (g->d[2] + 2) - 1;
+  l /= (g->d[2] + 2);
+  u[1] = l % (g->d[1] + 2) - 1;
+  u[0] = l / (g->d[1] + 2) - 1;
+}
+
+/* Interpolation parameter of the vertex on edge (u, u + e_a). */
+static double edge_t(const grid_t* g, const int64_t u[3], int a) {
+  if (g->dtype == OR_U8) return 0.5;
+  int64_t v[3] = {u[0], u[1], u[2]};
+  v[a] += 1;
+  double pa = value_at(g, u), pb = value_at(g, v);
+  return (0.5 - pa) / (pb - pa);
+}
+
+/* Physical position of the vertex on edge (u, u + e_a) with parameter t. */
+static void edge_pos(const grid_t* g, const int64_t u[3], int a, double t, double x[3]) {
+  for (int k = 0; k < 3; ++k) x[k] = ((double)u[k] + (k == a ? t : 0.0)) * g->s[k];
+}
+
+static int edge_crosses(const grid_t* g, const int64_t u[3], int a) {
+  int64_t v[3] = {u[0], u[1], u[2]};
+  v[a] += 1;
+  return inside_at(g, u) != inside_at(g, v);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neumaier-compensated summation.                                           */
+typedef struct {
+  double s, c;
+} ksum_t;
+
+static void kadd(ksum_t* k, double x) {
+  double t = k->s + x;
+  if (fabs(k->s) >= fabs(x))
+    k->c += (k->s - t) + x;
+  else
+    k->c += (x - t) + k->s;
+  k->s = t;
+}
+
+static double kval(const ksum_t* k) { return k->s + k->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Per-cube surface, traced from its definition.                              */
+/* Corner c has offset ((c>>2)&1, (c>>1)&1, c&1) along axes (0, 1, 2).        */
+/* Cube edge e = 4*a + 2*o_b + o_c runs along axis a from the corner whose    */
+/* bit a is clear; b < c are the other two axes, o_b and o_c their offsets.   */
+
+static int corner_of(const int o[3]) { return (o[0] << 2) | (o[1] << 1) | o[2]; }
+
+static void edge_ends(int e, int* a, int* c0, int* c1) {
+  int ax = e / 4, ob = (e % 4) >> 1, oc = e & 1;
+  int b = (ax == 0) ? 1 : 0;
+  int c = (ax == 2) ? 1 : 2;
+  int o[3] = {0, 0, 0};
+  o[b] = ob;
+  o[c] = oc;
+  *c0 = corner_of(o);
+  o[ax] = 1;
+  *c1 = corner_of(o);
+  *a = ax;
+}
+
+static int edge_between(int ca, int cb) {
+  for (int e = 0; e < 12; ++e) {
+    int a, c0, c1;
+    edge_ends(e, &a, &c0, &c1);
+    if ((c0 == ca && c1 == cb) || (c0 == cb && c1 == ca)) return e;
+  }
+  return -1;
+}
+
+static void corner_pos(int c, double p[3]) {
+  p[0] = (c >> 2) & 1;
+  p[1] = (c >> 1) & 1;
+  p[2] = c & 1;
+}
+
+static void edge_mid(int e, double p[3]) {
+  int a, c0, c1;
+  edge_ends(e, &a, &c0, &c1);
+  corner_pos(c0, p);
+  p[a] = 0.5;
+}
+
+static void cross3(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Add the directed segment on a face of outward normal m that separates
+   inside corner `ic` from the outside corners: orient P -> Q so that
+   (m x (Q - P)) . (I - P) < 0.  Returns nonzero on an inconsistency. */
+static int add_segment(int next[12], int e1, int e2, int ic, const double m[3]) {
+  double P[3], Q[3], I[3], d[3], w[3], r[3];
+  edge_mid(e1, P);
+  edge_mid(e2, Q);
+  corner_pos(ic, I);
+  for (int k = 0; k < 3; ++k) {
+    d[k] = Q[k] - P[k];
+    w[k] = I[k] - P[k];
+  }
+  cross3(m, d, r);
+  double s = dot3(r, w);
+  if (s == 0.0) return 1;
+  int from = e1, to = e2;
+  if (s > 0.0) {
+    from = e2;
+    to = e1;
+  }
+  if (next[from] != -1) return 1;
+  next[from] = to;
+  return 0;
+}
+
+/* Triangles of one cube case, as triples of cube-edge numbers.  Returns the
+   number of triangles, or -1 if the traced segments do not close into loops. */
+static int trace_cube(int cas, int tri[][3]) {
+  int next[12];
+  for (int e = 0; e < 12; ++e) next[e] = -1;
+  static const int og[4] = {0, 1, 1, 0}, oh[4] = {0, 0, 1, 1};
+  for (int f = 0; f < 3; ++f) {
+    int gax = (f == 0) ? 1 : 0;
+    int hax = (f == 2) ? 1 : 2;
+    for (int sg = 0; sg < 2; ++sg) {
+      double m[3] = {0.0, 0.0, 0.0};
+      m[f] = sg ? 1.0 : -1.0;
+      int fc[4], in[4], fe[4], cr[4], n = 0;
+      for (int k = 0; k < 4; ++k) {
+        int o[3];
+        o[f] = sg;
+        o[gax] = og[k];
+        o[hax] = oh[k];
+        fc[k] = corner_of(o);
+        in[k] = (cas >> fc[k]) & 1;
+      }
+      for (int k = 0; k < 4; ++k) {
+        fe[k] = edge_between(fc[k], fc[(k + 1) % 4]);
+        cr[k] = in[k] != in[(k + 1) % 4];
+        n += cr[k];
+      }
+      if (n == 2) {
+        int e1 = -1, e2 = -1, ic = -1;
+        for (int k = 0; k < 4; ++k) {
+          if (cr[k]) {
+            if (e1 < 0)
+              e1 = fe[k];
+            else
+              e2 = fe[k];
+          }
+          if (in[k] && ic < 0) ic = fc[k];
+        }
+        if (add_segment(next, e1, e2, ic, m)) return -1;
+      } else if (n == 4) {
+        for (int k = 0; k < 4; ++k)
+          if (in[k] && add_segment(next, fe[(k + 3) % 4], fe[k], fc[k], m)) return -1;
+      } else if (n != 0) {
+        return -1;
+      }
+    }
+  }
+  /* Each crossing edge must have exactly one successor and one predecessor. */
+  int indeg[12] = {0};
+  for (int e = 0; e < 12; ++e)
+    if (next[e] >= 0) indeg[next[e]]++;
+  for (int e = 0; e < 12; ++e) {
+    int a, c0, c1;
+    edge_ends(e, &a, &c0, &c1);
+    int crossing = ((cas >> c0) & 1) != ((cas >> c1) & 1);
+    if (crossing != (next[e] >= 0) || crossing != (indeg[e] == 1)) return -1;
+  }
+  /* Loops, each started at its smallest edge (edges are visited in order). */
+  int seen[12] = {0}, nt = 0;
+  for (int e = 0; e < 12; ++e) {
+    if (next[e] < 0 || seen[e]) continue;
+    int loop[12], len = 0, cur = e;
+    do {
+      if (len >= 12) return -1;
+      loop[len++] = cur;
+      seen[cur] = 1;
+      cur = next[cur];
+    } while (cur != e);
+    for (int i = 1; i + 1 < len; ++i) {
+      tri[nt][0] = loop[0];
+      tri[nt][1] = loop[i];
+      tri[nt][2] = loop[i + 1];
+      nt++;
+    }
+  }
+  return nt;
+}
+
+/* Per-case cache filled from trace_cube (the oracle's own tracer). */
+static int g_case_ready = 0;
+static int g_case_nt[256];
+static int g_case_tri[256][16][3];
+
+static int case_cache_init(void) {
+  if (g_case_ready) return OR_OK;
+  for (int c = 0; c < 256; ++c) {
+    int nt = trace_cube(c, g_case_tri[c]);
+    if (nt < 0) return OR_EINTERNAL;
+    g_case_nt[c] = nt;
+  }
+  g_case_ready = 1;
+  return OR_OK;
+}
+
+/* Exported: the triangles the oracle traces for one cube case. */
+int oracle_cube_triangles(int cas, int* tri_edges, int* n_tri) {
+  if (cas < 0 || cas > 255 || !tri_edges || !n_tri) return OR_EINVAL;
+  int tri[16][3];
+  int nt = trace_cube(cas, tri);
+  if (nt < 0) return OR_EINTERNAL;
+  for (int i = 0; i < nt; ++i)
+    for (int k = 0; k < 3; ++k) tri_edges[3 * i + k] = tri[i][k];
+  *n_tri = nt;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vertices.                                                                 */
+
+int oracle_count_vertices(const void* vol, int dtype, const int64_t dims[3],
+                          const double spacing[3], int64_t* n_out) {
+  grid_t g;
+  int st = grid_init(&g, vol, dtype, dims, spacing);
+  if (st) return st;
+  int64_t n = 0;
+  int64_t u[3];
+  for (u[0] = -1; u[0] < g.d[0]; ++u[0])
+    for (u[1] = -1; u[1] < g.d[1]; ++u[1])
+      for (u[2] = -1; u[2] < g.d[2]; ++u[2])
+        for (int a = 0; a < 3; ++a) n += edge_crosses(&g, u, a);
+  *n_out = n;
+  return OR_OK;
+}
+
+/* Vertex list in ascending id order: ids, positions (n*3) and, if t_out is
+   not NULL, interpolation parameters. */
+int oracle_vertices(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                    int64_t cap, int64_t* ids, double* pos, double* t_out, int64_t* n_out) {
+  grid_t g;
+  int st = grid_init(&g, vol, dtype, dims, spacing);
+  if (st) return st;
+  int64_t n = 0;
+  int64_t u[3];
+  for (u[0] = -1; u[0] < g.d[0]; ++u[0])
+    for (u[1] = -1; u[1] < g.d[1]; ++u[1])
+      for (u[2] = -1; u[2] < g.d[2]; ++u[2])
+        for (int a = 0; a < 3; ++a) {
+          if (!edge_crosses(&g, u, a)) continue;
+          if (n < cap) {
+            double t = edge_t(&g, u, a);
+            if (ids) ids[n] = vertex_id(&g, u, a);
+            if (pos) edge_pos(&g, u, a, t, pos + 3 * n);
+            if (t_out) t_out[n] = t;
+          }
+          n++;
+        }
+  *n_out = n;
+  return n > cap ? OR_ECAPACITY : OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh: area and signed volume.                                             */
+
+/* Vertex of cube-edge e of the cube with min corner cu. */
+static void cube_edge_vertex(const grid_t* g, const int64_t cu[3], int e, double x[3],
+                             int64_t* id) {
+  int a, c0, c1;
+  edge_ends(e, &a, &c0, &c1);
+  int64_t u[3] = {cu[0] + ((c0 >> 2) & 1), cu[1] + ((c0 >> 1) & 1), cu[2] + (c0 & 1)};
+  edge_pos(g, u, a, edge_t(g, u, a), x);
+  if (id) *id = vertex_id(g, u, a);
+}
+
+static int cube_case(const grid_t* g, const int64_t cu[3]) {
+  int cas = 0;
+  for (int c = 0; c < 8; ++c) {
+    int64_t v[3] = {cu[0] + ((c >> 2) & 1), cu[1] + ((c >> 1) & 1), cu[2] + (c & 1)};
+    cas |= inside_at(g, v) << c;
+  }
+  return cas;
+}
+
+/* Surface area, signed volume (tetrahedra against `origin`), triangle count,
+   and optionally the triangles as vertex-id triples. */
+int oracle_mesh(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                const double origin[3], double* area, double* signed_volume, int64_t* n_tri,
+                int64_t tri_cap, int64_t* tri_ids) {
+  grid_t g;
+  int st = grid_init(&g, vol, dtype, dims, spacing);
+  if (st) return st;
+  if ((st = case_cache_init())) return st;
+  ksum_t ka = {0, 0}, kv = {0, 0};
+  int64_t nt = 0;
+  int64_t cu[3];
+  for (cu[0] = -1; cu[0] < g.d[0]; ++cu[0])
+    for (cu[1] = -1; cu[1] < g.d[1]; ++cu[1])
+      for (cu[2] = -1; cu[2] < g.d[2]; ++cu[2]) {
+        int cas = cube_case(&g, cu);
+        if (cas == 0 || cas == 255) continue;
+        for (int i = 0; i < g_case_nt[cas]; ++i) {
+          double P[3][3];
+          int64_t id[3];
+          for (int k = 0; k < 3; ++k) cube_edge_vertex(&g, cu, g_case_tri[cas][i][k], P[k], &id[k]);
+          double e1[3], e2[3], n[3], a[3], b[3], c[3], bc[3];
+          for (int k = 0; k < 3; ++k) {
+            e1[k] = P[1][k] - P[0][k];
+            e2[k] = P[2][k] - P[0][k];
+            a[k] = P[0][k] - origin[k];
+            b[k] = P[1][k] - origin[k];
+            c[k] = P[2][k] - origin[k];
+          }
+          cross3(e1, e2, n);
+          kadd(&ka, 0.5 * sqrt(dot3(n, n)));
+          cross3(b, c, bc);
+          kadd(&kv, dot3(a, bc) / 6.0);
+          if (tri_ids && nt < tri_cap)
+            for (int k = 0; k < 3; ++k) tri_ids[3 * nt + k] = id[k];
+          nt++;
+        }
+      }
+  *area = kval(&ka);
+  *signed_volume = kval(&kv);
+  *n_tri = nt;
+  return (tri_ids && nt > tri_cap) ? OR_ECAPACITY : OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diameters.                                                                */
+
+static double dist2(const double* p, const double* q) {
+  double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+typedef struct {
+  double d2;
+  int64_t i, j;
+} best_t;
+
+/* Larger d2 wins; equal d2: lexicographically smaller (i, j). */
+static int better(const best_t* x, const best_t* y) {
+  if (x->d2 != y->d2) return x->d2 > y->d2;
+  if (x->i != y->i) return x->i < y->i;
+  return x->j < y->j;
+}
+
+/* Maximum squared distance over pairs (idx[i], idx[j]), i < j, of an index list
+   whose order is ascending id; returns indices into pos. */
+static best_t max_pair(const double* pos, const int64_t* idx, int64_t n) {
+  best_t best = {-1.0, -1, -1};
+#pragma omp parallel
+  {
+    best_t mine = {-1.0, -1, -1};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+      const double* p = pos + 3 * idx[i];
+      for (int64_t j = i + 1; j < n; ++j) {
+        double d2 = dist2(p, pos + 3 * idx[j]);
+        if (d2 > mine.d2 || (d2 == mine.d2 && (idx[i] < mine.i || (idx[i] == mine.i && idx[j] < mine.j)))) {
+          mine.d2 = d2;
+          mine.i = idx[i];
+          mine.j = idx[j];
+        }
+      }
+    }
+#pragma omp critical
+    {
+      if (mine.i >= 0 && (best.i < 0 || better(&mine, &best))) best = mine;
+    }
+  }
+  return best;
+}
+
+/* d2_out[0] = max squared 3D distance, d2_out[1 + k] = max squared distance
+   between vertices with equal key_k.  pair_idx[2f], pair_idx[2f+1] = indices
+   (into the vertex list) of the maximising pair of feature f, -1 if none.
+   Vertices must be in ascending id order (as oracle_vertices returns them). */
+int oracle_diameters(const int64_t* ids, const double* pos, int64_t n, const int64_t dims[3],
+                     double d2_out[4], int64_t pair_idx[8]) {
+  if ((!ids || !pos) && n > 0) return OR_EINVAL;
+  grid_t g;
+  double unit[3] = {1.0, 1.0, 1.0};
+  uint8_t dummy = 0;
+  int st = grid_init(&g, &dummy, OR_U8, dims, unit);
+  if (st) return st;
+  for (int f = 0; f < 4; ++f) {
+    d2_out[f] = 0.0;
+    pair_idx[2 * f] = pair_idx[2 * f + 1] = -1;
+  }
+  if (n < 2) return OR_OK;
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* key = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!idx || !key) {
+    free(idx);
+    free(key);
+    return OR_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) idx[i] = i;
+  best_t b = max_pair(pos, idx, n);
+  d2_out[0] = b.d2;
+  pair_idx[0] = b.i;
+  pair_idx[1] = b.j;
+  for (int k = 0; k < 3; ++k) {
+    /* Stable counting sort by plane key (vertices are already in id order). */
+    int64_t nb = 2 * g.d[k] + 1;
+    int64_t* cnt = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
+    if (!cnt) {
+      free(idx);
+      free(key);
+      return OR_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t u[3];
+      int a;
+      decode_id(&g, ids[i], u, &a);
+      key[i] = 2 * u[k] + (a == k) + 1; /* in [0, 2*d_k] */
+      cnt[key[i] + 1]++;
+    }
+    for (int64_t q = 0; q < nb; ++q) cnt[q + 1] += cnt[q];
+    int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+    if (!cur) {
+      free(cnt);
+      free(idx);
+      free(key);
+      return OR_ENOMEM;
+    }
+    memcpy(cur, cnt, sizeof(int64_t) * (size_t)nb);
+    for (int64_t i = 0; i < n; ++i) idx[cur[key[i]]++] = i;
+    best_t bk = {-1.0, -1, -1};
+    for (int64_t q = 0; q < nb; ++q) {
+      int64_t m = cnt[q + 1] - cnt[q];
+      if (m < 2) continue;
+      best_t bq = max_pair(pos, idx + cnt[q], m);
+      if (bk.i < 0 || better(&bq, &bk)) bk = bq;
+    }
+    if (bk.i >= 0) {
+      d2_out[1 + k] = bk.d2;
+      pair_idx[2 + 2 * k] = bk.i;
+      pair_idx[3 + 2 * k] = bk.j;
+    }
+    free(cur);
+    free(cnt);
+  }
+  free(idx);
+  free(key);
+  return OR_OK;
+}
+
+/* Bounded sample for CPU timing: max squared distance over pairs (i, j) with
+   i in [i0, i1) and j in (i, n). */
+int oracle_max_pair_rows(const double* pos, int64_t n, int64_t i0, int64_t i1, double* best_d2,
+                         int* threads_used) {
+  if (!pos || !best_d2 || i0 < 0 || i1 > n || i0 > i1) return OR_EINVAL;
+  double best = 0.0;
+  int nth = 1;
+#pragma omp parallel reduction(max : best)
+  {
+#ifdef _OPENMP
+#pragma omp single
+    nth = omp_get_num_threads();
+#endif
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t i = i0; i < i1; ++i)
+      for (int64_t j = i + 1; j < n; ++j) {
+        double d2 = dist2(pos + 3 * i, pos + 3 * j);
+        if (d2 > best) best = d2;
+      }
+  }
+  *best_d2 = best;
+  if (threads_used) *threads_used = nth;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* All six features.                                                         */
+
+/* out = {MeshVolume, SurfaceArea, Maximum3DDiameter, Maximum2DDiameterSlice,
+          Maximum2DDiameterColumn, Maximum2DDiameterRow};
+   counts = {V, T}; pair_ids = canonical ids of the maximising pairs (-1 if none);
+   signed_volume_out (optional) = the signed sum before the absolute value. */
+int oracle_shape3d(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                   double out[6], int64_t counts[2], int64_t pair_ids[8],
+                   double* signed_volume_out) {
+  grid_t g;
+  int st = grid_init(&g, vol, dtype, dims, spacing);
+  if (st) return st;
+  int64_t n = 0;
+  if ((st = oracle_count_vertices(vol, dtype, dims, spacing, &n))) return st;
+  for (int f = 0; f < 6; ++f) out[f] = 0.0;
+  for (int f = 0; f < 8; ++f) pair_ids[f] = -1;
+  counts[0] = n;
+  counts[1] = 0;
+  if (signed_volume_out) *signed_volume_out = 0.0;
+  if (n == 0) return OR_EMPTY;
+  int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  double* pos = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  if (!ids || !pos) {
+    free(ids);
+    free(pos);
+    return OR_ENOMEM;
+  }
+  int64_t n2 = 0;
+  st = oracle_vertices(vol, dtype, dims, spacing, n, ids, pos, NULL, &n2);
+  if (st) {
+    free(ids);
+    free(pos);
+    return st;
+  }
+  double origin[3];
+  for (int k = 0; k < 3; ++k) origin[k] = 0.5 * (double)g.d[k] * g.s[k];
+  double area = 0.0, sv = 0.0;
+  int64_t nt = 0;
+  st = oracle_mesh(vol, dtype, dims, spacing, origin, &area, &sv, &nt, 0, NULL);
+  if (st) {
+    free(ids);
+    free(pos);
+    return st;
+  }
+  double d2[4];
+  int64_t pidx[8];
+  st = oracle_diameters(ids, pos, n, dims, d2, pidx);
+  if (st) {
+    free(ids);
+    free(pos);
+    return st;
+  }
+  out[0] = fabs(sv);
+  out[1] = area;
+  for (int f = 0; f < 4; ++f) out[2 + f] = sqrt(d2[f]);
+  for (int f = 0; f < 8; ++f) pair_ids[f] = pidx[f] >= 0 ? ids[pidx[f]] : -1;
+  counts[1] = nt;
+  if (signed_volume_out) *signed_volume_out = sv;
+  free(ids);
+  free(pos);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reference gradient of L = sum_f g_f F_f with respect to a soft mask.      */
+
+static int64_t find_id(const int64_t* ids, int64_t n, int64_t id) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (ids[mid] < id)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < n && ids[lo] == id) ? lo : -1;
+}
+
+/* grad_p (d0*d1*d2 doubles) = dL/dp.  If pair_ids_in is not NULL it gives the
+   canonical ids of the maximising pair of each diameter (8 entries, -1 for
+   none) and is used instead of the oracle's own tie-break. */
+int oracle_soft_grad(const float* p, const int64_t dims[3], const double spacing[3],
+                     const double gout[6], const int64_t* pair_ids_in, double* grad_p) {
+  grid_t g;
+  int st = grid_init(&g, p, OR_F32, dims, spacing);
+  if (st) return st;
+  if (!gout || !grad_p) return OR_EINVAL;
+  if ((st = case_cache_init())) return st;
+  int64_t N = g.d[0] * g.d[1] * g.d[2];
+  for (int64_t i = 0; i < N; ++i) grad_p[i] = 0.0;
+  double out[6], sv;
+  int64_t counts[2], pairs[8];
+  st = oracle_shape3d(p, OR_F32, dims, spacing, out, counts, pairs, &sv);
+  if (st == OR_EMPTY) return OR_OK;
+  if (st) return st;
+  if (pair_ids_in)
+    for (int f = 0; f < 8; ++f) pairs[f] = pair_ids_in[f];
+  int64_t n = counts[0];
+  int64_t* ids = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  double* pos = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+  double* tv = (double*)malloc(sizeof(double) * (size_t)n);
+  double* gx = (double*)calloc(3 * (size_t)n, sizeof(double));
+  if (!ids || !pos || !tv || !gx) {
+    free(ids);
+    free(pos);
+    free(tv);
+    free(gx);
+    return OR_ENOMEM;
+  }
+  int64_t n2;
+  oracle_vertices(p, OR_F32, dims, spacing, n, ids, pos, tv, &n2);
+  double origin[3];
+  for (int k = 0; k < 3; ++k) origin[k] = 0.5 * (double)g.d[k] * g.s[k];
+  double sgn = sv >= 0.0 ? 1.0 : -1.0;
+  /* Area and volume: per triangle, add the partial derivatives to its vertices. */
+  int64_t cu[3];
+  for (cu[0] = -1; cu[0] < g.d[0]; ++cu[0])
+    for (cu[1] = -1; cu[1] < g.d[1]; ++cu[1])
+      for (cu[2] = -1; cu[2] < g.d[2]; ++cu[2]) {
+        int cas = cube_case(&g, cu);
+        if (cas == 0 || cas == 255) continue;
+        for (int i = 0; i < g_case_nt[cas]; ++i) {
+          double P[3][3];
+          int64_t id[3], vi[3];
+          for (int k = 0; k < 3; ++k) {
+            cube_edge_vertex(&g, cu, g_case_tri[cas][i][k], P[k], &id[k]);
+            vi[k] = find_id(ids, n, id[k]);
+          }
+          double e1[3], e2[3], nrm[3];
+          for (int k = 0; k < 3; ++k) {
+            e1[k] = P[1][k] - P[0][k];
+            e2[k] = P[2][k] - P[0][k];
+          }
+          cross3(e1, e2, nrm);
+          double len = sqrt(dot3(nrm, nrm));
+          for (int v = 0; v < 3; ++v) {
+            const double* A = P[v];
+            const double* B = P[(v + 1) % 3];
+            const double* C = P[(v + 2) % 3];
+            double ga[3] = {0, 0, 0};
+            if (len > 0.0) {
+              /* dArea_T/dA = 1/2 nhat x (C - B) */
+              double nh[3] = {nrm[0] / len, nrm[1] / len, nrm[2] / len}, cb[3], r[3];
+              for (int k = 0; k < 3; ++k) cb[k] = C[k] - B[k];
+              cross3(nh, cb, r);
+              for (int k = 0; k < 3; ++k) ga[k] = 0.5 * r[k];
+            }
+            /* dSV_T/dA = (B' x C') / 6 with primes relative to the origin */
+            double Bp[3], Cp[3], bc[3];
+            for (int k = 0; k < 3; ++k) {
+              Bp[k] = B[k] - origin[k];
+              Cp[k] = C[k] - origin[k];
+            }
+            cross3(Bp, Cp, bc);
+            for (int k = 0; k < 3; ++k)
+              gx[3 * vi[v] + k] += gout[1] * ga[k] + gout[0] * sgn * bc[k] / 6.0;
+          }
+        }
+      }
+  /* Diameters: subgradient at the maximising pair. */
+  for (int f = 0; f < 4; ++f) {
+    if (pairs[2 * f] < 0) continue;
+    double D = out[2 + f];
+    if (!(D > 0.0)) continue;
+    int64_t i = find_id(ids, n, pairs[2 * f]), j = find_id(ids, n, pairs[2 * f + 1]);
+    if (i < 0 || j < 0) continue;
+    for (int k = 0; k < 3; ++k) {
+      double u = (pos[3 * i + k] - pos[3 * j + k]) / D;
+      gx[3 * i + k] += gout[2 + f] * u;
+      gx[3 * j + k] -= gout[2 + f] * u;
+    }
+  }
+  /* Chain rule through t(p_u, p_b) for every vertex. */
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t u[3], b[3];
+    int a;
+    decode_id(&g, ids[v], u, &a);
+    for (int k = 0; k < 3; ++k) b[k] = u[k];
+    b[a] += 1;
+    double pa = value_at(&g, u), pb = value_at(&g, b);
+    double den = pb - pa;
+    double dLdt = gx[3 * v + a] * g.s[a];
+    if (in_range(&g, u)) grad_p[lin(&g, u)] += dLdt * (0.5 - pb) / (den * den);
+    if (in_range(&g, b)) grad_p[lin(&g, b)] += dLdt * (-(0.5 - pa)) / (den * den);
+  }
+  free(ids);
+  free(pos);
+  free(tv);
+  free(gx);
+  return OR_OK;
+}
+
+int oracle_version(void) { return 1; }

@@ -1,0 +1,137 @@
+"""Seeded synthetic inputs (region-of-interest masks and soft masks).
+
+This module only draws random shapes; it holds none of the shape-feature
+arithmetic.  Tests, the benchmark and the oracle checks all take their inputs
+from here, so the GPU path and the oracle always see the same arrays.
+
+Shapes are built in index space (voxel centres at integer coordinates, axis 0
+slowest).  Every generator takes an explicit ``numpy.random.Generator``; use
+``rng(config, roi)`` for the fixed workload seeds.
+
+The paper measured on kidney-tumour CT segmentations; these generators are
+synthetic stand-ins with the same size range (tens of kilobytes to tens of
+megabytes of mask, a few thousand to about a million mesh vertices).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(config: int, roi: int = 0) -> np.random.Generator:
+    """Generator for workload ``config`` and region ``roi``."""
+    return np.random.default_rng(np.random.SeedSequence([2510, 2894, int(config), int(roi)]))
+
+
+def _rotation(g: np.random.Generator) -> np.ndarray:
+    """Uniformly random rotation matrix (QR of a Gaussian matrix, sign-fixed)."""
+    q, r = np.linalg.qr(g.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def ellipsoid_params(g: np.random.Generator, n: int, semi_lo, semi_hi, centre_lo, centre_hi):
+    """n ellipsoids: (centre[3], semi-axes[3], rotation[3,3]) each."""
+    out = []
+    for _ in range(n):
+        semi = g.uniform(semi_lo, semi_hi, size=3)
+        centre = g.uniform(centre_lo, centre_hi, size=3)
+        out.append((centre, semi, _rotation(g)))
+    return out
+
+
+def _ellipsoid_field(shape, centre, semi, rot, margin=0.0):
+    """Bounding-box slices and the normalised radius sum((R^T (x - c) / a)^2) on them."""
+    reach = float(np.max(semi)) + margin + 1.0
+    lo = [max(0, int(np.floor(centre[k] - reach))) for k in range(3)]
+    hi = [min(shape[k], int(np.ceil(centre[k] + reach)) + 1) for k in range(3)]
+    if any(h <= l for l, h in zip(lo, hi)):
+        return None, None
+    zz, yy, xx = np.meshgrid(*[np.arange(lo[k], hi[k], dtype=np.float64) - centre[k] for k in range(3)],
+                             indexing="ij")
+    pts = np.stack([zz, yy, xx], axis=-1)
+    q = pts @ rot  # rows are (x - c)^T R  ->  R^T (x - c)
+    rr = np.sum((q / semi) ** 2, axis=-1)
+    sl = tuple(slice(lo[k], hi[k]) for k in range(3))
+    return sl, rr
+
+
+def ellipsoid_union(shape, params) -> np.ndarray:
+    """Boolean union of ellipsoids evaluated at voxel centres."""
+    out = np.zeros(shape, dtype=bool)
+    for centre, semi, rot in params:
+        sl, rr = _ellipsoid_field(shape, centre, semi, rot)
+        if sl is not None:
+            out[sl] |= rr <= 1.0
+    return out
+
+
+def random_mask(shape, density: float, g: np.random.Generator) -> np.ndarray:
+    """I.i.d. Bernoulli mask (uint8 0/1)."""
+    return (g.random(shape) < density).astype(np.uint8)
+
+
+def box_mask(shape, lo, size) -> np.ndarray:
+    m = np.zeros(shape, dtype=np.uint8)
+    m[lo[0]:lo[0] + size[0], lo[1]:lo[1] + size[1], lo[2]:lo[2] + size[2]] = 1
+    return m
+
+
+def single_roi(seed: int = 0, shape=(64, 64, 64)):
+    """One ellipsoid, semi-axes U[8, 24] voxels, random orientation, centre U[24, 40]^3.
+
+    Returns (uint8 mask, spacing) with spacing (1, 1, 1) mm.
+    """
+    g = rng(1, seed)
+    params = ellipsoid_params(g, 1, 8.0, 24.0, 24.0, 40.0)
+    return ellipsoid_union(shape, params).astype(np.uint8), (1.0, 1.0, 1.0)
+
+
+def large_roi(seed: int = 0, shape=(300, 512, 512), n_ellipsoids: int = 20, sigma: float = 3.0):
+    """Union of 20 ellipsoids (semi-axes U[20, 90] voxels, centres uniform over
+    the array), Gaussian-smoothed indicator (sigma 3) thresholded at 0.5.
+
+    The array is (300, 512, 512) in (axis0, axis1, axis2) order, i.e. 300 slices
+    of 512 x 512; spacing (1.25, 0.7, 0.7) mm in the same order.
+    """
+    from scipy.ndimage import gaussian_filter
+
+    g = rng(2, seed)
+    params = ellipsoid_params(g, n_ellipsoids, 20.0, 90.0, 0.0, 1.0)
+    params = [(c * np.asarray(shape, dtype=np.float64), s, r) for c, s, r in params]
+    ind = ellipsoid_union(shape, params).astype(np.float32)
+    sm = gaussian_filter(ind, sigma=sigma, mode="constant", truncate=4.0)
+    return (sm > 0.5).astype(np.uint8), (1.25, 0.7, 0.7)
+
+
+def signed_distance(inside: np.ndarray, spacing=(1.0, 1.0, 1.0)) -> np.ndarray:
+    """Signed distance (negative inside) between voxel centres and the boundary,
+    from two Euclidean distance transforms, shifted by half a voxel."""
+    from scipy.ndimage import distance_transform_edt
+
+    out_d = distance_transform_edt(~inside, sampling=spacing)
+    in_d = distance_transform_edt(inside, sampling=spacing)
+    return np.where(inside, -(in_d - 0.5), out_d - 0.5)
+
+
+def soft_roi(shape, g: np.random.Generator, n_ellipsoids: int = 8, semi_lo: float = 16.0,
+             semi_hi: float = 64.0, tau: float = 1.0) -> np.ndarray:
+    """float32 probability mask p = sigmoid(-sd / tau) of an ellipsoid union."""
+    shape = tuple(int(s) for s in shape)
+    lo = np.minimum(np.asarray(shape) * 0.25, np.asarray(shape) / 2.0)
+    hi = np.asarray(shape) - lo
+    params = ellipsoid_params(g, n_ellipsoids, semi_lo, semi_hi, lo, hi)
+    inside = ellipsoid_union(shape, params)
+    sd = signed_distance(inside)
+    return (1.0 / (1.0 + np.exp(sd / tau))).astype(np.float32)
+
+
+def differentiable_roi(seed: int = 0, shape=(256, 256, 256)):
+    """Soft mask of an 8-ellipsoid union, semi-axes U[16, 64], tau = 1 voxel; spacing (1, 1, 1)."""
+    return soft_roi(shape, rng(4, seed), 8, 16.0, 64.0, 1.0), (1.0, 1.0, 1.0)
+
+
+def differentiable_small(seed: int = 0, shape=(32, 32, 32)):
+    """Small instance of the differentiable workload (semi-axes U[3, 8])."""
+    return soft_roi(shape, rng(4, 1000 + seed), 8, 3.0, 8.0, 1.0), (1.0, 1.0, 1.0)

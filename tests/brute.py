@@ -1,0 +1,66 @@
+"""Brute-force helpers for pinning the oracle on small inputs.
+
+These recompute the vertex set and the diameters straight from their
+definitions with numpy, independently of the C oracle: a vertex for every pair
+of 6-neighbour voxels (with the one-voxel zero pad) whose inside test differs,
+and maxima over all vertex pairs.
+"""
+import numpy as np
+
+
+def inside(vol):
+    return (vol != 0) if vol.dtype == np.uint8 else (vol > np.float32(0.5))
+
+
+def vertex_set(vol, spacing):
+    """ids (ascending) and positions from neighbour label changes (np.diff)."""
+    ins = np.pad(inside(vol), 1)
+    pval = np.pad(vol.astype(np.float64), 1) if vol.dtype == np.float32 else None
+    d = np.array(vol.shape, dtype=np.int64)
+    recs = []
+    for a in range(3):
+        ch = np.diff(ins.astype(np.int8), axis=a) != 0
+        idx = np.argwhere(ch)  # padded coordinates of the lower end point
+        u = idx - 1            # array coordinates, in [-1, d-1] along a
+        if pval is not None:
+            hi = idx.copy()
+            hi[:, a] += 1
+            pa = pval[tuple(idx.T)]
+            pb = pval[tuple(hi.T)]
+            t = (0.5 - pa) / (pb - pa)
+        else:
+            t = np.full(len(u), 0.5)
+        lin = ((u[:, 0] + 1) * (d[1] + 2) + (u[:, 1] + 1)) * (d[2] + 2) + (u[:, 2] + 1)
+        ids = 3 * lin + a
+        pos = u.astype(np.float64)
+        pos[:, a] += t
+        pos = pos * np.asarray(spacing, dtype=np.float64)
+        key = 2 * u
+        key[:, a] += 1
+        recs.append((ids, pos, key))
+    ids = np.concatenate([r[0] for r in recs])
+    pos = np.concatenate([r[1] for r in recs])
+    key = np.concatenate([r[2] for r in recs])
+    o = np.argsort(ids, kind="stable")
+    return ids[o], pos[o], key[o]
+
+
+def max_d2(pos, groups=None):
+    """Maximum squared pairwise distance (over pairs in the same group if given)."""
+    if len(pos) < 2:
+        return 0.0
+    diff = pos[:, None, :] - pos[None, :, :]
+    d2 = np.sum(diff * diff, axis=-1)
+    if groups is not None:
+        d2 = np.where(groups[:, None] == groups[None, :], d2, -1.0)
+    np.fill_diagonal(d2, -1.0)
+    return max(float(d2.max()), 0.0)
+
+
+def diameters(vol, spacing):
+    """(3D, slice, column, row) maximum distances by brute force."""
+    ids, pos, key = vertex_set(vol, spacing)
+    out = [np.sqrt(max_d2(pos))]
+    for k in range(3):
+        out.append(np.sqrt(max_d2(pos, key[:, k])))
+    return np.array(out), len(ids)

@@ -1,0 +1,416 @@
+"""Pins of the CPU FP64 oracle against facts fixed by the mathematics.
+
+Each test checks the oracle against something other than itself: closed forms
+(single voxel, solid boxes, one soft voxel), brute force on tiny inputs,
+invariants (translation, axis permutation, scaling, origin of the tetrahedron
+sum) and topological identities (closed oriented surface, Euler
+characteristic).  A plausible mistake (a dropped triangle, a flipped segment,
+a wrong index, a transposed spacing) fails at least one of them.
+"""
+import collections
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_02894_amd import synth
+from tests import brute
+
+
+def feats(vol, sp):
+    return O.shape3d(vol, sp)
+
+
+# --------------------------------------------------------------------------
+# P1 -- a single voxel gives an octahedron.
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_single_voxel_closed_form(seed):
+    g = np.random.default_rng(seed)
+    shape = tuple(int(x) for x in g.integers(1, 6, size=3))
+    pos = tuple(int(g.integers(0, s)) for s in shape)
+    sp = tuple(float(x) for x in g.uniform(0.3, 2.5, size=3))
+    m = np.zeros(shape, np.uint8)
+    m[pos] = 7  # any nonzero label is inside
+    r = feats(m, sp)
+    s0, s1, s2 = sp
+    assert r["V"] == 6 and r["T"] == 8
+    f = r["features"]
+    assert f[0] == pytest.approx(s0 * s1 * s2 / 6, rel=1e-14)
+    assert f[1] == pytest.approx(math.sqrt(s0 * s0 * s1 * s1 + s1 * s1 * s2 * s2 + s0 * s0 * s2 * s2), rel=1e-14)
+    assert f[2] == pytest.approx(max(sp), rel=1e-15)
+    assert f[3] == pytest.approx(max(s1, s2), rel=1e-15)
+    assert f[4] == pytest.approx(max(s0, s2), rel=1e-15)
+    assert f[5] == pytest.approx(max(s0, s1), rel=1e-15)
+
+
+def test_single_voxel_unit_values():
+    m = np.zeros((1, 1, 1), np.uint8)
+    m[0, 0, 0] = 1
+    f = feats(m, (1, 1, 1))["features"]
+    np.testing.assert_allclose(f, [1 / 6, math.sqrt(3), 1, 1, 1, 1], rtol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# P2 -- solid boxes.
+
+
+def box_expect(a, s):
+    A = [x - 1 for x in a]
+    s0, s1, s2 = s
+    V = 2 * (a[0] * a[1] + a[1] * a[2] + a[0] * a[2])
+    vol = s0 * s1 * s2 * (A[0] * A[1] * A[2] + (A[0] * A[1] + A[1] * A[2] + A[0] * A[2])
+                           + (A[0] + A[1] + A[2]) / 2 + 1 / 6)
+    area = (2 * (A[1] * A[2] * s1 * s2 + A[0] * A[2] * s0 * s2 + A[0] * A[1] * s0 * s1)
+            + 2 * (A[0] * s0 * math.hypot(s1, s2) + A[1] * s1 * math.hypot(s0, s2) + A[2] * s2 * math.hypot(s0, s1))
+            + math.sqrt(s0 * s0 * s1 * s1 + s1 * s1 * s2 * s2 + s0 * s0 * s2 * s2))
+    d3 = max((s[k] * a[k]) ** 2 + sum((s[j] * A[j]) ** 2 for j in range(3) if j != k) for k in range(3))
+    d2 = []
+    for k in range(3):
+        i, j = [x for x in range(3) if x != k]
+        d2.append(max((s[i] * a[i]) ** 2 + (s[j] * A[j]) ** 2, (s[j] * a[j]) ** 2 + (s[i] * A[i]) ** 2))
+    return V, vol, area, math.sqrt(d3), [math.sqrt(x) for x in d2]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_box_closed_form(seed):
+    g = np.random.default_rng(100 + seed)
+    a = [int(x) for x in g.integers(1, 6, size=3)]
+    margin = [int(x) for x in g.integers(0, 3, size=3)]
+    shape = tuple(a[k] + margin[k] + int(g.integers(0, 3)) for k in range(3))
+    sp = tuple(float(x) for x in g.uniform(0.4, 2.0, size=3))
+    m = synth.box_mask(shape, margin, a)
+    r = feats(m, sp)
+    V, vol, area, d3, d2 = box_expect(a, sp)
+    assert r["V"] == V
+    assert r["T"] == 2 * V - 4
+    f = r["features"]
+    assert f[0] == pytest.approx(vol, rel=1e-13)
+    assert f[1] == pytest.approx(area, rel=1e-13)
+    assert f[2] == pytest.approx(d3, rel=1e-14)
+    np.testing.assert_allclose(f[3:], d2, rtol=1e-14)
+
+
+def test_box_2x2x2_volume():
+    r = feats(synth.box_mask((2, 2, 2), (0, 0, 0), (2, 2, 2)), (1, 1, 1))
+    assert r["features"][0] == pytest.approx(17 / 3, rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# P4 / P6 -- vertex set and diameters by brute force; vertex count by label changes.
+
+
+def small_masks():
+    out = []
+    for c in range(256):  # every 2x2x2 mask
+        m = np.array([(c >> b) & 1 for b in range(8)], np.uint8).reshape(2, 2, 2)
+        out.append((m, (1.0, 1.0, 1.0)))
+    g = np.random.default_rng(7)
+    for n in range(3, 9):
+        for dens in (0.2, 0.5, 0.8):
+            shape = tuple(int(x) for x in g.integers(n - 1, n + 2, size=3))
+            sp = tuple(float(x) for x in g.uniform(0.5, 1.7, size=3))
+            out.append((synth.random_mask(shape, dens, g), sp))
+    return out
+
+
+def test_vertex_set_bruteforce():
+    for m, sp in small_masks():
+        ids, pos, _ = O.vertices(m, sp)
+        bids, bpos, _ = brute.vertex_set(m, sp)
+        np.testing.assert_array_equal(ids, bids)
+        np.testing.assert_array_equal(pos, bpos)
+
+
+def test_vertex_count_label_changes():
+    g = np.random.default_rng(11)
+    for _ in range(20):
+        shape = tuple(int(x) for x in g.integers(2, 12, size=3))
+        m = synth.random_mask(shape, float(g.uniform(0.1, 0.9)), g)
+        ins = np.pad(m != 0, 1).astype(np.int8)
+        n = sum(int(np.count_nonzero(np.diff(ins, axis=a))) for a in range(3))
+        assert O.count_vertices(m) == n
+
+
+def test_diameters_bruteforce():
+    for m, sp in small_masks():
+        r = feats(m, sp)
+        d, nv = brute.diameters(m, sp)
+        assert r["V"] == nv
+        np.testing.assert_allclose(r["features"][2:], d, rtol=1e-14, atol=0)
+
+
+def test_diameters_exact_half_units():
+    # unit spacing: every squared distance is an integer multiple of 1/4
+    g = np.random.default_rng(3)
+    for _ in range(10):
+        m = synth.random_mask(tuple(int(x) for x in g.integers(3, 8, size=3)), 0.4, g)
+        f = feats(m, (1, 1, 1))["features"]
+        q = 4 * f[2:] ** 2
+        np.testing.assert_allclose(q, np.round(q), rtol=0, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Surface topology: closed, consistently oriented, Euler characteristic.
+
+
+def directed_edges(tris):
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    return e
+
+
+def test_closed_oriented_surface():
+    for m, sp in small_masks():
+        area, sv, nt, tris = O.mesh(m, sp, triangles=True)
+        if nt == 0:
+            continue
+        # an oriented closed surface: every directed edge occurs as often as its
+        # reverse (a loop crossing an ambiguous face twice may put the same face
+        # diagonal in both neighbouring cubes, so multiplicities can be 2)
+        e = directed_edges(tris)
+        fwd = collections.Counter(map(tuple, e))
+        rev = collections.Counter(map(tuple, e[:, ::-1]))
+        assert fwd == rev, "a directed edge has no matching reverse"
+        assert max(fwd.values()) <= 2
+        assert sv > 0, "normals must point outward"
+
+
+def euler(tris, nv):
+    e = directed_edges(tris)
+    und = set(map(lambda x: (min(x), max(x)), map(tuple, e)))
+    return nv - len(und) + len(tris)
+
+
+def test_euler_characteristic():
+    # genus-0 surfaces: one component -> 2, two separate components -> 4
+    m = synth.box_mask((6, 7, 8), (1, 1, 1), (3, 4, 5))
+    _, _, nt, tris = O.mesh(m, triangles=True)
+    assert euler(tris, O.count_vertices(m)) == 2
+    m3 = np.zeros((8, 8, 8), np.uint8)
+    m3[1:3, 1:3, 1:3] = 1
+    m3[5:7, 5:7, 5:7] = 1
+    _, _, nt, tris = O.mesh(m3, triangles=True)
+    assert euler(tris, O.count_vertices(m3)) == 4
+    g = synth.rng(99, 0)
+    for k in range(4):
+        params = synth.ellipsoid_params(g, 1, 4.0, 9.0, 10.0, 14.0)
+        e = synth.ellipsoid_union((24, 24, 24), params).astype(np.uint8)
+        _, _, nt, tris = O.mesh(e, triangles=True)
+        from scipy import ndimage
+        ncomp = ndimage.label(e)[1]
+        if ncomp == 1:
+            assert euler(tris, O.count_vertices(e)) == 2
+
+
+def test_signed_volume_origin_invariance():
+    for i, (m, sp) in enumerate(small_masks()[::7]):
+        a0, v0, _, _ = O.mesh(m, sp, origin=(0.0, 0.0, 0.0))
+        a1, v1, _, _ = O.mesh(m, sp, origin=(13.5, -7.25, 101.0))
+        assert a0 == a1
+        assert v1 == pytest.approx(v0, rel=1e-11, abs=1e-11)
+
+
+# --------------------------------------------------------------------------
+# P3 -- invariants.
+
+
+def test_translation_invariance():
+    g = np.random.default_rng(21)
+    for _ in range(6):
+        m = synth.random_mask(tuple(int(x) for x in g.integers(3, 7, size=3)), 0.5, g)
+        r0 = feats(m, (1, 1, 1))
+        off = [int(x) for x in g.integers(0, 5, size=3)]
+        big = np.zeros(tuple(m.shape[k] + off[k] + 3 for k in range(3)), np.uint8)
+        big[off[0]:off[0] + m.shape[0], off[1]:off[1] + m.shape[1], off[2]:off[2] + m.shape[2]] = m
+        r1 = feats(big, (1, 1, 1))
+        assert (r0["V"], r0["T"]) == (r1["V"], r1["T"])
+        np.testing.assert_array_equal(r0["features"][2:], r1["features"][2:])  # exact half units
+        np.testing.assert_allclose(r0["features"][:2], r1["features"][:2], rtol=1e-12)
+
+
+def test_axis_permutation():
+    g = np.random.default_rng(5)
+    for _ in range(6):
+        m = synth.random_mask(tuple(int(x) for x in g.integers(3, 7, size=3)), 0.45, g)
+        sp = tuple(float(x) for x in g.uniform(0.5, 1.5, size=3))
+        r0 = feats(m, sp)
+        for perm in itertools.permutations(range(3)):
+            mp = np.ascontiguousarray(np.transpose(m, perm))
+            spp = tuple(sp[p] for p in perm)
+            r1 = feats(mp, spp)
+            assert (r0["V"], r0["T"]) == (r1["V"], r1["T"])
+            assert r1["features"][2] == pytest.approx(r0["features"][2], rel=1e-15)
+            for k in range(3):
+                assert r1["features"][3 + k] == pytest.approx(r0["features"][3 + perm[k]], rel=1e-15)
+
+
+def test_axis_permutation_planar_boxes():
+    # all loops are planar for a union of separated boxes: area/volume permute exactly
+    m = np.zeros((9, 8, 7), np.uint8)
+    m[1:4, 2:6, 1:3] = 1
+    m[6:8, 1:3, 3:6] = 1
+    sp = (0.9, 1.3, 0.6)
+    r0 = feats(m, sp)
+    for perm in itertools.permutations(range(3)):
+        r1 = feats(np.ascontiguousarray(np.transpose(m, perm)), tuple(sp[p] for p in perm))
+        np.testing.assert_allclose(r1["features"][:2], r0["features"][:2], rtol=1e-13)
+
+
+def test_spacing_scaling():
+    g = np.random.default_rng(8)
+    m = synth.random_mask((6, 5, 7), 0.5, g)
+    sp = (0.8, 1.1, 0.65)
+    f0 = feats(m, sp)["features"]
+    f1 = feats(m, tuple(2 * s for s in sp))["features"]  # power of two: exact
+    assert f1[0] == pytest.approx(8 * f0[0], rel=1e-13)
+    assert f1[1] == pytest.approx(4 * f0[1], rel=1e-13)
+    np.testing.assert_array_equal(f1[2:], 2 * f0[2:])
+
+
+def test_empty_mask():
+    r = O.shape3d(np.zeros((4, 5, 6), np.uint8), (1, 1, 1))
+    assert r["status"] == O.EMPTY and r["V"] == 0
+    np.testing.assert_array_equal(r["features"], np.zeros(6))
+
+
+def test_full_array_is_a_box():
+    m = np.ones((3, 4, 5), np.uint8)
+    r = feats(m, (1.0, 1.0, 1.0))
+    V, vol, area, d3, d2 = box_expect([3, 4, 5], (1.0, 1.0, 1.0))
+    assert r["V"] == V
+    assert r["features"][0] == pytest.approx(vol, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# P7 -- loose convergence to the continuous ellipsoid volume.
+
+
+def test_ellipsoid_volume_convergence():
+    semi = np.array([18.0, 14.0, 11.0])
+    params = [(np.array([24.0, 24.0, 24.0]), semi, np.eye(3))]
+    e = synth.ellipsoid_union((48, 48, 48), params).astype(np.uint8)
+    v = feats(e, (1, 1, 1))["features"][0]
+    assert abs(v / (4 / 3 * math.pi * semi.prod()) - 1) < 0.05
+
+
+# --------------------------------------------------------------------------
+# P8 -- a soft mask with values in {0, 1} is the binary mask.
+
+
+def test_soft_reduces_to_binary():
+    for m, sp in small_masks()[::5]:
+        rb = feats(m, sp)
+        rs = feats((m != 0).astype(np.float32), sp)
+        assert (rb["V"], rb["T"]) == (rs["V"], rs["T"])
+        np.testing.assert_array_equal(rb["features"], rs["features"])
+
+
+# --------------------------------------------------------------------------
+# P9 -- one soft voxel: asymmetric octahedron and its gradient.
+
+
+def octa(rp, rm, s):
+    """Volume and area of the octahedron with vertex offsets +rp_k s_k, -rm_k s_k."""
+    vol = (rp[0] + rm[0]) * (rp[1] + rm[1]) * (rp[2] + rm[2]) * s[0] * s[1] * s[2] / 6
+    area = 0.0
+    for a in (rp[0], rm[0]):
+        for b in (rp[1], rm[1]):
+            for c in (rp[2], rm[2]):
+                x, y, z = a * s[0], b * s[1], c * s[2]
+                area += 0.5 * math.sqrt((x * y) ** 2 + (y * z) ** 2 + (x * z) ** 2)
+    return vol, area
+
+
+@pytest.mark.parametrize("q", [1.0, 0.9, 0.75, 0.6])
+def test_soft_single_voxel_closed_form(q):
+    s = (1.3, 0.8, 1.05)
+    p = np.zeros((3, 3, 3), np.float32)
+    p[1, 1, 1] = q
+    qd = float(np.float32(q))
+    r = (qd - 0.5) / qd
+    f = feats(p, s)["features"]
+    vol, area = octa([r] * 3, [r] * 3, s)
+    assert f[0] == pytest.approx(vol, rel=1e-13)
+    assert f[1] == pytest.approx(area, rel=1e-13)
+    assert f[2] == pytest.approx(2 * r * max(s), rel=1e-14)
+
+
+def test_soft_single_voxel_gradient():
+    s = (1.3, 0.8, 1.05)
+    q = 1.0
+    p = np.zeros((3, 3, 3), np.float32)
+    p[1, 1, 1] = q
+    gout = np.array([0.7, 1.3, 0.9, 0.0, 0.0, 0.0])
+    grad = O.soft_grad(p, s, gout)
+    r = (q - 0.5) / q
+
+    def L(rp, rm):
+        vol, area = octa(rp, rm, s)
+        diam = max((rp[k] + rm[k]) * s[k] for k in range(3))
+        return gout[0] * vol + gout[1] * area + gout[2] * diam
+
+    h = 1e-6
+    # centre voxel: every radius moves with dr/dq = 0.5 / q^2
+    drdq = 0.5 / q ** 2
+    dL = (L([r + h] * 3, [r + h] * 3) - L([r - h] * 3, [r - h] * 3)) / (2 * h) * drdq
+    assert grad[1, 1, 1] == pytest.approx(dL, rel=1e-7)
+    # neighbour on +k / -k: only that radius moves, dr/dp_n = (q - 0.5) / q^2
+    drdn = (q - 0.5) / q ** 2
+    for k in range(3):
+        for sign in (+1, -1):
+            rp, rm = [r] * 3, [r] * 3
+            rp2, rm2 = list(rp), list(rm)
+            rp3, rm3 = list(rp), list(rm)
+            if sign > 0:
+                rp2[k] += h
+                rp3[k] -= h
+            else:
+                rm2[k] += h
+                rm3[k] -= h
+            dLn = (L(rp2, rm2) - L(rp3, rm3)) / (2 * h) * drdn
+            idx = [1, 1, 1]
+            idx[k] += sign
+            assert grad[tuple(idx)] == pytest.approx(dLn, rel=1e-7, abs=1e-12)
+    # exact values at q = 1 with unit weights on volume and area (unit spacing)
+    gu = O.soft_grad(p, (1, 1, 1), [1, 0, 0, 0, 0, 0])
+    assert gu[1, 1, 1] == pytest.approx(0.5, rel=1e-14)
+    assert gu[2, 1, 1] == pytest.approx(1 / 12, rel=1e-14)
+    ga = O.soft_grad(p, (1, 1, 1), [0, 1, 0, 0, 0, 0])
+    assert ga[1, 1, 1] == pytest.approx(2 * math.sqrt(3), rel=1e-14)
+    assert ga[1, 0, 1] == pytest.approx(1 / math.sqrt(3), rel=1e-14)
+    assert np.count_nonzero(ga) == 7
+
+
+# --------------------------------------------------------------------------
+# FD check of the reference gradient on the small differentiable instance.
+
+
+def test_soft_grad_finite_differences():
+    p, sp = synth.differentiable_small(0, shape=(20, 20, 20))
+    sp = (1.0, 0.9, 1.2)
+    gout = np.array([0.1, 1.0, 1.0, 0.5, 0.7, 0.3])
+    base = O.shape3d(p, sp)
+    grad = O.soft_grad(p, sp, gout)
+    h = 2.0 ** -13
+    cand = np.argwhere((p > 0.02) & (p < 0.98) & (np.abs(p - 0.5) > 4 * h))
+    g = np.random.default_rng(0)
+    pick = cand[g.choice(len(cand), size=min(60, len(cand)), replace=False)]
+    checked = 0
+    for idx in map(tuple, pick):
+        pp = p.copy()
+        pm = p.copy()
+        pp[idx] += np.float32(h)
+        pm[idx] -= np.float32(h)
+        dp = float(pp[idx]) - float(p[idx])
+        dm = float(p[idx]) - float(pm[idx])
+        assert dp == h and dm == h
+        rp, rm = O.shape3d(pp, sp), O.shape3d(pm, sp)
+        if not (np.array_equal(rp["pair_ids"], base["pair_ids"]) and np.array_equal(rm["pair_ids"], base["pair_ids"])):
+            continue  # the maximising pair switched: not differentiable here
+        fd = (gout @ rp["features"] - gout @ rm["features"]) / (2 * h)
+        assert grad[idx] == pytest.approx(fd, rel=2e-5, abs=2e-6), idx
+        checked += 1
+    assert checked >= 40
