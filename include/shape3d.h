@@ -1,0 +1,125 @@
+/*
+ * shape3d.h -- C ABI of the MI355X (gfx950) 3D shape-feature library.
+ *
+ * The library computes the six mesh-based shape features of a region of
+ * interest (ROI) that the paper accelerates (Sec. 2, "PyRadiomics-cuda
+ * design"): the mesh volume and surface area of a marching-cubes surface
+ * ("Marching cubes fused parallel kernels" paragraph), and the maximum
+ * distance between mesh vertices in 3D and within each axis-aligned plane
+ * ("Parallel diameter calculation" paragraph; the planar diameters of the
+ * feature list in Sec. 2).
+ *
+ * Conventions shared by every entry point:
+ *   - the volume is C-contiguous with shape (d0, d1, d2) (axis 0 slowest);
+ *     dims and spacing are given in that same axis order; spacing in mm;
+ *   - dtype SHAPE3D_U8: uint8 mask, voxel inside iff value != 0, mesh
+ *     vertices at edge midpoints; dtype SHAPE3D_F32: float32 probabilities,
+ *     inside iff p > 0.5, vertices linearly interpolated at the 0.5 level;
+ *   - voxels outside the array count as outside (one-voxel zero pad);
+ *   - features, in order: MeshVolume (mm^3, absolute value of the signed
+ *     tetrahedron sum), SurfaceArea (mm^2), Maximum3DDiameter,
+ *     Maximum2DDiameterSlice (vertex pairs on a common plane of axis 0),
+ *     ...Column (axis 1), ...Row (axis 2), all in mm;
+ *   - a mesh vertex is identified by its canonical id
+ *     3 * (((u0+1)*(d1+2) + (u1+1))*(d2+2) + (u2+1)) + a for the grid edge
+ *     (u, u + e_a) it lies on;
+ *   - the maximising pair of a diameter is the pair with the largest
+ *     distance and, among equal distances, the lexicographically smallest
+ *     pair of canonical ids.
+ *
+ * Pointers documented as DEVICE point to memory on the current HIP device;
+ * HOST pointers to ordinary host memory.  `stream` is a hipStream_t (NULL =
+ * the null stream).  The caller owns every buffer it passes.  The library
+ * owns a workspace per device that grows on demand and is kept between calls
+ * (shape3d_release frees it).  Calls are serialised by an internal lock;
+ * device buffers given to a call must stay valid until it returns.
+ *
+ * Every function returns a status.  On a failure (negative status) the
+ * outputs are left untouched and shape3d_last_error() describes the cause.
+ * There is no CPU fallback: without a usable GPU the functions return
+ * SHAPE3D_ENODEV.
+ */
+#ifndef SHAPE3D_H
+#define SHAPE3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHAPE3D_OK 0
+#define SHAPE3D_EMPTY 1      /* no foreground voxel: features are all 0 */
+#define SHAPE3D_EINVAL (-1)  /* bad argument (null pointer, dims, spacing, dtype) */
+#define SHAPE3D_ENODEV (-2)  /* no usable HIP device */
+#define SHAPE3D_EHIP (-3)    /* a HIP runtime call failed */
+#define SHAPE3D_ECAPACITY (-4) /* an internal bound was exceeded */
+#define SHAPE3D_ENOMEM (-5)  /* device allocation failed */
+
+#define SHAPE3D_U8 0
+#define SHAPE3D_F32 1
+
+/* Largest accepted extent of one axis. */
+#define SHAPE3D_MAX_DIM 1000000
+
+/* Per-call statistics (optional output of shape3d_ex). */
+typedef struct {
+  int64_t n_vertices;      /* V: mesh vertices (crossing grid edges) */
+  int64_t n_triangles;     /* T: mesh triangles */
+  int64_t pair_ids[4][2];  /* canonical ids of the maximising pair: 3D, slice, column, row (-1: none) */
+  int64_t pairs_3d;        /* V*(V-1)/2 */
+  int64_t pairs_2d;        /* sum over planes of n*(n-1)/2 */
+  int64_t candidates[4];   /* rows re-examined in FP64 per diameter */
+  float ms[8];             /* device time per phase (ms), filled when timing != 0:
+                              0 mesh count, 1 mesh emit, 2 plane bucketing, 3 pair maxima (MFMA),
+                              4 exact refinement, 5 finalisation, 6 whole call, 7 reserved */
+} shape3d_stats;
+
+/*
+ * shape3d -- the six features of one binary ROI, synchronously.
+ *   mask:    DEVICE, uint8 (d0, d1, d2), C-contiguous; nonzero = inside.
+ *   dims:    HOST int64[3]; each in [1, SHAPE3D_MAX_DIM].
+ *   spacing: HOST double[3]; each finite and > 0.
+ *   out:     HOST double[6], the features in the order above.
+ * Uses the null stream.  Returns SHAPE3D_OK, SHAPE3D_EMPTY (out all zero) or
+ * a negative error.
+ */
+int shape3d(const uint8_t* mask, const int64_t dims[3], const double spacing[3], double out[6]);
+
+/*
+ * shape3d_ex -- as shape3d, for either dtype, on `stream`, with optional
+ * statistics.  vol: DEVICE volume of `dtype`.  out: HOST double[6].
+ * stats: HOST, may be NULL.  timing: nonzero records per-phase HIP events
+ * into stats->ms (costs a few microseconds).  Returns when the results are
+ * on the host.
+ */
+int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+               double out[6], shape3d_stats* stats, int timing, void* stream);
+
+/*
+ * shape3d_vertices -- the mesh vertex set, for verification.
+ *   ids:  DEVICE int64[cap]; receives the canonical ids of all V vertices
+ *         (in the library's emission order, which is deterministic).
+ *   pos:  DEVICE double[3*cap] or NULL; receives their positions (mm,
+ *         index * spacing, not centred).
+ *   n_out: HOST; receives V.  If V > cap nothing is written to ids/pos and
+ *         SHAPE3D_ECAPACITY is returned with *n_out = V.
+ */
+int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                     int64_t* ids, double* pos, int64_t cap, int64_t* n_out, void* stream);
+
+/* Message describing the last failure of the calling thread ("" if none). */
+const char* shape3d_last_error(void);
+
+/* Frees the library's device workspace.  Safe to call at any time between calls. */
+int shape3d_release(void);
+
+/* Library version (major*100 + minor). */
+int shape3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHAPE3D_H */

@@ -61,6 +61,7 @@ def _load():
         lib.oracle_vertices.argtypes = [vp, ctypes.c_int, i64p, f64p, ctypes.c_int64, i64p, f64p, f64p, i64p]
         lib.oracle_mesh.argtypes = [vp, ctypes.c_int, i64p, f64p, f64p, f64p, f64p, i64p, ctypes.c_int64, i64p]
         lib.oracle_diameters.argtypes = [i64p, f64p, ctypes.c_int64, i64p, f64p, i64p]
+        lib.oracle_diameters_which.argtypes = [i64p, f64p, ctypes.c_int64, i64p, ctypes.c_int, f64p, i64p]
         lib.oracle_shape3d.argtypes = [vp, ctypes.c_int, i64p, f64p, f64p, i64p, i64p, f64p]
         lib.oracle_soft_grad.argtypes = [vp, i64p, f64p, f64p, i64p, f64p]
         lib.oracle_cube_triangles.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -148,17 +149,19 @@ def mesh(vol: np.ndarray, spacing=(1.0, 1.0, 1.0), origin=None, triangles: bool 
     return float(area[0]), float(sv[0]), int(nt[0]), tris
 
 
-def diameters(ids: np.ndarray, pos: np.ndarray, dims):
-    """(d2[4] = squared {3D, slice, column, row}, pair_idx int64[4,2] into the vertex list)."""
+def diameters(ids: np.ndarray, pos: np.ndarray, dims, which: int = 15):
+    """(d2[4] = squared {3D, slice, column, row}, pair_idx int64[4,2] into the vertex list).
+
+    ``which`` selects features by bit (bit 0: 3D, bit 1 + k: planes of axis k)."""
     lib = _load()
     ids = np.ascontiguousarray(ids, dtype=np.int64)
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int64).reshape(3))
     d2 = np.zeros(4)
     pidx = np.zeros(8, dtype=np.int64)
-    _check(lib.oracle_diameters(_p(ids, ctypes.c_int64), _p(pos, ctypes.c_double), len(ids),
-                                _p(dims, ctypes.c_int64), _p(d2, ctypes.c_double), _p(pidx, ctypes.c_int64)),
-           "diameters")
+    _check(lib.oracle_diameters_which(_p(ids, ctypes.c_int64), _p(pos, ctypes.c_double), len(ids),
+                                      _p(dims, ctypes.c_int64), int(which), _p(d2, ctypes.c_double),
+                                      _p(pidx, ctypes.c_int64)), "diameters")
     return d2, pidx.reshape(4, 2)
 
 

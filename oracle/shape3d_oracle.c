@@ -496,8 +496,23 @@ static best_t max_pair(const double* pos, const int64_t* idx, int64_t n) {
    between vertices with equal key_k.  pair_idx[2f], pair_idx[2f+1] = indices
    (into the vertex list) of the maximising pair of feature f, -1 if none.
    Vertices must be in ascending id order (as oracle_vertices returns them). */
+static int diameters_which(const int64_t* ids, const double* pos, int64_t n, const int64_t dims[3],
+                           int which, double d2_out[4], int64_t pair_idx[8]);
+
 int oracle_diameters(const int64_t* ids, const double* pos, int64_t n, const int64_t dims[3],
                      double d2_out[4], int64_t pair_idx[8]) {
+  return diameters_which(ids, pos, n, dims, 15, d2_out, pair_idx);
+}
+
+/* As oracle_diameters, computing only the features whose bit is set in
+   `which` (bit 0: 3D, bit 1 + k: planes of axis k); the others are 0. */
+int oracle_diameters_which(const int64_t* ids, const double* pos, int64_t n, const int64_t dims[3],
+                           int which, double d2_out[4], int64_t pair_idx[8]) {
+  return diameters_which(ids, pos, n, dims, which, d2_out, pair_idx);
+}
+
+static int diameters_which(const int64_t* ids, const double* pos, int64_t n, const int64_t dims[3],
+                           int which, double d2_out[4], int64_t pair_idx[8]) {
   if ((!ids || !pos) && n > 0) return OR_EINVAL;
   grid_t g;
   double unit[3] = {1.0, 1.0, 1.0};
@@ -517,11 +532,14 @@ int oracle_diameters(const int64_t* ids, const double* pos, int64_t n, const int
     return OR_ENOMEM;
   }
   for (int64_t i = 0; i < n; ++i) idx[i] = i;
-  best_t b = max_pair(pos, idx, n);
-  d2_out[0] = b.d2;
-  pair_idx[0] = b.i;
-  pair_idx[1] = b.j;
+  if (which & 1) {
+    best_t b = max_pair(pos, idx, n);
+    d2_out[0] = b.d2;
+    pair_idx[0] = b.i;
+    pair_idx[1] = b.j;
+  }
   for (int k = 0; k < 3; ++k) {
+    if (!(which & (2 << k))) continue;
     /* Stable counting sort by plane key (vertices are already in id order). */
     int64_t nb = 2 * g.d[k] + 1;
     int64_t* cnt = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));

@@ -201,40 +201,45 @@ def render(table):
     w("#pragma once")
     w("#include <stdint.h>")
     w("")
+    w("// Storage qualifier of the tables; device code defines it as __constant__ const.")
+    w("#ifndef MC_TABLE_QUAL")
+    w("#define MC_TABLE_QUAL const")
+    w("#endif")
+    w("")
     w("#define MC_MAX_TRI %d" % MAX_TRI)
     w("")
     w("// axis and start corner of each cube edge")
-    w("static const uint8_t MC_EDGE_AXIS[12] = {%s};" % ", ".join(str(edge_axis_start(e)[0]) for e in range(12)))
-    w("static const uint8_t MC_EDGE_C0[12] = {%s};" % ", ".join(str(edge_axis_start(e)[1]) for e in range(12)))
+    w("static MC_TABLE_QUAL uint8_t MC_EDGE_AXIS[12] = {%s};" % ", ".join(str(edge_axis_start(e)[0]) for e in range(12)))
+    w("static MC_TABLE_QUAL uint8_t MC_EDGE_C0[12] = {%s};" % ", ".join(str(edge_axis_start(e)[1]) for e in range(12)))
     w("// edge midpoint in half-voxel units relative to the cube's min corner")
-    w("static const int8_t MC_EDGE_HALF[12][3] = {%s};" % ", ".join(
+    w("static MC_TABLE_QUAL int8_t MC_EDGE_HALF[12][3] = {%s};" % ", ".join(
         "{%d, %d, %d}" % half_unit(e) for e in range(12)))
     w("")
-    w("static const uint8_t MC_NTRI[256] = {")
+    w("static MC_TABLE_QUAL uint8_t MC_NTRI[256] = {")
     for r in range(0, 256, 16):
         w("    " + ", ".join("%d" % len(table[c]["tris"]) for c in range(r, r + 16)) + ",")
     w("};")
     w("")
     w("// triangles as cube-edge triples (unused slots are 0)")
-    w("static const uint8_t MC_TRI[256][MC_MAX_TRI][3] = {")
+    w("static MC_TABLE_QUAL uint8_t MC_TRI[256][MC_MAX_TRI][3] = {")
     for c in range(256):
         t = table[c]["tris"] + [(0, 0, 0)] * (MAX_TRI - len(table[c]["tris"]))
         w("    {%s}," % ", ".join("{%d, %d, %d}" % x for x in t))
     w("};")
     w("")
     w("// per-triangle integer normal (l_b - l_a) x (l_c - l_a) in half-voxel units")
-    w("static const int8_t MC_TRI_N[256][MC_MAX_TRI][3] = {")
+    w("static MC_TABLE_QUAL int8_t MC_TRI_N[256][MC_MAX_TRI][3] = {")
     for c in range(256):
         n = table[c]["normals"] + [(0, 0, 0)] * (MAX_TRI - len(table[c]["normals"]))
         w("    {%s}," % ", ".join("{%d, %d, %d}" % x for x in n))
     w("};")
     w("")
     w("// per-case sum of triangle normals M and of l_a . (l_b x l_c) (kappa)")
-    w("static const int8_t MC_CASE_M[256][3] = {")
+    w("static MC_TABLE_QUAL int8_t MC_CASE_M[256][3] = {")
     for r in range(0, 256, 8):
         w("    " + ", ".join("{%d, %d, %d}" % tuple(table[c]["M"]) for c in range(r, r + 8)) + ",")
     w("};")
-    w("static const int16_t MC_CASE_KAPPA[256] = {")
+    w("static MC_TABLE_QUAL int16_t MC_CASE_KAPPA[256] = {")
     for r in range(0, 256, 16):
         w("    " + ", ".join("%d" % table[c]["kappa"] for c in range(r, r + 16)) + ",")
     w("};")

@@ -1,0 +1,572 @@
+// mesh.hip -- the marching-cubes mesh pass (paper Sec. 2, "Marching cubes
+// fused parallel kernels"): cube classification, vertex counting and
+// emission, surface area and signed volume.
+//
+// Each thread owns 32 consecutive cubes along axis 2 of one cube row and
+// marches through kTZ cube planes along axis 0, keeping the previous voxel
+// plane's two rows as bit masks; every mask byte (or float) is turned into a
+// bit once per row it borders.  Crossing edges and active cubes come from
+// bitwise operations on eight 32-bit corner masks; only active cubes (a few
+// percent) touch the case tables.
+//
+// Area and volume (binary masks): vertices sit at edge midpoints, so each
+// case's area is a fixed number for the call's spacing and its volume term is
+// an integer in units of s0*s1*s2/48 (see gen_mc_table.py).  The binary pass
+// therefore accumulates the volume exactly in int64 and the area as FP64
+// sums in a fixed order.  Soft masks evaluate every triangle in FP64.
+#include <hip/hip_runtime.h>
+
+#define MC_TABLE_QUAL __constant__ const
+#include "mc_table.h"
+#include "s3d_device.h"
+#include "s3d_launch.h"
+
+namespace s3d {
+
+// ---------------------------------------------------------------------------
+// Row loaders: bits of voxels [32l, 32l + 32) of row (z, y), and the bit of
+// voxel 32l - 1.  Out-of-range voxels read as outside.
+
+__device__ inline uint32_t nz4(uint32_t w) {
+  // high bit of each byte set iff the byte is nonzero, then gathered to bits 0..3
+  const uint32_t t = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+  return (t * 0x00204081u) >> 28;
+}
+
+template <int DT>
+__device__ inline void load_row(const void* vol, const int* d, int z, int y, int l, uint32_t& bits,
+                                uint32_t& xm1) {
+  bits = 0u;
+  xm1 = 0u;
+  if (z < 0 || z >= d[0] || y < 0 || y >= d[1]) return;
+  const int x0 = 32 * l;
+  int n = d[2] - x0;
+  if (DT == 0) {
+    const uint8_t* row = (const uint8_t*)vol + ((size_t)z * d[1] + y) * (size_t)d[2];
+    if (l > 0) xm1 = row[x0 - 1] != 0;
+    if (n <= 0) return;
+    const uint8_t* p = row + x0;
+    if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
+      const uint4 a = *(const uint4*)p;
+      const uint4 b = *(const uint4*)(p + 16);
+      bits = nz4(a.x) | (nz4(a.y) << 4) | (nz4(a.z) << 8) | (nz4(a.w) << 12) | (nz4(b.x) << 16) |
+             (nz4(b.y) << 20) | (nz4(b.z) << 24) | (nz4(b.w) << 28);
+    } else {
+      if (n > 32) n = 32;
+      for (int i = 0; i < n; ++i) bits |= (uint32_t)(p[i] != 0) << i;
+    }
+  } else {
+    const float* row = (const float*)vol + ((size_t)z * d[1] + y) * (size_t)d[2];
+    if (l > 0) xm1 = row[x0 - 1] > 0.5f;
+    if (n <= 0) return;
+    const float* p = row + x0;
+    if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float4 v = ((const float4*)p)[i];
+        bits |= ((uint32_t)(v.x > 0.5f) | ((uint32_t)(v.y > 0.5f) << 1) | ((uint32_t)(v.z > 0.5f) << 2) |
+                 ((uint32_t)(v.w > 0.5f) << 3))
+                << (4 * i);
+      }
+    } else {
+      if (n > 32) n = 32;
+      for (int i = 0; i < n; ++i) bits |= (uint32_t)(p[i] > 0.5f) << i;
+    }
+  }
+}
+
+__device__ inline double soft_value(const float* vol, const int* d, int z, int y, int x) {
+  if (z < 0 || y < 0 || x < 0 || z >= d[0] || y >= d[1] || x >= d[2]) return 0.0;
+  return (double)vol[((size_t)z * d[1] + y) * (size_t)d[2] + x];
+}
+
+// Thread coordinates inside a brick.
+struct Lane {
+  int y, l;        // cube row (voxel rows y, y+1) and 32-cube group
+  int pz0, pz1;    // cube planes [pz0, pz1) as pz = z + 1
+  uint32_t vmask;  // cubes of this group inside [-1, d2 - 1]
+  bool valid;
+};
+
+__device__ inline Lane lane_of(const Roi& R, long long local_brick, int tid) {
+  Lane L;
+  const int bx = (int)(local_brick / R.nzc), zc = (int)(local_brick % R.nzc);
+  const int rg = bx * kBrickThreads + tid;
+  L.valid = rg < R.nrg;
+  const int ry = L.valid ? rg / R.G : 0;
+  L.l = L.valid ? rg - ry * R.G : 0;
+  L.y = ry - 1;
+  L.pz0 = zc * kTZ;
+  L.pz1 = min(L.pz0 + kTZ, R.d[0] + 1);
+  const int kmax = R.d[2] - 32 * L.l;  // cube x = 32l - 1 + k valid iff k <= kmax
+  L.vmask = kmax >= 31 ? 0xffffffffu : ((1u << (kmax + 1)) - 1u);
+  return L;
+}
+
+// Corner masks of the 32 cubes between voxel planes z (rows r0*) and z + 1
+// (rows r1*); corner c = 4*dz + 2*dy + dx.
+struct Corners {
+  uint32_t c[8];
+};
+
+__device__ inline Corners make_corners(uint32_t r00, uint32_t x00, uint32_t r01, uint32_t x01, uint32_t r10,
+                                       uint32_t x10, uint32_t r11, uint32_t x11) {
+  Corners C;
+  C.c[0] = (r00 << 1) | x00;
+  C.c[1] = r00;
+  C.c[2] = (r01 << 1) | x01;
+  C.c[3] = r01;
+  C.c[4] = (r10 << 1) | x10;
+  C.c[5] = r10;
+  C.c[6] = (r11 << 1) | x11;
+  C.c[7] = r11;
+  return C;
+}
+
+__device__ inline int case_of(const Corners& C, int k) {
+  int cas = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) cas |= (int)((C.c[c] >> k) & 1u) << c;
+  return cas;
+}
+
+// ---------------------------------------------------------------------------
+// Count pass.
+
+template <int DT>
+__global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restrict__ rois, int n_rois,
+                                                              long long nbricks, BrickPart* __restrict__ part) {
+  __shared__ double s_area[256];
+  __shared__ int s_tk[256];
+  __shared__ int s_tm[256];
+  __shared__ double s_rd[2][4];
+  __shared__ long long s_rl[4];
+  __shared__ int s_ri[8][4];
+
+  const long long brick = xcd_remap(blockIdx.x, nbricks);
+  const int roi = find_roi(rois, n_rois, brick);
+  const Roi R = rois[roi];
+  const int tid = threadIdx.x;
+  {
+    const int c = tid;
+    const int nt = MC_NTRI[c];
+    double a = 0.0;
+    if (DT == 0) {
+      for (int t = 0; t < nt; ++t) {
+        const double n0 = R.s[1] * R.s[2] * MC_TRI_N[c][t][0];
+        const double n1 = R.s[0] * R.s[2] * MC_TRI_N[c][t][1];
+        const double n2 = R.s[0] * R.s[1] * MC_TRI_N[c][t][2];
+        a += 0.125 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+      }
+    }
+    s_area[c] = a;
+    s_tk[c] = nt | ((MC_CASE_KAPPA[c] + 128) << 8);
+    s_tm[c] = (MC_CASE_M[c][0] + 128) | ((MC_CASE_M[c][1] + 128) << 8) | ((MC_CASE_M[c][2] + 128) << 16);
+  }
+  __syncthreads();
+
+  const Lane L = lane_of(R, brick - R.brick_begin, tid);
+  int nv = 0, nt = 0;
+  double area = 0.0, vol_d = 0.0;
+  long long vol_i = 0;
+  int bb[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  // origin of the soft tetrahedron sum: the array centre (as the FP64 oracle uses)
+  const double o0 = 0.5 * R.d[0] * R.s[0], o1 = 0.5 * R.d[1] * R.s[1], o2 = 0.5 * R.d[2] * R.s[2];
+
+  if (L.valid) {
+    uint32_t r00, x00, r01, x01;
+    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y, L.l, r00, x00);
+    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y + 1, L.l, r01, x01);
+    for (int pz = L.pz0; pz < L.pz1; ++pz) {
+      const int z = pz - 1;
+      uint32_t r10, x10, r11, x11;
+      load_row<DT>(R.vol, R.d, z + 1, L.y, L.l, r10, x10);
+      load_row<DT>(R.vol, R.d, z + 1, L.y + 1, L.l, r11, x11);
+      const Corners C = make_corners(r00, x00, r01, x01, r10, x10, r11, x11);
+      uint32_t any = 0u, all = 0xffffffffu;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        any |= C.c[c];
+        all &= C.c[c];
+      }
+      nv += __popc((C.c[0] ^ C.c[4]) & L.vmask) + __popc((C.c[0] ^ C.c[2]) & L.vmask) +
+            __popc((C.c[0] ^ C.c[1]) & L.vmask);
+      uint32_t active = any & ~all & L.vmask;
+      while (active) {
+        const int k = __ffs(active) - 1;
+        active &= active - 1u;
+        const int cas = case_of(C, k);
+        const int x = 32 * L.l - 1 + k;
+        const int tk = s_tk[cas];
+        nt += tk & 0xff;
+        bb[0] = min(bb[0], z);
+        bb[1] = min(bb[1], L.y);
+        bb[2] = min(bb[2], x);
+        bb[3] = max(bb[3], z);
+        bb[4] = max(bb[4], L.y);
+        bb[5] = max(bb[5], x);
+        if (DT == 0) {
+          const int tm = s_tm[cas];
+          area += s_area[cas];
+          vol_i += (long long)((tk >> 8) - 128) +
+                   2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)L.y * (((tm >> 8) & 0xff) - 128) +
+                          (long long)x * (((tm >> 16) & 0xff) - 128));
+        } else {
+          const float* pv = (const float*)R.vol;
+          double pc[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) pc[c] = soft_value(pv, R.d, z + ((c >> 2) & 1), L.y + ((c >> 1) & 1), x + (c & 1));
+          const int ntri = tk & 0xff;
+          for (int t = 0; t < ntri; ++t) {
+            double P[3][3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+              const int e = MC_TRI[cas][t][v];
+              const int a = MC_EDGE_AXIS[e], c0 = MC_EDGE_C0[e];
+              const int c1 = c0 | (4 >> a);
+              const double tt = (0.5 - pc[c0]) / (pc[c1] - pc[c0]);
+              const int u0 = z + ((c0 >> 2) & 1), u1 = L.y + ((c0 >> 1) & 1), u2 = x + (c0 & 1);
+              P[v][0] = ((double)u0 + (a == 0 ? tt : 0.0)) * R.s[0] - o0;
+              P[v][1] = ((double)u1 + (a == 1 ? tt : 0.0)) * R.s[1] - o1;
+              P[v][2] = ((double)u2 + (a == 2 ? tt : 0.0)) * R.s[2] - o2;
+            }
+            const double e1x = P[1][0] - P[0][0], e1y = P[1][1] - P[0][1], e1z = P[1][2] - P[0][2];
+            const double e2x = P[2][0] - P[0][0], e2y = P[2][1] - P[0][1], e2z = P[2][2] - P[0][2];
+            const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+            area += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+            const double bcx = P[1][1] * P[2][2] - P[1][2] * P[2][1];
+            const double bcy = P[1][2] * P[2][0] - P[1][0] * P[2][2];
+            const double bcz = P[1][0] * P[2][1] - P[1][1] * P[2][0];
+            vol_d += (P[0][0] * bcx + P[0][1] * bcy + P[0][2] * bcz) / 6.0;
+          }
+        }
+      }
+      r00 = r10;
+      x00 = x10;
+      r01 = r11;
+      x01 = x11;
+    }
+  }
+
+  // fixed-order block reduction
+  const int lane = tid & 63, wid = tid >> 6;
+  nv = wave_sum(nv);
+  nt = wave_sum(nt);
+  area = wave_sum(area);
+  vol_d = wave_sum(vol_d);
+  vol_i = wave_sum(vol_i);
+  for (int k = 0; k < 3; ++k) {
+    bb[k] = wave_min(bb[k]);
+    bb[3 + k] = wave_max(bb[3 + k]);
+  }
+  if (lane == 0) {
+    s_ri[0][wid] = nv;
+    s_ri[1][wid] = nt;
+    for (int k = 0; k < 6; ++k) s_ri[2 + k][wid] = bb[k];
+    s_rd[0][wid] = area;
+    s_rd[1][wid] = vol_d;
+    s_rl[wid] = vol_i;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    BrickPart P;
+    P.nv = s_ri[0][0] + s_ri[0][1] + s_ri[0][2] + s_ri[0][3];
+    P.nt = s_ri[1][0] + s_ri[1][1] + s_ri[1][2] + s_ri[1][3];
+    for (int k = 0; k < 3; ++k) {
+      P.bb[k] = min(min(s_ri[2 + k][0], s_ri[2 + k][1]), min(s_ri[2 + k][2], s_ri[2 + k][3]));
+      P.bb[3 + k] = max(max(s_ri[5 + k][0], s_ri[5 + k][1]), max(s_ri[5 + k][2], s_ri[5 + k][3]));
+    }
+    P.area = ((s_rd[0][0] + s_rd[0][1]) + s_rd[0][2]) + s_rd[0][3];
+    P.vol_d = ((s_rd[1][0] + s_rd[1][1]) + s_rd[1][2]) + s_rd[1][3];
+    P.vol_i = s_rl[0] + s_rl[1] + s_rl[2] + s_rl[3];
+    part[brick] = P;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-ROI totals: exclusive scan of brick vertex counts, fixed-order sums.
+// One 1024-thread workgroup per ROI.
+
+__global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ rois, int n_rois, long long nbricks,
+                                                      int dtype, const BrickPart* __restrict__ part,
+                                                      long long* __restrict__ brick_voff, RoiMeta* __restrict__ meta) {
+  __shared__ long long s_l[2][1024];
+  __shared__ double s_d[2][1024];
+  __shared__ int s_b[6][1024];
+  const int r = blockIdx.x, tid = threadIdx.x;
+  const Roi R = rois[r];
+  const long long b0 = R.brick_begin, b1 = (r + 1 < n_rois) ? rois[r + 1].brick_begin : nbricks;
+  const long long n = b1 - b0;
+  const long long chunk = (n + 1023) / 1024;
+  const long long lo = b0 + min(n, chunk * tid), hi = b0 + min(n, chunk * (tid + 1));
+  long long nv = 0, nt = 0, vi = 0;
+  double area = 0.0, vd = 0.0;
+  int bb[6] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN};
+  for (long long b = lo; b < hi; ++b) {
+    const BrickPart P = part[b];
+    nv += P.nv;
+    nt += P.nt;
+    vi += P.vol_i;
+    area += P.area;
+    vd += P.vol_d;
+    for (int k = 0; k < 3; ++k) {
+      bb[k] = min(bb[k], P.bb[k]);
+      bb[3 + k] = max(bb[3 + k], P.bb[3 + k]);
+    }
+  }
+  // exclusive scan of nv over threads (Hillis-Steele in shared memory)
+  s_l[0][tid] = nv;
+  __syncthreads();
+  int src = 0;
+  for (int d = 1; d < 1024; d <<= 1) {
+    long long v = s_l[src][tid];
+    if (tid >= d) v += s_l[src][tid - d];
+    s_l[1 - src][tid] = v;
+    __syncthreads();
+    src = 1 - src;
+  }
+  long long off = s_l[src][tid] - nv;
+  for (long long b = lo; b < hi; ++b) {
+    brick_voff[b] = off;
+    off += part[b].nv;
+  }
+  const long long V = s_l[src][1023];
+  __syncthreads();
+  // fixed-order tree reductions
+  s_l[0][tid] = nt;
+  s_l[1][tid] = vi;
+  s_d[0][tid] = area;
+  s_d[1][tid] = vd;
+  for (int k = 0; k < 6; ++k) s_b[k][tid] = bb[k];
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (tid < w) {
+      s_l[0][tid] += s_l[0][tid + w];
+      s_l[1][tid] += s_l[1][tid + w];
+      s_d[0][tid] += s_d[0][tid + w];
+      s_d[1][tid] += s_d[1][tid + w];
+      for (int k = 0; k < 3; ++k) {
+        s_b[k][tid] = min(s_b[k][tid], s_b[k][tid + w]);
+        s_b[3 + k][tid] = max(s_b[3 + k][tid], s_b[3 + k][tid + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    RoiMeta M;
+    M.V = V;
+    M.T = s_l[0][0];
+    M.row_off = 0;
+    M.V_pad = (V + kSegAlign - 1) / kSegAlign * kSegAlign;
+    M.area = s_d[0][0];
+    M.vol = dtype == 0 ? (double)s_l[1][0] * (R.s[0] * R.s[1] * R.s[2] / 48.0) : s_d[1][0];
+    double R2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      M.bb[k] = s_b[k][0];
+      M.bb[3 + k] = s_b[3 + k][0];
+      if (V > 0) {
+        M.center[k] = 0.5 * (double)(M.bb[k] + M.bb[3 + k] + 1) * R.s[k];
+        const double h = 0.5 * (double)(M.bb[3 + k] - M.bb[k] + 1) * R.s[k];
+        R2 += h * h;
+      } else {
+        M.center[k] = 0.0;
+      }
+    }
+    M.R2 = R2;
+    meta[r] = M;
+  }
+}
+
+// Layout-0 row offsets of the ROIs (exclusive scan of V_pad), one workgroup.
+__global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restrict__ meta,
+                                                   long long* __restrict__ totals) {
+  __shared__ long long s[2][1024];
+  const int tid = threadIdx.x;
+  const int chunk = (n_rois + 1023) / 1024;
+  const int lo = min(n_rois, chunk * tid), hi = min(n_rois, chunk * (tid + 1));
+  long long sum = 0, vmax = 0;
+  for (int r = lo; r < hi; ++r) {
+    sum += meta[r].V_pad;
+    vmax = max(vmax, meta[r].V);
+  }
+  s[0][tid] = sum;
+  __syncthreads();
+  int src = 0;
+  for (int d = 1; d < 1024; d <<= 1) {
+    long long v = s[src][tid];
+    if (tid >= d) v += s[src][tid - d];
+    s[1 - src][tid] = v;
+    __syncthreads();
+    src = 1 - src;
+  }
+  long long off = s[src][tid] - sum;
+  for (int r = lo; r < hi; ++r) {
+    meta[r].row_off = off;
+    off += meta[r].V_pad;
+  }
+  const long long rows0 = s[src][1023];
+  __syncthreads();
+  s[0][tid] = vmax;
+  __syncthreads();
+  for (int w = 512; w >= 1; w >>= 1) {
+    if (tid < w) s[0][tid] = max(s[0][tid], s[0][tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    totals[0] = rows0;
+    totals[1] = s[0][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Emission pass: the same classification, writing each crossing edge's vertex
+// at its deterministic row (brick order, then plane, thread, axis, cube).
+
+template <int DT>
+__global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restrict__ rois, int n_rois,
+                                                             long long nbricks, const BrickPart* __restrict__ part,
+                                                             const long long* __restrict__ brick_voff,
+                                                             const RoiMeta* __restrict__ meta,
+                                                             unsigned long long* __restrict__ key,
+                                                             double* __restrict__ tsoft, float* __restrict__ pos,
+                                                             int* __restrict__ orig, float* __restrict__ rowmax) {
+  __shared__ int s_scan[4];
+  const long long brick = xcd_remap(blockIdx.x, nbricks);
+  if (part[brick].nv == 0) return;
+  const int roi = find_roi(rois, n_rois, brick);
+  const Roi R = rois[roi];
+  const RoiMeta M = meta[roi];
+  const int tid = threadIdx.x;
+  const Lane L = lane_of(R, brick - R.brick_begin, tid);
+  long long base = M.row_off + brick_voff[brick];
+
+  uint32_t r00 = 0, x00 = 0, r01 = 0, x01 = 0;
+  if (L.valid) {
+    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y, L.l, r00, x00);
+    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y + 1, L.l, r01, x01);
+  }
+  // every thread of the brick runs the same number of steps (block scans inside)
+  const int steps = min(kTZ, R.d[0] + 1 - (int)(((brick - R.brick_begin) % R.nzc) * kTZ));
+  for (int st = 0; st < steps; ++st) {
+    const int z = L.pz0 + st - 1;
+    uint32_t e[3] = {0u, 0u, 0u};
+    uint32_t r10 = 0, x10 = 0, r11 = 0, x11 = 0;
+    if (L.valid) {
+      load_row<DT>(R.vol, R.d, z + 1, L.y, L.l, r10, x10);
+      load_row<DT>(R.vol, R.d, z + 1, L.y + 1, L.l, r11, x11);
+      const Corners C = make_corners(r00, x00, r01, x01, r10, x10, r11, x11);
+      e[0] = (C.c[0] ^ C.c[4]) & L.vmask;
+      e[1] = (C.c[0] ^ C.c[2]) & L.vmask;
+      e[2] = (C.c[0] ^ C.c[1]) & L.vmask;
+    }
+    const int cnt = __popc(e[0]) + __popc(e[1]) + __popc(e[2]);
+    int total;
+    const int off = block_excl_scan256(cnt, s_scan, total);
+    long long row = base + off;
+    for (int a = 0; a < 3; ++a) {
+      uint32_t m = e[a];
+      while (m) {
+        const int k = __ffs(m) - 1;
+        m &= m - 1u;
+        const int u0 = z, u1 = L.y, u2 = 32 * L.l - 1 + k;
+        double t = 0.5;
+        if (DT == 1) {
+          const float* pv = (const float*)R.vol;
+          const double pa = soft_value(pv, R.d, u0, u1, u2);
+          const double pb = soft_value(pv, R.d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
+          t = (0.5 - pa) / (pb - pa);
+          tsoft[row] = t;
+        }
+        key[row] = pack_key(u0, u1, u2, a);
+        const double px = ((double)u0 + (a == 0 ? t : 0.0)) * R.s[0] - M.center[0];
+        const double py = ((double)u1 + (a == 1 ? t : 0.0)) * R.s[1] - M.center[1];
+        const double pz = ((double)u2 + (a == 2 ? t : 0.0)) * R.s[2] - M.center[2];
+        const float fx = (float)px, fy = (float)py, fz = (float)pz;
+        const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
+        float* blk = pos + (row >> 4) * 64 + (row & 15);
+        blk[0] = fx;
+        blk[16] = fy;
+        blk[32] = fz;
+        blk[48] = fw;
+        orig[row] = (int)row;
+        rowmax[row] = 0.0f;
+        ++row;
+      }
+    }
+    base += total;
+    r00 = r10;
+    x00 = x10;
+    r01 = r11;
+    x01 = x11;
+  }
+}
+
+// Pads each ROI's layout-0 rows to V_pad with copies of its first row and
+// tags the ROI's blocks with its 3D segment (segment id = roi).
+__global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, float* __restrict__ pos,
+                              int* __restrict__ orig, float* __restrict__ rowmax, int* __restrict__ blkseg,
+                              Seg* __restrict__ segs) {
+  const int r = blockIdx.x;
+  if (r >= n_rois) return;
+  const RoiMeta M = meta[r];
+  const long long r0 = M.row_off;
+  if (threadIdx.x == 0) {
+    Seg S;
+    S.row_begin = r0;
+    S.n_rows = M.V >= 2 ? (int)M.V_pad : 0;
+    S.group = r * 4;
+    segs[r] = S;
+  }
+  for (long long i = threadIdx.x; i < M.V_pad / kBlk; i += blockDim.x) blkseg[r0 / kBlk + i] = r;
+  if (M.V == 0) return;
+  const float* src = pos + (r0 >> 4) * 64 + (r0 & 15);
+  for (long long row = r0 + M.V + threadIdx.x; row < r0 + M.V_pad; row += blockDim.x) {
+    float* dst = pos + (row >> 4) * 64 + (row & 15);
+    dst[0] = src[0];
+    dst[16] = src[16];
+    dst[32] = src[32];
+    dst[48] = src[48];
+    orig[row] = (int)r0;
+    rowmax[row] = 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, BrickPart* part,
+                             hipStream_t st) {
+  if (nbricks <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_mesh_count<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+                       part);
+  else
+    hipLaunchKernelGGL(k_mesh_count<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+                       part);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
+                              long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st) {
+  hipLaunchKernelGGL(k_mesh_totals, dim3(n_rois), dim3(1024), 0, st, rois, n_rois, nbricks, dtype, part, brick_voff,
+                     meta);
+  hipLaunchKernelGGL(k_roi_rows, dim3(1), dim3(1024), 0, st, n_rois, meta, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, const BrickPart* part,
+                            const long long* brick_voff, const RoiMeta* meta, unsigned long long* key, double* tsoft,
+                            float* pos, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st) {
+  if (nbricks > 0) {
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+                         part, brick_voff, meta, key, tsoft, pos, orig, rowmax);
+    else
+      hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+                         part, brick_voff, meta, key, tsoft, pos, orig, rowmax);
+  }
+  hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, orig, rowmax, blkseg, segs);
+  return hipGetLastError();
+}
+
+}  // namespace s3d

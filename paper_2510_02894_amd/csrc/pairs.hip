@@ -1,0 +1,525 @@
+// pairs.hip -- maximum vertex distances (paper Sec. 2, "Parallel diameter
+// calculation"): the 3D diameter over all vertex pairs and the planar
+// diameters over vertex pairs that share a plane of each axis.
+//
+// Design for CDNA4:
+//   * plane buckets by a counting sort on the plane key 2*u_k + [a == k];
+//     every bucket with two or more vertices becomes a segment, as does each
+//     ROI's whole vertex list, and all segments are processed in one launch;
+//   * squared distances come from the Gram form
+//       d2(i, j) = w_i + w_j - 2 p_i . p_j,  w = |p|^2,
+//     which is a K = 4 contraction [-2x_i, -2y_i, -2z_i, 1] . [x_j, y_j, z_j, w_j]
+//     and maps exactly onto v_mfma_f32_16x16x4_f32: one instruction gives the
+//     256 pair values of a 16 x 16 tile; the VALU keeps per-row running maxima
+//     (v_max3) beside the matrix core;
+//   * a wave owns 8 row blocks (128 rows, kept in registers as A operands)
+//     and streams column blocks of one 4096-row chunk of the upper triangle;
+//     work items are handed out by an atomic counter in column-major order so
+//     concurrently running waves share the column data in L2;
+//   * FP32 row maxima are then refined exactly: every row whose FP32 maximum
+//     lies within a rigorous rounding bound of the group maximum is rescanned
+//     against its whole segment in FP64 (the same operations as the oracle),
+//     which yields the exact maximum and the canonical tie-break.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "s3d_device.h"
+#include "s3d_launch.h"
+
+namespace s3d {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+enum { T_ROWS0 = 0, T_VMAX = 1, T_ROWS2D = 2, T_NSEG2D = 3, T_NCOL = 4, T_NITEM = 5 };
+
+__device__ inline int bucket_roi(const Roi* rois, int n, long long b, int& axis) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (rois[mid].bucket_base[0] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  axis = (b >= rois[lo].bucket_base[2]) ? 2 : (b >= rois[lo].bucket_base[1] ? 1 : 0);
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Plane buckets.
+
+__global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
+                              const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
+                              long long rows0, unsigned int* __restrict__ bcnt) {
+  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
+       row += (long long)gridDim.x * blockDim.x) {
+    const int roi = blkseg[row >> 4];
+    const RoiMeta& M = meta[roi];
+    if (row - M.row_off >= M.V) continue;
+    const unsigned long long k = key[row];
+    const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};  // u + 1
+    const int a = (int)((k >> 60) & 3);
+    for (int ax = 0; ax < 3; ++ax) {
+      const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
+      atomicAdd(&bcnt[b], 1u);
+    }
+  }
+}
+
+__global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long nb, long long* __restrict__ bsz,
+                               long long* __restrict__ bflag) {
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (long long)gridDim.x * blockDim.x) {
+    const unsigned int c = bcnt[b];
+    bsz[b] = c >= 2 ? (long long)((c + kSegAlign - 1) / kSegAlign * kSegAlign) : 0;
+    bflag[b] = c >= 2 ? 1 : 0;
+  }
+}
+
+__global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
+                                 const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
+                                 long long rows0, const unsigned int* __restrict__ bcnt,
+                                 unsigned int* __restrict__ bcur, const long long* __restrict__ brow,
+                                 float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax) {
+  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
+       row += (long long)gridDim.x * blockDim.x) {
+    const int roi = blkseg[row >> 4];
+    const RoiMeta& M = meta[roi];
+    if (row - M.row_off >= M.V) continue;
+    const unsigned long long k = key[row];
+    const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};
+    const int a = (int)((k >> 60) & 3);
+    const float* src = pos + (row >> 4) * 64 + (row & 15);
+    const float sx = src[0], sy = src[16], sz = src[32], sw = src[48];
+    for (int ax = 0; ax < 3; ++ax) {
+      const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
+      if (bcnt[b] < 2) continue;
+      const long long dst_row = rows0 + brow[b] + atomicAdd(&bcur[b], 1u);
+      float* dst = pos + (dst_row >> 4) * 64 + (dst_row & 15);
+      dst[0] = sx;
+      dst[16] = sy;
+      dst[32] = sz;
+      dst[48] = sw;
+      orig[dst_row] = (int)row;
+      rowmax[dst_row] = 0.0f;
+    }
+  }
+}
+
+// Segments of the buckets: pad rows, block tags and the segment table.
+__global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long long nb, long long rows0,
+                             const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
+                             const long long* __restrict__ brow, const long long* __restrict__ bseg,
+                             float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax,
+                             int* __restrict__ blkseg, Seg* __restrict__ segs) {
+  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (long long)gridDim.x * blockDim.x) {
+    const unsigned int c = bcnt[b];
+    if (c < 2) continue;
+    int axis;
+    const int roi = bucket_roi(rois, n_rois, b, axis);
+    const long long sid = n_rois + bseg[b];
+    const long long r0 = rows0 + brow[b];
+    const long long n = bsz[b];
+    Seg S;
+    S.row_begin = r0;
+    S.n_rows = (int)n;
+    S.group = roi * 4 + 1 + axis;
+    segs[sid] = S;
+    for (long long i = 0; i < n / kBlk; ++i) blkseg[r0 / kBlk + i] = (int)sid;
+    const float* src = pos + (r0 >> 4) * 64 + (r0 & 15);
+    const int o = orig[r0];
+    for (long long row = r0 + c; row < r0 + n; ++row) {
+      float* dst = pos + (row >> 4) * 64 + (row & 15);
+      dst[0] = src[0];
+      dst[16] = src[16];
+      dst[32] = src[32];
+      dst[48] = src[48];
+      orig[row] = o;
+      rowmax[row] = 0.0f;
+    }
+  }
+}
+
+// Columns (4096-row chunks) per segment.
+__global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __restrict__ totals,
+                           const Seg* __restrict__ segs, long long* __restrict__ ncol) {
+  const long long nseg = n_rois + totals[T_NSEG2D];
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < seg_cap;
+       s += (long long)gridDim.x * blockDim.x) {
+    const long long rows = s < nseg ? segs[s].n_rows : 0;
+    ncol[s] = (rows + kJchunkBlocks * kBlk - 1) / (kJchunkBlocks * kBlk);
+  }
+}
+
+// Column table and items per column: items of column jc of a segment are the
+// 128-row tiles that start before the column ends (upper triangle).
+__global__ void k_col_fill(int n_rois, long long seg_cap, const long long* __restrict__ totals,
+                           const Seg* __restrict__ segs, const long long* __restrict__ ncol,
+                           const long long* __restrict__ colbase, Col* __restrict__ cols,
+                           long long* __restrict__ nitem) {
+  const long long nseg = n_rois + totals[T_NSEG2D];
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += (long long)gridDim.x * blockDim.x) {
+    const long long nc = ncol[s];
+    if (nc == 0) continue;
+    const long long nblk = segs[s].n_rows / kBlk;
+    const long long nt = (nblk + kItileBlocks - 1) / kItileBlocks;
+    for (long long jc = 0; jc < nc; ++jc) {
+      const long long c = colbase[s] + jc;
+      Col C;
+      C.seg = (int)s;
+      C.jc = (int)jc;
+      cols[c] = C;
+      const long long lim = (jc + 1) * (kJchunkBlocks / kItileBlocks);
+      nitem[c] = nt < lim ? nt : lim;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair maxima on the matrix cores.
+
+// 16 MFMAs: the 8 row blocks against two column blocks, folded into the
+// running row maxima with v_max3.
+__device__ __forceinline__ void pair_tile(const float (&A)[kItileBlocks], float b0, float b1,
+                                          v4f (&acc)[kItileBlocks]) {
+  const v4f zero = {0.f, 0.f, 0.f, 0.f};
+  v4f d[2 * kItileBlocks];
+#pragma unroll
+  for (int r = 0; r < kItileBlocks; ++r) {
+    d[2 * r] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], b0, zero, 0, 0, 0);
+    d[2 * r + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], b1, zero, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < kItileBlocks; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = fmaxf(acc[r][q], fmaxf(d[2 * r][q], d[2 * r + 1][q]));
+}
+
+__global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ pos, const Seg* __restrict__ segs,
+                                                     const Col* __restrict__ cols,
+                                                     const long long* __restrict__ itembase,
+                                                     const long long* __restrict__ totals,
+                                                     unsigned int* __restrict__ work_ctr, float* __restrict__ rowmax) {
+  const int lane = threadIdx.x & 63;
+  const long long n_items = totals[T_NITEM];
+  const long long ncol = totals[T_NCOL];
+  for (;;) {
+    unsigned int got = 0;
+    if (lane == 0) got = atomicAdd(work_ctr, 1u);
+    const long long item = (long long)__builtin_amdgcn_readfirstlane((int)__shfl(got, 0, 64));
+    if (item >= n_items) break;
+    long long lo = 0, hi = ncol - 1;
+    while (lo < hi) {
+      const long long mid = (lo + hi + 1) >> 1;
+      if (itembase[mid] <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const Col C = cols[lo];
+    const Seg S = segs[C.seg];
+    const int it = (int)(item - itembase[lo]);
+    const long long rb = S.row_begin >> 4;
+    const int nb = S.n_rows >> 4;
+    const int i0 = it * kItileBlocks;
+    const int j0 = max(C.jc * kJchunkBlocks, i0);
+    const int j1 = min((C.jc + 1) * kJchunkBlocks, nb);
+
+    float A[kItileBlocks];
+#pragma unroll
+    for (int r = 0; r < kItileBlocks; ++r) {
+      const int blk = min(i0 + r, nb - 1);
+      const float v = pos[(rb + blk) * 64 + lane];
+      A[r] = lane < 48 ? -2.0f * v : 1.0f;
+    }
+    v4f acc[kItileBlocks];
+#pragma unroll
+    for (int r = 0; r < kItileBlocks; ++r) acc[r] = v4f{-3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
+
+    // Column blocks are consumed in pairs; two pairs are kept in flight
+    // (double buffering).  Prefetch addresses are clamped to the last pair of
+    // the range so every load stays inside the segment, and a clamped pair is
+    // simply processed twice.
+    const float* B = pos + rb * 64 + lane;
+    float b0 = B[j0 * 64], b1 = B[(j0 + 1) * 64];
+    for (int jb = j0; jb < j1; jb += 4) {
+      const int jn = min(jb + 2, j1 - 2);
+      const float c0 = B[jn * 64], c1 = B[(jn + 1) * 64];
+      pair_tile(A, b0, b1, acc);
+      const int jm = min(jb + 4, j1 - 2);
+      b0 = B[jm * 64];
+      b1 = B[(jm + 1) * 64];
+      pair_tile(A, c0, c1, acc);  // repeats the last pair when the pair count is odd: harmless for a max
+    }
+    // D[i][j] sits in lane 16*(i/4) + j, register i%4: reduce over j (the low 4 lane bits)
+#pragma unroll
+    for (int r = 0; r < kItileBlocks; ++r) {
+      if (i0 + r >= nb) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float m = acc[r][q];
+        m = fmaxf(m, __shfl_xor(m, 1, 64));
+        m = fmaxf(m, __shfl_xor(m, 2, 64));
+        m = fmaxf(m, __shfl_xor(m, 4, 64));
+        m = fmaxf(m, __shfl_xor(m, 8, 64));
+        if ((lane & 15) == q) {
+          const long long row = (rb + i0 + r) * 16 + 4 * (lane >> 4) + q;
+          const float w = pos[(rb + i0 + r) * 64 + 48 + 4 * (lane >> 4) + q];
+          const float val = fmaxf(m + w, 0.0f);
+          atomicMax((int*)&rowmax[row], __float_as_int(val));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact refinement.
+
+__global__ void k_group_max(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
+                            const Seg* __restrict__ segs, const long long* __restrict__ totals,
+                            GroupRes* __restrict__ gres) {
+  const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
+  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
+       row += (long long)gridDim.x * blockDim.x) {
+    const int s = blkseg[row >> 4];
+    const int g = s >= 0 ? segs[s].group : -1;
+    const float v = rowmax[row];
+    if (g >= 0) atomicMax((int*)&gres[g].gmax, __float_as_int(v));
+  }
+}
+
+__global__ void k_candidates(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
+                             const Seg* __restrict__ segs, const RoiMeta* __restrict__ meta,
+                             const long long* __restrict__ totals, GroupRes* __restrict__ gres,
+                             unsigned int* __restrict__ ncand, int* __restrict__ cand) {
+  const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
+  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
+       row += (long long)gridDim.x * blockDim.x) {
+    const int s = blkseg[row >> 4];
+    if (s < 0) continue;
+    const Seg S = segs[s];
+    if (row - S.row_begin >= S.n_rows || S.n_rows == 0) continue;
+    const int g = S.group;
+    const float gm = gres[g].gmax;
+    if (!(gm > 0.0f)) continue;
+    // The FP32 Gram value of a pair differs from its exact squared distance
+    // by less than 2^-18 * max(R^2, d2) (coordinate rounding plus at most six
+    // FP32 roundings of terms bounded by 4 R^2); keep every row within twice
+    // that of the group maximum.
+    const double R2 = meta[g >> 2].R2;
+    const float tau = (float)((double)gm - 7.62939453125e-06 * (R2 > (double)gm ? R2 : (double)gm));
+    if (rowmax[row] >= tau) {
+      const unsigned int idx = atomicAdd(ncand, 1u);
+      if (idx < (unsigned int)kMaxCand) cand[idx] = (int)row;
+      atomicAdd(&gres[g].n_cand, 1);
+    }
+  }
+}
+
+template <int PASS>
+__global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
+                                               const int* __restrict__ blkseg, const Seg* __restrict__ segs,
+                                               const int* __restrict__ orig, const unsigned long long* __restrict__ key,
+                                               const double* __restrict__ tsoft, const Roi* __restrict__ rois,
+                                               long long max_chunks, GroupRes* __restrict__ gres) {
+  __shared__ unsigned long long sh[4];
+  const unsigned int nc = min(*ncand_p, (unsigned int)kMaxCand);
+  const long long n_work = (long long)nc * max_chunks;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (long long w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const int row_i = cand[w / max_chunks];
+    const long long chunk = w % max_chunks;
+    const Seg S = segs[blkseg[row_i >> 4]];
+    const long long jb = S.row_begin + chunk * kExactChunk;
+    const long long je = min(jb + (long long)kExactChunk, S.row_begin + (long long)S.n_rows);
+    if (jb >= je) continue;
+    const int g = S.group;
+    const Roi& R = rois[g >> 2];
+    const int vi = orig[row_i];
+    const unsigned long long ki = key[vi];
+    double pi[3];
+    key_position(ki, tsoft ? tsoft[vi] : 0.5, R.s, pi);
+    const unsigned long long idi = key_canonical_id(ki, R.d);
+    const double target = __longlong_as_double((long long)gres[g].best_bits);
+    const unsigned long long lo_ref = gres[g].id_lo, hi_ref = gres[g].id_hi;
+    unsigned long long red = PASS == 0 ? 0ull : ~0ull;
+    for (long long j = jb + tid; j < je; j += 256) {
+      const int vj = orig[j];
+      const unsigned long long kj = key[vj];
+      double pj[3];
+      key_position(kj, tsoft ? tsoft[vj] : 0.5, R.s, pj);
+      const double d2 = dist2_exact(pi, pj);
+      if (PASS == 0) {
+        red = max(red, (unsigned long long)__double_as_longlong(d2));
+      } else if (vi != vj && d2 == target) {
+        const unsigned long long idj = key_canonical_id(kj, R.d);
+        const unsigned long long lo = min(idi, idj), hi = max(idi, idj);
+        if (PASS == 1) red = min(red, lo);
+        if (PASS == 2 && lo == lo_ref) red = min(red, hi);
+        if (PASS == 3 && lo == lo_ref && hi == hi_ref) {
+          gres[g].row_i = idi == lo ? vi : vj;
+          gres[g].row_j = idi == lo ? vj : vi;
+        }
+      }
+    }
+    if (PASS == 3) continue;
+    for (int m = 32; m >= 1; m >>= 1) {
+      const unsigned long long o = __shfl_xor(red, m, 64);
+      red = PASS == 0 ? max(red, o) : min(red, o);
+    }
+    __syncthreads();
+    if (lane == 0) sh[wid] = red;
+    __syncthreads();
+    if (tid == 0) {
+      for (int k = 1; k < 4; ++k) red = PASS == 0 ? max(red, sh[k]) : min(red, sh[k]);
+      red = PASS == 0 ? max(red, sh[0]) : min(red, sh[0]);
+      if (PASS == 0) atomicMax(&gres[g].best_bits, red);
+      if (PASS == 1) atomicMin(&gres[g].id_lo, red);
+      if (PASS == 2) atomicMin(&gres[g].id_hi, red);
+    }
+  }
+}
+
+__global__ void k_init_groups(GroupRes* gres, long long n) {
+  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (long long)gridDim.x * blockDim.x) {
+    GroupRes G;
+    G.best_bits = 0ull;
+    G.id_lo = ~0ull;
+    G.id_hi = ~0ull;
+    G.row_i = -1;
+    G.row_j = -1;
+    G.gmax = 0.0f;
+    G.n_cand = 0;
+    gres[g] = G;
+  }
+}
+
+__global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const GroupRes* __restrict__ gres,
+                           const unsigned int* __restrict__ ncand, const unsigned long long* __restrict__ key,
+                           const Roi* __restrict__ rois, RoiResult* __restrict__ res) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
+    const RoiMeta M = meta[r];
+    RoiResult Q;
+    Q.V = M.V;
+    Q.T = M.T;
+    Q.pairs2d = 0;
+    Q.out[0] = fabs(M.vol);
+    Q.out[1] = M.area;
+    for (int f = 0; f < 4; ++f) {
+      const GroupRes G = gres[4 * r + f];
+      const double d2 = __longlong_as_double((long long)G.best_bits);
+      Q.out[2 + f] = sqrt(d2);
+      const bool have = G.id_lo != ~0ull;
+      Q.ids[f][0] = have ? (long long)G.id_lo : -1;
+      Q.ids[f][1] = have ? (long long)G.id_hi : -1;
+      Q.rows[f][0] = have ? G.row_i : -1;
+      Q.rows[f][1] = have ? G.row_j : -1;
+      Q.cand[f] = G.n_cand;
+    }
+    Q.status = M.V == 0 ? 1 : 0;
+    if (*ncand > (unsigned int)kMaxCand) Q.status = -4;
+    Q.pad_ = 0;
+    res[r] = Q;
+  }
+}
+
+__global__ void k_export_vertices(const unsigned long long* __restrict__ key, const double* __restrict__ tsoft,
+                                  const Roi* __restrict__ rois, long long V, long long* __restrict__ ids,
+                                  double* __restrict__ pos) {
+  const Roi R = rois[0];
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x) {
+    ids[v] = (long long)key_canonical_id(key[v], R.d);
+    if (pos) {
+      double x[3];
+      key_position(key[v], tsoft ? tsoft[v] : 0.5, R.s, x);
+      pos[3 * v] = x[0];
+      pos[3 * v + 1] = x[1];
+      pos[3 * v + 2] = x[2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static unsigned grid_for(long long n, long long cap = 8192) {
+  long long g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_fill_u32(B.bcnt, 0u, B.n_buckets, st))) return e;
+  if ((e = launch_fill_u32(B.bcur, 0u, B.n_buckets, st))) return e;
+  hipLaunchKernelGGL(k_bucket_hist, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
+                     B.rows0, B.bcnt);
+  hipLaunchKernelGGL(k_bucket_sizes, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.bcnt, B.n_buckets, B.bsz,
+                     B.bflag);
+  if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;
+  if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
+                     B.rows0, B.bcnt, B.bcur, B.brow, B.pos, B.orig, B.rowmax);
+  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
+                     B.rows0, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs);
+  hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
+                     B.ncol);
+  if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
+  if ((e = launch_fill_i64(B.nitem, 0, B.col_cap, st))) return e;
+  hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
+                     B.ncol, B.colbase, B.cols, B.nitem);
+  if ((e = launch_scan(B.nitem, B.itembase, B.col_cap, B.totals + T_NITEM, B.scan_tmp, st))) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_fill_u32(B.counters, 0u, 2, st))) return e;
+  int per_cu = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_maxima, 256, 0))) return e;
+  const unsigned grid = (unsigned)(B.cu_count * (per_cu > 0 ? per_cu : 1));
+  hipLaunchKernelGGL(k_pair_maxima, dim3(grid), dim3(256), 0, st, B.pos, B.segs, B.cols, B.itembase, B.totals,
+                     B.counters, B.rowmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_groups, dim3(grid_for(4ll * B.n_rois)), dim3(256), 0, st, B.gres, 4ll * B.n_rois);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
+                     B.totals, B.gres);
+  hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
+                     B.meta, B.totals, B.gres, B.counters + 1, B.cand);
+  const long long max_chunks = (B.max_rows_seg + kExactChunk - 1) / kExactChunk;
+  const unsigned grid = 1024;
+  hipLaunchKernelGGL(k_exact<0>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
+                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
+  hipLaunchKernelGGL(k_exact<1>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
+                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
+  hipLaunchKernelGGL(k_exact<2>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
+                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
+  hipLaunchKernelGGL(k_exact<3>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
+                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const PairBufs& B, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(B.n_rois)), dim3(256), 0, st, B.n_rois, B.meta, B.gres,
+                     B.counters + 1, B.key, B.rois, B.res);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_vertices(const unsigned long long* key, const double* tsoft, const RoiMeta* meta,
+                                  const Roi* rois, long long* ids, double* pos, long long V, hipStream_t st) {
+  (void)meta;
+  if (V <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export_vertices, dim3(grid_for(V)), dim3(256), 0, st, key, tsoft, rois, V, ids, pos);
+  return hipGetLastError();
+}
+
+}  // namespace s3d

@@ -1,0 +1,96 @@
+// s3d_device.h -- device helpers shared by the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "s3d_internal.h"
+
+namespace s3d {
+
+// Maps a workgroup index to a work index so that each of the 8 XCDs (which
+// receive workgroups round-robin) walks one contiguous range of work indices:
+// neighbouring bricks then share that XCD's L2.  A bijection on [0, n).
+__device__ inline long long xcd_remap(long long bid, long long n) {
+  const long long per = n / 8, rem = n % 8;
+  const long long x = bid % 8, idx = bid / 8;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
+// Index of the last ROI whose first brick is <= b (ROIs are sorted by brick_begin).
+__device__ inline int find_roi(const Roi* rois, int n, long long b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (rois[mid].brick_begin <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// Exclusive prefix sum over a 256-thread block; `total` receives the block sum.
+// `sh` must hold 4 ints of shared memory.  Contains barriers.
+__device__ inline int block_excl_scan256(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) sh[wid] = inc;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wid; ++w) base += sh[w];
+  total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return base + inc - v;
+}
+
+// Exact FP64 squared distance in a fixed operation order (no contraction).
+__device__ inline double dist2_exact(const double* p, const double* q) {
+  double dx = __dsub_rn(p[0], q[0]), dy = __dsub_rn(p[1], q[1]), dz = __dsub_rn(p[2], q[2]);
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Physical FP64 position of a vertex from its key and interpolation parameter,
+// ((double)u_k + [k == a] * t) * s_k, in that operation order.
+__device__ inline void key_position(uint64_t key, double t, const double* s, double* x) {
+  const int u2 = (int)(key & 0xFFFFF) - 1;
+  const int u1 = (int)((key >> 20) & 0xFFFFF) - 1;
+  const int u0 = (int)((key >> 40) & 0xFFFFF) - 1;
+  const int a = (int)((key >> 60) & 3);
+  x[0] = __dmul_rn(__dadd_rn((double)u0, a == 0 ? t : 0.0), s[0]);
+  x[1] = __dmul_rn(__dadd_rn((double)u1, a == 1 ? t : 0.0), s[1]);
+  x[2] = __dmul_rn(__dadd_rn((double)u2, a == 2 ? t : 0.0), s[2]);
+}
+
+// Canonical id 3 * lin_pad(u) + a of a vertex key for a ROI of dims d.
+__device__ inline unsigned long long key_canonical_id(uint64_t key, const int* d) {
+  const unsigned long long p2 = key & 0xFFFFF, p1 = (key >> 20) & 0xFFFFF, p0 = (key >> 40) & 0xFFFFF;
+  const unsigned long long a = (key >> 60) & 3;
+  const unsigned long long lin = (p0 * (unsigned long long)(d[1] + 2) + p1) * (unsigned long long)(d[2] + 2) + p2;
+  return 3ull * lin + a;
+}
+
+}  // namespace s3d

@@ -1,0 +1,85 @@
+// s3d_launch.h -- host-side launchers of the kernels (one per pipeline step).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "s3d_internal.h"
+
+namespace s3d {
+
+// Per-ROI result record written by the finalisation kernel.
+struct RoiResult {
+  double out[6];
+  long long V, T;
+  long long ids[4][2];
+  long long rows[4][2];
+  long long cand[4];
+  long long pairs2d;
+  int status;
+  int pad_;
+};
+
+// mesh.hip
+hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, BrickPart* part,
+                             hipStream_t st);
+hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
+                              long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st);
+hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, const BrickPart* part,
+                            const long long* brick_voff, const RoiMeta* meta, unsigned long long* key, double* tsoft,
+                            float* pos, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
+
+// scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
+// tmp must hold scan_tmp_elems(n) int64.
+long long scan_tmp_elems(long long n);
+hipError_t launch_scan(const long long* in, long long* out, long long n, long long* total, long long* tmp,
+                       hipStream_t st);
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t st);
+hipError_t launch_fill_i64(long long* p, long long v, long long n, hipStream_t st);
+
+// Buffers of the diameter passes.
+struct PairBufs {
+  const Roi* rois;
+  int n_rois;
+  const RoiMeta* meta;
+  const unsigned long long* key;
+  const double* tsoft;  // null for binary masks
+  float* pos;
+  int* orig;
+  float* rowmax;
+  int* blkseg;
+  Seg* segs;
+  long long rows0;      // layout-0 rows (host copy)
+  long long n_buckets;  // plane buckets of all ROIs
+  unsigned int* bcnt;   // [n_buckets]
+  unsigned int* bcur;   // [n_buckets]
+  long long* bsz;       // [n_buckets]
+  long long* bflag;     // [n_buckets]
+  long long* brow;      // [n_buckets]
+  long long* bseg;      // [n_buckets]
+  long long seg_cap;    // n_rois + n_buckets
+  long long* ncol;      // [seg_cap]
+  long long* colbase;   // [seg_cap]
+  long long col_cap;
+  Col* cols;            // [col_cap]
+  long long* nitem;     // [col_cap]
+  long long* itembase;  // [col_cap]
+  long long* totals;    // device scalars: see pairs.hip
+  long long* scan_tmp;
+  unsigned int* counters;  // [0] work items, [1] candidates
+  GroupRes* gres;          // [4 * n_rois]
+  int* cand;               // [kMaxCand]
+  long long max_rows_seg;  // bound on rows of one segment
+  long long rows_bound;    // bound on rows of all layouts (allocation)
+  RoiResult* res;          // [n_rois]
+  int cu_count;
+};
+
+// pairs.hip
+hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list
+hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass over the work list
+hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset per-group results
+hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
+hipError_t launch_finalize(const PairBufs& B, hipStream_t st);      // per-ROI results
+hipError_t launch_export_vertices(const unsigned long long* key, const double* tsoft, const RoiMeta* meta,
+                                  const Roi* rois, long long* ids, double* pos, long long V, hipStream_t st);
+
+}  // namespace s3d

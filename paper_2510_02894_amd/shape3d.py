@@ -1,0 +1,192 @@
+"""Python binding of ``libshape3d.so`` (see ``include/shape3d.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Volumes are CUDA/HIP torch tensors (``torch.uint8`` binary masks or
+``torch.float32`` soft masks, C-contiguous, shape (d0, d1, d2)); the work runs
+on the current torch stream.  There is no CPU path: a missing library or a CPU
+tensor raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshape3d.so")
+
+OK, EMPTY, EINVAL, ENODEV, EHIP, ECAPACITY, ENOMEM = 0, 1, -1, -2, -3, -4, -5
+U8, F32 = 0, 1
+FEATURES = (
+    "MeshVolume",
+    "SurfaceArea",
+    "Maximum3DDiameter",
+    "Maximum2DDiameterSlice",
+    "Maximum2DDiameterColumn",
+    "Maximum2DDiameterRow",
+)
+PHASES = ("mesh_count", "mesh_emit", "buckets", "pair_maxima", "refine", "finalize", "total")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_int64),
+        ("n_triangles", ctypes.c_int64),
+        ("pair_ids", (ctypes.c_int64 * 2) * 4),
+        ("pairs_3d", ctypes.c_int64),
+        ("pairs_2d", ctypes.c_int64),
+        ("candidates", ctypes.c_int64 * 4),
+        ("ms", ctypes.c_float * 8),
+    ]
+
+    def as_dict(self):
+        return dict(
+            V=int(self.n_vertices),
+            T=int(self.n_triangles),
+            pair_ids=np.array([[self.pair_ids[f][0], self.pair_ids[f][1]] for f in range(4)], dtype=np.int64),
+            pairs_3d=int(self.pairs_3d),
+            candidates=[int(x) for x in self.candidates],
+            ms={PHASES[k]: float(self.ms[k]) for k in range(len(PHASES))},
+        )
+
+
+class Shape3DError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("shape3d failed with status %d: %s" % (status, message))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load ``libshape3d.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libshape3d.so is not built; run `python -m paper_2510_02894_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        lib.shape3d.argtypes = [ctypes.c_void_p, i64p, f64p, f64p]
+        lib.shape3d.restype = ctypes.c_int
+        lib.shape3d_ex.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, f64p, ctypes.POINTER(Stats),
+                                   ctypes.c_int, ctypes.c_void_p]
+        lib.shape3d_ex.restype = ctypes.c_int
+        lib.shape3d_vertices.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, i64p, ctypes.c_void_p]
+        lib.shape3d_vertices.restype = ctypes.c_int
+        lib.shape3d_last_error.argtypes = []
+        lib.shape3d_last_error.restype = ctypes.c_char_p
+        lib.shape3d_release.argtypes = []
+        lib.shape3d_release.restype = ctypes.c_int
+        lib.shape3d_version.argtypes = []
+        lib.shape3d_version.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, allow_empty: bool = True) -> int:
+    if status < 0 or (status == EMPTY and not allow_empty):
+        msg = load().shape3d_last_error().decode(errors="replace")
+        raise Shape3DError(status, msg)
+    return status
+
+
+def _dims_spacing(shape, spacing):
+    dims = (ctypes.c_int64 * 3)(*[int(x) for x in shape])
+    sp = (ctypes.c_double * 3)(*[float(x) for x in spacing])
+    return dims, sp
+
+
+def _volume(vol):
+    import torch
+
+    if not isinstance(vol, torch.Tensor) or not vol.is_cuda:
+        raise TypeError("volume must be a GPU torch tensor")
+    if vol.dim() != 3:
+        raise ValueError("volume must be 3-D")
+    if vol.dtype == torch.uint8:
+        dt = U8
+    elif vol.dtype == torch.float32:
+        dt = F32
+    else:
+        raise TypeError("volume dtype must be uint8 or float32")
+    if not vol.is_contiguous():
+        raise ValueError("volume must be C-contiguous")
+    return dt
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def features(vol, spacing: Sequence[float] = (1.0, 1.0, 1.0), stats: bool = False, timing: bool = False):
+    """The six features (float64 numpy array, order of ``FEATURES``); with
+    ``stats=True`` returns ``(features, stats_dict, status)``."""
+    lib = load()
+    dt = _volume(vol)
+    dims, sp = _dims_spacing(vol.shape, spacing)
+    out = (ctypes.c_double * 6)()
+    st = Stats()
+    rc = lib.shape3d_ex(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, out, ctypes.byref(st), 1 if timing else 0,
+                        _stream())
+    _check(rc)
+    f = np.array(out[:], dtype=np.float64)
+    if stats:
+        d = st.as_dict()
+        if rc == EMPTY:
+            d["pair_ids"][:] = -1
+        return f, d, rc
+    return f
+
+
+def features_dict(vol, spacing=(1.0, 1.0, 1.0)):
+    return dict(zip(FEATURES, features(vol, spacing).tolist()))
+
+
+def shape3d_u8(mask, spacing=(1.0, 1.0, 1.0)):
+    """The plain synchronous entry point ``shape3d`` (binary mask, null stream)."""
+    lib = load()
+    if _volume(mask) != U8:
+        raise TypeError("shape3d takes a uint8 mask")
+    dims, sp = _dims_spacing(mask.shape, spacing)
+    out = (ctypes.c_double * 6)()
+    rc = lib.shape3d(ctypes.c_void_p(mask.data_ptr()), dims, sp, out)
+    _check(rc)
+    return np.array(out[:], dtype=np.float64), rc
+
+
+def vertices(vol, spacing=(1.0, 1.0, 1.0), with_pos: bool = True):
+    """(canonical ids int64 tensor [V], positions float64 tensor [V, 3] or None)."""
+    import torch
+
+    lib = load()
+    dt = _volume(vol)
+    dims, sp = _dims_spacing(vol.shape, spacing)
+    n = ctypes.c_int64(0)
+    rc = lib.shape3d_vertices(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, None, None, 0, ctypes.byref(n),
+                              _stream())
+    if rc not in (OK, EMPTY, ECAPACITY):
+        _check(rc)
+    V = int(n.value)
+    ids = torch.empty(max(V, 1), dtype=torch.int64, device=vol.device)
+    pos = torch.empty((max(V, 1), 3), dtype=torch.float64, device=vol.device) if with_pos else None
+    if V > 0:
+        rc = lib.shape3d_vertices(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, ctypes.c_void_p(ids.data_ptr()),
+                                  ctypes.c_void_p(pos.data_ptr()) if pos is not None else None, V, ctypes.byref(n),
+                                  _stream())
+        _check(rc)
+    return ids[:V], (pos[:V] if pos is not None else None)
+
+
+def release():
+    return load().shape3d_release()
+
+
+def version() -> int:
+    return load().shape3d_version()

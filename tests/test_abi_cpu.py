@@ -1,0 +1,67 @@
+"""CPU-side checks of the C ABI: the library loads and exports what the header declares."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shape3d.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(shape3d[a-z_0-9]*)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ("shape3d", "shape3d_ex", "shape3d_vertices", "shape3d_last_error", "shape3d_release", "shape3d_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2510_02894_amd import shape3d as S
+
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(S.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (shape3d[a-z_0-9]*)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_version_and_no_device_error():
+    from paper_2510_02894_amd import shape3d as S
+
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("library not built")
+    lib = S.load()
+    assert lib.shape3d_version() == 100
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    dims = (ctypes.c_int64 * 3)(4, 4, 4)
+    sp = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    out = (ctypes.c_double * 6)()
+    # no device: the call must fail loudly, never compute on the CPU
+    rc = lib.shape3d(ctypes.c_void_p(0x1000), dims, sp, out)
+    assert rc in (S.ENODEV, S.EINVAL)
+    rc = lib.shape3d(None, dims, sp, out)
+    assert rc == S.EINVAL
+
+
+def test_cpu_tensor_is_rejected():
+    import torch
+
+    from paper_2510_02894_amd import shape3d as S
+
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("library not built")
+    with pytest.raises(TypeError):
+        S.features(torch.zeros((4, 4, 4), dtype=torch.uint8), (1, 1, 1))
