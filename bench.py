@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the shape-feature path on one MI355X.
+
+Workload (one step = one full call of the library: marching-cubes mesh pass,
+plane buckets, all-pairs 3D and in-plane maxima, exact refinement, results on
+the host): the large single ROI, a uint8 mask of 300 x 512 x 512 voxels
+(axis 0 = slices) with spacing (1.25, 0.7, 0.7) mm, the union of 20 seeded
+ellipsoids (semi-axes 20-90 voxels) thresholded after Gaussian smoothing
+(sigma 3).  Four copies of the mask rotate through the steps so the 256 MB
+Infinity Cache does not hold the input.
+
+Prints one JSON line: value = 3D diameter vertex pairs V(V-1)/2 per second of
+whole-call time; roofline of the dominant kernel (the MFMA pair pass) from HIP
+events recorded around it inside the library; cpu_baseline = the FP64 oracle
+timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
+FLOPS_PER_PAIR = 8              # Gram form: 16x16x4 MFMA = 2048 flops per 256 pairs
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_02894_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, launches_per_step: int = 1):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("source_hash") != source_hash():
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(mask, spacing, target_s):
+    from oracle import oracle as O
+
+    t0 = time.perf_counter()
+    ids, pos, _ = O.vertices(mask, spacing)
+    t_vert = time.perf_counter() - t0
+    V = len(ids)
+    # calibrate on a few rows, then size the sample to about target_s seconds
+    rows = 64
+    t0 = time.perf_counter()
+    O.max_pair_rows(pos, 0, rows)
+    dt = time.perf_counter() - t0
+    rate_rows = rows / max(dt, 1e-6)
+    nrows = int(min(V, max(rows, rate_rows * target_s)))
+    t0 = time.perf_counter()
+    _, threads = O.max_pair_rows(pos, 0, nrows)
+    dt = time.perf_counter() - t0
+    pairs = sum(V - 1 - i for i in range(0, nrows)) if nrows < 10000 else nrows * (V - 1) - nrows * (nrows - 1) // 2
+    return dict(
+        value=pairs / dt,
+        unit="pairs/s",
+        cores=int(threads),
+        kind="oracle",
+        sample="rows 0..%d of the FP64 all-pairs maximum over the %d mesh vertices of the same mask "
+               "(%.3g of %.3g pairs, %.1f s; vertex extraction %.1f s)" % (
+                   nrows, V, float(pairs), V * (V - 1) / 2.0, dt, t_vert),
+    )
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_02894_amd import shape3d as S
+    from paper_2510_02894_amd import synth
+
+    S.load()
+    t0 = time.perf_counter()
+    mask, spacing = synth.large_roi(0)
+    log("generated mask %s in %.1f s (%d voxels inside)" % (mask.shape, time.perf_counter() - t0,
+                                                          int(mask.sum())))
+    dev = torch.device("cuda:0")
+    vols = [torch.from_numpy(mask).to(dev) for _ in range(max(1, args.copies))]
+    torch.cuda.synchronize()
+
+    def step(i):
+        return S.features(vols[i % len(vols)], spacing, stats=True, timing=True)
+
+    for i in range(args.warmup):
+        f, st, rc = step(i)
+        log("warmup %d: %.3f ms total, V=%d" % (i, st["ms"]["total"], st["V"]))
+    torch.cuda.synchronize()
+    phases = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        f, st, rc = step(i)
+        phases.append(st["ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    V = st["V"]
+    pairs3 = V * (V - 1) // 2
+    pairs2 = st["pairs_2d"]
+    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    log("phases (ms): " + ", ".join("%s %.4f" % kv for kv in avg.items()))
+
+    t_pair = avg["pair_maxima"] * 1e-3
+    achieved = FLOPS_PER_PAIR * (pairs3 + pairs2) / t_pair / 1e12
+    traffic = measured_traffic("k_pair_maxima")
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": traffic}
+    N = int(np.prod(mask.shape))
+    t_mesh = (avg["mesh_count"] + avg["mesh_emit"]) * 1e-3
+    mesh_bytes = N * 1 + 24 * V
+    mesh = {"bound": "hbm", "achieved": mesh_bytes / t_mesh / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": mesh_bytes / t_mesh / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic("k_mesh_count")}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample (about %.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(mask, spacing, args.cpu_seconds)
+
+    rec = {
+        "metric": "diameter vertex-pairs/s",
+        "value": pairs3 / (ms_per_step * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "large ROI: uint8 mask 300x512x512 (axis0 = slices), spacing (1.25,0.7,0.7) mm, "
+                        "union of 20 ellipsoids, Gaussian-smoothed (sigma 3) and thresholded",
+            "voxels": N,
+            "inside_voxels": int(mask.sum()),
+            "vertices": V,
+            "triangles": st["T"],
+            "pairs_3d": pairs3,
+            "pairs_in_plane": pairs2,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases_ms": avg,
+        "mesh_roofline": mesh,
+        "features": [float(x) for x in f],
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

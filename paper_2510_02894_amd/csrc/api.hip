@@ -47,7 +47,7 @@ struct Workspace {
   int device = -1;
   int cu_count = 0;
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
-      bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res;
+      bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase;
   void* host = nullptr;
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
@@ -56,7 +56,7 @@ struct Workspace {
   std::vector<Buf*> all() {
     return {&rois, &part,  &brick_voff, &meta,  &totals, &key,  &tsoft,   &pos,      &orig,     &rowmax,
             &blkseg, &segs, &bcnt,      &bcur,  &bsz,    &bflag, &brow,   &bseg,     &ncol,     &colbase,
-            &cols,  &nitem, &itembase,  &scan_tmp, &counters, &gres, &cand, &res};
+            &cols,  &nitem, &itembase,  &scan_tmp, &counters, &gres, &cand, &res, &pairs2d, &cand_nch, &cand_chbase};
   }
 };
 
@@ -176,19 +176,21 @@ struct Sizes {
 };
 
 // Steps up to and including the per-ROI totals; reads back V.
-int run_mesh_totals(Workspace& w, const Plan& P, int dtype, hipStream_t st, RoiMeta* meta_h, long long* totals_h) {
+int run_mesh_totals(Workspace& w, const Plan& P, int dtype, hipStream_t st, RoiMeta* meta_h, long long* totals_h,
+                    hipEvent_t ev_after = nullptr) {
   int rc;
   if ((rc = ensure(w.rois, sizeof(Roi)))) return rc;
   if ((rc = ensure(w.part, sizeof(BrickPart) * P.nbricks))) return rc;
   if ((rc = ensure(w.brick_voff, sizeof(long long) * P.nbricks))) return rc;
   if ((rc = ensure(w.meta, sizeof(RoiMeta)))) return rc;
-  if ((rc = ensure(w.totals, sizeof(long long) * 8))) return rc;
+  if ((rc = ensure(w.totals, sizeof(long long) * 16))) return rc;
   if ((rc = ensure_host(w, 1 << 16))) return rc;
   memcpy(w.host, &P.roi, sizeof(Roi));
   HIPCK(hipMemcpyAsync(w.rois.p, w.host, sizeof(Roi), hipMemcpyHostToDevice, st));
   HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, 1, P.nbricks, (BrickPart*)w.part.p, st));
   HIPCK(launch_mesh_totals((const Roi*)w.rois.p, 1, P.nbricks, dtype, (const BrickPart*)w.part.p,
                            (long long*)w.brick_voff.p, (RoiMeta*)w.meta.p, (long long*)w.totals.p, st));
+  if (ev_after) HIPCK(hipEventRecord(ev_after, st));
   char* h = (char*)w.host + 4096;
   HIPCK(hipMemcpyAsync(h, w.meta.p, sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
   HIPCK(hipMemcpyAsync(h + 1024, w.totals.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
@@ -208,7 +210,7 @@ int ensure_vertex_bufs(Workspace& w, const Plan& P, int dtype, const RoiMeta& M,
   S.seg_cap = 1 + P.n_buckets;
   S.col_cap = S.seg_cap + S.rows_bound / (kJchunkBlocks * kBlk) + 1;
   S.max_rows_seg = std::max<long long>(M.V_pad, kSegAlign);
-  const long long scan_n = std::max(P.n_buckets, std::max(S.seg_cap, S.col_cap));
+  const long long scan_n = std::max(std::max(P.n_buckets, (long long)kMaxCand), std::max(S.seg_cap, S.col_cap));
   if ((rc = ensure(w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
   if (dtype == SHAPE3D_F32 && (rc = ensure(w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
   if ((rc = ensure(w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
@@ -232,6 +234,9 @@ int ensure_vertex_bufs(Workspace& w, const Plan& P, int dtype, const RoiMeta& M,
   if ((rc = ensure(w.gres, sizeof(GroupRes) * 4))) return rc;
   if ((rc = ensure(w.cand, sizeof(int) * kMaxCand))) return rc;
   if ((rc = ensure(w.res, sizeof(RoiResult)))) return rc;
+  if ((rc = ensure(w.pairs2d, sizeof(long long)))) return rc;
+  if ((rc = ensure(w.cand_nch, sizeof(long long) * kMaxCand))) return rc;
+  if ((rc = ensure(w.cand_chbase, sizeof(long long) * kMaxCand))) return rc;
   return SHAPE3D_OK;
 }
 
@@ -270,6 +275,9 @@ PairBufs pair_bufs(Workspace& w, const Plan& P, int dtype, const Sizes& S) {
   B.max_rows_seg = S.max_rows_seg;
   B.rows_bound = S.rows_bound;
   B.res = (RoiResult*)w.res.p;
+  B.pairs2d = (long long*)w.pairs2d.p;
+  B.cand_nch = (long long*)w.cand_nch.p;
+  B.cand_chbase = (long long*)w.cand_chbase.p;
   B.cu_count = w.cu_count;
   return B;
 }
@@ -294,8 +302,7 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   if (timing) HIPCK(hipEventRecord(w.ev[0], st));
   RoiMeta M;
   long long totals_h[2];
-  if ((rc = run_mesh_totals(w, P, dtype, st, &M, totals_h))) return rc;
-  if (timing) HIPCK(hipEventRecord(w.ev[1], st));
+  if ((rc = run_mesh_totals(w, P, dtype, st, &M, totals_h, timing ? w.ev[1] : nullptr))) return rc;
   if (M.V == 0) {
     for (int f = 0; f < 6; ++f) out[f] = 0.0;
     if (stats) {
@@ -308,10 +315,12 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   Sizes S;
   if ((rc = ensure_vertex_bufs(w, P, dtype, M, totals_h, S))) return rc;
   const PairBufs B = pair_bufs(w, P, dtype, S);
+  if (timing) HIPCK(hipEventRecord(w.ev[7], st));
   if ((rc = run_emit(w, P, dtype, st))) return rc;
   if (timing) HIPCK(hipEventRecord(w.ev[2], st));
   HIPCK(launch_buckets(B, st));
   HIPCK(launch_init_groups(B, st));
+  HIPCK(launch_fill_u32(B.counters, 0u, 2, st));
   if (timing) HIPCK(hipEventRecord(w.ev[3], st));
   HIPCK(launch_pair_maxima(B, st));
   if (timing) HIPCK(hipEventRecord(w.ev[4], st));
@@ -334,10 +343,11 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
       stats->candidates[f] = rh->cand[f];
     }
     stats->pairs_3d = rh->V * (rh->V - 1) / 2;
+    stats->pairs_2d = rh->pairs2d;
     if (timing) {
-      // phases: 0 mesh count + totals (incl. read-back), 1 emit, 2 buckets + work list, 3 MFMA, 4 refine,
-      // 5 finalise, 6 whole call
-      const int a[7] = {0, 1, 2, 3, 4, 5, 0};
+      // phases: 0 mesh count + totals, 1 emit, 2 buckets + work list, 3 MFMA pair maxima, 4 refine,
+      // 5 finalise + read-back, 6 whole call (including the vertex-count read-back)
+      const int a[7] = {0, 7, 2, 3, 4, 5, 0};
       const int b[7] = {1, 2, 3, 4, 5, 6, 6};
       for (int k = 0; k < 7; ++k) {
         float ms = 0.f;

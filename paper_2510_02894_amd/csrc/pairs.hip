@@ -31,7 +31,7 @@ namespace s3d {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-enum { T_ROWS0 = 0, T_VMAX = 1, T_ROWS2D = 2, T_NSEG2D = 3, T_NCOL = 4, T_NITEM = 5 };
+enum { T_ROWS0 = 0, T_VMAX = 1, T_ROWS2D = 2, T_NSEG2D = 3, T_NCOL = 4, T_NITEM = 5, T_NEXACT = 6 };
 
 __device__ inline int bucket_roi(const Roi* rois, int n, long long b, int& axis) {
   int lo = 0, hi = n - 1;
@@ -49,22 +49,46 @@ __device__ inline int bucket_roi(const Roi* rois, int n, long long b, int& axis)
 // ---------------------------------------------------------------------------
 // Plane buckets.
 
+__device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b);
+
 __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
                               const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
                               long long rows0, unsigned int* __restrict__ bcnt) {
+  // the trip count is uniform per wave (rows0 is a multiple of the wave size)
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
        row += (long long)gridDim.x * blockDim.x) {
     const int roi = blkseg[row >> 4];
     const RoiMeta& M = meta[roi];
-    if (row - M.row_off >= M.V) continue;
-    const unsigned long long k = key[row];
-    const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};  // u + 1
-    const int a = (int)((k >> 60) & 3);
-    for (int ax = 0; ax < 3; ++ax) {
-      const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
-      atomicAdd(&bcnt[b], 1u);
+    if (row - M.row_off < M.V) {
+      const unsigned long long k = key[row];
+      const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};  // u + 1
+      const int a = (int)((k >> 60) & 3);
+      for (int ax = 0; ax < 3; ++ax) {
+        const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
+        wave_aggregated_inc(bcnt, b);
+      }
     }
   }
+}
+
+// Adds 1 to counter[b] for every active lane and returns the lane's previous
+// count; lanes with the same b are served by one atomic (consecutive vertices
+// mostly share a plane).
+__device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b) {
+  unsigned long long todo = __ballot(1);
+  unsigned int result = 0;
+  const int lane = threadIdx.x & 63;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const long long bl = __shfl(b, leader, 64);
+    const unsigned long long same = __ballot(b == bl) & todo;
+    unsigned int base = 0;
+    if (lane == leader) base = atomicAdd(&counter[bl], (unsigned int)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (b == bl) result = base + (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return result;
 }
 
 __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long nb, long long* __restrict__ bsz,
@@ -94,7 +118,7 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
     for (int ax = 0; ax < 3; ++ax) {
       const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
       if (bcnt[b] < 2) continue;
-      const long long dst_row = rows0 + brow[b] + atomicAdd(&bcur[b], 1u);
+      const long long dst_row = rows0 + brow[b] + wave_aggregated_inc(bcur, b);
       float* dst = pos + (dst_row >> 4) * 64 + (dst_row & 15);
       dst[0] = sx;
       dst[16] = sy;
@@ -111,12 +135,13 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
                              const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                              const long long* __restrict__ brow, const long long* __restrict__ bseg,
                              float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax,
-                             int* __restrict__ blkseg, Seg* __restrict__ segs) {
+                             int* __restrict__ blkseg, Seg* __restrict__ segs, long long* __restrict__ pairs2d) {
   for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (long long)gridDim.x * blockDim.x) {
     const unsigned int c = bcnt[b];
     if (c < 2) continue;
     int axis;
     const int roi = bucket_roi(rois, n_rois, b, axis);
+    atomicAdd((unsigned long long*)&pairs2d[roi], (unsigned long long)c * (c - 1) / 2);
     const long long sid = n_rois + bseg[b];
     const long long r0 = rows0 + brow[b];
     const long long n = bsz[b];
@@ -276,16 +301,42 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
 // ---------------------------------------------------------------------------
 // Exact refinement.
 
+// Group maxima of the FP32 row maxima.  Each lane reduces one 16-row block
+// (a block lies in one segment, hence one group); each wave then issues one
+// atomic per distinct group among its 64 blocks (usually one).
 __global__ void k_group_max(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
                             const Seg* __restrict__ segs, const long long* __restrict__ totals,
                             GroupRes* __restrict__ gres) {
-  const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
-  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
-       row += (long long)gridDim.x * blockDim.x) {
-    const int s = blkseg[row >> 4];
-    const int g = s >= 0 ? segs[s].group : -1;
-    const float v = rowmax[row];
-    if (g >= 0) atomicMax((int*)&gres[g].gmax, __float_as_int(v));
+  const long long nblk = (totals[T_ROWS0] + totals[T_ROWS2D]) / kBlk;
+  const int lane = threadIdx.x & 63;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long base = wave * 64; base < nblk; base += nwaves * 64) {
+    const long long blk = base + lane;
+    int g = -1;
+    float m = 0.0f;
+    if (blk < nblk) {
+      const int s = blkseg[blk];
+      if (s >= 0) {
+        g = segs[s].group;
+        const float4* p = (const float4*)(rowmax + blk * kBlk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float4 v = p[i];
+          m = fmaxf(m, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
+        }
+      }
+    }
+    unsigned long long todo = __ballot(g >= 0);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int gl = __shfl(g, leader, 64);
+      const unsigned long long same = __ballot(g == gl) & todo;
+      float v = g == gl ? m : 0.0f;
+      for (int k = 32; k >= 1; k >>= 1) v = fmaxf(v, __shfl_xor(v, k, 64));
+      if (lane == leader) atomicMax((int*)&gres[gl].gmax, __float_as_int(v));
+      todo &= ~same;
+    }
   }
 }
 
@@ -317,23 +368,49 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
   }
 }
 
+// Chunks of each candidate's segment (0 beyond the candidate count).
+__global__ void k_cand_chunks(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
+                              const int* __restrict__ blkseg, const Seg* __restrict__ segs,
+                              long long* __restrict__ nch) {
+  const unsigned int nc = min(*ncand_p, (unsigned int)kMaxCand);
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < kMaxCand;
+       c += (long long)gridDim.x * blockDim.x) {
+    long long n = 0;
+    if (c < nc) n = (segs[blkseg[cand[c] >> 4]].n_rows + kExactChunk - 1) / kExactChunk;
+    nch[c] = n;
+  }
+}
+
+// Exact FP64 rescans of candidate rows.  Work item = (candidate, chunk of its
+// segment) from the prefix sum chbase.  PASS 0: maximum squared distance;
+// PASS 1: smallest id of the pairs that reach it; PASS 2: smallest partner id
+// of those; PASS 3: the rows of the chosen pair.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
+                                               const long long* __restrict__ chbase,
+                                               const long long* __restrict__ n_work_p,
                                                const int* __restrict__ blkseg, const Seg* __restrict__ segs,
                                                const int* __restrict__ orig, const unsigned long long* __restrict__ key,
                                                const double* __restrict__ tsoft, const Roi* __restrict__ rois,
-                                               long long max_chunks, GroupRes* __restrict__ gres) {
+                                               GroupRes* __restrict__ gres) {
   __shared__ unsigned long long sh[4];
-  const unsigned int nc = min(*ncand_p, (unsigned int)kMaxCand);
-  const long long n_work = (long long)nc * max_chunks;
+  const int nc = (int)min(*ncand_p, (unsigned int)kMaxCand);
+  const long long n_work = *n_work_p;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (long long w = blockIdx.x; w < n_work; w += gridDim.x) {
-    const int row_i = cand[w / max_chunks];
-    const long long chunk = w % max_chunks;
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (chbase[mid] <= w)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int row_i = cand[lo];
+    const long long chunk = w - chbase[lo];
     const Seg S = segs[blkseg[row_i >> 4]];
     const long long jb = S.row_begin + chunk * kExactChunk;
     const long long je = min(jb + (long long)kExactChunk, S.row_begin + (long long)S.n_rows);
-    if (jb >= je) continue;
     const int g = S.group;
     const Roi& R = rois[g >> 2];
     const int vi = orig[row_i];
@@ -354,12 +431,12 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
         red = max(red, (unsigned long long)__double_as_longlong(d2));
       } else if (vi != vj && d2 == target) {
         const unsigned long long idj = key_canonical_id(kj, R.d);
-        const unsigned long long lo = min(idi, idj), hi = max(idi, idj);
-        if (PASS == 1) red = min(red, lo);
-        if (PASS == 2 && lo == lo_ref) red = min(red, hi);
-        if (PASS == 3 && lo == lo_ref && hi == hi_ref) {
-          gres[g].row_i = idi == lo ? vi : vj;
-          gres[g].row_j = idi == lo ? vj : vi;
+        const unsigned long long lo_id = min(idi, idj), hi_id = max(idi, idj);
+        if (PASS == 1) red = min(red, lo_id);
+        if (PASS == 2 && lo_id == lo_ref) red = min(red, hi_id);
+        if (PASS == 3 && lo_id == lo_ref && hi_id == hi_ref) {
+          gres[g].row_i = idi == lo_id ? vi : vj;
+          gres[g].row_j = idi == lo_id ? vj : vi;
         }
       }
     }
@@ -372,8 +449,7 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
     if (lane == 0) sh[wid] = red;
     __syncthreads();
     if (tid == 0) {
-      for (int k = 1; k < 4; ++k) red = PASS == 0 ? max(red, sh[k]) : min(red, sh[k]);
-      red = PASS == 0 ? max(red, sh[0]) : min(red, sh[0]);
+      for (int k = 0; k < 4; ++k) red = PASS == 0 ? max(red, sh[k]) : min(red, sh[k]);
       if (PASS == 0) atomicMax(&gres[g].best_bits, red);
       if (PASS == 1) atomicMin(&gres[g].id_lo, red);
       if (PASS == 2) atomicMin(&gres[g].id_hi, red);
@@ -397,13 +473,14 @@ __global__ void k_init_groups(GroupRes* gres, long long n) {
 
 __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const GroupRes* __restrict__ gres,
                            const unsigned int* __restrict__ ncand, const unsigned long long* __restrict__ key,
-                           const Roi* __restrict__ rois, RoiResult* __restrict__ res) {
+                           const Roi* __restrict__ rois, const long long* __restrict__ pairs2d,
+                           RoiResult* __restrict__ res) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
     const RoiMeta M = meta[r];
     RoiResult Q;
     Q.V = M.V;
     Q.T = M.T;
-    Q.pairs2d = 0;
+    Q.pairs2d = pairs2d[r];
     Q.out[0] = fabs(M.vol);
     Q.out[1] = M.area;
     for (int f = 0; f < 4; ++f) {
@@ -454,6 +531,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipError_t e;
   if ((e = launch_fill_u32(B.bcnt, 0u, B.n_buckets, st))) return e;
   if ((e = launch_fill_u32(B.bcur, 0u, B.n_buckets, st))) return e;
+  if ((e = launch_fill_i64(B.pairs2d, 0, B.n_rois, st))) return e;
   hipLaunchKernelGGL(k_bucket_hist, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
                      B.rows0, B.bcnt);
   hipLaunchKernelGGL(k_bucket_sizes, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.bcnt, B.n_buckets, B.bsz,
@@ -463,7 +541,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
                      B.rows0, B.bcnt, B.bcur, B.brow, B.pos, B.orig, B.rowmax);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
-                     B.rows0, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs);
+                     B.rows0, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs, B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.ncol);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
@@ -474,9 +552,9 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The work counter (B.counters[0]) must be zero when this is enqueued.
 hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
   hipError_t e;
-  if ((e = launch_fill_u32(B.counters, 0u, 2, st))) return e;
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_maxima, 256, 0))) return e;
   const unsigned grid = (unsigned)(B.cu_count * (per_cu > 0 ? per_cu : 1));
@@ -491,26 +569,29 @@ hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
 }
 
 hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
-  hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
-                     B.totals, B.gres);
+  hipError_t e;
+  hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound / kBlk, 1024)), dim3(256), 0, st, B.rowmax, B.blkseg,
+                     B.segs, B.totals, B.gres);
   hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
                      B.meta, B.totals, B.gres, B.counters + 1, B.cand);
-  const long long max_chunks = (B.max_rows_seg + kExactChunk - 1) / kExactChunk;
-  const unsigned grid = 1024;
-  hipLaunchKernelGGL(k_exact<0>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
-                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
-  hipLaunchKernelGGL(k_exact<1>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
-                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
-  hipLaunchKernelGGL(k_exact<2>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
-                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
-  hipLaunchKernelGGL(k_exact<3>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg, B.segs, B.orig,
-                     B.key, B.tsoft, B.rois, max_chunks, B.gres);
+  hipLaunchKernelGGL(k_cand_chunks, dim3(grid_for(kMaxCand)), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg,
+                     B.segs, B.cand_nch);
+  if ((e = launch_scan(B.cand_nch, B.cand_chbase, kMaxCand, B.totals + T_NEXACT, B.scan_tmp, st))) return e;
+  const unsigned grid = (unsigned)(B.cu_count * 8);
+#define S3D_EXACT(P)                                                                                             \
+  hipLaunchKernelGGL(k_exact<P>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.cand_chbase,             \
+                     B.totals + T_NEXACT, B.blkseg, B.segs, B.orig, B.key, B.tsoft, B.rois, B.gres)
+  S3D_EXACT(0);
+  S3D_EXACT(1);
+  S3D_EXACT(2);
+  S3D_EXACT(3);
+#undef S3D_EXACT
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(B.n_rois)), dim3(256), 0, st, B.n_rois, B.meta, B.gres,
-                     B.counters + 1, B.key, B.rois, B.res);
+                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res);
   return hipGetLastError();
 }
 

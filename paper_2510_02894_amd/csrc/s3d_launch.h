@@ -67,9 +67,12 @@ struct PairBufs {
   unsigned int* counters;  // [0] work items, [1] candidates
   GroupRes* gres;          // [4 * n_rois]
   int* cand;               // [kMaxCand]
+  long long* cand_nch;     // [kMaxCand] chunks of each candidate's segment
+  long long* cand_chbase;  // [kMaxCand] prefix sum of cand_nch
   long long max_rows_seg;  // bound on rows of one segment
   long long rows_bound;    // bound on rows of all layouts (allocation)
   RoiResult* res;          // [n_rois]
+  long long* pairs2d;      // [n_rois] in-plane pairs n*(n-1)/2 summed over buckets
   int cu_count;
 };
 

@@ -47,6 +47,7 @@ class Stats(ctypes.Structure):
             T=int(self.n_triangles),
             pair_ids=np.array([[self.pair_ids[f][0], self.pair_ids[f][1]] for f in range(4)], dtype=np.int64),
             pairs_3d=int(self.pairs_3d),
+            pairs_2d=int(self.pairs_2d),
             candidates=[int(x) for x in self.candidates],
             ms={PHASES[k]: float(self.ms[k]) for k in range(len(PHASES))},
         )
