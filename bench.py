@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -113,6 +115,15 @@ def main():
     from paper_2510_02894_amd import synth
 
     S.load()
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 device copies of %d bytes" % nbytes)
+        del src, dst
     t0 = time.perf_counter()
     mask, spacing = synth.large_roi(0)
     log("generated mask %s in %.1f s (%d voxels inside)" % (mask.shape, time.perf_counter() - t0,
