@@ -60,8 +60,10 @@ extern "C" {
 #define SHAPE3D_U8 0
 #define SHAPE3D_F32 1
 
-/* Largest accepted extent of one axis. */
+/* Largest accepted extent of axes 0 and 1, and of axis 2 (the contiguous axis,
+   whose rows one workgroup of the mesh pass stages in LDS). */
 #define SHAPE3D_MAX_DIM 1000000
+#define SHAPE3D_MAX_DIM2 32767
 
 /* Per-call statistics (optional output of shape3d_ex). */
 typedef struct {
@@ -79,7 +81,8 @@ typedef struct {
 /*
  * shape3d -- the six features of one binary ROI, synchronously.
  *   mask:    DEVICE, uint8 (d0, d1, d2), C-contiguous; nonzero = inside.
- *   dims:    HOST int64[3]; each in [1, SHAPE3D_MAX_DIM].
+ *   dims:    HOST int64[3]; dims[0], dims[1] in [1, SHAPE3D_MAX_DIM],
+ *            dims[2] in [1, SHAPE3D_MAX_DIM2].
  *   spacing: HOST double[3]; each finite and > 0.
  *   out:     HOST double[6], the features in the order above.
  * Uses the null stream.  Returns SHAPE3D_OK, SHAPE3D_EMPTY (out all zero) or

@@ -120,6 +120,9 @@ int check_args(const void* vol, int dtype, const int64_t dims[3], const double s
   if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "dtype must be SHAPE3D_U8 or SHAPE3D_F32");
   for (int k = 0; k < 3; ++k) {
     if (dims[k] < 1 || dims[k] > SHAPE3D_MAX_DIM) return fail(SHAPE3D_EINVAL, "dims out of range");
+  }
+  if (dims[2] > SHAPE3D_MAX_DIM2) return fail(SHAPE3D_EINVAL, "dims[2] out of range");
+  for (int k = 0; k < 3; ++k) {
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return fail(SHAPE3D_EINVAL, "spacing must be finite and > 0");
   }
   const size_t elem = dtype == SHAPE3D_U8 ? 1 : 4;
@@ -187,7 +190,7 @@ int run_mesh_totals(Workspace& w, const Plan& P, int dtype, hipStream_t st, RoiM
   if ((rc = ensure_host(w, 1 << 16))) return rc;
   memcpy(w.host, &P.roi, sizeof(Roi));
   HIPCK(hipMemcpyAsync(w.rois.p, w.host, sizeof(Roi), hipMemcpyHostToDevice, st));
-  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, 1, P.nbricks, (BrickPart*)w.part.p, st));
+  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, 1, P.nbricks, P.roi.G, (BrickPart*)w.part.p, st));
   HIPCK(launch_mesh_totals((const Roi*)w.rois.p, 1, P.nbricks, dtype, (const BrickPart*)w.part.p,
                            (long long*)w.brick_voff.p, (RoiMeta*)w.meta.p, (long long*)w.totals.p, st));
   if (ev_after) HIPCK(hipEventRecord(ev_after, st));
@@ -283,7 +286,7 @@ PairBufs pair_bufs(Workspace& w, const Plan& P, int dtype, const Sizes& S) {
 }
 
 int run_emit(Workspace& w, const Plan& P, int dtype, hipStream_t st) {
-  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, 1, P.nbricks, (const BrickPart*)w.part.p,
+  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, 1, P.nbricks, P.roi.G, (const BrickPart*)w.part.p,
                          (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p, (unsigned long long*)w.key.p,
                          dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, (int*)w.orig.p,
                          (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));

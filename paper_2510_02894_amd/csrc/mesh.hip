@@ -2,12 +2,13 @@
 // fused parallel kernels"): cube classification, vertex counting and
 // emission, surface area and signed volume.
 //
-// Each thread owns 32 consecutive cubes along axis 2 of one cube row and
-// marches through kTZ cube planes along axis 0, keeping the previous voxel
-// plane's two rows as bit masks; every mask byte (or float) is turned into a
-// bit once per row it borders.  Crossing edges and active cubes come from
-// bitwise operations on eight 32-bit corner masks; only active cubes (a few
-// percent) touch the case tables.
+// A workgroup handles a brick: 256 row-groups (32 consecutive cubes along
+// axis 2 of one cube row) times up to kTZ cube planes.  It first stages every
+// voxel row-group the brick touches in LDS as 32-bit masks (all loads issued
+// at once; each mask byte or float becomes one bit once), then each thread
+// classifies its 32 cubes of every plane pair from LDS: crossing edges and
+// active cubes come from bitwise operations on eight 32-bit corner masks, and
+// only active cubes (a few percent) touch the case tables.
 //
 // Area and volume (binary masks): vertices sit at edge midpoints, so each
 // case's area is a fixed number for the call's spacing and its volume term is
@@ -24,8 +25,8 @@
 namespace s3d {
 
 // ---------------------------------------------------------------------------
-// Row loaders: bits of voxels [32l, 32l + 32) of row (z, y), and the bit of
-// voxel 32l - 1.  Out-of-range voxels read as outside.
+// Row loader: bits of voxels [32l, 32l + 32) of row (z, y); voxels outside the
+// array read as outside.
 
 __device__ inline uint32_t nz4(uint32_t w) {
   // high bit of each byte set iff the byte is nonzero, then gathered to bits 0..3
@@ -34,18 +35,14 @@ __device__ inline uint32_t nz4(uint32_t w) {
 }
 
 template <int DT>
-__device__ inline void load_row(const void* vol, const int* d, int z, int y, int l, uint32_t& bits,
-                                uint32_t& xm1) {
-  bits = 0u;
-  xm1 = 0u;
-  if (z < 0 || z >= d[0] || y < 0 || y >= d[1]) return;
+__device__ inline uint32_t row_bits(const void* vol, const int* d, int z, int y, int l) {
+  uint32_t bits = 0u;
+  if (z < 0 || z >= d[0] || y < 0 || y >= d[1]) return 0u;
   const int x0 = 32 * l;
   int n = d[2] - x0;
+  if (n <= 0) return 0u;
   if (DT == 0) {
-    const uint8_t* row = (const uint8_t*)vol + ((size_t)z * d[1] + y) * (size_t)d[2];
-    if (l > 0) xm1 = row[x0 - 1] != 0;
-    if (n <= 0) return;
-    const uint8_t* p = row + x0;
+    const uint8_t* p = (const uint8_t*)vol + ((size_t)z * d[1] + y) * (size_t)d[2] + x0;
     if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
       const uint4 a = *(const uint4*)p;
       const uint4 b = *(const uint4*)(p + 16);
@@ -56,10 +53,7 @@ __device__ inline void load_row(const void* vol, const int* d, int z, int y, int
       for (int i = 0; i < n; ++i) bits |= (uint32_t)(p[i] != 0) << i;
     }
   } else {
-    const float* row = (const float*)vol + ((size_t)z * d[1] + y) * (size_t)d[2];
-    if (l > 0) xm1 = row[x0 - 1] > 0.5f;
-    if (n <= 0) return;
-    const float* p = row + x0;
+    const float* p = (const float*)vol + ((size_t)z * d[1] + y) * (size_t)d[2] + x0;
     if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -73,6 +67,7 @@ __device__ inline void load_row(const void* vol, const int* d, int z, int y, int
       for (int i = 0; i < n; ++i) bits |= (uint32_t)(p[i] > 0.5f) << i;
     }
   }
+  return bits;
 }
 
 __device__ inline double soft_value(const float* vol, const int* d, int z, int y, int x) {
@@ -80,24 +75,116 @@ __device__ inline double soft_value(const float* vol, const int* d, int z, int y
   return (double)vol[((size_t)z * d[1] + y) * (size_t)d[2] + x];
 }
 
+// A brick is kBrickThreads consecutive row-groups (rg = cube row * G + group)
+// times up to kTZ cube planes.  Its workgroup first loads, as bit masks, every
+// voxel row-group it needs into LDS: planes pz0-1 .. pz1-1 and row-groups
+// rg0-1 .. rg0+kBrickThreads+G-1 (the row after each cube row, and the word
+// before the first group for the x-1 voxel).  All these loads are issued at
+// once, each voxel row-group is converted once, and the cube classification
+// then reads LDS only.
+struct Tile {
+  int rg0;       // first row-group of the brick
+  int pz0, pz1;  // cube planes [pz0, pz1), pz = z + 1
+  int np;        // voxel planes held: pz1 - pz0 + 1
+  int nw;        // words per plane: kBrickThreads + 1 + G
+};
+
+__device__ inline Tile tile_of(const Roi& R, long long local_brick) {
+  Tile T;
+  const int bx = (int)(local_brick / R.nzc), zc = (int)(local_brick % R.nzc);
+  T.rg0 = bx * kBrickThreads;
+  T.pz0 = zc * kTZ;
+  T.pz1 = min(T.pz0 + kTZ, R.d[0] + 1);
+  T.np = T.pz1 - T.pz0 + 1;
+  T.nw = kBrickThreads + 1 + R.G;
+  return T;
+}
+
+// Address of voxel row-group vrg of voxel plane p of the tile, or null when it
+// lies outside the array or is not a full aligned 32-voxel run (then the slow
+// per-voxel path of row_bits is used).
+template <int DT>
+__device__ inline const void* fast_row_ptr(const Roi& R, const Tile& T, int p, int vrg) {
+  if (vrg < 0) return nullptr;
+  const int ry = vrg / R.G;
+  const int z = T.pz0 - 1 + p, y = ry - 1, x0 = 32 * (vrg - ry * R.G);
+  if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1] || x0 + 32 > R.d[2]) return nullptr;
+  const size_t off = ((size_t)z * R.d[1] + y) * (size_t)R.d[2] + x0;
+  const char* ptr = (const char*)R.vol + off * (DT == 0 ? 1 : 4);
+  return (((uintptr_t)ptr) & 15u) == 0 ? ptr : nullptr;
+}
+
+template <int DT>
+__device__ inline uint32_t slow_row_bits(const Roi& R, const Tile& T, int p, int vrg) {
+  if (vrg < 0) return 0u;
+  const int ry = vrg / R.G;
+  return row_bits<DT>(R.vol, R.d, T.pz0 - 1 + p, ry - 1, vrg - ry * R.G);
+}
+
+// Stages the tile's voxel row-groups in LDS.  Each thread issues the loads of
+// kLoadBatch row-groups before converting any of them, so a workgroup keeps
+// its whole tile in flight instead of one row-group per thread at a time.
+template <int DT>
+__device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) {
+  constexpr int kLoadBatch = 10;
+  const int n = T.np * T.nw;
+  for (int base = threadIdx.x; base < n; base += kBrickThreads * kLoadBatch) {
+    if (DT == 0) {
+      uint4 a[kLoadBatch], b[kLoadBatch];
+      bool fast[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        const int idx = base + u * kBrickThreads;
+        const void* ptr = nullptr;
+        if (idx < n) {
+          const int p = idx / T.nw;
+          ptr = fast_row_ptr<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+        }
+        fast[u] = ptr != nullptr;
+        if (fast[u]) {
+          a[u] = *(const uint4*)ptr;
+          b[u] = *((const uint4*)ptr + 1);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; ++u) {
+        const int idx = base + u * kBrickThreads;
+        if (idx >= n) continue;
+        uint32_t bits;
+        if (fast[u]) {
+          bits = nz4(a[u].x) | (nz4(a[u].y) << 4) | (nz4(a[u].z) << 8) | (nz4(a[u].w) << 12) |
+                 (nz4(b[u].x) << 16) | (nz4(b[u].y) << 20) | (nz4(b[u].z) << 24) | (nz4(b[u].w) << 28);
+        } else {
+          const int p = idx / T.nw;
+          bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+        }
+        s_bits[idx] = bits;
+      }
+    } else {
+      for (int u = 0; u < kLoadBatch; ++u) {
+        const int idx = base + u * kBrickThreads;
+        if (idx >= n) break;
+        const int p = idx / T.nw;
+        s_bits[idx] = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+      }
+    }
+  }
+}
+
 // Thread coordinates inside a brick.
 struct Lane {
   int y, l;        // cube row (voxel rows y, y+1) and 32-cube group
-  int pz0, pz1;    // cube planes [pz0, pz1) as pz = z + 1
   uint32_t vmask;  // cubes of this group inside [-1, d2 - 1]
   bool valid;
 };
 
-__device__ inline Lane lane_of(const Roi& R, long long local_brick, int tid) {
+__device__ inline Lane lane_of(const Roi& R, const Tile& T, int tid) {
   Lane L;
-  const int bx = (int)(local_brick / R.nzc), zc = (int)(local_brick % R.nzc);
-  const int rg = bx * kBrickThreads + tid;
+  const int rg = T.rg0 + tid;
   L.valid = rg < R.nrg;
   const int ry = L.valid ? rg / R.G : 0;
   L.l = L.valid ? rg - ry * R.G : 0;
   L.y = ry - 1;
-  L.pz0 = zc * kTZ;
-  L.pz1 = min(L.pz0 + kTZ, R.d[0] + 1);
   const int kmax = R.d[2] - 32 * L.l;  // cube x = 32l - 1 + k valid iff k <= kmax
   L.vmask = kmax >= 31 ? 0xffffffffu : ((1u << (kmax + 1)) - 1u);
   return L;
@@ -123,6 +210,20 @@ __device__ inline Corners make_corners(uint32_t r00, uint32_t x00, uint32_t r01,
   return C;
 }
 
+// Corner masks of plane pair (p, p+1) of the tile for thread tid.
+__device__ inline Corners tile_corners(const uint32_t* s_bits, const Tile& T, const Lane& L, int p, int tid, int G) {
+  uint32_t r[2][2], x[2][2];
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+      const int w = (p + dz) * T.nw + tid + 1 + dy * G;
+      r[dz][dy] = s_bits[w];
+      x[dz][dy] = L.l > 0 ? (s_bits[w - 1] >> 31) : 0u;
+    }
+  return make_corners(r[0][0], x[0][0], r[0][1], x[0][1], r[1][0], x[1][0], r[1][1], x[1][1]);
+}
+
 __device__ inline int case_of(const Corners& C, int k) {
   int cas = 0;
 #pragma unroll
@@ -136,6 +237,7 @@ __device__ inline int case_of(const Corners& C, int k) {
 template <int DT>
 __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restrict__ rois, int n_rois,
                                                               long long nbricks, BrickPart* __restrict__ part) {
+  extern __shared__ uint32_t s_bits[];
   __shared__ double s_area[256];
   __shared__ int s_tk[256];
   __shared__ int s_tm[256];
@@ -165,7 +267,10 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   }
   __syncthreads();
 
-  const Lane L = lane_of(R, brick - R.brick_begin, tid);
+  const Tile T = tile_of(R, brick - R.brick_begin);
+  load_tile<DT>(R, T, s_bits);
+  __syncthreads();
+  const Lane L = lane_of(R, T, tid);
   int nv = 0, nt = 0;
   double area = 0.0, vol_d = 0.0;
   long long vol_i = 0;
@@ -174,15 +279,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   const double o0 = 0.5 * R.d[0] * R.s[0], o1 = 0.5 * R.d[1] * R.s[1], o2 = 0.5 * R.d[2] * R.s[2];
 
   if (L.valid) {
-    uint32_t r00, x00, r01, x01;
-    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y, L.l, r00, x00);
-    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y + 1, L.l, r01, x01);
-    for (int pz = L.pz0; pz < L.pz1; ++pz) {
-      const int z = pz - 1;
-      uint32_t r10, x10, r11, x11;
-      load_row<DT>(R.vol, R.d, z + 1, L.y, L.l, r10, x10);
-      load_row<DT>(R.vol, R.d, z + 1, L.y + 1, L.l, r11, x11);
-      const Corners C = make_corners(r00, x00, r01, x01, r10, x10, r11, x11);
+    for (int p = 0; p + 1 < T.np; ++p) {
+      const int z = T.pz0 - 1 + p;
+      const Corners C = tile_corners(s_bits, T, L, p, tid, R.G);
       uint32_t any = 0u, all = 0xffffffffu;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -241,10 +340,6 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
           }
         }
       }
-      r00 = r10;
-      x00 = x10;
-      r01 = r11;
-      x01 = x11;
     }
   }
 
@@ -430,6 +525,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
                                                              unsigned long long* __restrict__ key,
                                                              double* __restrict__ tsoft, float* __restrict__ pos,
                                                              int* __restrict__ orig, float* __restrict__ rowmax) {
+  extern __shared__ uint32_t s_bits[];
   __shared__ int s_scan[4];
   const long long brick = xcd_remap(blockIdx.x, nbricks);
   if (part[brick].nv == 0) return;
@@ -437,24 +533,17 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   const Roi R = rois[roi];
   const RoiMeta M = meta[roi];
   const int tid = threadIdx.x;
-  const Lane L = lane_of(R, brick - R.brick_begin, tid);
+  const Tile T = tile_of(R, brick - R.brick_begin);
+  load_tile<DT>(R, T, s_bits);
+  __syncthreads();
+  const Lane L = lane_of(R, T, tid);
   long long base = M.row_off + brick_voff[brick];
-
-  uint32_t r00 = 0, x00 = 0, r01 = 0, x01 = 0;
-  if (L.valid) {
-    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y, L.l, r00, x00);
-    load_row<DT>(R.vol, R.d, L.pz0 - 1, L.y + 1, L.l, r01, x01);
-  }
-  // every thread of the brick runs the same number of steps (block scans inside)
-  const int steps = min(kTZ, R.d[0] + 1 - (int)(((brick - R.brick_begin) % R.nzc) * kTZ));
-  for (int st = 0; st < steps; ++st) {
-    const int z = L.pz0 + st - 1;
+  // every thread of the brick runs the same steps (block scans inside)
+  for (int p = 0; p + 1 < T.np; ++p) {
+    const int z = T.pz0 - 1 + p;
     uint32_t e[3] = {0u, 0u, 0u};
-    uint32_t r10 = 0, x10 = 0, r11 = 0, x11 = 0;
     if (L.valid) {
-      load_row<DT>(R.vol, R.d, z + 1, L.y, L.l, r10, x10);
-      load_row<DT>(R.vol, R.d, z + 1, L.y + 1, L.l, r11, x11);
-      const Corners C = make_corners(r00, x00, r01, x01, r10, x10, r11, x11);
+      const Corners C = tile_corners(s_bits, T, L, p, tid, R.G);
       e[0] = (C.c[0] ^ C.c[4]) & L.vmask;
       e[1] = (C.c[0] ^ C.c[2]) & L.vmask;
       e[2] = (C.c[0] ^ C.c[1]) & L.vmask;
@@ -494,10 +583,6 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
       }
     }
     base += total;
-    r00 = r10;
-    x00 = x10;
-    r01 = r11;
-    x01 = x11;
   }
 }
 
@@ -534,14 +619,17 @@ __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, floa
 // ---------------------------------------------------------------------------
 // Launchers.
 
-hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, BrickPart* part,
+size_t mesh_lds_bytes(int max_G) { return sizeof(uint32_t) * (size_t)(kTZ + 1) * (kBrickThreads + 1 + max_G); }
+
+hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G, BrickPart* part,
                              hipStream_t st) {
   if (nbricks <= 0) return hipSuccess;
+  const size_t lds = mesh_lds_bytes(max_G);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_mesh_count<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+    hipLaunchKernelGGL(k_mesh_count<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
                        part);
   else
-    hipLaunchKernelGGL(k_mesh_count<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+    hipLaunchKernelGGL(k_mesh_count<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
                        part);
   return hipGetLastError();
 }
@@ -554,15 +642,17 @@ hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, in
   return hipGetLastError();
 }
 
-hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, const BrickPart* part,
-                            const long long* brick_voff, const RoiMeta* meta, unsigned long long* key, double* tsoft,
-                            float* pos, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st) {
+hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                            const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
+                            unsigned long long* key, double* tsoft, float* pos, int* orig, float* rowmax, int* blkseg,
+                            Seg* segs, hipStream_t st) {
+  const size_t lds = mesh_lds_bytes(max_G);
   if (nbricks > 0) {
     if (dtype == 0)
-      hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+      hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
                          part, brick_voff, meta, key, tsoft, pos, orig, rowmax);
     else
-      hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), 0, st, rois, n_rois, nbricks,
+      hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
                          part, brick_voff, meta, key, tsoft, pos, orig, rowmax);
   }
   hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, orig, rowmax, blkseg, segs);

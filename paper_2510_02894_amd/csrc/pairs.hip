@@ -214,10 +214,18 @@ __device__ __forceinline__ void pair_tile(const float (&A)[kItileBlocks], float 
     d[2 * r] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], b0, zero, 0, 0, 0);
     d[2 * r + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], b1, zero, 0, 0, 0);
   }
+  // One v_max3 per two pair values (the floor: the matrix core and the VALU do
+  // not co-execute, so every VALU cycle adds to the MFMA cycles).  The empty asm
+  // pins the running maximum after each tile so the compiler cannot
+  // re-associate two tiles into max/max/max3 (three ops per four values).
 #pragma unroll
   for (int r = 0; r < kItileBlocks; ++r)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[r][q] = fmaxf(acc[r][q], fmaxf(d[2 * r][q], d[2 * r + 1][q]));
+    for (int q = 0; q < 4; ++q) {
+      float a = fmaxf(acc[r][q], fmaxf(d[2 * r][q], d[2 * r + 1][q]));
+      asm volatile("" : "+v"(a));
+      acc[r][q] = a;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ pos, const Seg* __restrict__ segs,
@@ -228,22 +236,46 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
   const int lane = threadIdx.x & 63;
   const long long n_items = totals[T_NITEM];
   const long long ncol = totals[T_NCOL];
+  // Items are handed out in increasing order, so a wave's next item is usually
+  // in the same column as its last one or a few columns later: walk forward a
+  // few steps from the cached column, else binary-search the rest.
+  long long col = 0, col_lo = 0, col_hi = ncol > 1 ? itembase[1] : n_items;
   for (;;) {
     unsigned int got = 0;
     if (lane == 0) got = atomicAdd(work_ctr, 1u);
     const long long item = (long long)__builtin_amdgcn_readfirstlane((int)__shfl(got, 0, 64));
     if (item >= n_items) break;
-    long long lo = 0, hi = ncol - 1;
-    while (lo < hi) {
-      const long long mid = (lo + hi + 1) >> 1;
-      if (itembase[mid] <= item)
-        lo = mid;
-      else
-        hi = mid - 1;
+    int steps = 0;
+    while (item >= col_hi && steps < 4) {
+      ++col;
+      ++steps;
+      col_lo = col_hi;
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
     }
+    if (item >= col_hi) {
+      long long lo2 = col, hi2 = ncol - 1;
+      while (lo2 < hi2) {
+        const long long mid = (lo2 + hi2 + 1) >> 1;
+        if (itembase[mid] <= item)
+          lo2 = mid;
+        else
+          hi2 = mid - 1;
+      }
+      col = lo2;
+      col_lo = itembase[col];
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+    }
+    // an empty column shares its base with the next one: skip forward to the
+    // last column whose base is <= item
+    while (col + 1 < ncol && item >= col_hi) {
+      ++col;
+      col_lo = col_hi;
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+    }
+    const long long lo = col;
     const Col C = cols[lo];
     const Seg S = segs[C.seg];
-    const int it = (int)(item - itembase[lo]);
+    const int it = (int)(item - col_lo);
     const long long rb = S.row_begin >> 4;
     const int nb = S.n_rows >> 4;
     const int i0 = it * kItileBlocks;

@@ -19,13 +19,16 @@ struct RoiResult {
 };
 
 // mesh.hip
-hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, BrickPart* part,
+// Dynamic LDS of the mesh kernels for ROIs with at most max_G row-groups per row.
+size_t mesh_lds_bytes(int max_G);
+hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G, BrickPart* part,
                              hipStream_t st);
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
                               long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st);
-hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, const BrickPart* part,
-                            const long long* brick_voff, const RoiMeta* meta, unsigned long long* key, double* tsoft,
-                            float* pos, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
+hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                            const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
+                            unsigned long long* key, double* tsoft, float* pos, int* orig, float* rowmax, int* blkseg,
+                            Seg* segs, hipStream_t st);
 
 // scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
 // tmp must hold scan_tmp_elems(n) int64.
