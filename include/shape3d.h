@@ -112,6 +112,42 @@ int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double s
 int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
                      int64_t* ids, double* pos, int64_t cap, int64_t* n_out, void* stream);
 
+/*
+ * Differentiable soft-mask mode.  The paper's mesh pass (Sec. 2, marching
+ * cubes on the segmentation threshold) applied to a float32 probability map
+ * p with isolevel 0.5: vertices at t = (0.5 - p_u) / (p_b - p_u) along each
+ * crossing edge, so the six features are piecewise-smooth functions of p.
+ *
+ * shape3d_soft_forward -- the features of a soft mask (as shape3d_ex with
+ * SHAPE3D_F32) and, in `saved` (HOST, caller-owned), what the backward pass
+ * needs: dims, spacing, features, the signed volume and the maximising pairs.
+ *   p: DEVICE float32 (d0, d1, d2).  out: HOST double[6].  Synchronous.
+ *
+ * shape3d_soft_backward -- dL/dp for L = sum_f grad_out[f] * F_f, the exact
+ * derivative of the forward pass where the triangulation and the maximising
+ * pairs do not change (area and volume through every vertex position, each
+ * diameter through its maximising pair; MeshVolume = |signed volume| uses
+ * its sign).
+ *   p:        DEVICE float32, the same values the forward pass saw.
+ *   saved:    HOST, from shape3d_soft_forward on p.
+ *   grad_out: HOST double[6], finite.
+ *   grad_p:   DEVICE float32 (d0, d1, d2), fully written (0 away from the surface).
+ * Synchronous on `stream`.
+ */
+typedef struct {
+  int64_t dims[3];
+  double spacing[3];
+  double features[6];
+  double signed_volume;
+  int64_t pair_ids[4][2];
+  int status;
+} shape3d_soft_saved;
+
+int shape3d_soft_forward(const float* p, const int64_t dims[3], const double spacing[3], double out[6],
+                         shape3d_soft_saved* saved, void* stream);
+int shape3d_soft_backward(const float* p, const shape3d_soft_saved* saved, const double grad_out[6],
+                          float* grad_p, void* stream);
+
 /* Message describing the last failure of the calling thread ("" if none). */
 const char* shape3d_last_error(void);
 

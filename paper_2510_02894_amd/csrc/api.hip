@@ -294,7 +294,7 @@ int run_emit(Workspace& w, const Plan& P, int dtype, hipStream_t st) {
 }
 
 int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double out[6],
-                 shape3d_stats* stats, int timing, hipStream_t st) {
+                 shape3d_stats* stats, int timing, hipStream_t st, RoiResult* raw = nullptr) {
   int rc = check_args(vol, dtype, dims, spacing);
   if (rc) return rc;
   if (!out) return fail(SHAPE3D_EINVAL, "null out");
@@ -311,6 +311,10 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
     if (stats) {
       memset(stats, 0, sizeof(*stats));
       for (int f = 0; f < 4; ++f) stats->pair_ids[f][0] = stats->pair_ids[f][1] = -1;
+    }
+    if (raw) {
+      memset(raw, 0, sizeof(*raw));
+      for (int f = 0; f < 4; ++f) raw->ids[f][0] = raw->ids[f][1] = -1;
     }
     g_err.clear();
     return SHAPE3D_EMPTY;
@@ -336,6 +340,7 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   HIPCK(hipStreamSynchronize(st));
   if (rh->status < 0) return fail(rh->status, "candidate rows of the exact refinement exceeded their capacity");
   for (int f = 0; f < 6; ++f) out[f] = rh->out[f];
+  if (raw) *raw = *rh;
   if (stats) {
     memset(stats, 0, sizeof(*stats));
     stats->n_vertices = rh->V;
@@ -402,6 +407,61 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
                                dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr, (const RoiMeta*)w.meta.p,
                                (const Roi*)w.rois.p, (long long*)ids, pos, M.V, st));
   HIPCK(hipStreamSynchronize(st));
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
+int shape3d_soft_forward(const float* p, const int64_t dims[3], const double spacing[3], double out[6],
+                         shape3d_soft_saved* saved, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!saved) return fail(SHAPE3D_EINVAL, "null saved context");
+  RoiResult raw;
+  const int rc = shape3d_impl(p, SHAPE3D_F32, dims, spacing, out, nullptr, 0, (hipStream_t)stream, &raw);
+  if (rc < 0) return rc;
+  for (int k = 0; k < 3; ++k) {
+    saved->dims[k] = dims[k];
+    saved->spacing[k] = spacing[k];
+  }
+  for (int f = 0; f < 6; ++f) saved->features[f] = out[f];
+  saved->signed_volume = raw.vol_signed;
+  for (int f = 0; f < 4; ++f) {
+    saved->pair_ids[f][0] = raw.ids[f][0];
+    saved->pair_ids[f][1] = raw.ids[f][1];
+  }
+  saved->status = rc;
+  return rc;
+}
+
+int shape3d_soft_backward(const float* p, const shape3d_soft_saved* saved, const double grad_out[6], float* grad_p,
+                          void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!saved || !grad_out || !grad_p) return fail(SHAPE3D_EINVAL, "null argument");
+  int rc = check_args(p, SHAPE3D_F32, saved->dims, saved->spacing);
+  if (rc) return rc;
+  rc = check_args(grad_p, SHAPE3D_F32, saved->dims, saved->spacing);
+  if (rc) return rc;
+  for (int f = 0; f < 6; ++f)
+    if (!std::isfinite(grad_out[f])) return fail(SHAPE3D_EINVAL, "grad_out must be finite");
+  Workspace* wp = nullptr;
+  if ((rc = get_workspace(&wp))) return rc;
+  SoftBwdArgs A;
+  memset(&A, 0, sizeof(A));
+  for (int k = 0; k < 3; ++k) {
+    A.d[k] = (int)saved->dims[k];
+    A.s[k] = saved->spacing[k];
+    A.o[k] = 0.5 * (double)saved->dims[k] * saved->spacing[k];
+  }
+  for (int f = 0; f < 6; ++f) A.gout[f] = grad_out[f];
+  // an empty mask has no surface: every gradient is zero
+  const bool empty = saved->status == SHAPE3D_EMPTY;
+  A.g_vol_signed = grad_out[0] * (saved->signed_volume >= 0.0 ? 1.0 : -1.0);
+  for (int f = 0; f < 4; ++f) {
+    A.D[f] = empty ? 0.0 : saved->features[2 + f];
+    A.pair_ids[f][0] = saved->pair_ids[f][0];
+    A.pair_ids[f][1] = saved->pair_ids[f][1];
+  }
+  HIPCK(launch_soft_backward(p, A, grad_p, wp->cu_count, (hipStream_t)stream));
+  HIPCK(hipStreamSynchronize((hipStream_t)stream));
   g_err.clear();
   return SHAPE3D_OK;
 }

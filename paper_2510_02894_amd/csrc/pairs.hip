@@ -514,6 +514,7 @@ __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const G
     Q.T = M.T;
     Q.pairs2d = pairs2d[r];
     Q.out[0] = fabs(M.vol);
+    Q.vol_signed = M.vol;
     Q.out[1] = M.area;
     for (int f = 0; f < 4; ++f) {
       const GroupRes G = gres[4 * r + f];

@@ -9,6 +9,7 @@ namespace s3d {
 // Per-ROI result record written by the finalisation kernel.
 struct RoiResult {
   double out[6];
+  double vol_signed;
   long long V, T;
   long long ids[4][2];
   long long rows[4][2];
@@ -78,6 +79,19 @@ struct PairBufs {
   long long* pairs2d;      // [n_rois] in-plane pairs n*(n-1)/2 summed over buckets
   int cu_count;
 };
+
+// soft.hip: adjoint of the soft-mask forward pass.
+struct SoftBwdArgs {
+  int d[3];
+  int pad_;
+  double s[3];
+  double o[3];                  // origin of the signed volume sum (array centre)
+  double gout[6];               // dL/dF
+  double g_vol_signed;          // gout[0] * sign(signed volume)
+  double D[4];                  // the four diameters (maxima), 0 if none
+  long long pair_ids[4][2];     // canonical ids of the maximising pairs, -1 if none
+};
+hipError_t launch_soft_backward(const float* p, const SoftBwdArgs& A, float* grad, int cu_count, hipStream_t st);
 
 // pairs.hip
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list

@@ -53,6 +53,17 @@ class Stats(ctypes.Structure):
         )
 
 
+class SoftSaved(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int64 * 3),
+        ("spacing", ctypes.c_double * 3),
+        ("features", ctypes.c_double * 6),
+        ("signed_volume", ctypes.c_double),
+        ("pair_ids", (ctypes.c_int64 * 2) * 4),
+        ("status", ctypes.c_int),
+    ]
+
+
 class Shape3DError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("shape3d failed with status %d: %s" % (status, message))
@@ -79,6 +90,12 @@ def load():
         lib.shape3d_vertices.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int64, i64p, ctypes.c_void_p]
         lib.shape3d_vertices.restype = ctypes.c_int
+        lib.shape3d_soft_forward.argtypes = [ctypes.c_void_p, i64p, f64p, f64p, ctypes.POINTER(SoftSaved),
+                                             ctypes.c_void_p]
+        lib.shape3d_soft_forward.restype = ctypes.c_int
+        lib.shape3d_soft_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(SoftSaved), f64p, ctypes.c_void_p,
+                                              ctypes.c_void_p]
+        lib.shape3d_soft_backward.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -183,6 +200,67 @@ def vertices(vol, spacing=(1.0, 1.0, 1.0), with_pos: bool = True):
                                   _stream())
         _check(rc)
     return ids[:V], (pos[:V] if pos is not None else None)
+
+
+def soft_forward(p, spacing=(1.0, 1.0, 1.0)):
+    """Features of a float32 soft mask and the context its backward pass needs."""
+    lib = load()
+    if _volume(p) != F32:
+        raise TypeError("soft masks are float32")
+    dims, sp = _dims_spacing(p.shape, spacing)
+    out = (ctypes.c_double * 6)()
+    saved = SoftSaved()
+    _check(lib.shape3d_soft_forward(ctypes.c_void_p(p.data_ptr()), dims, sp, out, ctypes.byref(saved), _stream()))
+    return np.array(out[:], dtype=np.float64), saved
+
+
+def soft_backward(p, saved: SoftSaved, grad_out):
+    """dL/dp (float32 tensor like p) for L = sum_f grad_out[f] * F_f."""
+    import torch
+
+    lib = load()
+    if _volume(p) != F32:
+        raise TypeError("soft masks are float32")
+    g = (ctypes.c_double * 6)(*[float(x) for x in np.asarray(grad_out, dtype=np.float64).reshape(6)])
+    grad = torch.empty_like(p)
+    _check(lib.shape3d_soft_backward(ctypes.c_void_p(p.data_ptr()), ctypes.byref(saved), g,
+                                     ctypes.c_void_p(grad.data_ptr()), _stream()))
+    return grad
+
+
+def _autograd_function():
+    import torch
+
+    class Shape3DFunction(torch.autograd.Function):
+        """features = Shape3DFunction.apply(p, spacing): float64 tensor [6] on p's
+        device; differentiable with respect to the float32 soft mask p."""
+
+        @staticmethod
+        def forward(ctx, p, spacing):
+            p = p.contiguous()
+            feats, saved = soft_forward(p, spacing)
+            ctx.save_for_backward(p)
+            ctx.saved = saved
+            return torch.tensor(feats, dtype=torch.float64, device=p.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (p,) = ctx.saved_tensors
+            g = grad_out.detach().to("cpu", torch.float64).numpy()
+            return soft_backward(p, ctx.saved, g), None
+
+    return Shape3DFunction
+
+
+_FN = None
+
+
+def shape_features(p, spacing=(1.0, 1.0, 1.0)):
+    """Differentiable features of a soft mask (see Shape3DFunction)."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_function()
+    return _FN.apply(p, tuple(float(x) for x in spacing))
 
 
 def release():
