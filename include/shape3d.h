@@ -101,6 +101,37 @@ int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double s
                double out[6], shape3d_stats* stats, int timing, void* stream);
 
 /*
+ * shape3d_batched -- the six features of many ROIs in one pass of the
+ * pipeline (all ROIs' bricks, vertices, plane buckets and pair tiles share
+ * each launch).  The paper computes one ROI per call (Sec. 3 measures cases
+ * one by one); a batch lets small ROIs fill the GPU together.
+ *   base:   DEVICE pointer; ROI r's volume (dtype, C-contiguous) starts at
+ *           base + rois[r].offset elements.  Every ROI must lie inside the
+ *           allocation that holds base.
+ *   rois:   HOST array of n_rois descriptors (dims and spacing as in shape3d).
+ *   n_rois: 1 .. SHAPE3D_MAX_ROIS.
+ *   out:    HOST double[6 * n_rois]; status: HOST int[n_rois] (SHAPE3D_OK or
+ *           SHAPE3D_EMPTY per ROI).
+ *   flags:  SHAPE3D_BATCH_GRAPH records the launch sequence as a hipGraph on
+ *           the first call and replays it on later calls with the same base,
+ *           dtype and ROI table (the device buffers are sized by the first
+ *           call; if a replay finds more vertices than they hold, the call is
+ *           re-run eagerly and recorded again).
+ * Synchronous on `stream`.  Returns SHAPE3D_OK or a negative error.
+ */
+typedef struct {
+  int64_t offset;     /* element offset of the ROI's volume from base */
+  int64_t dims[3];
+  double spacing[3];
+} shape3d_roi;
+
+#define SHAPE3D_BATCH_GRAPH 1
+#define SHAPE3D_MAX_ROIS (1 << 20)
+
+int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out,
+                    int* status, int flags, void* stream);
+
+/*
  * shape3d_vertices -- the mesh vertex set, for verification.
  *   ids:  DEVICE int64[cap]; receives the canonical ids of all V vertices
  *         (in the library's emission order, which is deterministic).

@@ -1,11 +1,17 @@
 // api.hip -- the C ABI (include/shape3d.h): argument checks, the per-device
-// workspace, and the launch sequence of one call.
+// workspace, and the launch sequence of a call.
 //
-// Sequence of a call (all on the caller's stream):
+// Every call processes a batch of ROIs (a single ROI is a batch of one), all
+// on the caller's stream:
 //   mesh count -> per-ROI totals (vertex offsets, area, volume, centre)
-//   -> read back the vertex count (sizes the vertex buffers)
-//   -> emission -> plane buckets and work list -> MFMA pair maxima
-//   -> exact FP64 refinement -> finalisation -> read back the results.
+//   -> read back the total vertex rows (sizes the vertex buffers)
+//   -> capacity check -> emission -> plane buckets and work list
+//   -> MFMA pair maxima -> exact FP64 refinement -> finalisation
+//   -> read back the per-ROI results.
+// The batched entry point can record everything after the ROI table upload as
+// a hipGraph and replay it for later calls with the same layout; the capacity
+// check turns a replay on larger meshes into SHAPE3D_ECAPACITY for the graph
+// run, after which the call is re-run eagerly with larger buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,33 +49,58 @@ struct Buf {
   size_t cap = 0;
 };
 
+struct GraphRec {
+  hipGraphExec_t exec = nullptr;
+  long long generation = -1;
+  RoiResult* host_res = nullptr;  // pinned, written by the graph's last copy
+  long long n_rois = 0;
+};
+
 struct Workspace {
   int device = -1;
   int cu_count = 0;
+  long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
       bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase;
-  void* host = nullptr;
+  void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
   bool events = false;
+  hipStream_t graph_stream = nullptr;  // graphs are recorded and replayed here (the caller's
+                                       // stream may be the legacy null stream, which cannot record)
+  long long rows0_cap = 0;  // layout-0 rows the vertex buffers were sized for
+  std::map<std::string, GraphRec> graphs;
 
   std::vector<Buf*> all() {
-    return {&rois, &part,  &brick_voff, &meta,  &totals, &key,  &tsoft,   &pos,      &orig,     &rowmax,
-            &blkseg, &segs, &bcnt,      &bcur,  &bsz,    &bflag, &brow,   &bseg,     &ncol,     &colbase,
-            &cols,  &nitem, &itembase,  &scan_tmp, &counters, &gres, &cand, &res, &pairs2d, &cand_nch, &cand_chbase};
+    return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
+            &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &ncol,     &colbase,
+            &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
+            &cand_chbase};
   }
 };
 
 std::map<int, Workspace*> g_ws;
 
-int ensure(Buf& b, size_t bytes) {
+void drop_graphs(Workspace& w) {
+  for (auto& kv : w.graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.host_res) (void)hipHostFree(kv.second.host_res);
+  }
+  w.graphs.clear();
+}
+
+int ensure(Workspace& w, Buf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return SHAPE3D_OK;
   size_t want = std::max(bytes, b.cap + b.cap / 2);
+  want = (want + 255) & ~(size_t)255;
+  // recorded graphs hold the old pointer: finish outstanding work and drop them
+  (void)hipDeviceSynchronize();
+  drop_graphs(w);
+  w.generation++;
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.cap = 0;
-  want = (want + 255) & ~(size_t)255;
   if (hipMalloc(&b.p, want) != hipSuccess) {
     (void)hipGetLastError();
     b.p = nullptr;
@@ -81,6 +112,9 @@ int ensure(Buf& b, size_t bytes) {
 
 int ensure_host(Workspace& w, size_t bytes) {
   if (w.host_cap >= bytes) return SHAPE3D_OK;
+  (void)hipDeviceSynchronize();
+  drop_graphs(w);
+  w.generation++;
   if (w.host) (void)hipHostFree(w.host);
   w.host = nullptr;
   w.host_cap = 0;
@@ -109,52 +143,70 @@ int get_workspace(Workspace** out) {
     w->cu_count = prop.multiProcessorCount;
     for (int i = 0; i < 8; ++i) HIPCK(hipEventCreate(&w->ev[i]));
     w->events = true;
+    HIPCK(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
     it = g_ws.emplace(dev, w).first;
   }
   *out = it->second;
   return SHAPE3D_OK;
 }
 
-int check_args(const void* vol, int dtype, const int64_t dims[3], const double spacing[3]) {
-  if (!vol || !dims || !spacing) return fail(SHAPE3D_EINVAL, "null argument");
-  if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "dtype must be SHAPE3D_U8 or SHAPE3D_F32");
+int check_dims_spacing(const int64_t dims[3], const double spacing[3]) {
   for (int k = 0; k < 3; ++k) {
     if (dims[k] < 1 || dims[k] > SHAPE3D_MAX_DIM) return fail(SHAPE3D_EINVAL, "dims out of range");
-  }
-  if (dims[2] > SHAPE3D_MAX_DIM2) return fail(SHAPE3D_EINVAL, "dims[2] out of range");
-  for (int k = 0; k < 3; ++k) {
     if (!(spacing[k] > 0.0) || !std::isfinite(spacing[k])) return fail(SHAPE3D_EINVAL, "spacing must be finite and > 0");
   }
-  const size_t elem = dtype == SHAPE3D_U8 ? 1 : 4;
-  const size_t need = (size_t)dims[0] * (size_t)dims[1] * (size_t)dims[2] * elem;
+  if (dims[2] > SHAPE3D_MAX_DIM2) return fail(SHAPE3D_EINVAL, "dims[2] out of range");
+  return SHAPE3D_OK;
+}
+
+// The device allocation holding ptr: [*base, *base + *size) (*base = null if
+// the runtime cannot tell).  Fails for host memory.
+int device_range(const void* ptr, const char** base, size_t* size) {
   hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, vol) != hipSuccess) {
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
     (void)hipGetLastError();
     return fail(SHAPE3D_EINVAL, "volume pointer is not HIP device memory");
   }
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
     return fail(SHAPE3D_EINVAL, "volume pointer is not HIP device memory");
-  void* base = nullptr;
-  size_t size = 0;
-  if (hipMemGetAddressRange(&base, &size, (void*)vol) == hipSuccess && base) {
-    if ((const char*)vol + need > (const char*)base + size)
-      return fail(SHAPE3D_EINVAL, "volume extends past the end of its allocation");
+  void* b = nullptr;
+  size_t s = 0;
+  if (hipMemGetAddressRange(&b, &s, (void*)ptr) == hipSuccess && b) {
+    *base = (const char*)b;
+    *size = s;
   } else {
     (void)hipGetLastError();
+    *base = nullptr;
+    *size = 0;
   }
   return SHAPE3D_OK;
 }
 
-// Host description of one ROI.
-struct Plan {
-  Roi roi;
-  long long nbricks;
-  long long n_buckets;
+int check_args(const void* vol, int dtype, const int64_t dims[3], const double spacing[3]) {
+  if (!vol || !dims || !spacing) return fail(SHAPE3D_EINVAL, "null argument");
+  if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "dtype must be SHAPE3D_U8 or SHAPE3D_F32");
+  int rc = check_dims_spacing(dims, spacing);
+  if (rc) return rc;
+  const size_t need = (size_t)dims[0] * (size_t)dims[1] * (size_t)dims[2] * (dtype == SHAPE3D_U8 ? 1 : 4);
+  const char* base;
+  size_t size;
+  if ((rc = device_range(vol, &base, &size))) return rc;
+  if (base && (const char*)vol + need > base + size)
+    return fail(SHAPE3D_EINVAL, "volume extends past the end of its allocation");
+  return SHAPE3D_OK;
+}
+
+// Host description of a batch.
+struct Batch {
+  std::vector<Roi> rois;
+  long long nbricks = 0;
+  long long n_buckets = 0;
+  int max_G = 1;
+  int n() const { return (int)rois.size(); }
 };
 
-Plan make_plan(const void* vol, const int64_t dims[3], const double spacing[3]) {
-  Plan P;
-  Roi& R = P.roi;
+void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double spacing[3]) {
+  Roi R;
   memset(&R, 0, sizeof(R));
   R.vol = vol;
   for (int k = 0; k < 3; ++k) {
@@ -165,88 +217,90 @@ Plan make_plan(const void* vol, const int64_t dims[3], const double spacing[3]) 
   R.nrg = (R.d[1] + 1) * R.G;
   R.nzc = (R.d[0] + 1 + kTZ - 1) / kTZ;
   R.bpz = (R.nrg + kBrickThreads - 1) / kBrickThreads;
-  R.brick_begin = 0;
-  R.bucket_base[0] = 0;
-  R.bucket_base[1] = 2ll * R.d[0] + 1;
+  R.brick_begin = B.nbricks;
+  R.bucket_base[0] = B.n_buckets;
+  R.bucket_base[1] = R.bucket_base[0] + 2ll * R.d[0] + 1;
   R.bucket_base[2] = R.bucket_base[1] + 2ll * R.d[1] + 1;
-  P.nbricks = (long long)R.nzc * R.bpz;
-  P.n_buckets = R.bucket_base[2] + 2ll * R.d[2] + 1;
-  return P;
+  B.nbricks += (long long)R.nzc * R.bpz;
+  B.n_buckets = R.bucket_base[2] + 2ll * R.d[2] + 1;
+  B.max_G = std::max(B.max_G, R.G);
+  B.rois.push_back(R);
 }
 
 struct Sizes {
-  long long V, rows0, rows_bound, seg_cap, col_cap, max_rows_seg;
+  long long rows0, rows_bound, seg_cap, col_cap;
 };
 
-// Steps up to and including the per-ROI totals; reads back V.
-int run_mesh_totals(Workspace& w, const Plan& P, int dtype, hipStream_t st, RoiMeta* meta_h, long long* totals_h,
-                    hipEvent_t ev_after = nullptr) {
-  int rc;
-  if ((rc = ensure(w.rois, sizeof(Roi)))) return rc;
-  if ((rc = ensure(w.part, sizeof(BrickPart) * P.nbricks))) return rc;
-  if ((rc = ensure(w.brick_voff, sizeof(long long) * P.nbricks))) return rc;
-  if ((rc = ensure(w.meta, sizeof(RoiMeta)))) return rc;
-  if ((rc = ensure(w.totals, sizeof(long long) * 16))) return rc;
-  if ((rc = ensure_host(w, 1 << 16))) return rc;
-  memcpy(w.host, &P.roi, sizeof(Roi));
-  HIPCK(hipMemcpyAsync(w.rois.p, w.host, sizeof(Roi), hipMemcpyHostToDevice, st));
-  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, 1, P.nbricks, P.roi.G, (BrickPart*)w.part.p, st));
-  HIPCK(launch_mesh_totals((const Roi*)w.rois.p, 1, P.nbricks, dtype, (const BrickPart*)w.part.p,
-                           (long long*)w.brick_voff.p, (RoiMeta*)w.meta.p, (long long*)w.totals.p, st));
-  if (ev_after) HIPCK(hipEventRecord(ev_after, st));
-  char* h = (char*)w.host + 4096;
-  HIPCK(hipMemcpyAsync(h, w.meta.p, sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(h + 1024, w.totals.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
-  memcpy(meta_h, h, sizeof(RoiMeta));
-  memcpy(totals_h, h + 1024, sizeof(long long) * 2);
-  return SHAPE3D_OK;
-}
-
-int ensure_vertex_bufs(Workspace& w, const Plan& P, int dtype, const RoiMeta& M, const long long* totals_h,
-                       Sizes& S) {
-  int rc;
-  S.V = M.V;
-  S.rows0 = totals_h[0];
-  const long long rows2d_bound = 3 * S.V + (long long)(kSegAlign - 1) * P.n_buckets;
+Sizes sizes_for(const Batch& B, long long rows0) {
+  Sizes S;
+  S.rows0 = rows0;
+  // plane layouts: every vertex lies in one bucket per axis, each bucket padded by < 32 rows
+  const long long rows2d_bound = 3 * S.rows0 + (long long)(kSegAlign - 1) * B.n_buckets;
   S.rows_bound = (S.rows0 + rows2d_bound + kBlk - 1) / kBlk * kBlk;
-  S.seg_cap = 1 + P.n_buckets;
+  S.seg_cap = B.n() + B.n_buckets;
   S.col_cap = S.seg_cap + S.rows_bound / (kJchunkBlocks * kBlk) + 1;
-  S.max_rows_seg = std::max<long long>(M.V_pad, kSegAlign);
-  const long long scan_n = std::max(std::max(P.n_buckets, (long long)kMaxCand), std::max(S.seg_cap, S.col_cap));
-  if ((rc = ensure(w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
-  if (dtype == SHAPE3D_F32 && (rc = ensure(w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
-  if ((rc = ensure(w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
-  if ((rc = ensure(w.orig, sizeof(int) * S.rows_bound))) return rc;
-  if ((rc = ensure(w.rowmax, sizeof(float) * S.rows_bound))) return rc;
-  if ((rc = ensure(w.blkseg, sizeof(int) * (S.rows_bound / kBlk + 1)))) return rc;
-  if ((rc = ensure(w.segs, sizeof(Seg) * S.seg_cap))) return rc;
-  if ((rc = ensure(w.bcnt, sizeof(unsigned int) * P.n_buckets))) return rc;
-  if ((rc = ensure(w.bcur, sizeof(unsigned int) * P.n_buckets))) return rc;
-  if ((rc = ensure(w.bsz, sizeof(long long) * P.n_buckets))) return rc;
-  if ((rc = ensure(w.bflag, sizeof(long long) * P.n_buckets))) return rc;
-  if ((rc = ensure(w.brow, sizeof(long long) * P.n_buckets))) return rc;
-  if ((rc = ensure(w.bseg, sizeof(long long) * P.n_buckets))) return rc;
-  if ((rc = ensure(w.ncol, sizeof(long long) * S.seg_cap))) return rc;
-  if ((rc = ensure(w.colbase, sizeof(long long) * S.seg_cap))) return rc;
-  if ((rc = ensure(w.cols, sizeof(Col) * S.col_cap))) return rc;
-  if ((rc = ensure(w.nitem, sizeof(long long) * S.col_cap))) return rc;
-  if ((rc = ensure(w.itembase, sizeof(long long) * S.col_cap))) return rc;
-  if ((rc = ensure(w.scan_tmp, sizeof(long long) * scan_tmp_elems(scan_n)))) return rc;
-  if ((rc = ensure(w.counters, sizeof(unsigned int) * 4))) return rc;
-  if ((rc = ensure(w.gres, sizeof(GroupRes) * 4))) return rc;
-  if ((rc = ensure(w.cand, sizeof(int) * kMaxCand))) return rc;
-  if ((rc = ensure(w.res, sizeof(RoiResult)))) return rc;
-  if ((rc = ensure(w.pairs2d, sizeof(long long)))) return rc;
-  if ((rc = ensure(w.cand_nch, sizeof(long long) * kMaxCand))) return rc;
-  if ((rc = ensure(w.cand_chbase, sizeof(long long) * kMaxCand))) return rc;
+  return S;
+}
+
+// Buffers that depend only on the batch layout.
+int ensure_layout_bufs(Workspace& w, const Batch& B) {
+  int rc;
+  const int n = B.n();
+  if ((rc = ensure(w, w.rois, sizeof(Roi) * n))) return rc;
+  if ((rc = ensure(w, w.part, sizeof(BrickPart) * B.nbricks))) return rc;
+  if ((rc = ensure(w, w.brick_voff, sizeof(long long) * B.nbricks))) return rc;
+  if ((rc = ensure(w, w.meta, sizeof(RoiMeta) * n))) return rc;
+  if ((rc = ensure(w, w.totals, sizeof(long long) * 16))) return rc;
+  if ((rc = ensure(w, w.counters, sizeof(unsigned int) * 4))) return rc;
+  if ((rc = ensure(w, w.gres, sizeof(GroupRes) * 4 * (size_t)n))) return rc;
+  if ((rc = ensure(w, w.res, sizeof(RoiResult) * n))) return rc;
+  if ((rc = ensure(w, w.pairs2d, sizeof(long long) * n))) return rc;
+  if ((rc = ensure(w, w.bcnt, sizeof(unsigned int) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.bcur, sizeof(unsigned int) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.bsz, sizeof(long long) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.bflag, sizeof(long long) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.brow, sizeof(long long) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.bseg, sizeof(long long) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.cand, sizeof(int) * kMaxCand))) return rc;
+  if ((rc = ensure(w, w.cand_nch, sizeof(long long) * kMaxCand))) return rc;
+  if ((rc = ensure(w, w.cand_chbase, sizeof(long long) * kMaxCand))) return rc;
+  // pinned staging: [0, 4096) read-backs, then the ROI table, then the results
+  const size_t host_need = 4096 + sizeof(Roi) * (size_t)n + 256 + sizeof(RoiResult) * (size_t)n;
+  if ((rc = ensure_host(w, host_need))) return rc;
   return SHAPE3D_OK;
 }
 
-PairBufs pair_bufs(Workspace& w, const Plan& P, int dtype, const Sizes& S) {
+RoiResult* host_results(Workspace& w, const Batch& B) {
+  const uintptr_t p = (uintptr_t)w.host + 4096 + sizeof(Roi) * (size_t)B.n();
+  return (RoiResult*)((p + 255) & ~(uintptr_t)255);
+}
+
+// Buffers sized by the layout-0 row count (all ROIs' padded vertex rows).
+int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0, Sizes& S) {
+  int rc;
+  S = sizes_for(B, std::max<long long>(rows0, w.rows0_cap));
+  const long long scan_n = std::max(std::max(B.n_buckets, (long long)kMaxCand), std::max(S.seg_cap, S.col_cap));
+  if ((rc = ensure(w, w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
+  if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
+  if ((rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
+  if ((rc = ensure(w, w.orig, sizeof(int) * S.rows_bound))) return rc;
+  if ((rc = ensure(w, w.rowmax, sizeof(float) * S.rows_bound))) return rc;
+  if ((rc = ensure(w, w.blkseg, sizeof(int) * (S.rows_bound / kBlk + 1)))) return rc;
+  if ((rc = ensure(w, w.segs, sizeof(Seg) * S.seg_cap))) return rc;
+  if ((rc = ensure(w, w.ncol, sizeof(long long) * S.seg_cap))) return rc;
+  if ((rc = ensure(w, w.colbase, sizeof(long long) * S.seg_cap))) return rc;
+  if ((rc = ensure(w, w.cols, sizeof(Col) * S.col_cap))) return rc;
+  if ((rc = ensure(w, w.nitem, sizeof(long long) * S.col_cap))) return rc;
+  if ((rc = ensure(w, w.itembase, sizeof(long long) * S.col_cap))) return rc;
+  if ((rc = ensure(w, w.scan_tmp, sizeof(long long) * scan_tmp_elems(scan_n)))) return rc;
+  w.rows0_cap = S.rows0;
+  return SHAPE3D_OK;
+}
+
+PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
   PairBufs B;
   B.rois = (const Roi*)w.rois.p;
-  B.n_rois = 1;
+  B.n_rois = Bt.n();
   B.meta = (const RoiMeta*)w.meta.p;
   B.key = (const unsigned long long*)w.key.p;
   B.tsoft = dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr;
@@ -256,7 +310,7 @@ PairBufs pair_bufs(Workspace& w, const Plan& P, int dtype, const Sizes& S) {
   B.blkseg = (int*)w.blkseg.p;
   B.segs = (Seg*)w.segs.p;
   B.rows0 = S.rows0;
-  B.n_buckets = P.n_buckets;
+  B.n_buckets = Bt.n_buckets;
   B.bcnt = (unsigned int*)w.bcnt.p;
   B.bcur = (unsigned int*)w.bcur.p;
   B.bsz = (long long*)w.bsz.p;
@@ -275,7 +329,7 @@ PairBufs pair_bufs(Workspace& w, const Plan& P, int dtype, const Sizes& S) {
   B.counters = (unsigned int*)w.counters.p;
   B.gres = (GroupRes*)w.gres.p;
   B.cand = (int*)w.cand.p;
-  B.max_rows_seg = S.max_rows_seg;
+  B.max_rows_seg = S.rows0;
   B.rows_bound = S.rows_bound;
   B.res = (RoiResult*)w.res.p;
   B.pairs2d = (long long*)w.pairs2d.p;
@@ -285,12 +339,84 @@ PairBufs pair_bufs(Workspace& w, const Plan& P, int dtype, const Sizes& S) {
   return B;
 }
 
-int run_emit(Workspace& w, const Plan& P, int dtype, hipStream_t st) {
-  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, 1, P.nbricks, P.roi.G, (const BrickPart*)w.part.p,
-                         (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p, (unsigned long long*)w.key.p,
+// Mesh count and per-ROI totals (launches only).
+int launch_head(Workspace& w, const Batch& Bt, int dtype, hipStream_t st) {
+  HIPCK(launch_fill_u32((unsigned int*)w.counters.p, 0u, 4, st));
+  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (BrickPart*)w.part.p, st));
+  HIPCK(launch_mesh_totals((const Roi*)w.rois.p, Bt.n(), Bt.nbricks, dtype, (const BrickPart*)w.part.p,
+                           (long long*)w.brick_voff.p, (RoiMeta*)w.meta.p, (long long*)w.totals.p, st));
+  return SHAPE3D_OK;
+}
+
+// Everything after the totals (launches only).  ev: optional phase events
+// recorded before emission, buckets, pairs, refinement and finalisation.
+int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStream_t st, RoiResult* host_res,
+                hipEvent_t* ev) {
+  const PairBufs B = pair_bufs(w, Bt, dtype, S);
+  HIPCK(launch_check_capacity(Bt.n(), S.rows0, (RoiMeta*)w.meta.p, (long long*)w.totals.p,
+                              (unsigned int*)w.counters.p + 2, st));
+  if (ev) HIPCK(hipEventRecord(ev[0], st));
+  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (const BrickPart*)w.part.p,
+                         (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
+                         (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
                          dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, (int*)w.orig.p,
                          (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
+  if (ev) HIPCK(hipEventRecord(ev[1], st));
+  HIPCK(launch_buckets(B, st));
+  HIPCK(launch_init_groups(B, st));
+  HIPCK(launch_fill_u32(B.counters, 0u, 2, st));
+  if (ev) HIPCK(hipEventRecord(ev[2], st));
+  HIPCK(launch_pair_maxima(B, st));
+  if (ev) HIPCK(hipEventRecord(ev[3], st));
+  HIPCK(launch_refine(B, st));
+  if (ev) HIPCK(hipEventRecord(ev[4], st));
+  HIPCK(launch_finalize(B, st));
+  HIPCK(hipMemcpyAsync(host_res, w.res.p, sizeof(RoiResult) * Bt.n(), hipMemcpyDeviceToHost, st));
   return SHAPE3D_OK;
+}
+
+// One eager run of a batch; results land in host_res (pinned, one per ROI).
+int run_eager(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, RoiResult* host_res, int timing,
+              float* phase_ms) {
+  int rc;
+  char* h = (char*)w.host;
+  memcpy(h + 4096, Bt.rois.data(), sizeof(Roi) * Bt.n());
+  HIPCK(hipMemcpyAsync(w.rois.p, h + 4096, sizeof(Roi) * Bt.n(), hipMemcpyHostToDevice, st));
+  if (timing) HIPCK(hipEventRecord(w.ev[0], st));
+  if ((rc = launch_head(w, Bt, dtype, st))) return rc;
+  if (timing) HIPCK(hipEventRecord(w.ev[1], st));
+  long long* th = (long long*)h;
+  HIPCK(hipMemcpyAsync(th, w.totals.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  Sizes S;
+  if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
+  if ((rc = launch_tail(w, Bt, dtype, S, st, host_res, timing ? &w.ev[2] : nullptr))) return rc;
+  if (timing) HIPCK(hipEventRecord(w.ev[7], st));
+  HIPCK(hipStreamSynchronize(st));
+  if (timing && phase_ms) {
+    // 0 mesh count + totals, 1 emit, 2 buckets + work list, 3 MFMA pair maxima, 4 refine,
+    // 5 finalise + read-back, 6 whole call (including the row-count read-back)
+    const int a[7] = {0, 2, 3, 4, 5, 6, 0};
+    const int b[7] = {1, 3, 4, 5, 6, 7, 7};
+    for (int k = 0; k < 7; ++k) HIPCK(hipEventElapsedTime(&phase_ms[k], w.ev[a[k]], w.ev[b[k]]));
+  }
+  return SHAPE3D_OK;
+}
+
+void fill_stats(shape3d_stats* stats, const RoiResult& R, const float* ms) {
+  if (!stats) return;
+  memset(stats, 0, sizeof(*stats));
+  stats->n_vertices = R.V;
+  stats->n_triangles = R.T;
+  for (int f = 0; f < 4; ++f) {
+    stats->pair_ids[f][0] = R.ids[f][0];
+    stats->pair_ids[f][1] = R.ids[f][1];
+    stats->candidates[f] = R.cand[f];
+  }
+  stats->pairs_3d = R.V * (R.V - 1) / 2;
+  stats->pairs_2d = R.pairs2d;
+  if (ms)
+    for (int k = 0; k < 7; ++k) stats->ms[k] = ms[k];
 }
 
 int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double out[6],
@@ -301,70 +427,52 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   Workspace* wp = nullptr;
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
-  const Plan P = make_plan(vol, dims, spacing);
-  if (timing) HIPCK(hipEventRecord(w.ev[0], st));
-  RoiMeta M;
-  long long totals_h[2];
-  if ((rc = run_mesh_totals(w, P, dtype, st, &M, totals_h, timing ? w.ev[1] : nullptr))) return rc;
-  if (M.V == 0) {
-    for (int f = 0; f < 6; ++f) out[f] = 0.0;
-    if (stats) {
-      memset(stats, 0, sizeof(*stats));
-      for (int f = 0; f < 4; ++f) stats->pair_ids[f][0] = stats->pair_ids[f][1] = -1;
-    }
-    if (raw) {
-      memset(raw, 0, sizeof(*raw));
-      for (int f = 0; f < 4; ++f) raw->ids[f][0] = raw->ids[f][1] = -1;
-    }
-    g_err.clear();
-    return SHAPE3D_EMPTY;
-  }
-  Sizes S;
-  if ((rc = ensure_vertex_bufs(w, P, dtype, M, totals_h, S))) return rc;
-  const PairBufs B = pair_bufs(w, P, dtype, S);
-  if (timing) HIPCK(hipEventRecord(w.ev[7], st));
-  if ((rc = run_emit(w, P, dtype, st))) return rc;
-  if (timing) HIPCK(hipEventRecord(w.ev[2], st));
-  HIPCK(launch_buckets(B, st));
-  HIPCK(launch_init_groups(B, st));
-  HIPCK(launch_fill_u32(B.counters, 0u, 2, st));
-  if (timing) HIPCK(hipEventRecord(w.ev[3], st));
-  HIPCK(launch_pair_maxima(B, st));
-  if (timing) HIPCK(hipEventRecord(w.ev[4], st));
-  HIPCK(launch_refine(B, st));
-  if (timing) HIPCK(hipEventRecord(w.ev[5], st));
-  HIPCK(launch_finalize(B, st));
-  RoiResult* rh = (RoiResult*)((char*)w.host + 8192);
-  HIPCK(hipMemcpyAsync(rh, w.res.p, sizeof(RoiResult), hipMemcpyDeviceToHost, st));
-  if (timing) HIPCK(hipEventRecord(w.ev[6], st));
-  HIPCK(hipStreamSynchronize(st));
-  if (rh->status < 0) return fail(rh->status, "candidate rows of the exact refinement exceeded their capacity");
-  for (int f = 0; f < 6; ++f) out[f] = rh->out[f];
-  if (raw) *raw = *rh;
-  if (stats) {
-    memset(stats, 0, sizeof(*stats));
-    stats->n_vertices = rh->V;
-    stats->n_triangles = rh->T;
-    for (int f = 0; f < 4; ++f) {
-      stats->pair_ids[f][0] = rh->ids[f][0];
-      stats->pair_ids[f][1] = rh->ids[f][1];
-      stats->candidates[f] = rh->cand[f];
-    }
-    stats->pairs_3d = rh->V * (rh->V - 1) / 2;
-    stats->pairs_2d = rh->pairs2d;
-    if (timing) {
-      // phases: 0 mesh count + totals, 1 emit, 2 buckets + work list, 3 MFMA pair maxima, 4 refine,
-      // 5 finalise + read-back, 6 whole call (including the vertex-count read-back)
-      const int a[7] = {0, 7, 2, 3, 4, 5, 0};
-      const int b[7] = {1, 2, 3, 4, 5, 6, 6};
-      for (int k = 0; k < 7; ++k) {
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, w.ev[a[k]], w.ev[b[k]]));
-        stats->ms[k] = ms;
-      }
-    }
-  }
+  Batch Bt;
+  batch_add(Bt, vol, dims, spacing);
+  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  RoiResult* hres = host_results(w, Bt);
+  float ms[8] = {0};
+  if ((rc = run_eager(w, Bt, dtype, st, hres, timing, ms))) return rc;
+  if (hres->status < 0) return fail(hres->status, "an internal capacity was exceeded");
+  for (int f = 0; f < 6; ++f) out[f] = hres->out[f];
+  if (raw) *raw = *hres;
+  fill_stats(stats, *hres, timing ? ms : nullptr);
   g_err.clear();
+  return hres->status;
+}
+
+std::string layout_signature(const void* base, int dtype, const shape3d_roi* rois, int64_t n) {
+  std::string sig((const char*)&base, sizeof(base));
+  sig.append((const char*)&dtype, sizeof(dtype));
+  sig.append((const char*)rois, sizeof(shape3d_roi) * (size_t)n);
+  return sig;
+}
+
+// Records launch_head + launch_tail for the batch as a graph (buffers already sized).
+int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, GraphRec& rec) {
+  rec.n_rois = Bt.n();
+  if (hipHostMalloc((void**)&rec.host_res, sizeof(RoiResult) * Bt.n(), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    rec.host_res = nullptr;
+    return fail(SHAPE3D_ENOMEM, "pinned host allocation failed");
+  }
+  const Sizes S = sizes_for(Bt, w.rows0_cap);
+  hipGraph_t graph = nullptr;
+  HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int rc = launch_head(w, Bt, dtype, st);
+  if (!rc) rc = launch_tail(w, Bt, dtype, S, st, rec.host_res, nullptr);
+  const hipError_t ec = hipStreamEndCapture(st, &graph);
+  if (rc || ec != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : fail(SHAPE3D_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ec));
+  }
+  const hipError_t ei = hipGraphInstantiate(&rec.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    rec.exec = nullptr;
+    return fail(SHAPE3D_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+  }
+  rec.generation = w.generation;
   return SHAPE3D_OK;
 }
 
@@ -383,6 +491,86 @@ int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double s
   return shape3d_impl(vol, dtype, dims, spacing, out, stats, timing, (hipStream_t)stream);
 }
 
+int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out, int* status,
+                    int flags, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!base || !rois || !out || !status || n_rois < 1) return fail(SHAPE3D_EINVAL, "null argument or empty batch");
+  if (n_rois > SHAPE3D_MAX_ROIS) return fail(SHAPE3D_EINVAL, "too many ROIs");
+  if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "bad dtype");
+  const size_t elem = dtype == SHAPE3D_U8 ? 1 : 4;
+  const char* abase;
+  size_t asize;
+  int rc = device_range(base, &abase, &asize);
+  if (rc) return rc;
+  Batch Bt;
+  for (int64_t r = 0; r < n_rois; ++r) {
+    if ((rc = check_dims_spacing(rois[r].dims, rois[r].spacing))) return rc;
+    if (rois[r].offset < 0) return fail(SHAPE3D_EINVAL, "negative ROI offset");
+    const char* v = (const char*)base + (size_t)rois[r].offset * elem;
+    const size_t need = (size_t)rois[r].dims[0] * (size_t)rois[r].dims[1] * (size_t)rois[r].dims[2] * elem;
+    if (abase && v + need > abase + asize) return fail(SHAPE3D_EINVAL, "ROI extends past the end of the allocation");
+    batch_add(Bt, v, rois[r].dims, rois[r].spacing);
+    if (Bt.nbricks > (1ll << 31) - 1) return fail(SHAPE3D_EINVAL, "batch too large");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* wp = nullptr;
+  if ((rc = get_workspace(&wp))) return rc;
+  Workspace& w = *wp;
+  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  const bool use_graph = (flags & SHAPE3D_BATCH_GRAPH) != 0;
+  const std::string sig = use_graph ? layout_signature(base, dtype, rois, n_rois) : std::string();
+  const RoiResult* hres = nullptr;
+  bool done = false;
+  if (use_graph) {
+    auto it = w.graphs.find(sig);
+    if (it != w.graphs.end() && it->second.generation == w.generation && it->second.exec) {
+      // the ROI table of this layout is still on the device only if no other layout ran since
+      char* h = (char*)w.host;
+      memcpy(h + 4096, Bt.rois.data(), sizeof(Roi) * Bt.n());
+      hipStream_t gs = w.graph_stream;
+      HIPCK(hipEventRecord(w.ev[0], st));  // the caller's earlier work (e.g. writing the masks) first
+      HIPCK(hipStreamWaitEvent(gs, w.ev[0], 0));
+      HIPCK(hipMemcpyAsync(w.rois.p, h + 4096, sizeof(Roi) * Bt.n(), hipMemcpyHostToDevice, gs));
+      HIPCK(hipGraphLaunch(it->second.exec, gs));
+      HIPCK(hipStreamSynchronize(gs));
+      hres = it->second.host_res;
+      done = true;
+      for (int64_t r = 0; r < n_rois; ++r)
+        if (hres[r].status < 0) done = false;  // capacity exceeded on new contents: run eagerly
+    }
+  }
+  if (!done) {
+    RoiResult* eager = host_results(w, Bt);
+    if ((rc = run_eager(w, Bt, dtype, st, eager, 0, nullptr))) return rc;
+    hres = eager;
+    if (use_graph) {
+      auto old = w.graphs.find(sig);
+      if (old != w.graphs.end()) {
+        if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
+        if (old->second.host_res) (void)hipHostFree(old->second.host_res);
+        w.graphs.erase(old);
+      }
+      GraphRec rec;
+      HIPCK(hipStreamSynchronize(st));
+      rc = capture_graph(w, Bt, dtype, w.graph_stream, rec);
+      if (rc) {
+        if (rec.exec) (void)hipGraphExecDestroy(rec.exec);
+        if (rec.host_res) (void)hipHostFree(rec.host_res);
+        return rc;
+      }
+      w.graphs.emplace(sig, rec);
+    }
+  }
+  for (int64_t r = 0; r < n_rois; ++r) {
+    for (int f = 0; f < 6; ++f) out[6 * r + f] = hres[r].out[f];
+    status[r] = hres[r].status;
+  }
+  for (int64_t r = 0; r < n_rois; ++r)
+    if (hres[r].status < 0) return fail(hres[r].status, "an internal capacity was exceeded");
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
 int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], int64_t* ids,
                      double* pos, int64_t cap, int64_t* n_out, void* stream) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -393,19 +581,34 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
   Workspace* wp = nullptr;
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
-  const Plan P = make_plan(vol, dims, spacing);
-  RoiMeta M;
-  long long totals_h[2];
-  if ((rc = run_mesh_totals(w, P, dtype, st, &M, totals_h))) return rc;
-  *n_out = M.V;
-  if (M.V > cap) return fail(SHAPE3D_ECAPACITY, "vertex buffer too small");
-  if (M.V == 0) return SHAPE3D_EMPTY;
+  Batch Bt;
+  batch_add(Bt, vol, dims, spacing);
+  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  char* h = (char*)w.host;
+  memcpy(h + 4096, Bt.rois.data(), sizeof(Roi));
+  HIPCK(hipMemcpyAsync(w.rois.p, h + 4096, sizeof(Roi), hipMemcpyHostToDevice, st));
+  if ((rc = launch_head(w, Bt, dtype, st))) return rc;
+  long long* th = (long long*)h;
+  RoiMeta* mh = (RoiMeta*)(h + 1024);
+  HIPCK(hipMemcpyAsync(th, w.totals.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(mh, w.meta.p, sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  const long long V = mh->V;
+  *n_out = V;
+  if (V > cap) return fail(SHAPE3D_ECAPACITY, "vertex buffer too small");
+  if (V == 0) return SHAPE3D_EMPTY;
   Sizes S;
-  if ((rc = ensure_vertex_bufs(w, P, dtype, M, totals_h, S))) return rc;
-  if ((rc = run_emit(w, P, dtype, st))) return rc;
+  if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
+  HIPCK(launch_check_capacity(1, S.rows0, (RoiMeta*)w.meta.p, (long long*)w.totals.p,
+                              (unsigned int*)w.counters.p + 2, st));
+  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, 1, Bt.nbricks, Bt.max_G, (const BrickPart*)w.part.p,
+                         (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
+                         (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
+                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, (int*)w.orig.p,
+                         (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   HIPCK(launch_export_vertices((const unsigned long long*)w.key.p,
                                dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr, (const RoiMeta*)w.meta.p,
-                               (const Roi*)w.rois.p, (long long*)ids, pos, M.V, st));
+                               (const Roi*)w.rois.p, (long long*)ids, pos, V, st));
   HIPCK(hipStreamSynchronize(st));
   g_err.clear();
   return SHAPE3D_OK;
@@ -423,10 +626,10 @@ int shape3d_soft_forward(const float* p, const int64_t dims[3], const double spa
     saved->spacing[k] = spacing[k];
   }
   for (int f = 0; f < 6; ++f) saved->features[f] = out[f];
-  saved->signed_volume = raw.vol_signed;
+  saved->signed_volume = rc == SHAPE3D_EMPTY ? 0.0 : raw.vol_signed;
   for (int f = 0; f < 4; ++f) {
-    saved->pair_ids[f][0] = raw.ids[f][0];
-    saved->pair_ids[f][1] = raw.ids[f][1];
+    saved->pair_ids[f][0] = rc == SHAPE3D_EMPTY ? -1 : raw.ids[f][0];
+    saved->pair_ids[f][1] = rc == SHAPE3D_EMPTY ? -1 : raw.ids[f][1];
   }
   saved->status = rc;
   return rc;
@@ -476,6 +679,8 @@ int shape3d_release(void) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(w->device);
     (void)hipDeviceSynchronize();
+    drop_graphs(*w);
+    if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
     for (Buf* b : w->all())
       if (b->p) (void)hipFree(b->p);
     if (w->host) (void)hipHostFree(w->host);
@@ -488,6 +693,6 @@ int shape3d_release(void) {
   return SHAPE3D_OK;
 }
 
-int shape3d_version(void) { return 100; }
+int shape3d_version(void) { return 101; }
 
 }  // extern "C"

@@ -513,6 +513,24 @@ __global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restri
   }
 }
 
+// Refuses a call whose vertex rows exceed the rows the buffers were sized for
+// (possible when a captured graph is replayed on new mask contents): raises
+// the overflow flag and empties every ROI, so all later kernels do no work.
+__global__ void k_check_capacity(int n_rois, long long rows0_cap, RoiMeta* __restrict__ meta,
+                                 long long* __restrict__ totals, unsigned int* __restrict__ overflow) {
+  if (totals[0] <= rows0_cap) return;
+  for (int r = threadIdx.x; r < n_rois; r += blockDim.x) {
+    meta[r].V = 0;
+    meta[r].V_pad = 0;
+    meta[r].row_off = 0;
+  }
+  if (threadIdx.x == 0) {
+    *overflow = 1u;
+    totals[0] = 0;
+    totals[1] = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Emission pass: the same classification, writing each crossing edge's vertex
 // at its deterministic row (brick order, then plane, thread, axis, cube).
@@ -522,13 +540,14 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
                                                              long long nbricks, const BrickPart* __restrict__ part,
                                                              const long long* __restrict__ brick_voff,
                                                              const RoiMeta* __restrict__ meta,
+                                                             const unsigned int* __restrict__ overflow,
                                                              unsigned long long* __restrict__ key,
                                                              double* __restrict__ tsoft, float* __restrict__ pos,
                                                              int* __restrict__ orig, float* __restrict__ rowmax) {
   extern __shared__ uint32_t s_bits[];
   __shared__ int s_scan[4];
   const long long brick = xcd_remap(blockIdx.x, nbricks);
-  if (part[brick].nv == 0) return;
+  if (*overflow != 0u || part[brick].nv == 0) return;
   const int roi = find_roi(rois, n_rois, brick);
   const Roi R = rois[roi];
   const RoiMeta M = meta[roi];
@@ -642,18 +661,24 @@ hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, in
   return hipGetLastError();
 }
 
+hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
+                                 unsigned int* overflow, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(256), 0, st, n_rois, rows0_cap, meta, totals, overflow);
+  return hipGetLastError();
+}
+
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
-                            unsigned long long* key, double* tsoft, float* pos, int* orig, float* rowmax, int* blkseg,
-                            Seg* segs, hipStream_t st) {
+                            const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
+                            int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st) {
   const size_t lds = mesh_lds_bytes(max_G);
   if (nbricks > 0) {
     if (dtype == 0)
       hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, key, tsoft, pos, orig, rowmax);
+                         part, brick_voff, meta, overflow, key, tsoft, pos, orig, rowmax);
     else
       hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, key, tsoft, pos, orig, rowmax);
+                         part, brick_voff, meta, overflow, key, tsoft, pos, orig, rowmax);
   }
   hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, orig, rowmax, blkseg, segs);
   return hipGetLastError();

@@ -53,7 +53,8 @@ __device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long l
 
 __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
                               const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
-                              long long rows0, unsigned int* __restrict__ bcnt) {
+                              const long long* __restrict__ totals, unsigned int* __restrict__ bcnt) {
+  const long long rows0 = totals[T_ROWS0];
   // the trip count is uniform per wave (rows0 is a multiple of the wave size)
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
        row += (long long)gridDim.x * blockDim.x) {
@@ -102,9 +103,10 @@ __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long 
 
 __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
                                  const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
-                                 long long rows0, const unsigned int* __restrict__ bcnt,
+                                 const long long* __restrict__ totals, const unsigned int* __restrict__ bcnt,
                                  unsigned int* __restrict__ bcur, const long long* __restrict__ brow,
                                  float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax) {
+  const long long rows0 = totals[T_ROWS0];
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
        row += (long long)gridDim.x * blockDim.x) {
     const int roi = blkseg[row >> 4];
@@ -131,11 +133,13 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
 }
 
 // Segments of the buckets: pad rows, block tags and the segment table.
-__global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long long nb, long long rows0,
+__global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long long nb,
+                              const long long* __restrict__ totals,
                              const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                              const long long* __restrict__ brow, const long long* __restrict__ bseg,
                              float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax,
                              int* __restrict__ blkseg, Seg* __restrict__ segs, long long* __restrict__ pairs2d) {
+  const long long rows0 = totals[T_ROWS0];
   for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (long long)gridDim.x * blockDim.x) {
     const unsigned int c = bcnt[b];
     if (c < 2) continue;
@@ -528,7 +532,7 @@ __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const G
       Q.cand[f] = G.n_cand;
     }
     Q.status = M.V == 0 ? 1 : 0;
-    if (*ncand > (unsigned int)kMaxCand) Q.status = -4;
+    if (*ncand > (unsigned int)kMaxCand || ncand[1] != 0u) Q.status = -4;
     Q.pad_ = 0;
     res[r] = Q;
   }
@@ -566,15 +570,15 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_fill_u32(B.bcur, 0u, B.n_buckets, st))) return e;
   if ((e = launch_fill_i64(B.pairs2d, 0, B.n_rois, st))) return e;
   hipLaunchKernelGGL(k_bucket_hist, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.rows0, B.bcnt);
+                     B.totals, B.bcnt);
   hipLaunchKernelGGL(k_bucket_sizes, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.bcnt, B.n_buckets, B.bsz,
                      B.bflag);
   if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.rows0, B.bcnt, B.bcur, B.brow, B.pos, B.orig, B.rowmax);
+                     B.totals, B.bcnt, B.bcur, B.brow, B.pos, B.orig, B.rowmax);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
-                     B.rows0, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs, B.pairs2d);
+                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs, B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.ncol);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;

@@ -26,10 +26,12 @@ hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long n
                              hipStream_t st);
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
                               long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st);
+hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
+                                 unsigned int* overflow, hipStream_t st);
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
-                            unsigned long long* key, double* tsoft, float* pos, int* orig, float* rowmax, int* blkseg,
-                            Seg* segs, hipStream_t st);
+                            const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
+                            int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
 
 // scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
 // tmp must hold scan_tmp_elems(n) int64.
@@ -68,7 +70,7 @@ struct PairBufs {
   long long* itembase;  // [col_cap]
   long long* totals;    // device scalars: see pairs.hip
   long long* scan_tmp;
-  unsigned int* counters;  // [0] work items, [1] candidates
+  unsigned int* counters;  // [0] work items, [1] candidates, [2] overflow flag
   GroupRes* gres;          // [4 * n_rois]
   int* cand;               // [kMaxCand]
   long long* cand_nch;     // [kMaxCand] chunks of each candidate's segment

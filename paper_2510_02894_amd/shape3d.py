@@ -64,6 +64,13 @@ class SoftSaved(ctypes.Structure):
     ]
 
 
+class Roi(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("dims", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3)]
+
+
+BATCH_GRAPH = 1
+
+
 class Shape3DError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("shape3d failed with status %d: %s" % (status, message))
@@ -96,6 +103,10 @@ def load():
         lib.shape3d_soft_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(SoftSaved), f64p, ctypes.c_void_p,
                                               ctypes.c_void_p]
         lib.shape3d_soft_backward.restype = ctypes.c_int
+        lib.shape3d_batched.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Roi), ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                        ctypes.c_void_p]
+        lib.shape3d_batched.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -200,6 +211,44 @@ def vertices(vol, spacing=(1.0, 1.0, 1.0), with_pos: bool = True):
                                   _stream())
         _check(rc)
     return ids[:V], (pos[:V] if pos is not None else None)
+
+
+def roi_table(offsets, shapes, spacings):
+    """ctypes array of ROI descriptors (element offsets, (d0, d1, d2), spacing)."""
+    n = len(offsets)
+    tab = (Roi * n)()
+    for r in range(n):
+        tab[r].offset = int(offsets[r])
+        for k in range(3):
+            tab[r].dims[k] = int(shapes[r][k])
+            tab[r].spacing[k] = float(spacings[r][k])
+    return tab
+
+
+def batched(base, table, graph: bool = False):
+    """Features of a batch of ROIs packed in the 1-D GPU tensor ``base``
+    (uint8 or float32); ``table`` from ``roi_table``.  Returns
+    (features float64[n, 6], status int32[n])."""
+    import torch
+
+    lib = load()
+    if not isinstance(base, torch.Tensor) or not base.is_cuda or not base.is_contiguous():
+        raise TypeError("base must be a contiguous GPU tensor")
+    if base.dtype == torch.uint8:
+        dt = U8
+    elif base.dtype == torch.float32:
+        dt = F32
+    else:
+        raise TypeError("base dtype must be uint8 or float32")
+    n = len(table)
+    out = np.zeros((n, 6), dtype=np.float64)
+    status = np.zeros(n, dtype=np.int32)
+    rc = lib.shape3d_batched(ctypes.c_void_p(base.data_ptr()), dt, table, n,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), BATCH_GRAPH if graph else 0,
+                             _stream())
+    _check(rc)
+    return out, status
 
 
 def soft_forward(p, spacing=(1.0, 1.0, 1.0)):

@@ -135,3 +135,65 @@ def differentiable_roi(seed: int = 0, shape=(256, 256, 256)):
 def differentiable_small(seed: int = 0, shape=(32, 32, 32)):
     """Small instance of the differentiable workload (semi-axes U[3, 8])."""
     return soft_roi(shape, rng(4, 1000 + seed), 8, 3.0, 8.0, 1.0), (1.0, 1.0, 1.0)
+
+
+def batched_params(n: int, seed: int = 0, lmin: float = 8.0, lmax: float = 128.0):
+    """Per-ROI parameters of the batched workload: edge L log-uniform in
+    [lmin, lmax], per-axis aspect log-uniform in [0.5, 2] (dims clipped to
+    [4, 256]), spacing U[0.5, 1.5] mm per axis, 1-6 ellipsoids with centres
+    uniform in the box and semi-axes U[0.15, 0.45] times the box."""
+    out = []
+    for r in range(n):
+        g = rng(3, seed * 1000003 + r)
+        L = float(np.exp(g.uniform(np.log(lmin), np.log(lmax))))
+        aspect = np.exp(g.uniform(np.log(0.5), np.log(2.0), size=3))
+        dims = tuple(int(np.clip(round(L * a), 4, 256)) for a in aspect)
+        spacing = tuple(float(x) for x in g.uniform(0.5, 1.5, size=3))
+        k = int(g.integers(1, 7))
+        ell = []
+        for _ in range(k):
+            centre = g.uniform(0.0, 1.0, size=3) * (np.asarray(dims) - 1)
+            semi = g.uniform(0.15, 0.45, size=3) * np.asarray(dims)
+            ell.append((centre, semi, _rotation(g)))
+        out.append((dims, spacing, ell))
+    return out
+
+
+def batched_rois(n: int, seed: int = 0, lmin: float = 8.0, lmax: float = 128.0):
+    """Packed uint8 masks of the batched workload: (buffer, offsets, shapes,
+    spacings), ROI r occupying buffer[offsets[r]:offsets[r] + prod(shapes[r])]."""
+    params = batched_params(n, seed, lmin, lmax)
+    sizes = [int(np.prod(d)) for d, _, _ in params]
+    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    buf = np.zeros(int(sum(sizes)), dtype=np.uint8)
+    for (dims, _, ell), off, sz in zip(params, offsets, sizes):
+        buf[off:off + sz] = ellipsoid_union(dims, ell).reshape(-1)
+    return buf, offsets, [p[0] for p in params], [p[1] for p in params]
+
+
+def batched_rois_torch(n: int, seed: int = 0, lmin: float = 8.0, lmax: float = 128.0, device="cuda:0"):
+    """As batched_rois, evaluated with torch on ``device`` (the parameters are
+    the same draws; the packed buffer is a uint8 tensor on the device)."""
+    import torch
+
+    params = batched_params(n, seed, lmin, lmax)
+    sizes = [int(np.prod(d)) for d, _, _ in params]
+    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    buf = torch.zeros(int(sum(sizes)), dtype=torch.uint8, device=device)
+    for (dims, _, ell), off, sz in zip(params, offsets, sizes):
+        view = buf[int(off):int(off) + sz].view(dims)
+        for centre, semi, rot in ell:
+            reach = float(np.max(semi)) + 1.0
+            lo = [max(0, int(np.floor(centre[k] - reach))) for k in range(3)]
+            hi = [min(dims[k], int(np.ceil(centre[k] + reach)) + 1) for k in range(3)]
+            if any(h <= l for l, h in zip(lo, hi)):
+                continue
+            axes = [torch.arange(lo[k], hi[k], dtype=torch.float64, device=device) - float(centre[k])
+                    for k in range(3)]
+            zz, yy, xx = torch.meshgrid(*axes, indexing="ij")
+            pts = torch.stack([zz, yy, xx], dim=-1)
+            q = pts @ torch.as_tensor(rot, dtype=torch.float64, device=device)
+            rr = torch.sum((q / torch.as_tensor(semi, dtype=torch.float64, device=device)) ** 2, dim=-1)
+            sub = view[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+            sub |= (rr <= 1.0).to(torch.uint8)
+    return buf, offsets, [p[0] for p in params], [p[1] for p in params]
