@@ -94,6 +94,95 @@ def cpu_baseline(mask, spacing, target_s):
     )
 
 
+def bench_batched(args, S):
+    """ROIs/s of the batched workload (4096 uint8 ROIs, edges log-uniform 8-128
+    voxels) replayed as one hipGraph, beside a loop of single-ROI calls."""
+    import torch
+
+    from paper_2510_02894_amd import synth
+
+    t0 = time.perf_counter()
+    buf, offs, shapes, sps = synth.batched_rois_torch(args.batch_rois, 0)
+    torch.cuda.synchronize()
+    log("batched: generated %d ROIs (%.2f GB) in %.1f s" % (len(offs), buf.numel() / 1e9, time.perf_counter() - t0))
+    table = S.roi_table(offs, shapes, sps)
+    out, status = S.batched(buf, table, graph=True)   # eager run + graph recording
+    for _ in range(max(1, args.warmup)):
+        S.batched(buf, table, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out2, _ = S.batched(buf, table, graph=True)
+    torch.cuda.synchronize()
+    ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        S.batched(buf, table, graph=False)
+    torch.cuda.synchronize()
+    ms_eager = 1e3 * (time.perf_counter() - t0) / max(1, args.steps // 2)
+    # sequential single-ROI calls on the same inputs (one pass)
+    seq = np.zeros_like(out)
+    t0 = time.perf_counter()
+    for r in range(len(offs)):
+        n = int(np.prod(shapes[r]))
+        seq[r] = S.features(buf[int(offs[r]):int(offs[r]) + n].view(shapes[r]), sps[r])
+    torch.cuda.synchronize()
+    ms_seq = 1e3 * (time.perf_counter() - t0)
+    rec = {
+        "workload": "%d uint8 ROIs, edges log-uniform 8-128 voxels, aspect 0.5-2, 1-6 ellipsoids, spacing "
+                    "U[0.5,1.5] mm" % len(offs),
+        "voxels": int(buf.numel()),
+        "ms_per_batch_graph": ms_graph,
+        "ms_per_batch_eager": ms_eager,
+        "rois_per_s": len(offs) / (ms_graph * 1e-3),
+        "sequential_single_roi_ms": ms_seq,
+        "sequential_rois_per_s": len(offs) / (ms_seq * 1e-3),
+        "speedup_vs_sequential": ms_seq / ms_graph,
+        "identical_to_single_roi_calls": bool(np.array_equal(out2, seq)),
+        "empty_rois": int(np.sum(status == 1)),
+    }
+    log("batched: graph %.2f ms, eager %.2f ms, sequential %.1f ms" % (ms_graph, ms_eager, ms_seq))
+    return rec
+
+
+def bench_differentiable(args, S):
+    """Forward vs forward+backward on the 256^3 soft mask (L = area + 0.1 volume + diameter)."""
+    import torch
+
+    from paper_2510_02894_amd import synth
+
+    t0 = time.perf_counter()
+    p, sp = synth.differentiable_roi(0)
+    log("differentiable: generated %s in %.1f s" % (p.shape, time.perf_counter() - t0))
+    pt = torch.from_numpy(p).cuda()
+    gout = [0.1, 1.0, 1.0, 0.0, 0.0, 0.0]
+    for _ in range(max(1, args.warmup)):
+        f, saved = S.soft_forward(pt, sp)
+        S.soft_backward(pt, saved, gout)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.features(pt, sp)
+    torch.cuda.synchronize()
+    ms_fwd = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f, saved = S.soft_forward(pt, sp)
+        g = S.soft_backward(pt, saved, gout)
+    torch.cuda.synchronize()
+    ms_fb = 1e3 * (time.perf_counter() - t0) / args.steps
+    _, st, _ = S.features(pt, sp, stats=True)
+    rec = {
+        "workload": "float32 soft mask 256^3, 8-ellipsoid union, tau 1 voxel; L = area + 0.1 volume + diameter",
+        "vertices": st["V"],
+        "fwd_ms": ms_fwd,
+        "fwd_bwd_ms": ms_fb,
+        "ratio": ms_fb / ms_fwd,
+    }
+    log("differentiable: fwd %.2f ms, fwd+bwd %.2f ms" % (ms_fwd, ms_fb))
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +191,9 @@ def main():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-differentiable", action="store_true")
+    ap.add_argument("--batch-rois", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -164,6 +256,9 @@ def main():
     mesh = {"bound": "hbm", "achieved": mesh_bytes / t_mesh / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": mesh_bytes / t_mesh / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic("k_mesh_count")}
 
+    batched = None if args.skip_batched else bench_batched(args, S)
+    differentiable = None if args.skip_differentiable else bench_differentiable(args, S)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample (about %.0f s)" % args.cpu_seconds)
@@ -196,6 +291,8 @@ def main():
         "cpu_baseline": cpu,
         "phases_ms": avg,
         "mesh_roofline": mesh,
+        "batched": batched,
+        "differentiable": differentiable,
         "features": [float(x) for x in f],
     }
     print(json.dumps(rec), flush=True)

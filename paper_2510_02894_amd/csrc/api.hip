@@ -261,9 +261,6 @@ int ensure_layout_bufs(Workspace& w, const Batch& B) {
   if ((rc = ensure(w, w.bflag, sizeof(long long) * B.n_buckets))) return rc;
   if ((rc = ensure(w, w.brow, sizeof(long long) * B.n_buckets))) return rc;
   if ((rc = ensure(w, w.bseg, sizeof(long long) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.cand, sizeof(int) * kMaxCand))) return rc;
-  if ((rc = ensure(w, w.cand_nch, sizeof(long long) * kMaxCand))) return rc;
-  if ((rc = ensure(w, w.cand_chbase, sizeof(long long) * kMaxCand))) return rc;
   // pinned staging: [0, 4096) read-backs, then the ROI table, then the results
   const size_t host_need = 4096 + sizeof(Roi) * (size_t)n + 256 + sizeof(RoiResult) * (size_t)n;
   if ((rc = ensure_host(w, host_need))) return rc;
@@ -279,7 +276,7 @@ RoiResult* host_results(Workspace& w, const Batch& B) {
 int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0, Sizes& S) {
   int rc;
   S = sizes_for(B, std::max<long long>(rows0, w.rows0_cap));
-  const long long scan_n = std::max(std::max(B.n_buckets, (long long)kMaxCand), std::max(S.seg_cap, S.col_cap));
+  const long long scan_n = std::max(std::max(B.n_buckets, S.rows_bound), std::max(S.seg_cap, S.col_cap));
   if ((rc = ensure(w, w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
   if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
   if ((rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
@@ -293,6 +290,10 @@ int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0,
   if ((rc = ensure(w, w.nitem, sizeof(long long) * S.col_cap))) return rc;
   if ((rc = ensure(w, w.itembase, sizeof(long long) * S.col_cap))) return rc;
   if ((rc = ensure(w, w.scan_tmp, sizeof(long long) * scan_tmp_elems(scan_n)))) return rc;
+  // candidate rows of the exact refinement: every row could be one
+  if ((rc = ensure(w, w.cand, sizeof(int) * S.rows_bound))) return rc;
+  if ((rc = ensure(w, w.cand_nch, sizeof(long long) * S.rows_bound))) return rc;
+  if ((rc = ensure(w, w.cand_chbase, sizeof(long long) * S.rows_bound))) return rc;
   w.rows0_cap = S.rows0;
   return SHAPE3D_OK;
 }
@@ -329,6 +330,7 @@ PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
   B.counters = (unsigned int*)w.counters.p;
   B.gres = (GroupRes*)w.gres.p;
   B.cand = (int*)w.cand.p;
+  B.cand_cap = S.rows_bound;
   B.max_rows_seg = S.rows0;
   B.rows_bound = S.rows_bound;
   B.res = (RoiResult*)w.res.p;

@@ -379,7 +379,7 @@ __global__ void k_group_max(const float* __restrict__ rowmax, const int* __restr
 __global__ void k_candidates(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
                              const Seg* __restrict__ segs, const RoiMeta* __restrict__ meta,
                              const long long* __restrict__ totals, GroupRes* __restrict__ gres,
-                             unsigned int* __restrict__ ncand, int* __restrict__ cand) {
+                             unsigned int* __restrict__ ncand, int* __restrict__ cand, long long cand_cap) {
   const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
        row += (long long)gridDim.x * blockDim.x) {
@@ -398,7 +398,7 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
     const float tau = (float)((double)gm - 7.62939453125e-06 * (R2 > (double)gm ? R2 : (double)gm));
     if (rowmax[row] >= tau) {
       const unsigned int idx = atomicAdd(ncand, 1u);
-      if (idx < (unsigned int)kMaxCand) cand[idx] = (int)row;
+      if (idx < cand_cap) cand[idx] = (int)row;
       atomicAdd(&gres[g].n_cand, 1);
     }
   }
@@ -407,9 +407,9 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
 // Chunks of each candidate's segment (0 beyond the candidate count).
 __global__ void k_cand_chunks(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
                               const int* __restrict__ blkseg, const Seg* __restrict__ segs,
-                              long long* __restrict__ nch) {
-  const unsigned int nc = min(*ncand_p, (unsigned int)kMaxCand);
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < kMaxCand;
+                              long long* __restrict__ nch, long long cand_cap) {
+  const long long nc = min((long long)*ncand_p, cand_cap);
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cand_cap;
        c += (long long)gridDim.x * blockDim.x) {
     long long n = 0;
     if (c < nc) n = (segs[blkseg[cand[c] >> 4]].n_rows + kExactChunk - 1) / kExactChunk;
@@ -428,9 +428,9 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
                                                const int* __restrict__ blkseg, const Seg* __restrict__ segs,
                                                const int* __restrict__ orig, const unsigned long long* __restrict__ key,
                                                const double* __restrict__ tsoft, const Roi* __restrict__ rois,
-                                               GroupRes* __restrict__ gres) {
+                                               GroupRes* __restrict__ gres, long long cand_cap) {
   __shared__ unsigned long long sh[4];
-  const int nc = (int)min(*ncand_p, (unsigned int)kMaxCand);
+  const int nc = (int)min((long long)*ncand_p, cand_cap);
   const long long n_work = *n_work_p;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (long long w = blockIdx.x; w < n_work; w += gridDim.x) {
@@ -510,7 +510,7 @@ __global__ void k_init_groups(GroupRes* gres, long long n) {
 __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const GroupRes* __restrict__ gres,
                            const unsigned int* __restrict__ ncand, const unsigned long long* __restrict__ key,
                            const Roi* __restrict__ rois, const long long* __restrict__ pairs2d,
-                           RoiResult* __restrict__ res) {
+                           RoiResult* __restrict__ res, long long cand_cap) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
     const RoiMeta M = meta[r];
     RoiResult Q;
@@ -532,7 +532,7 @@ __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const G
       Q.cand[f] = G.n_cand;
     }
     Q.status = M.V == 0 ? 1 : 0;
-    if (*ncand > (unsigned int)kMaxCand || ncand[1] != 0u) Q.status = -4;
+    if ((long long)*ncand > cand_cap || ncand[1] != 0u) Q.status = -4;
     Q.pad_ = 0;
     res[r] = Q;
   }
@@ -610,14 +610,14 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound / kBlk, 1024)), dim3(256), 0, st, B.rowmax, B.blkseg,
                      B.segs, B.totals, B.gres);
   hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
-                     B.meta, B.totals, B.gres, B.counters + 1, B.cand);
-  hipLaunchKernelGGL(k_cand_chunks, dim3(grid_for(kMaxCand)), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg,
-                     B.segs, B.cand_nch);
-  if ((e = launch_scan(B.cand_nch, B.cand_chbase, kMaxCand, B.totals + T_NEXACT, B.scan_tmp, st))) return e;
+                     B.meta, B.totals, B.gres, B.counters + 1, B.cand, B.cand_cap);
+  hipLaunchKernelGGL(k_cand_chunks, dim3(grid_for(B.cand_cap)), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg,
+                     B.segs, B.cand_nch, B.cand_cap);
+  if ((e = launch_scan(B.cand_nch, B.cand_chbase, B.cand_cap, B.totals + T_NEXACT, B.scan_tmp, st))) return e;
   const unsigned grid = (unsigned)(B.cu_count * 8);
 #define S3D_EXACT(P)                                                                                             \
   hipLaunchKernelGGL(k_exact<P>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.cand_chbase,             \
-                     B.totals + T_NEXACT, B.blkseg, B.segs, B.orig, B.key, B.tsoft, B.rois, B.gres)
+                     B.totals + T_NEXACT, B.blkseg, B.segs, B.orig, B.key, B.tsoft, B.rois, B.gres, B.cand_cap)
   S3D_EXACT(0);
   S3D_EXACT(1);
   S3D_EXACT(2);
@@ -628,7 +628,7 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
 
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(B.n_rois)), dim3(256), 0, st, B.n_rois, B.meta, B.gres,
-                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res);
+                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res, B.cand_cap);
   return hipGetLastError();
 }
 

@@ -25,7 +25,6 @@ constexpr int kItileBlocks = 8;     // A blocks per wave (128 rows)
 constexpr int kJchunkBlocks = 256;  // B blocks per work item (4096 rows)
 constexpr int kScanTile = 2048;     // elements per block of the device scan
 constexpr int kExactChunk = 4096;   // rows per block of the exact refinement
-constexpr int kMaxCand = 1 << 16;   // candidate rows for the exact refinement
 
 // Key of a vertex: edge (u, u + e_a): bits 0..19 u2+1, 20..39 u1+1, 40..59 u0+1, 60..61 a.
 __host__ __device__ inline uint64_t pack_key(int u0, int u1, int u2, int a) {

@@ -72,9 +72,10 @@ struct PairBufs {
   long long* scan_tmp;
   unsigned int* counters;  // [0] work items, [1] candidates, [2] overflow flag
   GroupRes* gres;          // [4 * n_rois]
-  int* cand;               // [kMaxCand]
-  long long* cand_nch;     // [kMaxCand] chunks of each candidate's segment
-  long long* cand_chbase;  // [kMaxCand] prefix sum of cand_nch
+  long long cand_cap;      // candidate capacity: every row could be one
+  int* cand;               // [cand_cap]
+  long long* cand_nch;     // [cand_cap] chunks of each candidate's segment
+  long long* cand_chbase;  // [cand_cap] prefix sum of cand_nch
   long long max_rows_seg;  // bound on rows of one segment
   long long rows_bound;    // bound on rows of all layouts (allocation)
   RoiResult* res;          // [n_rois]
