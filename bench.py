@@ -120,14 +120,6 @@ def bench_batched(args, S):
         S.batched(buf, table, graph=False)
     torch.cuda.synchronize()
     ms_eager = 1e3 * (time.perf_counter() - t0) / max(1, args.steps // 2)
-    # sequential single-ROI calls on the same inputs (one pass)
-    seq = np.zeros_like(out)
-    t0 = time.perf_counter()
-    for r in range(len(offs)):
-        n = int(np.prod(shapes[r]))
-        seq[r] = S.features(buf[int(offs[r]):int(offs[r]) + n].view(shapes[r]), sps[r])
-    torch.cuda.synchronize()
-    ms_seq = 1e3 * (time.perf_counter() - t0)
     rec = {
         "workload": "%d uint8 ROIs, edges log-uniform 8-128 voxels, aspect 0.5-2, 1-6 ellipsoids, spacing "
                     "U[0.5,1.5] mm" % len(offs),
@@ -135,13 +127,31 @@ def bench_batched(args, S):
         "ms_per_batch_graph": ms_graph,
         "ms_per_batch_eager": ms_eager,
         "rois_per_s": len(offs) / (ms_graph * 1e-3),
-        "sequential_single_roi_ms": ms_seq,
-        "sequential_rois_per_s": len(offs) / (ms_seq * 1e-3),
-        "speedup_vs_sequential": ms_seq / ms_graph,
-        "identical_to_single_roi_calls": bool(np.array_equal(out2, seq)),
         "empty_rois": int(np.sum(status == 1)),
     }
-    log("batched: graph %.2f ms, eager %.2f ms, sequential %.1f ms" % (ms_graph, ms_eager, ms_seq))
+    if not args.skip_sequential:
+        # sequential single-ROI calls on the same inputs (one pass)
+        seq = np.zeros_like(out)
+        pairs = 0
+        t0 = time.perf_counter()
+        for r in range(len(offs)):
+            n = int(np.prod(shapes[r]))
+            seq[r], st, _ = S.features(buf[int(offs[r]):int(offs[r]) + n].view(shapes[r]), sps[r], stats=True)
+            pairs += st["V"] * (st["V"] - 1) // 2
+        torch.cuda.synchronize()
+        ms_seq = 1e3 * (time.perf_counter() - t0)
+        rec.update({
+            "pairs_3d": pairs,
+            "pairs_3d_per_s": pairs / (ms_graph * 1e-3),
+            "sequential_single_roi_ms": ms_seq,
+            "sequential_rois_per_s": len(offs) / (ms_seq * 1e-3),
+            "speedup_vs_sequential": ms_seq / ms_graph,
+            "identical_to_single_roi_calls": bool(np.array_equal(out2, seq)),
+        })
+        log("batched: graph %.2f ms, eager %.2f ms, sequential %.1f ms, %.3g 3D pairs" % (
+            ms_graph, ms_eager, ms_seq, pairs))
+    else:
+        log("batched: graph %.2f ms, eager %.2f ms" % (ms_graph, ms_eager))
     return rec
 
 
@@ -171,15 +181,77 @@ def bench_differentiable(args, S):
         g = S.soft_backward(pt, saved, gout)
     torch.cuda.synchronize()
     ms_fb = 1e3 * (time.perf_counter() - t0) / args.steps
-    _, st, _ = S.features(pt, sp, stats=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = S.soft_backward(pt, saved, gout)
+    torch.cuda.synchronize()
+    ms_b = 1e3 * (time.perf_counter() - t0) / args.steps
+    _, st, _ = S.features(pt, sp, stats=True, timing=True)
     rec = {
         "workload": "float32 soft mask 256^3, 8-ellipsoid union, tau 1 voxel; L = area + 0.1 volume + diameter",
         "vertices": st["V"],
         "fwd_ms": ms_fwd,
         "fwd_bwd_ms": ms_fb,
+        "bwd_ms": ms_b,
         "ratio": ms_fb / ms_fwd,
+        "fwd_phases_ms": st["ms"],
     }
     log("differentiable: fwd %.2f ms, fwd+bwd %.2f ms" % (ms_fwd, ms_fb))
+    return rec
+
+
+def bench_batched_soft(args, S):
+    """Batched soft masks (256 float32 ROIs, cubic edges log-uniform 48-160,
+    tau U[0.5, 2], spacing (2.0, 0.8, 0.8) mm): batched forward alone vs
+    forward + backward of all six features (grad_out = 1)."""
+    import torch
+
+    from paper_2510_02894_amd import synth
+
+    t0 = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    buf, offs, shapes, sps = synth.soft_batch(args.soft_rois, 0, workers=workers)
+    base = torch.from_numpy(buf).cuda()
+    del buf
+    torch.cuda.synchronize()
+    log("batched soft: generated %d ROIs (%.2f GB) in %.1f s" % (len(offs), base.numel() * 4 / 1e9,
+                                                                time.perf_counter() - t0))
+    table = S.roi_table(offs, shapes, sps)
+    gout = np.ones((len(offs), 6))
+    grad = torch.empty_like(base)
+    for _ in range(max(1, args.warmup)):
+        f, saved = S.batched_soft_forward(base, table, graph=True)
+        S.batched_soft_backward(base, table, saved, gout, grad=grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.batched(base, table, graph=True)
+    torch.cuda.synchronize()
+    ms_fwd = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f, saved = S.batched_soft_forward(base, table, graph=True)
+        S.batched_soft_backward(base, table, saved, gout, grad=grad)
+    torch.cuda.synchronize()
+    ms_fb = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.batched_soft_backward(base, table, saved, gout, grad=grad)
+    torch.cuda.synchronize()
+    ms_b = 1e3 * (time.perf_counter() - t0) / args.steps
+    V = int(sum(s.n_vertices for s in saved))
+    rec = {
+        "workload": "%d float32 soft ROIs, cubic edges log-uniform 48-160 voxels, 8-ellipsoid unions, tau U[0.5,2], "
+                    "spacing (2.0,0.8,0.8) mm; gradients of all six features" % len(offs),
+        "voxels": int(base.numel()),
+        "vertices": V,
+        "fwd_ms": ms_fwd,
+        "fwd_bwd_ms": ms_fb,
+        "bwd_ms": ms_b,
+        "ratio": ms_fb / ms_fwd,
+        "bwd_hbm_gbs": 3 * 4 * base.numel() / (ms_b * 1e-3) / 1e9,
+    }
+    log("batched soft: fwd %.2f ms, fwd+bwd %.2f ms, bwd %.2f ms" % (ms_fwd, ms_fb, ms_b))
     return rec
 
 
@@ -194,6 +266,12 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-differentiable", action="store_true")
     ap.add_argument("--batch-rois", type=int, default=4096)
+    ap.add_argument("--skip-batched-soft", action="store_true")
+    ap.add_argument("--soft-rois", type=int, default=256)
+    ap.add_argument("--skip-large", action="store_true",
+                    help="only the batched / differentiable sections (for profiling them)")
+    ap.add_argument("--skip-sequential", action="store_true",
+                    help="batched section without the loop of single-ROI calls")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -216,6 +294,12 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 device copies of %d bytes" % nbytes)
         del src, dst
+    if args.skip_large:
+        rec = {"batched": None if args.skip_batched else bench_batched(args, S),
+               "differentiable": None if args.skip_differentiable else bench_differentiable(args, S),
+               "batched_soft": None if args.skip_batched_soft else bench_batched_soft(args, S)}
+        print(json.dumps(rec), flush=True)
+        return
     t0 = time.perf_counter()
     mask, spacing = synth.large_roi(0)
     log("generated mask %s in %.1f s (%d voxels inside)" % (mask.shape, time.perf_counter() - t0,
@@ -258,6 +342,7 @@ def main():
 
     batched = None if args.skip_batched else bench_batched(args, S)
     differentiable = None if args.skip_differentiable else bench_differentiable(args, S)
+    batched_soft = None if args.skip_batched_soft else bench_batched_soft(args, S)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -293,6 +378,7 @@ def main():
         "mesh_roofline": mesh,
         "batched": batched,
         "differentiable": differentiable,
+        "batched_soft": batched_soft,
         "features": [float(x) for x in f],
     }
     print(json.dumps(rec), flush=True)

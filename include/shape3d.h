@@ -151,7 +151,8 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
  *
  * shape3d_soft_forward -- the features of a soft mask (as shape3d_ex with
  * SHAPE3D_F32) and, in `saved` (HOST, caller-owned), what the backward pass
- * needs: dims, spacing, features, the signed volume and the maximising pairs.
+ * needs: dims, spacing, features, the signed volume, the maximising pairs and
+ * the vertex count.
  *   p: DEVICE float32 (d0, d1, d2).  out: HOST double[6].  Synchronous.
  *
  * shape3d_soft_backward -- dL/dp for L = sum_f grad_out[f] * F_f, the exact
@@ -163,7 +164,8 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
  *   saved:    HOST, from shape3d_soft_forward on p.
  *   grad_out: HOST double[6], finite.
  *   grad_p:   DEVICE float32 (d0, d1, d2), fully written (0 away from the surface).
- * Synchronous on `stream`.
+ * Synchronous on `stream`.  If p does not have the crossing edges the forward
+ * pass counted, SHAPE3D_EINVAL is returned and grad_p is unspecified.
  */
 typedef struct {
   int64_t dims[3];
@@ -171,6 +173,7 @@ typedef struct {
   double features[6];
   double signed_volume;
   int64_t pair_ids[4][2];
+  int64_t n_vertices;     /* V of the forward pass: crossing edges of p */
   int status;
 } shape3d_soft_saved;
 
@@ -178,6 +181,33 @@ int shape3d_soft_forward(const float* p, const int64_t dims[3], const double spa
                          shape3d_soft_saved* saved, void* stream);
 int shape3d_soft_backward(const float* p, const shape3d_soft_saved* saved, const double grad_out[6],
                           float* grad_p, void* stream);
+
+/*
+ * Batched soft mode: the two passes above for a table of float32 ROIs, each
+ * pass one pipeline over all ROIs (the forward is shape3d_batched's).
+ *
+ * shape3d_batched_soft_forward
+ *   base, rois, n_rois, flags: as shape3d_batched (dtype SHAPE3D_F32).
+ *   out:   HOST double[6 * n_rois].
+ *   saved: HOST shape3d_soft_saved[n_rois]; saved[r].status is SHAPE3D_OK or
+ *          SHAPE3D_EMPTY.
+ *
+ * shape3d_batched_soft_backward -- dL/dp of every ROI for
+ * L = sum_r sum_f grad_out[6 r + f] * F_f(ROI r), in three launches over all
+ * ROIs (crossing-edge lists, per-vertex gradients, per-voxel sums).
+ *   base, rois, n_rois: as the forward call.
+ *   saved:     HOST, from shape3d_batched_soft_forward on the same inputs.
+ *   grad_out:  HOST double[6 * n_rois], finite.
+ *   grad_base: DEVICE float32; ROI r's gradient is written at
+ *              grad_base + rois[r].offset in the ROI's layout (elements
+ *              outside every ROI are not touched; ROIs must not overlap).
+ * Synchronous on `stream`.  Errors as shape3d_soft_backward.
+ */
+int shape3d_batched_soft_forward(const float* base, const shape3d_roi* rois, int64_t n_rois, double* out,
+                                 shape3d_soft_saved* saved, int flags, void* stream);
+int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, int64_t n_rois,
+                                  const shape3d_soft_saved* saved, const double* grad_out, float* grad_base,
+                                  void* stream);
 
 /* Message describing the last failure of the calling thread ("" if none). */
 const char* shape3d_last_error(void);

@@ -61,7 +61,8 @@ struct Workspace {
   int cu_count = 0;
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
-      bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase;
+      bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
+      soft_rois, soft_edges, soft_q, soft_row_base, soft_row_cnt, soft_ctr;
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
@@ -75,7 +76,7 @@ struct Workspace {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
             &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &ncol,     &colbase,
             &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
-            &cand_chbase};
+            &cand_chbase, &soft_rois, &soft_edges, &soft_q, &soft_row_base, &soft_row_cnt, &soft_ctr};
   }
 };
 
@@ -478,25 +479,11 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
   return SHAPE3D_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int shape3d(const uint8_t* mask, const int64_t dims[3], const double spacing[3], double out[6]) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return shape3d_impl(mask, SHAPE3D_U8, dims, spacing, out, nullptr, 0, nullptr);
-}
-
-int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double out[6],
-               shape3d_stats* stats, int timing, void* stream) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return shape3d_impl(vol, dtype, dims, spacing, out, stats, timing, (hipStream_t)stream);
-}
-
-int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out, int* status,
-                    int flags, void* stream) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  if (!base || !rois || !out || !status || n_rois < 1) return fail(SHAPE3D_EINVAL, "null argument or empty batch");
+// The batched forward pass; on success *hres_out points at the per-ROI results
+// (pinned host memory owned by the workspace, valid until the next call).
+int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int flags, hipStream_t st,
+                 const RoiResult** hres_out) {
+  if (!base || !rois || n_rois < 1) return fail(SHAPE3D_EINVAL, "null argument or empty batch");
   if (n_rois > SHAPE3D_MAX_ROIS) return fail(SHAPE3D_EINVAL, "too many ROIs");
   if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "bad dtype");
   const size_t elem = dtype == SHAPE3D_U8 ? 1 : 4;
@@ -514,7 +501,6 @@ int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_
     batch_add(Bt, v, rois[r].dims, rois[r].spacing);
     if (Bt.nbricks > (1ll << 31) - 1) return fail(SHAPE3D_EINVAL, "batch too large");
   }
-  hipStream_t st = (hipStream_t)stream;
   Workspace* wp = nullptr;
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
@@ -563,12 +549,134 @@ int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_
       w.graphs.emplace(sig, rec);
     }
   }
+  *hres_out = hres;
+  for (int64_t r = 0; r < n_rois; ++r)
+    if (hres[r].status < 0) return fail(hres[r].status, "an internal capacity was exceeded");
+  return SHAPE3D_OK;
+}
+
+void fill_saved(shape3d_soft_saved* saved, const int64_t dims[3], const double spacing[3], const RoiResult& raw,
+                int status) {
+  for (int k = 0; k < 3; ++k) {
+    saved->dims[k] = dims[k];
+    saved->spacing[k] = spacing[k];
+  }
+  const bool empty = status == SHAPE3D_EMPTY;
+  for (int f = 0; f < 6; ++f) saved->features[f] = empty ? 0.0 : raw.out[f];
+  saved->signed_volume = empty ? 0.0 : raw.vol_signed;
+  for (int f = 0; f < 4; ++f) {
+    saved->pair_ids[f][0] = empty ? -1 : raw.ids[f][0];
+    saved->pair_ids[f][1] = empty ? -1 : raw.ids[f][1];
+  }
+  saved->n_vertices = empty ? 0 : raw.V;
+  saved->status = status;
+}
+
+// dL/dp of every ROI of a table (arguments already checked against their allocations).
+int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_rois, const shape3d_soft_saved* saved,
+                       const double* grad_out, float* grad_base, hipStream_t st) {
+  int rc;
+  Workspace* wp = nullptr;
+  if ((rc = get_workspace(&wp))) return rc;
+  Workspace& w = *wp;
+  std::vector<SoftBwdRoi> table((size_t)n_rois);
+  long long n_rows = 0, n_vrows = 0, cap = 0;
+  for (int64_t r = 0; r < n_rois; ++r) {
+    const shape3d_soft_saved& S = saved[r];
+    for (int k = 0; k < 3; ++k)
+      if (S.dims[k] != rois[r].dims[k] || S.spacing[k] != rois[r].spacing[k])
+        return fail(SHAPE3D_EINVAL, "saved context does not match the ROI");
+    if (S.status != SHAPE3D_OK && S.status != SHAPE3D_EMPTY) return fail(SHAPE3D_EINVAL, "saved context of a failed call");
+    if (S.n_vertices < 0) return fail(SHAPE3D_EINVAL, "bad saved vertex count");
+    for (int f = 0; f < 6; ++f)
+      if (!std::isfinite(grad_out[6 * r + f])) return fail(SHAPE3D_EINVAL, "grad_out must be finite");
+    SoftBwdRoi& R = table[(size_t)r];
+    memset(&R, 0, sizeof(R));
+    R.p = base + rois[r].offset;
+    R.grad = grad_base + rois[r].offset;
+    for (int k = 0; k < 3; ++k) {
+      R.d[k] = (int)rois[r].dims[k];
+      R.s[k] = rois[r].spacing[k];
+      R.o[k] = 0.5 * (double)rois[r].dims[k] * rois[r].spacing[k];
+    }
+    const double* g = grad_out + 6 * r;
+    R.g_area = g[1];
+    R.g_vol_signed = g[0] * (S.signed_volume >= 0.0 ? 1.0 : -1.0);
+    for (int f = 0; f < 4; ++f) {
+      const double D = S.features[2 + f];
+      const bool has = S.status == SHAPE3D_OK && D > 0.0 && S.pair_ids[f][0] >= 0 && S.pair_ids[f][1] >= 0;
+      R.gdiam[f] = has ? g[2 + f] / D : 0.0;
+      R.pair_ids[f][0] = S.pair_ids[f][0];
+      R.pair_ids[f][1] = S.pair_ids[f][1];
+    }
+    R.row_begin = n_rows;
+    R.vrow_begin = n_vrows;
+    n_rows += (long long)(R.d[0] + 1) * (R.d[1] + 1);
+    n_vrows += (long long)R.d[0] * R.d[1];
+    cap += S.n_vertices;
+  }
+  if (n_rows / 32 > (1ll << 31) - 2) return fail(SHAPE3D_EINVAL, "batch too large");
+  const size_t tbytes = sizeof(SoftBwdRoi) * (size_t)n_rois;
+  if ((rc = ensure(w, w.soft_rois, tbytes))) return rc;
+  if ((rc = ensure(w, w.soft_edges, sizeof(unsigned long long) * std::max<long long>(cap, 1)))) return rc;
+  if ((rc = ensure(w, w.soft_q, sizeof(double) * std::max<long long>(cap, 1)))) return rc;
+  if ((rc = ensure(w, w.soft_row_base, sizeof(long long) * n_rows))) return rc;
+  if ((rc = ensure(w, w.soft_row_cnt, sizeof(int) * n_rows))) return rc;
+  if ((rc = ensure(w, w.soft_ctr, sizeof(long long) * 2))) return rc;
+  if ((rc = ensure_host(w, std::max<size_t>(w.host_cap, 4096 + tbytes)))) return rc;
+  char* h = (char*)w.host;
+  memcpy(h + 4096, table.data(), tbytes);
+  HIPCK(hipMemcpyAsync(w.soft_rois.p, h + 4096, tbytes, hipMemcpyHostToDevice, st));
+  SoftBwdBufs B;
+  B.rois = (const SoftBwdRoi*)w.soft_rois.p;
+  B.n_rois = (int)n_rois;
+  B.n_rows = n_rows;
+  B.n_vrows = n_vrows;
+  B.cap = cap;
+  B.edges = (unsigned long long*)w.soft_edges.p;
+  B.q = (double*)w.soft_q.p;
+  B.row_base = (long long*)w.soft_row_base.p;
+  B.row_cnt = (int*)w.soft_row_cnt.p;
+  B.counters = (long long*)w.soft_ctr.p;
+  B.cu_count = w.cu_count;
+  HIPCK(launch_soft_backward(B, st));
+  long long* used = (long long*)h;
+  HIPCK(hipMemcpyAsync(used, w.soft_ctr.p, sizeof(long long), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  if (*used != cap)
+    return fail(SHAPE3D_EINVAL, "the probabilities differ from those of the forward pass (crossing edges " +
+                                    std::to_string(*used) + ", saved " + std::to_string(cap) + "); grad is undefined");
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int shape3d(const uint8_t* mask, const int64_t dims[3], const double spacing[3], double out[6]) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return shape3d_impl(mask, SHAPE3D_U8, dims, spacing, out, nullptr, 0, nullptr);
+}
+
+int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double out[6],
+               shape3d_stats* stats, int timing, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return shape3d_impl(vol, dtype, dims, spacing, out, stats, timing, (hipStream_t)stream);
+}
+
+int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out, int* status,
+                    int flags, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!out || !status) return fail(SHAPE3D_EINVAL, "null output");
+  const RoiResult* hres = nullptr;
+  const int rc = batched_impl(base, dtype, rois, n_rois, flags, (hipStream_t)stream, &hres);
+  if (rc < 0 && !hres) return rc;
   for (int64_t r = 0; r < n_rois; ++r) {
     for (int f = 0; f < 6; ++f) out[6 * r + f] = hres[r].out[f];
     status[r] = hres[r].status;
   }
-  for (int64_t r = 0; r < n_rois; ++r)
-    if (hres[r].status < 0) return fail(hres[r].status, "an internal capacity was exceeded");
+  if (rc < 0) return rc;
   g_err.clear();
   return SHAPE3D_OK;
 }
@@ -623,17 +731,7 @@ int shape3d_soft_forward(const float* p, const int64_t dims[3], const double spa
   RoiResult raw;
   const int rc = shape3d_impl(p, SHAPE3D_F32, dims, spacing, out, nullptr, 0, (hipStream_t)stream, &raw);
   if (rc < 0) return rc;
-  for (int k = 0; k < 3; ++k) {
-    saved->dims[k] = dims[k];
-    saved->spacing[k] = spacing[k];
-  }
-  for (int f = 0; f < 6; ++f) saved->features[f] = out[f];
-  saved->signed_volume = rc == SHAPE3D_EMPTY ? 0.0 : raw.vol_signed;
-  for (int f = 0; f < 4; ++f) {
-    saved->pair_ids[f][0] = rc == SHAPE3D_EMPTY ? -1 : raw.ids[f][0];
-    saved->pair_ids[f][1] = rc == SHAPE3D_EMPTY ? -1 : raw.ids[f][1];
-  }
-  saved->status = rc;
+  fill_saved(saved, dims, spacing, raw, rc);
   return rc;
 }
 
@@ -641,34 +739,54 @@ int shape3d_soft_backward(const float* p, const shape3d_soft_saved* saved, const
                           void* stream) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!saved || !grad_out || !grad_p) return fail(SHAPE3D_EINVAL, "null argument");
-  int rc = check_args(p, SHAPE3D_F32, saved->dims, saved->spacing);
-  if (rc) return rc;
-  rc = check_args(grad_p, SHAPE3D_F32, saved->dims, saved->spacing);
-  if (rc) return rc;
-  for (int f = 0; f < 6; ++f)
-    if (!std::isfinite(grad_out[f])) return fail(SHAPE3D_EINVAL, "grad_out must be finite");
-  Workspace* wp = nullptr;
-  if ((rc = get_workspace(&wp))) return rc;
-  SoftBwdArgs A;
-  memset(&A, 0, sizeof(A));
+  shape3d_roi roi;
+  roi.offset = 0;
   for (int k = 0; k < 3; ++k) {
-    A.d[k] = (int)saved->dims[k];
-    A.s[k] = saved->spacing[k];
-    A.o[k] = 0.5 * (double)saved->dims[k] * saved->spacing[k];
+    roi.dims[k] = saved->dims[k];
+    roi.spacing[k] = saved->spacing[k];
   }
-  for (int f = 0; f < 6; ++f) A.gout[f] = grad_out[f];
-  // an empty mask has no surface: every gradient is zero
-  const bool empty = saved->status == SHAPE3D_EMPTY;
-  A.g_vol_signed = grad_out[0] * (saved->signed_volume >= 0.0 ? 1.0 : -1.0);
-  for (int f = 0; f < 4; ++f) {
-    A.D[f] = empty ? 0.0 : saved->features[2 + f];
-    A.pair_ids[f][0] = saved->pair_ids[f][0];
-    A.pair_ids[f][1] = saved->pair_ids[f][1];
+  int rc = check_args(p, SHAPE3D_F32, saved->dims, saved->spacing);
+  if (!rc) rc = check_args(grad_p, SHAPE3D_F32, saved->dims, saved->spacing);
+  if (rc) return rc;
+  return soft_backward_impl(p, &roi, 1, saved, grad_out, grad_p, (hipStream_t)stream);
+}
+
+int shape3d_batched_soft_forward(const float* base, const shape3d_roi* rois, int64_t n_rois, double* out,
+                                 shape3d_soft_saved* saved, int flags, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!out || !saved) return fail(SHAPE3D_EINVAL, "null output");
+  const RoiResult* hres = nullptr;
+  const int rc = batched_impl(base, SHAPE3D_F32, rois, n_rois, flags, (hipStream_t)stream, &hres);
+  if (rc < 0) return rc;
+  for (int64_t r = 0; r < n_rois; ++r) {
+    for (int f = 0; f < 6; ++f) out[6 * r + f] = hres[r].out[f];
+    fill_saved(&saved[r], rois[r].dims, rois[r].spacing, hres[r], hres[r].status);
   }
-  HIPCK(launch_soft_backward(p, A, grad_p, wp->cu_count, (hipStream_t)stream));
-  HIPCK(hipStreamSynchronize((hipStream_t)stream));
   g_err.clear();
   return SHAPE3D_OK;
+}
+
+int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, int64_t n_rois,
+                                  const shape3d_soft_saved* saved, const double* grad_out, float* grad_base,
+                                  void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!base || !rois || !saved || !grad_out || !grad_base || n_rois < 1)
+    return fail(SHAPE3D_EINVAL, "null argument or empty batch");
+  if (n_rois > SHAPE3D_MAX_ROIS) return fail(SHAPE3D_EINVAL, "too many ROIs");
+  const char *pb, *gb;
+  size_t ps, gs;
+  int rc = device_range(base, &pb, &ps);
+  if (!rc) rc = device_range(grad_base, &gb, &gs);
+  if (rc) return rc;
+  for (int64_t r = 0; r < n_rois; ++r) {
+    if ((rc = check_dims_spacing(rois[r].dims, rois[r].spacing))) return rc;
+    if (rois[r].offset < 0) return fail(SHAPE3D_EINVAL, "negative ROI offset");
+    const size_t need = (size_t)rois[r].dims[0] * (size_t)rois[r].dims[1] * (size_t)rois[r].dims[2] * 4;
+    const size_t off = (size_t)rois[r].offset * 4;
+    if ((pb && (const char*)base + off + need > pb + ps) || (gb && (const char*)grad_base + off + need > gb + gs))
+      return fail(SHAPE3D_EINVAL, "ROI extends past the end of the allocation");
+  }
+  return soft_backward_impl(base, rois, n_rois, saved, grad_out, grad_base, (hipStream_t)stream);
 }
 
 const char* shape3d_last_error(void) { return g_err.c_str(); }
@@ -695,6 +813,6 @@ int shape3d_release(void) {
   return SHAPE3D_OK;
 }
 
-int shape3d_version(void) { return 101; }
+int shape3d_version(void) { return 102; }
 
 }  // extern "C"

@@ -83,18 +83,39 @@ struct PairBufs {
   int cu_count;
 };
 
-// soft.hip: adjoint of the soft-mask forward pass.
-struct SoftBwdArgs {
+// soft.hip: adjoint of the soft-mask forward pass, for a table of ROIs.
+// Rows: a "padded row" is a cube row (u0, u1) with u0 in [-1, d0-1], u1 in
+// [-1, d1-1]; a "voxel row" is (w0, w1) in [0, d0) x [0, d1).  Both are
+// numbered globally, ROI after ROI.
+struct SoftBwdRoi {
+  const float* p;             // the ROI's probabilities (d0, d1, d2)
+  float* grad;                // dL/dp, same layout
   int d[3];
   int pad_;
   double s[3];
-  double o[3];                  // origin of the signed volume sum (array centre)
-  double gout[6];               // dL/dF
-  double g_vol_signed;          // gout[0] * sign(signed volume)
-  double D[4];                  // the four diameters (maxima), 0 if none
-  long long pair_ids[4][2];     // canonical ids of the maximising pairs, -1 if none
+  double o[3];                // origin of the signed volume sum (array centre)
+  double g_area;              // dL/dSurfaceArea
+  double g_vol_signed;        // dL/dMeshVolume * sign(signed volume)
+  double gdiam[4];            // dL/dD_f / D_f (0 if the feature has no pair)
+  long long pair_ids[4][2];   // canonical ids of the maximising pairs, -1 if none
+  long long row_begin;        // first global padded row
+  long long vrow_begin;       // first global voxel row
 };
-hipError_t launch_soft_backward(const float* p, const SoftBwdArgs& A, float* grad, int cu_count, hipStream_t st);
+
+struct SoftBwdBufs {
+  const SoftBwdRoi* rois;     // [n_rois], DEVICE
+  int n_rois;
+  long long n_rows;           // padded rows of all ROIs
+  long long n_vrows;          // voxel rows of all ROIs
+  long long cap;              // crossing-edge capacity (the forward pass's vertex count)
+  unsigned long long* edges;  // [cap] (global padded row << 17) | ((u2 + 1) * 3 + a), sorted within a row
+  double* q;                  // [cap] dL/dx_v along the edge axis, times the spacing of that axis
+  long long* row_base;        // [n_rows] first edge of each padded row
+  int* row_cnt;               // [n_rows] edges of each padded row
+  long long* counters;        // [0] edges reserved
+  int cu_count;
+};
+hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 
 // pairs.hip
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list

@@ -13,9 +13,17 @@
 // plus the diameter subgradient g_f (x_v - x_other) / D_f when v is an end
 // point of the maximising pair of feature f.
 //
-// One thread per voxel gathers everything it needs (gather form, no float
-// atomics: deterministic); a vertex's gradient is evaluated by both end points
-// of its edge.  Voxels on no crossing edge write 0.
+// Three passes over every ROI of a table:
+//   1. k_soft_edges: one wave per padded cube row lists the row's crossing
+//      edges in (u2, a) order; a workgroup reserves room for its rows with one
+//      atomic and records each row's first entry and count;
+//   2. k_soft_vertex_grad: one thread per crossing edge (the surface is sparse,
+//      so a thread per voxel would leave most lanes idle around the FP64 work)
+//      computes (dL/dx_v)_a * s_a;
+//   3. k_soft_gather: one wave per voxel row sums, for each voxel, the terms of
+//      its (at most six) incident crossing edges, found by binary search in the
+//      edge's row, and writes dL/dp densely (0 away from the surface).
+// No float atomics: the result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #define MC_TABLE_QUAL __constant__ const
@@ -111,64 +119,204 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
     }
 }
 
-__global__ __launch_bounds__(256) void k_soft_backward(const float* __restrict__ p, SoftBwdArgs A,
-                                                       float* __restrict__ grad) {
-  const long long N = (long long)A.d[0] * A.d[1] * A.d[2];
-  for (long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x; w < N;
-       w += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(w % A.d[2]);
-    const long long r = w / A.d[2];
-    const int y = (int)(r % A.d[1]);
-    const int z = (int)(r / A.d[1]);
-    const bool in_w = p[w] > 0.5f;
-    double g = 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int dir = -1; dir <= 1; dir += 2) {
-        const int nz = z + (a == 0 ? dir : 0), ny = y + (a == 1 ? dir : 0), nx = x + (a == 2 ? dir : 0);
-        if (pin(p, A.d, nz, ny, nx) == in_w) continue;
-        // edge from u (lower end) along axis a
-        const int u0 = dir > 0 ? z : nz, u1 = dir > 0 ? y : ny, u2 = dir > 0 ? x : nx;
-        const double pu = pval(p, A.d, u0, u1, u2);
-        const double pb = pval(p, A.d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
-        const double den = pb - pu;
-        const double dt = dir > 0 ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den);
-        double gx[3] = {0.0, 0.0, 0.0};
-        vertex_grad_mesh(p, A.d, A.s, A.o, u0, u1, u2, a, A.gout[1], A.g_vol_signed, gx);
-        const unsigned long long id = 3ull * ((((unsigned long long)(u0 + 1)) * (A.d[1] + 2) + (u1 + 1)) *
-                                                  (unsigned long long)(A.d[2] + 2) +
-                                              (u2 + 1)) +
-                                      a;
-        for (int f = 0; f < 4; ++f) {
-          if (!(A.D[f] > 0.0)) continue;
-          const long long i_id = A.pair_ids[f][0], j_id = A.pair_ids[f][1];
-          if ((long long)id != i_id && (long long)id != j_id) continue;
-          const long long other = (long long)id == i_id ? j_id : i_id;
-          // decode the partner's edge and position
-          const long long lin = other / 3;
-          const int oa = (int)(other % 3);
-          const int o2 = (int)(lin % (A.d[2] + 2)) - 1;
-          const long long l2 = lin / (A.d[2] + 2);
-          const int o1 = (int)(l2 % (A.d[1] + 2)) - 1;
-          const int o0 = (int)(l2 / (A.d[1] + 2)) - 1;
-          double xv[3], xo[3];
-          vertex_pos(p, A.d, A.s, A.o, u0, u1, u2, a, xv);
-          vertex_pos(p, A.d, A.s, A.o, o0, o1, o2, oa, xo);
-          // dD/dx_v = (x_v - x_other) / D for either end point
-          for (int q = 0; q < 3; ++q) gx[q] += A.gout[2 + f] * (xv[q] - xo[q]) / A.D[f];
-        }
-        g += gx[a] * A.s[a] * dt;
+constexpr int kRowsPerWave = 8;
+constexpr int kRowsPerBlock = 4 * kRowsPerWave;
+
+// Last ROI whose first padded row (voxel row) is <= row.
+__device__ inline int soft_roi_of_row(const SoftBwdRoi* r, int n, long long row) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r[mid].row_begin <= row)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline int soft_roi_of_vrow(const SoftBwdRoi* r, int n, long long vrow) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r[mid].vrow_begin <= vrow)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Bit a set iff the edge (u, u + e_a) crosses the 0.5 level.
+__device__ inline unsigned crossing_bits(const float* p, const int* d, int u0, int u1, int u2) {
+  const bool c = pin(p, d, u0, u1, u2);
+  return (unsigned)(pin(p, d, u0 + 1, u1, u2) != c) | ((unsigned)(pin(p, d, u0, u1 + 1, u2) != c) << 1) |
+         ((unsigned)(pin(p, d, u0, u1, u2 + 1) != c) << 2);
+}
+
+__global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
+  __shared__ int cnt[kRowsPerBlock];
+  __shared__ long long pre[kRowsPerBlock];
+  __shared__ long long base_sh;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long long row0 = (long long)blockIdx.x * kRowsPerBlock;
+  // pass 1: crossing edges per row
+  for (int k = 0; k < kRowsPerWave; ++k) {
+    const int li = wid * kRowsPerWave + k;
+    const long long row = row0 + li;
+    int c = 0;
+    if (row < B.n_rows) {
+      const SoftBwdRoi* R = B.rois + soft_roi_of_row(B.rois, B.n_rois, row);
+      const long long lr = row - R->row_begin;
+      const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
+      for (int x0 = 0; x0 <= R->d[2]; x0 += 64) {
+        const unsigned b = x0 + lane <= R->d[2] ? crossing_bits(R->p, R->d, u0, u1, x0 + lane - 1) : 0u;
+        c += __popcll(__ballot(b & 1u)) + __popcll(__ballot(b & 2u)) + __popcll(__ballot(b & 4u));
       }
-    grad[w] = (float)g;
+    }
+    if (lane == 0) cnt[li] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int i = 0; i < kRowsPerBlock; ++i) {
+      pre[i] = tot;
+      tot += cnt[i];
+    }
+    long long base = 0;
+    if (tot > 0) base = (long long)atomicAdd((unsigned long long*)B.counters, (unsigned long long)tot);
+    base_sh = base + tot <= B.cap ? base : -1;  // -1: no room (the input differs from the forward pass)
+  }
+  __syncthreads();
+  const long long base = base_sh;
+  if (threadIdx.x < kRowsPerBlock && row0 + threadIdx.x < B.n_rows) {
+    B.row_base[row0 + threadIdx.x] = base >= 0 ? base + pre[threadIdx.x] : 0;
+    B.row_cnt[row0 + threadIdx.x] = base >= 0 ? cnt[threadIdx.x] : 0;
+  }
+  if (base < 0) return;
+  // pass 2: write the rows' edges, sorted by (u2, a)
+  for (int k = 0; k < kRowsPerWave; ++k) {
+    const int li = wid * kRowsPerWave + k;
+    const long long row = row0 + li;
+    if (row >= B.n_rows || cnt[li] == 0) continue;
+    const SoftBwdRoi* R = B.rois + soft_roi_of_row(B.rois, B.n_rois, row);
+    const long long lr = row - R->row_begin;
+    const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
+    long long off = base + pre[li];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int x0 = 0; x0 <= R->d[2]; x0 += 64) {
+      const int x1 = x0 + lane;  // u2 + 1
+      const unsigned b = x1 <= R->d[2] ? crossing_bits(R->p, R->d, u0, u1, x1 - 1) : 0u;
+      const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
+      long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
+      for (int a = 0; a < 3; ++a)
+        if ((b >> a) & 1u) B.edges[slot++] = ((unsigned long long)row << 17) | (unsigned long long)(x1 * 3 + a);
+      off += __popcll(m0) + __popcll(m1) + __popcll(m2);
+    }
   }
 }
 
-hipError_t launch_soft_backward(const float* p, const SoftBwdArgs& A, float* grad, int cu_count, hipStream_t st) {
-  const long long N = (long long)A.d[0] * A.d[1] * A.d[2];
-  long long g = (N + 255) / 256;
-  const long long cap = (long long)cu_count * 32;
-  if (g > cap) g = cap;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_soft_backward, dim3((unsigned)g), dim3(256), 0, st, p, A, grad);
+__global__ __launch_bounds__(256) void k_soft_vertex_grad(SoftBwdBufs B) {
+  const long long n = min(B.counters[0], B.cap);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long e = B.edges[i];
+    const long long row = (long long)(e >> 17);
+    const int key = (int)(e & 0x1FFFFull);
+    const int a = key % 3, u2 = key / 3 - 1;
+    const SoftBwdRoi* R = B.rois + soft_roi_of_row(B.rois, B.n_rois, row);
+    const long long lr = row - R->row_begin;
+    const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
+    double gx[3] = {0.0, 0.0, 0.0};
+    vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, gx);
+    const long long id = 3ll * ((((long long)(u0 + 1)) * (R->d[1] + 2) + (u1 + 1)) * (long long)(R->d[2] + 2) +
+                                (u2 + 1)) +
+                         a;
+    for (int f = 0; f < 4; ++f) {
+      const double gd = R->gdiam[f];
+      if (gd == 0.0) continue;
+      const long long i_id = R->pair_ids[f][0], j_id = R->pair_ids[f][1];
+      if (id != i_id && id != j_id) continue;
+      const long long other = id == i_id ? j_id : i_id;
+      const long long lin = other / 3;
+      const int oa = (int)(other % 3);
+      const int o2 = (int)(lin % (R->d[2] + 2)) - 1;
+      const long long l2 = lin / (R->d[2] + 2);
+      const int o1 = (int)(l2 % (R->d[1] + 2)) - 1;
+      const int o0 = (int)(l2 / (R->d[1] + 2)) - 1;
+      double xv[3], xo[3];
+      vertex_pos(R->p, R->d, R->s, R->o, u0, u1, u2, a, xv);
+      vertex_pos(R->p, R->d, R->s, R->o, o0, o1, o2, oa, xo);
+      // dD/dx_v = (x_v - x_other) / D for either end point
+      for (int c = 0; c < 3; ++c) gx[c] += gd * (xv[c] - xo[c]);
+    }
+    B.q[i] = gx[a] * R->s[a];
+  }
+}
+
+// q of edge key (u2 + 1) * 3 + a of padded row `row` (0 if it is not listed).
+__device__ inline double edge_q(const SoftBwdBufs& B, long long row, int key) {
+  long long lo = B.row_base[row], hi = lo + B.row_cnt[row] - 1;
+  while (lo <= hi) {
+    const long long mid = (lo + hi) >> 1;
+    const int k = (int)(B.edges[mid] & 0x1FFFFull);
+    if (k == key) return B.q[mid];
+    if (k < key)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < kRowsPerWave; ++k) {
+    const long long vrow = (long long)blockIdx.x * kRowsPerBlock + wid * kRowsPerWave + k;
+    if (vrow >= B.n_vrows) break;
+    const SoftBwdRoi* R = B.rois + soft_roi_of_vrow(B.rois, B.n_rois, vrow);
+    const int* d = R->d;
+    const float* p = R->p;
+    const long long lr = vrow - R->vrow_begin;
+    const int w0 = (int)(lr / d[1]), w1 = (int)(lr % d[1]);
+    // padded row of the cube row (w0, w1); (w0, w1 - 1) is the one before it
+    // and (w0 - 1, w1) the one d1 + 1 before it
+    const long long rw = R->row_begin + (long long)(w0 + 1) * (d[1] + 1) + (w1 + 1);
+    const size_t rbase = ((size_t)w0 * d[1] + w1) * (size_t)d[2];
+    for (int x = lane; x < d[2]; x += 64) {
+      const bool in_w = p[rbase + x] > 0.5f;
+      double g = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int dir = -1; dir <= 1; dir += 2) {
+          const int nz = w0 + (a == 0 ? dir : 0), ny = w1 + (a == 1 ? dir : 0), nx = x + (a == 2 ? dir : 0);
+          if (pin(p, d, nz, ny, nx) == in_w) continue;
+          // the edge (u, u + e_a) with u = w (dir > 0) or w - e_a (dir < 0)
+          const int u0 = dir > 0 ? w0 : nz, u1 = dir > 0 ? w1 : ny, u2 = dir > 0 ? x : nx;
+          const long long row = dir > 0 || a == 2 ? rw : (a == 0 ? rw - (d[1] + 1) : rw - 1);
+          const double q = edge_q(B, row, (u2 + 1) * 3 + a);
+          const double pu = pval(p, d, u0, u1, u2);
+          const double pb = pval(p, d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
+          const double den = pb - pu;
+          g += q * (dir > 0 ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den));
+        }
+      R->grad[rbase + x] = (float)g;
+    }
+  }
+}
+
+hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_fill_i64(B.counters, 0, 1, st))) return e;
+  const long long nb = (B.n_rows + kRowsPerBlock - 1) / kRowsPerBlock;
+  if (nb > 0) hipLaunchKernelGGL(k_soft_edges, dim3((unsigned)nb), dim3(256), 0, st, B);
+  if ((e = hipGetLastError())) return e;
+  long long g = (B.cap + 255) / 256;
+  const long long gcap = (long long)B.cu_count * 16;
+  if (g > gcap) g = gcap;
+  if (g > 0) hipLaunchKernelGGL(k_soft_vertex_grad, dim3((unsigned)g), dim3(256), 0, st, B);
+  if ((e = hipGetLastError())) return e;
+  const long long nv = (B.n_vrows + kRowsPerBlock - 1) / kRowsPerBlock;
+  if (nv > 0) hipLaunchKernelGGL(k_soft_gather, dim3((unsigned)nv), dim3(256), 0, st, B);
   return hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ class SoftSaved(ctypes.Structure):
         ("features", ctypes.c_double * 6),
         ("signed_volume", ctypes.c_double),
         ("pair_ids", (ctypes.c_int64 * 2) * 4),
+        ("n_vertices", ctypes.c_int64),
         ("status", ctypes.c_int),
     ]
 
@@ -107,6 +108,13 @@ def load():
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                         ctypes.c_void_p]
         lib.shape3d_batched.restype = ctypes.c_int
+        lib.shape3d_batched_soft_forward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Roi), ctypes.c_int64, f64p,
+                                                     ctypes.POINTER(SoftSaved), ctypes.c_int, ctypes.c_void_p]
+        lib.shape3d_batched_soft_forward.restype = ctypes.c_int
+        lib.shape3d_batched_soft_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Roi), ctypes.c_int64,
+                                                      ctypes.POINTER(SoftSaved), f64p, ctypes.c_void_p,
+                                                      ctypes.c_void_p]
+        lib.shape3d_batched_soft_backward.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -277,6 +285,46 @@ def soft_backward(p, saved: SoftSaved, grad_out):
     return grad
 
 
+def _soft_base(base):
+    import torch
+
+    if not isinstance(base, torch.Tensor) or not base.is_cuda or not base.is_contiguous():
+        raise TypeError("base must be a contiguous GPU tensor")
+    if base.dtype != torch.float32:
+        raise TypeError("soft masks are float32")
+
+
+def batched_soft_forward(base, table, graph: bool = False):
+    """Features of a batch of float32 soft masks packed in ``base`` and the
+    per-ROI contexts of the backward pass: (features float64[n, 6], saved)."""
+    lib = load()
+    _soft_base(base)
+    n = len(table)
+    out = np.zeros((n, 6), dtype=np.float64)
+    saved = (SoftSaved * n)()
+    _check(lib.shape3d_batched_soft_forward(ctypes.c_void_p(base.data_ptr()), table, n,
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), saved,
+                                            BATCH_GRAPH if graph else 0, _stream()))
+    return out, saved
+
+
+def batched_soft_backward(base, table, saved, grad_out, grad=None):
+    """dL/dbase (float32 tensor like base; 0 outside the ROIs unless ``grad``
+    is given) for L = sum_r sum_f grad_out[r, f] * F_f(ROI r)."""
+    import torch
+
+    lib = load()
+    _soft_base(base)
+    n = len(table)
+    g = np.ascontiguousarray(np.asarray(grad_out, dtype=np.float64).reshape(n, 6))
+    if grad is None:
+        grad = torch.zeros_like(base)
+    _check(lib.shape3d_batched_soft_backward(ctypes.c_void_p(base.data_ptr()), table, n, saved,
+                                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             ctypes.c_void_p(grad.data_ptr()), _stream()))
+    return grad
+
+
 def _autograd_function():
     import torch
 
@@ -301,7 +349,42 @@ def _autograd_function():
     return Shape3DFunction
 
 
+def _batched_autograd_function():
+    import torch
+
+    class BatchedShape3DFunction(torch.autograd.Function):
+        """features = BatchedShape3DFunction.apply(base, table, graph): float64
+        tensor [n, 6]; differentiable with respect to the packed float32 soft
+        masks ``base``."""
+
+        @staticmethod
+        def forward(ctx, base, table, graph):
+            feats, saved = batched_soft_forward(base, table, graph)
+            ctx.save_for_backward(base)
+            ctx.table = table
+            ctx.saved = saved
+            return torch.from_numpy(feats).to(base.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (base,) = ctx.saved_tensors
+            g = grad_out.detach().to("cpu", torch.float64).numpy()
+            return batched_soft_backward(base, ctx.table, ctx.saved, g), None, None
+
+    return BatchedShape3DFunction
+
+
 _FN = None
+_BFN = None
+
+
+def batched_shape_features(base, table, graph: bool = False):
+    """Differentiable features [n, 6] of packed float32 soft masks (see
+    BatchedShape3DFunction)."""
+    global _BFN
+    if _BFN is None:
+        _BFN = _batched_autograd_function()
+    return _BFN.apply(base, table, graph)
 
 
 def shape_features(p, spacing=(1.0, 1.0, 1.0)):

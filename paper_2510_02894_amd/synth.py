@@ -127,6 +127,47 @@ def soft_roi(shape, g: np.random.Generator, n_ellipsoids: int = 8, semi_lo: floa
     return (1.0 / (1.0 + np.exp(sd / tau))).astype(np.float32)
 
 
+def soft_batch_params(n: int, seed: int = 0, lmin: float = 48.0, lmax: float = 160.0):
+    """Per-ROI parameters of the batched soft workload: cubic edge L log-uniform
+    in [lmin, lmax], tau U[0.5, 2] voxels, 8 ellipsoids with semi-axes
+    U[L/16, L/4] and centres uniform in the middle half of the box (the 256^3
+    differentiable workload scaled to L)."""
+    out = []
+    for r in range(n):
+        g = rng(5, seed * 1000003 + r)
+        L = int(round(float(np.exp(g.uniform(np.log(lmin), np.log(lmax))))))
+        tau = float(g.uniform(0.5, 2.0))
+        out.append((L, tau, int(g.integers(0, 2 ** 63 - 1))))
+    return out
+
+
+def _soft_batch_member(args):
+    L, tau, sub = args
+    g = np.random.default_rng(sub)
+    return soft_roi((L, L, L), g, 8, L / 16.0, L / 4.0, tau)
+
+
+SOFT_BATCH_SPACING = (2.0, 0.8, 0.8)
+
+
+def soft_batch(n: int, seed: int = 0, lmin: float = 48.0, lmax: float = 160.0, workers: int = 1):
+    """Packed float32 soft masks of the batched soft workload: (buffer,
+    offsets, shapes, spacings); spacing (2.0, 0.8, 0.8) mm in array order for
+    every ROI.  ``workers`` > 1 generates in a process pool."""
+    params = soft_batch_params(n, seed, lmin, lmax)
+    if workers > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(workers) as pool:
+            vols = pool.map(_soft_batch_member, params, chunksize=1)
+    else:
+        vols = [_soft_batch_member(p) for p in params]
+    sizes = [v.size for v in vols]
+    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    buf = np.concatenate([v.reshape(-1) for v in vols]).astype(np.float32)
+    return buf, offsets, [v.shape for v in vols], [SOFT_BATCH_SPACING] * n
+
+
 def differentiable_roi(seed: int = 0, shape=(256, 256, 256)):
     """Soft mask of an 8-ellipsoid union, semi-axes U[16, 64], tau = 1 voxel; spacing (1, 1, 1)."""
     return soft_roi(shape, rng(4, seed), 8, 16.0, 64.0, 1.0), (1.0, 1.0, 1.0)

@@ -19,7 +19,7 @@ def declared_functions():
 def test_header_declares_entry_points():
     names = declared_functions()
     for n in ("shape3d", "shape3d_ex", "shape3d_vertices", "shape3d_batched", "shape3d_soft_forward",
-              "shape3d_soft_backward", "shape3d_last_error", "shape3d_release", "shape3d_version"):
+              "shape3d_soft_backward", "shape3d_batched_soft_forward", "shape3d_batched_soft_backward", "shape3d_last_error", "shape3d_release", "shape3d_version"):
         assert n in names
 
 
@@ -66,3 +66,26 @@ def test_cpu_tensor_is_rejected():
         pytest.skip("library not built")
     with pytest.raises(TypeError):
         S.features(torch.zeros((4, 4, 4), dtype=torch.uint8), (1, 1, 1))
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C sizes and field offsets."""
+    from paper_2510_02894_amd import shape3d as S
+
+    structs = {"shape3d_stats": S.Stats, "shape3d_soft_saved": S.SoftSaved, "shape3d_roi": S.Roi}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "shape3d.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
