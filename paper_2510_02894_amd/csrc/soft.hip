@@ -38,17 +38,6 @@ __device__ inline double pval(const float* p, const int* d, int z, int y, int x)
   return (double)p[((size_t)z * d[1] + y) * (size_t)d[2] + x];
 }
 
-__device__ inline bool pin(const float* p, const int* d, int z, int y, int x) {
-  if (z < 0 || y < 0 || x < 0 || z >= d[0] || y >= d[1] || x >= d[2]) return false;
-  return p[((size_t)z * d[1] + y) * (size_t)d[2] + x] > 0.5f;
-}
-
-__device__ inline void cross3(const double* a, const double* b, double* r) {
-  r[0] = a[1] * b[2] - a[2] * b[1];
-  r[1] = a[2] * b[0] - a[0] * b[2];
-  r[2] = a[0] * b[1] - a[1] * b[0];
-}
-
 // Position (relative to the origin o) of the vertex on the edge from voxel u
 // along axis a.
 __device__ inline void vertex_pos(const float* p, const int* d, const double* s, const double* o, int u0, int u1,
@@ -61,62 +50,86 @@ __device__ inline void vertex_pos(const float* p, const int* d, const double* s,
   x[2] = ((double)u2 + (a == 2 ? t : 0.0)) * s[2] - o[2];
 }
 
+struct D3 {
+  double x, y, z;
+};
+
+__device__ inline D3 sub3(const D3& a, const D3& b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline D3 cross3(const D3& a, const D3& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// p at (z, y, x), 0 outside the array; the load is always issued (at a
+// clamped address) so that several of them are in flight together.
+__device__ inline double pld(const float* p, const int* d, int z, int y, int x) {
+  const bool ok = (unsigned)z < (unsigned)d[0] && (unsigned)y < (unsigned)d[1] && (unsigned)x < (unsigned)d[2];
+  const int zc = min(max(z, 0), d[0] - 1), yc = min(max(y, 0), d[1] - 1), xc = min(max(x, 0), d[2] - 1);
+  const float v = p[((size_t)zc * d[1] + yc) * (size_t)d[2] + xc];
+  return ok ? (double)v : 0.0;
+}
+
+// v[k] for a register array indexed by a run-time k in [0, 8) (selects, no scratch).
+__device__ inline double sel8(const double* v, int k) {
+  const double a = (k & 1) ? v[1] : v[0], b = (k & 1) ? v[3] : v[2];
+  const double c = (k & 1) ? v[5] : v[4], e = (k & 1) ? v[7] : v[6];
+  const double ab = (k & 2) ? b : a, ce = (k & 2) ? e : c;
+  return (k & 4) ? ce : ab;
+}
+
+// Position (relative to o) of the vertex on cube edge e of the cube with min
+// corner (c0, c1, c2) and corner values pc.
+__device__ inline D3 cube_vertex(const double* pc, int e, int c0, int c1, int c2, const double* s, const double* o) {
+  const int ea = MC_EDGE_AXIS[e], k0 = MC_EDGE_C0[e];
+  const int k1 = k0 | (4 >> ea);
+  const double p0 = sel8(pc, k0), p1 = sel8(pc, k1);
+  const double tt = (0.5 - p0) / (p1 - p0);
+  const int w0 = c0 + ((k0 >> 2) & 1), w1 = c1 + ((k0 >> 1) & 1), w2 = c2 + (k0 & 1);
+  return {((double)w0 + (ea == 0 ? tt : 0.0)) * s[0] - o[0], ((double)w1 + (ea == 1 ? tt : 0.0)) * s[1] - o[1],
+          ((double)w2 + (ea == 2 ? tt : 0.0)) * s[2] - o[2]};
+}
+
 // dL/dx of the vertex on edge (u, a) from the area and volume terms.
 __device__ inline void vertex_grad_mesh(const float* p, const int* d, const double* s, const double* o, int u0, int u1,
                                         int u2, int a, double g_area, double g_vol_signed, double* gx) {
-  const int b_ax = a == 0 ? 1 : 0, c_ax = a == 2 ? 1 : 2;
-  for (int ob = 0; ob < 2; ++ob)
-    for (int oc = 0; oc < 2; ++oc) {
-      int c[3] = {u0, u1, u2};  // cube min corner
-      c[b_ax] -= ob;
-      c[c_ax] -= oc;
-      const int le = 4 * a + 2 * ob + oc;  // the edge's number inside this cube
-      double pc[8];
-      int cas = 0;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int z = c[0] + ((k >> 2) & 1), y = c[1] + ((k >> 1) & 1), x = c[2] + (k & 1);
-        pc[k] = pval(p, d, z, y, x);
-        cas |= (int)pin(p, d, z, y, x) << k;
+  for (int q = 0; q < 4; ++q) {
+    const int ob = q >> 1, oc = q & 1;
+    // min corner of the cube: the edge's two other axes step back by ob and oc
+    const int c0 = u0 - (a != 0 ? ob : 0);
+    const int c1 = u1 - (a == 0 ? ob : (a == 1 ? 0 : oc));
+    const int c2 = u2 - (a == 2 ? 0 : oc);
+    const int le = 4 * a + 2 * ob + oc;  // the edge's number inside this cube
+    double pc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pc[k] = pld(p, d, c0 + ((k >> 2) & 1), c1 + ((k >> 1) & 1), c2 + (k & 1));
+    int cas = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cas |= (int)(pc[k] > 0.5) << k;
+    const int nt = MC_NTRI[cas];
+    for (int t = 0; t < nt; ++t) {
+      const int e0 = MC_TRI[cas][t][0], e1 = MC_TRI[cas][t][1], e2 = MC_TRI[cas][t][2];
+      if (e0 != le && e1 != le && e2 != le) continue;
+      const D3 P0 = cube_vertex(pc, e0, c0, c1, c2, s, o);
+      const D3 P1 = cube_vertex(pc, e1, c0, c1, c2, s, o);
+      const D3 P2 = cube_vertex(pc, e2, c0, c1, c2, s, o);
+      // B, C: the next two vertices after this one in the triangle's order
+      const D3 B = e0 == le ? P1 : (e1 == le ? P2 : P0);
+      const D3 C = e0 == le ? P2 : (e1 == le ? P0 : P1);
+      const D3 n = cross3(sub3(P1, P0), sub3(P2, P0));
+      const double len = sqrt(n.x * n.x + n.y * n.y + n.z * n.z);
+      if (len > 0.0) {
+        const D3 nh = {n.x / len, n.y / len, n.z / len};
+        const D3 r = cross3(nh, sub3(C, B));
+        gx[0] += g_area * 0.5 * r.x;
+        gx[1] += g_area * 0.5 * r.y;
+        gx[2] += g_area * 0.5 * r.z;
       }
-      const int nt = MC_NTRI[cas];
-      for (int t = 0; t < nt; ++t) {
-        int k = -1;
-        for (int v = 0; v < 3; ++v)
-          if (MC_TRI[cas][t][v] == le) k = v;
-        if (k < 0) continue;
-        double P[3][3];
-        for (int v = 0; v < 3; ++v) {
-          const int e = MC_TRI[cas][t][v];
-          const int ea = MC_EDGE_AXIS[e], c0 = MC_EDGE_C0[e];
-          const int c1 = c0 | (4 >> ea);
-          const double tt = (0.5 - pc[c0]) / (pc[c1] - pc[c0]);
-          const int w0 = c[0] + ((c0 >> 2) & 1), w1 = c[1] + ((c0 >> 1) & 1), w2 = c[2] + (c0 & 1);
-          P[v][0] = ((double)w0 + (ea == 0 ? tt : 0.0)) * s[0] - o[0];
-          P[v][1] = ((double)w1 + (ea == 1 ? tt : 0.0)) * s[1] - o[1];
-          P[v][2] = ((double)w2 + (ea == 2 ? tt : 0.0)) * s[2] - o[2];
-        }
-        const double* B = P[(k + 1) % 3];
-        const double* C = P[(k + 2) % 3];
-        double e1[3], e2[3], n[3];
-        for (int q = 0; q < 3; ++q) {
-          e1[q] = P[1][q] - P[0][q];
-          e2[q] = P[2][q] - P[0][q];
-        }
-        cross3(e1, e2, n);
-        const double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        if (len > 0.0) {
-          const double nh[3] = {n[0] / len, n[1] / len, n[2] / len};
-          const double cb[3] = {C[0] - B[0], C[1] - B[1], C[2] - B[2]};
-          double r[3];
-          cross3(nh, cb, r);
-          for (int q = 0; q < 3; ++q) gx[q] += g_area * 0.5 * r[q];
-        }
-        double bc[3];
-        cross3(B, C, bc);
-        for (int q = 0; q < 3; ++q) gx[q] += g_vol_signed * bc[q] / 6.0;
-      }
+      const D3 bc = cross3(B, C);
+      gx[0] += g_vol_signed * bc.x / 6.0;
+      gx[1] += g_vol_signed * bc.y / 6.0;
+      gx[2] += g_vol_signed * bc.z / 6.0;
     }
+  }
 }
 
 constexpr int kRowsPerWave = 8;
@@ -147,11 +160,68 @@ __device__ inline int soft_roi_of_vrow(const SoftBwdRoi* r, int n, long long vro
   return lo;
 }
 
-// Bit a set iff the edge (u, u + e_a) crosses the 0.5 level.
-__device__ inline unsigned crossing_bits(const float* p, const int* d, int u0, int u1, int u2) {
-  const bool c = pin(p, d, u0, u1, u2);
-  return (unsigned)(pin(p, d, u0 + 1, u1, u2) != c) | ((unsigned)(pin(p, d, u0, u1 + 1, u2) != c) << 1) |
-         ((unsigned)(pin(p, d, u0, u1, u2 + 1) != c) << 2);
+// A voxel row (z, y) of a ROI: its first element and whether it lies inside
+// the array (an outside row reads row 0 and reports 0: the zero pad).
+struct RowPtr {
+  const float* ptr;
+  bool ok;
+};
+
+__device__ inline RowPtr row_ptr(const float* p, const int* d, int z, int y) {
+  const bool ok = (unsigned)z < (unsigned)d[0] && (unsigned)y < (unsigned)d[1];
+  return {p + ((size_t)(ok ? z : 0) * d[1] + (ok ? y : 0)) * (size_t)d[2], ok};
+}
+
+// Element x of a row, 0 outside; the load is always issued at a clamped address.
+__device__ inline float row_ld(const RowPtr& r, int x, int d2) {
+  const float v = r.ptr[min(max(x, 0), d2 - 1)];
+  return r.ok && (unsigned)x < (unsigned)d2 ? v : 0.0f;
+}
+
+// Bit a set iff the edge (u, u + e_a) crosses the 0.5 level; A, Z, Y are the
+// rows (u0, u1), (u0 + 1, u1), (u0, u1 + 1).
+__device__ inline unsigned crossing_bits(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int u2, int d2) {
+  const float va = row_ld(A, u2, d2), vz = row_ld(Z, u2, d2), vy = row_ld(Y, u2, d2), vx = row_ld(A, u2 + 1, d2);
+  const bool c = va > 0.5f;
+  return (unsigned)((vz > 0.5f) != c) | ((unsigned)((vy > 0.5f) != c) << 1) | ((unsigned)((vx > 0.5f) != c) << 2);
+}
+
+// Walks consecutive padded rows (u0, u1) of the ROI table: one ROI lookup
+// and one division per wave, then increments.
+struct PaddedRowWalk {
+  const SoftBwdRoi* rois;
+  int n, r;
+  const SoftBwdRoi* R;
+  int u0, u1;
+
+  __device__ void start(const SoftBwdRoi* rs, int nr, long long row) {
+    rois = rs;
+    n = nr;
+    r = soft_roi_of_row(rs, nr, row);
+    R = rs + r;
+    const long long lr = row - R->row_begin;
+    u0 = (int)(lr / (R->d[1] + 1)) - 1;
+    u1 = (int)(lr % (R->d[1] + 1)) - 1;
+  }
+  __device__ void next() {
+    if (++u1 == R->d[1]) {
+      u1 = -1;
+      if (++u0 == R->d[0] && r + 1 < n) {
+        R = rois + ++r;
+        u0 = -1;
+      }
+    }
+  }
+};
+
+// Crossing bits of the cubes u2 = x1 - 1 and x1 + 63 of a padded row (two
+// chunks of 64 cubes per step, all eight loads issued together); 0 past the row.
+__device__ inline void row_bits2(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int x1, int d2, unsigned& b0,
+                                 unsigned& b1) {
+  b0 = crossing_bits(A, Z, Y, x1 - 1, d2);
+  b1 = crossing_bits(A, Z, Y, x1 + 63, d2);
+  b0 = x1 <= d2 ? b0 : 0u;
+  b1 = x1 + 64 <= d2 ? b1 : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
@@ -160,21 +230,29 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   __shared__ long long base_sh;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long row0 = (long long)blockIdx.x * kRowsPerBlock;
+  const long long wrow0 = row0 + wid * kRowsPerWave;
   // pass 1: crossing edges per row
-  for (int k = 0; k < kRowsPerWave; ++k) {
-    const int li = wid * kRowsPerWave + k;
-    const long long row = row0 + li;
-    int c = 0;
-    if (row < B.n_rows) {
-      const SoftBwdRoi* R = B.rois + soft_roi_of_row(B.rois, B.n_rois, row);
-      const long long lr = row - R->row_begin;
-      const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
-      for (int x0 = 0; x0 <= R->d[2]; x0 += 64) {
-        const unsigned b = x0 + lane <= R->d[2] ? crossing_bits(R->p, R->d, u0, u1, x0 + lane - 1) : 0u;
-        c += __popcll(__ballot(b & 1u)) + __popcll(__ballot(b & 2u)) + __popcll(__ballot(b & 4u));
+  {
+    PaddedRowWalk W;
+    if (wrow0 < B.n_rows) W.start(B.rois, B.n_rois, wrow0);
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const long long row = wrow0 + k;
+      int c = 0;
+      if (row < B.n_rows) {
+        const SoftBwdRoi* R = W.R;
+        const int d2 = R->d[2];
+        const RowPtr A = row_ptr(R->p, R->d, W.u0, W.u1), Z = row_ptr(R->p, R->d, W.u0 + 1, W.u1),
+                     Y = row_ptr(R->p, R->d, W.u0, W.u1 + 1);
+        for (int x0 = 0; x0 <= d2; x0 += 128) {
+          unsigned b0, b1;
+          row_bits2(A, Z, Y, x0 + lane, d2, b0, b1);
+          c += __popcll(__ballot(b0 & 1u)) + __popcll(__ballot(b0 & 2u)) + __popcll(__ballot(b0 & 4u)) +
+               __popcll(__ballot(b1 & 1u)) + __popcll(__ballot(b1 & 2u)) + __popcll(__ballot(b1 & 4u));
+        }
+        W.next();
       }
+      if (lane == 0) cnt[wid * kRowsPerWave + k] = c;
     }
-    if (lane == 0) cnt[li] = c;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -193,26 +271,37 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
     B.row_base[row0 + threadIdx.x] = base >= 0 ? base + pre[threadIdx.x] : 0;
     B.row_cnt[row0 + threadIdx.x] = base >= 0 ? cnt[threadIdx.x] : 0;
   }
-  if (base < 0) return;
+  if (base < 0 || wrow0 >= B.n_rows) return;
   // pass 2: write the rows' edges, sorted by (u2, a)
+  PaddedRowWalk W;
+  W.start(B.rois, B.n_rois, wrow0);
+  const unsigned long long below = (1ull << lane) - 1ull;
   for (int k = 0; k < kRowsPerWave; ++k) {
     const int li = wid * kRowsPerWave + k;
-    const long long row = row0 + li;
-    if (row >= B.n_rows || cnt[li] == 0) continue;
-    const SoftBwdRoi* R = B.rois + soft_roi_of_row(B.rois, B.n_rois, row);
-    const long long lr = row - R->row_begin;
-    const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
-    long long off = base + pre[li];
-    const unsigned long long below = (1ull << lane) - 1ull;
-    for (int x0 = 0; x0 <= R->d[2]; x0 += 64) {
-      const int x1 = x0 + lane;  // u2 + 1
-      const unsigned b = x1 <= R->d[2] ? crossing_bits(R->p, R->d, u0, u1, x1 - 1) : 0u;
-      const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
-      long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
-      for (int a = 0; a < 3; ++a)
-        if ((b >> a) & 1u) B.edges[slot++] = ((unsigned long long)row << 17) | (unsigned long long)(x1 * 3 + a);
-      off += __popcll(m0) + __popcll(m1) + __popcll(m2);
+    const long long row = wrow0 + k;
+    if (row >= B.n_rows) break;
+    if (cnt[li] != 0) {
+      const SoftBwdRoi* R = W.R;
+      const int d2 = R->d[2];
+      const RowPtr A = row_ptr(R->p, R->d, W.u0, W.u1), Z = row_ptr(R->p, R->d, W.u0 + 1, W.u1),
+                   Y = row_ptr(R->p, R->d, W.u0, W.u1 + 1);
+      long long off = base + pre[li];
+      for (int x0 = 0; x0 <= d2; x0 += 128) {
+        unsigned bb[2];
+        row_bits2(A, Z, Y, x0 + lane, d2, bb[0], bb[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const unsigned b = bb[h];
+          const int x1 = x0 + 64 * h + lane;  // u2 + 1
+          const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
+          long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
+          for (int a = 0; a < 3; ++a)
+            if ((b >> a) & 1u) B.edges[slot++] = ((unsigned long long)row << 17) | (unsigned long long)(x1 * 3 + a);
+          off += __popcll(m0) + __popcll(m1) + __popcll(m2);
+        }
+      }
     }
+    W.next();
   }
 }
 
@@ -269,37 +358,73 @@ __device__ inline double edge_q(const SoftBwdBufs& B, long long row, int key) {
   return 0.0;
 }
 
+// dL/dp of voxel (w0, w1, x) of ROI R from its row and the four neighbouring
+// rows; rw is the padded row of the cube row (w0, w1).
+__device__ inline double voxel_grad(const SoftBwdBufs& B, const SoftBwdRoi* R, long long rw, int x, float vc,
+                                    const float* nv) {
+  const bool in_w = vc > 0.5f;
+  double g = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int a = j >> 1;
+    const bool up = j & 1;  // the neighbour is w + e_a (w is the edge's lower end)
+    if ((nv[j] > 0.5f) == in_w) continue;
+    // the edge (u, u + e_a) with u = w (up) or w - e_a; (w0, w1 - 1) is the
+    // padded row before rw and (w0 - 1, w1) the one d1 + 1 before it
+    const int u2 = a == 2 && !up ? x - 1 : x;
+    const long long row = up || a == 2 ? rw : (a == 0 ? rw - (R->d[1] + 1) : rw - 1);
+    const double q = edge_q(B, row, (u2 + 1) * 3 + a);
+    const double pu = up ? (double)vc : (double)nv[j], pb = up ? (double)nv[j] : (double)vc;
+    const double den = pb - pu;
+    g += q * (up ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den));
+  }
+  return g;
+}
+
 __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const long long wrow0 = (long long)blockIdx.x * kRowsPerBlock + wid * kRowsPerWave;
+  if (wrow0 >= B.n_vrows) return;
+  int r = soft_roi_of_vrow(B.rois, B.n_rois, wrow0);
+  const SoftBwdRoi* R = B.rois + r;
+  long long lr = wrow0 - R->vrow_begin;
+  int w0 = (int)(lr / R->d[1]), w1 = (int)(lr % R->d[1]);
   for (int k = 0; k < kRowsPerWave; ++k) {
-    const long long vrow = (long long)blockIdx.x * kRowsPerBlock + wid * kRowsPerWave + k;
-    if (vrow >= B.n_vrows) break;
-    const SoftBwdRoi* R = B.rois + soft_roi_of_vrow(B.rois, B.n_rois, vrow);
+    if (wrow0 + k >= B.n_vrows) break;
     const int* d = R->d;
     const float* p = R->p;
-    const long long lr = vrow - R->vrow_begin;
-    const int w0 = (int)(lr / d[1]), w1 = (int)(lr % d[1]);
-    // padded row of the cube row (w0, w1); (w0, w1 - 1) is the one before it
-    // and (w0 - 1, w1) the one d1 + 1 before it
+    const int d2 = d[2];
     const long long rw = R->row_begin + (long long)(w0 + 1) * (d[1] + 1) + (w1 + 1);
-    const size_t rbase = ((size_t)w0 * d[1] + w1) * (size_t)d[2];
-    for (int x = lane; x < d[2]; x += 64) {
-      const bool in_w = p[rbase + x] > 0.5f;
-      double g = 0.0;
-      for (int a = 0; a < 3; ++a)
-        for (int dir = -1; dir <= 1; dir += 2) {
-          const int nz = w0 + (a == 0 ? dir : 0), ny = w1 + (a == 1 ? dir : 0), nx = x + (a == 2 ? dir : 0);
-          if (pin(p, d, nz, ny, nx) == in_w) continue;
-          // the edge (u, u + e_a) with u = w (dir > 0) or w - e_a (dir < 0)
-          const int u0 = dir > 0 ? w0 : nz, u1 = dir > 0 ? w1 : ny, u2 = dir > 0 ? x : nx;
-          const long long row = dir > 0 || a == 2 ? rw : (a == 0 ? rw - (d[1] + 1) : rw - 1);
-          const double q = edge_q(B, row, (u2 + 1) * 3 + a);
-          const double pu = pval(p, d, u0, u1, u2);
-          const double pb = pval(p, d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
-          const double den = pb - pu;
-          g += q * (dir > 0 ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den));
-        }
-      R->grad[rbase + x] = (float)g;
+    const RowPtr C = row_ptr(p, d, w0, w1), Zm = row_ptr(p, d, w0 - 1, w1), Zp = row_ptr(p, d, w0 + 1, w1),
+                 Ym = row_ptr(p, d, w0, w1 - 1), Yp = row_ptr(p, d, w0, w1 + 1);
+    float* grow = R->grad + ((size_t)w0 * d[1] + w1) * (size_t)d2;
+    for (int x0 = 0; x0 < d2; x0 += 128) {
+      // two voxels per lane, all fourteen loads issued together
+      float vc[2], nv[2][6];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = x0 + 64 * h + lane;
+        vc[h] = row_ld(C, x, d2);
+        nv[h][0] = row_ld(Zm, x, d2);
+        nv[h][1] = row_ld(Zp, x, d2);
+        nv[h][2] = row_ld(Ym, x, d2);
+        nv[h][3] = row_ld(Yp, x, d2);
+        nv[h][4] = row_ld(C, x - 1, d2);
+        nv[h][5] = row_ld(C, x + 1, d2);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = x0 + 64 * h + lane;
+        if (x < d2) grow[x] = (float)voxel_grad(B, R, rw, x, vc[h], nv[h]);
+      }
+    }
+    // next voxel row
+    if (++w1 == d[1]) {
+      w1 = 0;
+      if (++w0 == d[0] && r + 1 < B.n_rois) {
+        R = B.rois + ++r;
+        w0 = 0;
+      }
     }
   }
 }
