@@ -94,6 +94,37 @@ def cpu_baseline(mask, spacing, target_s):
     )
 
 
+def bench_single_roi(args, S):
+    """Latency of the plain entry point on the single-ROI workload (64^3 uint8,
+    one ellipsoid with semi-axes 8-24 voxels): host-to-host, synchronous."""
+    import torch
+
+    from paper_2510_02894_amd import synth
+
+    mask, sp = synth.single_roi(0)
+    vol = torch.from_numpy(mask).cuda()
+    for _ in range(5):
+        S.shape3d_u8(vol, sp)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(max(20, 5 * args.steps)):
+        t0 = time.perf_counter()
+        S.shape3d_u8(vol, sp)
+        lat.append(1e6 * (time.perf_counter() - t0))
+    _, st, _ = S.features(vol, sp, stats=True, timing=True)
+    rec = {
+        "workload": "single ROI: uint8 64^3, one ellipsoid (semi-axes 8-24 voxels), spacing (1,1,1) mm",
+        "vertices": st["V"],
+        "calls": len(lat),
+        "latency_us_median": float(np.median(lat)),
+        "latency_us_p10": float(np.percentile(lat, 10)),
+        "latency_us_p90": float(np.percentile(lat, 90)),
+        "device_phases_ms": st["ms"],
+    }
+    log("single ROI: median %.1f us host-to-host" % rec["latency_us_median"])
+    return rec
+
+
 def bench_batched(args, S):
     """ROIs/s of the batched workload (4096 uint8 ROIs, edges log-uniform 8-128
     voxels) replayed as one hipGraph, beside a loop of single-ROI calls."""
@@ -106,15 +137,27 @@ def bench_batched(args, S):
     torch.cuda.synchronize()
     log("batched: generated %d ROIs (%.2f GB) in %.1f s" % (len(offs), buf.numel() / 1e9, time.perf_counter() - t0))
     table = S.roi_table(offs, shapes, sps)
-    out, status = S.batched(buf, table, graph=True)   # eager run + graph recording
-    for _ in range(max(1, args.warmup)):
-        S.batched(buf, table, graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out2, _ = S.batched(buf, table, graph=True)
-    torch.cuda.synchronize()
-    ms_graph = 1e3 * (time.perf_counter() - t0) / args.steps
+
+    def timed_graph():
+        out, status = S.batched(buf, table, graph=True)   # eager run + graph recording
+        for _ in range(max(1, args.warmup)):
+            S.batched(buf, table, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out2, _ = S.batched(buf, table, graph=True)
+        torch.cuda.synchronize()
+        return out, status, out2, 1e3 * (time.perf_counter() - t0) / args.steps
+
+    default_tiles = S.get_tuning()
+    out, status, out2, ms_default = timed_graph()
+    tiles = default_tiles
+    if not args.no_autotune:
+        tiles, _ = S.autotune(buf, table, reps=2)
+        out, status, out2, ms_graph = timed_graph()
+        log("batched: autotuned tiles %s (default %s: %.2f ms)" % (tiles, default_tiles, ms_default))
+    else:
+        ms_graph = ms_default
     t0 = time.perf_counter()
     for _ in range(max(1, args.steps // 2)):
         S.batched(buf, table, graph=False)
@@ -127,6 +170,8 @@ def bench_batched(args, S):
         "ms_per_batch_graph": ms_graph,
         "ms_per_batch_eager": ms_eager,
         "rois_per_s": len(offs) / (ms_graph * 1e-3),
+        "tiles": list(tiles),
+        "ms_per_batch_default_tiles": ms_default,
         "empty_rois": int(np.sum(status == 1)),
     }
     if not args.skip_sequential:
@@ -166,6 +211,8 @@ def bench_differentiable(args, S):
     log("differentiable: generated %s in %.1f s" % (p.shape, time.perf_counter() - t0))
     pt = torch.from_numpy(p).cuda()
     gout = [0.1, 1.0, 1.0, 0.0, 0.0, 0.0]
+    if not args.no_autotune:
+        S.autotune(pt.view(-1), S.roi_table([0], [p.shape], [sp]), reps=2)
     for _ in range(max(1, args.warmup)):
         f, saved = S.soft_forward(pt, sp)
         S.soft_backward(pt, saved, gout)
@@ -194,6 +241,7 @@ def bench_differentiable(args, S):
         "fwd_bwd_ms": ms_fb,
         "bwd_ms": ms_b,
         "ratio": ms_fb / ms_fwd,
+        "tiles": list(S.get_tuning()),
         "fwd_phases_ms": st["ms"],
     }
     log("differentiable: fwd %.2f ms, fwd+bwd %.2f ms" % (ms_fwd, ms_fb))
@@ -217,6 +265,8 @@ def bench_batched_soft(args, S):
     log("batched soft: generated %d ROIs (%.2f GB) in %.1f s" % (len(offs), base.numel() * 4 / 1e9,
                                                                 time.perf_counter() - t0))
     table = S.roi_table(offs, shapes, sps)
+    if not args.no_autotune:
+        S.autotune(base, table, reps=2)
     gout = np.ones((len(offs), 6))
     grad = torch.empty_like(base)
     for _ in range(max(1, args.warmup)):
@@ -250,6 +300,7 @@ def bench_batched_soft(args, S):
         "bwd_ms": ms_b,
         "ratio": ms_fb / ms_fwd,
         "bwd_hbm_gbs": 3 * 4 * base.numel() / (ms_b * 1e-3) / 1e9,
+        "tiles": list(S.get_tuning()),
     }
     log("batched soft: fwd %.2f ms, fwd+bwd %.2f ms, bwd %.2f ms" % (ms_fwd, ms_fb, ms_b))
     return rec
@@ -267,6 +318,7 @@ def main():
     ap.add_argument("--skip-differentiable", action="store_true")
     ap.add_argument("--batch-rois", type=int, default=4096)
     ap.add_argument("--skip-batched-soft", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default pair-pass tiles")
     ap.add_argument("--soft-rois", type=int, default=256)
     ap.add_argument("--skip-large", action="store_true",
                     help="only the batched / differentiable sections (for profiling them)")
@@ -308,6 +360,11 @@ def main():
     vols = [torch.from_numpy(mask).to(dev) for _ in range(max(1, args.copies))]
     torch.cuda.synchronize()
 
+    tiles = S.get_tuning()
+    if not args.no_autotune:
+        tiles, _ = S.autotune(vols[0].view(-1), S.roi_table([0], [mask.shape], [spacing]), reps=2)
+        log("large ROI: autotuned pair-pass tiles %s" % (tiles,))
+
     def step(i):
         return S.features(vols[i % len(vols)], spacing, stats=True, timing=True)
 
@@ -340,6 +397,7 @@ def main():
     mesh = {"bound": "hbm", "achieved": mesh_bytes / t_mesh / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": mesh_bytes / t_mesh / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic("k_mesh_count")}
 
+    single = bench_single_roi(args, S)
     batched = None if args.skip_batched else bench_batched(args, S)
     differentiable = None if args.skip_differentiable else bench_differentiable(args, S)
     batched_soft = None if args.skip_batched_soft else bench_batched_soft(args, S)
@@ -374,8 +432,13 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tiles": list(tiles),
         "phases_ms": avg,
+        "step_ms_median": float(np.median([p["total"] for p in phases])),
+        "step_ms_p10": float(np.percentile([p["total"] for p in phases], 10)),
+        "step_ms_p90": float(np.percentile([p["total"] for p in phases], 90)),
         "mesh_roofline": mesh,
+        "single_roi": single,
         "batched": batched,
         "differentiable": differentiable,
         "batched_soft": batched_soft,

@@ -56,6 +56,7 @@ extern "C" {
 #define SHAPE3D_EHIP (-3)    /* a HIP runtime call failed */
 #define SHAPE3D_ECAPACITY (-4) /* an internal bound was exceeded */
 #define SHAPE3D_ENOMEM (-5)  /* device allocation failed */
+#define SHAPE3D_EINTERNAL (-6) /* an internal consistency check failed */
 
 #define SHAPE3D_U8 0
 #define SHAPE3D_F32 1
@@ -208,6 +209,55 @@ int shape3d_batched_soft_forward(const float* base, const shape3d_roi* rois, int
 int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, int64_t n_rois,
                                   const shape3d_soft_saved* saved, const double* grad_out, float* grad_base,
                                   void* stream);
+
+/*
+ * Tile sizes of the all-pairs pass and their autotuner.  The paper sizes its
+ * diameter kernel by hand for one GPU (Sec. 3, micro-benchmarks of the kernel
+ * variants); here the tiles are chosen per workload class by timing.  Tiles
+ * change only the order of the work: every result is identical for every
+ * valid setting.
+ *   itile_blocks:  16-row blocks each wave keeps in registers: 2, 4 or 8
+ *                  (kernel 1: 4 or 8).
+ *   jchunk_blocks: 16-row column blocks per work item: 64, 128, 256 or 512.
+ *   blocks_per_cu: persistent workgroups per compute unit, 0 = as many as fit
+ *                  (at most 64).
+ *   kernel:        0 = FP32 Gram values on the 16x16x4 FP32 matrix cores;
+ *                  1 = FP32-accurate Gram values from coordinates split into
+ *                  two f16 parts on the 32x32x16 f16 matrix cores.  Both are
+ *                  followed by the same exact FP64 refinement.
+ * The setting is process-wide (all devices); the default is {8, 256, 0, 0}.
+ *
+ * shape3d_get_tuning / shape3d_set_tuning -- read or replace the setting
+ * (HOST struct).  Setting drops the graphs recorded by shape3d_batched.
+ * Neither needs a device.  SHAPE3D_EINVAL for unsupported values.
+ *
+ * shape3d_autotune -- runs the batch (as shape3d_batched, eagerly) once per
+ * candidate setting (kernel 0 with itile 2, 4, 8 and kernel 1 with itile 4, 8,
+ * each with the four jchunk values; `reps` timed runs each, 1..100), keeps
+ * the tiling with the shortest pair-pass time (HIP events) and makes it the
+ * current setting.  Returns SHAPE3D_EINTERNAL if a candidate changes any
+ * result.
+ *   cache_path: HOST path of a text file or NULL.  Lines are
+ *               "<class> <kernel> <itile> <jchunk> <blocks_per_cu> <ms>", the class
+ *               being the dtype and the rounded log2 of the ROI count, of
+ *               the total and of the largest vertex count.  A line for the
+ *               batch's class is used without timing; otherwise the choice is
+ *               appended.
+ *   best:       HOST; receives the chosen tiles.  best_ms: HOST; its pair-pass
+ *               time (from the cache on a hit).
+ * Synchronous on `stream`.
+ */
+typedef struct {
+  int32_t itile_blocks;
+  int32_t jchunk_blocks;
+  int32_t blocks_per_cu;
+  int32_t kernel;
+} shape3d_tuning;
+
+int shape3d_get_tuning(shape3d_tuning* t);
+int shape3d_set_tuning(const shape3d_tuning* t);
+int shape3d_autotune(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int reps,
+                     const char* cache_path, shape3d_tuning* best, double* best_ms, void* stream);
 
 /* Message describing the last failure of the calling thread ("" if none). */
 const char* shape3d_last_error(void);

@@ -62,7 +62,7 @@ struct Workspace {
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
       bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
-      soft_rois, soft_edges, soft_q, soft_row_base, soft_row_cnt, soft_ctr;
+      posh, soft_rois, soft_edges, soft_q, soft_row_base, soft_row_cnt, soft_ctr;
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
@@ -76,11 +76,20 @@ struct Workspace {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
             &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &ncol,     &colbase,
             &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
-            &cand_chbase, &soft_rois, &soft_edges, &soft_q, &soft_row_base, &soft_row_cnt, &soft_ctr};
+            &cand_chbase, &posh, &soft_rois, &soft_edges, &soft_q, &soft_row_base, &soft_row_cnt, &soft_ctr};
   }
 };
 
 std::map<int, Workspace*> g_ws;
+
+// Tile sizes of the pair pass for every device (results do not depend on them).
+Tuning g_tune = {8, 256, 0, 0};
+
+bool valid_tuning(const Tuning& t) {
+  return (t.itile == 2 || t.itile == 4 || t.itile == 8) &&
+         (t.jchunk == 64 || t.jchunk == 128 || t.jchunk == 256 || t.jchunk == 512) && t.blocks_per_cu >= 0 &&
+         t.blocks_per_cu <= 64 && (t.kernel == 0 || (t.kernel == 1 && t.itile >= 4));
+}
 
 void drop_graphs(Workspace& w) {
   for (auto& kv : w.graphs) {
@@ -239,7 +248,7 @@ Sizes sizes_for(const Batch& B, long long rows0) {
   const long long rows2d_bound = 3 * S.rows0 + (long long)(kSegAlign - 1) * B.n_buckets;
   S.rows_bound = (S.rows0 + rows2d_bound + kBlk - 1) / kBlk * kBlk;
   S.seg_cap = B.n() + B.n_buckets;
-  S.col_cap = S.seg_cap + S.rows_bound / (kJchunkBlocks * kBlk) + 1;
+  S.col_cap = S.seg_cap + S.rows_bound / (kMinJchunk * kBlk) + 1;
   return S;
 }
 
@@ -281,6 +290,8 @@ int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0,
   if ((rc = ensure(w, w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
   if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
   if ((rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
+  // split-f16 operands: 2 KB per 32-row block
+  if (g_tune.kernel == 1 && (rc = ensure(w, w.posh, (size_t)2048 * ((S.rows_bound + 31) / 32)))) return rc;
   if ((rc = ensure(w, w.orig, sizeof(int) * S.rows_bound))) return rc;
   if ((rc = ensure(w, w.rowmax, sizeof(float) * S.rows_bound))) return rc;
   if ((rc = ensure(w, w.blkseg, sizeof(int) * (S.rows_bound / kBlk + 1)))) return rc;
@@ -307,6 +318,7 @@ PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
   B.key = (const unsigned long long*)w.key.p;
   B.tsoft = dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr;
   B.pos = (float*)w.pos.p;
+  B.posh = (uint4*)w.posh.p;
   B.orig = (int*)w.orig.p;
   B.rowmax = (float*)w.rowmax.p;
   B.blkseg = (int*)w.blkseg.p;
@@ -332,6 +344,7 @@ PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
   B.gres = (GroupRes*)w.gres.p;
   B.cand = (int*)w.cand.p;
   B.cand_cap = S.rows_bound;
+  B.tune = g_tune;
   B.max_rows_seg = S.rows0;
   B.rows_bound = S.rows_bound;
   B.res = (RoiResult*)w.res.p;
@@ -481,8 +494,8 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
 
 // The batched forward pass; on success *hres_out points at the per-ROI results
 // (pinned host memory owned by the workspace, valid until the next call).
-int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int flags, hipStream_t st,
-                 const RoiResult** hres_out) {
+// Validates a ROI table against the allocation holding base and builds the batch.
+int make_batch(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, Batch& Bt) {
   if (!base || !rois || n_rois < 1) return fail(SHAPE3D_EINVAL, "null argument or empty batch");
   if (n_rois > SHAPE3D_MAX_ROIS) return fail(SHAPE3D_EINVAL, "too many ROIs");
   if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "bad dtype");
@@ -491,7 +504,6 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
   size_t asize;
   int rc = device_range(base, &abase, &asize);
   if (rc) return rc;
-  Batch Bt;
   for (int64_t r = 0; r < n_rois; ++r) {
     if ((rc = check_dims_spacing(rois[r].dims, rois[r].spacing))) return rc;
     if (rois[r].offset < 0) return fail(SHAPE3D_EINVAL, "negative ROI offset");
@@ -501,6 +513,14 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
     batch_add(Bt, v, rois[r].dims, rois[r].spacing);
     if (Bt.nbricks > (1ll << 31) - 1) return fail(SHAPE3D_EINVAL, "batch too large");
   }
+  return SHAPE3D_OK;
+}
+
+int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int flags, hipStream_t st,
+                 const RoiResult** hres_out) {
+  Batch Bt;
+  int rc = make_batch(base, dtype, rois, n_rois, Bt);
+  if (rc) return rc;
   Workspace* wp = nullptr;
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
@@ -647,6 +667,104 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
     return fail(SHAPE3D_EINVAL, "the probabilities differ from those of the forward pass (crossing edges " +
                                     std::to_string(*used) + ", saved " + std::to_string(cap) + "); grad is undefined");
   g_err.clear();
+  return SHAPE3D_OK;
+}
+
+// Workload class of a batch for the tuning cache: dtype, and the binary
+// orders of magnitude of the ROI count, of the total and of the largest
+// vertex count (the pair work is about sum V^2 / 2).
+std::string tuning_key(int dtype, int64_t n_rois, const RoiResult* res) {
+  long long vsum = 0, vmax = 0;
+  for (int64_t r = 0; r < n_rois; ++r) {
+    vsum += res[r].V;
+    vmax = std::max(vmax, res[r].V);
+  }
+  auto lg = [](long long x) { return x > 0 ? (int)std::lround(std::log2((double)x)) : -1; };
+  char buf[96];
+  snprintf(buf, sizeof(buf), "%s:n%d:v%d:m%d", dtype == SHAPE3D_U8 ? "u8" : "f32", lg(n_rois), lg(vsum), lg(vmax));
+  return buf;
+}
+
+// Looks `key` up in a tuning cache file (lines "key kernel itile jchunk blocks_per_cu ms").
+bool tuning_cache_find(const char* path, const std::string& key, Tuning& t, double& ms) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[256], k[128];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    Tuning c;
+    double m;
+    if (sscanf(line, "%127s %d %d %d %d %lf", k, &c.kernel, &c.itile, &c.jchunk, &c.blocks_per_cu, &m) == 6 &&
+        key == k && valid_tuning(c)) {
+      t = c;  // the last entry for a key wins
+      ms = m;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+int autotune_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int reps,
+                  const char* cache_path, Tuning& best, double& best_ms, hipStream_t st) {
+  Batch Bt;
+  int rc = make_batch(base, dtype, rois, n_rois, Bt);
+  if (rc) return rc;
+  if (reps < 1 || reps > 100) return fail(SHAPE3D_EINVAL, "reps must be in [1, 100]");
+  Workspace* wp = nullptr;
+  if ((rc = get_workspace(&wp))) return rc;
+  Workspace& w = *wp;
+  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  const Tuning saved = g_tune;
+  // reference run with the current tiles: vertex counts (for the cache key) and results
+  std::vector<RoiResult> ref((size_t)n_rois);
+  RoiResult* hres = host_results(w, Bt);
+  float ms[8] = {0};
+  if ((rc = run_eager(w, Bt, dtype, st, hres, 1, ms))) return rc;
+  for (int64_t r = 0; r < n_rois; ++r)
+    if (hres[r].status < 0) return fail(hres[r].status, "an internal capacity was exceeded");
+  std::copy(hres, hres + n_rois, ref.begin());
+  const std::string key = tuning_key(dtype, n_rois, ref.data());
+  if (cache_path && tuning_cache_find(cache_path, key, best, best_ms)) {
+    g_tune = best;
+    for (auto& kv : g_ws) drop_graphs(*kv.second);
+    return SHAPE3D_OK;
+  }
+  best_ms = 1e300;
+  best = saved;
+  static const int kCand[5][2] = {{0, 2}, {0, 4}, {0, 8}, {1, 4}, {1, 8}};  // (kernel, itile)
+  for (const auto& kc : kCand)
+    for (int jc : {64, 128, 256, 512}) {
+      g_tune = Tuning{kc[1], jc, 0, kc[0]};
+      double t = 1e300;
+      for (int k = 0; k < reps; ++k) {
+        if ((rc = run_eager(w, Bt, dtype, st, hres, 1, ms))) {
+          g_tune = saved;
+          return rc;
+        }
+        t = std::min(t, (double)ms[3]);
+      }
+      // the tiles only change the work order: every result must be identical
+      for (int64_t r = 0; r < n_rois; ++r)
+        if (memcmp(hres[r].out, ref[(size_t)r].out, sizeof(ref[0].out)) != 0 ||
+            memcmp(hres[r].ids, ref[(size_t)r].ids, sizeof(ref[0].ids)) != 0 || hres[r].status != ref[(size_t)r].status) {
+          g_tune = saved;
+          return fail(SHAPE3D_EINTERNAL, "pair-pass tiles changed a result");
+        }
+      if (t < best_ms) {
+        best_ms = t;
+        best = g_tune;
+      }
+    }
+  g_tune = best;
+  for (auto& kv : g_ws) drop_graphs(*kv.second);
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(SHAPE3D_EINVAL, std::string("cannot append to the tuning cache ") + cache_path);
+    fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), best.kernel, best.itile, best.jchunk, best.blocks_per_cu,
+            best_ms);
+    fclose(f);
+  }
   return SHAPE3D_OK;
 }
 
@@ -813,6 +931,44 @@ int shape3d_release(void) {
   return SHAPE3D_OK;
 }
 
-int shape3d_version(void) { return 102; }
+int shape3d_get_tuning(shape3d_tuning* t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!t) return fail(SHAPE3D_EINVAL, "null argument");
+  t->itile_blocks = g_tune.itile;
+  t->jchunk_blocks = g_tune.jchunk;
+  t->blocks_per_cu = g_tune.blocks_per_cu;
+  t->kernel = g_tune.kernel;
+  return SHAPE3D_OK;
+}
+
+int shape3d_set_tuning(const shape3d_tuning* t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!t) return fail(SHAPE3D_EINVAL, "null argument");
+  const Tuning c{t->itile_blocks, t->jchunk_blocks, t->blocks_per_cu, t->kernel};
+  if (!valid_tuning(c)) return fail(SHAPE3D_EINVAL, "unsupported tile sizes");
+  g_tune = c;
+  for (auto& kv : g_ws) drop_graphs(*kv.second);  // recorded graphs hold the old tiles
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
+int shape3d_autotune(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int reps,
+                     const char* cache_path, shape3d_tuning* best, double* best_ms, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!best || !best_ms) return fail(SHAPE3D_EINVAL, "null output");
+  Tuning b;
+  double ms = 0.0;
+  const int rc = autotune_impl(base, dtype, rois, n_rois, reps, cache_path, b, ms, (hipStream_t)stream);
+  if (rc < 0) return rc;
+  best->itile_blocks = b.itile;
+  best->jchunk_blocks = b.jchunk;
+  best->blocks_per_cu = b.blocks_per_cu;
+  best->kernel = b.kernel;
+  *best_ms = ms;
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
+int shape3d_version(void) { return 103; }
 
 }  // extern "C"

@@ -70,6 +70,17 @@ __device__ inline uint32_t row_bits(const void* vol, const int* d, int z, int y,
   return bits;
 }
 
+// Capacity of the per-plane list of compacted cubes or edges of a brick.
+constexpr int kMeshItems = 2048;
+
+// v[k] of an 8-entry register array for a run-time k (selects, no scratch).
+__device__ inline double sel8d(const double* v, int k) {
+  const double a = (k & 1) ? v[1] : v[0], b = (k & 1) ? v[3] : v[2];
+  const double c = (k & 1) ? v[5] : v[4], e = (k & 1) ? v[7] : v[6];
+  const double ab = (k & 2) ? b : a, ce = (k & 2) ? e : c;
+  return (k & 4) ? ce : ab;
+}
+
 __device__ inline double soft_value(const float* vol, const int* d, int z, int y, int x) {
   if (z < 0 || y < 0 || x < 0 || z >= d[0] || y >= d[1] || x >= d[2]) return 0.0;
   return (double)vol[((size_t)z * d[1] + y) * (size_t)d[2] + x];
@@ -126,7 +137,7 @@ __device__ inline uint32_t slow_row_bits(const Roi& R, const Tile& T, int p, int
 // its whole tile in flight instead of one row-group per thread at a time.
 template <int DT>
 __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) {
-  constexpr int kLoadBatch = 10;
+  constexpr int kLoadBatch = 5;
   const int n = T.np * T.nw;
   for (int base = threadIdx.x; base < n; base += kBrickThreads * kLoadBatch) {
     if (DT == 0) {
@@ -241,6 +252,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   __shared__ double s_area[256];
   __shared__ int s_tk[256];
   __shared__ int s_tm[256];
+  __shared__ uint32_t s_items[kMeshItems];
+  __shared__ int s_scan[4];
   __shared__ double s_rd[2][4];
   __shared__ long long s_rl[4];
   __shared__ int s_ri[8][4];
@@ -278,10 +291,16 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   // origin of the soft tetrahedron sum: the array centre (as the FP64 oracle uses)
   const double o0 = 0.5 * R.d[0] * R.s[0], o1 = 0.5 * R.d[1] * R.s[1], o2 = 0.5 * R.d[2] * R.s[2];
 
-  if (L.valid) {
-    for (int p = 0; p + 1 < T.np; ++p) {
-      const int z = T.pz0 - 1 + p;
-      const Corners C = tile_corners(s_bits, T, L, p, tid, R.G);
+  // Per cube plane: counts and bounding box from the masks, then the active
+  // cubes of the whole workgroup are compacted into s_items (block scan) and
+  // processed densely, so that a lane whose 32 cubes all touch the surface
+  // does not hold up its wave.
+  for (int p = 0; p + 1 < T.np; ++p) {
+    const int z = T.pz0 - 1 + p;
+    uint32_t active = 0u;
+    Corners C;
+    if (L.valid) {
+      C = tile_corners(s_bits, T, L, p, tid, R.G);
       uint32_t any = 0u, all = 0xffffffffu;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -290,44 +309,62 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
       }
       nv += __popc((C.c[0] ^ C.c[4]) & L.vmask) + __popc((C.c[0] ^ C.c[2]) & L.vmask) +
             __popc((C.c[0] ^ C.c[1]) & L.vmask);
-      uint32_t active = any & ~all & L.vmask;
-      while (active) {
-        const int k = __ffs(active) - 1;
-        active &= active - 1u;
-        const int cas = case_of(C, k);
-        const int x = 32 * L.l - 1 + k;
-        const int tk = s_tk[cas];
-        nt += tk & 0xff;
+      active = any & ~all & L.vmask;
+      if (active) {
         bb[0] = min(bb[0], z);
         bb[1] = min(bb[1], L.y);
-        bb[2] = min(bb[2], x);
+        bb[2] = min(bb[2], 32 * L.l - 1 + (__ffs(active) - 1));
         bb[3] = max(bb[3], z);
         bb[4] = max(bb[4], L.y);
-        bb[5] = max(bb[5], x);
+        bb[5] = max(bb[5], 32 * L.l - 1 + (31 - __clz(active)));
+      }
+    }
+    int total;
+    const int off = block_excl_scan256(__popc(active), s_scan, total);
+    for (int c0 = 0; c0 < total; c0 += kMeshItems) {
+      // this thread's items with index in [c0, c0 + kMeshItems)
+      uint32_t m = active;
+      int idx = off;
+      while (m && idx < c0 + kMeshItems) {
+        const int k = __ffs(m) - 1;
+        m &= m - 1u;
+        if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 16) | ((uint32_t)k << 8) | (uint32_t)case_of(C, k);
+        ++idx;
+      }
+      __syncthreads();
+      const int n = min(kMeshItems, total - c0);
+      for (int i = tid; i < n; i += kBrickThreads) {
+        const uint32_t it = s_items[i];
+        const int cas = (int)(it & 0xffu), k = (int)((it >> 8) & 31u), t = (int)(it >> 16);
+        const int rg = T.rg0 + t;
+        const int ry = rg / R.G;
+        const int y = ry - 1, x = 32 * (rg - ry * R.G) - 1 + k;
+        const int tk = s_tk[cas];
+        nt += tk & 0xff;
         if (DT == 0) {
           const int tm = s_tm[cas];
           area += s_area[cas];
           vol_i += (long long)((tk >> 8) - 128) +
-                   2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)L.y * (((tm >> 8) & 0xff) - 128) +
+                   2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)y * (((tm >> 8) & 0xff) - 128) +
                           (long long)x * (((tm >> 16) & 0xff) - 128));
         } else {
           const float* pv = (const float*)R.vol;
           double pc[8];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) pc[c] = soft_value(pv, R.d, z + ((c >> 2) & 1), L.y + ((c >> 1) & 1), x + (c & 1));
+          for (int c = 0; c < 8; ++c) pc[c] = soft_value(pv, R.d, z + ((c >> 2) & 1), y + ((c >> 1) & 1), x + (c & 1));
           const int ntri = tk & 0xff;
-          for (int t = 0; t < ntri; ++t) {
+          for (int tr = 0; tr < ntri; ++tr) {
             double P[3][3];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-              const int e = MC_TRI[cas][t][v];
-              const int a = MC_EDGE_AXIS[e], c0 = MC_EDGE_C0[e];
-              const int c1 = c0 | (4 >> a);
-              const double tt = (0.5 - pc[c0]) / (pc[c1] - pc[c0]);
-              const int u0 = z + ((c0 >> 2) & 1), u1 = L.y + ((c0 >> 1) & 1), u2 = x + (c0 & 1);
-              P[v][0] = ((double)u0 + (a == 0 ? tt : 0.0)) * R.s[0] - o0;
-              P[v][1] = ((double)u1 + (a == 1 ? tt : 0.0)) * R.s[1] - o1;
-              P[v][2] = ((double)u2 + (a == 2 ? tt : 0.0)) * R.s[2] - o2;
+              const int e = MC_TRI[cas][tr][v];
+              const int ax = MC_EDGE_AXIS[e], k0 = MC_EDGE_C0[e];
+              const int k1 = k0 | (4 >> ax);
+              const double tt = (0.5 - sel8d(pc, k0)) / (sel8d(pc, k1) - sel8d(pc, k0));
+              const int u0 = z + ((k0 >> 2) & 1), u1 = y + ((k0 >> 1) & 1), u2 = x + (k0 & 1);
+              P[v][0] = ((double)u0 + (ax == 0 ? tt : 0.0)) * R.s[0] - o0;
+              P[v][1] = ((double)u1 + (ax == 1 ? tt : 0.0)) * R.s[1] - o1;
+              P[v][2] = ((double)u2 + (ax == 2 ? tt : 0.0)) * R.s[2] - o2;
             }
             const double e1x = P[1][0] - P[0][0], e1y = P[1][1] - P[0][1], e1z = P[1][2] - P[0][2];
             const double e2x = P[2][0] - P[0][0], e2y = P[2][1] - P[0][1], e2z = P[2][2] - P[0][2];
@@ -340,6 +377,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
           }
         }
       }
+      __syncthreads();
     }
   }
 
@@ -546,6 +584,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
                                                              int* __restrict__ orig, float* __restrict__ rowmax) {
   extern __shared__ uint32_t s_bits[];
   __shared__ int s_scan[4];
+  __shared__ uint32_t s_items[kMeshItems];
   const long long brick = xcd_remap(blockIdx.x, nbricks);
   if (*overflow != 0u || part[brick].nv == 0) return;
   const int roi = find_roi(rois, n_rois, brick);
@@ -557,7 +596,10 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   __syncthreads();
   const Lane L = lane_of(R, T, tid);
   long long base = M.row_off + brick_voff[brick];
-  // every thread of the brick runs the same steps (block scans inside)
+  // Every thread of the brick runs the same steps (block scans inside).  Per
+  // cube plane the crossing edges are listed in LDS in row order (thread,
+  // axis, cube) and then written by consecutive threads to consecutive rows,
+  // so the stores of a wave are contiguous.
   for (int p = 0; p + 1 < T.np; ++p) {
     const int z = T.pz0 - 1 + p;
     uint32_t e[3] = {0u, 0u, 0u};
@@ -570,25 +612,38 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
     const int cnt = __popc(e[0]) + __popc(e[1]) + __popc(e[2]);
     int total;
     const int off = block_excl_scan256(cnt, s_scan, total);
-    long long row = base + off;
-    for (int a = 0; a < 3; ++a) {
-      uint32_t m = e[a];
-      while (m) {
-        const int k = __ffs(m) - 1;
-        m &= m - 1u;
-        const int u0 = z, u1 = L.y, u2 = 32 * L.l - 1 + k;
-        double t = 0.5;
+    for (int c0 = 0; c0 < total; c0 += kMeshItems) {
+      int idx = off;
+      for (int a = 0; a < 3; ++a) {
+        uint32_t m = e[a];
+        while (m && idx < c0 + kMeshItems) {
+          const int k = __ffs(m) - 1;
+          m &= m - 1u;
+          if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 8) | ((uint32_t)a << 5) | (uint32_t)k;
+          ++idx;
+        }
+      }
+      __syncthreads();
+      const int n = min(kMeshItems, total - c0);
+      for (int i = tid; i < n; i += kBrickThreads) {
+        const uint32_t it = s_items[i];
+        const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), t = (int)(it >> 8);
+        const int rg = T.rg0 + t;
+        const int ry = rg / R.G;
+        const int u0 = z, u1 = ry - 1, u2 = 32 * (rg - ry * R.G) - 1 + k;
+        const long long row = base + c0 + i;
+        double tv = 0.5;
         if (DT == 1) {
           const float* pv = (const float*)R.vol;
           const double pa = soft_value(pv, R.d, u0, u1, u2);
           const double pb = soft_value(pv, R.d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
-          t = (0.5 - pa) / (pb - pa);
-          tsoft[row] = t;
+          tv = (0.5 - pa) / (pb - pa);
+          tsoft[row] = tv;
         }
         key[row] = pack_key(u0, u1, u2, a);
-        const double px = ((double)u0 + (a == 0 ? t : 0.0)) * R.s[0] - M.center[0];
-        const double py = ((double)u1 + (a == 1 ? t : 0.0)) * R.s[1] - M.center[1];
-        const double pz = ((double)u2 + (a == 2 ? t : 0.0)) * R.s[2] - M.center[2];
+        const double px = ((double)u0 + (a == 0 ? tv : 0.0)) * R.s[0] - M.center[0];
+        const double py = ((double)u1 + (a == 1 ? tv : 0.0)) * R.s[1] - M.center[1];
+        const double pz = ((double)u2 + (a == 2 ? tv : 0.0)) * R.s[2] - M.center[2];
         const float fx = (float)px, fy = (float)py, fz = (float)pz;
         const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
         float* blk = pos + (row >> 4) * 64 + (row & 15);
@@ -598,8 +653,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
         blk[48] = fw;
         orig[row] = (int)row;
         rowmax[row] = 0.0f;
-        ++row;
       }
+      __syncthreads();
     }
     base += total;
   }

@@ -169,36 +169,36 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
   }
 }
 
-// Columns (4096-row chunks) per segment.
+// Columns (chunks of jchunk row blocks) per segment.
 __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __restrict__ totals,
-                           const Seg* __restrict__ segs, long long* __restrict__ ncol) {
+                           const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk) {
   const long long nseg = n_rois + totals[T_NSEG2D];
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < seg_cap;
        s += (long long)gridDim.x * blockDim.x) {
     const long long rows = s < nseg ? segs[s].n_rows : 0;
-    ncol[s] = (rows + kJchunkBlocks * kBlk - 1) / (kJchunkBlocks * kBlk);
+    ncol[s] = (rows + (long long)jchunk * kBlk - 1) / ((long long)jchunk * kBlk);
   }
 }
 
 // Column table and items per column: items of column jc of a segment are the
-// 128-row tiles that start before the column ends (upper triangle).
+// row tiles (itile blocks) that start before the column ends (upper triangle).
 __global__ void k_col_fill(int n_rois, long long seg_cap, const long long* __restrict__ totals,
                            const Seg* __restrict__ segs, const long long* __restrict__ ncol,
                            const long long* __restrict__ colbase, Col* __restrict__ cols,
-                           long long* __restrict__ nitem) {
+                           long long* __restrict__ nitem, int itile, int jchunk) {
   const long long nseg = n_rois + totals[T_NSEG2D];
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += (long long)gridDim.x * blockDim.x) {
     const long long nc = ncol[s];
     if (nc == 0) continue;
     const long long nblk = segs[s].n_rows / kBlk;
-    const long long nt = (nblk + kItileBlocks - 1) / kItileBlocks;
+    const long long nt = (nblk + itile - 1) / itile;
     for (long long jc = 0; jc < nc; ++jc) {
       const long long c = colbase[s] + jc;
       Col C;
       C.seg = (int)s;
       C.jc = (int)jc;
       cols[c] = C;
-      const long long lim = (jc + 1) * (kJchunkBlocks / kItileBlocks);
+      const long long lim = (jc + 1) * (jchunk / itile);
       nitem[c] = nt < lim ? nt : lim;
     }
   }
@@ -207,14 +207,14 @@ __global__ void k_col_fill(int n_rois, long long seg_cap, const long long* __res
 // ---------------------------------------------------------------------------
 // Pair maxima on the matrix cores.
 
-// 16 MFMAs: the 8 row blocks against two column blocks, folded into the
+// 2*IT MFMAs: the IT row blocks against two column blocks, folded into the
 // running row maxima with v_max3.
-__device__ __forceinline__ void pair_tile(const float (&A)[kItileBlocks], float b0, float b1,
-                                          v4f (&acc)[kItileBlocks]) {
+template <int IT>
+__device__ __forceinline__ void pair_tile(const float (&A)[IT], float b0, float b1, v4f (&acc)[IT]) {
   const v4f zero = {0.f, 0.f, 0.f, 0.f};
-  v4f d[2 * kItileBlocks];
+  v4f d[2 * IT];
 #pragma unroll
-  for (int r = 0; r < kItileBlocks; ++r) {
+  for (int r = 0; r < IT; ++r) {
     d[2 * r] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], b0, zero, 0, 0, 0);
     d[2 * r + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[r], b1, zero, 0, 0, 0);
   }
@@ -223,7 +223,7 @@ __device__ __forceinline__ void pair_tile(const float (&A)[kItileBlocks], float 
   // pins the running maximum after each tile so the compiler cannot
   // re-associate two tiles into max/max/max3 (three ops per four values).
 #pragma unroll
-  for (int r = 0; r < kItileBlocks; ++r)
+  for (int r = 0; r < IT; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       float a = fmaxf(acc[r][q], fmaxf(d[2 * r][q], d[2 * r + 1][q]));
@@ -232,11 +232,13 @@ __device__ __forceinline__ void pair_tile(const float (&A)[kItileBlocks], float 
     }
 }
 
+template <int IT>
 __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ pos, const Seg* __restrict__ segs,
                                                      const Col* __restrict__ cols,
                                                      const long long* __restrict__ itembase,
                                                      const long long* __restrict__ totals,
-                                                     unsigned int* __restrict__ work_ctr, float* __restrict__ rowmax) {
+                                                     unsigned int* __restrict__ work_ctr, float* __restrict__ rowmax,
+                                                     int jchunk) {
   const int lane = threadIdx.x & 63;
   const long long n_items = totals[T_NITEM];
   const long long ncol = totals[T_NCOL];
@@ -282,20 +284,20 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
     const int it = (int)(item - col_lo);
     const long long rb = S.row_begin >> 4;
     const int nb = S.n_rows >> 4;
-    const int i0 = it * kItileBlocks;
-    const int j0 = max(C.jc * kJchunkBlocks, i0);
-    const int j1 = min((C.jc + 1) * kJchunkBlocks, nb);
+    const int i0 = it * IT;
+    const int j0 = max(C.jc * jchunk, i0);
+    const int j1 = min((C.jc + 1) * jchunk, nb);
 
-    float A[kItileBlocks];
+    float A[IT];
 #pragma unroll
-    for (int r = 0; r < kItileBlocks; ++r) {
+    for (int r = 0; r < IT; ++r) {
       const int blk = min(i0 + r, nb - 1);
       const float v = pos[(rb + blk) * 64 + lane];
       A[r] = lane < 48 ? -2.0f * v : 1.0f;
     }
-    v4f acc[kItileBlocks];
+    v4f acc[IT];
 #pragma unroll
-    for (int r = 0; r < kItileBlocks; ++r) acc[r] = v4f{-3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
+    for (int r = 0; r < IT; ++r) acc[r] = v4f{-3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
 
     // Column blocks are consumed in pairs; two pairs are kept in flight
     // (double buffering).  Prefetch addresses are clamped to the last pair of
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
     }
     // D[i][j] sits in lane 16*(i/4) + j, register i%4: reduce over j (the low 4 lane bits)
 #pragma unroll
-    for (int r = 0; r < kItileBlocks; ++r) {
+    for (int r = 0; r < IT; ++r) {
       if (i0 + r >= nb) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -327,6 +329,183 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
           const long long row = (rb + i0 + r) * 16 + 4 * (lane >> 4) + q;
           const float w = pos[(rb + i0 + r) * 64 + 48 + 4 * (lane >> 4) + q];
           const float val = fmaxf(m + w, 0.0f);
+          atomicMax((int*)&rowmax[row], __float_as_int(val));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split-f16 pair maxima on the 32x32x16 f16 matrix cores.
+//
+// Each centred FP32 coordinate, scaled by 2^e (h_scale_exp), is split into
+// h = f16(x) and l = f16(x - h); x_i . x_j is then h_i.h_j + h_i.l_j + l_i.h_j
+// up to l_i.l_j ~ 2^-22 |x_i||x_j|, and w = |x|^2 likewise splits into two
+// f16.  One K = 16 contraction gives the whole squared distance:
+//   A_i = [-2h, -2h, -2l, w_hi, w_lo, 1, 1, 0, 0, 0]_i   (3+3+3+1+1+1+1+3)
+//   B_j = [ h,   l,   h,  1,    1,  w_hi, w_lo, 0, 0, 0]_j
+// so a v_mfma_f32_32x32x16_f16 yields 1024 pair values (FP32 accumulation)
+// for the cost of a quarter of the FP32 16x16x4 instructions per pair.  The
+// bound on the error (a few 2^-18 R^2, see k_candidates) is covered by the
+// exact FP64 refinement that follows.
+//
+// Operand layout (posh): per 32-row block, 64 lanes x 16 B of A then 64 lanes
+// x 16 B of B; lane l holds K entries 8*(l/32) .. 8*(l/32)+7 of row l % 32.
+
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Builds the split-f16 operands of every row in a segment.
+__global__ void k_pack_h(const float* __restrict__ pos, const int* __restrict__ blkseg, const Seg* __restrict__ segs,
+                         const RoiMeta* __restrict__ meta, const long long* __restrict__ totals,
+                         uint4* __restrict__ posh) {
+  const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
+  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
+       row += (long long)gridDim.x * blockDim.x) {
+    const int s = blkseg[row >> 4];
+    if (s < 0) continue;
+    const int e = h_scale_exp(meta[segs[s].group >> 2].R2);
+    const float* src = pos + (row >> 4) * 64 + (row & 15);
+    float x[3] = {ldexpf(src[0], e), ldexpf(src[16], e), ldexpf(src[32], e)};
+    const float w = ldexpf(src[48], 2 * e);
+    _Float16 h[3], l[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      h[c] = (_Float16)x[c];
+      l[c] = (_Float16)(x[c] - (float)h[c]);
+    }
+    const _Float16 wh = (_Float16)w, wl = (_Float16)(w - (float)wh);
+    const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f, m2 = (_Float16)-2.0f;
+    v8h a0 = {m2 * h[0], m2 * h[1], m2 * h[2], m2 * h[0], m2 * h[1], m2 * h[2], m2 * l[0], m2 * l[1]};
+    v8h a1 = {m2 * l[2], wh, wl, one, one, zero, zero, zero};
+    v8h b0 = {h[0], h[1], h[2], l[0], l[1], l[2], h[0], h[1]};
+    v8h b1 = {h[2], one, one, wh, wl, zero, zero, zero};
+    uint4* blk = posh + (row >> 5) * 128;
+    const int i = (int)(row & 31);
+    blk[i] = *(const uint4*)&a0;
+    blk[32 + i] = *(const uint4*)&a1;
+    blk[64 + i] = *(const uint4*)&b0;
+    blk[96 + i] = *(const uint4*)&b1;
+  }
+}
+
+// 2*IT MFMAs: the IT row blocks against two column blocks, folded into the
+// running maxima with v_max3 (one per two pair values, as in pair_tile).
+template <int IT>
+__device__ __forceinline__ void pair_tile_h(const v8h (&A)[IT], const v8h& b0, const v8h& b1, v16f (&acc)[IT]) {
+  const v16f zero = {};
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const v16f d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[r], b0, zero, 0, 0, 0);
+    const v16f d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[r], b1, zero, 0, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      float a = fmaxf(acc[r][q], fmaxf(d0[q], d1[q]));
+      asm volatile("" : "+v"(a));
+      acc[r][q] = a;
+    }
+  }
+}
+
+// Work items as for k_pair_maxima with itile = 2 * IT 16-row blocks: IT
+// 32-row blocks of A against the column chunk's 32-row blocks of B.
+template <int IT>
+__global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__ posh, const Seg* __restrict__ segs,
+                                                       const Col* __restrict__ cols,
+                                                       const long long* __restrict__ itembase,
+                                                       const long long* __restrict__ totals,
+                                                       const RoiMeta* __restrict__ meta,
+                                                       unsigned int* __restrict__ work_ctr,
+                                                       float* __restrict__ rowmax, int jchunk) {
+  const int lane = threadIdx.x & 63;
+  const long long n_items = totals[T_NITEM];
+  const long long ncol = totals[T_NCOL];
+  long long col = 0, col_lo = 0, col_hi = ncol > 1 ? itembase[1] : n_items;
+  for (;;) {
+    unsigned int got = 0;
+    if (lane == 0) got = atomicAdd(work_ctr, 1u);
+    const long long item = (long long)__builtin_amdgcn_readfirstlane((int)__shfl(got, 0, 64));
+    if (item >= n_items) break;
+    int steps = 0;
+    while (item >= col_hi && steps < 4) {
+      ++col;
+      ++steps;
+      col_lo = col_hi;
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+    }
+    if (item >= col_hi) {
+      long long lo2 = col, hi2 = ncol - 1;
+      while (lo2 < hi2) {
+        const long long mid = (lo2 + hi2 + 1) >> 1;
+        if (itembase[mid] <= item)
+          lo2 = mid;
+        else
+          hi2 = mid - 1;
+      }
+      col = lo2;
+      col_lo = itembase[col];
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+    }
+    while (col + 1 < ncol && item >= col_hi) {
+      ++col;
+      col_lo = col_hi;
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+    }
+    const Col C = cols[col];
+    const Seg S = segs[C.seg];
+    const int it = (int)(item - col_lo);
+    // 32-row block coordinates (segments start and end on 32-row boundaries)
+    const long long rb = S.row_begin >> 5;
+    const int nb = S.n_rows >> 5;
+    const int i0 = it * IT;
+    const int j0 = max(C.jc * (jchunk >> 1), i0);
+    const int j1 = min((C.jc + 1) * (jchunk >> 1), nb);
+
+    v8h A[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      const int blk = min(i0 + r, nb - 1);
+      const uint4 v = posh[(rb + blk) * 128 + lane];
+      A[r] = *(const v8h*)&v;
+    }
+    v16f acc[IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[r][q] = -3.0e38f;
+
+    // column blocks in pairs, two pairs in flight; indices clamped to the last
+    // block of the range (a repeated block is harmless for a maximum)
+    const uint4* Bp = posh + rb * 128 + 64 + lane;
+    const int jl = j1 - 1;
+    uint4 u0 = Bp[(long long)j0 * 128], u1 = Bp[(long long)min(j0 + 1, jl) * 128];
+    for (int jb = j0; jb < j1; jb += 4) {
+      const uint4 u2 = Bp[(long long)min(jb + 2, jl) * 128], u3 = Bp[(long long)min(jb + 3, jl) * 128];
+      pair_tile_h<IT>(A, *(const v8h*)&u0, *(const v8h*)&u1, acc);
+      u0 = Bp[(long long)min(jb + 4, jl) * 128];
+      u1 = Bp[(long long)min(jb + 5, jl) * 128];
+      pair_tile_h<IT>(A, *(const v8h*)&u2, *(const v8h*)&u3, acc);
+    }
+    // D[i][j] sits in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4:
+    // reduce over j (the low 5 lane bits), then undo the scale
+    const int e = h_scale_exp(meta[S.group >> 2].R2);
+    const float unscale = ldexpf(1.0f, -2 * e);
+#pragma unroll
+    for (int r = 0; r < IT; ++r) {
+      if (i0 + r >= nb) continue;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        float m = acc[r][q];
+        m = fmaxf(m, __shfl_xor(m, 1, 64));
+        m = fmaxf(m, __shfl_xor(m, 2, 64));
+        m = fmaxf(m, __shfl_xor(m, 4, 64));
+        m = fmaxf(m, __shfl_xor(m, 8, 64));
+        m = fmaxf(m, __shfl_xor(m, 16, 64));
+        if ((lane & 31) == q) {
+          const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+          const long long row = (rb + i0 + r) * 32 + i;
+          const float val = fmaxf(m, 0.0f) * unscale;
           atomicMax((int*)&rowmax[row], __float_as_int(val));
         }
       }
@@ -379,7 +558,8 @@ __global__ void k_group_max(const float* __restrict__ rowmax, const int* __restr
 __global__ void k_candidates(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
                              const Seg* __restrict__ segs, const RoiMeta* __restrict__ meta,
                              const long long* __restrict__ totals, GroupRes* __restrict__ gres,
-                             unsigned int* __restrict__ ncand, int* __restrict__ cand, long long cand_cap) {
+                             unsigned int* __restrict__ ncand, int* __restrict__ cand, long long cand_cap,
+                             double band) {
   const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
        row += (long long)gridDim.x * blockDim.x) {
@@ -390,12 +570,11 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
     const int g = S.group;
     const float gm = gres[g].gmax;
     if (!(gm > 0.0f)) continue;
-    // The FP32 Gram value of a pair differs from its exact squared distance
-    // by less than 2^-18 * max(R^2, d2) (coordinate rounding plus at most six
-    // FP32 roundings of terms bounded by 4 R^2); keep every row within twice
-    // that of the group maximum.
+    // A pair value of the MFMA pass differs from the exact squared distance by
+    // less than half of band * max(R^2, d2) (FP32 Gram form: 2^-18; split f16:
+    // 2^-16, see the pass); keep every row within that band of the group maximum.
     const double R2 = meta[g >> 2].R2;
-    const float tau = (float)((double)gm - 7.62939453125e-06 * (R2 > (double)gm ? R2 : (double)gm));
+    const float tau = (float)((double)gm - band * (R2 > (double)gm ? R2 : (double)gm));
     if (rowmax[row] >= tau) {
       const unsigned int idx = atomicAdd(ncand, 1u);
       if (idx < cand_cap) cand[idx] = (int)row;
@@ -580,24 +759,66 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs, B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
-                     B.ncol);
+                     B.ncol, B.tune.jchunk);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
   if ((e = launch_fill_i64(B.nitem, 0, B.col_cap, st))) return e;
   hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
-                     B.ncol, B.colbase, B.cols, B.nitem);
+                     B.ncol, B.colbase, B.cols, B.nitem, B.tune.itile, B.tune.jchunk);
   if ((e = launch_scan(B.nitem, B.itembase, B.col_cap, B.totals + T_NITEM, B.scan_tmp, st))) return e;
   return hipGetLastError();
 }
 
 // The work counter (B.counters[0]) must be zero when this is enqueued.
-hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
+template <int IT>
+hipError_t launch_pair_maxima_it(const PairBufs& B, hipStream_t st) {
   hipError_t e;
   int per_cu = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_maxima, 256, 0))) return e;
-  const unsigned grid = (unsigned)(B.cu_count * (per_cu > 0 ? per_cu : 1));
-  hipLaunchKernelGGL(k_pair_maxima, dim3(grid), dim3(256), 0, st, B.pos, B.segs, B.cols, B.itembase, B.totals,
-                     B.counters, B.rowmax);
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_maxima<IT>, 256, 0))) return e;
+  if (per_cu < 1) per_cu = 1;
+  if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
+  const unsigned grid = (unsigned)(B.cu_count * per_cu);
+  hipLaunchKernelGGL(k_pair_maxima<IT>, dim3(grid), dim3(256), 0, st, B.pos, B.segs, B.cols, B.itembase, B.totals,
+                     B.counters, B.rowmax, B.tune.jchunk);
   return hipGetLastError();
+}
+
+template <int IT>
+hipError_t launch_pair_maxima_h(const PairBufs& B, hipStream_t st) {
+  hipError_t e;
+  hipLaunchKernelGGL(k_pack_h, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.pos, B.blkseg, B.segs, B.meta,
+                     B.totals, B.posh);
+  if ((e = hipGetLastError())) return e;
+  int per_cu = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_maxima_h<IT>, 256, 0))) return e;
+  if (per_cu < 1) per_cu = 1;
+  if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
+  const unsigned grid = (unsigned)(B.cu_count * per_cu);
+  hipLaunchKernelGGL(k_pair_maxima_h<IT>, dim3(grid), dim3(256), 0, st, B.posh, B.segs, B.cols, B.itembase,
+                     B.totals, B.meta, B.counters, B.rowmax, B.tune.jchunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
+  if (B.tune.kernel == 1) {
+    switch (B.tune.itile) {
+      case 4:
+        return launch_pair_maxima_h<2>(B, st);
+      case 8:
+        return launch_pair_maxima_h<4>(B, st);
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  switch (B.tune.itile) {
+    case 2:
+      return launch_pair_maxima_it<2>(B, st);
+    case 4:
+      return launch_pair_maxima_it<4>(B, st);
+    case 8:
+      return launch_pair_maxima_it<8>(B, st);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
@@ -610,7 +831,8 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound / kBlk, 1024)), dim3(256), 0, st, B.rowmax, B.blkseg,
                      B.segs, B.totals, B.gres);
   hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
-                     B.meta, B.totals, B.gres, B.counters + 1, B.cand, B.cand_cap);
+                     B.meta, B.totals, B.gres, B.counters + 1, B.cand, B.cand_cap,
+                     B.tune.kernel == 1 ? 6.103515625e-05 /* 2^-14 */ : 7.62939453125e-06 /* 2^-17 */);
   hipLaunchKernelGGL(k_cand_chunks, dim3(grid_for(B.cand_cap)), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg,
                      B.segs, B.cand_nch, B.cand_cap);
   if ((e = launch_scan(B.cand_nch, B.cand_chbase, B.cand_cap, B.totals + T_NEXACT, B.scan_tmp, st))) return e;

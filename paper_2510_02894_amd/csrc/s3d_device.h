@@ -85,6 +85,18 @@ __device__ inline void key_position(uint64_t key, double t, const double* s, dou
   x[2] = __dmul_rn(__dadd_rn((double)u2, a == 2 ? t : 0.0), s[2]);
 }
 
+// Binary exponent e of the scale 2^e applied to a ROI's centred coordinates
+// before the split-f16 pair pass: with R2 a bound on |x|^2, 64 <= 2^e R < 128,
+// so scaled coordinates and |x|^2 (< 2^14) are far inside the f16 range.
+__host__ __device__ inline int h_scale_exp(double R2) {
+  if (!(R2 > 0.0)) return 0;
+  int k;
+  (void)frexp(R2, &k);                                  // 2^(k-1) <= R2 < 2^k
+  const int half = k >= 0 ? (k + 1) / 2 : -((-k) / 2);  // ceil(k / 2)
+  const int e = 7 - half;
+  return e < -120 ? -120 : (e > 120 ? 120 : e);
+}
+
 // Canonical id 3 * lin_pad(u) + a of a vertex key for a ROI of dims d.
 __device__ inline unsigned long long key_canonical_id(uint64_t key, const int* d) {
   const unsigned long long p2 = key & 0xFFFFF, p1 = (key >> 20) & 0xFFFFF, p0 = (key >> 40) & 0xFFFFF;

@@ -21,8 +21,7 @@ constexpr int kBrickThreads = 256;  // threads (row-groups) per brick
 constexpr int kTZ = 8;              // cube planes per brick
 constexpr int kBlk = 16;            // rows per position block
 constexpr int kSegAlign = 32;       // segment rows padded to a multiple of this
-constexpr int kItileBlocks = 8;     // A blocks per wave (128 rows)
-constexpr int kJchunkBlocks = 256;  // B blocks per work item (4096 rows)
+constexpr int kMinJchunk = 64;      // smallest column chunk (row blocks) the pair pass may be tuned to
 constexpr int kScanTile = 2048;     // elements per block of the device scan
 constexpr int kExactChunk = 4096;   // rows per block of the exact refinement
 

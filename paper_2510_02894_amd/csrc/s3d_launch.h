@@ -41,6 +41,14 @@ hipError_t launch_scan(const long long* in, long long* out, long long n, long lo
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t st);
 hipError_t launch_fill_i64(long long* p, long long v, long long n, hipStream_t st);
 
+// Tile sizes of the pair pass (chosen by the autotuner; results do not depend on them).
+struct Tuning {
+  int itile;          // 16-row blocks per wave: 2, 4 or 8 (kernel 1: 4 or 8)
+  int jchunk;         // 16-row column blocks per work item: 64, 128, 256 or 512
+  int blocks_per_cu;  // persistent workgroups per CU (0: as many as fit)
+  int kernel;         // 0: FP32 16x16x4 MFMA; 1: split-f16 32x32x16 MFMA
+};
+
 // Buffers of the diameter passes.
 struct PairBufs {
   const Roi* rois;
@@ -49,6 +57,7 @@ struct PairBufs {
   const unsigned long long* key;
   const double* tsoft;  // null for binary masks
   float* pos;
+  uint4* posh;          // split-f16 operands, 64 B per row (kernel 1)
   int* orig;
   float* rowmax;
   int* blkseg;
@@ -78,6 +87,7 @@ struct PairBufs {
   long long* cand_chbase;  // [cand_cap] prefix sum of cand_nch
   long long max_rows_seg;  // bound on rows of one segment
   long long rows_bound;    // bound on rows of all layouts (allocation)
+  Tuning tune;
   RoiResult* res;          // [n_rois]
   long long* pairs2d;      // [n_rois] in-plane pairs n*(n-1)/2 summed over buckets
   int cu_count;

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libshape3d.so")
 
-OK, EMPTY, EINVAL, ENODEV, EHIP, ECAPACITY, ENOMEM = 0, 1, -1, -2, -3, -4, -5
+OK, EMPTY, EINVAL, ENODEV, EHIP, ECAPACITY, ENOMEM, EINTERNAL = 0, 1, -1, -2, -3, -4, -5, -6
 U8, F32 = 0, 1
 FEATURES = (
     "MeshVolume",
@@ -63,6 +63,14 @@ class SoftSaved(ctypes.Structure):
         ("n_vertices", ctypes.c_int64),
         ("status", ctypes.c_int),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("itile_blocks", ctypes.c_int32), ("jchunk_blocks", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.itile_blocks, self.jchunk_blocks, self.blocks_per_cu, self.kernel)
 
 
 class Roi(ctypes.Structure):
@@ -115,6 +123,14 @@ def load():
                                                       ctypes.POINTER(SoftSaved), f64p, ctypes.c_void_p,
                                                       ctypes.c_void_p]
         lib.shape3d_batched_soft_backward.restype = ctypes.c_int
+        lib.shape3d_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        lib.shape3d_get_tuning.restype = ctypes.c_int
+        lib.shape3d_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+        lib.shape3d_set_tuning.restype = ctypes.c_int
+        lib.shape3d_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Roi), ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(Tuning),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+        lib.shape3d_autotune.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -393,6 +409,37 @@ def shape_features(p, spacing=(1.0, 1.0, 1.0)):
     if _FN is None:
         _FN = _autograd_function()
     return _FN.apply(p, tuple(float(x) for x in spacing))
+
+
+def get_tuning():
+    """Current pair-pass setting (itile_blocks, jchunk_blocks, blocks_per_cu, kernel)."""
+    t = Tuning()
+    _check(load().shape3d_get_tuning(ctypes.byref(t)))
+    return t.as_tuple()
+
+
+def set_tuning(itile_blocks: int, jchunk_blocks: int, blocks_per_cu: int = 0, kernel: int = 0):
+    t = Tuning(int(itile_blocks), int(jchunk_blocks), int(blocks_per_cu), int(kernel))
+    _check(load().shape3d_set_tuning(ctypes.byref(t)))
+
+
+def autotune(base, table, reps: int = 2, cache_path=None):
+    """Choose the pair-pass setting for this batch (see shape3d_autotune):
+    returns ((itile, jchunk, blocks_per_cu, kernel), pair-pass ms)."""
+    import torch
+
+    lib = load()
+    if not isinstance(base, torch.Tensor) or not base.is_cuda or not base.is_contiguous():
+        raise TypeError("base must be a contiguous GPU tensor")
+    dt = U8 if base.dtype == torch.uint8 else (F32 if base.dtype == torch.float32 else None)
+    if dt is None:
+        raise TypeError("base dtype must be uint8 or float32")
+    t = Tuning()
+    ms = ctypes.c_double(0.0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib.shape3d_autotune(ctypes.c_void_p(base.data_ptr()), dt, table, len(table), int(reps), path,
+                                ctypes.byref(t), ctypes.byref(ms), _stream()))
+    return t.as_tuple(), float(ms.value)
 
 
 def release():

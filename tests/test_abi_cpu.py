@@ -19,7 +19,8 @@ def declared_functions():
 def test_header_declares_entry_points():
     names = declared_functions()
     for n in ("shape3d", "shape3d_ex", "shape3d_vertices", "shape3d_batched", "shape3d_soft_forward",
-              "shape3d_soft_backward", "shape3d_batched_soft_forward", "shape3d_batched_soft_backward", "shape3d_last_error", "shape3d_release", "shape3d_version"):
+              "shape3d_soft_backward", "shape3d_batched_soft_forward", "shape3d_batched_soft_backward",
+              "shape3d_get_tuning", "shape3d_set_tuning", "shape3d_autotune", "shape3d_last_error", "shape3d_release", "shape3d_version"):
         assert n in names
 
 
@@ -72,7 +73,8 @@ def test_binding_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors of the header's structs have the C sizes and field offsets."""
     from paper_2510_02894_amd import shape3d as S
 
-    structs = {"shape3d_stats": S.Stats, "shape3d_soft_saved": S.SoftSaved, "shape3d_roi": S.Roi}
+    structs = {"shape3d_stats": S.Stats, "shape3d_soft_saved": S.SoftSaved, "shape3d_roi": S.Roi,
+               "shape3d_tuning": S.Tuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "shape3d.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -89,3 +91,24 @@ def test_binding_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_tuning_setting_is_validated_without_a_device():
+    from paper_2510_02894_amd import shape3d as S
+
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("library not built")
+    before = S.get_tuning()
+    assert before == (8, 256, 0, 0)
+    for bad in [(3, 256, 0, 0), (8, 100, 0, 0), (8, 256, -1, 0), (8, 256, 65, 0), (16, 256, 0, 0), (2, 256, 0, 1),
+                (8, 256, 0, 2)]:
+        with pytest.raises(S.Shape3DError) as ei:
+            S.set_tuning(*bad)
+        assert ei.value.status == S.EINVAL
+        assert S.get_tuning() == before
+    for kernel, tiles in ((0, (2, 4, 8)), (1, (4, 8))):
+        for it in tiles:
+            for jc in (64, 128, 256, 512):
+                S.set_tuning(it, jc, 2, kernel)
+                assert S.get_tuning() == (it, jc, 2, kernel)
+    S.set_tuning(*before)
