@@ -31,8 +31,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_F16_MFMA_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
-FLOPS_PER_PAIR = 8              # Gram form: 16x16x4 MFMA = 2048 flops per 256 pairs
+# Gram form on the matrix cores, flops per vertex pair as executed:
+# kernel 0: v_mfma_f32_16x16x4_f32, 2048 flops per 256 pairs;
+# kernel 1: v_mfma_f32_32x32x16_f16 (split f16), 32768 flops per 1024 pairs.
+FLOPS_PER_PAIR = {0: 8, 1: 32}
+PEAK_TFLOPS = {0: PEAK_FP32_MFMA_TFLOPS, 1: PEAK_F16_MFMA_TFLOPS}
+# Pairs per SIMD cycle when the MFMA and the VALU maxima (one v_max3 per two
+# pair values, 4 cycles per wave64 instruction) issue one after the other:
+# kernel 0: 256 pairs per (32 + 8) cycles; kernel 1: 1024 pairs per (32 + 32).
+PAIRS_PER_SIMD_CYCLE = {0: 256.0 / 40.0, 1: 1024.0 / 64.0}
+SIMDS, CLOCK_GHZ = 1024, 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -387,10 +397,16 @@ def main():
     log("phases (ms): " + ", ".join("%s %.4f" % kv for kv in avg.items()))
 
     t_pair = avg["pair_maxima"] * 1e-3
-    achieved = FLOPS_PER_PAIR * (pairs3 + pairs2) / t_pair / 1e12
-    traffic = measured_traffic("k_pair_maxima")
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": traffic}
+    kern = int(tiles[3])
+    achieved = FLOPS_PER_PAIR[kern] * (pairs3 + pairs2) / t_pair / 1e12
+    traffic = measured_traffic("k_pair_maxima_h" if kern == 1 else "k_pair_maxima")
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[kern], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS[kern], "traffic": traffic,
+                "kernel": "split-f16 v_mfma_f32_32x32x16_f16" if kern == 1 else "fp32 v_mfma_f32_16x16x4_f32"}
+    ceiling = PAIRS_PER_SIMD_CYCLE[kern] * SIMDS * CLOCK_GHZ * 1e9
+    pair_issue = {"achieved_pairs_per_s": (pairs3 + pairs2) / t_pair, "ceiling_pairs_per_s": ceiling,
+                  "frac": (pairs3 + pairs2) / t_pair / ceiling,
+                  "note": "ceiling with MFMA and VALU maxima issued one after the other (they do not co-issue)"}
     N = int(np.prod(mask.shape))
     t_mesh = (avg["mesh_count"] + avg["mesh_emit"]) * 1e-3
     mesh_bytes = N * 1 + 24 * V
@@ -418,7 +434,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16" if kern == 1 else "f32",
         "data": "synthetic",
         "config": {
             "workload": "large ROI: uint8 mask 300x512x512 (axis0 = slices), spacing (1.25,0.7,0.7) mm, "
@@ -431,6 +447,7 @@ def main():
             "pairs_in_plane": pairs2,
         },
         "roofline": roofline,
+        "pair_issue_roofline": pair_issue,
         "cpu_baseline": cpu,
         "tiles": list(tiles),
         "phases_ms": avg,
