@@ -70,6 +70,7 @@ struct Workspace {
   hipStream_t graph_stream = nullptr;  // graphs are recorded and replayed here (the caller's
                                        // stream may be the legacy null stream, which cannot record)
   long long rows0_cap = 0;  // layout-0 rows the vertex buffers were sized for
+  long long last_rows0 = 0;  // layout-0 rows of the last eager run (a recorded graph is sized for them)
   std::map<std::string, GraphRec> graphs;
 
   std::vector<Buf*> all() {
@@ -283,9 +284,12 @@ RoiResult* host_results(Workspace& w, const Batch& B) {
 }
 
 // Buffers sized by the layout-0 row count (all ROIs' padded vertex rows).
-int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0, Sizes& S) {
+// Grows the vertex buffers to hold rows0 layout-0 rows (they never shrink) and
+// returns in S the sizes of this call's work, which follow rows0 itself.
+int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0, Sizes& S_call) {
   int rc;
-  S = sizes_for(B, std::max<long long>(rows0, w.rows0_cap));
+  const Sizes S = sizes_for(B, std::max<long long>(rows0, w.rows0_cap));
+  S_call = sizes_for(B, rows0);
   const long long scan_n = std::max(std::max(B.n_buckets, S.rows_bound), std::max(S.seg_cap, S.col_cap));
   if ((rc = ensure(w, w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
   if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
@@ -406,6 +410,7 @@ int run_eager(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, RoiResul
   HIPCK(hipStreamSynchronize(st));
   Sizes S;
   if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
+  w.last_rows0 = th[0];
   if ((rc = launch_tail(w, Bt, dtype, S, st, host_res, timing ? &w.ev[2] : nullptr))) return rc;
   if (timing) HIPCK(hipEventRecord(w.ev[7], st));
   HIPCK(hipStreamSynchronize(st));
@@ -472,7 +477,9 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
     rec.host_res = nullptr;
     return fail(SHAPE3D_ENOMEM, "pinned host allocation failed");
   }
-  const Sizes S = sizes_for(Bt, w.rows0_cap);
+  // sized for the eager run just made: a replay that finds more rows than
+  // that is caught by the capacity check and re-run eagerly
+  const Sizes S = sizes_for(Bt, w.last_rows0);
   hipGraph_t graph = nullptr;
   HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int rc = launch_head(w, Bt, dtype, st);
