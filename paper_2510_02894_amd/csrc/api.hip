@@ -62,7 +62,7 @@ struct Workspace {
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
       bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
-      posh, soft_rois, soft_edges, soft_q, soft_row_base, soft_row_cnt, soft_ctr;
+      posh, soft_rois, soft_edges, soft_field, soft_ctr;
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
@@ -77,7 +77,7 @@ struct Workspace {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
             &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &ncol,     &colbase,
             &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
-            &cand_chbase, &posh, &soft_rois, &soft_edges, &soft_q, &soft_row_base, &soft_row_cnt, &soft_ctr};
+            &cand_chbase, &posh, &soft_rois, &soft_edges, &soft_field, &soft_ctr};
   }
 };
 
@@ -607,7 +607,7 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
   std::vector<SoftBwdRoi> table((size_t)n_rois);
-  long long n_rows = 0, n_vrows = 0, cap = 0;
+  long long n_rows = 0, n_vrows = 0, n_field = 0, cap = 0;
   for (int64_t r = 0; r < n_rois; ++r) {
     const shape3d_soft_saved& S = saved[r];
     for (int k = 0; k < 3; ++k)
@@ -638,6 +638,8 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
     }
     R.row_begin = n_rows;
     R.vrow_begin = n_vrows;
+    R.field_begin = n_field;
+    n_field += 3ll * (R.d[0] + 1) * (R.d[1] + 1) * (R.d[2] + 1);
     n_rows += (long long)(R.d[0] + 1) * (R.d[1] + 1);
     n_vrows += (long long)R.d[0] * R.d[1];
     cap += S.n_vertices;
@@ -646,9 +648,8 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   const size_t tbytes = sizeof(SoftBwdRoi) * (size_t)n_rois;
   if ((rc = ensure(w, w.soft_rois, tbytes))) return rc;
   if ((rc = ensure(w, w.soft_edges, sizeof(unsigned long long) * std::max<long long>(cap, 1)))) return rc;
-  if ((rc = ensure(w, w.soft_q, sizeof(double) * std::max<long long>(cap, 1)))) return rc;
-  if ((rc = ensure(w, w.soft_row_base, sizeof(long long) * n_rows))) return rc;
-  if ((rc = ensure(w, w.soft_row_cnt, sizeof(int) * n_rows))) return rc;
+  // one float per grid edge; only crossing edges' slots are ever written or read
+  if ((rc = ensure(w, w.soft_field, sizeof(float) * n_field))) return rc;
   if ((rc = ensure(w, w.soft_ctr, sizeof(long long) * 2))) return rc;
   if ((rc = ensure_host(w, std::max<size_t>(w.host_cap, 4096 + tbytes)))) return rc;
   char* h = (char*)w.host;
@@ -661,9 +662,8 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   B.n_vrows = n_vrows;
   B.cap = cap;
   B.edges = (unsigned long long*)w.soft_edges.p;
-  B.q = (double*)w.soft_q.p;
-  B.row_base = (long long*)w.soft_row_base.p;
-  B.row_cnt = (int*)w.soft_row_cnt.p;
+  B.field = (float*)w.soft_field.p;
+  B.n_field = n_field;
   B.counters = (long long*)w.soft_ctr.p;
   B.cu_count = w.cu_count;
   HIPCK(launch_soft_backward(B, st));

@@ -172,11 +172,42 @@ __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) 
         s_bits[idx] = bits;
       }
     } else {
-      for (int u = 0; u < kLoadBatch; ++u) {
-        const int idx = base + u * kBrickThreads;
-        if (idx >= n) break;
-        const int p = idx / T.nw;
-        s_bits[idx] = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+      // float32: a row-group is 128 B; two of them (sixteen float4 loads) are
+      // in flight per thread before any is converted
+      for (int u0 = 0; u0 < kLoadBatch; u0 += 2) {
+        float4 v[2][8];
+        bool fast[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int idx = base + (u0 + h) * kBrickThreads;
+          const void* ptr = nullptr;
+          if (u0 + h < kLoadBatch && idx < n) {
+            const int p = idx / T.nw;
+            ptr = fast_row_ptr<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+          }
+          fast[h] = ptr != nullptr;
+          if (fast[h]) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[h][i] = ((const float4*)ptr)[i];
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int idx = base + (u0 + h) * kBrickThreads;
+          if (u0 + h >= kLoadBatch || idx >= n) continue;
+          uint32_t bits = 0u;
+          if (fast[h]) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              bits |= ((uint32_t)(v[h][i].x > 0.5f) | ((uint32_t)(v[h][i].y > 0.5f) << 1) |
+                       ((uint32_t)(v[h][i].z > 0.5f) << 2) | ((uint32_t)(v[h][i].w > 0.5f) << 3))
+                      << (4 * i);
+          } else {
+            const int p = idx / T.nw;
+            bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+          }
+          s_bits[idx] = bits;
+        }
       }
     }
   }

@@ -49,6 +49,7 @@ __device__ inline int bucket_roi(const Roi* rois, int n, long long b, int& axis)
 // ---------------------------------------------------------------------------
 // Plane buckets.
 
+template <bool want_old>
 __device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b);
 
 __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
@@ -66,30 +67,41 @@ __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __res
       const int a = (int)((k >> 60) & 3);
       for (int ax = 0; ax < 3; ++ax) {
         const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
-        wave_aggregated_inc(bcnt, b);
+        wave_aggregated_inc<false>(bcnt, b);
       }
     }
   }
 }
 
 // Adds 1 to counter[b] for every active lane and returns the lane's previous
-// count; lanes with the same b are served by one atomic (consecutive vertices
-// mostly share a plane).
+// count (or nothing, with want_old = false).  Lanes with the same b form one
+// group served by one atomic of its leader; the groups are found first (ALU
+// only) and then all leaders issue their atomics together, so a wave waits
+// for one atomic round trip however many distinct buckets its lanes hit.
+template <bool want_old>
 __device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b) {
   unsigned long long todo = __ballot(1);
-  unsigned int result = 0;
   const int lane = threadIdx.x & 63;
+  int leader_of_me = lane;
+  unsigned int rank = 0, group = 0;
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
     const long long bl = __shfl(b, leader, 64);
     const unsigned long long same = __ballot(b == bl) & todo;
-    unsigned int base = 0;
-    if (lane == leader) base = atomicAdd(&counter[bl], (unsigned int)__popcll(same));
-    base = __shfl(base, leader, 64);
-    if (b == bl) result = base + (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+    if (b == bl) {
+      leader_of_me = leader;
+      rank = (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) group = (unsigned int)__popcll(same);
     todo &= ~same;
   }
-  return result;
+  if (!want_old) {
+    if (group) atomicAdd(&counter[b], group);
+    return 0u;
+  }
+  unsigned int base = 0;
+  if (group) base = atomicAdd(&counter[b], group);
+  return __shfl(base, leader_of_me, 64) + rank;
 }
 
 __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long nb, long long* __restrict__ bsz,
@@ -120,7 +132,7 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
     for (int ax = 0; ax < 3; ++ax) {
       const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
       if (bcnt[b] < 2) continue;
-      const long long dst_row = rows0 + brow[b] + wave_aggregated_inc(bcur, b);
+      const long long dst_row = rows0 + brow[b] + wave_aggregated_inc<true>(bcur, b);
       float* dst = pos + (dst_row >> 4) * 64 + (dst_row & 15);
       dst[0] = sx;
       dst[16] = sy;

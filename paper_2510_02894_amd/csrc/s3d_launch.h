@@ -96,7 +96,9 @@ struct PairBufs {
 // soft.hip: adjoint of the soft-mask forward pass, for a table of ROIs.
 // Rows: a "padded row" is a cube row (u0, u1) with u0 in [-1, d0-1], u1 in
 // [-1, d1-1]; a "voxel row" is (w0, w1) in [0, d0) x [0, d1).  Both are
-// numbered globally, ROI after ROI.
+// numbered globally, ROI after ROI.  The edge field has one slot per grid
+// edge (u, u + e_a), u in [-1, d-1]^3: slot field_begin + 3 * cube(u) + a with
+// cube(u) = ((u0 + 1) (d1 + 1) + u1 + 1) (d2 + 1) + u2 + 1.
 struct SoftBwdRoi {
   const float* p;             // the ROI's probabilities (d0, d1, d2)
   float* grad;                // dL/dp, same layout
@@ -110,6 +112,7 @@ struct SoftBwdRoi {
   long long pair_ids[4][2];   // canonical ids of the maximising pairs, -1 if none
   long long row_begin;        // first global padded row
   long long vrow_begin;       // first global voxel row
+  long long field_begin;      // first slot of the ROI in the edge field
 };
 
 struct SoftBwdBufs {
@@ -118,10 +121,9 @@ struct SoftBwdBufs {
   long long n_rows;           // padded rows of all ROIs
   long long n_vrows;          // voxel rows of all ROIs
   long long cap;              // crossing-edge capacity (the forward pass's vertex count)
-  unsigned long long* edges;  // [cap] (global padded row << 17) | ((u2 + 1) * 3 + a), sorted within a row
-  double* q;                  // [cap] dL/dx_v along the edge axis, times the spacing of that axis
-  long long* row_base;        // [n_rows] first edge of each padded row
-  int* row_cnt;               // [n_rows] edges of each padded row
+  unsigned long long* edges;  // [cap] edge-field slots of the crossing edges
+  float* field;               // edge field: (dL/dx_v)_a * s_a at crossing edges (other slots unused)
+  long long n_field;          // slots of the edge field
   long long* counters;        // [0] edges reserved
   int cu_count;
 };

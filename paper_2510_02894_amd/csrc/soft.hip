@@ -15,15 +15,16 @@
 //
 // Three passes over every ROI of a table:
 //   1. k_soft_edges: one wave per padded cube row lists the row's crossing
-//      edges in (u2, a) order; a workgroup reserves room for its rows with one
-//      atomic and records each row's first entry and count;
+//      edges (their slots in the edge field); a workgroup reserves room for
+//      its rows with one atomic;
 //   2. k_soft_vertex_grad: one thread per crossing edge (the surface is sparse,
 //      so a thread per voxel would leave most lanes idle around the FP64 work)
-//      computes (dL/dx_v)_a * s_a;
+//      computes (dL/dx_v)_a * s_a into the edge's field slot;
 //   3. k_soft_gather: one wave per voxel row sums, for each voxel, the terms of
-//      its (at most six) incident crossing edges, found by binary search in the
-//      edge's row, and writes dL/dp densely (0 away from the surface).
-// No float atomics: the result does not depend on scheduling.
+//      its (at most six) incident crossing edges, read directly from their
+//      field slots, and writes dL/dp densely (0 away from the surface).
+// Only slots of crossing edges are written and read, so the field is never
+// cleared.  No float atomics: the result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #define MC_TABLE_QUAL __constant__ const
@@ -178,6 +179,18 @@ __device__ inline float row_ld(const RowPtr& r, int x, int d2) {
   return r.ok && (unsigned)x < (unsigned)d2 ? v : 0.0f;
 }
 
+__device__ inline int soft_roi_of_slot(const SoftBwdRoi* r, int n, long long slot) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (r[mid].field_begin <= slot)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // Bit a set iff the edge (u, u + e_a) crosses the 0.5 level; A, Z, Y are the
 // rows (u0, u1), (u0 + 1, u1), (u0, u1 + 1).
 __device__ inline unsigned crossing_bits(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int u2, int d2) {
@@ -267,12 +280,8 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   }
   __syncthreads();
   const long long base = base_sh;
-  if (threadIdx.x < kRowsPerBlock && row0 + threadIdx.x < B.n_rows) {
-    B.row_base[row0 + threadIdx.x] = base >= 0 ? base + pre[threadIdx.x] : 0;
-    B.row_cnt[row0 + threadIdx.x] = base >= 0 ? cnt[threadIdx.x] : 0;
-  }
   if (base < 0 || wrow0 >= B.n_rows) return;
-  // pass 2: write the rows' edges, sorted by (u2, a)
+  // pass 2: write the rows' edges (field slots), in (row, u2, a) order
   PaddedRowWalk W;
   W.start(B.rois, B.n_rois, wrow0);
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -286,6 +295,8 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
       const RowPtr A = row_ptr(R->p, R->d, W.u0, W.u1), Z = row_ptr(R->p, R->d, W.u0 + 1, W.u1),
                    Y = row_ptr(R->p, R->d, W.u0, W.u1 + 1);
       long long off = base + pre[li];
+      // slot of cube (u0, u1, -1) of this row: the row's local index times d2 + 1
+      const long long slot0 = R->field_begin + 3ll * (row - R->row_begin) * (d2 + 1);
       for (int x0 = 0; x0 <= d2; x0 += 128) {
         unsigned bb[2];
         row_bits2(A, Z, Y, x0 + lane, d2, bb[0], bb[1]);
@@ -296,7 +307,7 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
           const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
           long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
           for (int a = 0; a < 3; ++a)
-            if ((b >> a) & 1u) B.edges[slot++] = ((unsigned long long)row << 17) | (unsigned long long)(x1 * 3 + a);
+            if ((b >> a) & 1u) B.edges[slot++] = (unsigned long long)(slot0 + 3ll * x1 + a);
           off += __popcll(m0) + __popcll(m1) + __popcll(m2);
         }
       }
@@ -309,12 +320,16 @@ __global__ __launch_bounds__(256) void k_soft_vertex_grad(SoftBwdBufs B) {
   const long long n = min(B.counters[0], B.cap);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const unsigned long long e = B.edges[i];
-    const long long row = (long long)(e >> 17);
-    const int key = (int)(e & 0x1FFFFull);
-    const int a = key % 3, u2 = key / 3 - 1;
-    const SoftBwdRoi* R = B.rois + soft_roi_of_row(B.rois, B.n_rois, row);
-    const long long lr = row - R->row_begin;
+    const long long slot = (long long)B.edges[i];
+    // an entry no block wrote (only when the input has more crossing edges
+    // than the forward pass: the call then fails) must not address memory
+    if (slot < 0 || slot >= B.n_field) continue;
+    const SoftBwdRoi* R = B.rois + soft_roi_of_slot(B.rois, B.n_rois, slot);
+    const long long local = slot - R->field_begin;
+    const int a = (int)(local % 3);
+    const long long cube = local / 3;
+    const int u2 = (int)(cube % (R->d[2] + 1)) - 1;
+    const long long lr = cube / (R->d[2] + 1);
     const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
     double gx[3] = {0.0, 0.0, 0.0};
     vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, gx);
@@ -339,44 +354,42 @@ __global__ __launch_bounds__(256) void k_soft_vertex_grad(SoftBwdBufs B) {
       // dD/dx_v = (x_v - x_other) / D for either end point
       for (int c = 0; c < 3; ++c) gx[c] += gd * (xv[c] - xo[c]);
     }
-    B.q[i] = gx[a] * R->s[a];
+    B.field[slot] = (float)(gx[a] * R->s[a]);
   }
 }
 
-// q of edge key (u2 + 1) * 3 + a of padded row `row` (0 if it is not listed).
-__device__ inline double edge_q(const SoftBwdBufs& B, long long row, int key) {
-  long long lo = B.row_base[row], hi = lo + B.row_cnt[row] - 1;
-  while (lo <= hi) {
-    const long long mid = (lo + hi) >> 1;
-    const int k = (int)(B.edges[mid] & 0x1FFFFull);
-    if (k == key) return B.q[mid];
-    if (k < key)
-      lo = mid + 1;
-    else
-      hi = mid - 1;
-  }
-  return 0.0;
-}
-
-// dL/dp of voxel (w0, w1, x) of ROI R from its row and the four neighbouring
-// rows; rw is the padded row of the cube row (w0, w1).
-__device__ inline double voxel_grad(const SoftBwdBufs& B, const SoftBwdRoi* R, long long rw, int x, float vc,
-                                    const float* nv) {
+// dL/dp of voxel w from its value vc and its six neighbours nv (indexed
+// 2a + (neighbour is w + e_a)); slot_w is the field slot of edge (w, axis 0)
+// and stride[a] the slot distance between the edges (w - e_a, a) and (w, a).
+__device__ inline double voxel_grad(const float* __restrict__ field, long long slot_w, const long long* stride,
+                                    float vc, const float* nv) {
   const bool in_w = vc > 0.5f;
-  double g = 0.0;
+  bool cross[6];
+  bool any = false;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    const int a = j >> 1;
-    const bool up = j & 1;  // the neighbour is w + e_a (w is the edge's lower end)
-    if ((nv[j] > 0.5f) == in_w) continue;
-    // the edge (u, u + e_a) with u = w (up) or w - e_a; (w0, w1 - 1) is the
-    // padded row before rw and (w0 - 1, w1) the one d1 + 1 before it
-    const int u2 = a == 2 && !up ? x - 1 : x;
-    const long long row = up || a == 2 ? rw : (a == 0 ? rw - (R->d[1] + 1) : rw - 1);
-    const double q = edge_q(B, row, (u2 + 1) * 3 + a);
-    const double pu = up ? (double)vc : (double)nv[j], pb = up ? (double)nv[j] : (double)vc;
-    const double den = pb - pu;
-    g += q * (up ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den));
+    cross[j] = (nv[j] > 0.5f) != in_w;
+    any |= cross[j];
+  }
+  double g = 0.0;
+  if (__ballot(any)) {
+    // every lane loads all six slots (its own edge (w, 0) stands in where an
+    // edge does not cross), so the loads issue together
+    float q[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int a = j >> 1;
+      const long long sl = slot_w + a - ((j & 1) ? 0 : stride[a]);
+      q[j] = field[cross[j] ? sl : slot_w];
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (!cross[j]) continue;
+      const bool up = j & 1;  // the neighbour is w + e_a (w is the edge's lower end)
+      const double pu = up ? (double)vc : (double)nv[j], pb = up ? (double)nv[j] : (double)vc;
+      const double den = pb - pu;
+      g += (double)q[j] * (up ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den));
+    }
   }
   return g;
 }
@@ -394,7 +407,9 @@ __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
     const int* d = R->d;
     const float* p = R->p;
     const int d2 = d[2];
-    const long long rw = R->row_begin + (long long)(w0 + 1) * (d[1] + 1) + (w1 + 1);
+    // slot of edge ((w0, w1, -1), axis 0); voxel x adds 3 (x + 1)
+    const long long slot_row = R->field_begin + 3ll * ((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d2 + 1);
+    const long long stride[3] = {3ll * (d[1] + 1) * (d2 + 1), 3ll * (d2 + 1), 3};
     const RowPtr C = row_ptr(p, d, w0, w1), Zm = row_ptr(p, d, w0 - 1, w1), Zp = row_ptr(p, d, w0 + 1, w1),
                  Ym = row_ptr(p, d, w0, w1 - 1), Yp = row_ptr(p, d, w0, w1 + 1);
     float* grow = R->grad + ((size_t)w0 * d[1] + w1) * (size_t)d2;
@@ -415,7 +430,15 @@ __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int x = x0 + 64 * h + lane;
-        if (x < d2) grow[x] = (float)voxel_grad(B, R, rw, x, vc[h], nv[h]);
+        // lanes past the row end take part (the wave votes inside) with no
+        // crossing edge and an in-range slot
+        if (x >= d2) {
+          vc[h] = 0.0f;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) nv[h][j] = 0.0f;
+        }
+        const double g = voxel_grad(B.field, slot_row + 3ll * (min(x, d2 - 1) + 1), stride, vc[h], nv[h]);
+        if (x < d2) grow[x] = (float)g;
       }
     }
     // next voxel row
