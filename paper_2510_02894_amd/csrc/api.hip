@@ -644,7 +644,7 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
     n_vrows += (long long)R.d[0] * R.d[1];
     cap += S.n_vertices;
   }
-  if (n_rows / 32 > (1ll << 31) - 2) return fail(SHAPE3D_EINVAL, "batch too large");
+  if (n_rows / 32 > (1ll << 31) - 2 || n_vrows / 4 > (1ll << 31) - 2) return fail(SHAPE3D_EINVAL, "batch too large");
   const size_t tbytes = sizeof(SoftBwdRoi) * (size_t)n_rois;
   if ((rc = ensure(w, w.soft_rois, tbytes))) return rc;
   if ((rc = ensure(w, w.soft_edges, sizeof(unsigned long long) * std::max<long long>(cap, 1)))) return rc;

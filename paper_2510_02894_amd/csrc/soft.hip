@@ -173,6 +173,13 @@ __device__ inline RowPtr row_ptr(const float* p, const int* d, int z, int y) {
   return {p + ((size_t)(ok ? z : 0) * d[1] + (ok ? y : 0)) * (size_t)d[2], ok};
 }
 
+// Element x in [0, d2) of a row, 0 if the row is outside the array (its
+// pointer then addresses row 0, so the load is always in range).
+__device__ inline float row_in(const RowPtr& r, int x) {
+  const float v = r.ptr[x];
+  return r.ok ? v : 0.0f;
+}
+
 // Element x of a row, 0 outside; the load is always issued at a clamped address.
 __device__ inline float row_ld(const RowPtr& r, int x, int d2) {
   const float v = r.ptr[min(max(x, 0), d2 - 1)];
@@ -237,6 +244,49 @@ __device__ inline void row_bits2(const RowPtr& A, const RowPtr& Z, const RowPtr&
   b1 = x1 + 64 <= d2 ? b1 : 0u;
 }
 
+// Crossing bits of every cube of a padded row with at most 64 * NC cubes:
+// chunk c (cubes u2 = 64c - 1 + lane) in bits 3c .. 3c + 2 of the result.
+// Chunks past the row end are skipped (a uniform branch); the loads of the
+// others are all issued before any is used.
+template <int NC>
+__device__ inline uint32_t row_bits_all(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int lane, int d2) {
+  float va[NC], vz[NC], vy[NC], vx[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (64 * c > d2) break;
+    const int x1 = min(64 * c + lane, d2);  // u2 + 1
+    const int i0 = max(x1 - 1, 0), i1 = min(x1, d2 - 1);
+    va[c] = A.ptr[i0];
+    vz[c] = Z.ptr[i0];
+    vy[c] = Y.ptr[i0];
+    vx[c] = A.ptr[i1];
+  }
+  uint32_t out = 0u;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (64 * c > d2) break;
+    const int x1 = 64 * c + lane;
+    const bool lo_ok = x1 >= 1, hi_ok = x1 <= d2 - 1;  // voxels u2 and u2 + 1 inside the row
+    const bool in = A.ok && lo_ok && va[c] > 0.5f;
+    const bool iz = Z.ok && lo_ok && vz[c] > 0.5f;
+    const bool iy = Y.ok && lo_ok && vy[c] > 0.5f;
+    const bool ix = A.ok && hi_ok && vx[c] > 0.5f;
+    const uint32_t b = (uint32_t)(iz != in) | ((uint32_t)(iy != in) << 1) | ((uint32_t)(ix != in) << 2);
+    out |= (x1 <= d2 ? b : 0u) << (3 * c);
+  }
+  return out;
+}
+
+// Cached crossing bits of a row (see row_bits_all), or kUncached for rows of
+// more than 512 cubes, whose bits are recomputed chunk by chunk.
+constexpr uint32_t kUncached = 0x80000000u;
+
+__device__ inline uint32_t row_bits_cached(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int lane, int d2) {
+  if (d2 + 1 <= 256) return row_bits_all<4>(A, Z, Y, lane, d2);
+  if (d2 + 1 <= 512) return row_bits_all<8>(A, Z, Y, lane, d2);
+  return kUncached;
+}
+
 __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   __shared__ int cnt[kRowsPerBlock];
   __shared__ long long pre[kRowsPerBlock];
@@ -244,23 +294,31 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const long long row0 = (long long)blockIdx.x * kRowsPerBlock;
   const long long wrow0 = row0 + wid * kRowsPerWave;
-  // pass 1: crossing edges per row
+  // pass 1: crossing edges per row; the bits of short rows stay in registers
+  uint32_t cache[kRowsPerWave];
   {
     PaddedRowWalk W;
     if (wrow0 < B.n_rows) W.start(B.rois, B.n_rois, wrow0);
+#pragma unroll
     for (int k = 0; k < kRowsPerWave; ++k) {
       const long long row = wrow0 + k;
       int c = 0;
+      cache[k] = 0u;
       if (row < B.n_rows) {
         const SoftBwdRoi* R = W.R;
         const int d2 = R->d[2];
         const RowPtr A = row_ptr(R->p, R->d, W.u0, W.u1), Z = row_ptr(R->p, R->d, W.u0 + 1, W.u1),
                      Y = row_ptr(R->p, R->d, W.u0, W.u1 + 1);
-        for (int x0 = 0; x0 <= d2; x0 += 128) {
-          unsigned b0, b1;
-          row_bits2(A, Z, Y, x0 + lane, d2, b0, b1);
-          c += __popcll(__ballot(b0 & 1u)) + __popcll(__ballot(b0 & 2u)) + __popcll(__ballot(b0 & 4u)) +
-               __popcll(__ballot(b1 & 1u)) + __popcll(__ballot(b1 & 2u)) + __popcll(__ballot(b1 & 4u));
+        cache[k] = row_bits_cached(A, Z, Y, lane, d2);
+        if (cache[k] != kUncached) {
+          c = wave_sum(__popc(cache[k]));
+        } else {
+          for (int x0 = 0; x0 <= d2; x0 += 128) {
+            unsigned b0, b1;
+            row_bits2(A, Z, Y, x0 + lane, d2, b0, b1);
+            c += __popc(b0) + __popc(b1);
+          }
+          c = wave_sum(c);
         }
         W.next();
       }
@@ -285,6 +343,7 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   PaddedRowWalk W;
   W.start(B.rois, B.n_rois, wrow0);
   const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
   for (int k = 0; k < kRowsPerWave; ++k) {
     const int li = wid * kRowsPerWave + k;
     const long long row = wrow0 + k;
@@ -297,19 +356,20 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
       long long off = base + pre[li];
       // slot of cube (u0, u1, -1) of this row: the row's local index times d2 + 1
       const long long slot0 = R->field_begin + 3ll * (row - R->row_begin) * (d2 + 1);
-      for (int x0 = 0; x0 <= d2; x0 += 128) {
-        unsigned bb[2];
-        row_bits2(A, Z, Y, x0 + lane, d2, bb[0], bb[1]);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const unsigned b = bb[h];
-          const int x1 = x0 + 64 * h + lane;  // u2 + 1
-          const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
-          long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
-          for (int a = 0; a < 3; ++a)
-            if ((b >> a) & 1u) B.edges[slot++] = (unsigned long long)(slot0 + 3ll * x1 + a);
-          off += __popcll(m0) + __popcll(m1) + __popcll(m2);
+      for (int x0 = 0; x0 <= d2; x0 += 64) {
+        const int x1 = x0 + lane;  // u2 + 1
+        unsigned b;
+        if (cache[k] != kUncached) {
+          b = (cache[k] >> (3 * (x0 >> 6))) & 7u;
+        } else {
+          unsigned b1;
+          row_bits2(A, Z, Y, x1, d2, b, b1);
         }
+        const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
+        long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
+        for (int a = 0; a < 3; ++a)
+          if ((b >> a) & 1u) B.edges[slot++] = (unsigned long long)(slot0 + 3ll * x1 + a);
+        off += __popcll(m0) + __popcll(m1) + __popcll(m2);
       }
     }
     W.next();
@@ -394,60 +454,46 @@ __device__ inline double voxel_grad(const float* __restrict__ field, long long s
   return g;
 }
 
+// One wave per voxel row: up to 256 voxels (four per lane) per step, with all
+// 28 loads of a step issued before any is used, so that a wave waits for
+// memory once per 256 voxels.
 __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const long long wrow0 = (long long)blockIdx.x * kRowsPerBlock + wid * kRowsPerWave;
-  if (wrow0 >= B.n_vrows) return;
-  int r = soft_roi_of_vrow(B.rois, B.n_rois, wrow0);
-  const SoftBwdRoi* R = B.rois + r;
-  long long lr = wrow0 - R->vrow_begin;
-  int w0 = (int)(lr / R->d[1]), w1 = (int)(lr % R->d[1]);
-  for (int k = 0; k < kRowsPerWave; ++k) {
-    if (wrow0 + k >= B.n_vrows) break;
-    const int* d = R->d;
-    const float* p = R->p;
-    const int d2 = d[2];
-    // slot of edge ((w0, w1, -1), axis 0); voxel x adds 3 (x + 1)
-    const long long slot_row = R->field_begin + 3ll * ((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d2 + 1);
-    const long long stride[3] = {3ll * (d[1] + 1) * (d2 + 1), 3ll * (d2 + 1), 3};
-    const RowPtr C = row_ptr(p, d, w0, w1), Zm = row_ptr(p, d, w0 - 1, w1), Zp = row_ptr(p, d, w0 + 1, w1),
-                 Ym = row_ptr(p, d, w0, w1 - 1), Yp = row_ptr(p, d, w0, w1 + 1);
-    float* grow = R->grad + ((size_t)w0 * d[1] + w1) * (size_t)d2;
-    for (int x0 = 0; x0 < d2; x0 += 128) {
-      // two voxels per lane, all fourteen loads issued together
-      float vc[2], nv[2][6];
+  constexpr int kV = 4;  // voxels per lane per step
+  const int lane = threadIdx.x & 63;
+  const long long vrow = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (vrow >= B.n_vrows) return;
+  const SoftBwdRoi* R = B.rois + soft_roi_of_vrow(B.rois, B.n_rois, vrow);
+  const int* d = R->d;
+  const float* p = R->p;
+  const int d2 = d[2];
+  const long long lr = vrow - R->vrow_begin;
+  const int w0 = (int)(lr / d[1]), w1 = (int)(lr % d[1]);
+  // slot of edge ((w0, w1, -1), axis 0); voxel x adds 3 (x + 1)
+  const long long slot_row = R->field_begin + 3ll * ((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d2 + 1);
+  const long long stride[3] = {3ll * (d[1] + 1) * (d2 + 1), 3ll * (d2 + 1), 3};
+  const RowPtr C = row_ptr(p, d, w0, w1), Zm = row_ptr(p, d, w0 - 1, w1), Zp = row_ptr(p, d, w0 + 1, w1),
+               Ym = row_ptr(p, d, w0, w1 - 1), Yp = row_ptr(p, d, w0, w1 + 1);
+  float* grow = R->grad + ((size_t)w0 * d[1] + w1) * (size_t)d2;
+  for (int x0 = 0; x0 < d2; x0 += 64 * kV) {
+    // lanes past the row end sit out (the wave's vote inside voxel_grad only
+    // counts active lanes); addresses are the uniform row bases plus x
+    float vc[kV], nv[kV][6];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int x = x0 + 64 * h + lane;
-        vc[h] = row_ld(C, x, d2);
-        nv[h][0] = row_ld(Zm, x, d2);
-        nv[h][1] = row_ld(Zp, x, d2);
-        nv[h][2] = row_ld(Ym, x, d2);
-        nv[h][3] = row_ld(Yp, x, d2);
-        nv[h][4] = row_ld(C, x - 1, d2);
-        nv[h][5] = row_ld(C, x + 1, d2);
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int x = x0 + 64 * h + lane;
-        // lanes past the row end take part (the wave votes inside) with no
-        // crossing edge and an in-range slot
-        if (x >= d2) {
-          vc[h] = 0.0f;
-#pragma unroll
-          for (int j = 0; j < 6; ++j) nv[h][j] = 0.0f;
-        }
-        const double g = voxel_grad(B.field, slot_row + 3ll * (min(x, d2 - 1) + 1), stride, vc[h], nv[h]);
-        if (x < d2) grow[x] = (float)g;
-      }
+    for (int h = 0; h < kV; ++h) {
+      const int x = min(x0 + 64 * h + lane, d2 - 1);
+      vc[h] = C.ptr[x];
+      nv[h][0] = row_in(Zm, x);
+      nv[h][1] = row_in(Zp, x);
+      nv[h][2] = row_in(Ym, x);
+      nv[h][3] = row_in(Yp, x);
+      const float xm = C.ptr[max(x - 1, 0)], xp = C.ptr[min(x + 1, d2 - 1)];
+      nv[h][4] = x > 0 ? xm : 0.0f;
+      nv[h][5] = x < d2 - 1 ? xp : 0.0f;
     }
-    // next voxel row
-    if (++w1 == d[1]) {
-      w1 = 0;
-      if (++w0 == d[0] && r + 1 < B.n_rois) {
-        R = B.rois + ++r;
-        w0 = 0;
-      }
+#pragma unroll
+    for (int h = 0; h < kV; ++h) {
+      const int x = x0 + 64 * h + lane;
+      if (x < d2) grow[x] = (float)voxel_grad(B.field, slot_row + 3ll * (x + 1), stride, vc[h], nv[h]);
     }
   }
 }
@@ -463,7 +509,7 @@ hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st) {
   if (g > gcap) g = gcap;
   if (g > 0) hipLaunchKernelGGL(k_soft_vertex_grad, dim3((unsigned)g), dim3(256), 0, st, B);
   if ((e = hipGetLastError())) return e;
-  const long long nv = (B.n_vrows + kRowsPerBlock - 1) / kRowsPerBlock;
+  const long long nv = (B.n_vrows + 3) / 4;  // four voxel rows (waves) per workgroup
   if (nv > 0) hipLaunchKernelGGL(k_soft_gather, dim3((unsigned)nv), dim3(256), 0, st, B);
   return hipGetLastError();
 }
