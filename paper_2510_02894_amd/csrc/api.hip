@@ -582,6 +582,14 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
   return SHAPE3D_OK;
 }
 
+// Magic numbers of the soft kernels' 32-bit division by D (numerators < 2^31).
+void magic_div(unsigned int D, unsigned int& m, int& sh) {
+  int k = 0;
+  while ((1ull << k) < D) ++k;  // ceil(log2 D)
+  sh = 31 + k;
+  m = (unsigned int)((1ull << sh) / D + 1);
+}
+
 void fill_saved(shape3d_soft_saved* saved, const int64_t dims[3], const double spacing[3], const RoiResult& raw,
                 int status) {
   for (int k = 0; k < 3; ++k) {
@@ -607,7 +615,7 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
   std::vector<SoftBwdRoi> table((size_t)n_rois);
-  long long n_rows = 0, n_vrows = 0, n_field = 0, cap = 0;
+  long long n_cblocks = 0, n_vblocks = 0, n_field = 0, cap = 0;
   for (int64_t r = 0; r < n_rois; ++r) {
     const shape3d_soft_saved& S = saved[r];
     for (int k = 0; k < 3; ++k)
@@ -636,15 +644,24 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
       R.pair_ids[f][0] = S.pair_ids[f][0];
       R.pair_ids[f][1] = S.pair_ids[f][1];
     }
-    R.row_begin = n_rows;
-    R.vrow_begin = n_vrows;
+    const long long ncube = (long long)(R.d[0] + 1) * (R.d[1] + 1) * (R.d[2] + 1);
+    const long long nvox = (long long)R.d[0] * R.d[1] * R.d[2];
+    if (ncube >= (1ll << 31)) return fail(SHAPE3D_EINVAL, "soft ROI too large for the backward pass (2^31 cubes)");
+    R.n_cubes = (unsigned int)ncube;
+    R.n_vox = (unsigned int)nvox;
+    magic_div((unsigned int)((R.d[1] + 1) * (R.d[2] + 1)), R.m_cplane, R.sh_cplane);
+    magic_div((unsigned int)(R.d[2] + 1), R.m_c2, R.sh_c2);
+    magic_div((unsigned int)(R.d[1] * R.d[2]), R.m_plane, R.sh_plane);
+    magic_div((unsigned int)R.d[2], R.m_d2, R.sh_d2);
     R.field_begin = n_field;
-    n_field += 3ll * (R.d[0] + 1) * (R.d[1] + 1) * (R.d[2] + 1);
-    n_rows += (long long)(R.d[0] + 1) * (R.d[1] + 1);
-    n_vrows += (long long)R.d[0] * R.d[1];
+    R.cblk_begin = n_cblocks;
+    R.vblk_begin = n_vblocks;
+    n_field += 3 * ncube;
+    n_cblocks += (ncube + 4095) / 4096;
+    n_vblocks += (nvox + 255) / 256;
     cap += S.n_vertices;
   }
-  if (n_rows / 32 > (1ll << 31) - 2 || n_vrows / 4 > (1ll << 31) - 2) return fail(SHAPE3D_EINVAL, "batch too large");
+  if (n_cblocks > (1ll << 31) - 2 || n_vblocks > (1ll << 31) - 2) return fail(SHAPE3D_EINVAL, "batch too large");
   const size_t tbytes = sizeof(SoftBwdRoi) * (size_t)n_rois;
   if ((rc = ensure(w, w.soft_rois, tbytes))) return rc;
   if ((rc = ensure(w, w.soft_edges, sizeof(unsigned long long) * std::max<long long>(cap, 1)))) return rc;
@@ -658,8 +675,8 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   SoftBwdBufs B;
   B.rois = (const SoftBwdRoi*)w.soft_rois.p;
   B.n_rois = (int)n_rois;
-  B.n_rows = n_rows;
-  B.n_vrows = n_vrows;
+  B.n_cblocks = n_cblocks;
+  B.n_vblocks = n_vblocks;
   B.cap = cap;
   B.edges = (unsigned long long*)w.soft_edges.p;
   B.field = (float*)w.soft_field.p;

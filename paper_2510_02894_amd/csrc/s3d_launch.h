@@ -94,11 +94,11 @@ struct PairBufs {
 };
 
 // soft.hip: adjoint of the soft-mask forward pass, for a table of ROIs.
-// Rows: a "padded row" is a cube row (u0, u1) with u0 in [-1, d0-1], u1 in
-// [-1, d1-1]; a "voxel row" is (w0, w1) in [0, d0) x [0, d1).  Both are
-// numbered globally, ROI after ROI.  The edge field has one slot per grid
-// edge (u, u + e_a), u in [-1, d-1]^3: slot field_begin + 3 * cube(u) + a with
-// cube(u) = ((u0 + 1) (d1 + 1) + u1 + 1) (d2 + 1) + u2 + 1.
+// Cubes u in [-1, d-1]^3 have the flat index cube(u) = ((u0 + 1) (d1 + 1) +
+// u1 + 1) (d2 + 1) + u2 + 1; grid edge (u, u + e_a) has the edge-field slot
+// field_begin + 3 cube(u) + a.  Local indices are below 2^31 (checked on the
+// host), so the kernels divide with 32-bit magic numbers: floor(n / D) =
+// (n * m) >> sh with sh = 31 + ceil(log2 D) and m = floor(2^sh / D) + 1.
 struct SoftBwdRoi {
   const float* p;             // the ROI's probabilities (d0, d1, d2)
   float* grad;                // dL/dp, same layout
@@ -110,16 +110,20 @@ struct SoftBwdRoi {
   double g_vol_signed;        // dL/dMeshVolume * sign(signed volume)
   double gdiam[4];            // dL/dD_f / D_f (0 if the feature has no pair)
   long long pair_ids[4][2];   // canonical ids of the maximising pairs, -1 if none
-  long long row_begin;        // first global padded row
-  long long vrow_begin;       // first global voxel row
   long long field_begin;      // first slot of the ROI in the edge field
+  long long cblk_begin;       // first workgroup of the edge pass
+  long long vblk_begin;       // first workgroup of the gather pass
+  unsigned int n_cubes;       // (d0 + 1)(d1 + 1)(d2 + 1)
+  unsigned int n_vox;         // d0 d1 d2
+  unsigned int m_cplane, m_c2, m_plane, m_d2;  // magic numbers for (d1+1)(d2+1), d2+1, d1 d2, d2
+  int sh_cplane, sh_c2, sh_plane, sh_d2;
 };
 
 struct SoftBwdBufs {
   const SoftBwdRoi* rois;     // [n_rois], DEVICE
   int n_rois;
-  long long n_rows;           // padded rows of all ROIs
-  long long n_vrows;          // voxel rows of all ROIs
+  long long n_cblocks;        // workgroups of the edge pass
+  long long n_vblocks;        // workgroups of the gather pass
   long long cap;              // crossing-edge capacity (the forward pass's vertex count)
   unsigned long long* edges;  // [cap] edge-field slots of the crossing edges
   float* field;               // edge field: (dL/dx_v)_a * s_a at crossing edges (other slots unused)

@@ -133,246 +133,98 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
   }
 }
 
-constexpr int kRowsPerWave = 8;
-constexpr int kRowsPerBlock = 4 * kRowsPerWave;
+constexpr int kCubeBlock = 4096;   // cubes per workgroup of the edge pass (16 per thread)
+constexpr int kVoxBlock = 256;     // voxels per workgroup of the gather pass (1 per thread)
 
-// Last ROI whose first padded row (voxel row) is <= row.
-__device__ inline int soft_roi_of_row(const SoftBwdRoi* r, int n, long long row) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (r[mid].row_begin <= row)
-      lo = mid;
-    else
-      hi = mid - 1;
+// floor(n / d) for n < 2^31 with the ROI's precomputed (m, sh): (n * m) >> sh.
+__device__ inline unsigned int fdiv(unsigned int n, unsigned int m, int sh) {
+  return (unsigned int)(((unsigned long long)n * m) >> sh);
+}
+
+// Last ROI whose first element of the given kind is <= x.
+#define S3D_SOFT_ROI_SEARCH(name, member)                                   \
+  __device__ inline int name(const SoftBwdRoi* r, int n, long long x) {     \
+    int lo = 0, hi = n - 1;                                                  \
+    while (lo < hi) {                                                        \
+      const int mid = (lo + hi + 1) >> 1;                                    \
+      if (r[mid].member <= x)                                                \
+        lo = mid;                                                            \
+      else                                                                   \
+        hi = mid - 1;                                                        \
+    }                                                                        \
+    return lo;                                                               \
   }
-  return lo;
-}
+S3D_SOFT_ROI_SEARCH(soft_roi_of_cblk, cblk_begin)
+S3D_SOFT_ROI_SEARCH(soft_roi_of_vblk, vblk_begin)
+S3D_SOFT_ROI_SEARCH(soft_roi_of_slot, field_begin)
+#undef S3D_SOFT_ROI_SEARCH
 
-__device__ inline int soft_roi_of_vrow(const SoftBwdRoi* r, int n, long long vrow) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (r[mid].vrow_begin <= vrow)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// A voxel row (z, y) of a ROI: its first element and whether it lies inside
-// the array (an outside row reads row 0 and reports 0: the zero pad).
-struct RowPtr {
-  const float* ptr;
-  bool ok;
-};
-
-__device__ inline RowPtr row_ptr(const float* p, const int* d, int z, int y) {
-  const bool ok = (unsigned)z < (unsigned)d[0] && (unsigned)y < (unsigned)d[1];
-  return {p + ((size_t)(ok ? z : 0) * d[1] + (ok ? y : 0)) * (size_t)d[2], ok};
-}
-
-// Element x in [0, d2) of a row, 0 if the row is outside the array (its
-// pointer then addresses row 0, so the load is always in range).
-__device__ inline float row_in(const RowPtr& r, int x) {
-  const float v = r.ptr[x];
-  return r.ok ? v : 0.0f;
-}
-
-// Element x of a row, 0 outside; the load is always issued at a clamped address.
-__device__ inline float row_ld(const RowPtr& r, int x, int d2) {
-  const float v = r.ptr[min(max(x, 0), d2 - 1)];
-  return r.ok && (unsigned)x < (unsigned)d2 ? v : 0.0f;
-}
-
-__device__ inline int soft_roi_of_slot(const SoftBwdRoi* r, int n, long long slot) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (r[mid].field_begin <= slot)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// Bit a set iff the edge (u, u + e_a) crosses the 0.5 level; A, Z, Y are the
-// rows (u0, u1), (u0 + 1, u1), (u0, u1 + 1).
-__device__ inline unsigned crossing_bits(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int u2, int d2) {
-  const float va = row_ld(A, u2, d2), vz = row_ld(Z, u2, d2), vy = row_ld(Y, u2, d2), vx = row_ld(A, u2 + 1, d2);
-  const bool c = va > 0.5f;
-  return (unsigned)((vz > 0.5f) != c) | ((unsigned)((vy > 0.5f) != c) << 1) | ((unsigned)((vx > 0.5f) != c) << 2);
-}
-
-// Walks consecutive padded rows (u0, u1) of the ROI table: one ROI lookup
-// and one division per wave, then increments.
-struct PaddedRowWalk {
-  const SoftBwdRoi* rois;
-  int n, r;
-  const SoftBwdRoi* R;
-  int u0, u1;
-
-  __device__ void start(const SoftBwdRoi* rs, int nr, long long row) {
-    rois = rs;
-    n = nr;
-    r = soft_roi_of_row(rs, nr, row);
-    R = rs + r;
-    const long long lr = row - R->row_begin;
-    u0 = (int)(lr / (R->d[1] + 1)) - 1;
-    u1 = (int)(lr % (R->d[1] + 1)) - 1;
-  }
-  __device__ void next() {
-    if (++u1 == R->d[1]) {
-      u1 = -1;
-      if (++u0 == R->d[0] && r + 1 < n) {
-        R = rois + ++r;
-        u0 = -1;
-      }
-    }
-  }
-};
-
-// Crossing bits of the cubes u2 = x1 - 1 and x1 + 63 of a padded row (two
-// chunks of 64 cubes per step, all eight loads issued together); 0 past the row.
-__device__ inline void row_bits2(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int x1, int d2, unsigned& b0,
-                                 unsigned& b1) {
-  b0 = crossing_bits(A, Z, Y, x1 - 1, d2);
-  b1 = crossing_bits(A, Z, Y, x1 + 63, d2);
-  b0 = x1 <= d2 ? b0 : 0u;
-  b1 = x1 + 64 <= d2 ? b1 : 0u;
-}
-
-// Crossing bits of every cube of a padded row with at most 64 * NC cubes:
-// chunk c (cubes u2 = 64c - 1 + lane) in bits 3c .. 3c + 2 of the result.
-// Chunks past the row end are skipped (a uniform branch); the loads of the
-// others are all issued before any is used.
-template <int NC>
-__device__ inline uint32_t row_bits_all(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int lane, int d2) {
-  float va[NC], vz[NC], vy[NC], vx[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    if (64 * c > d2) break;
-    const int x1 = min(64 * c + lane, d2);  // u2 + 1
-    const int i0 = max(x1 - 1, 0), i1 = min(x1, d2 - 1);
-    va[c] = A.ptr[i0];
-    vz[c] = Z.ptr[i0];
-    vy[c] = Y.ptr[i0];
-    vx[c] = A.ptr[i1];
-  }
-  uint32_t out = 0u;
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    if (64 * c > d2) break;
-    const int x1 = 64 * c + lane;
-    const bool lo_ok = x1 >= 1, hi_ok = x1 <= d2 - 1;  // voxels u2 and u2 + 1 inside the row
-    const bool in = A.ok && lo_ok && va[c] > 0.5f;
-    const bool iz = Z.ok && lo_ok && vz[c] > 0.5f;
-    const bool iy = Y.ok && lo_ok && vy[c] > 0.5f;
-    const bool ix = A.ok && hi_ok && vx[c] > 0.5f;
-    const uint32_t b = (uint32_t)(iz != in) | ((uint32_t)(iy != in) << 1) | ((uint32_t)(ix != in) << 2);
-    out |= (x1 <= d2 ? b : 0u) << (3 * c);
-  }
-  return out;
-}
-
-// Cached crossing bits of a row (see row_bits_all), or kUncached for rows of
-// more than 512 cubes, whose bits are recomputed chunk by chunk.
-constexpr uint32_t kUncached = 0x80000000u;
-
-__device__ inline uint32_t row_bits_cached(const RowPtr& A, const RowPtr& Z, const RowPtr& Y, int lane, int d2) {
-  if (d2 + 1 <= 256) return row_bits_all<4>(A, Z, Y, lane, d2);
-  if (d2 + 1 <= 512) return row_bits_all<8>(A, Z, Y, lane, d2);
-  return kUncached;
-}
-
+// Pass 1.  A workgroup takes kCubeBlock consecutive cubes (flat index l over
+// [-1, d-1]^3, the cube's edge-field index) of one ROI, 16 per thread; the
+// crossing edges are counted, room is reserved with one atomic per workgroup
+// and their field slots written in (thread, cube, axis) order.
 __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
-  __shared__ int cnt[kRowsPerBlock];
-  __shared__ long long pre[kRowsPerBlock];
+  constexpr int kPer = kCubeBlock / 256;
+  __shared__ int s_scan[4];
   __shared__ long long base_sh;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const long long row0 = (long long)blockIdx.x * kRowsPerBlock;
-  const long long wrow0 = row0 + wid * kRowsPerWave;
-  // pass 1: crossing edges per row; the bits of short rows stay in registers
-  uint32_t cache[kRowsPerWave];
-  {
-    PaddedRowWalk W;
-    if (wrow0 < B.n_rows) W.start(B.rois, B.n_rois, wrow0);
+  const SoftBwdRoi* R = B.rois + soft_roi_of_cblk(B.rois, B.n_rois, blockIdx.x);
+  const int* d = R->d;
+  const float* p = R->p;
+  const unsigned int l0 = (unsigned int)(blockIdx.x - R->cblk_begin) * kCubeBlock + threadIdx.x;
+  const unsigned int plane = (unsigned int)d[1] * d[2];
+  unsigned long long bits = 0ull;  // 3 bits per cube k
 #pragma unroll
-    for (int k = 0; k < kRowsPerWave; ++k) {
-      const long long row = wrow0 + k;
-      int c = 0;
-      cache[k] = 0u;
-      if (row < B.n_rows) {
-        const SoftBwdRoi* R = W.R;
-        const int d2 = R->d[2];
-        const RowPtr A = row_ptr(R->p, R->d, W.u0, W.u1), Z = row_ptr(R->p, R->d, W.u0 + 1, W.u1),
-                     Y = row_ptr(R->p, R->d, W.u0, W.u1 + 1);
-        cache[k] = row_bits_cached(A, Z, Y, lane, d2);
-        if (cache[k] != kUncached) {
-          c = wave_sum(__popc(cache[k]));
-        } else {
-          for (int x0 = 0; x0 <= d2; x0 += 128) {
-            unsigned b0, b1;
-            row_bits2(A, Z, Y, x0 + lane, d2, b0, b1);
-            c += __popc(b0) + __popc(b1);
-          }
-          c = wave_sum(c);
-        }
-        W.next();
-      }
-      if (lane == 0) cnt[wid * kRowsPerWave + k] = c;
+  for (int h = 0; h < kPer; h += 8) {
+    float v[8][4];
+    bool ok[8][4];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const unsigned int l = l0 + 256u * (h + k);
+      const unsigned int c0 = fdiv(l, R->m_cplane, R->sh_cplane);
+      const unsigned int r = l - c0 * (unsigned int)((d[1] + 1) * (d[2] + 1));
+      const unsigned int c1 = fdiv(r, R->m_c2, R->sh_c2);
+      const int u0 = (int)c0 - 1, u1 = (int)c1 - 1, u2 = (int)(r - c1 * (unsigned int)(d[2] + 1)) - 1;
+      const bool in_rng = l < R->n_cubes;
+      const bool lo0 = u0 >= 0, lo1 = u1 >= 0, lo2 = u2 >= 0;
+      // voxel index of u, with each coordinate clamped to 0 (the +axis
+      // neighbours below step from it; a clamped axis means that neighbour
+      // is the voxel at 0 on that axis)
+      const unsigned int iv = in_rng ? ((unsigned int)max(u0, 0) * d[1] + max(u1, 0)) * d[2] + max(u2, 0) : 0u;
+      ok[k][0] = in_rng && lo0 && lo1 && lo2;
+      ok[k][1] = in_rng && u0 + 1 < d[0] && lo1 && lo2;
+      ok[k][2] = in_rng && lo0 && u1 + 1 < d[1] && lo2;
+      ok[k][3] = in_rng && lo0 && lo1 && u2 + 1 < d[2];
+      // neighbours along +axis: +plane, +d2, +1 (clamped to iv when outside)
+      v[k][0] = p[iv];
+      v[k][1] = p[ok[k][1] ? iv + plane - (lo0 ? 0u : plane) : 0u];
+      v[k][2] = p[ok[k][2] ? iv + (unsigned int)d[2] - (lo1 ? 0u : (unsigned int)d[2]) : 0u];
+      v[k][3] = p[ok[k][3] ? iv + 1u - (lo2 ? 0u : 1u) : 0u];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool c = ok[k][0] && v[k][0] > 0.5f;
+      const unsigned long long b = (unsigned long long)((ok[k][1] && v[k][1] > 0.5f) != c) |
+                                   ((unsigned long long)((ok[k][2] && v[k][2] > 0.5f) != c) << 1) |
+                                   ((unsigned long long)((ok[k][3] && v[k][3] > 0.5f) != c) << 2);
+      bits |= (l0 + 256u * (h + k) < R->n_cubes ? b : 0ull) << (3 * (h + k));
     }
   }
-  __syncthreads();
+  int total;
+  const int off = block_excl_scan256(__popcll(bits), s_scan, total);
   if (threadIdx.x == 0) {
-    long long tot = 0;
-    for (int i = 0; i < kRowsPerBlock; ++i) {
-      pre[i] = tot;
-      tot += cnt[i];
-    }
     long long base = 0;
-    if (tot > 0) base = (long long)atomicAdd((unsigned long long*)B.counters, (unsigned long long)tot);
-    base_sh = base + tot <= B.cap ? base : -1;  // -1: no room (the input differs from the forward pass)
+    if (total > 0) base = (long long)atomicAdd((unsigned long long*)B.counters, (unsigned long long)total);
+    base_sh = base + total <= B.cap ? base : -1;  // -1: no room (the input differs from the forward pass)
   }
   __syncthreads();
   const long long base = base_sh;
-  if (base < 0 || wrow0 >= B.n_rows) return;
-  // pass 2: write the rows' edges (field slots), in (row, u2, a) order
-  PaddedRowWalk W;
-  W.start(B.rois, B.n_rois, wrow0);
-  const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll
-  for (int k = 0; k < kRowsPerWave; ++k) {
-    const int li = wid * kRowsPerWave + k;
-    const long long row = wrow0 + k;
-    if (row >= B.n_rows) break;
-    if (cnt[li] != 0) {
-      const SoftBwdRoi* R = W.R;
-      const int d2 = R->d[2];
-      const RowPtr A = row_ptr(R->p, R->d, W.u0, W.u1), Z = row_ptr(R->p, R->d, W.u0 + 1, W.u1),
-                   Y = row_ptr(R->p, R->d, W.u0, W.u1 + 1);
-      long long off = base + pre[li];
-      // slot of cube (u0, u1, -1) of this row: the row's local index times d2 + 1
-      const long long slot0 = R->field_begin + 3ll * (row - R->row_begin) * (d2 + 1);
-      for (int x0 = 0; x0 <= d2; x0 += 64) {
-        const int x1 = x0 + lane;  // u2 + 1
-        unsigned b;
-        if (cache[k] != kUncached) {
-          b = (cache[k] >> (3 * (x0 >> 6))) & 7u;
-        } else {
-          unsigned b1;
-          row_bits2(A, Z, Y, x1, d2, b, b1);
-        }
-        const unsigned long long m0 = __ballot(b & 1u), m1 = __ballot(b & 2u), m2 = __ballot(b & 4u);
-        long long slot = off + __popcll(m0 & below) + __popcll(m1 & below) + __popcll(m2 & below);
-        for (int a = 0; a < 3; ++a)
-          if ((b >> a) & 1u) B.edges[slot++] = (unsigned long long)(slot0 + 3ll * x1 + a);
-        off += __popcll(m0) + __popcll(m1) + __popcll(m2);
-      }
-    }
-    W.next();
+  if (base < 0) return;
+  long long slot = base + off;
+  while (bits) {
+    const int i = __ffsll((long long)bits) - 1;
+    bits &= bits - 1ull;
+    const int k = i / 3, a = i - 3 * k;
+    B.edges[slot++] = (unsigned long long)(R->field_begin + 3ll * (l0 + 256u * k) + a);
   }
 }
 
@@ -454,63 +306,53 @@ __device__ inline double voxel_grad(const float* __restrict__ field, long long s
   return g;
 }
 
-// One wave per voxel row: up to 256 voxels (four per lane) per step, with all
-// 28 loads of a step issued before any is used, so that a wave waits for
-// memory once per 256 voxels.
+// Pass 3.  One thread per voxel (flat index over the ROI, 256 per workgroup),
+// all seven loads issued together; the voxel's crossing edges read their
+// values from the edge field and dL/dp is written densely.
 __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
-  constexpr int kV = 4;  // voxels per lane per step
-  const int lane = threadIdx.x & 63;
-  const long long vrow = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (vrow >= B.n_vrows) return;
-  const SoftBwdRoi* R = B.rois + soft_roi_of_vrow(B.rois, B.n_rois, vrow);
+  const SoftBwdRoi* R = B.rois + soft_roi_of_vblk(B.rois, B.n_rois, blockIdx.x);
+  const unsigned int l = (unsigned int)(blockIdx.x - R->vblk_begin) * kVoxBlock + threadIdx.x;
+  if (l >= R->n_vox) return;
   const int* d = R->d;
   const float* p = R->p;
-  const int d2 = d[2];
-  const long long lr = vrow - R->vrow_begin;
-  const int w0 = (int)(lr / d[1]), w1 = (int)(lr % d[1]);
-  // slot of edge ((w0, w1, -1), axis 0); voxel x adds 3 (x + 1)
-  const long long slot_row = R->field_begin + 3ll * ((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d2 + 1);
-  const long long stride[3] = {3ll * (d[1] + 1) * (d2 + 1), 3ll * (d2 + 1), 3};
-  const RowPtr C = row_ptr(p, d, w0, w1), Zm = row_ptr(p, d, w0 - 1, w1), Zp = row_ptr(p, d, w0 + 1, w1),
-               Ym = row_ptr(p, d, w0, w1 - 1), Yp = row_ptr(p, d, w0, w1 + 1);
-  float* grow = R->grad + ((size_t)w0 * d[1] + w1) * (size_t)d2;
-  for (int x0 = 0; x0 < d2; x0 += 64 * kV) {
-    // lanes past the row end sit out (the wave's vote inside voxel_grad only
-    // counts active lanes); addresses are the uniform row bases plus x
-    float vc[kV], nv[kV][6];
-#pragma unroll
-    for (int h = 0; h < kV; ++h) {
-      const int x = min(x0 + 64 * h + lane, d2 - 1);
-      vc[h] = C.ptr[x];
-      nv[h][0] = row_in(Zm, x);
-      nv[h][1] = row_in(Zp, x);
-      nv[h][2] = row_in(Ym, x);
-      nv[h][3] = row_in(Yp, x);
-      const float xm = C.ptr[max(x - 1, 0)], xp = C.ptr[min(x + 1, d2 - 1)];
-      nv[h][4] = x > 0 ? xm : 0.0f;
-      nv[h][5] = x < d2 - 1 ? xp : 0.0f;
-    }
-#pragma unroll
-    for (int h = 0; h < kV; ++h) {
-      const int x = x0 + 64 * h + lane;
-      if (x < d2) grow[x] = (float)voxel_grad(B.field, slot_row + 3ll * (x + 1), stride, vc[h], nv[h]);
-    }
-  }
+  const unsigned int plane = (unsigned int)d[1] * d[2];
+  const unsigned int w0 = fdiv(l, R->m_plane, R->sh_plane);
+  const unsigned int r = l - w0 * plane;
+  const unsigned int w1 = fdiv(r, R->m_d2, R->sh_d2);
+  const unsigned int x = r - w1 * (unsigned int)d[2];
+  const bool zm = w0 > 0, zp = w0 + 1 < (unsigned int)d[0], ym = w1 > 0, yp = w1 + 1 < (unsigned int)d[1];
+  const bool xm = x > 0, xp = x + 1 < (unsigned int)d[2];
+  float nv[6];
+  const float vc = p[l];
+  nv[0] = p[zm ? l - plane : l];
+  nv[1] = p[zp ? l + plane : l];
+  nv[2] = p[ym ? l - d[2] : l];
+  nv[3] = p[yp ? l + d[2] : l];
+  nv[4] = p[xm ? l - 1 : l];
+  nv[5] = p[xp ? l + 1 : l];
+  nv[0] = zm ? nv[0] : 0.0f;
+  nv[1] = zp ? nv[1] : 0.0f;
+  nv[2] = ym ? nv[2] : 0.0f;
+  nv[3] = yp ? nv[3] : 0.0f;
+  nv[4] = xm ? nv[4] : 0.0f;
+  nv[5] = xp ? nv[5] : 0.0f;
+  // field slot of edge (w, axis 0): 3 * cube(w)
+  const long long cube = ((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d[2] + 1) + (x + 1);
+  const long long stride[3] = {3ll * (d[1] + 1) * (d[2] + 1), 3ll * (d[2] + 1), 3};
+  R->grad[l] = (float)voxel_grad(B.field, R->field_begin + 3ll * cube, stride, vc, nv);
 }
 
 hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st) {
   hipError_t e;
   if ((e = launch_fill_i64(B.counters, 0, 1, st))) return e;
-  const long long nb = (B.n_rows + kRowsPerBlock - 1) / kRowsPerBlock;
-  if (nb > 0) hipLaunchKernelGGL(k_soft_edges, dim3((unsigned)nb), dim3(256), 0, st, B);
+  if (B.n_cblocks > 0) hipLaunchKernelGGL(k_soft_edges, dim3((unsigned)B.n_cblocks), dim3(256), 0, st, B);
   if ((e = hipGetLastError())) return e;
   long long g = (B.cap + 255) / 256;
   const long long gcap = (long long)B.cu_count * 16;
   if (g > gcap) g = gcap;
   if (g > 0) hipLaunchKernelGGL(k_soft_vertex_grad, dim3((unsigned)g), dim3(256), 0, st, B);
   if ((e = hipGetLastError())) return e;
-  const long long nv = (B.n_vrows + 3) / 4;  // four voxel rows (waves) per workgroup
-  if (nv > 0) hipLaunchKernelGGL(k_soft_gather, dim3((unsigned)nv), dim3(256), 0, st, B);
+  if (B.n_vblocks > 0) hipLaunchKernelGGL(k_soft_gather, dim3((unsigned)B.n_vblocks), dim3(256), 0, st, B);
   return hipGetLastError();
 }
 
