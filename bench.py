@@ -329,6 +329,7 @@ def main():
     ap.add_argument("--batch-rois", type=int, default=4096)
     ap.add_argument("--skip-batched-soft", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pair-pass tiles")
+    ap.add_argument("--skip-single", action="store_true")
     ap.add_argument("--soft-rois", type=int, default=256)
     ap.add_argument("--skip-large", action="store_true",
                     help="only the batched / differentiable sections (for profiling them)")
@@ -413,7 +414,7 @@ def main():
     mesh = {"bound": "hbm", "achieved": mesh_bytes / t_mesh / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": mesh_bytes / t_mesh / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic("k_mesh_count")}
 
-    single = bench_single_roi(args, S)
+    single = None if args.skip_single else bench_single_roi(args, S)
     batched = None if args.skip_batched else bench_batched(args, S)
     differentiable = None if args.skip_differentiable else bench_differentiable(args, S)
     batched_soft = None if args.skip_batched_soft else bench_batched_soft(args, S)

@@ -225,7 +225,8 @@ int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, in
  *                  1 = FP32-accurate Gram values from coordinates split into
  *                  two f16 parts on the 32x32x16 f16 matrix cores.  Both are
  *                  followed by the same exact FP64 refinement.
- * The setting is process-wide (all devices); the default is {8, 256, 0, 0}.
+ * The setting is process-wide (all devices); the default is {8, 512, 0, 1}
+ * (the autotuner's choice on every workload measured).
  *
  * shape3d_get_tuning / shape3d_set_tuning -- read or replace the setting
  * (HOST struct).  Setting drops the graphs recorded by shape3d_batched.

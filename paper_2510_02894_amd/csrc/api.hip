@@ -84,7 +84,7 @@ struct Workspace {
 std::map<int, Workspace*> g_ws;
 
 // Tile sizes of the pair pass for every device (results do not depend on them).
-Tuning g_tune = {8, 256, 0, 0};
+Tuning g_tune = {8, 512, 0, 1};
 
 bool valid_tuning(const Tuning& t) {
   return (t.itile == 2 || t.itile == 4 || t.itile == 8) &&

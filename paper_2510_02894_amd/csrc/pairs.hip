@@ -78,6 +78,8 @@ __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __res
 // group served by one atomic of its leader; the groups are found first (ALU
 // only) and then all leaders issue their atomics together, so a wave waits
 // for one atomic round trip however many distinct buckets its lanes hit.
+// (Per-lane atomics are slower: lanes of a wave often share a bucket, and
+// colliding returning atomics serialise in memory.)
 template <bool want_old>
 __device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b) {
   unsigned long long todo = __ballot(1);
@@ -147,34 +149,40 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
 // Segments of the buckets: pad rows, block tags and the segment table.
 __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long long nb,
                               const long long* __restrict__ totals,
-                             const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
-                             const long long* __restrict__ brow, const long long* __restrict__ bseg,
-                             float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax,
-                             int* __restrict__ blkseg, Seg* __restrict__ segs, long long* __restrict__ pairs2d) {
+                              const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
+                              const long long* __restrict__ brow, const long long* __restrict__ bseg,
+                              float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax,
+                              int* __restrict__ blkseg, Seg* __restrict__ segs, long long* __restrict__ pairs2d) {
+  // one wave per bucket: its lanes tag the blocks and fill the pad rows
   const long long rows0 = totals[T_ROWS0];
-  for (long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += (long long)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long b = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < nb; b += nwaves) {
     const unsigned int c = bcnt[b];
     if (c < 2) continue;
-    int axis;
-    const int roi = bucket_roi(rois, n_rois, b, axis);
-    atomicAdd((unsigned long long*)&pairs2d[roi], (unsigned long long)c * (c - 1) / 2);
     const long long sid = n_rois + bseg[b];
     const long long r0 = rows0 + brow[b];
     const long long n = bsz[b];
-    Seg S;
-    S.row_begin = r0;
-    S.n_rows = (int)n;
-    S.group = roi * 4 + 1 + axis;
-    segs[sid] = S;
-    for (long long i = 0; i < n / kBlk; ++i) blkseg[r0 / kBlk + i] = (int)sid;
+    if (lane == 0) {
+      int axis;
+      const int roi = bucket_roi(rois, n_rois, b, axis);
+      atomicAdd((unsigned long long*)&pairs2d[roi], (unsigned long long)c * (c - 1) / 2);
+      Seg S;
+      S.row_begin = r0;
+      S.n_rows = (int)n;
+      S.group = roi * 4 + 1 + axis;
+      segs[sid] = S;
+    }
+    for (long long i = lane; i < n / kBlk; i += 64) blkseg[r0 / kBlk + i] = (int)sid;
     const float* src = pos + (r0 >> 4) * 64 + (r0 & 15);
+    const float sx = src[0], sy = src[16], sz = src[32], sw = src[48];
     const int o = orig[r0];
-    for (long long row = r0 + c; row < r0 + n; ++row) {
+    for (long long row = r0 + c + lane; row < r0 + n; row += 64) {
       float* dst = pos + (row >> 4) * 64 + (row & 15);
-      dst[0] = src[0];
-      dst[16] = src[16];
-      dst[32] = src[32];
-      dst[48] = src[48];
+      dst[0] = sx;
+      dst[16] = sy;
+      dst[32] = sz;
+      dst[48] = sw;
       orig[row] = o;
       rowmax[row] = 0.0f;
     }
@@ -768,7 +776,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
                      B.totals, B.bcnt, B.bcur, B.brow, B.pos, B.orig, B.rowmax);
-  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
+  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs, B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.ncol, B.tune.jchunk);

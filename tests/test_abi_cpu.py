@@ -99,7 +99,7 @@ def test_tuning_setting_is_validated_without_a_device():
     if not os.path.exists(S.LIB_PATH):
         pytest.skip("library not built")
     before = S.get_tuning()
-    assert before == (8, 256, 0, 0)
+    assert before == (8, 512, 0, 1)
     for bad in [(3, 256, 0, 0), (8, 100, 0, 0), (8, 256, -1, 0), (8, 256, 65, 0), (16, 256, 0, 0), (2, 256, 0, 1),
                 (8, 256, 0, 2)]:
         with pytest.raises(S.Shape3DError) as ei:
