@@ -75,7 +75,8 @@ typedef struct {
   int64_t pairs_2d;        /* sum over planes of n*(n-1)/2 */
   int64_t candidates[4];   /* rows re-examined in FP64 per diameter */
   float ms[8];             /* device time per phase (ms), filled when timing != 0:
-                              0 mesh count, 1 mesh emit, 2 plane bucketing, 3 pair maxima (MFMA),
+                              0 mesh count, 1 mesh emit, 2 plane bucketing (and split-f16 operands),
+                              3 pair maxima (MFMA),
                               4 exact refinement, 5 finalisation, 6 whole call, 7 reserved */
 } shape3d_stats;
 

@@ -383,6 +383,7 @@ int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStr
                          (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   if (ev) HIPCK(hipEventRecord(ev[1], st));
   HIPCK(launch_buckets(B, st));
+  HIPCK(launch_pack_operands(B, st));
   HIPCK(launch_init_groups(B, st));
   HIPCK(launch_fill_u32(B.counters, 0u, 2, st));
   if (ev) HIPCK(hipEventRecord(ev[2], st));

@@ -802,12 +802,16 @@ hipError_t launch_pair_maxima_it(const PairBufs& B, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_pack_operands(const PairBufs& B, hipStream_t st) {
+  if (B.tune.kernel != 1) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_h, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.pos, B.blkseg, B.segs, B.meta,
+                     B.totals, B.posh);
+  return hipGetLastError();
+}
+
 template <int IT>
 hipError_t launch_pair_maxima_h(const PairBufs& B, hipStream_t st) {
   hipError_t e;
-  hipLaunchKernelGGL(k_pack_h, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.pos, B.blkseg, B.segs, B.meta,
-                     B.totals, B.posh);
-  if ((e = hipGetLastError())) return e;
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_maxima_h<IT>, 256, 0))) return e;
   if (per_cu < 1) per_cu = 1;

@@ -135,6 +135,7 @@ hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 
 // pairs.hip
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list
+hipError_t launch_pack_operands(const PairBufs& B, hipStream_t st); // split-f16 operands (kernel 1 only)
 hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass over the work list
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset per-group results
 hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
