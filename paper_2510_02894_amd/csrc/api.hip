@@ -54,7 +54,10 @@ struct GraphRec {
   long long generation = -1;
   RoiResult* host_res = nullptr;  // pinned, written by the graph's last copy
   long long n_rois = 0;
+  long long stamp = 0;            // last use (the least recently used graph is dropped first)
 };
+
+constexpr size_t kMaxGraphs = 64;  // recorded batch layouts kept per device
 
 struct Workspace {
   int device = -1;
@@ -72,6 +75,7 @@ struct Workspace {
   long long rows0_cap = 0;  // layout-0 rows the vertex buffers were sized for
   long long last_rows0 = 0;  // layout-0 rows of the last eager run (a recorded graph is sized for them)
   std::map<std::string, GraphRec> graphs;
+  long long stamp = 0;
 
   std::vector<Buf*> all() {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
@@ -555,11 +559,20 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
         if (hres[r].status < 0) done = false;  // capacity exceeded on new contents: run eagerly
     }
   }
+  if (done) w.graphs[sig].stamp = ++w.stamp;
   if (!done) {
     RoiResult* eager = host_results(w, Bt);
     if ((rc = run_eager(w, Bt, dtype, st, eager, 0, nullptr))) return rc;
     hres = eager;
     if (use_graph) {
+      while (w.graphs.size() >= kMaxGraphs) {  // drop the least recently used graph
+        auto lru = w.graphs.begin();
+        for (auto g = w.graphs.begin(); g != w.graphs.end(); ++g)
+          if (g->second.stamp < lru->second.stamp) lru = g;
+        if (lru->second.exec) (void)hipGraphExecDestroy(lru->second.exec);
+        if (lru->second.host_res) (void)hipHostFree(lru->second.host_res);
+        w.graphs.erase(lru);
+      }
       auto old = w.graphs.find(sig);
       if (old != w.graphs.end()) {
         if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
@@ -574,6 +587,7 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
         if (rec.host_res) (void)hipHostFree(rec.host_res);
         return rc;
       }
+      rec.stamp = ++w.stamp;
       w.graphs.emplace(sig, rec);
     }
   }

@@ -78,9 +78,11 @@ __device__ inline double sel8(const double* v, int k) {
 }
 
 // Position (relative to o) of the vertex on cube edge e of the cube with min
-// corner (c0, c1, c2) and corner values pc.
+// corner (c0, c1, c2) and corner values pc.  Edge e = 4 axis + 2 o_b + o_c runs
+// from corner k0 (bits dz dy dx) along its axis.
 __device__ inline D3 cube_vertex(const double* pc, int e, int c0, int c1, int c2, const double* s, const double* o) {
-  const int ea = MC_EDGE_AXIS[e], k0 = MC_EDGE_C0[e];
+  const int ea = e >> 2;
+  const int k0 = ea == 0 ? (e & 3) : (ea == 1 ? 4 * ((e >> 1) & 1) + (e & 1) : 4 * ((e >> 1) & 1) + 2 * (e & 1));
   const int k1 = k0 | (4 >> ea);
   const double p0 = sel8(pc, k0), p1 = sel8(pc, k1);
   const double tt = (0.5 - p0) / (p1 - p0);
@@ -89,9 +91,11 @@ __device__ inline D3 cube_vertex(const double* pc, int e, int c0, int c1, int c2
           ((double)w2 + (ea == 2 ? tt : 0.0)) * s[2] - o[2]};
 }
 
-// dL/dx of the vertex on edge (u, a) from the area and volume terms.
+// dL/dx of the vertex on edge (u, a) from the area and volume terms; ntri and
+// tri are the case table's triangle counts and edge triples (in LDS).
 __device__ inline void vertex_grad_mesh(const float* p, const int* d, const double* s, const double* o, int u0, int u1,
-                                        int u2, int a, double g_area, double g_vol_signed, double* gx) {
+                                        int u2, int a, double g_area, double g_vol_signed, const uint8_t* ntri,
+                                        const uint8_t* tri, double* gx) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int ob = q >> 1, oc = q & 1;
@@ -106,9 +110,10 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
     int cas = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) cas |= (int)(pc[k] > 0.5) << k;
-    const int nt = MC_NTRI[cas];
+    const int nt = ntri[cas];
     for (int t = 0; t < nt; ++t) {
-      const int e0 = MC_TRI[cas][t][0], e1 = MC_TRI[cas][t][1], e2 = MC_TRI[cas][t][2];
+      const uint8_t* tr = tri + (cas * MC_MAX_TRI + t) * 3;
+      const int e0 = tr[0], e1 = tr[1], e2 = tr[2];
       if (e0 != le && e1 != le && e2 != le) continue;
       const D3 P0 = cube_vertex(pc, e0, c0, c1, c2, s, o);
       const D3 P1 = cube_vertex(pc, e1, c0, c1, c2, s, o);
@@ -228,7 +233,13 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_soft_vertex_grad(SoftBwdBufs B) {
+__global__ __launch_bounds__(256, 4) void k_soft_vertex_grad(SoftBwdBufs B) {
+  // the case table in LDS: its lookups depend on one another (case, then triangle, then edge)
+  __shared__ uint8_t s_ntri[256];
+  __shared__ uint8_t s_tri[256 * MC_MAX_TRI * 3];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) s_ntri[i] = MC_NTRI[i];
+  for (int i = threadIdx.x; i < 256 * MC_MAX_TRI * 3; i += blockDim.x) s_tri[i] = (&MC_TRI[0][0][0])[i];
+  __syncthreads();
   const long long n = min(B.counters[0], B.cap);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -244,7 +255,7 @@ __global__ __launch_bounds__(256) void k_soft_vertex_grad(SoftBwdBufs B) {
     const long long lr = cube / (R->d[2] + 1);
     const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
     double gx[3] = {0.0, 0.0, 0.0};
-    vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, gx);
+    vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, s_ntri, s_tri, gx);
     const long long id = 3ll * ((((long long)(u0 + 1)) * (R->d[1] + 2) + (u1 + 1)) * (long long)(R->d[2] + 2) +
                                 (u2 + 1)) +
                          a;
