@@ -50,10 +50,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash():
+# Sources that define each profiled kernel (the shared headers count for all).
+KERNEL_SOURCES = {
+    "k_pair_maxima_h": ["pairs.hip"], "k_pair_maxima": ["pairs.hip"], "k_pack_h": ["pairs.hip"],
+    "k_bucket_scatter": ["pairs.hip"], "k_bucket_hist": ["pairs.hip"],
+    "k_mesh_count": ["mesh.hip"], "k_mesh_emit": ["mesh.hip"],
+}
+SHARED_HEADERS = ["mc_table.h", "s3d_device.h", "s3d_internal.h", "s3d_launch.h"]
+
+
+def source_hash(files=None):
+    """Hash of the kernel sources (all of csrc, or the given files plus the shared headers)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2510_02894_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    names = sorted(os.listdir(csrc)) if files is None else sorted(set(files) | set(SHARED_HEADERS))
+    for name in names:
         if name.endswith((".hip", ".h")):
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(name.encode())
@@ -61,16 +72,16 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, launches_per_step: int = 1):
+def measured_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
+    was taken on the current sources of that kernel."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or rec.get("source_hash") != source_hash():
+    if not k or k.get("source_hash") != source_hash(KERNEL_SOURCES.get(kernel)):
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -410,9 +421,11 @@ def main():
                   "note": "ceiling with MFMA and VALU maxima issued one after the other (they do not co-issue)"}
     N = int(np.prod(mask.shape))
     t_mesh = (avg["mesh_count"] + avg["mesh_emit"]) * 1e-3
+    tc, te = measured_traffic("k_mesh_count"), measured_traffic("k_mesh_emit")
+    mesh_traffic = tc + te if tc is not None and te is not None else None
     mesh_bytes = N * 1 + 24 * V
     mesh = {"bound": "hbm", "achieved": mesh_bytes / t_mesh / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": mesh_bytes / t_mesh / 1e9 / PEAK_HBM_GBS, "traffic": measured_traffic("k_mesh_count")}
+            "frac": mesh_bytes / t_mesh / 1e9 / PEAK_HBM_GBS, "traffic": mesh_traffic}
 
     single = None if args.skip_single else bench_single_roi(args, S)
     batched = None if args.skip_batched else bench_batched(args, S)
