@@ -507,28 +507,39 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
       u1 = Bp[(long long)min(jb + 5, jl) * 128];
       pair_tile_h<IT>(A, *(const v8h*)&u2, *(const v8h*)&u3, acc);
     }
-    // D[i][j] sits in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4:
-    // reduce over j (the low 5 lane bits), then undo the scale
+    // D[i][j] sits in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4
+    // of acc[r]: reduce over j (the low 5 lane bits) with a butterfly that
+    // halves the registers at every step (lane bit s keeps one half and sends
+    // the other), 62 shuffles for 64 registers.  Afterwards a lane holds the
+    // maxima of registers t + 2 * rev5(lane & 31), t = 0, 1, of the flat
+    // index r * 16 + q; then undo the scale.
+    float v[16 * IT];
+#pragma unroll
+    for (int r = 0; r < IT; ++r)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[16 * r + q] = acc[r][q];
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+      const int h = (16 * IT) >> (st + 1);
+      const bool hi = (lane >> st) & 1;
+#pragma unroll
+      for (int t = 0; t < h; ++t) {
+        const float keep = hi ? v[t + h] : v[t], send = hi ? v[t] : v[t + h];
+        v[t] = fmaxf(keep, __shfl_xor(send, 1 << st, 64));
+      }
+    }
+    const int rev = ((lane & 1) << 4) | ((lane & 2) << 2) | (lane & 4) | ((lane & 8) >> 2) | ((lane & 16) >> 4);
     const int e = h_scale_exp(meta[S.group >> 2].R2);
     const float unscale = ldexpf(1.0f, -2 * e);
 #pragma unroll
-    for (int r = 0; r < IT; ++r) {
+    for (int t = 0; t < (16 * IT) / 32; ++t) {
+      const int flat = t + ((16 * IT) / 32) * rev;  // register index r * 16 + q
+      const int r = flat >> 4, q = flat & 15;
       if (i0 + r >= nb) continue;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        float m = acc[r][q];
-        m = fmaxf(m, __shfl_xor(m, 1, 64));
-        m = fmaxf(m, __shfl_xor(m, 2, 64));
-        m = fmaxf(m, __shfl_xor(m, 4, 64));
-        m = fmaxf(m, __shfl_xor(m, 8, 64));
-        m = fmaxf(m, __shfl_xor(m, 16, 64));
-        if ((lane & 31) == q) {
-          const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-          const long long row = (rb + i0 + r) * 32 + i;
-          const float val = fmaxf(m, 0.0f) * unscale;
-          atomicMax((int*)&rowmax[row], __float_as_int(val));
-        }
-      }
+      const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      const long long row = (rb + i0 + r) * 32 + i;
+      const float val = fmaxf(v[t], 0.0f) * unscale;
+      atomicMax((int*)&rowmax[row], __float_as_int(val));
     }
   }
 }
