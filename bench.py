@@ -38,11 +38,6 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
 # kernel 1: v_mfma_f32_32x32x16_f16 (split f16), 32768 flops per 1024 pairs.
 FLOPS_PER_PAIR = {0: 8, 1: 32}
 PEAK_TFLOPS = {0: PEAK_FP32_MFMA_TFLOPS, 1: PEAK_F16_MFMA_TFLOPS}
-# Pairs per SIMD cycle when the MFMA and the VALU maxima (one v_max3 per two
-# pair values, 4 cycles per wave64 instruction) issue one after the other:
-# kernel 0: 256 pairs per (32 + 8) cycles; kernel 1: 1024 pairs per (32 + 32).
-PAIRS_PER_SIMD_CYCLE = {0: 256.0 / 40.0, 1: 1024.0 / 64.0}
-SIMDS, CLOCK_GHZ = 1024, 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -415,10 +410,6 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[kern], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[kern], "traffic": traffic,
                 "kernel": "split-f16 v_mfma_f32_32x32x16_f16" if kern == 1 else "fp32 v_mfma_f32_16x16x4_f32"}
-    ceiling = PAIRS_PER_SIMD_CYCLE[kern] * SIMDS * CLOCK_GHZ * 1e9
-    pair_issue = {"achieved_pairs_per_s": (pairs3 + pairs2) / t_pair, "ceiling_pairs_per_s": ceiling,
-                  "frac": (pairs3 + pairs2) / t_pair / ceiling,
-                  "note": "ceiling with MFMA and VALU maxima issued one after the other (they do not co-issue)"}
     N = int(np.prod(mask.shape))
     t_mesh = (avg["mesh_count"] + avg["mesh_emit"]) * 1e-3
     tc, te = measured_traffic("k_mesh_count"), measured_traffic("k_mesh_emit")
@@ -461,7 +452,6 @@ def main():
             "pairs_in_plane": pairs2,
         },
         "roofline": roofline,
-        "pair_issue_roofline": pair_issue,
         "cpu_baseline": cpu,
         "tiles": list(tiles),
         "phases_ms": avg,

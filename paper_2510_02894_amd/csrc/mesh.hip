@@ -284,6 +284,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   __shared__ int s_tk[256];
   __shared__ int s_tm[256];
   __shared__ uint32_t s_items[kMeshItems];
+  __shared__ uint32_t s_ly[kBrickThreads];  // (y + 1) | l << 20 of each thread's row-group
   __shared__ int s_scan[4];
   __shared__ double s_rd[2][4];
   __shared__ long long s_rl[4];
@@ -315,6 +316,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   load_tile<DT>(R, T, s_bits);
   __syncthreads();
   const Lane L = lane_of(R, T, tid);
+  s_ly[tid] = (uint32_t)(L.y + 1) | ((uint32_t)L.l << 20);  // read back by the dense loop (after a barrier)
   int nv = 0, nt = 0;
   double area = 0.0, vol_d = 0.0;
   long long vol_i = 0;
@@ -356,20 +358,24 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
       // this thread's items with index in [c0, c0 + kMeshItems)
       uint32_t m = active;
       int idx = off;
+      // (the divergent part stays minimal: the case is found in the dense loop)
       while (m && idx < c0 + kMeshItems) {
         const int k = __ffs(m) - 1;
         m &= m - 1u;
-        if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 16) | ((uint32_t)k << 8) | (uint32_t)case_of(C, k);
+        if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 5) | (uint32_t)k;
         ++idx;
       }
       __syncthreads();
       const int n = min(kMeshItems, total - c0);
       for (int i = tid; i < n; i += kBrickThreads) {
         const uint32_t it = s_items[i];
-        const int cas = (int)(it & 0xffu), k = (int)((it >> 8) & 31u), t = (int)(it >> 16);
-        const int rg = T.rg0 + t;
-        const int ry = rg / R.G;
-        const int y = ry - 1, x = 32 * (rg - ry * R.G) - 1 + k;
+        const int k = (int)(it & 31u), t = (int)(it >> 5);
+        const uint32_t ly = s_ly[t];
+        Lane Lt;
+        Lt.y = (int)(ly & 0xfffffu) - 1;
+        Lt.l = (int)(ly >> 20);
+        const int cas = case_of(tile_corners(s_bits, T, Lt, p, t, R.G), k);
+        const int y = Lt.y, x = 32 * Lt.l - 1 + k;
         const int tk = s_tk[cas];
         nt += tk & 0xff;
         if (DT == 0) {
