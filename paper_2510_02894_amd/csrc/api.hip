@@ -65,7 +65,7 @@ struct Workspace {
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
       bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
-      posh, soft_rois, soft_edges, soft_field, soft_ctr;
+      posh, case_area, soft_rois, soft_edges, soft_field, soft_ctr;
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
@@ -81,7 +81,7 @@ struct Workspace {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
             &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &ncol,     &colbase,
             &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
-            &cand_chbase, &posh, &soft_rois, &soft_edges, &soft_field, &soft_ctr};
+            &cand_chbase, &posh, &case_area, &soft_rois, &soft_edges, &soft_field, &soft_ctr};
   }
 };
 
@@ -265,6 +265,7 @@ int ensure_layout_bufs(Workspace& w, const Batch& B) {
   if ((rc = ensure(w, w.part, sizeof(BrickPart) * B.nbricks))) return rc;
   if ((rc = ensure(w, w.brick_voff, sizeof(long long) * B.nbricks))) return rc;
   if ((rc = ensure(w, w.meta, sizeof(RoiMeta) * n))) return rc;
+  if ((rc = ensure(w, w.case_area, sizeof(double) * 256 * (size_t)n))) return rc;
   if ((rc = ensure(w, w.totals, sizeof(long long) * 16))) return rc;
   if ((rc = ensure(w, w.counters, sizeof(unsigned int) * 4))) return rc;
   if ((rc = ensure(w, w.gres, sizeof(GroupRes) * 4 * (size_t)n))) return rc;
@@ -366,7 +367,8 @@ PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
 // Mesh count and per-ROI totals (launches only).
 int launch_head(Workspace& w, const Batch& Bt, int dtype, hipStream_t st) {
   HIPCK(launch_fill_u32((unsigned int*)w.counters.p, 0u, 4, st));
-  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (BrickPart*)w.part.p, st));
+  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (double*)w.case_area.p,
+                          (BrickPart*)w.part.p, st));
   HIPCK(launch_mesh_totals((const Roi*)w.rois.p, Bt.n(), Bt.nbricks, dtype, (const BrickPart*)w.part.p,
                            (long long*)w.brick_voff.p, (RoiMeta*)w.meta.p, (long long*)w.totals.p, st));
   return SHAPE3D_OK;

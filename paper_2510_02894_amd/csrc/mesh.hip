@@ -274,11 +274,30 @@ __device__ inline int case_of(const Corners& C, int k) {
 }
 
 // ---------------------------------------------------------------------------
+// Binary masks: area of each case's triangles for each ROI's spacing (one
+// workgroup per ROI, one thread per case), read by every brick of the ROI.
+
+__global__ __launch_bounds__(256) void k_case_area(const Roi* __restrict__ rois, double* __restrict__ case_area) {
+  const Roi& R = rois[blockIdx.x];
+  const int c = threadIdx.x;
+  const int nt = MC_NTRI[c];
+  double a = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const double n0 = R.s[1] * R.s[2] * MC_TRI_N[c][t][0];
+    const double n1 = R.s[0] * R.s[2] * MC_TRI_N[c][t][1];
+    const double n2 = R.s[0] * R.s[1] * MC_TRI_N[c][t][2];
+    a += 0.125 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+  }
+  case_area[(size_t)blockIdx.x * 256 + c] = a;
+}
+
+// ---------------------------------------------------------------------------
 // Count pass.
 
 template <int DT>
 __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restrict__ rois, int n_rois,
-                                                              long long nbricks, BrickPart* __restrict__ part) {
+                                                              long long nbricks, const double* __restrict__ case_area,
+                                                              BrickPart* __restrict__ part) {
   extern __shared__ uint32_t s_bits[];
   __shared__ double s_area[256];
   __shared__ int s_tk[256];
@@ -297,16 +316,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   {
     const int c = tid;
     const int nt = MC_NTRI[c];
-    double a = 0.0;
-    if (DT == 0) {
-      for (int t = 0; t < nt; ++t) {
-        const double n0 = R.s[1] * R.s[2] * MC_TRI_N[c][t][0];
-        const double n1 = R.s[0] * R.s[2] * MC_TRI_N[c][t][1];
-        const double n2 = R.s[0] * R.s[1] * MC_TRI_N[c][t][2];
-        a += 0.125 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-      }
-    }
-    s_area[c] = a;
+    s_area[c] = DT == 0 ? case_area[(size_t)roi * 256 + c] : 0.0;
     s_tk[c] = nt | ((MC_CASE_KAPPA[c] + 128) << 8);
     s_tm[c] = (MC_CASE_M[c][0] + 128) | ((MC_CASE_M[c][1] + 128) << 8) | ((MC_CASE_M[c][2] + 128) << 16);
   }
@@ -622,6 +632,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   extern __shared__ uint32_t s_bits[];
   __shared__ int s_scan[4];
   __shared__ uint32_t s_items[kMeshItems];
+  __shared__ uint32_t s_ly[kBrickThreads];  // (y + 1) | l << 20 of each thread's row-group
   const long long brick = xcd_remap(blockIdx.x, nbricks);
   if (*overflow != 0u || part[brick].nv == 0) return;
   const int roi = find_roi(rois, n_rois, brick);
@@ -632,6 +643,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   load_tile<DT>(R, T, s_bits);
   __syncthreads();
   const Lane L = lane_of(R, T, tid);
+  s_ly[tid] = (uint32_t)(L.y + 1) | ((uint32_t)L.l << 20);  // read back by the dense loop (after a barrier)
   long long base = M.row_off + brick_voff[brick];
   // Every thread of the brick runs the same steps (block scans inside).  Per
   // cube plane the crossing edges are listed in LDS in row order (thread,
@@ -665,9 +677,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
       for (int i = tid; i < n; i += kBrickThreads) {
         const uint32_t it = s_items[i];
         const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), t = (int)(it >> 8);
-        const int rg = T.rg0 + t;
-        const int ry = rg / R.G;
-        const int u0 = z, u1 = ry - 1, u2 = 32 * (rg - ry * R.G) - 1 + k;
+        const uint32_t ly = s_ly[t];
+        const int u0 = z, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * (int)(ly >> 20) - 1 + k;
         const long long row = base + c0 + i;
         double tv = 0.5;
         if (DT == 1) {
@@ -732,16 +743,18 @@ __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, floa
 
 size_t mesh_lds_bytes(int max_G) { return sizeof(uint32_t) * (size_t)(kTZ + 1) * (kBrickThreads + 1 + max_G); }
 
-hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G, BrickPart* part,
-                             hipStream_t st) {
+hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                             double* case_area, BrickPart* part, hipStream_t st) {
   if (nbricks <= 0) return hipSuccess;
   const size_t lds = mesh_lds_bytes(max_G);
-  if (dtype == 0)
+  if (dtype == 0) {
+    hipLaunchKernelGGL(k_case_area, dim3((unsigned)n_rois), dim3(256), 0, st, rois, case_area);
     hipLaunchKernelGGL(k_mesh_count<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       part);
-  else
+                       case_area, part);
+  } else {
     hipLaunchKernelGGL(k_mesh_count<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       part);
+                       case_area, part);
+  }
   return hipGetLastError();
 }
 

@@ -22,8 +22,9 @@ struct RoiResult {
 // mesh.hip
 // Dynamic LDS of the mesh kernels for ROIs with at most max_G row-groups per row.
 size_t mesh_lds_bytes(int max_G);
-hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G, BrickPart* part,
-                             hipStream_t st);
+// case_area: [n_rois * 256] scratch for the binary masks' per-case areas.
+hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                             double* case_area, BrickPart* part, hipStream_t st);
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
                               long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st);
 hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
