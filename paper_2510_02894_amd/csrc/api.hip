@@ -267,7 +267,7 @@ int ensure_layout_bufs(Workspace& w, const Batch& B) {
   if ((rc = ensure(w, w.meta, sizeof(RoiMeta) * n))) return rc;
   if ((rc = ensure(w, w.case_area, sizeof(double) * 256 * (size_t)n))) return rc;
   if ((rc = ensure(w, w.totals, sizeof(long long) * 16))) return rc;
-  if ((rc = ensure(w, w.counters, sizeof(unsigned int) * 4))) return rc;
+  if ((rc = ensure(w, w.counters, sizeof(unsigned int) * kCounterWords))) return rc;
   if ((rc = ensure(w, w.gres, sizeof(GroupRes) * 4 * (size_t)n))) return rc;
   if ((rc = ensure(w, w.res, sizeof(RoiResult) * n))) return rc;
   if ((rc = ensure(w, w.pairs2d, sizeof(long long) * n))) return rc;
@@ -366,7 +366,7 @@ PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
 
 // Mesh count and per-ROI totals (launches only).
 int launch_head(Workspace& w, const Batch& Bt, int dtype, hipStream_t st) {
-  HIPCK(launch_fill_u32((unsigned int*)w.counters.p, 0u, 4, st));
+  HIPCK(launch_fill_u32((unsigned int*)w.counters.p, 0u, kCounterWords, st));
   HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (double*)w.case_area.p,
                           (BrickPart*)w.part.p, st));
   HIPCK(launch_mesh_totals((const Roi*)w.rois.p, Bt.n(), Bt.nbricks, dtype, (const BrickPart*)w.part.p,
@@ -391,7 +391,6 @@ int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStr
   HIPCK(launch_buckets(B, st));
   HIPCK(launch_pack_operands(B, st));
   HIPCK(launch_init_groups(B, st));
-  HIPCK(launch_fill_u32(B.counters, 0u, 2, st));
   if (ev) HIPCK(hipEventRecord(ev[2], st));
   HIPCK(launch_pair_maxima(B, st));
   if (ev) HIPCK(hipEventRecord(ev[3], st));

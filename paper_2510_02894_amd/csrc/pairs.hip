@@ -12,10 +12,11 @@
 //     and maps exactly onto v_mfma_f32_16x16x4_f32: one instruction gives the
 //     256 pair values of a 16 x 16 tile; the VALU keeps per-row running maxima
 //     (v_max3) beside the matrix core;
-//   * a wave owns 8 row blocks (128 rows, kept in registers as A operands)
-//     and streams column blocks of one 4096-row chunk of the upper triangle;
-//     work items are handed out by an atomic counter in column-major order so
-//     concurrently running waves share the column data in L2;
+//   * a wave owns a tile of row blocks (kept in registers as A operands) and
+//     streams the column blocks of one column chunk of the upper triangle;
+//     work items, in column-major order, are handed out by one atomic counter
+//     per XCD over a contiguous range each, so the waves of an XCD share the
+//     column data in its L2;
 //   * FP32 row maxima are then refined exactly: every row whose FP32 maximum
 //     lies within a rigorous rounding bound of the group maximum is rescanned
 //     against its whole segment in FP64 (the same operations as the oracle),
@@ -227,6 +228,96 @@ __global__ void k_col_fill(int n_rois, long long seg_cap, const long long* __res
 // ---------------------------------------------------------------------------
 // Pair maxima on the matrix cores.
 
+// Hands the work items [0, n) out to waves.  The items are split into
+// kWorkParts contiguous ranges, each with its own counter (kWorkStride words
+// apart, so the counters sit in different cache lines and their atomics do not
+// queue behind one another; one shared counter serialises its atomics at
+// roughly one per 18 ns, which bounded batches of small ROIs with millions of
+// items).  A wave starts on the range of its workgroup's XCD (workgroups are
+// dispatched round-robin over the 8 XCDs), takes `grab` consecutive items per
+// atomic (two when there are at least 8 items per wave, else one), and moves on
+// to the following ranges once its range is exhausted.  A range it moves on to
+// is first read with a plain device-scope load, so that the usual case at the
+// end (every range already exhausted) costs loads, which do not queue, rather
+// than atomics.  Every wave ends after at most kWorkParts failed grabs.  All
+// members are wave-uniform.  (Reading all counters at once with a ballot was
+// tried: the kernel then needs more than 168 VGPRs and loses a wave per SIMD.)
+struct WorkQueue {
+  unsigned int* ctr;
+  long long n, cur, end, lo, hi;
+  int part, left, grab;
+  bool look;  // read the current range's counter before the next atomic
+
+  __device__ WorkQueue(unsigned int* c, long long n_items)
+      : ctr(c), n(n_items), cur(0), end(0), part((int)(blockIdx.x % kWorkParts)), left(kWorkParts), look(false) {
+    const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+    grab = n_items >= 8 * waves ? 2 : 1;
+    set_range();
+  }
+  __device__ void set_range() {
+    lo = n * part / kWorkParts;
+    hi = n * (part + 1) / kWorkParts;
+  }
+  // The next item, or -1 once every range is exhausted.
+  __device__ long long next(int lane) {
+    if (cur < end) return cur++;
+    while (left > 0) {
+      unsigned int got = 0;
+      if (lane == 0) {
+        unsigned int* c = ctr + part * kWorkStride;
+        if (look) got = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!look || lo + (long long)got * grab < hi) got = atomicAdd(c, 1u);
+      }
+      const long long first = lo + (long long)__builtin_amdgcn_readfirstlane((int)__shfl(got, 0, 64)) * grab;
+      if (first < hi) {
+        cur = first + 1;
+        end = min(first + grab, hi);
+        look = false;
+        return first;
+      }
+      --left;
+      part = (part + 1) % kWorkParts;
+      set_range();
+      look = true;
+    }
+    return -1;
+  }
+};
+
+// The column of an item: the last column whose first item is <= item (empty
+// columns share their base with the next one).  A wave's items mostly ascend
+// within a range, so the cached column is walked forward a few steps before
+// falling back to a binary search.
+struct ColumnOf {
+  const long long* itembase;
+  long long n_items, ncol, col, col_lo, col_hi;
+
+  __device__ ColumnOf(const long long* ib, long long ni, long long nc)
+      : itembase(ib), n_items(ni), ncol(nc), col(0), col_lo(0), col_hi(nc > 1 ? ib[1] : ni) {}
+  __device__ void advance() {
+    ++col;
+    col_lo = col_hi;
+    col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+  }
+  __device__ void locate(long long item) {
+    for (int steps = 0; steps < 4 && item >= col_hi; ++steps) advance();
+    if (item < col_lo || item >= col_hi) {
+      long long lo2 = item < col_lo ? 0 : col, hi2 = ncol - 1;
+      while (lo2 < hi2) {
+        const long long mid = (lo2 + hi2 + 1) >> 1;
+        if (itembase[mid] <= item)
+          lo2 = mid;
+        else
+          hi2 = mid - 1;
+      }
+      col = lo2;
+      col_lo = itembase[col];
+      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
+    }
+    while (col + 1 < ncol && item >= col_hi) advance();
+  }
+};
+
 // 2*IT MFMAs: the IT row blocks against two column blocks, folded into the
 // running row maxima with v_max3.
 template <int IT>
@@ -260,48 +351,13 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
                                                      unsigned int* __restrict__ work_ctr, float* __restrict__ rowmax,
                                                      int jchunk) {
   const int lane = threadIdx.x & 63;
-  const long long n_items = totals[T_NITEM];
-  const long long ncol = totals[T_NCOL];
-  // Items are handed out in increasing order, so a wave's next item is usually
-  // in the same column as its last one or a few columns later: walk forward a
-  // few steps from the cached column, else binary-search the rest.
-  long long col = 0, col_lo = 0, col_hi = ncol > 1 ? itembase[1] : n_items;
-  for (;;) {
-    unsigned int got = 0;
-    if (lane == 0) got = atomicAdd(work_ctr, 1u);
-    const long long item = (long long)__builtin_amdgcn_readfirstlane((int)__shfl(got, 0, 64));
-    if (item >= n_items) break;
-    int steps = 0;
-    while (item >= col_hi && steps < 4) {
-      ++col;
-      ++steps;
-      col_lo = col_hi;
-      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
-    }
-    if (item >= col_hi) {
-      long long lo2 = col, hi2 = ncol - 1;
-      while (lo2 < hi2) {
-        const long long mid = (lo2 + hi2 + 1) >> 1;
-        if (itembase[mid] <= item)
-          lo2 = mid;
-        else
-          hi2 = mid - 1;
-      }
-      col = lo2;
-      col_lo = itembase[col];
-      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
-    }
-    // an empty column shares its base with the next one: skip forward to the
-    // last column whose base is <= item
-    while (col + 1 < ncol && item >= col_hi) {
-      ++col;
-      col_lo = col_hi;
-      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
-    }
-    const long long lo = col;
-    const Col C = cols[lo];
+  WorkQueue q(work_ctr, totals[T_NITEM]);
+  ColumnOf where(itembase, totals[T_NITEM], totals[T_NCOL]);
+  for (long long item; (item = q.next(lane)) >= 0;) {
+    where.locate(item);
+    const Col C = cols[where.col];
     const Seg S = segs[C.seg];
-    const int it = (int)(item - col_lo);
+    const int it = (int)(item - where.col_lo);
     const long long rb = S.row_begin >> 4;
     const int nb = S.n_rows >> 4;
     const int i0 = it * IT;
@@ -439,42 +495,13 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
                                                        unsigned int* __restrict__ work_ctr,
                                                        float* __restrict__ rowmax, int jchunk) {
   const int lane = threadIdx.x & 63;
-  const long long n_items = totals[T_NITEM];
-  const long long ncol = totals[T_NCOL];
-  long long col = 0, col_lo = 0, col_hi = ncol > 1 ? itembase[1] : n_items;
-  for (;;) {
-    unsigned int got = 0;
-    if (lane == 0) got = atomicAdd(work_ctr, 1u);
-    const long long item = (long long)__builtin_amdgcn_readfirstlane((int)__shfl(got, 0, 64));
-    if (item >= n_items) break;
-    int steps = 0;
-    while (item >= col_hi && steps < 4) {
-      ++col;
-      ++steps;
-      col_lo = col_hi;
-      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
-    }
-    if (item >= col_hi) {
-      long long lo2 = col, hi2 = ncol - 1;
-      while (lo2 < hi2) {
-        const long long mid = (lo2 + hi2 + 1) >> 1;
-        if (itembase[mid] <= item)
-          lo2 = mid;
-        else
-          hi2 = mid - 1;
-      }
-      col = lo2;
-      col_lo = itembase[col];
-      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
-    }
-    while (col + 1 < ncol && item >= col_hi) {
-      ++col;
-      col_lo = col_hi;
-      col_hi = col + 1 < ncol ? itembase[col + 1] : n_items;
-    }
-    const Col C = cols[col];
+  WorkQueue q(work_ctr, totals[T_NITEM]);
+  ColumnOf where(itembase, totals[T_NITEM], totals[T_NCOL]);
+  for (long long item; (item = q.next(lane)) >= 0;) {
+    where.locate(item);
+    const Col C = cols[where.col];
     const Seg S = segs[C.seg];
-    const int it = (int)(item - col_lo);
+    const int it = (int)(item - where.col_lo);
     // 32-row block coordinates (segments start and end on 32-row boundaries)
     const long long rb = S.row_begin >> 5;
     const int nb = S.n_rows >> 5;
@@ -703,7 +730,12 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
   }
 }
 
-__global__ void k_init_groups(GroupRes* gres, long long n) {
+// Also clears the candidate counter and the pair-pass work counters.
+__global__ void k_init_groups(GroupRes* gres, long long n, unsigned int* counters) {
+  if (blockIdx.x == 0) {
+    for (int i = kWorkStride + threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0u;
+    if (threadIdx.x == 0) counters[1] = 0u;
+  }
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (long long)gridDim.x * blockDim.x) {
     GroupRes G;
     G.best_bits = 0ull;
@@ -799,7 +831,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The work counter (B.counters[0]) must be zero when this is enqueued.
+// The work counters (B.counters + kWorkStride) must be zero when this is enqueued.
 template <int IT>
 hipError_t launch_pair_maxima_it(const PairBufs& B, hipStream_t st) {
   hipError_t e;
@@ -809,7 +841,7 @@ hipError_t launch_pair_maxima_it(const PairBufs& B, hipStream_t st) {
   if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
   hipLaunchKernelGGL(k_pair_maxima<IT>, dim3(grid), dim3(256), 0, st, B.pos, B.segs, B.cols, B.itembase, B.totals,
-                     B.counters, B.rowmax, B.tune.jchunk);
+                     B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
   return hipGetLastError();
 }
 
@@ -829,7 +861,7 @@ hipError_t launch_pair_maxima_h(const PairBufs& B, hipStream_t st) {
   if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
   hipLaunchKernelGGL(k_pair_maxima_h<IT>, dim3(grid), dim3(256), 0, st, B.posh, B.segs, B.cols, B.itembase,
-                     B.totals, B.meta, B.counters, B.rowmax, B.tune.jchunk);
+                     B.totals, B.meta, B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
   return hipGetLastError();
 }
 
@@ -857,7 +889,7 @@ hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
 }
 
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_groups, dim3(grid_for(4ll * B.n_rois)), dim3(256), 0, st, B.gres, 4ll * B.n_rois);
+  hipLaunchKernelGGL(k_init_groups, dim3(grid_for(4ll * B.n_rois)), dim3(256), 0, st, B.gres, 4ll * B.n_rois, B.counters);
   return hipGetLastError();
 }
 

@@ -24,6 +24,9 @@ constexpr int kSegAlign = 32;       // segment rows padded to a multiple of this
 constexpr int kMinJchunk = 64;      // smallest column chunk (row blocks) the pair pass may be tuned to
 constexpr int kScanTile = 2048;     // elements per block of the device scan
 constexpr int kExactChunk = 4096;   // rows per block of the exact refinement
+constexpr int kWorkParts = 8;       // work ranges (one per XCD) of the pair pass, each with its own counter
+constexpr int kWorkStride = 32;     // words between two work counters (one 128-byte line each)
+constexpr int kCounterWords = kWorkStride * (1 + kWorkParts);  // size of the counter block
 
 // Key of a vertex: edge (u, u + e_a): bits 0..19 u2+1, 20..39 u1+1, 40..59 u0+1, 60..61 a.
 __host__ __device__ inline uint64_t pack_key(int u0, int u1, int u2, int a) {

@@ -80,7 +80,7 @@ struct PairBufs {
   long long* itembase;  // [col_cap]
   long long* totals;    // device scalars: see pairs.hip
   long long* scan_tmp;
-  unsigned int* counters;  // [0] work items, [1] candidates, [2] overflow flag
+  unsigned int* counters;  // [1] candidates, [2] overflow flag; pair-pass work counters from word kWorkStride
   GroupRes* gres;          // [4 * n_rois]
   long long cand_cap;      // candidate capacity: every row could be one
   int* cand;               // [cand_cap]
@@ -138,7 +138,7 @@ hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list
 hipError_t launch_pack_operands(const PairBufs& B, hipStream_t st); // split-f16 operands (kernel 1 only)
 hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass over the work list
-hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset per-group results
+hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset per-group results and pair-pass counters
 hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st);      // per-ROI results
 hipError_t launch_export_vertices(const unsigned long long* key, const double* tsoft, const RoiMeta* meta,
