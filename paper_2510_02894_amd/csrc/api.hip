@@ -220,6 +220,14 @@ struct Batch {
   int n() const { return (int)rois.size(); }
 };
 
+// Magic numbers (fdiv) of the kernels' 32-bit division by D (numerators < 2^31).
+void magic_div(unsigned int D, unsigned int& m, int& sh) {
+  int k = 0;
+  while ((1ull << k) < D) ++k;  // ceil(log2 D)
+  sh = 31 + k;
+  m = (unsigned int)((1ull << sh) / D + 1);
+}
+
 void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double spacing[3]) {
   Roi R;
   memset(&R, 0, sizeof(R));
@@ -232,6 +240,8 @@ void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double sp
   R.nrg = (R.d[1] + 1) * R.G;
   R.nzc = (R.d[0] + 1 + kTZ - 1) / kTZ;
   R.bpz = (R.nrg + kBrickThreads - 1) / kBrickThreads;
+  magic_div((unsigned int)R.G, R.mG, R.shG);
+  magic_div((unsigned int)(kBrickThreads + 1 + R.G), R.mNW, R.shNW);
   R.brick_begin = B.nbricks;
   R.bucket_base[0] = B.n_buckets;
   R.bucket_base[1] = R.bucket_base[0] + 2ll * R.d[0] + 1;
@@ -596,14 +606,6 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
   for (int64_t r = 0; r < n_rois; ++r)
     if (hres[r].status < 0) return fail(hres[r].status, "an internal capacity was exceeded");
   return SHAPE3D_OK;
-}
-
-// Magic numbers of the soft kernels' 32-bit division by D (numerators < 2^31).
-void magic_div(unsigned int D, unsigned int& m, int& sh) {
-  int k = 0;
-  while ((1ull << k) < D) ++k;  // ceil(log2 D)
-  sh = 31 + k;
-  m = (unsigned int)((1ull << sh) / D + 1);
 }
 
 void fill_saved(shape3d_soft_saved* saved, const int64_t dims[3], const double spacing[3], const RoiResult& raw,

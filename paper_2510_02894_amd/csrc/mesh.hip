@@ -117,7 +117,7 @@ __device__ inline Tile tile_of(const Roi& R, long long local_brick) {
 template <int DT>
 __device__ inline const void* fast_row_ptr(const Roi& R, const Tile& T, int p, int vrg) {
   if (vrg < 0) return nullptr;
-  const int ry = vrg / R.G;
+  const int ry = (int)fdiv((unsigned int)vrg, R.mG, R.shG);
   const int z = T.pz0 - 1 + p, y = ry - 1, x0 = 32 * (vrg - ry * R.G);
   if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1] || x0 + 32 > R.d[2]) return nullptr;
   const size_t off = ((size_t)z * R.d[1] + y) * (size_t)R.d[2] + x0;
@@ -128,7 +128,7 @@ __device__ inline const void* fast_row_ptr(const Roi& R, const Tile& T, int p, i
 template <int DT>
 __device__ inline uint32_t slow_row_bits(const Roi& R, const Tile& T, int p, int vrg) {
   if (vrg < 0) return 0u;
-  const int ry = vrg / R.G;
+  const int ry = (int)fdiv((unsigned int)vrg, R.mG, R.shG);
   return row_bits<DT>(R.vol, R.d, T.pz0 - 1 + p, ry - 1, vrg - ry * R.G);
 }
 
@@ -148,7 +148,7 @@ __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) 
         const int idx = base + u * kBrickThreads;
         const void* ptr = nullptr;
         if (idx < n) {
-          const int p = idx / T.nw;
+          const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
           ptr = fast_row_ptr<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
         }
         fast[u] = ptr != nullptr;
@@ -166,7 +166,7 @@ __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) 
           bits = nz4(a[u].x) | (nz4(a[u].y) << 4) | (nz4(a[u].z) << 8) | (nz4(a[u].w) << 12) |
                  (nz4(b[u].x) << 16) | (nz4(b[u].y) << 20) | (nz4(b[u].z) << 24) | (nz4(b[u].w) << 28);
         } else {
-          const int p = idx / T.nw;
+          const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
           bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
         }
         s_bits[idx] = bits;
@@ -182,7 +182,7 @@ __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) 
           const int idx = base + (u0 + h) * kBrickThreads;
           const void* ptr = nullptr;
           if (u0 + h < kLoadBatch && idx < n) {
-            const int p = idx / T.nw;
+            const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
             ptr = fast_row_ptr<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
           }
           fast[h] = ptr != nullptr;
@@ -203,7 +203,7 @@ __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) 
                        ((uint32_t)(v[h][i].z > 0.5f) << 2) | ((uint32_t)(v[h][i].w > 0.5f) << 3))
                       << (4 * i);
           } else {
-            const int p = idx / T.nw;
+            const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
             bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
           }
           s_bits[idx] = bits;
@@ -224,7 +224,7 @@ __device__ inline Lane lane_of(const Roi& R, const Tile& T, int tid) {
   Lane L;
   const int rg = T.rg0 + tid;
   L.valid = rg < R.nrg;
-  const int ry = L.valid ? rg / R.G : 0;
+  const int ry = L.valid ? (int)fdiv((unsigned int)rg, R.mG, R.shG) : 0;
   L.l = L.valid ? rg - ry * R.G : 0;
   L.y = ry - 1;
   const int kmax = R.d[2] - 32 * L.l;  // cube x = 32l - 1 + k valid iff k <= kmax
@@ -334,98 +334,130 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   // origin of the soft tetrahedron sum: the array centre (as the FP64 oracle uses)
   const double o0 = 0.5 * R.d[0] * R.s[0], o1 = 0.5 * R.d[1] * R.s[1], o2 = 0.5 * R.d[2] * R.s[2];
 
-  // Per cube plane: counts and bounding box from the masks, then the active
-  // cubes of the whole workgroup are compacted into s_items (block scan) and
-  // processed densely, so that a lane whose 32 cubes all touch the surface
-  // does not hold up its wave.
-  for (int p = 0; p + 1 < T.np; ++p) {
-    const int z = T.pz0 - 1 + p;
-    uint32_t active = 0u;
-    Corners C;
-    if (L.valid) {
-      C = tile_corners(s_bits, T, L, p, tid, R.G);
-      uint32_t any = 0u, all = 0xffffffffu;
+  // All planes of the brick at once: each thread first classifies its 32
+  // cubes of every plane pair (voxel rows held in registers, each read from
+  // LDS once), counting crossing edges and collecting the active cubes per
+  // plane; one block scan then places every active cube of the brick in
+  // s_items, and the whole workgroup processes them densely, so that a lane
+  // whose cubes all touch the surface does not hold up its wave and the
+  // brick takes a few barriers instead of a few per plane.
+  static_assert(kTZ <= 8, "an item holds the plane in 3 bits");
+  uint32_t act[kTZ];
+  int cnt = 0;
+  {
+    uint32_t rr[kTZ + 1][2], xx[kTZ + 1][2];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        any |= C.c[c];
-        all &= C.c[c];
+    for (int p = 0; p <= kTZ; ++p)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        rr[p][dy] = 0u;
+        xx[p][dy] = 0u;
+        if (L.valid && p < T.np) {
+          const int w = p * T.nw + tid + 1 + dy * R.G;
+          rr[p][dy] = s_bits[w];
+          xx[p][dy] = L.l > 0 ? (s_bits[w - 1] >> 31) : 0u;
+        }
       }
-      nv += __popc((C.c[0] ^ C.c[4]) & L.vmask) + __popc((C.c[0] ^ C.c[2]) & L.vmask) +
-            __popc((C.c[0] ^ C.c[1]) & L.vmask);
-      active = any & ~all & L.vmask;
-      if (active) {
-        bb[0] = min(bb[0], z);
-        bb[1] = min(bb[1], L.y);
-        bb[2] = min(bb[2], 32 * L.l - 1 + (__ffs(active) - 1));
-        bb[3] = max(bb[3], z);
-        bb[4] = max(bb[4], L.y);
-        bb[5] = max(bb[5], 32 * L.l - 1 + (31 - __clz(active)));
+#pragma unroll
+    for (int p = 0; p < kTZ; ++p) {
+      act[p] = 0u;
+      if (L.valid && p + 1 < T.np) {
+        const Corners C = make_corners(rr[p][0], xx[p][0], rr[p][1], xx[p][1], rr[p + 1][0], xx[p + 1][0],
+                                       rr[p + 1][1], xx[p + 1][1]);
+        uint32_t any = 0u, all = 0xffffffffu;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          any |= C.c[c];
+          all &= C.c[c];
+        }
+        nv += __popc((C.c[0] ^ C.c[4]) & L.vmask) + __popc((C.c[0] ^ C.c[2]) & L.vmask) +
+              __popc((C.c[0] ^ C.c[1]) & L.vmask);
+        const uint32_t active = any & ~all & L.vmask;
+        if (active) {
+          const int z = T.pz0 - 1 + p;
+          bb[0] = min(bb[0], z);
+          bb[1] = min(bb[1], L.y);
+          bb[2] = min(bb[2], 32 * L.l - 1 + (__ffs(active) - 1));
+          bb[3] = max(bb[3], z);
+          bb[4] = max(bb[4], L.y);
+          bb[5] = max(bb[5], 32 * L.l - 1 + (31 - __clz(active)));
+        }
+        act[p] = active;
       }
+      cnt += __popc(act[p]);
     }
-    int total;
-    const int off = block_excl_scan256(__popc(active), s_scan, total);
-    for (int c0 = 0; c0 < total; c0 += kMeshItems) {
-      // this thread's items with index in [c0, c0 + kMeshItems)
-      uint32_t m = active;
-      int idx = off;
-      // (the divergent part stays minimal: the case is found in the dense loop)
+  }
+  int total;
+  const int off = block_excl_scan256(cnt, s_scan, total);
+  for (int c0 = 0; c0 < total; c0 += kMeshItems) {
+    // this thread's items with index in [c0, c0 + kMeshItems): (thread, plane, cube)
+    int idx = off;
+#pragma unroll
+    for (int p = 0; p < kTZ; ++p) {
+      uint32_t m = act[p];
+      const int np = __popc(m);
+      if (idx + np <= c0 || idx >= c0 + kMeshItems) {
+        idx += np;
+        continue;
+      }
       while (m && idx < c0 + kMeshItems) {
         const int k = __ffs(m) - 1;
         m &= m - 1u;
-        if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 5) | (uint32_t)k;
+        if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 8) | ((uint32_t)p << 5) | (uint32_t)k;
         ++idx;
       }
-      __syncthreads();
-      const int n = min(kMeshItems, total - c0);
-      for (int i = tid; i < n; i += kBrickThreads) {
-        const uint32_t it = s_items[i];
-        const int k = (int)(it & 31u), t = (int)(it >> 5);
-        const uint32_t ly = s_ly[t];
-        Lane Lt;
-        Lt.y = (int)(ly & 0xfffffu) - 1;
-        Lt.l = (int)(ly >> 20);
-        const int cas = case_of(tile_corners(s_bits, T, Lt, p, t, R.G), k);
-        const int y = Lt.y, x = 32 * Lt.l - 1 + k;
-        const int tk = s_tk[cas];
-        nt += tk & 0xff;
-        if (DT == 0) {
-          const int tm = s_tm[cas];
-          area += s_area[cas];
-          vol_i += (long long)((tk >> 8) - 128) +
-                   2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)y * (((tm >> 8) & 0xff) - 128) +
-                          (long long)x * (((tm >> 16) & 0xff) - 128));
-        } else {
-          const float* pv = (const float*)R.vol;
-          double pc[8];
+    }
+    __syncthreads();
+    const int n = min(kMeshItems, total - c0);
+    for (int i = tid; i < n; i += kBrickThreads) {
+      const uint32_t it = s_items[i];
+      const int k = (int)(it & 31u), p = (int)((it >> 5) & 7u), t = (int)(it >> 8);
+      const int z = T.pz0 - 1 + p;
+      const uint32_t ly = s_ly[t];
+      Lane Lt;
+      Lt.y = (int)(ly & 0xfffffu) - 1;
+      Lt.l = (int)(ly >> 20);
+      const int cas = case_of(tile_corners(s_bits, T, Lt, p, t, R.G), k);
+      const int y = Lt.y, x = 32 * Lt.l - 1 + k;
+      const int tk = s_tk[cas];
+      nt += tk & 0xff;
+      if (DT == 0) {
+        const int tm = s_tm[cas];
+        area += s_area[cas];
+        vol_i += (long long)((tk >> 8) - 128) +
+                 2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)y * (((tm >> 8) & 0xff) - 128) +
+                        (long long)x * (((tm >> 16) & 0xff) - 128));
+      } else {
+        const float* pv = (const float*)R.vol;
+        double pc[8];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) pc[c] = soft_value(pv, R.d, z + ((c >> 2) & 1), y + ((c >> 1) & 1), x + (c & 1));
-          const int ntri = tk & 0xff;
-          for (int tr = 0; tr < ntri; ++tr) {
-            double P[3][3];
+        for (int c = 0; c < 8; ++c) pc[c] = soft_value(pv, R.d, z + ((c >> 2) & 1), y + ((c >> 1) & 1), x + (c & 1));
+        const int ntri = tk & 0xff;
+        for (int tr = 0; tr < ntri; ++tr) {
+          double P[3][3];
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-              const int e = MC_TRI[cas][tr][v];
-              const int ax = MC_EDGE_AXIS[e], k0 = MC_EDGE_C0[e];
-              const int k1 = k0 | (4 >> ax);
-              const double tt = (0.5 - sel8d(pc, k0)) / (sel8d(pc, k1) - sel8d(pc, k0));
-              const int u0 = z + ((k0 >> 2) & 1), u1 = y + ((k0 >> 1) & 1), u2 = x + (k0 & 1);
-              P[v][0] = ((double)u0 + (ax == 0 ? tt : 0.0)) * R.s[0] - o0;
-              P[v][1] = ((double)u1 + (ax == 1 ? tt : 0.0)) * R.s[1] - o1;
-              P[v][2] = ((double)u2 + (ax == 2 ? tt : 0.0)) * R.s[2] - o2;
-            }
-            const double e1x = P[1][0] - P[0][0], e1y = P[1][1] - P[0][1], e1z = P[1][2] - P[0][2];
-            const double e2x = P[2][0] - P[0][0], e2y = P[2][1] - P[0][1], e2z = P[2][2] - P[0][2];
-            const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-            area += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
-            const double bcx = P[1][1] * P[2][2] - P[1][2] * P[2][1];
-            const double bcy = P[1][2] * P[2][0] - P[1][0] * P[2][2];
-            const double bcz = P[1][0] * P[2][1] - P[1][1] * P[2][0];
-            vol_d += (P[0][0] * bcx + P[0][1] * bcy + P[0][2] * bcz) / 6.0;
+          for (int v = 0; v < 3; ++v) {
+            const int e = MC_TRI[cas][tr][v];
+            const int ax = MC_EDGE_AXIS[e], k0 = MC_EDGE_C0[e];
+            const int k1 = k0 | (4 >> ax);
+            const double tt = (0.5 - sel8d(pc, k0)) / (sel8d(pc, k1) - sel8d(pc, k0));
+            const int u0 = z + ((k0 >> 2) & 1), u1 = y + ((k0 >> 1) & 1), u2 = x + (k0 & 1);
+            P[v][0] = ((double)u0 + (ax == 0 ? tt : 0.0)) * R.s[0] - o0;
+            P[v][1] = ((double)u1 + (ax == 1 ? tt : 0.0)) * R.s[1] - o1;
+            P[v][2] = ((double)u2 + (ax == 2 ? tt : 0.0)) * R.s[2] - o2;
           }
+          const double e1x = P[1][0] - P[0][0], e1y = P[1][1] - P[0][1], e1z = P[1][2] - P[0][2];
+          const double e2x = P[2][0] - P[0][0], e2y = P[2][1] - P[0][1], e2z = P[2][2] - P[0][2];
+          const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+          area += 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+          const double bcx = P[1][1] * P[2][2] - P[1][2] * P[2][1];
+          const double bcy = P[1][2] * P[2][0] - P[1][0] * P[2][2];
+          const double bcz = P[1][0] * P[2][1] - P[1][1] * P[2][0];
+          vol_d += (P[0][0] * bcx + P[0][1] * bcy + P[0][2] * bcz) / 6.0;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 
   // fixed-order block reduction
@@ -618,7 +650,7 @@ __global__ void k_check_capacity(int n_rois, long long rows0_cap, RoiMeta* __res
 
 // ---------------------------------------------------------------------------
 // Emission pass: the same classification, writing each crossing edge's vertex
-// at its deterministic row (brick order, then plane, thread, axis, cube).
+// at its deterministic row (brick order, then thread, plane, axis, cube).
 
 template <int DT>
 __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restrict__ rois, int n_rois,
@@ -644,67 +676,93 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   __syncthreads();
   const Lane L = lane_of(R, T, tid);
   s_ly[tid] = (uint32_t)(L.y + 1) | ((uint32_t)L.l << 20);  // read back by the dense loop (after a barrier)
-  long long base = M.row_off + brick_voff[brick];
-  // Every thread of the brick runs the same steps (block scans inside).  Per
-  // cube plane the crossing edges are listed in LDS in row order (thread,
-  // axis, cube) and then written by consecutive threads to consecutive rows,
-  // so the stores of a wave are contiguous.
-  for (int p = 0; p + 1 < T.np; ++p) {
-    const int z = T.pz0 - 1 + p;
-    uint32_t e[3] = {0u, 0u, 0u};
-    if (L.valid) {
-      const Corners C = tile_corners(s_bits, T, L, p, tid, R.G);
-      e[0] = (C.c[0] ^ C.c[4]) & L.vmask;
-      e[1] = (C.c[0] ^ C.c[2]) & L.vmask;
-      e[2] = (C.c[0] ^ C.c[1]) & L.vmask;
+  const long long base = M.row_off + brick_voff[brick];
+  // All planes at once, as in the count pass: each thread lists the crossing
+  // edges of its 32 cubes for every plane pair, one block scan places them,
+  // and the listed edges are written by consecutive threads to consecutive
+  // rows, so the stores of a wave are contiguous.
+  uint32_t e[kTZ][3];
+  int cnt = 0;
+  {
+    uint32_t rr[kTZ + 1][2], xx[kTZ + 1][2];
+#pragma unroll
+    for (int p = 0; p <= kTZ; ++p)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        rr[p][dy] = 0u;
+        xx[p][dy] = 0u;
+        if (L.valid && p < T.np) {
+          const int w = p * T.nw + tid + 1 + dy * R.G;
+          rr[p][dy] = s_bits[w];
+          xx[p][dy] = L.l > 0 ? (s_bits[w - 1] >> 31) : 0u;
+        }
+      }
+#pragma unroll
+    for (int p = 0; p < kTZ; ++p) {
+      // corner 0 of the cube is (rr[p][0] << 1 | xx[p][0]); its neighbours
+      // along axis 0, 1 and 2 are corners 4, 2 and 1
+      const uint32_t corner0 = (rr[p][0] << 1) | xx[p][0];
+      const bool on = L.valid && p + 1 < T.np;
+      e[p][0] = on ? (corner0 ^ ((rr[p + 1][0] << 1) | xx[p + 1][0])) & L.vmask : 0u;
+      e[p][1] = on ? (corner0 ^ ((rr[p][1] << 1) | xx[p][1])) & L.vmask : 0u;
+      e[p][2] = on ? (corner0 ^ rr[p][0]) & L.vmask : 0u;
+      cnt += __popc(e[p][0]) + __popc(e[p][1]) + __popc(e[p][2]);
     }
-    const int cnt = __popc(e[0]) + __popc(e[1]) + __popc(e[2]);
-    int total;
-    const int off = block_excl_scan256(cnt, s_scan, total);
-    for (int c0 = 0; c0 < total; c0 += kMeshItems) {
-      int idx = off;
+  }
+  int total;
+  const int off = block_excl_scan256(cnt, s_scan, total);
+  for (int c0 = 0; c0 < total; c0 += kMeshItems) {
+    // this thread's items with index in [c0, c0 + kMeshItems): (thread, plane, axis, cube)
+    int idx = off;
+#pragma unroll
+    for (int p = 0; p < kTZ; ++p)
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
-        uint32_t m = e[a];
+        uint32_t m = e[p][a];
+        const int nm = __popc(m);
+        if (idx + nm <= c0 || idx >= c0 + kMeshItems) {
+          idx += nm;
+          continue;
+        }
         while (m && idx < c0 + kMeshItems) {
           const int k = __ffs(m) - 1;
           m &= m - 1u;
-          if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 8) | ((uint32_t)a << 5) | (uint32_t)k;
+          if (idx >= c0)
+            s_items[idx - c0] = ((uint32_t)tid << 10) | ((uint32_t)p << 7) | ((uint32_t)a << 5) | (uint32_t)k;
           ++idx;
         }
       }
-      __syncthreads();
-      const int n = min(kMeshItems, total - c0);
-      for (int i = tid; i < n; i += kBrickThreads) {
-        const uint32_t it = s_items[i];
-        const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), t = (int)(it >> 8);
-        const uint32_t ly = s_ly[t];
-        const int u0 = z, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * (int)(ly >> 20) - 1 + k;
-        const long long row = base + c0 + i;
-        double tv = 0.5;
-        if (DT == 1) {
-          const float* pv = (const float*)R.vol;
-          const double pa = soft_value(pv, R.d, u0, u1, u2);
-          const double pb = soft_value(pv, R.d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
-          tv = (0.5 - pa) / (pb - pa);
-          tsoft[row] = tv;
-        }
-        key[row] = pack_key(u0, u1, u2, a);
-        const double px = ((double)u0 + (a == 0 ? tv : 0.0)) * R.s[0] - M.center[0];
-        const double py = ((double)u1 + (a == 1 ? tv : 0.0)) * R.s[1] - M.center[1];
-        const double pz = ((double)u2 + (a == 2 ? tv : 0.0)) * R.s[2] - M.center[2];
-        const float fx = (float)px, fy = (float)py, fz = (float)pz;
-        const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
-        float* blk = pos + (row >> 4) * 64 + (row & 15);
-        blk[0] = fx;
-        blk[16] = fy;
-        blk[32] = fz;
-        blk[48] = fw;
-        orig[row] = (int)row;
-        rowmax[row] = 0.0f;
+    __syncthreads();
+    const int n = min(kMeshItems, total - c0);
+    for (int i = tid; i < n; i += kBrickThreads) {
+      const uint32_t it = s_items[i];
+      const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), p = (int)((it >> 7) & 7u), t = (int)(it >> 10);
+      const uint32_t ly = s_ly[t];
+      const int u0 = T.pz0 - 1 + p, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * (int)(ly >> 20) - 1 + k;
+      const long long row = base + c0 + i;
+      double tv = 0.5;
+      if (DT == 1) {
+        const float* pv = (const float*)R.vol;
+        const double pa = soft_value(pv, R.d, u0, u1, u2);
+        const double pb = soft_value(pv, R.d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
+        tv = (0.5 - pa) / (pb - pa);
+        tsoft[row] = tv;
       }
-      __syncthreads();
+      key[row] = pack_key(u0, u1, u2, a);
+      const double px = ((double)u0 + (a == 0 ? tv : 0.0)) * R.s[0] - M.center[0];
+      const double py = ((double)u1 + (a == 1 ? tv : 0.0)) * R.s[1] - M.center[1];
+      const double pz = ((double)u2 + (a == 2 ? tv : 0.0)) * R.s[2] - M.center[2];
+      const float fx = (float)px, fy = (float)py, fz = (float)pz;
+      const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
+      float* blk = pos + (row >> 4) * 64 + (row & 15);
+      blk[0] = fx;
+      blk[16] = fy;
+      blk[32] = fz;
+      blk[48] = fw;
+      orig[row] = (int)row;
+      rowmax[row] = 0.0f;
     }
-    base += total;
+    __syncthreads();
   }
 }
 

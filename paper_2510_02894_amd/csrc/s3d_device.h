@@ -16,6 +16,13 @@ __device__ inline long long xcd_remap(long long bid, long long n) {
   return x * per + (x < rem ? x : rem) + idx;
 }
 
+// floor(n / d) for 0 <= n < 2^31 from the precomputed pair m = floor(2^sh / d) + 1,
+// sh = 31 + ceil(log2 d): (n * m) >> sh (the error term n (m - 2^sh / d) / 2^sh
+// stays below 1 / d, so the floor is exact).
+__device__ inline unsigned int fdiv(unsigned int n, unsigned int m, int sh) {
+  return (unsigned int)(((unsigned long long)n * m) >> sh);
+}
+
 // Index of the last ROI whose first brick is <= b (ROIs are sorted by brick_begin).
 __device__ inline int find_roi(const Roi* rois, int n, long long b) {
   int lo = 0, hi = n - 1;

@@ -43,6 +43,10 @@ struct Roi {
   int nrg;                // (d1 + 1) * G
   int nzc;                // z-chunks: ceil((d0 + 1) / kTZ)
   int bpz;                // bricks per z-chunk: ceil(nrg / kBrickThreads)
+  int shG;                // floor(n / G) = (n * mG) >> shG for 0 <= n < 2^31
+  unsigned int mG;
+  unsigned int mNW;       // the same for the tile width kBrickThreads + 1 + G
+  int shNW;
   int pad_;
   long long bucket_base[3];  // first global plane bucket of each axis
 };

@@ -141,11 +141,6 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
 constexpr int kCubeBlock = 4096;   // cubes per workgroup of the edge pass (16 per thread)
 constexpr int kVoxBlock = 256;     // voxels per workgroup of the gather pass (1 per thread)
 
-// floor(n / d) for n < 2^31 with the ROI's precomputed (m, sh): (n * m) >> sh.
-__device__ inline unsigned int fdiv(unsigned int n, unsigned int m, int sh) {
-  return (unsigned int)(((unsigned long long)n * m) >> sh);
-}
-
 // Last ROI whose first element of the given kind is <= x.
 #define S3D_SOFT_ROI_SEARCH(name, member)                                   \
   __device__ inline int name(const SoftBwdRoi* r, int n, long long x) {     \
