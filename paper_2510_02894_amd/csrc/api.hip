@@ -310,7 +310,7 @@ int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0,
   if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
   if ((rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
   // split-f16 operands: 2 KB per 32-row block
-  if (g_tune.kernel == 1 && (rc = ensure(w, w.posh, (size_t)2048 * ((S.rows_bound + 31) / 32)))) return rc;
+  if (g_tune.kernel == 1 && (rc = ensure(w, w.posh, (size_t)1024 * ((S.rows_bound + 31) / 32)))) return rc;
   if ((rc = ensure(w, w.orig, sizeof(int) * S.rows_bound))) return rc;
   if ((rc = ensure(w, w.rowmax, sizeof(float) * S.rows_bound))) return rc;
   if ((rc = ensure(w, w.blkseg, sizeof(int) * (S.rows_bound / kBlk + 1)))) return rc;

@@ -426,13 +426,14 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
 // bound on the error (a few 2^-18 R^2, see k_candidates) is covered by the
 // exact FP64 refinement that follows.
 //
-// Operand layout (posh): per 32-row block, 64 lanes x 16 B of A then 64 lanes
-// x 16 B of B; lane l holds K entries 8*(l/32) .. 8*(l/32)+7 of row l % 32.
+// Operand layout (posh): per 32-row block, 64 lanes x 16 B of B; lane l holds
+// K entries 8*(l/32) .. 8*(l/32)+7 of row l % 32.  The A operand, needed once
+// per work item, is rebuilt from B in registers (a_from_b).
 
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// Builds the split-f16 operands of every row in a segment.
+// Builds the split-f16 B operands of every row in a segment.
 __global__ void k_pack_h(const float* __restrict__ pos, const int* __restrict__ blkseg, const Seg* __restrict__ segs,
                          const RoiMeta* __restrict__ meta, const long long* __restrict__ totals,
                          uint4* __restrict__ posh) {
@@ -452,18 +453,28 @@ __global__ void k_pack_h(const float* __restrict__ pos, const int* __restrict__ 
       l[c] = (_Float16)(x[c] - (float)h[c]);
     }
     const _Float16 wh = (_Float16)w, wl = (_Float16)(w - (float)wh);
-    const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f, m2 = (_Float16)-2.0f;
-    v8h a0 = {m2 * h[0], m2 * h[1], m2 * h[2], m2 * h[0], m2 * h[1], m2 * h[2], m2 * l[0], m2 * l[1]};
-    v8h a1 = {m2 * l[2], wh, wl, one, one, zero, zero, zero};
+    const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f;
     v8h b0 = {h[0], h[1], h[2], l[0], l[1], l[2], h[0], h[1]};
     v8h b1 = {h[2], one, one, wh, wl, zero, zero, zero};
-    uint4* blk = posh + (row >> 5) * 128;
+    uint4* blk = posh + (row >> 5) * 64;
     const int i = (int)(row & 31);
-    blk[i] = *(const uint4*)&a0;
-    blk[32 + i] = *(const uint4*)&a1;
-    blk[64 + i] = *(const uint4*)&b0;
-    blk[96 + i] = *(const uint4*)&b1;
+    blk[i] = *(const uint4*)&b0;
+    blk[32 + i] = *(const uint4*)&b1;
   }
+}
+
+// The A operand of a 32-row block from its B operand, in registers: lanes
+// 0-31 (K 0-7) get -2 [h, h, l0, l1] from their own B entries, lanes 32-63
+// (K 8-15) get [-2 l2, w_hi, w_lo, 1, 1, 0, 0, 0], with l2 taken from the
+// partner lane (lane ^ 32).  Scaling by -2 is exact in f16.
+__device__ __forceinline__ v8h a_from_b(const uint4& u, int lane) {
+  const v8h b = *(const v8h*)&u;
+  const unsigned int pz = __shfl_xor(u.z, 32, 64);  // entries 4, 5 of the partner lane's B
+  const _Float16 l2 = __builtin_bit_cast(_Float16, (unsigned short)(pz >> 16));
+  const _Float16 m2 = (_Float16)-2.0f, one = (_Float16)1.0f, zero = (_Float16)0.0f;
+  const v8h lo = {m2 * b[0], m2 * b[1], m2 * b[2], m2 * b[0], m2 * b[1], m2 * b[2], m2 * b[3], m2 * b[4]};
+  const v8h hi = {m2 * l2, b[3], b[4], one, one, zero, zero, zero};
+  return lane < 32 ? lo : hi;
 }
 
 // 2*IT MFMAs: the IT row blocks against two column blocks, folded into the
@@ -513,8 +524,7 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
       const int blk = min(i0 + r, nb - 1);
-      const uint4 v = posh[(rb + blk) * 128 + lane];
-      A[r] = *(const v8h*)&v;
+      A[r] = a_from_b(posh[(rb + blk) * 64 + lane], lane);
     }
     v16f acc[IT];
 #pragma unroll
@@ -524,14 +534,14 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
 
     // column blocks in pairs, two pairs in flight; indices clamped to the last
     // block of the range (a repeated block is harmless for a maximum)
-    const uint4* Bp = posh + rb * 128 + 64 + lane;
+    const uint4* Bp = posh + rb * 64 + lane;
     const int jl = j1 - 1;
-    uint4 u0 = Bp[(long long)j0 * 128], u1 = Bp[(long long)min(j0 + 1, jl) * 128];
+    uint4 u0 = Bp[(long long)j0 * 64], u1 = Bp[(long long)min(j0 + 1, jl) * 64];
     for (int jb = j0; jb < j1; jb += 4) {
-      const uint4 u2 = Bp[(long long)min(jb + 2, jl) * 128], u3 = Bp[(long long)min(jb + 3, jl) * 128];
+      const uint4 u2 = Bp[(long long)min(jb + 2, jl) * 64], u3 = Bp[(long long)min(jb + 3, jl) * 64];
       pair_tile_h<IT>(A, *(const v8h*)&u0, *(const v8h*)&u1, acc);
-      u0 = Bp[(long long)min(jb + 4, jl) * 128];
-      u1 = Bp[(long long)min(jb + 5, jl) * 128];
+      u0 = Bp[(long long)min(jb + 4, jl) * 64];
+      u1 = Bp[(long long)min(jb + 5, jl) * 64];
       pair_tile_h<IT>(A, *(const v8h*)&u2, *(const v8h*)&u3, acc);
     }
     // D[i][j] sits in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4

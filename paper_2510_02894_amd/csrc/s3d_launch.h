@@ -58,7 +58,7 @@ struct PairBufs {
   const unsigned long long* key;
   const double* tsoft;  // null for binary masks
   float* pos;
-  uint4* posh;          // split-f16 operands, 64 B per row (kernel 1)
+  uint4* posh;          // split-f16 B operands, 32 B per row (kernel 1)
   int* orig;
   float* rowmax;
   int* blkseg;
