@@ -308,8 +308,9 @@ int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0,
   const long long scan_n = std::max(std::max(B.n_buckets, S.rows_bound), std::max(S.seg_cap, S.col_cap));
   if ((rc = ensure(w, w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
   if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
-  if ((rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
-  // split-f16 operands: 2 KB per 32-row block
+  // pair-pass operands: FP32 position blocks (kernel 0, 16 B per row) or
+  // split-f16 B operands (kernel 1, 1 KB per 32-row block)
+  if (g_tune.kernel == 0 && (rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
   if (g_tune.kernel == 1 && (rc = ensure(w, w.posh, (size_t)1024 * ((S.rows_bound + 31) / 32)))) return rc;
   if ((rc = ensure(w, w.orig, sizeof(int) * S.rows_bound))) return rc;
   if ((rc = ensure(w, w.rowmax, sizeof(float) * S.rows_bound))) return rc;
@@ -395,11 +396,10 @@ int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStr
   HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (const BrickPart*)w.part.p,
                          (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
                          (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
-                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, (int*)w.orig.p,
-                         (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
+                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, split_rows(B),
+                         (int*)w.orig.p, (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   if (ev) HIPCK(hipEventRecord(ev[1], st));
   HIPCK(launch_buckets(B, st));
-  HIPCK(launch_pack_operands(B, st));
   HIPCK(launch_init_groups(B, st));
   if (ev) HIPCK(hipEventRecord(ev[2], st));
   HIPCK(launch_pair_maxima(B, st));
@@ -874,8 +874,9 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
   HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, 1, Bt.nbricks, Bt.max_G, (const BrickPart*)w.part.p,
                          (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
                          (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
-                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, (int*)w.orig.p,
-                         (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
+                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p,
+                         g_tune.kernel == 1 ? (uint4*)w.posh.p : nullptr, (int*)w.orig.p, (float*)w.rowmax.p,
+                         (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   HIPCK(launch_export_vertices((const unsigned long long*)w.key.p,
                                dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr, (const RoiMeta*)w.meta.p,
                                (const Roi*)w.rois.p, (long long*)ids, pos, V, st));

@@ -660,7 +660,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
                                                              const unsigned int* __restrict__ overflow,
                                                              unsigned long long* __restrict__ key,
                                                              double* __restrict__ tsoft, float* __restrict__ pos,
-                                                             int* __restrict__ orig, float* __restrict__ rowmax) {
+                                                             uint4* __restrict__ posh, int* __restrict__ orig,
+                                                             float* __restrict__ rowmax) {
   extern __shared__ uint32_t s_bits[];
   __shared__ int s_scan[4];
   __shared__ uint32_t s_items[kMeshItems];
@@ -677,6 +678,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   const Lane L = lane_of(R, T, tid);
   s_ly[tid] = (uint32_t)(L.y + 1) | ((uint32_t)L.l << 20);  // read back by the dense loop (after a barrier)
   const long long base = M.row_off + brick_voff[brick];
+  const int e_split = h_scale_exp(M.R2);  // scale exponent of the split-f16 operands
   // All planes at once, as in the count pass: each thread lists the crossing
   // edges of its 32 cubes for every plane pair, one block scan places them,
   // and the listed edges are written by consecutive threads to consecutive
@@ -754,11 +756,15 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
       const double pz = ((double)u2 + (a == 2 ? tv : 0.0)) * R.s[2] - M.center[2];
       const float fx = (float)px, fy = (float)py, fz = (float)pz;
       const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
-      float* blk = pos + (row >> 4) * 64 + (row & 15);
-      blk[0] = fx;
-      blk[16] = fy;
-      blk[32] = fz;
-      blk[48] = fw;
+      if (posh) {
+        write_split_row(posh, row, fx, fy, fz, fw, e_split);
+      } else {
+        float* blk = pos + (row >> 4) * 64 + (row & 15);
+        blk[0] = fx;
+        blk[16] = fy;
+        blk[32] = fz;
+        blk[48] = fw;
+      }
       orig[row] = (int)row;
       rowmax[row] = 0.0f;
     }
@@ -769,8 +775,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
 // Pads each ROI's layout-0 rows to V_pad with copies of its first row and
 // tags the ROI's blocks with its 3D segment (segment id = roi).
 __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, float* __restrict__ pos,
-                              int* __restrict__ orig, float* __restrict__ rowmax, int* __restrict__ blkseg,
-                              Seg* __restrict__ segs) {
+                              uint4* __restrict__ posh, int* __restrict__ orig, float* __restrict__ rowmax,
+                              int* __restrict__ blkseg, Seg* __restrict__ segs) {
   const int r = blockIdx.x;
   if (r >= n_rois) return;
   const RoiMeta M = meta[r];
@@ -784,13 +790,8 @@ __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, floa
   }
   for (long long i = threadIdx.x; i < M.V_pad / kBlk; i += blockDim.x) blkseg[r0 / kBlk + i] = r;
   if (M.V == 0) return;
-  const float* src = pos + (r0 >> 4) * 64 + (r0 & 15);
   for (long long row = r0 + M.V + threadIdx.x; row < r0 + M.V_pad; row += blockDim.x) {
-    float* dst = pos + (row >> 4) * 64 + (row & 15);
-    dst[0] = src[0];
-    dst[16] = src[16];
-    dst[32] = src[32];
-    dst[48] = src[48];
+    copy_row_operands(pos, posh, r0, row);
     orig[row] = (int)r0;
     rowmax[row] = 0.0f;
   }
@@ -833,17 +834,17 @@ hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta,
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
                             const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
-                            int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st) {
+                            uint4* posh, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st) {
   const size_t lds = mesh_lds_bytes(max_G);
   if (nbricks > 0) {
     if (dtype == 0)
       hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, overflow, key, tsoft, pos, orig, rowmax);
+                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig, rowmax);
     else
       hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, overflow, key, tsoft, pos, orig, rowmax);
+                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig, rowmax);
   }
-  hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, orig, rowmax, blkseg, segs);
+  hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, posh, orig, rowmax, blkseg, segs);
   return hipGetLastError();
 }
 

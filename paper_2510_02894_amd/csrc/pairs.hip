@@ -120,7 +120,8 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
                                  const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
                                  const long long* __restrict__ totals, const unsigned int* __restrict__ bcnt,
                                  unsigned int* __restrict__ bcur, const long long* __restrict__ brow,
-                                 float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax) {
+                                 float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
+                                 float* __restrict__ rowmax) {
   const long long rows0 = totals[T_ROWS0];
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
        row += (long long)gridDim.x * blockDim.x) {
@@ -130,17 +131,11 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
     const unsigned long long k = key[row];
     const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};
     const int a = (int)((k >> 60) & 3);
-    const float* src = pos + (row >> 4) * 64 + (row & 15);
-    const float sx = src[0], sy = src[16], sz = src[32], sw = src[48];
     for (int ax = 0; ax < 3; ++ax) {
       const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
       if (bcnt[b] < 2) continue;
       const long long dst_row = rows0 + brow[b] + wave_aggregated_inc<true>(bcur, b);
-      float* dst = pos + (dst_row >> 4) * 64 + (dst_row & 15);
-      dst[0] = sx;
-      dst[16] = sy;
-      dst[32] = sz;
-      dst[48] = sw;
+      copy_row_operands(pos, posh, row, dst_row);
       orig[dst_row] = (int)row;
       rowmax[dst_row] = 0.0f;
     }
@@ -152,8 +147,9 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
                               const long long* __restrict__ totals,
                               const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                               const long long* __restrict__ brow, const long long* __restrict__ bseg,
-                              float* __restrict__ pos, int* __restrict__ orig, float* __restrict__ rowmax,
-                              int* __restrict__ blkseg, Seg* __restrict__ segs, long long* __restrict__ pairs2d) {
+                              float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
+                              float* __restrict__ rowmax, int* __restrict__ blkseg, Seg* __restrict__ segs,
+                              long long* __restrict__ pairs2d) {
   // one wave per bucket: its lanes tag the blocks and fill the pad rows
   const long long rows0 = totals[T_ROWS0];
   const int lane = threadIdx.x & 63;
@@ -175,15 +171,9 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
       segs[sid] = S;
     }
     for (long long i = lane; i < n / kBlk; i += 64) blkseg[r0 / kBlk + i] = (int)sid;
-    const float* src = pos + (r0 >> 4) * 64 + (r0 & 15);
-    const float sx = src[0], sy = src[16], sz = src[32], sw = src[48];
     const int o = orig[r0];
     for (long long row = r0 + c + lane; row < r0 + n; row += 64) {
-      float* dst = pos + (row >> 4) * 64 + (row & 15);
-      dst[0] = sx;
-      dst[16] = sy;
-      dst[32] = sz;
-      dst[48] = sw;
+      copy_row_operands(pos, posh, r0, row);
       orig[row] = o;
       rowmax[row] = 0.0f;
     }
@@ -430,38 +420,7 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
 // K entries 8*(l/32) .. 8*(l/32)+7 of row l % 32.  The A operand, needed once
 // per work item, is rebuilt from B in registers (a_from_b).
 
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
-
-// Builds the split-f16 B operands of every row in a segment.
-__global__ void k_pack_h(const float* __restrict__ pos, const int* __restrict__ blkseg, const Seg* __restrict__ segs,
-                         const RoiMeta* __restrict__ meta, const long long* __restrict__ totals,
-                         uint4* __restrict__ posh) {
-  const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
-  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
-       row += (long long)gridDim.x * blockDim.x) {
-    const int s = blkseg[row >> 4];
-    if (s < 0) continue;
-    const int e = h_scale_exp(meta[segs[s].group >> 2].R2);
-    const float* src = pos + (row >> 4) * 64 + (row & 15);
-    float x[3] = {ldexpf(src[0], e), ldexpf(src[16], e), ldexpf(src[32], e)};
-    const float w = ldexpf(src[48], 2 * e);
-    _Float16 h[3], l[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      h[c] = (_Float16)x[c];
-      l[c] = (_Float16)(x[c] - (float)h[c]);
-    }
-    const _Float16 wh = (_Float16)w, wl = (_Float16)(w - (float)wh);
-    const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f;
-    v8h b0 = {h[0], h[1], h[2], l[0], l[1], l[2], h[0], h[1]};
-    v8h b1 = {h[2], one, one, wh, wl, zero, zero, zero};
-    uint4* blk = posh + (row >> 5) * 64;
-    const int i = (int)(row & 31);
-    blk[i] = *(const uint4*)&b0;
-    blk[32 + i] = *(const uint4*)&b1;
-  }
-}
 
 // The A operand of a 32-row block from its B operand, in registers: lanes
 // 0-31 (K 0-7) get -2 [h, h, l0, l1] from their own B entries, lanes 32-63
@@ -816,6 +775,10 @@ static unsigned grid_for(long long n, long long cap = 8192) {
   return (unsigned)g;
 }
 
+// The split-f16 operand rows when the pair pass runs kernel 1 (then they are
+// written in place of the FP32 positions), else null.
+uint4* split_rows(const PairBufs& B) { return B.tune.kernel == 1 ? B.posh : nullptr; }
+
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipError_t e;
   if ((e = launch_fill_u32(B.bcnt, 0u, B.n_buckets, st))) return e;
@@ -828,9 +791,10 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.totals, B.bcnt, B.bcur, B.brow, B.pos, B.orig, B.rowmax);
+                     B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig, B.rowmax);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
-                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, B.orig, B.rowmax, B.blkseg, B.segs, B.pairs2d);
+                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.rowmax, B.blkseg, B.segs,
+                     B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.ncol, B.tune.jchunk);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
@@ -852,13 +816,6 @@ hipError_t launch_pair_maxima_it(const PairBufs& B, hipStream_t st) {
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
   hipLaunchKernelGGL(k_pair_maxima<IT>, dim3(grid), dim3(256), 0, st, B.pos, B.segs, B.cols, B.itembase, B.totals,
                      B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_operands(const PairBufs& B, hipStream_t st) {
-  if (B.tune.kernel != 1) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_h, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.pos, B.blkseg, B.segs, B.meta,
-                     B.totals, B.posh);
   return hipGetLastError();
 }
 

@@ -104,6 +104,54 @@ __host__ __device__ inline int h_scale_exp(double R2) {
   return e < -120 ? -120 : (e > 120 ? 120 : e);
 }
 
+// Split-f16 B operand of a row (the pair pass's kernel 1): the centred FP32
+// position (x, y, z) and w = |p|^2, scaled by 2^e and 2^(2e), each split into
+// h = f16(v) and l = f16(v - h).  K entries 0-7 [h, l, h0, h1] and 8-15
+// [h2, 1, 1, w_hi, w_lo, 0, 0, 0] go to lanes row % 32 and 32 + row % 32 of
+// the row's 32-row block (64 x 16 B per block).
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+__device__ inline void write_split_row(uint4* __restrict__ posh, long long row, float fx, float fy, float fz,
+                                       float fw, int e) {
+  const float x[3] = {ldexpf(fx, e), ldexpf(fy, e), ldexpf(fz, e)};
+  const float w = ldexpf(fw, 2 * e);
+  _Float16 h[3], l[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h[c] = (_Float16)x[c];
+    l[c] = (_Float16)(x[c] - (float)h[c]);
+  }
+  const _Float16 wh = (_Float16)w, wl = (_Float16)(w - (float)wh);
+  const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f;
+  const v8h b0 = {h[0], h[1], h[2], l[0], l[1], l[2], h[0], h[1]};
+  const v8h b1 = {h[2], one, one, wh, wl, zero, zero, zero};
+  uint4* blk = posh + (row >> 5) * 64;
+  const int i = (int)(row & 31);
+  blk[i] = *(const uint4*)&b0;
+  blk[32 + i] = *(const uint4*)&b1;
+}
+
+// Copies the pair-pass operands of row src to row dst: the split-f16 B
+// operand when posh is set, else the FP32 position block entries.
+__device__ inline void copy_row_operands(float* __restrict__ pos, uint4* __restrict__ posh, long long src,
+                                         long long dst) {
+  if (posh) {
+    const uint4* s = posh + (src >> 5) * 64 + (src & 31);
+    uint4* d = posh + (dst >> 5) * 64 + (dst & 31);
+    const uint4 a = s[0], b = s[32];
+    d[0] = a;
+    d[32] = b;
+  } else {
+    const float* s = pos + (src >> 4) * 64 + (src & 15);
+    float* d = pos + (dst >> 4) * 64 + (dst & 15);
+    const float a = s[0], b = s[16], c = s[32], w = s[48];
+    d[0] = a;
+    d[16] = b;
+    d[32] = c;
+    d[48] = w;
+  }
+}
+
 // Canonical id 3 * lin_pad(u) + a of a vertex key for a ROI of dims d.
 __device__ inline unsigned long long key_canonical_id(uint64_t key, const int* d) {
   const unsigned long long p2 = key & 0xFFFFF, p1 = (key >> 20) & 0xFFFFF, p0 = (key >> 40) & 0xFFFFF;

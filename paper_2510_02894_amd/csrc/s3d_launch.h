@@ -32,7 +32,7 @@ hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta,
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
                             const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
-                            int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
+                            uint4* posh, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
 
 // scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
 // tmp must hold scan_tmp_elems(n) int64.
@@ -135,8 +135,8 @@ struct SoftBwdBufs {
 hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 
 // pairs.hip
+uint4* split_rows(const PairBufs& B);  // split-f16 operand rows (kernel 1), else null
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list
-hipError_t launch_pack_operands(const PairBufs& B, hipStream_t st); // split-f16 operands (kernel 1 only)
 hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass over the work list
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset per-group results and pair-pass counters
 hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
