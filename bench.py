@@ -47,7 +47,7 @@ def log(*a):
 
 # Sources that define each profiled kernel (the shared headers count for all).
 KERNEL_SOURCES = {
-    "k_pair_maxima_h": ["pairs.hip"], "k_pair_maxima": ["pairs.hip"], "k_pack_h": ["pairs.hip"],
+    "k_pair_maxima_h": ["pairs.hip"], "k_pair_maxima": ["pairs.hip"],
     "k_bucket_scatter": ["pairs.hip"], "k_bucket_hist": ["pairs.hip"],
     "k_mesh_count": ["mesh.hip"], "k_mesh_emit": ["mesh.hip"],
 }
