@@ -610,17 +610,14 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
   }
 }
 
-// Chunks of each candidate's segment (0 beyond the candidate count).
+// Chunks of each candidate's segment, for the candidates found (the scan that
+// follows reads no further).
 __global__ void k_cand_chunks(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
                               const int* __restrict__ blkseg, const Seg* __restrict__ segs,
                               long long* __restrict__ nch, long long cand_cap) {
   const long long nc = min((long long)*ncand_p, cand_cap);
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cand_cap;
-       c += (long long)gridDim.x * blockDim.x) {
-    long long n = 0;
-    if (c < nc) n = (segs[blkseg[cand[c] >> 4]].n_rows + kExactChunk - 1) / kExactChunk;
-    nch[c] = n;
-  }
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x)
+    nch[c] = (segs[blkseg[cand[c] >> 4]].n_rows + kExactChunk - 1) / kExactChunk;
 }
 
 // Exact FP64 rescans of candidate rows.  Work item = (candidate, chunk of its
@@ -869,7 +866,8 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
                      B.tune.kernel == 1 ? 6.103515625e-05 /* 2^-14 */ : 7.62939453125e-06 /* 2^-17 */);
   hipLaunchKernelGGL(k_cand_chunks, dim3(grid_for(B.cand_cap)), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg,
                      B.segs, B.cand_nch, B.cand_cap);
-  if ((e = launch_scan(B.cand_nch, B.cand_chbase, B.cand_cap, B.totals + T_NEXACT, B.scan_tmp, st))) return e;
+  if ((e = launch_scan(B.cand_nch, B.cand_chbase, B.cand_cap, B.totals + T_NEXACT, B.scan_tmp, st, B.counters + 1)))
+    return e;
   const unsigned grid = (unsigned)(B.cu_count * 8);
 #define S3D_EXACT(P)                                                                                             \
   hipLaunchKernelGGL(k_exact<P>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.cand_chbase,             \

@@ -35,10 +35,12 @@ hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nb
                             uint4* posh, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
 
 // scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
-// tmp must hold scan_tmp_elems(n) int64.
+// With n_dev set, only the first min(n, *n_dev) elements are scanned (a count
+// known on the device only): later tiles cost an early exit and their outputs
+// are left unwritten.  tmp must hold scan_tmp_elems(n) int64.
 long long scan_tmp_elems(long long n);
 hipError_t launch_scan(const long long* in, long long* out, long long n, long long* total, long long* tmp,
-                       hipStream_t st);
+                       hipStream_t st, const unsigned int* n_dev = nullptr);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, long long n, hipStream_t st);
 hipError_t launch_fill_i64(long long* p, long long v, long long n, hipStream_t st);
 

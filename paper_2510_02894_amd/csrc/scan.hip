@@ -9,10 +9,23 @@ namespace s3d {
 constexpr int kScanThreads = 256;
 constexpr int kScanPer = kScanTile / kScanThreads;  // 8 consecutive elements per thread
 
+// The number of elements to scan: n, or fewer when the device holds a smaller
+// count (elements past it are treated as absent: their tiles sum to zero and
+// their outputs are not written).
+__device__ inline long long scan_count(long long n, const unsigned int* n_dev) {
+  return n_dev ? min(n, (long long)*n_dev) : n;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const long long* __restrict__ in, long long n,
+                                                              const unsigned int* __restrict__ n_dev,
                                                               long long* __restrict__ blk) {
   __shared__ long long sh[4];
+  n = scan_count(n, n_dev);
   const long long base = (long long)blockIdx.x * kScanTile;
+  if (base >= n && blockIdx.x > 0) {
+    if (threadIdx.x == 0) blk[blockIdx.x] = 0;
+    return;
+  }
   long long s = 0;
   for (int i = 0; i < kScanPer; ++i) {
     const long long idx = base + (long long)i * kScanThreads + threadIdx.x;
@@ -53,9 +66,12 @@ __global__ __launch_bounds__(1024) void k_scan_top(long long* __restrict__ blk, 
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const long long* __restrict__ in, long long n,
+                                                             const unsigned int* __restrict__ n_dev,
                                                              const long long* __restrict__ blk,
                                                              long long* __restrict__ out) {
   __shared__ long long sh[4];
+  n = scan_count(n, n_dev);
+  if ((long long)blockIdx.x * kScanTile >= n) return;  // uniform per workgroup
   const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
   long long v[kScanPer];
   long long s = 0;
@@ -83,12 +99,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const long long* __
 long long scan_tmp_elems(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 hipError_t launch_scan(const long long* in, long long* out, long long n, long long* total, long long* tmp,
-                       hipStream_t st) {
+                       hipStream_t st, const unsigned int* n_dev) {
   const long long nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
-  if (n > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, tmp);
-  else hipLaunchKernelGGL(k_scan_reduce, dim3(1), dim3(kScanThreads), 0, st, in, 0ll, tmp);
+  if (n > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, n_dev, tmp);
+  else hipLaunchKernelGGL(k_scan_reduce, dim3(1), dim3(kScanThreads), 0, st, in, 0ll, n_dev, tmp);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, tmp, nb, total);
-  if (n > 0) hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, tmp, out);
+  if (n > 0) hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, n_dev, tmp, out);
   return hipGetLastError();
 }
 
