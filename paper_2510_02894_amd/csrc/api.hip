@@ -397,10 +397,12 @@ int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStr
                          (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
                          (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
                          dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, split_rows(B),
-                         (int*)w.orig.p, (float*)w.rowmax.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
+                         (int*)w.orig.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   if (ev) HIPCK(hipEventRecord(ev[1], st));
   HIPCK(launch_buckets(B, st));
   HIPCK(launch_init_groups(B, st));
+  // row maxima start at zero (one dense fill over every row the layouts can hold)
+  HIPCK(launch_fill_u32((unsigned int*)B.rowmax, 0u, B.rows_bound, st));
   if (ev) HIPCK(hipEventRecord(ev[2], st));
   HIPCK(launch_pair_maxima(B, st));
   if (ev) HIPCK(hipEventRecord(ev[3], st));
@@ -875,7 +877,7 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
                          (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
                          (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
                          dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p,
-                         g_tune.kernel == 1 ? (uint4*)w.posh.p : nullptr, (int*)w.orig.p, (float*)w.rowmax.p,
+                         g_tune.kernel == 1 ? (uint4*)w.posh.p : nullptr, (int*)w.orig.p,
                          (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   HIPCK(launch_export_vertices((const unsigned long long*)w.key.p,
                                dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr, (const RoiMeta*)w.meta.p,

@@ -660,8 +660,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
                                                              const unsigned int* __restrict__ overflow,
                                                              unsigned long long* __restrict__ key,
                                                              double* __restrict__ tsoft, float* __restrict__ pos,
-                                                             uint4* __restrict__ posh, int* __restrict__ orig,
-                                                             float* __restrict__ rowmax) {
+                                                             uint4* __restrict__ posh, int* __restrict__ orig) {
   extern __shared__ uint32_t s_bits[];
   __shared__ int s_scan[4];
   __shared__ uint32_t s_items[kMeshItems];
@@ -766,7 +765,6 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
         blk[48] = fw;
       }
       orig[row] = (int)row;
-      rowmax[row] = 0.0f;
     }
     __syncthreads();
   }
@@ -775,8 +773,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
 // Pads each ROI's layout-0 rows to V_pad with copies of its first row and
 // tags the ROI's blocks with its 3D segment (segment id = roi).
 __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, float* __restrict__ pos,
-                              uint4* __restrict__ posh, int* __restrict__ orig, float* __restrict__ rowmax,
-                              int* __restrict__ blkseg, Seg* __restrict__ segs) {
+                              uint4* __restrict__ posh, int* __restrict__ orig, int* __restrict__ blkseg,
+                              Seg* __restrict__ segs) {
   const int r = blockIdx.x;
   if (r >= n_rois) return;
   const RoiMeta M = meta[r];
@@ -793,7 +791,6 @@ __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, floa
   for (long long row = r0 + M.V + threadIdx.x; row < r0 + M.V_pad; row += blockDim.x) {
     copy_row_operands(pos, posh, r0, row);
     orig[row] = (int)r0;
-    rowmax[row] = 0.0f;
   }
 }
 
@@ -834,17 +831,17 @@ hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta,
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
                             const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
-                            uint4* posh, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st) {
+                            uint4* posh, int* orig, int* blkseg, Seg* segs, hipStream_t st) {
   const size_t lds = mesh_lds_bytes(max_G);
   if (nbricks > 0) {
     if (dtype == 0)
       hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig, rowmax);
+                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig);
     else
       hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig, rowmax);
+                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig);
   }
-  hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, posh, orig, rowmax, blkseg, segs);
+  hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, posh, orig, blkseg, segs);
   return hipGetLastError();
 }
 

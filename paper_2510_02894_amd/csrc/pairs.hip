@@ -50,8 +50,24 @@ __device__ inline int bucket_roi(const Roi* rois, int n, long long b, int& axis)
 // ---------------------------------------------------------------------------
 // Plane buckets.
 
-template <bool want_old>
-__device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b);
+// Adds 1 to counter[b] for every active lane.  Lanes with the same b form one
+// group served by one atomic of its leader; the groups are found first (ALU
+// only) and then all leaders issue their atomics together.  (Per-lane atomics
+// are slower: lanes of a wave often share a bucket, and colliding atomics
+// serialise in memory.)
+__device__ inline void wave_aggregated_inc(unsigned int* counter, long long b) {
+  unsigned long long todo = __ballot(1);
+  const int lane = threadIdx.x & 63;
+  unsigned int group = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const long long bl = __shfl(b, leader, 64);
+    const unsigned long long same = __ballot(b == bl) & todo;
+    if (lane == leader) group = (unsigned int)__popcll(same);
+    todo &= ~same;
+  }
+  if (group) atomicAdd(&counter[b], group);
+}
 
 __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
                               const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
@@ -68,43 +84,10 @@ __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __res
       const int a = (int)((k >> 60) & 3);
       for (int ax = 0; ax < 3; ++ax) {
         const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
-        wave_aggregated_inc<false>(bcnt, b);
+        wave_aggregated_inc(bcnt, b);
       }
     }
   }
-}
-
-// Adds 1 to counter[b] for every active lane and returns the lane's previous
-// count (or nothing, with want_old = false).  Lanes with the same b form one
-// group served by one atomic of its leader; the groups are found first (ALU
-// only) and then all leaders issue their atomics together, so a wave waits
-// for one atomic round trip however many distinct buckets its lanes hit.
-// (Per-lane atomics are slower: lanes of a wave often share a bucket, and
-// colliding returning atomics serialise in memory.)
-template <bool want_old>
-__device__ inline unsigned int wave_aggregated_inc(unsigned int* counter, long long b) {
-  unsigned long long todo = __ballot(1);
-  const int lane = threadIdx.x & 63;
-  int leader_of_me = lane;
-  unsigned int rank = 0, group = 0;
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const long long bl = __shfl(b, leader, 64);
-    const unsigned long long same = __ballot(b == bl) & todo;
-    if (b == bl) {
-      leader_of_me = leader;
-      rank = (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
-    }
-    if (lane == leader) group = (unsigned int)__popcll(same);
-    todo &= ~same;
-  }
-  if (!want_old) {
-    if (group) atomicAdd(&counter[b], group);
-    return 0u;
-  }
-  unsigned int base = 0;
-  if (group) base = atomicAdd(&counter[b], group);
-  return __shfl(base, leader_of_me, 64) + rank;
 }
 
 __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long nb, long long* __restrict__ bsz,
@@ -120,24 +103,55 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
                                  const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
                                  const long long* __restrict__ totals, const unsigned int* __restrict__ bcnt,
                                  unsigned int* __restrict__ bcur, const long long* __restrict__ brow,
-                                 float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
-                                 float* __restrict__ rowmax) {
+                                 float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig) {
   const long long rows0 = totals[T_ROWS0];
+  const int lane = threadIdx.x & 63;
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
        row += (long long)gridDim.x * blockDim.x) {
     const int roi = blkseg[row >> 4];
     const RoiMeta& M = meta[roi];
-    if (row - M.row_off >= M.V) continue;
-    const unsigned long long k = key[row];
-    const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};
-    const int a = (int)((k >> 60) & 3);
+    long long b[3] = {0, 0, 0};
+    bool on[3] = {false, false, false};
+    if (row - M.row_off < M.V) {
+      const unsigned long long k = key[row];
+      const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};
+      const int a = (int)((k >> 60) & 3);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        b[ax] = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
+        on[ax] = bcnt[b[ax]] >= 2;
+      }
+    }
+    // The three buckets' slots: lanes are grouped per axis by bucket (ALU
+    // only) and the leaders' three atomics are all issued before any result
+    // is used, so a wave waits for one atomic round trip per row batch.
+    unsigned int base[3] = {0u, 0u, 0u}, rank[3] = {0u, 0u, 0u};
+    int lead[3] = {lane, lane, lane};
+#pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
-      if (bcnt[b] < 2) continue;
-      const long long dst_row = rows0 + brow[b] + wave_aggregated_inc<true>(bcur, b);
+      unsigned long long todo = __ballot(on[ax]);
+      unsigned int group = 0;
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const long long bl = __shfl(b[ax], leader, 64);
+        const bool mine = on[ax] && b[ax] == bl;
+        const unsigned long long same = __ballot(mine) & todo;
+        if (mine) {
+          lead[ax] = leader;
+          rank[ax] = (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) group = (unsigned int)__popcll(same);
+        todo &= ~same;
+      }
+      if (group) base[ax] = atomicAdd(&bcur[b[ax]], group);
+    }
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const unsigned int slot = __shfl(base[ax], lead[ax], 64) + rank[ax];
+      if (!on[ax]) continue;
+      const long long dst_row = rows0 + brow[b[ax]] + slot;
       copy_row_operands(pos, posh, row, dst_row);
       orig[dst_row] = (int)row;
-      rowmax[dst_row] = 0.0f;
     }
   }
 }
@@ -148,7 +162,7 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
                               const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                               const long long* __restrict__ brow, const long long* __restrict__ bseg,
                               float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
-                              float* __restrict__ rowmax, int* __restrict__ blkseg, Seg* __restrict__ segs,
+                              int* __restrict__ blkseg, Seg* __restrict__ segs,
                               long long* __restrict__ pairs2d) {
   // one wave per bucket: its lanes tag the blocks and fill the pad rows
   const long long rows0 = totals[T_ROWS0];
@@ -175,7 +189,6 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
     for (long long row = r0 + c + lane; row < r0 + n; row += 64) {
       copy_row_operands(pos, posh, r0, row);
       orig[row] = o;
-      rowmax[row] = 0.0f;
     }
   }
 }
@@ -416,9 +429,11 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
 // bound on the error (a few 2^-18 R^2, see k_candidates) is covered by the
 // exact FP64 refinement that follows.
 //
-// Operand layout (posh): per 32-row block, 64 lanes x 16 B of B; lane l holds
-// K entries 8*(l/32) .. 8*(l/32)+7 of row l % 32.  The A operand, needed once
-// per work item, is rebuilt from B in registers (a_from_b).
+// Operand layout (posh): 32 B per row, the B operand's K entries 0-7 then
+// 8-15 (write_split_row); lane l of a wave takes K entries 8*(l/32) ..
+// 8*(l/32)+7 of row l % 32, so a 32-row block is one contiguous 1 KB load.
+// The A operand, needed once per work item, is rebuilt from B in registers
+// (a_from_b).
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 
@@ -483,7 +498,7 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
 #pragma unroll
     for (int r = 0; r < IT; ++r) {
       const int blk = min(i0 + r, nb - 1);
-      A[r] = a_from_b(posh[(rb + blk) * 64 + lane], lane);
+      A[r] = a_from_b(posh[(rb + blk) * 64 + split_lane_index(lane)], lane);
     }
     v16f acc[IT];
 #pragma unroll
@@ -493,7 +508,7 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
 
     // column blocks in pairs, two pairs in flight; indices clamped to the last
     // block of the range (a repeated block is harmless for a maximum)
-    const uint4* Bp = posh + rb * 64 + lane;
+    const uint4* Bp = posh + rb * 64 + split_lane_index(lane);
     const int jl = j1 - 1;
     uint4 u0 = Bp[(long long)j0 * 64], u1 = Bp[(long long)min(j0 + 1, jl) * 64];
     for (int jb = j0; jb < j1; jb += 4) {
@@ -588,24 +603,40 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
                              unsigned int* __restrict__ ncand, int* __restrict__ cand, long long cand_cap,
                              double band) {
   const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
+  const int lane = threadIdx.x & 63;
+  // rows_total is a multiple of 32, so a wave's lanes leave the loop together
+  // or in two halves; the ballot below only counts the lanes still in it
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
        row += (long long)gridDim.x * blockDim.x) {
+    bool is = false;
+    int g = 0;
     const int s = blkseg[row >> 4];
-    if (s < 0) continue;
-    const Seg S = segs[s];
-    if (row - S.row_begin >= S.n_rows || S.n_rows == 0) continue;
-    const int g = S.group;
-    const float gm = gres[g].gmax;
-    if (!(gm > 0.0f)) continue;
-    // A pair value of the MFMA pass differs from the exact squared distance by
-    // less than half of band * max(R^2, d2) (FP32 Gram form: 2^-18; split f16:
-    // 2^-16, see the pass); keep every row within that band of the group maximum.
-    const double R2 = meta[g >> 2].R2;
-    const float tau = (float)((double)gm - band * (R2 > (double)gm ? R2 : (double)gm));
-    if (rowmax[row] >= tau) {
-      const unsigned int idx = atomicAdd(ncand, 1u);
-      if (idx < cand_cap) cand[idx] = (int)row;
-      atomicAdd(&gres[g].n_cand, 1);
+    if (s >= 0) {
+      const Seg S = segs[s];
+      g = S.group;
+      const float gm = S.n_rows > 0 && row - S.row_begin < S.n_rows ? gres[g].gmax : 0.0f;
+      if (gm > 0.0f) {
+        // A pair value of the MFMA pass differs from the exact squared distance
+        // by less than half of band * max(R^2, d2) (FP32 Gram form: 2^-18; split
+        // f16: 2^-16, see the pass); keep every row within that band of the
+        // group maximum.
+        const double R2 = meta[g >> 2].R2;
+        const float tau = (float)((double)gm - band * (R2 > (double)gm ? R2 : (double)gm));
+        is = rowmax[row] >= tau;
+      }
+    }
+    // one append per wave: the leader reserves the wave's slots
+    const unsigned long long m = __ballot(is);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned int base = 0;
+      if (lane == leader) base = atomicAdd(ncand, (unsigned int)__popcll(m));
+      base = __shfl(base, leader, 64);
+      if (is) {
+        const unsigned int idx = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+        if (idx < cand_cap) cand[idx] = (int)row;
+        atomicAdd(&gres[g].n_cand, 1);
+      }
     }
   }
 }
@@ -788,9 +819,9 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig, B.rowmax);
+                     B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
-                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.rowmax, B.blkseg, B.segs,
+                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
                      B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.ncol, B.tune.jchunk);

@@ -106,9 +106,11 @@ __host__ __device__ inline int h_scale_exp(double R2) {
 
 // Split-f16 B operand of a row (the pair pass's kernel 1): the centred FP32
 // position (x, y, z) and w = |p|^2, scaled by 2^e and 2^(2e), each split into
-// h = f16(v) and l = f16(v - h).  K entries 0-7 [h, l, h0, h1] and 8-15
-// [h2, 1, 1, w_hi, w_lo, 0, 0, 0] go to lanes row % 32 and 32 + row % 32 of
-// the row's 32-row block (64 x 16 B per block).
+// h = f16(v) and l = f16(v - h).  A row is 32 contiguous bytes: K entries 0-7
+// [h, l, h0, h1] (read by lane row % 32 of the MFMA) and then K entries 8-15
+// [h2, 1, 1, w_hi, w_lo, 0, 0, 0] (read by lane 32 + row % 32), so lane l of
+// a wave reads uint4 2 (l % 32) + l / 32 of the 32-row block: one contiguous
+// 1 KB load per block, and one 32-byte record per row to copy.
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 __device__ inline void write_split_row(uint4* __restrict__ posh, long long row, float fx, float fy, float fz,
@@ -125,22 +127,25 @@ __device__ inline void write_split_row(uint4* __restrict__ posh, long long row, 
   const _Float16 one = (_Float16)1.0f, zero = (_Float16)0.0f;
   const v8h b0 = {h[0], h[1], h[2], l[0], l[1], l[2], h[0], h[1]};
   const v8h b1 = {h[2], one, one, wh, wl, zero, zero, zero};
-  uint4* blk = posh + (row >> 5) * 64;
-  const int i = (int)(row & 31);
-  blk[i] = *(const uint4*)&b0;
-  blk[32 + i] = *(const uint4*)&b1;
+  uint4* r = posh + 2 * row;
+  r[0] = *(const uint4*)&b0;
+  r[1] = *(const uint4*)&b1;
 }
+
+// uint4 index, within a 32-row block of split-f16 operand rows, that lane l
+// passes to the MFMA.
+__device__ inline int split_lane_index(int lane) { return 2 * (lane & 31) + (lane >> 5); }
 
 // Copies the pair-pass operands of row src to row dst: the split-f16 B
 // operand when posh is set, else the FP32 position block entries.
 __device__ inline void copy_row_operands(float* __restrict__ pos, uint4* __restrict__ posh, long long src,
                                          long long dst) {
   if (posh) {
-    const uint4* s = posh + (src >> 5) * 64 + (src & 31);
-    uint4* d = posh + (dst >> 5) * 64 + (dst & 31);
-    const uint4 a = s[0], b = s[32];
+    const uint4* s = posh + 2 * src;
+    uint4* d = posh + 2 * dst;
+    const uint4 a = s[0], b = s[1];
     d[0] = a;
-    d[32] = b;
+    d[1] = b;
   } else {
     const float* s = pos + (src >> 4) * 64 + (src & 15);
     float* d = pos + (dst >> 4) * 64 + (dst & 15);

@@ -32,7 +32,7 @@ hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta,
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
                             const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
-                            uint4* posh, int* orig, float* rowmax, int* blkseg, Seg* segs, hipStream_t st);
+                            uint4* posh, int* orig, int* blkseg, Seg* segs, hipStream_t st);
 
 // scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
 // With n_dev set, only the first min(n, *n_dev) elements are scanned (a count
