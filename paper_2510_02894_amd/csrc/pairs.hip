@@ -195,11 +195,12 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
 
 // Columns (chunks of jchunk row blocks) per segment.
 __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __restrict__ totals,
-                           const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk) {
+                           const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk, int small_rows) {
   const long long nseg = n_rois + totals[T_NSEG2D];
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < seg_cap;
        s += (long long)gridDim.x * blockDim.x) {
-    const long long rows = s < nseg ? segs[s].n_rows : 0;
+    long long rows = s < nseg ? segs[s].n_rows : 0;
+    if (s >= n_rois && rows <= small_rows) rows = 0;  // a small bucket: k_pair_small_h
     ncol[s] = (rows + (long long)jchunk * kBlk - 1) / ((long long)jchunk * kBlk);
   }
 }
@@ -469,6 +470,71 @@ __device__ __forceinline__ void pair_tile_h(const v8h (&A)[IT], const v8h& b0, c
   }
 }
 
+// One tile of the split-f16 pair pass: 32-row blocks i0 .. i0 + IT - 1 of the
+// segment starting at block rb (nb blocks) against its column blocks
+// [j0, j1), folded into the row maxima (scale exponent e of the ROI).
+template <int IT>
+__device__ __forceinline__ void pair_item_h(const uint4* __restrict__ posh, float* __restrict__ rowmax, long long rb,
+                                            int nb, int i0, int j0, int j1, int e, int lane) {
+  v8h A[IT];
+#pragma unroll
+  for (int r = 0; r < IT; ++r) {
+    const int blk = min(i0 + r, nb - 1);
+    A[r] = a_from_b(posh[(rb + blk) * 64 + split_lane_index(lane)], lane);
+  }
+  v16f acc[IT];
+#pragma unroll
+  for (int r = 0; r < IT; ++r)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[r][q] = -3.0e38f;
+
+  // column blocks in pairs, two pairs in flight; indices clamped to the last
+  // block of the range (a repeated block is harmless for a maximum)
+  const uint4* Bp = posh + rb * 64 + split_lane_index(lane);
+  const int jl = j1 - 1;
+  uint4 u0 = Bp[(long long)j0 * 64], u1 = Bp[(long long)min(j0 + 1, jl) * 64];
+  for (int jb = j0; jb < j1; jb += 4) {
+    const uint4 u2 = Bp[(long long)min(jb + 2, jl) * 64], u3 = Bp[(long long)min(jb + 3, jl) * 64];
+    pair_tile_h<IT>(A, *(const v8h*)&u0, *(const v8h*)&u1, acc);
+    u0 = Bp[(long long)min(jb + 4, jl) * 64];
+    u1 = Bp[(long long)min(jb + 5, jl) * 64];
+    pair_tile_h<IT>(A, *(const v8h*)&u2, *(const v8h*)&u3, acc);
+  }
+  // D[i][j] sits in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4
+  // of acc[r]: reduce over j (the low 5 lane bits) with a butterfly that
+  // halves the registers at every step (lane bit s keeps one half and sends
+  // the other), 62 shuffles for 64 registers.  Afterwards a lane holds the
+  // maxima of registers t + 2 * rev5(lane & 31), t = 0, 1, of the flat
+  // index r * 16 + q; then undo the scale.
+  float v[16 * IT];
+#pragma unroll
+  for (int r = 0; r < IT; ++r)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[16 * r + q] = acc[r][q];
+#pragma unroll
+  for (int st = 0; st < 5; ++st) {
+    const int h = (16 * IT) >> (st + 1);
+    const bool hi = (lane >> st) & 1;
+#pragma unroll
+    for (int t = 0; t < h; ++t) {
+      const float keep = hi ? v[t + h] : v[t], send = hi ? v[t] : v[t + h];
+      v[t] = fmaxf(keep, __shfl_xor(send, 1 << st, 64));
+    }
+  }
+  const int rev = ((lane & 1) << 4) | ((lane & 2) << 2) | (lane & 4) | ((lane & 8) >> 2) | ((lane & 16) >> 4);
+  const float unscale = ldexpf(1.0f, -2 * e);
+#pragma unroll
+  for (int t = 0; t < (16 * IT) / 32; ++t) {
+    const int flat = t + ((16 * IT) / 32) * rev;  // register index r * 16 + q
+    const int r = flat >> 4, q = flat & 15;
+    if (i0 + r >= nb) continue;
+    const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+    const long long row = (rb + i0 + r) * 32 + i;
+    const float val = fmaxf(v[t], 0.0f) * unscale;
+    atomicMax((int*)&rowmax[row], __float_as_int(val));
+  }
+}
+
 // Work items as for k_pair_maxima with itile = 2 * IT 16-row blocks: IT
 // 32-row blocks of A against the column chunk's 32-row blocks of B.
 template <int IT>
@@ -486,6 +552,7 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
     where.locate(item);
     const Col C = cols[where.col];
     const Seg S = segs[C.seg];
+    const int e = h_scale_exp(meta[S.group >> 2].R2);
     const int it = (int)(item - where.col_lo);
     // 32-row block coordinates (segments start and end on 32-row boundaries)
     const long long rb = S.row_begin >> 5;
@@ -493,65 +560,36 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
     const int i0 = it * IT;
     const int j0 = max(C.jc * (jchunk >> 1), i0);
     const int j1 = min((C.jc + 1) * (jchunk >> 1), nb);
+    pair_item_h<IT>(posh, rowmax, rb, nb, i0, j0, j1, e, lane);
+  }
+}
 
-    v8h A[IT];
+// Plane buckets of at most kSmallBlocks 32-row blocks (most of them), which the
+// work list leaves out: a wave takes kSmallPerWave consecutive bucket segments
+// and runs their row tiles directly, without the work counter and the column
+// look-ups, whose chain of dependent loads dominated such small items.
+template <int IT>
+__global__ __launch_bounds__(256) void k_pair_small_h(const uint4* __restrict__ posh, const Seg* __restrict__ segs,
+                                                      int n_rois, const long long* __restrict__ totals,
+                                                      const RoiMeta* __restrict__ meta, float* __restrict__ rowmax) {
+  const int lane = threadIdx.x & 63;
+  const long long nseg2d = totals[T_NSEG2D];
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long s0 = wave * kSmallPerWave;
+  if (s0 >= nseg2d) return;
+  Seg S[kSmallPerWave];
 #pragma unroll
-    for (int r = 0; r < IT; ++r) {
-      const int blk = min(i0 + r, nb - 1);
-      A[r] = a_from_b(posh[(rb + blk) * 64 + split_lane_index(lane)], lane);
-    }
-    v16f acc[IT];
+  for (int k = 0; k < kSmallPerWave; ++k) {
+    S[k].n_rows = 0;
+    if (s0 + k < nseg2d) S[k] = segs[n_rois + s0 + k];
+  }
 #pragma unroll
-    for (int r = 0; r < IT; ++r)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[r][q] = -3.0e38f;
-
-    // column blocks in pairs, two pairs in flight; indices clamped to the last
-    // block of the range (a repeated block is harmless for a maximum)
-    const uint4* Bp = posh + rb * 64 + split_lane_index(lane);
-    const int jl = j1 - 1;
-    uint4 u0 = Bp[(long long)j0 * 64], u1 = Bp[(long long)min(j0 + 1, jl) * 64];
-    for (int jb = j0; jb < j1; jb += 4) {
-      const uint4 u2 = Bp[(long long)min(jb + 2, jl) * 64], u3 = Bp[(long long)min(jb + 3, jl) * 64];
-      pair_tile_h<IT>(A, *(const v8h*)&u0, *(const v8h*)&u1, acc);
-      u0 = Bp[(long long)min(jb + 4, jl) * 64];
-      u1 = Bp[(long long)min(jb + 5, jl) * 64];
-      pair_tile_h<IT>(A, *(const v8h*)&u2, *(const v8h*)&u3, acc);
-    }
-    // D[i][j] sits in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4
-    // of acc[r]: reduce over j (the low 5 lane bits) with a butterfly that
-    // halves the registers at every step (lane bit s keeps one half and sends
-    // the other), 62 shuffles for 64 registers.  Afterwards a lane holds the
-    // maxima of registers t + 2 * rev5(lane & 31), t = 0, 1, of the flat
-    // index r * 16 + q; then undo the scale.
-    float v[16 * IT];
-#pragma unroll
-    for (int r = 0; r < IT; ++r)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) v[16 * r + q] = acc[r][q];
-#pragma unroll
-    for (int st = 0; st < 5; ++st) {
-      const int h = (16 * IT) >> (st + 1);
-      const bool hi = (lane >> st) & 1;
-#pragma unroll
-      for (int t = 0; t < h; ++t) {
-        const float keep = hi ? v[t + h] : v[t], send = hi ? v[t] : v[t + h];
-        v[t] = fmaxf(keep, __shfl_xor(send, 1 << st, 64));
-      }
-    }
-    const int rev = ((lane & 1) << 4) | ((lane & 2) << 2) | (lane & 4) | ((lane & 8) >> 2) | ((lane & 16) >> 4);
-    const int e = h_scale_exp(meta[S.group >> 2].R2);
-    const float unscale = ldexpf(1.0f, -2 * e);
-#pragma unroll
-    for (int t = 0; t < (16 * IT) / 32; ++t) {
-      const int flat = t + ((16 * IT) / 32) * rev;  // register index r * 16 + q
-      const int r = flat >> 4, q = flat & 15;
-      if (i0 + r >= nb) continue;
-      const int i = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
-      const long long row = (rb + i0 + r) * 32 + i;
-      const float val = fmaxf(v[t], 0.0f) * unscale;
-      atomicMax((int*)&rowmax[row], __float_as_int(val));
-    }
+  for (int k = 0; k < kSmallPerWave; ++k) {
+    const int nb = S[k].n_rows >> 5;
+    if (nb == 0 || nb > kSmallBlocks) continue;
+    const int e = h_scale_exp(meta[S[k].group >> 2].R2);
+    const long long rb = S[k].row_begin >> 5;
+    for (int i0 = 0; i0 < nb; i0 += IT) pair_item_h<IT>(posh, rowmax, rb, nb, i0, i0, nb, e, lane);
   }
 }
 
@@ -803,6 +841,11 @@ static unsigned grid_for(long long n, long long cap = 8192) {
   return (unsigned)g;
 }
 
+// Whether small plane buckets go to k_pair_small_h: split-f16 kernel, and
+// enough buckets that the extra launch (about 15 us on a single small ROI)
+// is paid back by the work-list items it saves (about 1 ms on 4,096 ROIs).
+static bool small_buckets(const PairBufs& B) { return B.tune.kernel == 1 && B.n_buckets >= kSmallMinBuckets; }
+
 // The split-f16 operand rows when the pair pass runs kernel 1 (then they are
 // written in place of the FP32 positions), else null.
 uint4* split_rows(const PairBufs& B) { return B.tune.kernel == 1 ? B.posh : nullptr; }
@@ -824,7 +867,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
                      B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
-                     B.ncol, B.tune.jchunk);
+                     B.ncol, B.tune.jchunk, small_buckets(B) ? kSmallBlocks * 32 : 0);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
   if ((e = launch_fill_i64(B.nitem, 0, B.col_cap, st))) return e;
   hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
@@ -857,6 +900,13 @@ hipError_t launch_pair_maxima_h(const PairBufs& B, hipStream_t st) {
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
   hipLaunchKernelGGL(k_pair_maxima_h<IT>, dim3(grid), dim3(256), 0, st, B.posh, B.segs, B.cols, B.itembase,
                      B.totals, B.meta, B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
+  // small plane buckets (bucket count bounded by n_buckets on the host), in
+  // tiles of two row blocks: 124 VGPRs, four waves per SIMD for this
+  // latency-bound kernel
+  const long long waves = (B.n_buckets + kSmallPerWave - 1) / kSmallPerWave;
+  if (small_buckets(B) && waves > 0)
+    hipLaunchKernelGGL(k_pair_small_h<2>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, B.posh, B.segs,
+                       B.n_rois, B.totals, B.meta, B.rowmax);
   return hipGetLastError();
 }
 
