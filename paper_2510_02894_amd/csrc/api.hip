@@ -64,7 +64,7 @@ struct Workspace {
   int cu_count = 0;
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
-      bseg, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
+      bseg, bgroup, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
       posh, case_area, soft_rois, soft_edges, soft_field, soft_ctr;
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
@@ -79,7 +79,7 @@ struct Workspace {
 
   std::vector<Buf*> all() {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
-            &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &ncol,     &colbase,
+            &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &bgroup, &ncol,     &colbase,
             &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
             &cand_chbase, &posh, &case_area, &soft_rois, &soft_edges, &soft_field, &soft_ctr};
   }
@@ -287,6 +287,7 @@ int ensure_layout_bufs(Workspace& w, const Batch& B) {
   if ((rc = ensure(w, w.bflag, sizeof(long long) * B.n_buckets))) return rc;
   if ((rc = ensure(w, w.brow, sizeof(long long) * B.n_buckets))) return rc;
   if ((rc = ensure(w, w.bseg, sizeof(long long) * B.n_buckets))) return rc;
+  if ((rc = ensure(w, w.bgroup, sizeof(int) * B.n_buckets))) return rc;
   // pinned staging: [0, 4096) read-backs, then the ROI table, then the results
   const size_t host_need = 4096 + sizeof(Roi) * (size_t)n + 256 + sizeof(RoiResult) * (size_t)n;
   if ((rc = ensure_host(w, host_need))) return rc;
@@ -349,6 +350,7 @@ PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
   B.bcur = (unsigned int*)w.bcur.p;
   B.bsz = (long long*)w.bsz.p;
   B.bflag = (long long*)w.bflag.p;
+  B.bgroup = (int*)w.bgroup.p;
   B.brow = (long long*)w.brow.p;
   B.bseg = (long long*)w.bseg.p;
   B.seg_cap = S.seg_cap;

@@ -34,19 +34,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 enum { T_ROWS0 = 0, T_VMAX = 1, T_ROWS2D = 2, T_NSEG2D = 3, T_NCOL = 4, T_NITEM = 5, T_NEXACT = 6 };
 
-__device__ inline int bucket_roi(const Roi* rois, int n, long long b, int& axis) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (rois[mid].bucket_base[0] <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  axis = (b >= rois[lo].bucket_base[2]) ? 2 : (b >= rois[lo].bucket_base[1] ? 1 : 0);
-  return lo;
-}
-
 // ---------------------------------------------------------------------------
 // Plane buckets.
 
@@ -156,8 +143,21 @@ __global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __
   }
 }
 
+// The group (roi * 4 + 1 + axis) of every plane bucket: one workgroup per ROI
+// over its contiguous bucket range (so the segment pass needs no search of
+// the ROI table).
+__global__ void k_bucket_groups(const Roi* __restrict__ rois, int* __restrict__ bgroup) {
+  const Roi& R = rois[blockIdx.x];
+  const long long b0 = R.bucket_base[0];
+  const long long b1 = R.bucket_base[2] + 2ll * R.d[2] + 1;
+  for (long long b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+    const int axis = b >= R.bucket_base[2] ? 2 : (b >= R.bucket_base[1] ? 1 : 0);
+    bgroup[b] = (int)blockIdx.x * 4 + 1 + axis;
+  }
+}
+
 // Segments of the buckets: pad rows, block tags and the segment table.
-__global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long long nb,
+__global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long long nb,
                               const long long* __restrict__ totals,
                               const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                               const long long* __restrict__ brow, const long long* __restrict__ bseg,
@@ -175,13 +175,12 @@ __global__ void k_bucket_segs(const Roi* __restrict__ rois, int n_rois, long lon
     const long long r0 = rows0 + brow[b];
     const long long n = bsz[b];
     if (lane == 0) {
-      int axis;
-      const int roi = bucket_roi(rois, n_rois, b, axis);
-      atomicAdd((unsigned long long*)&pairs2d[roi], (unsigned long long)c * (c - 1) / 2);
+      const int group = bgroup[b];
+      atomicAdd((unsigned long long*)&pairs2d[group >> 2], (unsigned long long)c * (c - 1) / 2);
       Seg S;
       S.row_begin = r0;
       S.n_rows = (int)n;
-      S.group = roi * 4 + 1 + axis;
+      S.group = group;
       segs[sid] = S;
     }
     for (long long i = lane; i < n / kBlk; i += 64) blkseg[r0 / kBlk + i] = (int)sid;
@@ -640,42 +639,58 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
                              const long long* __restrict__ totals, GroupRes* __restrict__ gres,
                              unsigned int* __restrict__ ncand, int* __restrict__ cand, long long cand_cap,
                              double band) {
-  const long long rows_total = totals[T_ROWS0] + totals[T_ROWS2D];
+  // A thread per 16-row block (a block lies in one segment: one threshold and
+  // one set of look-ups for its 16 rows); a wave reserves its candidates'
+  // slots with one atomic.
+  const long long nblk = (totals[T_ROWS0] + totals[T_ROWS2D]) / kBlk;
   const int lane = threadIdx.x & 63;
-  // rows_total is a multiple of 32, so a wave's lanes leave the loop together
-  // or in two halves; the ballot below only counts the lanes still in it
-  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows_total;
-       row += (long long)gridDim.x * blockDim.x) {
-    bool is = false;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long base = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < nblk; base += stride) {
+    const long long blk = base + lane;
+    unsigned int mask = 0u;
     int g = 0;
-    const int s = blkseg[row >> 4];
+    const int s = blk < nblk ? blkseg[blk] : -1;
     if (s >= 0) {
       const Seg S = segs[s];
       g = S.group;
-      const float gm = S.n_rows > 0 && row - S.row_begin < S.n_rows ? gres[g].gmax : 0.0f;
+      const float gm = S.n_rows > 0 ? gres[g].gmax : 0.0f;
       if (gm > 0.0f) {
-        // A pair value of the MFMA pass differs from the exact squared distance
-        // by less than half of band * max(R^2, d2) (FP32 Gram form: 2^-18; split
-        // f16: 2^-16, see the pass); keep every row within that band of the
-        // group maximum.
+        // A pair value of the MFMA pass differs from the exact squared
+        // distance by less than half of band * max(R^2, d2) (FP32 Gram form:
+        // 2^-18; split f16: 2^-16, see the pass); keep every row within that
+        // band of the group maximum.
         const double R2 = meta[g >> 2].R2;
         const float tau = (float)((double)gm - band * (R2 > (double)gm ? R2 : (double)gm));
-        is = rowmax[row] >= tau;
+        const float4* p = (const float4*)(rowmax + blk * kBlk);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = p[q];
+          mask |= ((unsigned int)(v.x >= tau) | ((unsigned int)(v.y >= tau) << 1) |
+                   ((unsigned int)(v.z >= tau) << 2) | ((unsigned int)(v.w >= tau) << 3))
+                  << (4 * q);
+        }
       }
     }
-    // one append per wave: the leader reserves the wave's slots
-    const unsigned long long m = __ballot(is);
-    if (m) {
-      const int leader = __ffsll((long long)m) - 1;
-      unsigned int base = 0;
-      if (lane == leader) base = atomicAdd(ncand, (unsigned int)__popcll(m));
-      base = __shfl(base, leader, 64);
-      if (is) {
-        const unsigned int idx = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
-        if (idx < cand_cap) cand[idx] = (int)row;
-        atomicAdd(&gres[g].n_cand, 1);
-      }
+    const int cnt = __popc(mask);
+    int inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
     }
+    const int total = __shfl(inc, 63, 64);
+    if (total == 0) continue;
+    unsigned int first = 0;
+    if (lane == 63) first = atomicAdd(ncand, (unsigned int)total);
+    first = __shfl(first, 63, 64);
+    unsigned int idx = first + (unsigned int)(inc - cnt);
+    while (mask) {
+      const int i = __ffs(mask) - 1;
+      mask &= mask - 1u;
+      if (idx < cand_cap) cand[idx] = (int)(blk * kBlk + i);
+      ++idx;
+    }
+    if (cnt) atomicAdd(&gres[g].n_cand, cnt);
   }
 }
 
@@ -863,7 +878,8 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
                      B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig);
-  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.rois, B.n_rois, B.n_buckets,
+  hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup);
+  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
                      B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
@@ -942,7 +958,7 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
   hipError_t e;
   hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound / kBlk, 1024)), dim3(256), 0, st, B.rowmax, B.blkseg,
                      B.segs, B.totals, B.gres);
-  hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
+  hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound / kBlk)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
                      B.meta, B.totals, B.gres, B.counters + 1, B.cand, B.cand_cap,
                      B.tune.kernel == 1 ? 6.103515625e-05 /* 2^-14 */ : 7.62939453125e-06 /* 2^-17 */);
   hipLaunchKernelGGL(k_cand_chunks, dim3(grid_for(B.cand_cap)), dim3(256), 0, st, B.cand, B.counters + 1, B.blkseg,

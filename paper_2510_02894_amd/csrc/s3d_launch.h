@@ -73,6 +73,7 @@ struct PairBufs {
   long long* bflag;     // [n_buckets]
   long long* brow;      // [n_buckets]
   long long* bseg;      // [n_buckets]
+  int* bgroup;          // [n_buckets] group roi * 4 + 1 + axis of each plane bucket
   long long seg_cap;    // n_rois + n_buckets
   long long* ncol;      // [seg_cap]
   long long* colbase;   // [seg_cap]
