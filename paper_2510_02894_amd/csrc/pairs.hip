@@ -207,20 +207,26 @@ __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __res
 // Column table and items per column: items of column jc of a segment are the
 // row tiles (itile blocks) that start before the column ends (upper triangle).
 __global__ void k_col_fill(int n_rois, long long seg_cap, const long long* __restrict__ totals,
-                           const Seg* __restrict__ segs, const long long* __restrict__ ncol,
+                           const Seg* __restrict__ segs, const RoiMeta* __restrict__ meta,
+                           const long long* __restrict__ ncol,
                            const long long* __restrict__ colbase, Col* __restrict__ cols,
                            long long* __restrict__ nitem, int itile, int jchunk) {
   const long long nseg = n_rois + totals[T_NSEG2D];
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += (long long)gridDim.x * blockDim.x) {
     const long long nc = ncol[s];
     if (nc == 0) continue;
-    const long long nblk = segs[s].n_rows / kBlk;
+    const Seg S = segs[s];
+    const long long nblk = S.n_rows / kBlk;
     const long long nt = (nblk + itile - 1) / itile;
+    const int e = h_scale_exp(meta[S.group >> 2].R2);
     for (long long jc = 0; jc < nc; ++jc) {
       const long long c = colbase[s] + jc;
       Col C;
-      C.seg = (int)s;
+      C.row_begin = S.row_begin;
+      C.n_rows = S.n_rows;
+      C.group = S.group;
       C.jc = (int)jc;
+      C.e = e;
       cols[c] = C;
       const long long lim = (jc + 1) * (jchunk / itile);
       nitem[c] = nt < lim ? nt : lim;
@@ -347,8 +353,7 @@ __device__ __forceinline__ void pair_tile(const float (&A)[IT], float b0, float 
 }
 
 template <int IT>
-__global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ pos, const Seg* __restrict__ segs,
-                                                     const Col* __restrict__ cols,
+__global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ pos, const Col* __restrict__ cols,
                                                      const long long* __restrict__ itembase,
                                                      const long long* __restrict__ totals,
                                                      unsigned int* __restrict__ work_ctr, float* __restrict__ rowmax,
@@ -359,10 +364,9 @@ __global__ __launch_bounds__(256) void k_pair_maxima(const float* __restrict__ p
   for (long long item; (item = q.next(lane)) >= 0;) {
     where.locate(item);
     const Col C = cols[where.col];
-    const Seg S = segs[C.seg];
     const int it = (int)(item - where.col_lo);
-    const long long rb = S.row_begin >> 4;
-    const int nb = S.n_rows >> 4;
+    const long long rb = C.row_begin >> 4;
+    const int nb = C.n_rows >> 4;
     const int i0 = it * IT;
     const int j0 = max(C.jc * jchunk, i0);
     const int j1 = min((C.jc + 1) * jchunk, nb);
@@ -537,11 +541,9 @@ __device__ __forceinline__ void pair_item_h(const uint4* __restrict__ posh, floa
 // Work items as for k_pair_maxima with itile = 2 * IT 16-row blocks: IT
 // 32-row blocks of A against the column chunk's 32-row blocks of B.
 template <int IT>
-__global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__ posh, const Seg* __restrict__ segs,
-                                                       const Col* __restrict__ cols,
+__global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__ posh, const Col* __restrict__ cols,
                                                        const long long* __restrict__ itembase,
                                                        const long long* __restrict__ totals,
-                                                       const RoiMeta* __restrict__ meta,
                                                        unsigned int* __restrict__ work_ctr,
                                                        float* __restrict__ rowmax, int jchunk) {
   const int lane = threadIdx.x & 63;
@@ -549,13 +551,12 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
   ColumnOf where(itembase, totals[T_NITEM], totals[T_NCOL]);
   for (long long item; (item = q.next(lane)) >= 0;) {
     where.locate(item);
-    const Col C = cols[where.col];
-    const Seg S = segs[C.seg];
-    const int e = h_scale_exp(meta[S.group >> 2].R2);
+    const Col C = cols[where.col];  // the segment's rows and scale travel with the column
     const int it = (int)(item - where.col_lo);
     // 32-row block coordinates (segments start and end on 32-row boundaries)
-    const long long rb = S.row_begin >> 5;
-    const int nb = S.n_rows >> 5;
+    const long long rb = C.row_begin >> 5;
+    const int nb = C.n_rows >> 5;
+    const int e = C.e;
     const int i0 = it * IT;
     const int j0 = max(C.jc * (jchunk >> 1), i0);
     const int j1 = min((C.jc + 1) * (jchunk >> 1), nb);
@@ -887,7 +888,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
   if ((e = launch_fill_i64(B.nitem, 0, B.col_cap, st))) return e;
   hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
-                     B.ncol, B.colbase, B.cols, B.nitem, B.tune.itile, B.tune.jchunk);
+                     B.meta, B.ncol, B.colbase, B.cols, B.nitem, B.tune.itile, B.tune.jchunk);
   if ((e = launch_scan(B.nitem, B.itembase, B.col_cap, B.totals + T_NITEM, B.scan_tmp, st))) return e;
   return hipGetLastError();
 }
@@ -901,7 +902,7 @@ hipError_t launch_pair_maxima_it(const PairBufs& B, hipStream_t st) {
   if (per_cu < 1) per_cu = 1;
   if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
-  hipLaunchKernelGGL(k_pair_maxima<IT>, dim3(grid), dim3(256), 0, st, B.pos, B.segs, B.cols, B.itembase, B.totals,
+  hipLaunchKernelGGL(k_pair_maxima<IT>, dim3(grid), dim3(256), 0, st, B.pos, B.cols, B.itembase, B.totals,
                      B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
   return hipGetLastError();
 }
@@ -914,8 +915,8 @@ hipError_t launch_pair_maxima_h(const PairBufs& B, hipStream_t st) {
   if (per_cu < 1) per_cu = 1;
   if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
-  hipLaunchKernelGGL(k_pair_maxima_h<IT>, dim3(grid), dim3(256), 0, st, B.posh, B.segs, B.cols, B.itembase,
-                     B.totals, B.meta, B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
+  hipLaunchKernelGGL(k_pair_maxima_h<IT>, dim3(grid), dim3(256), 0, st, B.posh, B.cols, B.itembase, B.totals,
+                     B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
   // small plane buckets (bucket count bounded by n_buckets on the host), in
   // tiles of two row blocks: 124 VGPRs, four waves per SIMD for this
   // latency-bound kernel

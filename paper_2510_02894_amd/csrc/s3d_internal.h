@@ -81,8 +81,11 @@ struct Seg {
 };
 
 struct Col {
-  int seg;
-  int jc;
+  long long row_begin;  // the segment's first row
+  int n_rows;           // the segment's rows
+  int group;            // the segment's group (roi * 4 + feature)
+  int jc;               // column chunk index within the segment
+  int e;                // scale exponent of the ROI's split-f16 operands
 };
 
 // Per-group results of the diameter passes.
