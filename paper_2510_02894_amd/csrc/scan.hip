@@ -96,10 +96,52 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const long long* __
   }
 }
 
+// The whole scan in one 1024-thread workgroup, for n <= kScanSingleMax: each
+// thread sums a contiguous run of at most 64 elements, the run sums are
+// scanned (wave scans, then the 16 wave totals), and each thread writes its
+// run.  One launch instead of three for the many small scans of a call.
+constexpr long long kScanSingleMax = 1024 * 64;
+
+__global__ __launch_bounds__(1024) void k_scan_single(const long long* __restrict__ in, long long n,
+                                                      const unsigned int* __restrict__ n_dev,
+                                                      long long* __restrict__ out, long long* __restrict__ total) {
+  __shared__ long long sw[16];
+  n = scan_count(n, n_dev);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const long long per = (n + 1023) / 1024;
+  const long long lo = min(n, per * tid), hi = min(n, lo + per);
+  long long sum = 0;
+  for (long long i = lo; i < hi; ++i) sum += in[i];
+  long long inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const long long t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) sw[wid] = inc;
+  __syncthreads();
+  long long base = 0, all = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wid) base += sw[w];
+    all += sw[w];
+  }
+  long long off = base + inc - sum;
+  for (long long i = lo; i < hi; ++i) {
+    const long long v = in[i];
+    out[i] = off;
+    off += v;
+  }
+  if (tid == 0 && total) *total = all;
+}
+
 long long scan_tmp_elems(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 hipError_t launch_scan(const long long* in, long long* out, long long n, long long* total, long long* tmp,
                        hipStream_t st, const unsigned int* n_dev) {
+  if (n <= kScanSingleMax) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, st, in, n, n_dev, out, total);
+    return hipGetLastError();
+  }
   const long long nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
   if (n > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, n_dev, tmp);
   else hipLaunchKernelGGL(k_scan_reduce, dim3(1), dim3(kScanThreads), 0, st, in, 0ll, n_dev, tmp);
