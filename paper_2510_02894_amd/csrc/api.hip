@@ -402,9 +402,7 @@ int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStr
                          (int*)w.orig.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
   if (ev) HIPCK(hipEventRecord(ev[1], st));
   HIPCK(launch_buckets(B, st));
-  HIPCK(launch_init_groups(B, st));
-  // row maxima start at zero (one dense fill over every row the layouts can hold)
-  HIPCK(launch_fill_u32((unsigned int*)B.rowmax, 0u, B.rows_bound, st));
+  HIPCK(launch_init_groups(B, st));  // also zeroes the row maxima
   if (ev) HIPCK(hipEventRecord(ev[2], st));
   HIPCK(launch_pair_maxima(B, st));
   if (ev) HIPCK(hipEventRecord(ev[3], st));

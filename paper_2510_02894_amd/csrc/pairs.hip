@@ -23,6 +23,7 @@
 //     which yields the exact maximum and the canonical tie-break.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "s3d_device.h"
@@ -75,6 +76,17 @@ __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __res
       }
     }
   }
+}
+
+// Clears the bucket counters and the per-ROI in-plane pair counts (one launch).
+__global__ void k_zero_buckets(unsigned int* __restrict__ bcnt, unsigned int* __restrict__ bcur, long long nb,
+                               long long* __restrict__ pairs2d, long long n_rois) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) {
+    bcnt[i] = 0u;
+    bcur[i] = 0u;
+  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_rois; i += stride) pairs2d[i] = 0;
 }
 
 __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long nb, long long* __restrict__ bsz,
@@ -192,10 +204,15 @@ __global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long l
   }
 }
 
-// Columns (chunks of jchunk row blocks) per segment.
+// Columns (chunks of jchunk row blocks) per segment; also clears the item
+// counts of all col_cap columns (k_col_fill sets those of the real ones).
 __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __restrict__ totals,
-                           const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk, int small_rows) {
+                           const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk, int small_rows,
+                           long long* __restrict__ nitem, long long col_cap) {
   const long long nseg = n_rois + totals[T_NSEG2D];
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < col_cap;
+       c += (long long)gridDim.x * blockDim.x)
+    nitem[c] = 0;
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < seg_cap;
        s += (long long)gridDim.x * blockDim.x) {
     long long rows = s < nseg ? segs[s].n_rows : 0;
@@ -781,12 +798,16 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
   }
 }
 
-// Also clears the candidate counter and the pair-pass work counters.
-__global__ void k_init_groups(GroupRes* gres, long long n, unsigned int* counters) {
+// Also clears the candidate counter, the pair-pass work counters and the row
+// maxima of every row the layouts can hold (one launch before the pair pass).
+__global__ void k_init_groups(GroupRes* gres, long long n, unsigned int* counters, unsigned int* rowmax_bits,
+                              long long n_rows) {
   if (blockIdx.x == 0) {
     for (int i = kWorkStride + threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0u;
     if (threadIdx.x == 0) counters[1] = 0u;
   }
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += (long long)gridDim.x * blockDim.x)
+    rowmax_bits[r] = 0u;
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (long long)gridDim.x * blockDim.x) {
     GroupRes G;
     G.best_bits = 0ull;
@@ -868,9 +889,8 @@ uint4* split_rows(const PairBufs& B) { return B.tune.kernel == 1 ? B.posh : null
 
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipError_t e;
-  if ((e = launch_fill_u32(B.bcnt, 0u, B.n_buckets, st))) return e;
-  if ((e = launch_fill_u32(B.bcur, 0u, B.n_buckets, st))) return e;
-  if ((e = launch_fill_i64(B.pairs2d, 0, B.n_rois, st))) return e;
+  hipLaunchKernelGGL(k_zero_buckets, dim3(grid_for(std::max<long long>(B.n_buckets, B.n_rois), 4096)), dim3(256), 0,
+                     st, B.bcnt, B.bcur, B.n_buckets, B.pairs2d, (long long)B.n_rois);
   hipLaunchKernelGGL(k_bucket_hist, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
                      B.totals, B.bcnt);
   hipLaunchKernelGGL(k_bucket_sizes, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.bcnt, B.n_buckets, B.bsz,
@@ -883,10 +903,10 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
                      B.pairs2d);
-  hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
-                     B.ncol, B.tune.jchunk, small_buckets(B) ? kSmallBlocks * 32 : 0);
+  hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(std::max(B.seg_cap, B.col_cap))), dim3(256), 0, st, B.n_rois,
+                     B.seg_cap, B.totals, B.segs, B.ncol, B.tune.jchunk, small_buckets(B) ? kSmallBlocks * 32 : 0,
+                     B.nitem, B.col_cap);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
-  if ((e = launch_fill_i64(B.nitem, 0, B.col_cap, st))) return e;
   hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.meta, B.ncol, B.colbase, B.cols, B.nitem, B.tune.itile, B.tune.jchunk);
   if ((e = launch_scan(B.nitem, B.itembase, B.col_cap, B.totals + T_NITEM, B.scan_tmp, st))) return e;
@@ -951,7 +971,8 @@ hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
 }
 
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_groups, dim3(grid_for(4ll * B.n_rois)), dim3(256), 0, st, B.gres, 4ll * B.n_rois, B.counters);
+  hipLaunchKernelGGL(k_init_groups, dim3(grid_for(std::max<long long>(4ll * B.n_rois, B.rows_bound), 4096)), dim3(256), 0,
+                     st, B.gres, 4ll * B.n_rois, B.counters, (unsigned int*)B.rowmax, B.rows_bound);
   return hipGetLastError();
 }
 

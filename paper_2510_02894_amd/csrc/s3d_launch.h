@@ -141,7 +141,7 @@ hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 uint4* split_rows(const PairBufs& B);  // split-f16 operand rows (kernel 1), else null
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list
 hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass over the work list
-hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset per-group results and pair-pass counters
+hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset group results, pair-pass counters, row maxima
 hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st);      // per-ROI results
 hipError_t launch_export_vertices(const unsigned long long* key, const double* tsoft, const RoiMeta* meta,
