@@ -65,7 +65,7 @@ struct Workspace {
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
   Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
       bseg, bgroup, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
-      posh, case_area, soft_rois, soft_edges, soft_field, soft_ctr;
+      posh, case_area, soft_rois, soft_edges, soft_field, soft_ctr, soft_blk;
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
@@ -81,7 +81,7 @@ struct Workspace {
     return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
             &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &bgroup, &ncol,     &colbase,
             &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
-            &cand_chbase, &posh, &case_area, &soft_rois, &soft_edges, &soft_field, &soft_ctr};
+            &cand_chbase, &posh, &case_area, &soft_rois, &soft_edges, &soft_field, &soft_ctr, &soft_blk};
   }
 };
 
@@ -688,6 +688,10 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   // one float per grid edge; only crossing edges' slots are ever written or read
   if ((rc = ensure(w, w.soft_field, sizeof(float) * n_field))) return rc;
   if ((rc = ensure(w, w.soft_ctr, sizeof(long long) * 2))) return rc;
+  // with more than a few ROIs, a table gives each workgroup its ROI (instead
+  // of a binary search of the ROI table per workgroup)
+  const bool blk_table = n_rois > 8;
+  if (blk_table && (rc = ensure(w, w.soft_blk, sizeof(int) * (size_t)(n_cblocks + n_vblocks)))) return rc;
   if ((rc = ensure_host(w, std::max<size_t>(w.host_cap, 4096 + tbytes)))) return rc;
   char* h = (char*)w.host;
   memcpy(h + 4096, table.data(), tbytes);
@@ -703,6 +707,7 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
   B.n_field = n_field;
   B.counters = (long long*)w.soft_ctr.p;
   B.cu_count = w.cu_count;
+  B.blk_roi = blk_table ? (int*)w.soft_blk.p : nullptr;
   HIPCK(launch_soft_backward(B, st));
   long long* used = (long long*)h;
   HIPCK(hipMemcpyAsync(used, w.soft_ctr.p, sizeof(long long), hipMemcpyDeviceToHost, st));

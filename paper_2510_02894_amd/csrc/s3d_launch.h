@@ -129,11 +129,13 @@ struct SoftBwdBufs {
   long long n_cblocks;        // workgroups of the edge pass
   long long n_vblocks;        // workgroups of the gather pass
   long long cap;              // crossing-edge capacity (the forward pass's vertex count)
-  unsigned long long* edges;  // [cap] edge-field slots of the crossing edges
+  unsigned long long* edges;  // [cap] crossing edges: ROI index << 40 | local field slot
   float* field;               // edge field: (dL/dx_v)_a * s_a at crossing edges (other slots unused)
   long long n_field;          // slots of the edge field
   long long* counters;        // [0] edges reserved
   int cu_count;
+  int* blk_roi;               // [n_cblocks + n_vblocks] ROI of each edge-pass then gather-pass
+                              // workgroup, or null (then found by binary search)
 };
 hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 

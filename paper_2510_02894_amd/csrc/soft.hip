@@ -156,7 +156,6 @@ constexpr int kVoxBlock = 256;     // voxels per workgroup of the gather pass (1
   }
 S3D_SOFT_ROI_SEARCH(soft_roi_of_cblk, cblk_begin)
 S3D_SOFT_ROI_SEARCH(soft_roi_of_vblk, vblk_begin)
-S3D_SOFT_ROI_SEARCH(soft_roi_of_slot, field_begin)
 #undef S3D_SOFT_ROI_SEARCH
 
 // Pass 1.  A workgroup takes kCubeBlock consecutive cubes (flat index l over
@@ -167,7 +166,8 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   constexpr int kPer = kCubeBlock / 256;
   __shared__ int s_scan[4];
   __shared__ long long base_sh;
-  const SoftBwdRoi* R = B.rois + soft_roi_of_cblk(B.rois, B.n_rois, blockIdx.x);
+  const int roi = B.blk_roi ? B.blk_roi[blockIdx.x] : soft_roi_of_cblk(B.rois, B.n_rois, blockIdx.x);
+  const SoftBwdRoi* R = B.rois + roi;
   const int* d = R->d;
   const float* p = R->p;
   const unsigned int l0 = (unsigned int)(blockIdx.x - R->cblk_begin) * kCubeBlock + threadIdx.x;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
     const int i = __ffsll((long long)bits) - 1;
     bits &= bits - 1ull;
     const int k = i / 3, a = i - 3 * k;
-    B.edges[slot++] = (unsigned long long)(R->field_begin + 3ll * (l0 + 256u * k) + a);
+    B.edges[slot++] = ((unsigned long long)roi << 40) | (3ull * (l0 + 256u * k) + (unsigned long long)a);
   }
 }
 
@@ -238,17 +238,23 @@ __global__ __launch_bounds__(256, 4) void k_soft_vertex_grad(SoftBwdBufs B) {
   const long long n = min(B.counters[0], B.cap);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const long long slot = (long long)B.edges[i];
+    const unsigned long long entry = B.edges[i];
+    const unsigned int roi = (unsigned int)(entry >> 40);
+    const unsigned long long local = entry & ((1ull << 40) - 1ull);
     // an entry no block wrote (only when the input has more crossing edges
     // than the forward pass: the call then fails) must not address memory
-    if (slot < 0 || slot >= B.n_field) continue;
-    const SoftBwdRoi* R = B.rois + soft_roi_of_slot(B.rois, B.n_rois, slot);
-    const long long local = slot - R->field_begin;
-    const int a = (int)(local % 3);
-    const long long cube = local / 3;
-    const int u2 = (int)(cube % (R->d[2] + 1)) - 1;
-    const long long lr = cube / (R->d[2] + 1);
-    const int u0 = (int)(lr / (R->d[1] + 1)) - 1, u1 = (int)(lr % (R->d[1] + 1)) - 1;
+    if (roi >= (unsigned int)B.n_rois) continue;
+    const SoftBwdRoi* R = B.rois + roi;
+    if (local >= 3ull * R->n_cubes) continue;
+    const long long slot = R->field_begin + (long long)local;
+    // local = 3 cube(u) + a with cube(u) < 2^31: 32-bit decoding
+    const unsigned int l32 = (unsigned int)local;
+    const unsigned int cube = l32 / 3u;
+    const int a = (int)(l32 - 3u * cube);
+    const unsigned int c0 = fdiv(cube, R->m_cplane, R->sh_cplane);
+    const unsigned int r = cube - c0 * (unsigned int)((R->d[1] + 1) * (R->d[2] + 1));
+    const unsigned int c1 = fdiv(r, R->m_c2, R->sh_c2);
+    const int u0 = (int)c0 - 1, u1 = (int)c1 - 1, u2 = (int)(r - c1 * (unsigned int)(R->d[2] + 1)) - 1;
     double gx[3] = {0.0, 0.0, 0.0};
     vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, s_ntri, s_tri, gx);
     const long long id = 3ll * ((((long long)(u0 + 1)) * (R->d[1] + 2) + (u1 + 1)) * (long long)(R->d[2] + 2) +
@@ -316,7 +322,8 @@ __device__ inline double voxel_grad(const float* __restrict__ field, long long s
 // all seven loads issued together; the voxel's crossing edges read their
 // values from the edge field and dL/dp is written densely.
 __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
-  const SoftBwdRoi* R = B.rois + soft_roi_of_vblk(B.rois, B.n_rois, blockIdx.x);
+  const SoftBwdRoi* R =
+      B.rois + (B.blk_roi ? B.blk_roi[B.n_cblocks + blockIdx.x] : soft_roi_of_vblk(B.rois, B.n_rois, blockIdx.x));
   const unsigned int l = (unsigned int)(blockIdx.x - R->vblk_begin) * kVoxBlock + threadIdx.x;
   if (l >= R->n_vox) return;
   const int* d = R->d;
@@ -348,9 +355,21 @@ __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
   R->grad[l] = (float)voxel_grad(B.field, R->field_begin + 3ll * cube, stride, vc, nv);
 }
 
+// The ROI of every workgroup of the edge and gather passes (one workgroup per
+// ROI writes its two contiguous block ranges).
+__global__ void k_soft_block_rois(SoftBwdBufs B) {
+  int* blk_roi = B.blk_roi;
+  const SoftBwdRoi& R = B.rois[blockIdx.x];
+  const long long nc = ((long long)R.n_cubes + kCubeBlock - 1) / kCubeBlock;
+  const long long nv = ((long long)R.n_vox + kVoxBlock - 1) / kVoxBlock;
+  for (long long i = threadIdx.x; i < nc; i += blockDim.x) blk_roi[R.cblk_begin + i] = (int)blockIdx.x;
+  for (long long i = threadIdx.x; i < nv; i += blockDim.x) blk_roi[B.n_cblocks + R.vblk_begin + i] = (int)blockIdx.x;
+}
+
 hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st) {
   hipError_t e;
   if ((e = launch_fill_i64(B.counters, 0, 1, st))) return e;
+  if (B.blk_roi) hipLaunchKernelGGL(k_soft_block_rois, dim3((unsigned)B.n_rois), dim3(256), 0, st, B);
   if (B.n_cblocks > 0) hipLaunchKernelGGL(k_soft_edges, dim3((unsigned)B.n_cblocks), dim3(256), 0, st, B);
   if ((e = hipGetLastError())) return e;
   long long g = (B.cap + 255) / 256;
