@@ -677,8 +677,8 @@ int soft_backward_impl(const float* base, const shape3d_roi* rois, int64_t n_roi
     R.cblk_begin = n_cblocks;
     R.vblk_begin = n_vblocks;
     n_field += 3 * ncube;
-    n_cblocks += (ncube + 4095) / 4096;
-    n_vblocks += (nvox + 255) / 256;
+    n_cblocks += (ncube + kCubeBlock - 1) / kCubeBlock;
+    n_vblocks += (nvox + kVoxBlock - 1) / kVoxBlock;
     cap += S.n_vertices;
   }
   if (n_cblocks > (1ll << 31) - 2 || n_vblocks > (1ll << 31) - 2) return fail(SHAPE3D_EINVAL, "batch too large");

@@ -103,6 +103,10 @@ struct PairBufs {
 // field_begin + 3 cube(u) + a.  Local indices are below 2^31 (checked on the
 // host), so the kernels divide with 32-bit magic numbers: floor(n / D) =
 // (n * m) >> sh with sh = 31 + ceil(log2 D) and m = floor(2^sh / D) + 1.
+constexpr int kCubeBlock = 4096;   // cubes per workgroup of the edge pass (16 per thread)
+constexpr int kVoxPer = 4;         // voxels per thread of the gather pass (256 apart)
+constexpr int kVoxBlock = 256 * kVoxPer;  // voxels per workgroup of the gather pass
+
 struct SoftBwdRoi {
   const float* p;             // the ROI's probabilities (d0, d1, d2)
   float* grad;                // dL/dp, same layout

@@ -138,8 +138,6 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
   }
 }
 
-constexpr int kCubeBlock = 4096;   // cubes per workgroup of the edge pass (16 per thread)
-constexpr int kVoxBlock = 256;     // voxels per workgroup of the gather pass (1 per thread)
 
 // Last ROI whose first element of the given kind is <= x.
 #define S3D_SOFT_ROI_SEARCH(name, member)                                   \
@@ -318,41 +316,53 @@ __device__ inline double voxel_grad(const float* __restrict__ field, long long s
   return g;
 }
 
-// Pass 3.  One thread per voxel (flat index over the ROI, 256 per workgroup),
-// all seven loads issued together; the voxel's crossing edges read their
-// values from the edge field and dL/dp is written densely.
+// Pass 3.  kVoxPer voxels per thread, 256 apart (flat index over the ROI,
+// kVoxBlock per workgroup, so each load instruction of a wave reads 64
+// consecutive floats), all 7 loads of each issued together; the voxel's
+// crossing edges read their values from the edge field and dL/dp is written
+// densely.
 __global__ __launch_bounds__(256) void k_soft_gather(SoftBwdBufs B) {
   const SoftBwdRoi* R =
       B.rois + (B.blk_roi ? B.blk_roi[B.n_cblocks + blockIdx.x] : soft_roi_of_vblk(B.rois, B.n_rois, blockIdx.x));
-  const unsigned int l = (unsigned int)(blockIdx.x - R->vblk_begin) * kVoxBlock + threadIdx.x;
-  if (l >= R->n_vox) return;
+  const unsigned int l0 = (unsigned int)(blockIdx.x - R->vblk_begin) * kVoxBlock + threadIdx.x;
+  if (l0 >= R->n_vox) return;
   const int* d = R->d;
   const float* p = R->p;
   const unsigned int plane = (unsigned int)d[1] * d[2];
-  const unsigned int w0 = fdiv(l, R->m_plane, R->sh_plane);
-  const unsigned int r = l - w0 * plane;
-  const unsigned int w1 = fdiv(r, R->m_d2, R->sh_d2);
-  const unsigned int x = r - w1 * (unsigned int)d[2];
-  const bool zm = w0 > 0, zp = w0 + 1 < (unsigned int)d[0], ym = w1 > 0, yp = w1 + 1 < (unsigned int)d[1];
-  const bool xm = x > 0, xp = x + 1 < (unsigned int)d[2];
-  float nv[6];
-  const float vc = p[l];
-  nv[0] = p[zm ? l - plane : l];
-  nv[1] = p[zp ? l + plane : l];
-  nv[2] = p[ym ? l - d[2] : l];
-  nv[3] = p[yp ? l + d[2] : l];
-  nv[4] = p[xm ? l - 1 : l];
-  nv[5] = p[xp ? l + 1 : l];
-  nv[0] = zm ? nv[0] : 0.0f;
-  nv[1] = zp ? nv[1] : 0.0f;
-  nv[2] = ym ? nv[2] : 0.0f;
-  nv[3] = yp ? nv[3] : 0.0f;
-  nv[4] = xm ? nv[4] : 0.0f;
-  nv[5] = xp ? nv[5] : 0.0f;
-  // field slot of edge (w, axis 0): 3 * cube(w)
-  const long long cube = ((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d[2] + 1) + (x + 1);
   const long long stride[3] = {3ll * (d[1] + 1) * (d[2] + 1), 3ll * (d[2] + 1), 3};
-  R->grad[l] = (float)voxel_grad(B.field, R->field_begin + 3ll * cube, stride, vc, nv);
+  float vc[kVoxPer], nv[kVoxPer][6];
+  long long slot[kVoxPer];
+#pragma unroll
+  for (int j = 0; j < kVoxPer; ++j) {
+    // voxels past the ROI's end repeat its last voxel (loaded, not written)
+    const unsigned int l = min(l0 + 256u * j, R->n_vox - 1u);
+    const unsigned int w0 = fdiv(l, R->m_plane, R->sh_plane);
+    const unsigned int r = l - w0 * plane;
+    const unsigned int w1 = fdiv(r, R->m_d2, R->sh_d2);
+    const unsigned int x = r - w1 * (unsigned int)d[2];
+    const bool zm = w0 > 0, zp = w0 + 1 < (unsigned int)d[0], ym = w1 > 0, yp = w1 + 1 < (unsigned int)d[1];
+    const bool xm = x > 0, xp = x + 1 < (unsigned int)d[2];
+    vc[j] = p[l];
+    nv[j][0] = p[zm ? l - plane : l];
+    nv[j][1] = p[zp ? l + plane : l];
+    nv[j][2] = p[ym ? l - d[2] : l];
+    nv[j][3] = p[yp ? l + d[2] : l];
+    nv[j][4] = p[xm ? l - 1 : l];
+    nv[j][5] = p[xp ? l + 1 : l];
+    nv[j][0] = zm ? nv[j][0] : 0.0f;
+    nv[j][1] = zp ? nv[j][1] : 0.0f;
+    nv[j][2] = ym ? nv[j][2] : 0.0f;
+    nv[j][3] = yp ? nv[j][3] : 0.0f;
+    nv[j][4] = xm ? nv[j][4] : 0.0f;
+    nv[j][5] = xp ? nv[j][5] : 0.0f;
+    // field slot of edge (w, axis 0): 3 * cube(w)
+    slot[j] = R->field_begin + 3ll * (((long long)(w0 + 1) * (d[1] + 1) + (w1 + 1)) * (d[2] + 1) + (x + 1));
+  }
+#pragma unroll
+  for (int j = 0; j < kVoxPer; ++j) {
+    const float g = (float)voxel_grad(B.field, slot[j], stride, vc[j], nv[j]);
+    if (l0 + 256u * j < R->n_vox) R->grad[l0 + 256u * j] = g;
+  }
 }
 
 // The ROI of every workgroup of the edge and gather passes (one workgroup per
