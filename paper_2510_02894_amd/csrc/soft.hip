@@ -96,6 +96,8 @@ __device__ inline D3 cube_vertex(const double* pc, int e, int c0, int c1, int c2
 __device__ inline void vertex_grad_mesh(const float* p, const int* d, const double* s, const double* o, int u0, int u1,
                                         int u2, int a, double g_area, double g_vol_signed, const uint8_t* ntri,
                                         const uint8_t* tri, double* gx) {
+  // per-edge factors of the two terms (divisions hoisted out of the triangle loop)
+  const double ga = 0.5 * g_area, gv = g_vol_signed / 6.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int ob = q >> 1, oc = q & 1;
@@ -124,16 +126,17 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
       const D3 n = cross3(sub3(P1, P0), sub3(P2, P0));
       const double len = sqrt(n.x * n.x + n.y * n.y + n.z * n.z);
       if (len > 0.0) {
-        const D3 nh = {n.x / len, n.y / len, n.z / len};
+        const double il = 1.0 / len;
+        const D3 nh = {n.x * il, n.y * il, n.z * il};
         const D3 r = cross3(nh, sub3(C, B));
-        gx[0] += g_area * 0.5 * r.x;
-        gx[1] += g_area * 0.5 * r.y;
-        gx[2] += g_area * 0.5 * r.z;
+        gx[0] += ga * r.x;
+        gx[1] += ga * r.y;
+        gx[2] += ga * r.z;
       }
       const D3 bc = cross3(B, C);
-      gx[0] += g_vol_signed * bc.x / 6.0;
-      gx[1] += g_vol_signed * bc.y / 6.0;
-      gx[2] += g_vol_signed * bc.z / 6.0;
+      gx[0] += gv * bc.x;
+      gx[1] += gv * bc.y;
+      gx[2] += gv * bc.z;
     }
   }
 }
