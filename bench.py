@@ -67,9 +67,10 @@ def source_hash(files=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, tiles=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current sources of that kernel."""
+    was taken on the current sources of that kernel (and, for the pair pass,
+    with the same tiles)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -77,6 +78,8 @@ def measured_traffic(kernel: str):
         return None
     k = rec.get("kernels", {}).get(kernel)
     if not k or k.get("source_hash") != source_hash(KERNEL_SOURCES.get(kernel)):
+        return None
+    if tiles is not None and list(rec.get("tiles", [])) != list(tiles):
         return None
     return k.get("hbm_bytes_per_launch")
 
@@ -408,7 +411,7 @@ def main():
     t_pair = avg["pair_maxima"] * 1e-3
     kern = int(tiles[3])
     achieved = FLOPS_PER_PAIR[kern] * (pairs3 + pairs2) / t_pair / 1e12
-    traffic = measured_traffic("k_pair_maxima_h" if kern == 1 else "k_pair_maxima")
+    traffic = measured_traffic("k_pair_maxima_h" if kern == 1 else "k_pair_maxima", tiles)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[kern], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[kern], "traffic": traffic,
                 "kernel": "split-f16 v_mfma_f32_32x32x16_f16" if kern == 1 else "fp32 v_mfma_f32_16x16x4_f32"}

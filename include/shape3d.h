@@ -219,15 +219,17 @@ int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, in
  * valid setting.
  *   itile_blocks:  16-row blocks each wave keeps in registers: 2, 4 or 8
  *                  (kernel 1: 4 or 8).
- *   jchunk_blocks: 16-row column blocks per work item: 64, 128, 256 or 512.
+ *   jchunk_blocks: 16-row column blocks per work item: 64, 128, 256, 512 or
+ *                  1024.
  *   blocks_per_cu: persistent workgroups per compute unit, 0 = as many as fit
  *                  (at most 64).
  *   kernel:        0 = FP32 Gram values on the 16x16x4 FP32 matrix cores;
  *                  1 = FP32-accurate Gram values from coordinates split into
  *                  two f16 parts on the 32x32x16 f16 matrix cores.  Both are
  *                  followed by the same exact FP64 refinement.
- * The setting is process-wide (all devices); the default is {8, 512, 0, 1}
- * (the autotuner's choice on every workload measured).
+ * The setting is process-wide (all devices); the default is {8, 1024, 0, 1}
+ * (the autotuner's choice on one very large ROI; batches of small ROIs gain
+ * about 1 % from jchunk 512).
  *
  * shape3d_get_tuning / shape3d_set_tuning -- read or replace the setting
  * (HOST struct).  Setting drops the graphs recorded by shape3d_batched.

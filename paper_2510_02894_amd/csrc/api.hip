@@ -88,11 +88,11 @@ struct Workspace {
 std::map<int, Workspace*> g_ws;
 
 // Tile sizes of the pair pass for every device (results do not depend on them).
-Tuning g_tune = {8, 512, 0, 1};
+Tuning g_tune = {8, 1024, 0, 1};
 
 bool valid_tuning(const Tuning& t) {
   return (t.itile == 2 || t.itile == 4 || t.itile == 8) &&
-         (t.jchunk == 64 || t.jchunk == 128 || t.jchunk == 256 || t.jchunk == 512) && t.blocks_per_cu >= 0 &&
+         (t.jchunk == 64 || t.jchunk == 128 || t.jchunk == 256 || t.jchunk == 512 || t.jchunk == 1024) && t.blocks_per_cu >= 0 &&
          t.blocks_per_cu <= 64 && (t.kernel == 0 || (t.kernel == 1 && t.itile >= 4));
 }
 
@@ -783,7 +783,7 @@ int autotune_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t 
   best = saved;
   static const int kCand[5][2] = {{0, 2}, {0, 4}, {0, 8}, {1, 4}, {1, 8}};  // (kernel, itile)
   for (const auto& kc : kCand)
-    for (int jc : {64, 128, 256, 512}) {
+    for (int jc : {64, 128, 256, 512, 1024}) {
       g_tune = Tuning{kc[1], jc, 0, kc[0]};
       double t = 1e300;
       for (int k = 0; k < reps; ++k) {

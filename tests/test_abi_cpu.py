@@ -99,16 +99,16 @@ def test_tuning_setting_is_validated_without_a_device():
     if not os.path.exists(S.LIB_PATH):
         pytest.skip("library not built")
     before = S.get_tuning()
-    assert before == (8, 512, 0, 1)
-    for bad in [(3, 256, 0, 0), (8, 100, 0, 0), (8, 256, -1, 0), (8, 256, 65, 0), (16, 256, 0, 0), (2, 256, 0, 1),
-                (8, 256, 0, 2)]:
+    assert before == (8, 1024, 0, 1)
+    for bad in [(3, 256, 0, 0), (8, 100, 0, 0), (8, 2048, 0, 0), (8, 256, -1, 0), (8, 256, 65, 0), (16, 256, 0, 0),
+                (2, 256, 0, 1), (8, 256, 0, 2)]:
         with pytest.raises(S.Shape3DError) as ei:
             S.set_tuning(*bad)
         assert ei.value.status == S.EINVAL
         assert S.get_tuning() == before
     for kernel, tiles in ((0, (2, 4, 8)), (1, (4, 8))):
         for it in tiles:
-            for jc in (64, 128, 256, 512):
+            for jc in (64, 128, 256, 512, 1024):
                 S.set_tuning(it, jc, 2, kernel)
                 assert S.get_tuning() == (it, jc, 2, kernel)
     S.set_tuning(*before)

@@ -29,7 +29,7 @@ def S():
 
     shape3d.load()
     yield shape3d
-    shape3d.set_tuning(8, 512, 0, 1)
+    shape3d.set_tuning(8, 1024, 0, 1)
 
 
 def test_small_bucket_kernel_matches_work_list(S):
@@ -50,7 +50,7 @@ def test_small_bucket_kernel_matches_work_list(S):
         if ref is None:
             ref = out
         assert np.array_equal(out, ref), (it, jc, kern)
-    S.set_tuning(8, 512, 0, 1)
+    S.set_tuning(8, 1024, 0, 1)
     out, _ = S.batched(buf, table, graph=True)
     assert np.array_equal(out, ref)
     host = buf.cpu().numpy()

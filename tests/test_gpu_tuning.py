@@ -11,8 +11,8 @@ from paper_2510_02894_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-TILINGS = [(it, jc, 0) for it in (2, 4, 8) for jc in (64, 128, 256, 512)] + \
-    [(it, jc, 1) for it in (4, 8) for jc in (64, 128, 256, 512)]
+TILINGS = [(it, jc, 0) for it in (2, 4, 8) for jc in (64, 128, 256, 512, 1024)] + \
+    [(it, jc, 1) for it in (4, 8) for jc in (64, 128, 256, 512, 1024)]
 
 
 def say(msg):
@@ -30,7 +30,7 @@ def S():
 
     shape3d.load()
     yield shape3d
-    shape3d.set_tuning(8, 512, 0, 1)
+    shape3d.set_tuning(8, 1024, 0, 1)
 
 
 def test_every_tiling_gives_identical_results_single_roi(S):
@@ -48,7 +48,7 @@ def test_every_tiling_gives_identical_results_single_roi(S):
         if ref is None:
             ref = got
         assert got == ref, (it, jc, kern)
-    S.set_tuning(8, 512, 0, 1)
+    S.set_tuning(8, 1024, 0, 1)
 
 
 def test_every_tiling_gives_identical_results_batched_and_graph(S):
@@ -57,7 +57,7 @@ def test_every_tiling_gives_identical_results_batched_and_graph(S):
     buf, offs, shapes, sps = synth.batched_rois(40, 7, lmin=8.0, lmax=48.0)
     base = torch.from_numpy(buf).cuda()
     table = S.roi_table(offs, shapes, sps)
-    S.set_tuning(8, 512, 0, 1)
+    S.set_tuning(8, 1024, 0, 1)
     ref, _ = S.batched(base, table)
     for it, jc, kern in TILINGS:
         for bpc in (0, 1):
@@ -67,7 +67,7 @@ def test_every_tiling_gives_identical_results_batched_and_graph(S):
             assert np.array_equal(out, ref), (it, jc, bpc, kern)
             out, _ = S.batched(base, table, graph=True)   # replays it
             assert np.array_equal(out, ref), (it, jc, bpc, kern)
-    S.set_tuning(8, 512, 0, 1)
+    S.set_tuning(8, 1024, 0, 1)
 
 
 def test_autotune_and_cache(S, tmp_path):
@@ -93,4 +93,4 @@ def test_autotune_and_cache(S, tmp_path):
     assert len([l for l in cache.read_text().split("\n") if l.strip()]) == 1
     out, _ = S.batched(base, table, graph=True)
     assert np.array_equal(out, ref)
-    S.set_tuning(8, 512, 0, 1)
+    S.set_tuning(8, 1024, 0, 1)
