@@ -24,7 +24,7 @@ constexpr int kSegAlign = 32;       // segment rows padded to a multiple of this
 constexpr int kMinJchunk = 64;      // smallest column chunk (row blocks) the pair pass may be tuned to
 constexpr int kScanTile = 2048;     // elements per block of the device scan
 constexpr int kExactChunk = 4096;   // rows per block of the exact refinement
-constexpr int kSmallBlocks = 8;     // plane buckets of up to this many 32-row blocks skip the work list
+constexpr int kSmallBlocks = 16;    // plane buckets of up to this many 32-row blocks skip the work list
 constexpr int kSmallPerWave = 4;    // bucket segments per wave of the small-bucket kernel
 constexpr long long kSmallMinBuckets = 1 << 16;  // calls with fewer plane buckets keep them all in the work list
 constexpr int kWorkParts = 8;       // work ranges (one per XCD) of the pair pass, each with its own counter

@@ -1,5 +1,5 @@
 """GPU parity of the small-plane-bucket kernel.  A batch with more than 2^16
-plane buckets sends the buckets of at most 8 blocks of 32 rows to their own
+plane buckets sends the buckets of at most 16 blocks of 32 rows to their own
 kernel under the split-f16 pair pass; the FP32 pass and single-ROI calls keep
 every bucket in the work list.  All of them must give identical features and
 pairs, and a sample of ROIs must match the oracle."""
