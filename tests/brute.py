@@ -64,3 +64,41 @@ def diameters(vol, spacing):
     for k in range(3):
         out.append(np.sqrt(max_d2(pos, key[:, k])))
     return np.array(out), len(ids)
+
+
+def max_pair(ids, pos, groups=None):
+    """(max d2, (id_lo, id_hi)): the largest squared distance over vertex pairs
+    (in the same group if given) and, among the pairs that reach it exactly,
+    the lexicographically smallest pair of canonical ids; (0.0, (-1, -1)) when
+    no pair exists.  Squared distances are evaluated as (dx*dx + dy*dy) + dz*dz
+    in FP64, so equal distances compare equal."""
+    ids = np.asarray(ids, dtype=np.int64)
+    pos = np.asarray(pos, dtype=np.float64)
+    n = len(ids)
+    if n < 2:
+        return 0.0, (-1, -1)
+    dx = pos[:, None, 0] - pos[None, :, 0]
+    dy = pos[:, None, 1] - pos[None, :, 1]
+    dz = pos[:, None, 2] - pos[None, :, 2]
+    d2 = (dx * dx + dy * dy) + dz * dz
+    valid = ~np.eye(n, dtype=bool)
+    if groups is not None:
+        groups = np.asarray(groups)
+        valid &= groups[:, None] == groups[None, :]
+    if not valid.any():
+        return 0.0, (-1, -1)
+    m = float(d2[valid].max())
+    ii, jj = np.nonzero(valid & (d2 == m))
+    lo = np.minimum(ids[ii], ids[jj])
+    hi = np.maximum(ids[ii], ids[jj])
+    k = np.lexsort((hi, lo))[0]
+    return m, (int(lo[k]), int(hi[k]))
+
+
+def max_pairs(vol, spacing):
+    """[(d2, (id_lo, id_hi))] for the 3D, slice, column and row diameters."""
+    ids, pos, key = vertex_set(vol, spacing)
+    out = [max_pair(ids, pos)]
+    for k in range(3):
+        out.append(max_pair(ids, pos, key[:, k]))
+    return out

@@ -153,6 +153,48 @@ def test_diameters_exact_half_units():
         np.testing.assert_allclose(q, np.round(q), rtol=0, atol=1e-9)
 
 
+def tie_rich_masks():
+    """Masks whose diameters are reached by many pairs: every 2x2x2 mask, solid
+    boxes, single voxels at unit spacing (a 3-way tie) and random masks made
+    mirror-symmetric on every axis (each maximising pair has mirror images)."""
+    out = []
+    for c in range(256):
+        m = np.array([(c >> b) & 1 for b in range(8)], np.uint8).reshape(2, 2, 2)
+        out.append((m, (1.0, 1.0, 1.0)))
+    for a in ((1, 1, 1), (2, 3, 4), (3, 3, 3), (5, 2, 3), (6, 6, 6)):
+        out.append((synth.box_mask(tuple(x + 2 for x in a), (1, 1, 1), a), (1.0, 1.0, 1.0)))
+    out.append((synth.box_mask((7, 9, 8), (1, 2, 1), (5, 5, 5)), (1.0, 0.5, 1.0)))
+    one = np.zeros((3, 4, 5), np.uint8)
+    one[1, 2, 3] = 1
+    out.append((one, (1.0, 1.0, 1.0)))
+    g = np.random.default_rng(21)
+    for n in (4, 6, 8, 10):
+        m = synth.random_mask((n, n + 1, n), 0.35, g)
+        m = m | m[::-1] | m[:, ::-1] | m[:, :, ::-1]
+        out.append((np.ascontiguousarray(m), (1.0, 1.0, 1.0)))
+        out.append((np.ascontiguousarray(m), (0.5, 1.0, 0.5)))
+    return out
+
+
+def test_tie_break_bruteforce():
+    # reading R11: among pairs at the FP64 maximum, the lexicographically
+    # smallest (id_lo, id_hi); checked against a numpy search of all pairs
+    n_ties = 0
+    for m, sp in tie_rich_masks():
+        r = feats(m, sp)
+        ref = brute.max_pairs(m, sp)
+        for f in range(4):
+            d2, (lo, hi) = ref[f]
+            assert tuple(int(x) for x in r["pair_ids"][f]) == (lo, hi), (m.shape, sp, f)
+            assert r["features"][2 + f] == math.sqrt(d2)
+        ids, pos, _ = brute.vertex_set(m, sp)
+        if len(ids) >= 2:
+            dx = pos[:, None, :] - pos[None, :, :]
+            d2 = np.sum(dx * dx, axis=-1)
+            n_ties += int(np.count_nonzero(d2 == d2.max()) // 2 > 1)
+    assert n_ties > 200  # most inputs have several maximising pairs
+
+
 # --------------------------------------------------------------------------
 # Surface topology: closed, consistently oriented, Euler characteristic.
 
