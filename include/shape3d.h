@@ -227,7 +227,15 @@ int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, in
  *                  1 = FP32-accurate Gram values from coordinates split into
  *                  two f16 parts on the 32x32x16 f16 matrix cores.  Both are
  *                  followed by the same exact FP64 refinement.
- * The setting is process-wide (all devices); the default is {8, 1024, 0, 1}
+ *   prune:         (kernel 1) skip the 3D pair tiles whose largest possible
+ *                  distance, from the bounding boxes of their vertex blocks,
+ *                  stays below a vertex-pair distance found by two
+ *                  farthest-point sweeps: 1 = for calls whose largest ROI may
+ *                  have 16,384 vertices or more, 2 = always, 0 = never (all
+ *                  pairs).  Exact: the maximising pairs are never skipped, and
+ *                  the FP64 refinement rescans its candidate rows against all
+ *                  vertices, so the results equal those of prune = 0.
+ * The setting is process-wide (all devices); the default is {8, 1024, 0, 1, 1}
  * (the autotuner's choice on one very large ROI; batches of small ROIs gain
  * about 1 % from jchunk 512).
  *
@@ -256,12 +264,96 @@ typedef struct {
   int32_t jchunk_blocks;
   int32_t blocks_per_cu;
   int32_t kernel;
+  int32_t prune;  /* kernel 1: 1 (default) prune the 3D pair tiles of large ROIs, 2 always, 0 never */
 } shape3d_tuning;
 
 int shape3d_get_tuning(shape3d_tuning* t);
 int shape3d_set_tuning(const shape3d_tuning* t);
 int shape3d_autotune(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int reps,
                      const char* cache_path, shape3d_tuning* best, double* best_ms, void* stream);
+
+/*
+ * Caller-provided workspaces and results that stay on the device.
+ *
+ * The calls above size the library's own device workspace, which means a
+ * device-to-host read of the vertex count after the mesh count pass.  The
+ * calls below run on a workspace the caller provides (or, for
+ * shape3d_batched_dev, optionally on the library's), write their results to
+ * device memory and return as soon as the work is enqueued: nothing is read
+ * back to the host.  The vertex capacity follows from ws_bytes; a mesh that
+ * needs more rows than fit ends with status SHAPE3D_ECAPACITY (out left
+ * untouched), never with an out-of-bounds write.  A workspace must not be used
+ * by two calls that are in flight at once (calls on one stream are ordered);
+ * its contents between calls are unspecified.
+ *
+ * shape3d_workspace_size -- bytes of a workspace that holds the mesh of any
+ *   mask of these dims (every grid edge crossing: an upper bound, about
+ *   3 (d0+1)(d1+1)(d2+1) vertex rows of ~110 B).  SHAPE3D_ECAPACITY if such a
+ *   mesh exceeds the kernels' 32-bit row indices.
+ * shape3d_workspace_size_v -- the same for meshes of at most max_vertices
+ *   vertices (max_vertices < 0: the worst case above).  Depends on the current
+ *   tuning (the operand layout of the pair pass).
+ * shape3d_batched_workspace_size -- the same for a batch of n_rois ROIs, each
+ *   at most max_dims, with at most max_vertices vertices in total.
+ * None of the three needs a device.
+ *
+ * shape3d_ex_async -- the six features of one ROI, as shape3d_ex, fully
+ * asynchronous on `stream`.
+ *   vol, dtype, dims, spacing: as shape3d_ex.
+ *   out:       DEVICE double[6], written unless the status is negative.
+ *   status:    DEVICE int[1]: SHAPE3D_OK, SHAPE3D_EMPTY or SHAPE3D_ECAPACITY.
+ *   workspace: DEVICE, 256-byte aligned, ws_bytes long (shape3d_workspace_size).
+ * The return value covers argument errors only (SHAPE3D_ECAPACITY if not even
+ * an empty mesh's buffers fit).
+ */
+int shape3d_workspace_size(const int64_t dims[3], int dtype, size_t* bytes);
+int shape3d_workspace_size_v(const int64_t dims[3], int dtype, int64_t max_vertices, size_t* bytes);
+int shape3d_batched_workspace_size(int64_t n_rois, const int64_t max_dims[3], int dtype, int64_t max_vertices,
+                                   size_t* bytes);
+int shape3d_ex_async(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double* out,
+                     int* status, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * shape3d_batched_dev -- shape3d_batched with the ROI table, the features and
+ * the statuses in device memory, so that a batch can be described by earlier
+ * device work (for instance a crop to each label's bounding box) and a
+ * recorded graph can be replayed on new table contents without any host
+ * involvement.
+ *   base:     DEVICE; ROI r's voxel (z, y, x) is
+ *             base[rois[r].offset + z strides[0] + y strides[1] + x].
+ *   rois:     DEVICE shape3d_roi_ex[n_rois].  strides of 0 mean the dense
+ *             layout (dims[1] dims[2], dims[2]); otherwise strides[1] >=
+ *             dims[2] and strides[0] >= (dims[1] - 1) strides[1] + dims[2].
+ *             label (uint8 only): 0 = nonzero voxels are inside; 1..255 =
+ *             voxels equal to label are inside (label maps).
+ *   max_dims: HOST int64[3], bounds on every ROI's dims (they size the
+ *             launches and buffers).  An entry that is out of bounds, reaches
+ *             past the allocation holding base, or is otherwise invalid gets
+ *             status SHAPE3D_EINVAL; the other ROIs are unaffected.
+ *   out:      DEVICE double[6 n_rois]; status: DEVICE int[n_rois].
+ *   workspace: DEVICE or NULL.  With a workspace: as shape3d_ex_async (no
+ *             host synchronisation; shape3d_batched_workspace_size).  With
+ *             NULL the library's workspace is used: the call reads the vertex
+ *             row count back once to size it, and with SHAPE3D_BATCH_GRAPH it
+ *             records the pipeline (table planning included) the first time
+ *             and later replays it for the same base, dtype, table pointer,
+ *             n_rois, max_dims and output pointers; a replay whose meshes
+ *             exceed the recorded capacity sets every status to
+ *             SHAPE3D_ECAPACITY (call without the flag once to resize).
+ * Enqueued on `stream`; returns without waiting for the results.
+ */
+typedef struct {
+  int64_t offset;      /* element offset of the ROI's voxel (0, 0, 0) from base */
+  int64_t dims[3];
+  double spacing[3];
+  int64_t strides[2];  /* elements between voxels along axes 0 and 1; 0 = dense */
+  int32_t label;       /* uint8: 0 = nonzero is inside, else voxels equal to label */
+  int32_t reserved;    /* must be 0 */
+} shape3d_roi_ex;
+
+int shape3d_batched_dev(const void* base, int dtype, const shape3d_roi_ex* rois, int64_t n_rois,
+                        const int64_t max_dims[3], double* out, int* status, void* workspace, size_t ws_bytes,
+                        int flags, void* stream);
 
 /* Message describing the last failure of the calling thread ("" if none). */
 const char* shape3d_last_error(void);

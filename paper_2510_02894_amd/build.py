@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshape3d.so")
-SOURCES = ["mesh.hip", "scan.hip", "pairs.hip", "soft.hip", "api.hip"]
+SOURCES = ["mesh.hip", "scan.hip", "pairs.hip", "prune.hip", "soft.hip", "api.hip"]
 # per-file flags: the pair kernel's maxima never see NaNs (MFMA results), so
 # fmaxf needs no canonicalisation there
 EXTRA = {"pairs.hip": ["-fno-honor-nans"]}

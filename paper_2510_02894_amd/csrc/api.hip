@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -27,6 +28,9 @@
 #include "s3d_launch.h"
 
 using namespace s3d;
+
+static_assert(sizeof(shape3d_roi_ex) == sizeof(RoiDesc), "shape3d_roi_ex and RoiDesc must have one layout");
+static_assert(offsetof(shape3d_roi_ex, label) == offsetof(RoiDesc, label), "shape3d_roi_ex and RoiDesc must have one layout");
 
 namespace {
 
@@ -49,10 +53,31 @@ struct Buf {
   size_t cap = 0;
 };
 
+// Device buffers of the forward pipeline.  The layout buffers depend on the
+// batch shape only (ROIs, bricks, plane buckets); the vertex buffers also on
+// the layout-0 row capacity.  The library's own workspace grows each buffer
+// on demand; a caller's workspace is carved into all of them at once.
+enum WsId {
+  W_ROIS, W_PLAN, W_PART, W_BRICK_VOFF, W_META, W_CASE_AREA, W_TOTALS, W_COUNTERS, W_GRES, W_RES, W_PAIRS2D,
+  W_BCNT, W_BCUR, W_BSZ, W_BFLAG, W_BROW, W_BSEG, W_BGROUP,
+  W_FIRST_VERTEX_BUF,
+  W_KEY = W_FIRST_VERTEX_BUF, W_TSOFT, W_POS, W_POSH, W_ORIG, W_ROWMAX, W_BLKSEG, W_SEGS, W_NCOL, W_COLBASE,
+  W_COLS, W_NITEM, W_ITEMBASE, W_SCAN_TMP, W_CAND, W_CAND_NCH, W_CAND_CHBASE, W_BLKREC, W_RSEED, W_PITEM,
+  W_NUM
+};
+
+struct Ptrs {
+  void* p[W_NUM] = {};
+  template <typename T>
+  T* as(int i) const {
+    return (T*)p[i];
+  }
+};
+
 struct GraphRec {
   hipGraphExec_t exec = nullptr;
   long long generation = -1;
-  RoiResult* host_res = nullptr;  // pinned, written by the graph's last copy
+  RoiResult* host_res = nullptr;  // pinned, written by the graph's last copy (host-output graphs)
   long long n_rois = 0;
   long long stamp = 0;            // last use (the least recently used graph is dropped first)
 };
@@ -63,37 +88,37 @@ struct Workspace {
   int device = -1;
   int cu_count = 0;
   long long generation = 0;  // bumped whenever a buffer is reallocated (graphs hold pointers)
-  Buf rois, part, brick_voff, meta, totals, key, tsoft, pos, orig, rowmax, blkseg, segs, bcnt, bcur, bsz, bflag, brow,
-      bseg, bgroup, ncol, colbase, cols, nitem, itembase, scan_tmp, counters, gres, cand, res, pairs2d, cand_nch, cand_chbase,
-      posh, case_area, soft_rois, soft_edges, soft_field, soft_ctr, soft_blk;
+  Buf buf[W_NUM];
+  Buf soft_rois, soft_edges, soft_field, soft_ctr, soft_blk;  // soft backward
   void* host = nullptr;  // pinned staging: ROI table, read-backs, results
   size_t host_cap = 0;
   hipEvent_t ev[8] = {};
   bool events = false;
   hipStream_t graph_stream = nullptr;  // graphs are recorded and replayed here (the caller's
                                        // stream may be the legacy null stream, which cannot record)
-  long long rows0_cap = 0;  // layout-0 rows the vertex buffers were sized for
+  long long rows0_cap = 0;   // layout-0 rows the vertex buffers were sized for
   long long last_rows0 = 0;  // layout-0 rows of the last eager run (a recorded graph is sized for them)
+  long long last_vmax = 0;   // largest vertex count of the last eager run
   std::map<std::string, GraphRec> graphs;
   long long stamp = 0;
 
-  std::vector<Buf*> all() {
-    return {&rois,     &part,    &brick_voff, &meta,    &totals, &key,   &tsoft, &pos,     &orig,     &rowmax,
-            &blkseg,   &segs,    &bcnt,       &bcur,    &bsz,    &bflag, &brow,  &bseg,    &bgroup, &ncol,     &colbase,
-            &cols,     &nitem,   &itembase,   &scan_tmp, &counters, &gres, &cand, &res,    &pairs2d,  &cand_nch,
-            &cand_chbase, &posh, &case_area, &soft_rois, &soft_edges, &soft_field, &soft_ctr, &soft_blk};
+  Ptrs ptrs() const {
+    Ptrs P;
+    for (int i = 0; i < W_NUM; ++i) P.p[i] = buf[i].p;
+    return P;
   }
+  std::vector<Buf*> soft_bufs() { return {&soft_rois, &soft_edges, &soft_field, &soft_ctr, &soft_blk}; }
 };
 
 std::map<int, Workspace*> g_ws;
 
 // Tile sizes of the pair pass for every device (results do not depend on them).
-Tuning g_tune = {8, 1024, 0, 1};
+Tuning g_tune = {8, 1024, 0, 1, 1};
 
 bool valid_tuning(const Tuning& t) {
   return (t.itile == 2 || t.itile == 4 || t.itile == 8) &&
          (t.jchunk == 64 || t.jchunk == 128 || t.jchunk == 256 || t.jchunk == 512 || t.jchunk == 1024) && t.blocks_per_cu >= 0 &&
-         t.blocks_per_cu <= 64 && (t.kernel == 0 || (t.kernel == 1 && t.itile >= 4));
+         t.blocks_per_cu <= 64 && (t.kernel == 0 || (t.kernel == 1 && t.itile >= 4)) && (t.prune >= 0 && t.prune <= 2);
 }
 
 void drop_graphs(Workspace& w) {
@@ -141,6 +166,11 @@ int ensure_host(Workspace& w, size_t bytes) {
   return SHAPE3D_OK;
 }
 
+int device_cu_count(int dev, int* cu) {
+  HIPCK(hipDeviceGetAttribute(cu, hipDeviceAttributeMultiprocessorCount, dev));
+  return SHAPE3D_OK;
+}
+
 int get_workspace(Workspace** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
@@ -153,9 +183,11 @@ int get_workspace(Workspace** out) {
   if (it == g_ws.end()) {
     Workspace* w = new Workspace();
     w->device = dev;
-    hipDeviceProp_t prop;
-    HIPCK(hipGetDeviceProperties(&prop, dev));
-    w->cu_count = prop.multiProcessorCount;
+    int rc = device_cu_count(dev, &w->cu_count);
+    if (rc) {
+      delete w;
+      return rc;
+    }
     for (int i = 0; i < 8; ++i) HIPCK(hipEventCreate(&w->ev[i]));
     w->events = true;
     HIPCK(hipStreamCreateWithFlags(&w->graph_stream, hipStreamNonBlocking));
@@ -176,14 +208,14 @@ int check_dims_spacing(const int64_t dims[3], const double spacing[3]) {
 
 // The device allocation holding ptr: [*base, *base + *size) (*base = null if
 // the runtime cannot tell).  Fails for host memory.
-int device_range(const void* ptr, const char** base, size_t* size) {
+int device_range(const void* ptr, const char** base, size_t* size, const char* what = "volume") {
   hipPointerAttribute_t attr;
   if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(SHAPE3D_EINVAL, "volume pointer is not HIP device memory");
+    return fail(SHAPE3D_EINVAL, std::string(what) + " pointer is not HIP device memory");
   }
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
-    return fail(SHAPE3D_EINVAL, "volume pointer is not HIP device memory");
+    return fail(SHAPE3D_EINVAL, std::string(what) + " pointer is not HIP device memory");
   void* b = nullptr;
   size_t s = 0;
   if (hipMemGetAddressRange(&b, &s, (void*)ptr) == hipSuccess && b) {
@@ -197,59 +229,73 @@ int device_range(const void* ptr, const char** base, size_t* size) {
   return SHAPE3D_OK;
 }
 
+// Checks that [ptr, ptr + bytes) is device memory inside one allocation.
+int check_device_span(const void* ptr, size_t bytes, const char* what) {
+  if (!ptr) return fail(SHAPE3D_EINVAL, std::string("null ") + what);
+  const char* base;
+  size_t size;
+  int rc = device_range(ptr, &base, &size, what);
+  if (rc) return rc;
+  if (base && (const char*)ptr + bytes > base + size)
+    return fail(SHAPE3D_EINVAL, std::string(what) + " extends past the end of its allocation");
+  return SHAPE3D_OK;
+}
+
 int check_args(const void* vol, int dtype, const int64_t dims[3], const double spacing[3]) {
   if (!vol || !dims || !spacing) return fail(SHAPE3D_EINVAL, "null argument");
   if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "dtype must be SHAPE3D_U8 or SHAPE3D_F32");
   int rc = check_dims_spacing(dims, spacing);
   if (rc) return rc;
   const size_t need = (size_t)dims[0] * (size_t)dims[1] * (size_t)dims[2] * (dtype == SHAPE3D_U8 ? 1 : 4);
-  const char* base;
-  size_t size;
-  if ((rc = device_range(vol, &base, &size))) return rc;
-  if (base && (const char*)vol + need > base + size)
-    return fail(SHAPE3D_EINVAL, "volume extends past the end of its allocation");
-  return SHAPE3D_OK;
+  return check_device_span(vol, need, "volume");
 }
 
-// Host description of a batch.
+// Host description of a batch: its ROIs (host tables), or only bounds on its
+// shape (tables planned on the device, `planned`).
 struct Batch {
   std::vector<Roi> rois;
-  long long nbricks = 0;
-  long long n_buckets = 0;
+  int n_rois = 0;
+  long long nbricks = 0;    // bricks (a bound when planned)
+  long long n_buckets = 0;  // plane buckets (a bound when planned)
   int max_G = 1;
-  int n() const { return (int)rois.size(); }
+  bool planned = false;
+  long long max_d[3] = {0, 0, 0};  // planned: every ROI's dims are at most these
+  int n() const { return n_rois; }
 };
 
-// Magic numbers (fdiv) of the kernels' 32-bit division by D (numerators < 2^31).
-void magic_div(unsigned int D, unsigned int& m, int& sh) {
-  int k = 0;
-  while ((1ull << k) < D) ++k;  // ceil(log2 D)
-  sh = 31 + k;
-  m = (unsigned int)((1ull << sh) / D + 1);
-}
-
-void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double spacing[3]) {
+void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double spacing[3], long long stride0 = 0,
+               long long stride1 = 0, int label = 0) {
   Roi R;
   memset(&R, 0, sizeof(R));
-  R.vol = vol;
-  for (int k = 0; k < 3; ++k) {
-    R.d[k] = (int)dims[k];
-    R.s[k] = spacing[k];
-  }
-  R.G = (R.d[2] + 1 + 31) / 32;
-  R.nrg = (R.d[1] + 1) * R.G;
-  R.nzc = (R.d[0] + 1 + kTZ - 1) / kTZ;
-  R.bpz = (R.nrg + kBrickThreads - 1) / kBrickThreads;
-  magic_div((unsigned int)R.G, R.mG, R.shG);
-  magic_div((unsigned int)(kBrickThreads + 1 + R.G), R.mNW, R.shNW);
+  const long long d[3] = {dims[0], dims[1], dims[2]};
+  const long long nb = roi_fill(R, vol, d, spacing, stride0, stride1, label);
   R.brick_begin = B.nbricks;
-  R.bucket_base[0] = B.n_buckets;
-  R.bucket_base[1] = R.bucket_base[0] + 2ll * R.d[0] + 1;
-  R.bucket_base[2] = R.bucket_base[1] + 2ll * R.d[1] + 1;
-  B.nbricks += (long long)R.nzc * R.bpz;
-  B.n_buckets = R.bucket_base[2] + 2ll * R.d[2] + 1;
+  R.brick_end = B.nbricks + nb;
+  roi_set_buckets(R, B.n_buckets);
+  B.nbricks += nb;
+  B.n_buckets += roi_buckets(R.d);
   B.max_G = std::max(B.max_G, R.G);
   B.rois.push_back(R);
+  B.n_rois = (int)B.rois.size();
+}
+
+// Bounds of a batch of n ROIs planned on the device, each at most max_dims.
+int batch_bounds(Batch& B, int64_t n, const int64_t max_dims[3]) {
+  const double one[3] = {1.0, 1.0, 1.0};
+  int rc = check_dims_spacing(max_dims, one);
+  if (rc) return rc;
+  Roi R;
+  memset(&R, 0, sizeof(R));
+  const long long d[3] = {max_dims[0], max_dims[1], max_dims[2]};
+  const long long nb = roi_fill(R, nullptr, d, one, 0, 0, 0);
+  B.planned = true;
+  B.n_rois = (int)n;
+  for (int k = 0; k < 3; ++k) B.max_d[k] = max_dims[k];
+  B.nbricks = nb * n;
+  B.n_buckets = roi_buckets(R.d) * n;
+  B.max_G = R.G;
+  if (B.nbricks > (1ll << 31) - 1) return fail(SHAPE3D_EINVAL, "batch too large (bricks of n_rois ROIs of max_dims)");
+  return SHAPE3D_OK;
 }
 
 struct Sizes {
@@ -267,31 +313,119 @@ Sizes sizes_for(const Batch& B, long long rows0) {
   return S;
 }
 
-// Buffers that depend only on the batch layout.
-int ensure_layout_bufs(Workspace& w, const Batch& B) {
-  int rc;
-  const int n = B.n();
-  if ((rc = ensure(w, w.rois, sizeof(Roi) * n))) return rc;
-  if ((rc = ensure(w, w.part, sizeof(BrickPart) * B.nbricks))) return rc;
-  if ((rc = ensure(w, w.brick_voff, sizeof(long long) * B.nbricks))) return rc;
-  if ((rc = ensure(w, w.meta, sizeof(RoiMeta) * n))) return rc;
-  if ((rc = ensure(w, w.case_area, sizeof(double) * 256 * (size_t)n))) return rc;
-  if ((rc = ensure(w, w.totals, sizeof(long long) * 16))) return rc;
-  if ((rc = ensure(w, w.counters, sizeof(unsigned int) * kCounterWords))) return rc;
-  if ((rc = ensure(w, w.gres, sizeof(GroupRes) * 4 * (size_t)n))) return rc;
-  if ((rc = ensure(w, w.res, sizeof(RoiResult) * n))) return rc;
-  if ((rc = ensure(w, w.pairs2d, sizeof(long long) * n))) return rc;
-  if ((rc = ensure(w, w.bcnt, sizeof(unsigned int) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.bcur, sizeof(unsigned int) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.bsz, sizeof(long long) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.bflag, sizeof(long long) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.brow, sizeof(long long) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.bseg, sizeof(long long) * B.n_buckets))) return rc;
-  if ((rc = ensure(w, w.bgroup, sizeof(int) * B.n_buckets))) return rc;
-  // pinned staging: [0, 4096) read-backs, then the ROI table, then the results
-  const size_t host_need = 4096 + sizeof(Roi) * (size_t)n + 256 + sizeof(RoiResult) * (size_t)n;
-  if ((rc = ensure_host(w, host_need))) return rc;
+// Row indices of every layout are 32-bit in the kernels.
+constexpr long long kMaxRows = (1ll << 31) - 1024;
+
+// Byte sizes of every buffer for a batch and a layout-0 row capacity.
+struct Layout {
+  size_t bytes[W_NUM];
+  Sizes S;
+};
+
+int ws_layout(const Batch& B, int dtype, const Tuning& t, long long rows0_cap, Layout& L) {
+  const Sizes S = sizes_for(B, rows0_cap);
+  if (S.rows_bound > kMaxRows || B.n_buckets > kMaxRows)
+    return fail(SHAPE3D_ECAPACITY, "mesh too large: " + std::to_string(S.rows_bound) +
+                                       " vertex rows exceed the 32-bit row indices of the kernels");
+  const long long n = B.n();
+  const long long scan_n = std::max(std::max(B.n_buckets, S.rows_bound), std::max(S.seg_cap, S.col_cap));
+  size_t* b = L.bytes;
+  b[W_ROIS] = sizeof(Roi) * n;
+  b[W_PLAN] = sizeof(long long) * 4;
+  b[W_PART] = sizeof(BrickPart) * B.nbricks;
+  b[W_BRICK_VOFF] = sizeof(long long) * B.nbricks;
+  b[W_META] = sizeof(RoiMeta) * n;
+  b[W_CASE_AREA] = sizeof(double) * 256 * n;
+  b[W_TOTALS] = sizeof(long long) * 16;
+  b[W_COUNTERS] = sizeof(unsigned int) * kCounterWords;
+  b[W_GRES] = sizeof(GroupRes) * 4 * n;
+  b[W_RES] = sizeof(RoiResult) * n;
+  b[W_PAIRS2D] = sizeof(long long) * n;
+  b[W_BCNT] = b[W_BCUR] = sizeof(unsigned int) * B.n_buckets;
+  b[W_BSZ] = b[W_BFLAG] = b[W_BROW] = b[W_BSEG] = sizeof(long long) * B.n_buckets;
+  b[W_BGROUP] = sizeof(int) * B.n_buckets;
+  const long long r0 = std::max<long long>(S.rows0, 1);
+  b[W_KEY] = sizeof(unsigned long long) * r0;
+  b[W_TSOFT] = dtype == SHAPE3D_F32 ? sizeof(double) * r0 : 0;
+  // pair-pass operands: FP32 position blocks (kernel 0, 16 B per row) or
+  // split-f16 B operands (kernel 1, 1 KB per 32-row block)
+  b[W_POS] = t.kernel == 0 ? sizeof(float) * 4 * S.rows_bound : 0;
+  b[W_POSH] = t.kernel == 1 ? (size_t)1024 * ((S.rows_bound + 31) / 32) : 0;
+  b[W_ORIG] = sizeof(int) * S.rows_bound;
+  b[W_ROWMAX] = sizeof(float) * S.rows_bound;
+  b[W_BLKSEG] = sizeof(int) * (S.rows_bound / kBlk + 1);
+  b[W_SEGS] = sizeof(Seg) * S.seg_cap;
+  b[W_NCOL] = b[W_COLBASE] = sizeof(long long) * S.seg_cap;
+  b[W_COLS] = sizeof(Col) * S.col_cap;
+  b[W_NITEM] = b[W_ITEMBASE] = sizeof(long long) * S.col_cap;
+  b[W_SCAN_TMP] = sizeof(long long) * scan_tmp_elems(scan_n);
+  // candidate rows of the exact refinement: every row could be one
+  b[W_CAND] = sizeof(int) * S.rows_bound;
+  b[W_CAND_NCH] = b[W_CAND_CHBASE] = sizeof(long long) * S.rows_bound;
+  // 3D pruning: a record per 32-row block of layout 0, a seed record per ROI,
+  // and pruned items (one per 8 rows; a longer list falls back to all pairs)
+  b[W_BLKREC] = t.kernel == 1 ? sizeof(BlkRec) * (S.rows0 / 32 + 1) : 0;
+  b[W_RSEED] = t.kernel == 1 ? sizeof(RoiSeed) * n : 0;
+  b[W_PITEM] = t.kernel == 1 ? sizeof(PItem) * (S.rows0 / 8 + 64) : 0;
+  L.S = S;
   return SHAPE3D_OK;
+}
+
+size_t aligned(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t ws_total(const Layout& L) {
+  size_t t = 0;
+  for (int i = 0; i < W_NUM; ++i) t += aligned(std::max<size_t>(L.bytes[i], 1));
+  return t;
+}
+
+// The largest layout-0 row capacity (a multiple of kSegAlign) whose buffers
+// fit in `bytes`; -1 if not even an empty mesh fits.
+long long rows_cap_for(const Batch& B, int dtype, const Tuning& t, size_t bytes) {
+  Layout L;
+  if (ws_layout(B, dtype, t, 0, L) || ws_total(L) > bytes) return -1;
+  long long lo = 0, hi = kMaxRows / 4 / kSegAlign;  // in units of kSegAlign rows
+  while (lo < hi) {
+    const long long mid = (lo + hi + 1) / 2;
+    if (!ws_layout(B, dtype, t, mid * kSegAlign, L) && ws_total(L) <= bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  g_err.clear();
+  return lo * kSegAlign;
+}
+
+// Pointers of a caller's workspace block laid out for L (256-byte aligned).
+int carve(const Layout& L, void* ws, size_t ws_bytes, Ptrs& P) {
+  if (((uintptr_t)ws & 255u) != 0) return fail(SHAPE3D_EINVAL, "workspace must be 256-byte aligned");
+  size_t off = 0;
+  for (int i = 0; i < W_NUM; ++i) {
+    P.p[i] = (char*)ws + off;
+    off += aligned(std::max<size_t>(L.bytes[i], 1));
+  }
+  if (off > ws_bytes) return fail(SHAPE3D_ECAPACITY, "workspace too small");
+  return SHAPE3D_OK;
+}
+
+// Grows the library's buffers [from, to) to the sizes of L.
+int ensure_bufs(Workspace& w, const Layout& L, int from, int to) {
+  for (int i = from; i < to; ++i) {
+    const int rc = ensure(w, w.buf[i], L.bytes[i]);
+    if (rc) return rc;
+  }
+  return SHAPE3D_OK;
+}
+
+// Buffers that depend only on the batch shape.
+int ensure_layout_bufs(Workspace& w, const Batch& B, int dtype) {
+  Layout L;
+  int rc = ws_layout(B, dtype, g_tune, 0, L);
+  if (!rc) rc = ensure_bufs(w, L, 0, W_FIRST_VERTEX_BUF);
+  if (rc) return rc;
+  // pinned staging: [0, 4096) read-backs, then the ROI table, then the results
+  const size_t host_need = 4096 + sizeof(Roi) * (size_t)B.n() + 256 + sizeof(RoiResult) * (size_t)B.n();
+  return ensure_host(w, host_need);
 }
 
 RoiResult* host_results(Workspace& w, const Batch& B) {
@@ -299,108 +433,101 @@ RoiResult* host_results(Workspace& w, const Batch& B) {
   return (RoiResult*)((p + 255) & ~(uintptr_t)255);
 }
 
-// Buffers sized by the layout-0 row count (all ROIs' padded vertex rows).
 // Grows the vertex buffers to hold rows0 layout-0 rows (they never shrink) and
 // returns in S the sizes of this call's work, which follow rows0 itself.
 int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0, Sizes& S_call) {
-  int rc;
-  const Sizes S = sizes_for(B, std::max<long long>(rows0, w.rows0_cap));
-  S_call = sizes_for(B, rows0);
-  const long long scan_n = std::max(std::max(B.n_buckets, S.rows_bound), std::max(S.seg_cap, S.col_cap));
-  if ((rc = ensure(w, w.key, sizeof(unsigned long long) * std::max<long long>(S.rows0, 1)))) return rc;
-  if (dtype == SHAPE3D_F32 && (rc = ensure(w, w.tsoft, sizeof(double) * std::max<long long>(S.rows0, 1)))) return rc;
-  // pair-pass operands: FP32 position blocks (kernel 0, 16 B per row) or
-  // split-f16 B operands (kernel 1, 1 KB per 32-row block)
-  if (g_tune.kernel == 0 && (rc = ensure(w, w.pos, sizeof(float) * 4 * S.rows_bound))) return rc;
-  if (g_tune.kernel == 1 && (rc = ensure(w, w.posh, (size_t)1024 * ((S.rows_bound + 31) / 32)))) return rc;
-  if ((rc = ensure(w, w.orig, sizeof(int) * S.rows_bound))) return rc;
-  if ((rc = ensure(w, w.rowmax, sizeof(float) * S.rows_bound))) return rc;
-  if ((rc = ensure(w, w.blkseg, sizeof(int) * (S.rows_bound / kBlk + 1)))) return rc;
-  if ((rc = ensure(w, w.segs, sizeof(Seg) * S.seg_cap))) return rc;
-  if ((rc = ensure(w, w.ncol, sizeof(long long) * S.seg_cap))) return rc;
-  if ((rc = ensure(w, w.colbase, sizeof(long long) * S.seg_cap))) return rc;
-  if ((rc = ensure(w, w.cols, sizeof(Col) * S.col_cap))) return rc;
-  if ((rc = ensure(w, w.nitem, sizeof(long long) * S.col_cap))) return rc;
-  if ((rc = ensure(w, w.itembase, sizeof(long long) * S.col_cap))) return rc;
-  if ((rc = ensure(w, w.scan_tmp, sizeof(long long) * scan_tmp_elems(scan_n)))) return rc;
-  // candidate rows of the exact refinement: every row could be one
-  if ((rc = ensure(w, w.cand, sizeof(int) * S.rows_bound))) return rc;
-  if ((rc = ensure(w, w.cand_nch, sizeof(long long) * S.rows_bound))) return rc;
-  if ((rc = ensure(w, w.cand_chbase, sizeof(long long) * S.rows_bound))) return rc;
-  w.rows0_cap = S.rows0;
+  Layout L, Lc;
+  int rc = ws_layout(B, dtype, g_tune, rows0, Lc);
+  if (!rc) rc = ws_layout(B, dtype, g_tune, std::max<long long>(rows0, w.rows0_cap), L);
+  if (!rc) rc = ensure_bufs(w, L, W_FIRST_VERTEX_BUF, W_NUM);
+  if (rc) return rc;
+  S_call = Lc.S;
+  w.rows0_cap = L.S.rows0;
   return SHAPE3D_OK;
 }
 
-PairBufs pair_bufs(Workspace& w, const Batch& Bt, int dtype, const Sizes& S) {
+PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, int cu_count) {
   PairBufs B;
-  B.rois = (const Roi*)w.rois.p;
+  B.rois = P.as<const Roi>(W_ROIS);
   B.n_rois = Bt.n();
-  B.meta = (const RoiMeta*)w.meta.p;
-  B.key = (const unsigned long long*)w.key.p;
-  B.tsoft = dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr;
-  B.pos = (float*)w.pos.p;
-  B.posh = (uint4*)w.posh.p;
-  B.orig = (int*)w.orig.p;
-  B.rowmax = (float*)w.rowmax.p;
-  B.blkseg = (int*)w.blkseg.p;
-  B.segs = (Seg*)w.segs.p;
+  B.meta = P.as<const RoiMeta>(W_META);
+  B.key = P.as<const unsigned long long>(W_KEY);
+  B.tsoft = dtype == SHAPE3D_F32 ? P.as<const double>(W_TSOFT) : nullptr;
+  B.pos = P.as<float>(W_POS);
+  B.posh = P.as<uint4>(W_POSH);
+  B.orig = P.as<int>(W_ORIG);
+  B.rowmax = P.as<float>(W_ROWMAX);
+  B.blkseg = P.as<int>(W_BLKSEG);
+  B.segs = P.as<Seg>(W_SEGS);
   B.rows0 = S.rows0;
   B.n_buckets = Bt.n_buckets;
-  B.bcnt = (unsigned int*)w.bcnt.p;
-  B.bcur = (unsigned int*)w.bcur.p;
-  B.bsz = (long long*)w.bsz.p;
-  B.bflag = (long long*)w.bflag.p;
-  B.bgroup = (int*)w.bgroup.p;
-  B.brow = (long long*)w.brow.p;
-  B.bseg = (long long*)w.bseg.p;
+  B.bcnt = P.as<unsigned int>(W_BCNT);
+  B.bcur = P.as<unsigned int>(W_BCUR);
+  B.bsz = P.as<long long>(W_BSZ);
+  B.bflag = P.as<long long>(W_BFLAG);
+  B.bgroup = P.as<int>(W_BGROUP);
+  B.brow = P.as<long long>(W_BROW);
+  B.bseg = P.as<long long>(W_BSEG);
   B.seg_cap = S.seg_cap;
-  B.ncol = (long long*)w.ncol.p;
-  B.colbase = (long long*)w.colbase.p;
+  B.ncol = P.as<long long>(W_NCOL);
+  B.colbase = P.as<long long>(W_COLBASE);
   B.col_cap = S.col_cap;
-  B.cols = (Col*)w.cols.p;
-  B.nitem = (long long*)w.nitem.p;
-  B.itembase = (long long*)w.itembase.p;
-  B.totals = (long long*)w.totals.p;
-  B.scan_tmp = (long long*)w.scan_tmp.p;
-  B.counters = (unsigned int*)w.counters.p;
-  B.gres = (GroupRes*)w.gres.p;
-  B.cand = (int*)w.cand.p;
+  B.cols = P.as<Col>(W_COLS);
+  B.nitem = P.as<long long>(W_NITEM);
+  B.itembase = P.as<long long>(W_ITEMBASE);
+  B.totals = P.as<long long>(W_TOTALS);
+  B.scan_tmp = P.as<long long>(W_SCAN_TMP);
+  B.counters = P.as<unsigned int>(W_COUNTERS);
+  B.gres = P.as<GroupRes>(W_GRES);
+  B.cand = P.as<int>(W_CAND);
   B.cand_cap = S.rows_bound;
   B.tune = g_tune;
   B.max_rows_seg = S.rows0;
   B.rows_bound = S.rows_bound;
-  B.res = (RoiResult*)w.res.p;
-  B.pairs2d = (long long*)w.pairs2d.p;
-  B.cand_nch = (long long*)w.cand_nch.p;
-  B.cand_chbase = (long long*)w.cand_chbase.p;
-  B.cu_count = w.cu_count;
+  B.res = P.as<RoiResult>(W_RES);
+  B.pairs2d = P.as<long long>(W_PAIRS2D);
+  B.cand_nch = P.as<long long>(W_CAND_NCH);
+  B.cand_chbase = P.as<long long>(W_CAND_CHBASE);
+  B.cu_count = cu_count;
+  B.prune = false;
+  B.blkrec = P.as<BlkRec>(W_BLKREC);
+  B.rseed = P.as<RoiSeed>(W_RSEED);
+  B.pitems = P.as<PItem>(W_PITEM);
+  B.pitem_cap = S.rows0 / 8 + 64;
   return B;
 }
 
 // Mesh count and per-ROI totals (launches only).
-int launch_head(Workspace& w, const Batch& Bt, int dtype, hipStream_t st) {
-  HIPCK(launch_fill_u32((unsigned int*)w.counters.p, 0u, kCounterWords, st));
-  HIPCK(launch_mesh_count(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (double*)w.case_area.p,
-                          (BrickPart*)w.part.p, st));
-  HIPCK(launch_mesh_totals((const Roi*)w.rois.p, Bt.n(), Bt.nbricks, dtype, (const BrickPart*)w.part.p,
-                           (long long*)w.brick_voff.p, (RoiMeta*)w.meta.p, (long long*)w.totals.p, st));
+int launch_head(const Ptrs& P, const Batch& Bt, int dtype, hipStream_t st) {
+  HIPCK(launch_fill_u32(P.as<unsigned int>(W_COUNTERS), 0u, kCounterWords, st));
+  HIPCK(launch_mesh_count(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<double>(W_CASE_AREA),
+                          P.as<BrickPart>(W_PART), st));
+  HIPCK(launch_mesh_totals(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, dtype, P.as<const BrickPart>(W_PART),
+                           P.as<long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS), st));
   return SHAPE3D_OK;
 }
 
-// Everything after the totals (launches only).  ev: optional phase events
-// recorded before emission, buckets, pairs, refinement and finalisation.
-int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStream_t st, RoiResult* host_res,
-                hipEvent_t* ev) {
-  const PairBufs B = pair_bufs(w, Bt, dtype, S);
-  HIPCK(launch_check_capacity(Bt.n(), S.rows0, (RoiMeta*)w.meta.p, (long long*)w.totals.p,
-                              (unsigned int*)w.counters.p + 2, st));
+// Everything after the totals, up to the per-ROI results in W_RES (launches
+// only).  ev: optional phase events recorded before emission, buckets, pairs,
+// refinement and finalisation.
+// vmax_hint: the largest vertex count of the batch (a bound), or -1 if unknown;
+// with prune = 1 the 3D pairs are pruned when it may reach kPruneMinV, with
+// prune = 2 always.
+int launch_tail(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, int cu_count, hipStream_t st,
+                hipEvent_t* ev, long long vmax_hint) {
+  PairBufs B = pair_bufs(P, Bt, dtype, S, cu_count);
+  B.prune = g_tune.kernel == 1 &&
+            (g_tune.prune == 2 || (g_tune.prune == 1 && (vmax_hint < 0 || vmax_hint >= kPruneMinV)));
+  HIPCK(launch_check_capacity(Bt.n(), S.rows0, P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
+                              P.as<unsigned int>(W_COUNTERS) + 2, st));
   if (ev) HIPCK(hipEventRecord(ev[0], st));
-  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, Bt.n(), Bt.nbricks, Bt.max_G, (const BrickPart*)w.part.p,
-                         (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
-                         (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
-                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p, split_rows(B),
-                         (int*)w.orig.p, (int*)w.blkseg.p, (Seg*)w.segs.p, st));
+  HIPCK(launch_mesh_emit(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<const BrickPart>(W_PART),
+                         P.as<const long long>(W_BRICK_VOFF), P.as<const RoiMeta>(W_META),
+                         P.as<const unsigned int>(W_COUNTERS) + 2, P.as<unsigned long long>(W_KEY),
+                         dtype == SHAPE3D_F32 ? P.as<double>(W_TSOFT) : nullptr, P.as<float>(W_POS), split_rows(B),
+                         P.as<int>(W_ORIG), P.as<int>(W_BLKSEG), P.as<Seg>(W_SEGS), st));
   if (ev) HIPCK(hipEventRecord(ev[1], st));
+  if (B.prune) HIPCK(launch_prune(B, st));
   HIPCK(launch_buckets(B, st));
   HIPCK(launch_init_groups(B, st));  // also zeroes the row maxima
   if (ev) HIPCK(hipEventRecord(ev[2], st));
@@ -409,27 +536,51 @@ int launch_tail(Workspace& w, const Batch& Bt, int dtype, const Sizes& S, hipStr
   HIPCK(launch_refine(B, st));
   if (ev) HIPCK(hipEventRecord(ev[4], st));
   HIPCK(launch_finalize(B, st));
-  HIPCK(hipMemcpyAsync(host_res, w.res.p, sizeof(RoiResult) * Bt.n(), hipMemcpyDeviceToHost, st));
   return SHAPE3D_OK;
 }
 
-// One eager run of a batch; results land in host_res (pinned, one per ROI).
-int run_eager(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, RoiResult* host_res, int timing,
-              float* phase_ms) {
-  int rc;
+// The ROI table into W_ROIS: a host table through the pinned staging buffer
+// (library workspace), or planned on the device from a caller's descriptors.
+struct DevTable {
+  const RoiDesc* rois = nullptr;
+  long long max_dims[3] = {0, 0, 0};
+  const void* base = nullptr;
+  long long alloc_elems = 0;
+};
+
+int upload_rois(Workspace& w, const Ptrs& P, const Batch& Bt, int dtype, const DevTable* dt, hipStream_t st) {
+  if (dt) {
+    HIPCK(launch_plan_rois(dt->rois, Bt.n(), dtype, dt->max_dims, dt->base, dt->alloc_elems, P.as<Roi>(W_ROIS),
+                           P.as<long long>(W_PLAN), st));
+    return SHAPE3D_OK;
+  }
   char* h = (char*)w.host;
   memcpy(h + 4096, Bt.rois.data(), sizeof(Roi) * Bt.n());
-  HIPCK(hipMemcpyAsync(w.rois.p, h + 4096, sizeof(Roi) * Bt.n(), hipMemcpyHostToDevice, st));
+  HIPCK(hipMemcpyAsync(P.p[W_ROIS], h + 4096, sizeof(Roi) * Bt.n(), hipMemcpyHostToDevice, st));
+  return SHAPE3D_OK;
+}
+
+// One eager run of a batch on the library workspace; the per-ROI results are
+// left in W_RES and, if host_res is set, copied there (pinned).
+int run_eager(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, RoiResult* host_res, int timing,
+              float* phase_ms, const DevTable* dt = nullptr) {
+  int rc;
+  char* h = (char*)w.host;
+  Ptrs P = w.ptrs();
+  if ((rc = upload_rois(w, P, Bt, dtype, dt, st))) return rc;
   if (timing) HIPCK(hipEventRecord(w.ev[0], st));
-  if ((rc = launch_head(w, Bt, dtype, st))) return rc;
+  if ((rc = launch_head(P, Bt, dtype, st))) return rc;
   if (timing) HIPCK(hipEventRecord(w.ev[1], st));
   long long* th = (long long*)h;
-  HIPCK(hipMemcpyAsync(th, w.totals.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(th, P.p[W_TOTALS], sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   Sizes S;
   if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
+  P = w.ptrs();
   w.last_rows0 = th[0];
-  if ((rc = launch_tail(w, Bt, dtype, S, st, host_res, timing ? &w.ev[2] : nullptr))) return rc;
+  w.last_vmax = th[1];
+  if ((rc = launch_tail(P, Bt, dtype, S, w.cu_count, st, timing ? &w.ev[2] : nullptr, th[1]))) return rc;
+  if (host_res) HIPCK(hipMemcpyAsync(host_res, P.p[W_RES], sizeof(RoiResult) * Bt.n(), hipMemcpyDeviceToHost, st));
   if (timing) HIPCK(hipEventRecord(w.ev[7], st));
   HIPCK(hipStreamSynchronize(st));
   if (timing && phase_ms) {
@@ -439,6 +590,31 @@ int run_eager(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, RoiResul
     const int b[7] = {1, 3, 4, 5, 6, 7, 7};
     for (int k = 0; k < 7; ++k) HIPCK(hipEventElapsedTime(&phase_ms[k], w.ev[a[k]], w.ev[b[k]]));
   }
+  return SHAPE3D_OK;
+}
+
+// The whole pipeline on fixed buffers (a caller's workspace), without any
+// host synchronisation: the ROI table is set on the device, the vertex
+// capacity comes from the workspace size, and a mesh beyond it ends with
+// status SHAPE3D_ECAPACITY for every ROI.  Results go to out/status (device).
+int run_fixed(const Batch& Bt, int dtype, const Roi* one_roi, const DevTable* dt, void* ws, size_t ws_bytes,
+              int cu_count, double* out, int* status, hipStream_t st) {
+  const long long cap = rows_cap_for(Bt, dtype, g_tune, ws_bytes);
+  if (cap < 0) return fail(SHAPE3D_ECAPACITY, "workspace too small for this input's mesh-pass buffers");
+  Layout L;
+  int rc = ws_layout(Bt, dtype, g_tune, cap, L);
+  Ptrs P;
+  if (!rc) rc = carve(L, ws, ws_bytes, P);
+  if (rc) return rc;
+  if (dt) {
+    HIPCK(launch_plan_rois(dt->rois, Bt.n(), dtype, dt->max_dims, dt->base, dt->alloc_elems, P.as<Roi>(W_ROIS),
+                           P.as<long long>(W_PLAN), st));
+  } else {
+    HIPCK(launch_set_roi(*one_roi, P.as<Roi>(W_ROIS), st));
+  }
+  if ((rc = launch_head(P, Bt, dtype, st))) return rc;
+  if ((rc = launch_tail(P, Bt, dtype, L.S, cu_count, st, nullptr, cap))) return rc;
+  HIPCK(launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, st));
   return SHAPE3D_OK;
 }
 
@@ -468,7 +644,7 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   Workspace& w = *wp;
   Batch Bt;
   batch_add(Bt, vol, dims, spacing);
-  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
   RoiResult* hres = host_results(w, Bt);
   float ms[8] = {0};
   if ((rc = run_eager(w, Bt, dtype, st, hres, timing, ms))) return rc;
@@ -480,28 +656,49 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   return hres->status;
 }
 
-std::string layout_signature(const void* base, int dtype, const shape3d_roi* rois, int64_t n) {
+std::string layout_signature(const void* base, int dtype, const void* table, size_t table_bytes,
+                             const void* extra = nullptr, size_t extra_bytes = 0) {
   std::string sig((const char*)&base, sizeof(base));
   sig.append((const char*)&dtype, sizeof(dtype));
-  sig.append((const char*)rois, sizeof(shape3d_roi) * (size_t)n);
+  sig.append((const char*)table, table_bytes);
+  if (extra) sig.append((const char*)extra, extra_bytes);
   return sig;
 }
 
-// Records launch_head + launch_tail for the batch as a graph (buffers already sized).
-int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, GraphRec& rec) {
+// Records the pipeline of a batch as a graph (buffers already sized by the
+// eager run just made: a replay that finds more rows than that is caught by
+// the capacity check).  Host tables: the ROI table is uploaded before each
+// replay and the results are copied to rec.host_res.  Device tables
+// (dt set): the graph plans the ROI table itself and ends with the results
+// in out/status on the device.
+int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, GraphRec& rec,
+                  const DevTable* dt = nullptr, double* out = nullptr, int* status = nullptr) {
   rec.n_rois = Bt.n();
-  if (hipHostMalloc((void**)&rec.host_res, sizeof(RoiResult) * Bt.n(), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    rec.host_res = nullptr;
-    return fail(SHAPE3D_ENOMEM, "pinned host allocation failed");
+  if (!dt) {
+    if (hipHostMalloc((void**)&rec.host_res, sizeof(RoiResult) * Bt.n(), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      rec.host_res = nullptr;
+      return fail(SHAPE3D_ENOMEM, "pinned host allocation failed");
+    }
   }
-  // sized for the eager run just made: a replay that finds more rows than
-  // that is caught by the capacity check and re-run eagerly
   const Sizes S = sizes_for(Bt, w.last_rows0);
+  const Ptrs P = w.ptrs();
   hipGraph_t graph = nullptr;
   HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  int rc = launch_head(w, Bt, dtype, st);
-  if (!rc) rc = launch_tail(w, Bt, dtype, S, st, rec.host_res, nullptr);
+  int rc = SHAPE3D_OK;
+  if (dt) {
+    const hipError_t e = launch_plan_rois(dt->rois, Bt.n(), dtype, dt->max_dims, dt->base, dt->alloc_elems,
+                                          P.as<Roi>(W_ROIS), P.as<long long>(W_PLAN), st);
+    if (e != hipSuccess) rc = fail(SHAPE3D_EHIP, std::string("plan: ") + hipGetErrorString(e));
+  }
+  if (!rc) rc = launch_head(P, Bt, dtype, st);
+  if (!rc) rc = launch_tail(P, Bt, dtype, S, w.cu_count, st, nullptr, w.last_vmax);
+  if (!rc) {
+    const hipError_t e = dt ? launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, st)
+                            : hipMemcpyAsync(rec.host_res, P.p[W_RES], sizeof(RoiResult) * Bt.n(),
+                                             hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) rc = fail(SHAPE3D_EHIP, std::string("results: ") + hipGetErrorString(e));
+  }
   const hipError_t ec = hipStreamEndCapture(st, &graph);
   if (rc || ec != hipSuccess || !graph) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -517,8 +714,25 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
   return SHAPE3D_OK;
 }
 
-// The batched forward pass; on success *hres_out points at the per-ROI results
-// (pinned host memory owned by the workspace, valid until the next call).
+void erase_graph(Workspace& w, std::map<std::string, GraphRec>::iterator it) {
+  if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+  if (it->second.host_res) (void)hipHostFree(it->second.host_res);
+  w.graphs.erase(it);
+}
+
+// Makes room for a new graph under `sig` (drops the least recently used ones
+// and any old graph of the same signature).
+void graph_slot(Workspace& w, const std::string& sig) {
+  auto old = w.graphs.find(sig);
+  if (old != w.graphs.end()) erase_graph(w, old);
+  while (w.graphs.size() >= kMaxGraphs) {
+    auto lru = w.graphs.begin();
+    for (auto g = w.graphs.begin(); g != w.graphs.end(); ++g)
+      if (g->second.stamp < lru->second.stamp) lru = g;
+    erase_graph(w, lru);
+  }
+}
+
 // Validates a ROI table against the allocation holding base and builds the batch.
 int make_batch(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, Batch& Bt) {
   if (!base || !rois || n_rois < 1) return fail(SHAPE3D_EINVAL, "null argument or empty batch");
@@ -541,6 +755,8 @@ int make_batch(const void* base, int dtype, const shape3d_roi* rois, int64_t n_r
   return SHAPE3D_OK;
 }
 
+// The batched forward pass; on success *hres_out points at the per-ROI results
+// (pinned host memory owned by the workspace, valid until the next call).
 int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int flags, hipStream_t st,
                  const RoiResult** hres_out) {
   Batch Bt;
@@ -549,9 +765,10 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
   Workspace* wp = nullptr;
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
-  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
   const bool use_graph = (flags & SHAPE3D_BATCH_GRAPH) != 0;
-  const std::string sig = use_graph ? layout_signature(base, dtype, rois, n_rois) : std::string();
+  const std::string sig =
+      use_graph ? layout_signature(base, dtype, rois, sizeof(shape3d_roi) * (size_t)n_rois) : std::string();
   const RoiResult* hres = nullptr;
   bool done = false;
   if (use_graph) {
@@ -563,7 +780,7 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
       hipStream_t gs = w.graph_stream;
       HIPCK(hipEventRecord(w.ev[0], st));  // the caller's earlier work (e.g. writing the masks) first
       HIPCK(hipStreamWaitEvent(gs, w.ev[0], 0));
-      HIPCK(hipMemcpyAsync(w.rois.p, h + 4096, sizeof(Roi) * Bt.n(), hipMemcpyHostToDevice, gs));
+      HIPCK(hipMemcpyAsync(w.buf[W_ROIS].p, h + 4096, sizeof(Roi) * Bt.n(), hipMemcpyHostToDevice, gs));
       HIPCK(hipGraphLaunch(it->second.exec, gs));
       HIPCK(hipStreamSynchronize(gs));
       hres = it->second.host_res;
@@ -578,20 +795,7 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
     if ((rc = run_eager(w, Bt, dtype, st, eager, 0, nullptr))) return rc;
     hres = eager;
     if (use_graph) {
-      while (w.graphs.size() >= kMaxGraphs) {  // drop the least recently used graph
-        auto lru = w.graphs.begin();
-        for (auto g = w.graphs.begin(); g != w.graphs.end(); ++g)
-          if (g->second.stamp < lru->second.stamp) lru = g;
-        if (lru->second.exec) (void)hipGraphExecDestroy(lru->second.exec);
-        if (lru->second.host_res) (void)hipHostFree(lru->second.host_res);
-        w.graphs.erase(lru);
-      }
-      auto old = w.graphs.find(sig);
-      if (old != w.graphs.end()) {
-        if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
-        if (old->second.host_res) (void)hipHostFree(old->second.host_res);
-        w.graphs.erase(old);
-      }
+      graph_slot(w, sig);
       GraphRec rec;
       HIPCK(hipStreamSynchronize(st));
       rc = capture_graph(w, Bt, dtype, w.graph_stream, rec);
@@ -607,6 +811,108 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
   *hres_out = hres;
   for (int64_t r = 0; r < n_rois; ++r)
     if (hres[r].status < 0) return fail(hres[r].status, "an internal capacity was exceeded");
+  return SHAPE3D_OK;
+}
+
+// The batched forward pass on a ROI table in device memory, with results left
+// on the device (see shape3d_batched_dev).
+int batched_dev_impl(const void* base, int dtype, const shape3d_roi_ex* rois, int64_t n_rois,
+                     const int64_t max_dims[3], double* out, int* status, void* ws, size_t ws_bytes, int flags,
+                     hipStream_t st) {
+  if (!base || !rois || !max_dims || !out || !status || n_rois < 1)
+    return fail(SHAPE3D_EINVAL, "null argument or empty batch");
+  if (n_rois > SHAPE3D_MAX_ROIS) return fail(SHAPE3D_EINVAL, "too many ROIs");
+  if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "bad dtype");
+  Batch Bt;
+  int rc = batch_bounds(Bt, n_rois, max_dims);
+  if (rc) return rc;
+  const char* abase;
+  size_t asize;
+  if ((rc = device_range(base, &abase, &asize))) return rc;
+  if (!abase) return fail(SHAPE3D_EINVAL, "the allocation holding base is unknown to the runtime");
+  const size_t elem = dtype == SHAPE3D_U8 ? 1 : 4;
+  if ((uintptr_t)base % elem) return fail(SHAPE3D_EINVAL, "misaligned base");
+  if ((rc = check_device_span(rois, sizeof(shape3d_roi_ex) * (size_t)n_rois, "ROI table"))) return rc;
+  if ((rc = check_device_span(out, sizeof(double) * 6 * (size_t)n_rois, "out"))) return rc;
+  if ((rc = check_device_span(status, sizeof(int) * (size_t)n_rois, "status"))) return rc;
+  DevTable dt;
+  dt.rois = (const RoiDesc*)rois;
+  for (int k = 0; k < 3; ++k) dt.max_dims[k] = max_dims[k];
+  dt.base = base;
+  dt.alloc_elems = (long long)(((size_t)(abase + asize - (const char*)base)) / elem);
+  if (ws) {
+    int dev = 0, cu = 0;
+    HIPCK(hipGetDevice(&dev));
+    if ((rc = device_cu_count(dev, &cu))) return rc;
+    if ((rc = check_device_span(ws, ws_bytes, "workspace"))) return rc;
+    return run_fixed(Bt, dtype, nullptr, &dt, ws, ws_bytes, cu, out, status, st);
+  }
+  Workspace* wp = nullptr;
+  if ((rc = get_workspace(&wp))) return rc;
+  Workspace& w = *wp;
+  if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
+  const bool use_graph = (flags & SHAPE3D_BATCH_GRAPH) != 0;
+  std::string sig;
+  if (use_graph) {
+    const void* extra[3] = {rois, out, status};
+    sig = layout_signature(base, dtype, max_dims, sizeof(int64_t) * 3, extra, sizeof(extra));
+    sig.append((const char*)&n_rois, sizeof(n_rois));
+    auto it = w.graphs.find(sig);
+    if (it != w.graphs.end() && it->second.generation == w.generation && it->second.exec) {
+      hipStream_t gs = w.graph_stream;
+      HIPCK(hipEventRecord(w.ev[0], st));  // the caller's earlier work (the table, the masks) first
+      HIPCK(hipStreamWaitEvent(gs, w.ev[0], 0));
+      HIPCK(hipGraphLaunch(it->second.exec, gs));
+      HIPCK(hipEventRecord(w.ev[1], gs));  // and the caller's later work after the results
+      HIPCK(hipStreamWaitEvent(st, w.ev[1], 0));
+      it->second.stamp = ++w.stamp;
+      g_err.clear();
+      return SHAPE3D_OK;
+    }
+  }
+  if ((rc = run_eager(w, Bt, dtype, st, nullptr, 0, nullptr, &dt))) return rc;
+  HIPCK(launch_results_out(w.ptrs().as<const RoiResult>(W_RES), Bt.n(), out, status, st));
+  if (use_graph) {
+    graph_slot(w, sig);
+    GraphRec rec;
+    HIPCK(hipStreamSynchronize(st));
+    rc = capture_graph(w, Bt, dtype, w.graph_stream, rec, &dt, out, status);
+    if (rc) {
+      if (rec.exec) (void)hipGraphExecDestroy(rec.exec);
+      return rc;
+    }
+    rec.stamp = ++w.stamp;
+    w.graphs.emplace(sig, rec);
+  }
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
+// Bytes of a caller workspace for a batch shape and a bound on the vertex
+// count (or the worst case of its dims when max_vertices < 0).
+int workspace_size_impl(const Batch& Bt, int dtype, long long max_vertices, size_t* bytes) {
+  if (!bytes) return fail(SHAPE3D_EINVAL, "null output");
+  if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "bad dtype");
+  long long rows0;
+  if (max_vertices < 0) {
+    // every grid edge of every ROI's padded cube grid could cross
+    long long worst = 0;
+    if (Bt.planned) {
+      worst = (3ll * (Bt.max_d[0] + 1) * (Bt.max_d[1] + 1) * (Bt.max_d[2] + 1) + kSegAlign) * Bt.n();
+    } else {
+      for (const Roi& R : Bt.rois) worst += 3ll * (R.d[0] + 1) * (R.d[1] + 1) * (R.d[2] + 1) + kSegAlign;
+    }
+    rows0 = worst;
+  } else {
+    rows0 = max_vertices + (long long)kSegAlign * Bt.n();
+  }
+  rows0 = (rows0 + kSegAlign - 1) / kSegAlign * kSegAlign;
+  Layout L;
+  const int rc = ws_layout(Bt, dtype, g_tune, std::min(rows0, kMaxRows), L);
+  if (rc) return rc;
+  if (rows0 > kMaxRows) return ws_layout(Bt, dtype, g_tune, rows0, L);
+  *bytes = ws_total(L);
+  g_err.clear();
   return SHAPE3D_OK;
 }
 
@@ -742,6 +1048,7 @@ bool tuning_cache_find(const char* path, const std::string& key, Tuning& t, doub
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
     Tuning c;
+    c.prune = g_tune.prune;  // the cache holds the tiles; pruning stays as set
     double m;
     if (sscanf(line, "%127s %d %d %d %d %lf", k, &c.kernel, &c.itile, &c.jchunk, &c.blocks_per_cu, &m) == 6 &&
         key == k && valid_tuning(c)) {
@@ -763,7 +1070,7 @@ int autotune_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t 
   Workspace* wp = nullptr;
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
-  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
   const Tuning saved = g_tune;
   // reference run with the current tiles: vertex counts (for the cache key) and results
   std::vector<RoiResult> ref((size_t)n_rois);
@@ -784,7 +1091,7 @@ int autotune_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t 
   static const int kCand[5][2] = {{0, 2}, {0, 4}, {0, 8}, {1, 4}, {1, 8}};  // (kernel, itile)
   for (const auto& kc : kCand)
     for (int jc : {64, 128, 256, 512, 1024}) {
-      g_tune = Tuning{kc[1], jc, 0, kc[0]};
+      g_tune = Tuning{kc[1], jc, 0, kc[0], saved.prune};
       double t = 1e300;
       for (int k = 0; k < reps; ++k) {
         if ((rc = run_eager(w, Bt, dtype, st, hres, 1, ms))) {
@@ -860,15 +1167,15 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
   Workspace& w = *wp;
   Batch Bt;
   batch_add(Bt, vol, dims, spacing);
-  if ((rc = ensure_layout_bufs(w, Bt))) return rc;
+  if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
+  Ptrs P = w.ptrs();
+  if ((rc = upload_rois(w, P, Bt, dtype, nullptr, st))) return rc;
+  if ((rc = launch_head(P, Bt, dtype, st))) return rc;
   char* h = (char*)w.host;
-  memcpy(h + 4096, Bt.rois.data(), sizeof(Roi));
-  HIPCK(hipMemcpyAsync(w.rois.p, h + 4096, sizeof(Roi), hipMemcpyHostToDevice, st));
-  if ((rc = launch_head(w, Bt, dtype, st))) return rc;
   long long* th = (long long*)h;
   RoiMeta* mh = (RoiMeta*)(h + 1024);
-  HIPCK(hipMemcpyAsync(th, w.totals.p, sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(mh, w.meta.p, sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(th, P.p[W_TOTALS], sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
+  HIPCK(hipMemcpyAsync(mh, P.p[W_META], sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
   HIPCK(hipStreamSynchronize(st));
   const long long V = mh->V;
   *n_out = V;
@@ -876,17 +1183,18 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
   if (V == 0) return SHAPE3D_EMPTY;
   Sizes S;
   if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
-  HIPCK(launch_check_capacity(1, S.rows0, (RoiMeta*)w.meta.p, (long long*)w.totals.p,
-                              (unsigned int*)w.counters.p + 2, st));
-  HIPCK(launch_mesh_emit(dtype, (const Roi*)w.rois.p, 1, Bt.nbricks, Bt.max_G, (const BrickPart*)w.part.p,
-                         (const long long*)w.brick_voff.p, (const RoiMeta*)w.meta.p,
-                         (const unsigned int*)w.counters.p + 2, (unsigned long long*)w.key.p,
-                         dtype == SHAPE3D_F32 ? (double*)w.tsoft.p : nullptr, (float*)w.pos.p,
-                         g_tune.kernel == 1 ? (uint4*)w.posh.p : nullptr, (int*)w.orig.p,
-                         (int*)w.blkseg.p, (Seg*)w.segs.p, st));
-  HIPCK(launch_export_vertices((const unsigned long long*)w.key.p,
-                               dtype == SHAPE3D_F32 ? (const double*)w.tsoft.p : nullptr, (const RoiMeta*)w.meta.p,
-                               (const Roi*)w.rois.p, (long long*)ids, pos, V, st));
+  P = w.ptrs();
+  HIPCK(launch_check_capacity(1, S.rows0, P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
+                              P.as<unsigned int>(W_COUNTERS) + 2, st));
+  HIPCK(launch_mesh_emit(dtype, P.as<const Roi>(W_ROIS), 1, Bt.nbricks, Bt.max_G, P.as<const BrickPart>(W_PART),
+                         P.as<const long long>(W_BRICK_VOFF), P.as<const RoiMeta>(W_META),
+                         P.as<const unsigned int>(W_COUNTERS) + 2, P.as<unsigned long long>(W_KEY),
+                         dtype == SHAPE3D_F32 ? P.as<double>(W_TSOFT) : nullptr, P.as<float>(W_POS),
+                         g_tune.kernel == 1 ? P.as<uint4>(W_POSH) : nullptr, P.as<int>(W_ORIG), P.as<int>(W_BLKSEG),
+                         P.as<Seg>(W_SEGS), st));
+  HIPCK(launch_export_vertices(P.as<const unsigned long long>(W_KEY),
+                               dtype == SHAPE3D_F32 ? P.as<const double>(W_TSOFT) : nullptr,
+                               P.as<const RoiMeta>(W_META), P.as<const Roi>(W_ROIS), (long long*)ids, pos, V, st));
   HIPCK(hipStreamSynchronize(st));
   g_err.clear();
   return SHAPE3D_OK;
@@ -957,6 +1265,57 @@ int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, in
   return soft_backward_impl(base, rois, n_rois, saved, grad_out, grad_base, (hipStream_t)stream);
 }
 
+int shape3d_workspace_size(const int64_t dims[3], int dtype, size_t* bytes) {
+  return shape3d_workspace_size_v(dims, dtype, -1, bytes);
+}
+
+int shape3d_workspace_size_v(const int64_t dims[3], int dtype, int64_t max_vertices, size_t* bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!dims) return fail(SHAPE3D_EINVAL, "null argument");
+  const double one[3] = {1.0, 1.0, 1.0};
+  int rc = check_dims_spacing(dims, one);
+  if (rc) return rc;
+  Batch Bt;
+  batch_add(Bt, nullptr, dims, one);
+  return workspace_size_impl(Bt, dtype, max_vertices < 0 ? -1 : max_vertices, bytes);
+}
+
+int shape3d_batched_workspace_size(int64_t n_rois, const int64_t max_dims[3], int dtype, int64_t max_vertices,
+                                   size_t* bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!max_dims || n_rois < 1 || n_rois > SHAPE3D_MAX_ROIS) return fail(SHAPE3D_EINVAL, "bad batch shape");
+  Batch Bt;
+  int rc = batch_bounds(Bt, n_rois, max_dims);
+  if (rc) return rc;
+  return workspace_size_impl(Bt, dtype, max_vertices < 0 ? -1 : max_vertices, bytes);
+}
+
+int shape3d_ex_async(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double* out,
+                     int* status, void* workspace, size_t ws_bytes, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = check_args(vol, dtype, dims, spacing);
+  if (rc) return rc;
+  if ((rc = check_device_span(out, sizeof(double) * 6, "out"))) return rc;
+  if ((rc = check_device_span(status, sizeof(int), "status"))) return rc;
+  if ((rc = check_device_span(workspace, ws_bytes, "workspace"))) return rc;
+  int dev = 0, cu = 0;
+  HIPCK(hipGetDevice(&dev));
+  if ((rc = device_cu_count(dev, &cu))) return rc;
+  Batch Bt;
+  batch_add(Bt, vol, dims, spacing);
+  rc = run_fixed(Bt, dtype, &Bt.rois[0], nullptr, workspace, ws_bytes, cu, out, status, (hipStream_t)stream);
+  if (!rc) g_err.clear();
+  return rc;
+}
+
+int shape3d_batched_dev(const void* base, int dtype, const shape3d_roi_ex* rois, int64_t n_rois,
+                        const int64_t max_dims[3], double* out, int* status, void* workspace, size_t ws_bytes,
+                        int flags, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return batched_dev_impl(base, dtype, rois, n_rois, max_dims, out, status, workspace, ws_bytes, flags,
+                          (hipStream_t)stream);
+}
+
 const char* shape3d_last_error(void) { return g_err.c_str(); }
 
 int shape3d_release(void) {
@@ -969,7 +1328,9 @@ int shape3d_release(void) {
     (void)hipDeviceSynchronize();
     drop_graphs(*w);
     if (w->graph_stream) (void)hipStreamDestroy(w->graph_stream);
-    for (Buf* b : w->all())
+    for (Buf& b : w->buf)
+      if (b.p) (void)hipFree(b.p);
+    for (Buf* b : w->soft_bufs())
       if (b->p) (void)hipFree(b->p);
     if (w->host) (void)hipHostFree(w->host);
     for (int i = 0; i < 8; ++i)
@@ -988,13 +1349,14 @@ int shape3d_get_tuning(shape3d_tuning* t) {
   t->jchunk_blocks = g_tune.jchunk;
   t->blocks_per_cu = g_tune.blocks_per_cu;
   t->kernel = g_tune.kernel;
+  t->prune = g_tune.prune;
   return SHAPE3D_OK;
 }
 
 int shape3d_set_tuning(const shape3d_tuning* t) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!t) return fail(SHAPE3D_EINVAL, "null argument");
-  const Tuning c{t->itile_blocks, t->jchunk_blocks, t->blocks_per_cu, t->kernel};
+  const Tuning c{t->itile_blocks, t->jchunk_blocks, t->blocks_per_cu, t->kernel, t->prune};
   if (!valid_tuning(c)) return fail(SHAPE3D_EINVAL, "unsupported tile sizes");
   g_tune = c;
   for (auto& kv : g_ws) drop_graphs(*kv.second);  // recorded graphs hold the old tiles
@@ -1014,6 +1376,7 @@ int shape3d_autotune(const void* base, int dtype, const shape3d_roi* rois, int64
   best->jchunk_blocks = b.jchunk;
   best->blocks_per_cu = b.blocks_per_cu;
   best->kernel = b.kernel;
+  best->prune = b.prune;
   *best_ms = ms;
   g_err.clear();
   return SHAPE3D_OK;

@@ -34,26 +34,36 @@ __device__ inline uint32_t nz4(uint32_t w) {
   return (t * 0x00204081u) >> 28;
 }
 
+// Bits 0..3 set for the bytes of w equal to the ROI's label (label != 0), or
+// for its nonzero bytes (label == 0).
+__device__ inline uint32_t in4(uint32_t w, uint32_t label4) {
+  return label4 ? (~nz4(w ^ label4) & 0xfu) : nz4(w);
+}
+
 template <int DT>
-__device__ inline uint32_t row_bits(const void* vol, const int* d, int z, int y, int l) {
+__device__ inline uint32_t row_bits(const Roi& R, int z, int y, int l) {
   uint32_t bits = 0u;
-  if (z < 0 || z >= d[0] || y < 0 || y >= d[1]) return 0u;
+  if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1]) return 0u;
   const int x0 = 32 * l;
-  int n = d[2] - x0;
+  int n = R.d[2] - x0;
   if (n <= 0) return 0u;
+  const size_t off = (size_t)z * (size_t)R.stride0 + (size_t)y * (size_t)R.stride1 + (size_t)x0;
   if (DT == 0) {
-    const uint8_t* p = (const uint8_t*)vol + ((size_t)z * d[1] + y) * (size_t)d[2] + x0;
+    const uint8_t* p = (const uint8_t*)R.vol + off;
+    const uint32_t label4 = (uint32_t)(R.label & 0xff) * 0x01010101u;
     if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
       const uint4 a = *(const uint4*)p;
       const uint4 b = *(const uint4*)(p + 16);
-      bits = nz4(a.x) | (nz4(a.y) << 4) | (nz4(a.z) << 8) | (nz4(a.w) << 12) | (nz4(b.x) << 16) |
-             (nz4(b.y) << 20) | (nz4(b.z) << 24) | (nz4(b.w) << 28);
+      bits = in4(a.x, label4) | (in4(a.y, label4) << 4) | (in4(a.z, label4) << 8) | (in4(a.w, label4) << 12) |
+             (in4(b.x, label4) << 16) | (in4(b.y, label4) << 20) | (in4(b.z, label4) << 24) |
+             (in4(b.w, label4) << 28);
     } else {
       if (n > 32) n = 32;
-      for (int i = 0; i < n; ++i) bits |= (uint32_t)(p[i] != 0) << i;
+      const int lab = R.label;
+      for (int i = 0; i < n; ++i) bits |= (uint32_t)(lab ? p[i] == lab : p[i] != 0) << i;
     }
   } else {
-    const float* p = (const float*)vol + ((size_t)z * d[1] + y) * (size_t)d[2] + x0;
+    const float* p = (const float*)R.vol + off;
     if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -81,9 +91,9 @@ __device__ inline double sel8d(const double* v, int k) {
   return (k & 4) ? ce : ab;
 }
 
-__device__ inline double soft_value(const float* vol, const int* d, int z, int y, int x) {
-  if (z < 0 || y < 0 || x < 0 || z >= d[0] || y >= d[1] || x >= d[2]) return 0.0;
-  return (double)vol[((size_t)z * d[1] + y) * (size_t)d[2] + x];
+__device__ inline double soft_value(const Roi& R, int z, int y, int x) {
+  if (z < 0 || y < 0 || x < 0 || z >= R.d[0] || y >= R.d[1] || x >= R.d[2]) return 0.0;
+  return (double)((const float*)R.vol)[(size_t)z * (size_t)R.stride0 + (size_t)y * (size_t)R.stride1 + (size_t)x];
 }
 
 // A brick is kBrickThreads consecutive row-groups (rg = cube row * G + group)
@@ -120,7 +130,7 @@ __device__ inline const void* fast_row_ptr(const Roi& R, const Tile& T, int p, i
   const int ry = (int)fdiv((unsigned int)vrg, R.mG, R.shG);
   const int z = T.pz0 - 1 + p, y = ry - 1, x0 = 32 * (vrg - ry * R.G);
   if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1] || x0 + 32 > R.d[2]) return nullptr;
-  const size_t off = ((size_t)z * R.d[1] + y) * (size_t)R.d[2] + x0;
+  const size_t off = (size_t)z * (size_t)R.stride0 + (size_t)y * (size_t)R.stride1 + (size_t)x0;
   const char* ptr = (const char*)R.vol + off * (DT == 0 ? 1 : 4);
   return (((uintptr_t)ptr) & 15u) == 0 ? ptr : nullptr;
 }
@@ -129,7 +139,7 @@ template <int DT>
 __device__ inline uint32_t slow_row_bits(const Roi& R, const Tile& T, int p, int vrg) {
   if (vrg < 0) return 0u;
   const int ry = (int)fdiv((unsigned int)vrg, R.mG, R.shG);
-  return row_bits<DT>(R.vol, R.d, T.pz0 - 1 + p, ry - 1, vrg - ry * R.G);
+  return row_bits<DT>(R, T.pz0 - 1 + p, ry - 1, vrg - ry * R.G);
 }
 
 // Stages the tile's voxel row-groups in LDS.  Each thread issues the loads of
@@ -139,6 +149,7 @@ template <int DT>
 __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) {
   constexpr int kLoadBatch = 5;
   const int n = T.np * T.nw;
+  const uint32_t label4 = (uint32_t)(R.label & 0xff) * 0x01010101u;
   for (int base = threadIdx.x; base < n; base += kBrickThreads * kLoadBatch) {
     if (DT == 0) {
       uint4 a[kLoadBatch], b[kLoadBatch];
@@ -163,8 +174,9 @@ __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) 
         if (idx >= n) continue;
         uint32_t bits;
         if (fast[u]) {
-          bits = nz4(a[u].x) | (nz4(a[u].y) << 4) | (nz4(a[u].z) << 8) | (nz4(a[u].w) << 12) |
-                 (nz4(b[u].x) << 16) | (nz4(b[u].y) << 20) | (nz4(b[u].z) << 24) | (nz4(b[u].w) << 28);
+          bits = in4(a[u].x, label4) | (in4(a[u].y, label4) << 4) | (in4(a[u].z, label4) << 8) |
+                 (in4(a[u].w, label4) << 12) | (in4(b[u].x, label4) << 16) | (in4(b[u].y, label4) << 20) |
+                 (in4(b[u].z, label4) << 24) | (in4(b[u].w, label4) << 28);
         } else {
           const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
           bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
@@ -312,6 +324,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   const long long brick = xcd_remap(blockIdx.x, nbricks);
   const int roi = find_roi(rois, n_rois, brick);
   const Roi R = rois[roi];
+  // a grid sized by a bound (ROI table planned on the device) ends past the last brick
+  if (brick >= R.brick_end) return;
   const int tid = threadIdx.x;
   {
     const int c = tid;
@@ -428,10 +442,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
                  2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)y * (((tm >> 8) & 0xff) - 128) +
                         (long long)x * (((tm >> 16) & 0xff) - 128));
       } else {
-        const float* pv = (const float*)R.vol;
         double pc[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) pc[c] = soft_value(pv, R.d, z + ((c >> 2) & 1), y + ((c >> 1) & 1), x + (c & 1));
+        for (int c = 0; c < 8; ++c) pc[c] = soft_value(R, z + ((c >> 2) & 1), y + ((c >> 1) & 1), x + (c & 1));
         const int ntri = tk & 0xff;
         for (int tr = 0; tr < ntri; ++tr) {
           double P[3][3];
@@ -507,7 +520,7 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
   __shared__ int s_b[6][1024];
   const int r = blockIdx.x, tid = threadIdx.x;
   const Roi R = rois[r];
-  const long long b0 = R.brick_begin, b1 = (r + 1 < n_rois) ? rois[r + 1].brick_begin : nbricks;
+  const long long b0 = R.brick_begin, b1 = R.brick_end;
   const long long n = b1 - b0;
   const long long chunk = (n + 1023) / 1024;
   const long long lo = b0 + min(n, chunk * tid), hi = b0 + min(n, chunk * (tid + 1));
@@ -589,44 +602,56 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
   }
 }
 
-// Layout-0 row offsets of the ROIs (exclusive scan of V_pad), one workgroup.
+// Layout-0 row offsets of the ROIs (exclusive scan of V_pad) and the first
+// 1024-row column of each ROI's 3D segment in the pruning pass (exclusive
+// scan of ceil(V_pad / 1024) over ROIs with two or more vertices), one
+// workgroup.  totals: [0] layout-0 rows, [1] largest V, [7] pruning columns.
 __global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restrict__ meta,
                                                    long long* __restrict__ totals) {
-  __shared__ long long s[2][1024];
+  __shared__ long long s[2][2][1024];
   const int tid = threadIdx.x;
   const int chunk = (n_rois + 1023) / 1024;
   const int lo = min(n_rois, chunk * tid), hi = min(n_rois, chunk * (tid + 1));
-  long long sum = 0, vmax = 0;
+  long long sum = 0, nsb = 0, vmax = 0;
   for (int r = lo; r < hi; ++r) {
-    sum += meta[r].V_pad;
-    vmax = max(vmax, meta[r].V);
+    const RoiMeta& M = meta[r];
+    sum += M.V_pad;
+    nsb += M.V >= 2 ? (M.V_pad + kPruneSB * 32 - 1) / (kPruneSB * 32) : 0;
+    vmax = max(vmax, M.V);
   }
-  s[0][tid] = sum;
+  s[0][0][tid] = sum;
+  s[1][0][tid] = nsb;
   __syncthreads();
   int src = 0;
   for (int d = 1; d < 1024; d <<= 1) {
-    long long v = s[src][tid];
-    if (tid >= d) v += s[src][tid - d];
-    s[1 - src][tid] = v;
+    for (int q = 0; q < 2; ++q) {
+      long long v = s[q][src][tid];
+      if (tid >= d) v += s[q][src][tid - d];
+      s[q][1 - src][tid] = v;
+    }
     __syncthreads();
     src = 1 - src;
   }
-  long long off = s[src][tid] - sum;
+  long long off = s[0][src][tid] - sum, soff = s[1][src][tid] - nsb;
   for (int r = lo; r < hi; ++r) {
-    meta[r].row_off = off;
-    off += meta[r].V_pad;
+    RoiMeta& M = meta[r];
+    M.row_off = off;
+    M.sb_off = soff;
+    off += M.V_pad;
+    soff += M.V >= 2 ? (M.V_pad + kPruneSB * 32 - 1) / (kPruneSB * 32) : 0;
   }
-  const long long rows0 = s[src][1023];
+  const long long rows0 = s[0][src][1023], nsb_total = s[1][src][1023];
   __syncthreads();
-  s[0][tid] = vmax;
+  s[0][0][tid] = vmax;
   __syncthreads();
   for (int w = 512; w >= 1; w >>= 1) {
-    if (tid < w) s[0][tid] = max(s[0][tid], s[0][tid + w]);
+    if (tid < w) s[0][0][tid] = max(s[0][0][tid], s[0][0][tid + w]);
     __syncthreads();
   }
   if (tid == 0) {
     totals[0] = rows0;
-    totals[1] = s[0][0];
+    totals[1] = s[0][0][0];
+    totals[7] = nsb_total;
   }
 }
 
@@ -645,6 +670,7 @@ __global__ void k_check_capacity(int n_rois, long long rows0_cap, RoiMeta* __res
     *overflow = 1u;
     totals[0] = 0;
     totals[1] = 0;
+    totals[7] = 0;
   }
 }
 
@@ -666,9 +692,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
   __shared__ uint32_t s_items[kMeshItems];
   __shared__ uint32_t s_ly[kBrickThreads];  // (y + 1) | l << 20 of each thread's row-group
   const long long brick = xcd_remap(blockIdx.x, nbricks);
-  if (*overflow != 0u || part[brick].nv == 0) return;
   const int roi = find_roi(rois, n_rois, brick);
   const Roi R = rois[roi];
+  if (brick >= R.brick_end || *overflow != 0u || part[brick].nv == 0) return;
   const RoiMeta M = meta[roi];
   const int tid = threadIdx.x;
   const Tile T = tile_of(R, brick - R.brick_begin);
@@ -743,9 +769,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restri
       const long long row = base + c0 + i;
       double tv = 0.5;
       if (DT == 1) {
-        const float* pv = (const float*)R.vol;
-        const double pa = soft_value(pv, R.d, u0, u1, u2);
-        const double pb = soft_value(pv, R.d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
+        const double pa = soft_value(R, u0, u1, u2);
+        const double pb = soft_value(R, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
         tv = (0.5 - pa) / (pb - pa);
         tsoft[row] = tv;
       }
@@ -792,6 +817,92 @@ __global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, floa
     copy_row_operands(pos, posh, r0, row);
     orig[row] = (int)r0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// ROI tables built on the device.
+
+// A caller's table of ROI descriptors (device memory) -> the mesh pass's ROI
+// table, in one workgroup: each descriptor is validated (dims within the
+// call's bounds, spacing finite and positive, strides that keep rows and
+// planes apart, every voxel inside the allocation [base, base + alloc_elems)
+// elements, a label only for uint8), its geometry filled as on the host, and
+// brick and bucket offsets placed by exclusive scans.  A rejected descriptor
+// becomes a 1x1x1 ROI with no bricks and status -1 (invalid argument).
+// plan[0] receives the brick count, plan[1] the bucket count.
+__global__ __launch_bounds__(1024) void k_plan_rois(const RoiDesc* __restrict__ in, int n, int dtype, long long md0,
+                                                    long long md1, long long md2, const char* __restrict__ base,
+                                                    long long alloc_elems, Roi* __restrict__ out,
+                                                    long long* __restrict__ plan) {
+  __shared__ long long s[2][2][1024];
+  const int tid = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = min(n, chunk * tid), hi = min(n, chunk * (tid + 1));
+  const size_t elem = dtype == 0 ? 1 : 4;
+  long long nbr = 0, nbu = 0;
+  for (int r = lo; r < hi; ++r) {
+    const RoiDesc D = in[r];
+    bool ok = true;
+    const long long dmax[3] = {md0, md1, md2};
+    for (int k = 0; k < 3; ++k) {
+      ok = ok && D.dims[k] >= 1 && D.dims[k] <= dmax[k];
+      ok = ok && D.spacing[k] > 0.0 && isfinite(D.spacing[k]);
+    }
+    ok = ok && D.offset >= 0 && D.strides[0] >= 0 && D.strides[1] >= 0 && D.label >= 0 && D.label <= 255 &&
+         (dtype == 0 || D.label == 0);
+    long long st1 = 0, st0 = 0;
+    if (ok) {
+      st1 = D.strides[1] > 0 ? D.strides[1] : D.dims[2];
+      st0 = D.strides[0] > 0 ? D.strides[0] : D.dims[1] * D.dims[2];
+      ok = st1 >= D.dims[2] && st0 >= (D.dims[1] - 1) * st1 + D.dims[2];
+      // the last voxel (products below 2^63: dims <= 2^20, strides checked against the allocation first)
+      ok = ok && st0 < alloc_elems && st1 < alloc_elems &&
+           D.offset + (D.dims[0] - 1) * st0 + (D.dims[1] - 1) * st1 + D.dims[2] <= alloc_elems;
+    }
+    Roi R;
+    if (ok) {
+      nbr += roi_fill(R, base + (size_t)D.offset * elem, D.dims, D.spacing, st0, st1, D.label);
+    } else {
+      const long long one[3] = {1, 1, 1};
+      const double unit[3] = {1.0, 1.0, 1.0};
+      (void)roi_fill(R, base, one, unit, 0, 0, 0);
+      R.status = -1;
+    }
+    nbu += roi_buckets(R.d);
+    out[r] = R;
+  }
+  s[0][0][tid] = nbr;
+  s[1][0][tid] = nbu;
+  __syncthreads();
+  int src = 0;
+  for (int d = 1; d < 1024; d <<= 1) {
+    for (int q = 0; q < 2; ++q) {
+      long long v = s[q][src][tid];
+      if (tid >= d) v += s[q][src][tid - d];
+      s[q][1 - src][tid] = v;
+    }
+    __syncthreads();
+    src = 1 - src;
+  }
+  long long boff = s[0][src][tid] - nbr, uoff = s[1][src][tid] - nbu;
+  for (int r = lo; r < hi; ++r) {
+    Roi& R = out[r];
+    const long long nb = R.status == 0 ? (long long)R.nzc * R.bpz : 0;
+    R.brick_begin = boff;
+    R.brick_end = boff + nb;
+    roi_set_buckets(R, uoff);
+    boff += nb;
+    uoff += roi_buckets(R.d);
+  }
+  if (tid == 1023) {
+    plan[0] = s[0][src][1023];
+    plan[1] = s[1][src][1023];
+  }
+}
+
+// One ROI descriptor passed by value (no host staging buffer).
+__global__ void k_set_roi(Roi R, Roi* __restrict__ out) {
+  if (threadIdx.x == 0) *out = R;
 }
 
 // ---------------------------------------------------------------------------
@@ -845,4 +956,17 @@ hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nb
   return hipGetLastError();
 }
 
+hipError_t launch_plan_rois(const RoiDesc* in, int n, int dtype, const long long max_dims[3], const void* base,
+                            long long alloc_elems, Roi* out, long long* plan, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan_rois, dim3(1), dim3(1024), 0, st, in, n, dtype, max_dims[0], max_dims[1], max_dims[2],
+                     (const char*)base, alloc_elems, out, plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_roi(const Roi& R, Roi* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_roi, dim3(1), dim3(64), 0, st, R, out);
+  return hipGetLastError();
+}
+
 }  // namespace s3d
+

@@ -33,7 +33,7 @@ namespace s3d {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-enum { T_ROWS0 = 0, T_VMAX = 1, T_ROWS2D = 2, T_NSEG2D = 3, T_NCOL = 4, T_NITEM = 5, T_NEXACT = 6 };
+enum { T_ROWS0 = 0, T_VMAX = 1, T_ROWS2D = 2, T_NSEG2D = 3, T_NCOL = 4, T_NITEM = 5, T_NEXACT = 6, T_NSB = 7 };
 
 // ---------------------------------------------------------------------------
 // Plane buckets.
@@ -206,10 +206,14 @@ __global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long l
 
 // Columns (chunks of jchunk row blocks) per segment; also clears the item
 // counts of all col_cap columns (k_col_fill sets those of the real ones).
+// With prune set, the 3D segments are left out (the pruned item list covers
+// them) unless that list overflowed (counters[4]).
 __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __restrict__ totals,
                            const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk, int small_rows,
-                           long long* __restrict__ nitem, long long col_cap) {
+                           long long* __restrict__ nitem, long long col_cap, int prune,
+                           const unsigned int* __restrict__ counters) {
   const long long nseg = n_rois + totals[T_NSEG2D];
+  const bool skip3d = prune && counters[4] == 0u;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < col_cap;
        c += (long long)gridDim.x * blockDim.x)
     nitem[c] = 0;
@@ -217,6 +221,7 @@ __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __res
        s += (long long)gridDim.x * blockDim.x) {
     long long rows = s < nseg ? segs[s].n_rows : 0;
     if (s >= n_rois && rows <= small_rows) rows = 0;  // a small bucket: k_pair_small_h
+    if (s < n_rois && skip3d) rows = 0;               // a 3D segment: k_pair_list_h
     ncol[s] = (rows + (long long)jchunk * kBlk - 1) / ((long long)jchunk * kBlk);
   }
 }
@@ -581,6 +586,24 @@ __global__ __launch_bounds__(256) void k_pair_maxima_h(const uint4* __restrict__
   }
 }
 
+// The pruned 3D work items (prune.hip): the same tiles as the work-list
+// kernel, read from an explicit list of (segment, row tile, column blocks).
+// The list is empty when it overflowed (the 3D segments are then in the
+// work list).
+template <int IT>
+__global__ __launch_bounds__(256) void k_pair_list_h(const uint4* __restrict__ posh, const PItem* __restrict__ items,
+                                                     const unsigned int* __restrict__ counters, long long cap,
+                                                     unsigned int* __restrict__ work_ctr,
+                                                     float* __restrict__ rowmax) {
+  const int lane = threadIdx.x & 63;
+  const long long n = counters[4] != 0u ? 0 : min((long long)counters[3], cap);
+  WorkQueue q(work_ctr, n);
+  for (long long item; (item = q.next(lane)) >= 0;) {
+    const PItem P = items[item];
+    pair_item_h<IT>(posh, rowmax, P.rb, P.nb, P.i0, P.j0, P.j1, P.e, lane);
+  }
+}
+
 // Plane buckets of at most kSmallBlocks 32-row blocks (most of them), which the
 // work list leaves out: a wave takes kSmallPerWave consecutive bucket segments
 // and runs their row tiles directly, without the work counter and the column
@@ -847,8 +870,21 @@ __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const G
     }
     Q.status = M.V == 0 ? 1 : 0;
     if ((long long)*ncand > cand_cap || ncand[1] != 0u) Q.status = -4;
+    if (rois[r].status != 0) Q.status = rois[r].status;
     Q.pad_ = 0;
     res[r] = Q;
+  }
+}
+
+// Per-ROI results to the caller's device arrays: out[6 r .. 6 r + 5] (left
+// untouched for a negative status) and status[r].
+__global__ void k_results_out(const RoiResult* __restrict__ res, int n_rois, double* __restrict__ out,
+                              int* __restrict__ status) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
+    const int st = res[r].status;
+    if (st >= 0)
+      for (int f = 0; f < 6; ++f) out[6 * r + f] = res[r].out[f];
+    if (status) status[r] = st;
   }
 }
 
@@ -905,7 +941,7 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
                      B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(std::max(B.seg_cap, B.col_cap))), dim3(256), 0, st, B.n_rois,
                      B.seg_cap, B.totals, B.segs, B.ncol, B.tune.jchunk, small_buckets(B) ? kSmallBlocks * 32 : 0,
-                     B.nitem, B.col_cap);
+                     B.nitem, B.col_cap, B.prune ? 1 : 0, B.counters);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.meta, B.ncol, B.colbase, B.cols, B.nitem, B.tune.itile, B.tune.jchunk);
@@ -935,6 +971,13 @@ hipError_t launch_pair_maxima_h(const PairBufs& B, hipStream_t st) {
   if (per_cu < 1) per_cu = 1;
   if (B.tune.blocks_per_cu > 0 && B.tune.blocks_per_cu < per_cu) per_cu = B.tune.blocks_per_cu;
   const unsigned grid = (unsigned)(B.cu_count * per_cu);
+  if (B.prune) {
+    int per = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pair_list_h<IT>, 256, 0))) return e;
+    if (per < 1) per = 1;
+    hipLaunchKernelGGL(k_pair_list_h<IT>, dim3((unsigned)(B.cu_count * per)), dim3(256), 0, st, B.posh, B.pitems,
+                       B.counters, B.pitem_cap, B.counters + kListCounters, B.rowmax);
+  }
   hipLaunchKernelGGL(k_pair_maxima_h<IT>, dim3(grid), dim3(256), 0, st, B.posh, B.cols, B.itembase, B.totals,
                      B.counters + kWorkStride, B.rowmax, B.tune.jchunk);
   // small plane buckets (bucket count bounded by n_buckets on the host), in
@@ -1002,6 +1045,11 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(B.n_rois)), dim3(256), 0, st, B.n_rois, B.meta, B.gres,
                      B.counters + 1, B.key, B.rois, B.pairs2d, B.res, B.cand_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_results_out(const RoiResult* res, int n_rois, double* out, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_results_out, dim3(grid_for(n_rois, 1024)), dim3(256), 0, st, res, n_rois, out, status);
   return hipGetLastError();
 }
 

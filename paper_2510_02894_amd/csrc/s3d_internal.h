@@ -13,6 +13,8 @@
 //   * a "segment" is a contiguous run of rows whose pairs are examined; a
 //     "group" is one feature of one ROI (roi * 4 + {0: 3D, 1..3: plane axis}).
 #pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace s3d {
@@ -29,7 +31,13 @@ constexpr int kSmallPerWave = 4;    // bucket segments per wave of the small-buc
 constexpr long long kSmallMinBuckets = 1 << 16;  // calls with fewer plane buckets keep them all in the work list
 constexpr int kWorkParts = 8;       // work ranges (one per XCD) of the pair pass, each with its own counter
 constexpr int kWorkStride = 32;     // words between two work counters (one 128-byte line each)
-constexpr int kCounterWords = kWorkStride * (1 + kWorkParts);  // size of the counter block
+// Counter block: word 1 candidates, 2 capacity overflow, 3 pruned work items,
+// 4 pruned-list overflow; the work counters of the pair pass from word
+// kWorkStride, then those of the pruned 3D pass.
+constexpr int kCounterWords = kWorkStride * (1 + 2 * kWorkParts);
+constexpr int kListCounters = kWorkStride * (1 + kWorkParts);  // first work counter of the pruned 3D pass
+constexpr int kPruneSB = 32;          // 32-row blocks per column of the 3D pruning pass (1024 rows)
+constexpr int kPruneMinV = 16384;     // below this largest vertex count a call runs the 3D pairs unpruned
 
 // Key of a vertex: edge (u, u + e_a): bits 0..19 u2+1, 20..39 u1+1, 40..59 u0+1, 60..61 a.
 __host__ __device__ inline uint64_t pack_key(int u0, int u1, int u2, int a) {
@@ -38,11 +46,14 @@ __host__ __device__ inline uint64_t pack_key(int u0, int u1, int u2, int a) {
 }
 
 struct Roi {
-  const void* vol;        // this ROI's volume (uint8 or float32)
+  const void* vol;        // this ROI's first voxel (uint8 or float32)
   int d[3];
   int G;                  // row-groups per cube row: ceil((d2 + 1) / 32)
   double s[3];
   long long brick_begin;  // first brick
+  long long brick_end;    // one past the last brick
+  long long stride0;      // elements between consecutive voxels along axis 0
+  long long stride1;      // ... along axis 1 (axis 2 is contiguous)
   int nrg;                // (d1 + 1) * G
   int nzc;                // z-chunks: ceil((d0 + 1) / kTZ)
   int bpz;                // bricks per z-chunk: ceil(nrg / kBrickThreads)
@@ -50,9 +61,66 @@ struct Roi {
   unsigned int mG;
   unsigned int mNW;       // the same for the tile width kBrickThreads + 1 + G
   int shNW;
+  int label;              // uint8 only: 0 = a voxel is inside iff nonzero; else iff it equals label
+  int status;             // 0, or a negative status for a rejected table entry (then it has no bricks)
   int pad_;
   long long bucket_base[3];  // first global plane bucket of each axis
 };
+
+// A ROI as a caller describes it (the layout of shape3d_roi_ex in shape3d.h).
+struct RoiDesc {
+  long long offset;      // element offset of the ROI's first voxel from the base pointer
+  long long dims[3];
+  double spacing[3];
+  long long strides[2];  // elements between voxels along axes 0 and 1; 0 = dense
+  int label;
+  int reserved;
+};
+
+// Magic numbers of the kernels' 32-bit division by D (numerators < 2^31):
+// floor(n / D) = (n * m) >> sh, sh = 31 + ceil(log2 D), m = floor(2^sh / D) + 1.
+__host__ __device__ inline void magic_div(unsigned int D, unsigned int& m, int& sh) {
+  int k = 0;
+  while ((1ull << k) < D) ++k;
+  sh = 31 + k;
+  m = (unsigned int)((1ull << sh) / D + 1);
+}
+
+// Fills the mesh-pass geometry of a ROI (everything but its brick and bucket
+// offsets) and returns its brick count.  Strides of 0 mean a dense layout.
+__host__ __device__ inline long long roi_fill(Roi& R, const void* vol, const long long dims[3],
+                                              const double spacing[3], long long stride0, long long stride1,
+                                              int label) {
+  R.vol = vol;
+  for (int k = 0; k < 3; ++k) {
+    R.d[k] = (int)dims[k];
+    R.s[k] = spacing[k];
+  }
+  R.stride1 = stride1 > 0 ? stride1 : (long long)R.d[2];
+  R.stride0 = stride0 > 0 ? stride0 : (long long)R.d[1] * R.d[2];
+  R.label = label;
+  R.status = 0;
+  R.pad_ = 0;
+  R.G = (R.d[2] + 1 + 31) / 32;
+  R.nrg = (R.d[1] + 1) * R.G;
+  R.nzc = (R.d[0] + 1 + kTZ - 1) / kTZ;
+  R.bpz = (R.nrg + kBrickThreads - 1) / kBrickThreads;
+  magic_div((unsigned int)R.G, R.mG, R.shG);
+  magic_div((unsigned int)(kBrickThreads + 1 + R.G), R.mNW, R.shNW);
+  return (long long)R.nzc * R.bpz;
+}
+
+// Plane buckets of a ROI: 2 d_k + 1 per axis.
+__host__ __device__ inline long long roi_buckets(const int d[3]) {
+  return 2ll * d[0] + 2ll * d[1] + 2ll * d[2] + 3;
+}
+
+// Sets the bucket offsets of a ROI whose buckets start at b0.
+__host__ __device__ inline void roi_set_buckets(Roi& R, long long b0) {
+  R.bucket_base[0] = b0;
+  R.bucket_base[1] = b0 + 2ll * R.d[0] + 1;
+  R.bucket_base[2] = R.bucket_base[1] + 2ll * R.d[1] + 1;
+}
 
 struct BrickPart {
   int nv, nt;
@@ -71,7 +139,7 @@ struct RoiMeta {
   double center[3];   // subtracted from positions before rounding to FP32
   double R2;          // bound on |centred FP32 position|^2
   int bb[6];
-  int pad_[2];
+  long long sb_off;   // first 1024-row column of the ROI's 3D segment in the pruning pass
 };
 
 struct Seg {
@@ -86,6 +154,29 @@ struct Col {
   int group;            // the segment's group (roi * 4 + feature)
   int jc;               // column chunk index within the segment
   int e;                // scale exponent of the ROI's split-f16 operands
+};
+
+// 3D pruning: per 32-row block of layout 0, the bounding box of its centred
+// FP32 positions and seven packed (value, row) maxima; per ROI, the seven
+// seeds and the partners found by two farthest-point sweeps; the pruned work
+// items of the 3D pair pass.
+struct BlkRec {
+  float box[6];                 // lo x, y, z, hi x, y, z
+  int pad_[2];
+  unsigned long long key[7];    // (ordered float bits << 32) | (0xffffffff - row)
+};
+
+struct RoiSeed {
+  unsigned long long key[3][7];  // 0: seed rows, 1: farthest from each seed, 2: farthest from those
+};
+
+struct PItem {
+  int rb;      // first 32-row block of the segment
+  int nb;      // its 32-row blocks
+  int i0;      // first row block of the tile
+  int j0, j1;  // column blocks [j0, j1)
+  int e;       // scale exponent of the split-f16 operands
+  int pad_[2];
 };
 
 // Per-group results of the diameter passes.

@@ -34,6 +34,12 @@ hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nb
                             const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
                             uint4* posh, int* orig, int* blkseg, Seg* segs, hipStream_t st);
 
+// ROI tables on the device: a caller's descriptors planned and validated in
+// one workgroup (plan[0] = bricks, plan[1] = buckets), or one ROI by value.
+hipError_t launch_plan_rois(const RoiDesc* in, int n, int dtype, const long long max_dims[3], const void* base,
+                            long long alloc_elems, Roi* out, long long* plan, hipStream_t st);
+hipError_t launch_set_roi(const Roi& R, Roi* out, hipStream_t st);
+
 // scan.hip: exclusive scan of n int64 (n known on the host); total -> *total.
 // With n_dev set, only the first min(n, *n_dev) elements are scanned (a count
 // known on the device only): later tiles cost an early exit and their outputs
@@ -50,6 +56,7 @@ struct Tuning {
   int jchunk;         // 16-row column blocks per work item: 64, 128, 256 or 512
   int blocks_per_cu;  // persistent workgroups per CU (0: as many as fit)
   int kernel;         // 0: FP32 16x16x4 MFMA; 1: split-f16 32x32x16 MFMA
+  int prune;          // 1: skip 3D pair tiles that cannot reach the diameter (kernel 1); 0: all pairs
 };
 
 // Buffers of the diameter passes.
@@ -95,6 +102,13 @@ struct PairBufs {
   RoiResult* res;          // [n_rois]
   long long* pairs2d;      // [n_rois] in-plane pairs n*(n-1)/2 summed over buckets
   int cu_count;
+  // 3D pruning (prune.hip), kernel 1 only: when `prune` is set the 3D
+  // segments run from the pruned item list instead of the work list
+  bool prune;
+  BlkRec* blkrec;          // [rows0 / 32] per 32-row block of layout 0
+  RoiSeed* rseed;          // [n_rois]
+  PItem* pitems;           // [pitem_cap]
+  long long pitem_cap;
 };
 
 // soft.hip: adjoint of the soft-mask forward pass, for a table of ROIs.
@@ -146,10 +160,14 @@ hipError_t launch_soft_backward(const SoftBwdBufs& B, hipStream_t st);
 // pairs.hip
 uint4* split_rows(const PairBufs& B);  // split-f16 operand rows (kernel 1), else null
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st);       // plane buckets, segments, work list
+// prune.hip: boxes, lower bound and the pruned 3D work items (B.prune set)
+hipError_t launch_prune(const PairBufs& B, hipStream_t st);
 hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass over the work list
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset group results, pair-pass counters, row maxima
 hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st);      // per-ROI results
+// res -> out[6 * n_rois] (not written for a negative status) and status[n_rois] (may be null), on the device
+hipError_t launch_results_out(const RoiResult* res, int n_rois, double* out, int* status, hipStream_t st);
 hipError_t launch_export_vertices(const unsigned long long* key, const double* tsoft, const RoiMeta* meta,
                                   const Roi* rois, long long* ids, double* pos, long long V, hipStream_t st);
 

@@ -67,7 +67,7 @@ class SoftSaved(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("itile_blocks", ctypes.c_int32), ("jchunk_blocks", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("prune", ctypes.c_int32)]
 
     def as_tuple(self):
         return (self.itile_blocks, self.jchunk_blocks, self.blocks_per_cu, self.kernel)
@@ -75,6 +75,11 @@ class Tuning(ctypes.Structure):
 
 class Roi(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_int64), ("dims", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3)]
+
+
+class RoiEx(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("dims", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
+                ("strides", ctypes.c_int64 * 2), ("label", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 BATCH_GRAPH = 1
@@ -131,6 +136,20 @@ def load():
                                          ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(Tuning),
                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
         lib.shape3d_autotune.restype = ctypes.c_int
+        sizep = ctypes.POINTER(ctypes.c_size_t)
+        lib.shape3d_workspace_size.argtypes = [i64p, ctypes.c_int, sizep]
+        lib.shape3d_workspace_size.restype = ctypes.c_int
+        lib.shape3d_workspace_size_v.argtypes = [i64p, ctypes.c_int, ctypes.c_int64, sizep]
+        lib.shape3d_workspace_size_v.restype = ctypes.c_int
+        lib.shape3d_batched_workspace_size.argtypes = [ctypes.c_int64, i64p, ctypes.c_int, ctypes.c_int64, sizep]
+        lib.shape3d_batched_workspace_size.restype = ctypes.c_int
+        lib.shape3d_ex_async.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.shape3d_ex_async.restype = ctypes.c_int
+        lib.shape3d_batched_dev.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, i64p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_int, ctypes.c_void_p]
+        lib.shape3d_batched_dev.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -249,6 +268,107 @@ def roi_table(offsets, shapes, spacings):
     return tab
 
 
+def _check_extents(table, numel: int):
+    """Every ROI of a dense table lies inside a base tensor of numel elements."""
+    for r in range(len(table)):
+        d = [int(table[r].dims[k]) for k in range(3)]
+        if min(d) < 1 or int(table[r].offset) < 0 or int(table[r].offset) + d[0] * d[1] * d[2] > numel:
+            raise ValueError("ROI %d (offset %d, dims %s) does not fit in a base of %d elements"
+                             % (r, int(table[r].offset), d, numel))
+
+
+def workspace_size(shape, dtype: int = U8, max_vertices: int = -1) -> int:
+    """Bytes of a caller workspace for one ROI of this shape (see shape3d_workspace_size_v)."""
+    n = ctypes.c_size_t(0)
+    dims = (ctypes.c_int64 * 3)(*[int(x) for x in shape])
+    _check(load().shape3d_workspace_size_v(dims, int(dtype), int(max_vertices), ctypes.byref(n)))
+    return int(n.value)
+
+
+def batched_workspace_size(n_rois: int, max_dims, dtype: int = U8, max_vertices: int = -1) -> int:
+    n = ctypes.c_size_t(0)
+    md = (ctypes.c_int64 * 3)(*[int(x) for x in max_dims])
+    _check(load().shape3d_batched_workspace_size(int(n_rois), md, int(dtype), int(max_vertices), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _workspace(ws):
+    import torch
+
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+        raise TypeError("workspace must be a contiguous GPU tensor")
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
+def features_async(vol, spacing, workspace):
+    """shape3d_ex_async: (out float64 tensor [6], status int32 tensor [1]), both
+    on the GPU and written on the current stream (nothing is read back)."""
+    import torch
+
+    lib = load()
+    dt = _volume(vol)
+    dims, sp = _dims_spacing(vol.shape, spacing)
+    out = torch.zeros(6, dtype=torch.float64, device=vol.device)
+    status = torch.full((1,), -100, dtype=torch.int32, device=vol.device)
+    wp, wb = _workspace(workspace)
+    _check(lib.shape3d_ex_async(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(status.data_ptr()), wp, wb, _stream()))
+    return out, status
+
+
+def roi_table_ex(offsets, shapes, spacings, strides=None, labels=None):
+    """ctypes array of shape3d_roi_ex descriptors (strides 0 = dense, label 0 = nonzero)."""
+    n = len(offsets)
+    tab = (RoiEx * n)()
+    for r in range(n):
+        tab[r].offset = int(offsets[r])
+        for k in range(3):
+            tab[r].dims[k] = int(shapes[r][k])
+            tab[r].spacing[k] = float(spacings[r][k])
+        if strides is not None:
+            tab[r].strides[0] = int(strides[r][0])
+            tab[r].strides[1] = int(strides[r][1])
+        tab[r].label = int(labels[r]) if labels is not None else 0
+    return tab
+
+
+def table_to_device(table, device="cuda"):
+    """The bytes of a ctypes ROI table as a GPU uint8 tensor."""
+    import torch
+
+    raw = np.frombuffer(bytes(table), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+def batched_dev(base, table_dev, n_rois: int, max_dims, workspace=None, graph: bool = False, out=None, status=None):
+    """shape3d_batched_dev: features of n_rois ROIs described by the
+    shape3d_roi_ex table held in the GPU tensor ``table_dev``; returns
+    (out float64 tensor [n, 6], status int32 tensor [n]) on the GPU."""
+    import torch
+
+    lib = load()
+    if not isinstance(base, torch.Tensor) or not base.is_cuda or not base.is_contiguous():
+        raise TypeError("base must be a contiguous GPU tensor")
+    dt = U8 if base.dtype == torch.uint8 else (F32 if base.dtype == torch.float32 else None)
+    if dt is None:
+        raise TypeError("base dtype must be uint8 or float32")
+    if table_dev.numel() * table_dev.element_size() < n_rois * ctypes.sizeof(RoiEx):
+        raise ValueError("table_dev holds fewer than n_rois descriptors")
+    if out is None:
+        out = torch.zeros((n_rois, 6), dtype=torch.float64, device=base.device)
+    if status is None:
+        status = torch.full((n_rois,), -100, dtype=torch.int32, device=base.device)
+    md = (ctypes.c_int64 * 3)(*[int(x) for x in max_dims])
+    wp, wb = (None, 0) if workspace is None else _workspace(workspace)
+    _check(lib.shape3d_batched_dev(ctypes.c_void_p(base.data_ptr()), dt, ctypes.c_void_p(table_dev.data_ptr()),
+                                   int(n_rois), md, ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(status.data_ptr()), wp, wb, BATCH_GRAPH if graph else 0,
+                                   _stream()))
+    return out, status
+
+
 def batched(base, table, graph: bool = False):
     """Features of a batch of ROIs packed in the 1-D GPU tensor ``base``
     (uint8 or float32); ``table`` from ``roi_table``.  Returns
@@ -265,6 +385,7 @@ def batched(base, table, graph: bool = False):
     else:
         raise TypeError("base dtype must be uint8 or float32")
     n = len(table)
+    _check_extents(table, base.numel())
     out = np.zeros((n, 6), dtype=np.float64)
     status = np.zeros(n, dtype=np.int32)
     rc = lib.shape3d_batched(ctypes.c_void_p(base.data_ptr()), dt, table, n,
@@ -418,8 +539,27 @@ def get_tuning():
     return t.as_tuple()
 
 
-def set_tuning(itile_blocks: int, jchunk_blocks: int, blocks_per_cu: int = 0, kernel: int = 0):
-    t = Tuning(int(itile_blocks), int(jchunk_blocks), int(blocks_per_cu), int(kernel))
+def get_prune() -> int:
+    """3D pruning mode: 0 never, 1 for large ROIs (default), 2 always."""
+    t = Tuning()
+    _check(load().shape3d_get_tuning(ctypes.byref(t)))
+    return int(t.prune)
+
+
+def set_tuning(itile_blocks: int, jchunk_blocks: int, blocks_per_cu: int = 0, kernel: int = 0, prune=None):
+    """Replace the pair-pass setting; ``prune`` None keeps the current choice."""
+    t = Tuning()
+    _check(load().shape3d_get_tuning(ctypes.byref(t)))
+    t = Tuning(int(itile_blocks), int(jchunk_blocks), int(blocks_per_cu), int(kernel),
+               int(t.prune if prune is None else prune))
+    _check(load().shape3d_set_tuning(ctypes.byref(t)))
+
+
+def set_prune(mode: int):
+    """3D pruning mode: 0 never, 1 for large ROIs (default), 2 always."""
+    t = Tuning()
+    _check(load().shape3d_get_tuning(ctypes.byref(t)))
+    t.prune = int(mode)
     _check(load().shape3d_set_tuning(ctypes.byref(t)))
 
 

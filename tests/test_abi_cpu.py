@@ -20,7 +20,9 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for n in ("shape3d", "shape3d_ex", "shape3d_vertices", "shape3d_batched", "shape3d_soft_forward",
               "shape3d_soft_backward", "shape3d_batched_soft_forward", "shape3d_batched_soft_backward",
-              "shape3d_get_tuning", "shape3d_set_tuning", "shape3d_autotune", "shape3d_last_error", "shape3d_release", "shape3d_version"):
+              "shape3d_get_tuning", "shape3d_set_tuning", "shape3d_autotune", "shape3d_last_error", "shape3d_release",
+              "shape3d_version", "shape3d_workspace_size", "shape3d_workspace_size_v", "shape3d_batched_workspace_size",
+              "shape3d_ex_async", "shape3d_batched_dev"):
         assert n in names
 
 
@@ -74,7 +76,7 @@ def test_binding_struct_layouts_match_header(tmp_path):
     from paper_2510_02894_amd import shape3d as S
 
     structs = {"shape3d_stats": S.Stats, "shape3d_soft_saved": S.SoftSaved, "shape3d_roi": S.Roi,
-               "shape3d_tuning": S.Tuning}
+               "shape3d_tuning": S.Tuning, "shape3d_roi_ex": S.RoiEx}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "shape3d.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -112,3 +114,49 @@ def test_tuning_setting_is_validated_without_a_device():
                 S.set_tuning(it, jc, 2, kernel)
                 assert S.get_tuning() == (it, jc, 2, kernel)
     S.set_tuning(*before)
+
+
+def test_workspace_size_arithmetic_without_a_device():
+    """Workspace sizes are host arithmetic: positive, growing with the vertex
+    bound, the worst case above any bound, and refused where the mesh could
+    exceed the kernels' 32-bit row indices."""
+    from paper_2510_02894_amd import shape3d as S
+
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("library not built")
+    sizes = [S.workspace_size((64, 64, 64), S.U8, v) for v in (0, 100, 10_000, 100_000)]
+    assert all(b > 0 for b in sizes) and sizes == sorted(sizes) and sizes[0] < sizes[-1]
+    worst = S.workspace_size((64, 64, 64), S.U8)
+    assert worst >= S.workspace_size((64, 64, 64), S.U8, 3 * 65 ** 3)
+    assert S.workspace_size((64, 64, 64), S.F32, 10_000) > S.workspace_size((64, 64, 64), S.U8, 10_000)
+    # 1e6 x 1e3 x 32767: every edge crossing gives ~1e14 rows, far past 2^31
+    with pytest.raises(S.Shape3DError) as e:
+        S.workspace_size((1_000_000, 1000, 32767))
+    assert e.value.status == S.ECAPACITY
+    # a vertex bound near 2^31 is refused as well
+    with pytest.raises(S.Shape3DError) as e:
+        S.workspace_size((64, 64, 64), S.U8, 1 << 31)
+    assert e.value.status == S.ECAPACITY
+    for bad in [(0, 4, 4), (4, 4, 40000)]:
+        with pytest.raises(S.Shape3DError) as e:
+            S.workspace_size(bad)
+        assert e.value.status == S.EINVAL
+    with pytest.raises(S.Shape3DError) as e:
+        S.workspace_size((4, 4, 4), 7)
+    assert e.value.status == S.EINVAL
+    b1 = S.batched_workspace_size(1, (64, 64, 64), S.U8, 10_000)
+    b4 = S.batched_workspace_size(4, (64, 64, 64), S.U8, 10_000)
+    assert b4 > b1 > 0
+
+
+def test_batch_extent_check_in_binding():
+    """The binding refuses a dense ROI table that reaches past the base tensor
+    (pure host arithmetic, checked before any library call)."""
+    from paper_2510_02894_amd import shape3d as S
+
+    t = S.roi_table([0, 64], [(4, 4, 4), (4, 4, 4)], [(1, 1, 1)] * 2)
+    S._check_extents(t, 128)
+    with pytest.raises(ValueError):
+        S._check_extents(t, 127)
+    with pytest.raises(ValueError):
+        S._check_extents(S.roi_table([-1], [(1, 1, 1)], [(1, 1, 1)]), 10)

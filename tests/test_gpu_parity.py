@@ -179,16 +179,28 @@ def test_errors(S):
     with pytest.raises(S.Shape3DError) as e:
         S.features(t, (1.0, float("nan"), 1.0))
     assert e.value.status == S.EINVAL
-    # dims larger than the allocation are refused before any kernel runs
+    # dims larger than the allocation are refused before any kernel runs: a
+    # raw 100-byte hipMalloc (the runtime that libshape3d.so uses) is exactly
+    # the allocation the range check sees
     import ctypes
 
     lib = S.load()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
     dims = (ctypes.c_int64 * 3)(64, 64, 64)
     sp = (ctypes.c_double * 3)(1, 1, 1)
-    out = (ctypes.c_double * 6)()
-    small = torch.zeros(100, dtype=torch.uint8, device="cuda")
-    big = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")  # own allocation block
-    del big
-    rc = lib.shape3d(ctypes.c_void_p(small.data_ptr()), dims, sp, out)
-    # refused, or (when the caching allocator's block is larger) read inside that block
-    assert rc in (S.EINVAL, S.OK, S.EMPTY)
+    out = (ctypes.c_double * 6)(*([7.0] * 6))
+    p = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(p), 100) == 0
+    try:
+        assert lib.shape3d(p, dims, sp, out) == S.EINVAL
+        assert list(out) == [7.0] * 6  # outputs untouched on failure
+        small = (ctypes.c_int64 * 3)(4, 5, 5)  # exactly 100 voxels: accepted
+        assert lib.shape3d(p, small, sp, out) in (S.OK, S.EMPTY)
+    finally:
+        hip.hipFree(p)
+    # the binding checks a batch table against the tensor before the call
+    t = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        S.batched(t, S.roi_table([0], [(5, 5, 5)], [(1, 1, 1)]))
