@@ -355,6 +355,31 @@ int shape3d_batched_dev(const void* base, int dtype, const shape3d_roi_ex* rois,
                         const int64_t max_dims[3], double* out, int* status, void* workspace, size_t ws_bytes,
                         int flags, void* stream);
 
+/*
+ * shape3d_noalloc -- shape3d_ex_async for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the call allocates nothing and needs no workspace argument.
+ * Its scratch memory is a static device array of
+ * SHAPE3D_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on
+ * holds until the process ends; the first call on a device (which must not be
+ * under graph capture) looks its address up.
+ *   vol, dtype, dims, spacing: as shape3d_ex; at most
+ *           SHAPE3D_NOALLOC_MAX_VOXELS voxels, else SHAPE3D_ECAPACITY is
+ *           returned and nothing is enqueued.
+ *   out:    DEVICE double[6]; status: DEVICE int[1] (SHAPE3D_OK,
+ *           SHAPE3D_EMPTY, or SHAPE3D_ECAPACITY when the mesh needs more
+ *           vertex rows than the scratch holds, about 250,000 vertices; out
+ *           is then untouched).
+ * Asynchronous on `stream`.  Every call on one GPU uses that GPU's one
+ * scratch array: calls that overlap on a device (other streams, other host
+ * threads' streams) race and give undefined results; calls on one stream
+ * are ordered and each starts from cleared counters.
+ */
+#define SHAPE3D_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define SHAPE3D_NOALLOC_MAX_VOXELS (1ll << 24)
+int shape3d_noalloc(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double* out,
+                    int* status, void* stream);
+
 /* Message describing the last failure of the calling thread ("" if none). */
 const char* shape3d_last_error(void);
 

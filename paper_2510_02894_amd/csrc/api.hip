@@ -112,6 +112,14 @@ struct Workspace {
 
 std::map<int, Workspace*> g_ws;
 
+// Scratch memory of shape3d_noalloc: one static device array per GPU (each
+// device holds its own copy until the process ends).  Host code never uses the
+// array's name as a device address: g_scratch[dev] holds the address that
+// hipGetSymbolAddress returned for it on device dev.
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[SHAPE3D_NOALLOC_SCRATCH_BYTES];
+void* g_scratch[kMaxScratchDevices] = {};
+
 // Tile sizes of the pair pass for every device (results do not depend on them).
 Tuning g_tune = {8, 1024, 0, 1, 1};
 
@@ -1304,6 +1312,44 @@ int shape3d_ex_async(const void* vol, int dtype, const int64_t dims[3], const do
   Batch Bt;
   batch_add(Bt, vol, dims, spacing);
   rc = run_fixed(Bt, dtype, &Bt.rois[0], nullptr, workspace, ws_bytes, cu, out, status, (hipStream_t)stream);
+  if (!rc) g_err.clear();
+  return rc;
+}
+
+int shape3d_noalloc(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double* out,
+                    int* status, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = check_args(vol, dtype, dims, spacing);
+  if (rc) return rc;
+  if ((double)dims[0] * (double)dims[1] * (double)dims[2] > (double)SHAPE3D_NOALLOC_MAX_VOXELS)
+    return fail(SHAPE3D_ECAPACITY, "input larger than the no-allocation limit of SHAPE3D_NOALLOC_MAX_VOXELS voxels");
+  if ((rc = check_device_span(out, sizeof(double) * 6, "out"))) return rc;
+  if ((rc = check_device_span(status, sizeof(int), "status"))) return rc;
+  int dev = 0, cu = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(SHAPE3D_ENODEV, "device index beyond the scratch table");
+  if (!g_scratch[dev]) {  // once per device, with that device current
+    void* ptr = nullptr;
+    HIPCK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SHAPE3D_EHIP, "no device address for the scratch array");
+    g_scratch[dev] = ptr;
+  }
+  if ((rc = device_cu_count(dev, &cu))) return rc;
+  // a one-ROI batch built without heap allocation (no ROI vector)
+  Batch Bt;
+  Roi R;
+  memset(&R, 0, sizeof(R));
+  const long long d[3] = {dims[0], dims[1], dims[2]};
+  const long long nb = roi_fill(R, vol, d, spacing, 0, 0, 0);
+  R.brick_begin = 0;
+  R.brick_end = nb;
+  roi_set_buckets(R, 0);
+  Bt.n_rois = 1;
+  Bt.nbricks = nb;
+  Bt.n_buckets = roi_buckets(R.d);
+  Bt.max_G = R.G;
+  rc = run_fixed(Bt, dtype, &R, nullptr, g_scratch[dev], (size_t)SHAPE3D_NOALLOC_SCRATCH_BYTES, cu, out, status,
+                 (hipStream_t)stream);
   if (!rc) g_err.clear();
   return rc;
 }

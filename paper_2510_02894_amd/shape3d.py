@@ -150,6 +150,9 @@ def load():
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_int, ctypes.c_void_p]
         lib.shape3d_batched_dev.restype = ctypes.c_int
+        lib.shape3d_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        lib.shape3d_noalloc.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -315,6 +318,23 @@ def features_async(vol, spacing, workspace):
     wp, wb = _workspace(workspace)
     _check(lib.shape3d_ex_async(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, ctypes.c_void_p(out.data_ptr()),
                                 ctypes.c_void_p(status.data_ptr()), wp, wb, _stream()))
+    return out, status
+
+
+def features_noalloc(vol, spacing, out=None, status=None):
+    """shape3d_noalloc (no allocation inside the library; the caller provides
+    out float64 [6] and status int32 [1] on the GPU, created here if None)."""
+    import torch
+
+    lib = load()
+    dt = _volume(vol)
+    dims, sp = _dims_spacing(vol.shape, spacing)
+    if out is None:
+        out = torch.zeros(6, dtype=torch.float64, device=vol.device)
+    if status is None:
+        status = torch.full((1,), -100, dtype=torch.int32, device=vol.device)
+    _check(lib.shape3d_noalloc(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(status.data_ptr()), _stream()))
     return out, status
 
 
