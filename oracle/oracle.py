@@ -33,6 +33,24 @@ FEATURES = (
     "Maximum2DDiameterRow",
 )
 
+# The whole Shape class: the six features above, then the members that are
+# closed forms of the mesh volume V, surface area A and inside-voxel count,
+# and the principal-axis members (eigenvalues of the inside voxels'
+# coordinate covariance).
+SHAPE_FEATURES = FEATURES + (
+    "VoxelVolume",
+    "SurfaceVolumeRatio",
+    "Sphericity",
+    "Compactness1",
+    "Compactness2",
+    "SphericalDisproportion",
+    "MajorAxisLength",
+    "MinorAxisLength",
+    "LeastAxisLength",
+    "Elongation",
+    "Flatness",
+)
+
 _lib = None
 
 
@@ -65,6 +83,7 @@ def _load():
         lib.oracle_shape3d.argtypes = [vp, ctypes.c_int, i64p, f64p, f64p, i64p, i64p, f64p]
         lib.oracle_soft_grad.argtypes = [vp, i64p, f64p, f64p, i64p, f64p]
         lib.oracle_cube_triangles.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        lib.oracle_moments.argtypes = [vp, ctypes.c_int, i64p, f64p, i64p, f64p, f64p]
         lib.oracle_max_pair_rows.argtypes = [f64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, f64p,
                                              ctypes.POINTER(ctypes.c_int)]
         _lib = lib
@@ -180,6 +199,62 @@ def shape3d(vol: np.ndarray, spacing=(1.0, 1.0, 1.0)):
     _check(st, "shape3d")
     return dict(features=out, status=int(st), V=int(counts[0]), T=int(counts[1]),
                 pair_ids=pairs.reshape(4, 2), signed_volume=float(sv[0]))
+
+
+def moments(vol: np.ndarray, spacing=(1.0, 1.0, 1.0)):
+    """(inside-voxel count, mean float64[3], population covariance float64[3,3]) of
+    the physical coordinates index * spacing of the voxels inside the region."""
+    lib = _load()
+    vol, dt = _vol(vol)
+    dims, sp = _dims_sp(vol, spacing)
+    n = np.zeros(1, dtype=np.int64)
+    mean = np.zeros(3)
+    cov = np.zeros(9)
+    _check(lib.oracle_moments(vol.ctypes.data, dt, _p(dims, ctypes.c_int64), _p(sp, ctypes.c_double),
+                              _p(n, ctypes.c_int64), _p(mean, ctypes.c_double), _p(cov, ctypes.c_double)),
+           "moments")
+    return int(n[0]), mean, cov.reshape(3, 3)
+
+
+def shape_class(vol: np.ndarray, spacing=(1.0, 1.0, 1.0), base=None):
+    """dict(features=float64[17] in the order of SHAPE_FEATURES, eigenvalues
+    float64[3] ascending, n_inside, status, and the entries of ``shape3d``).
+
+    The extra members are the Shape class's definitions, written out:
+      VoxelVolume            = n_inside * s0 * s1 * s2
+      SurfaceVolumeRatio     = A / V
+      Sphericity             = (36 pi V^2)^(1/3) / A
+      Compactness1           = V / (sqrt(pi) * A^(3/2))
+      Compactness2           = 36 pi V^2 / A^3
+      SphericalDisproportion = A / (36 pi V^2)^(1/3)
+      Major/Minor/LeastAxisLength = 4 sqrt(lambda), lambda the largest, middle
+                               and smallest eigenvalue of the covariance
+      Elongation             = sqrt(lambda_minor / lambda_major)
+      Flatness               = sqrt(lambda_least / lambda_major)
+    with V = MeshVolume and A = SurfaceArea.  Readings: an empty region gives
+    all zeros; negative eigenvalues (rounding of a singular covariance) count
+    as 0; Elongation and Flatness are 0 when lambda_major is 0 (one voxel).
+    ``base`` may pass an earlier ``shape3d`` result for the same input."""
+    r = dict(base) if base is not None else shape3d(vol, spacing)
+    n, _, cov = moments(vol, spacing)
+    f = np.zeros(len(SHAPE_FEATURES))
+    f[:6] = r["features"]
+    lam = np.zeros(3)
+    if r["status"] == OK:
+        sp = np.asarray(spacing, dtype=np.float64).reshape(3)
+        V, A = f[0], f[1]
+        lam = np.maximum(np.linalg.eigvalsh(cov), 0.0)  # ascending
+        f[6] = n * sp[0] * sp[1] * sp[2]
+        f[7] = A / V
+        f[8] = (36.0 * np.pi * V * V) ** (1.0 / 3.0) / A
+        f[9] = V / (np.sqrt(np.pi) * A ** 1.5)
+        f[10] = 36.0 * np.pi * V * V / A ** 3
+        f[11] = A / (36.0 * np.pi * V * V) ** (1.0 / 3.0)
+        f[12], f[13], f[14] = 4.0 * np.sqrt(lam[2]), 4.0 * np.sqrt(lam[1]), 4.0 * np.sqrt(lam[0])
+        f[15] = np.sqrt(lam[1] / lam[2]) if lam[2] > 0 else 0.0
+        f[16] = np.sqrt(lam[0] / lam[2]) if lam[2] > 0 else 0.0
+    r.update(features=f, eigenvalues=lam, n_inside=n, covariance=cov)
+    return r
 
 
 def soft_grad(p: np.ndarray, spacing, grad_out, pair_ids: Optional[np.ndarray] = None) -> np.ndarray:

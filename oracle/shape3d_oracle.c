@@ -803,4 +803,44 @@ int oracle_soft_grad(const float* p, const int64_t dims[3], const double spacing
   return OR_OK;
 }
 
-int oracle_version(void) { return 1; }
+/* ------------------------------------------------------------------------ */
+/* Second moments of the inside voxels.                                      */
+
+/* The principal-axis members of the Shape class (the class the paper
+   accelerates, Sec. 2 "PyRadiomics-cuda design") are built from the
+   population covariance of the physical coordinates (index * spacing) of the
+   voxels inside the region.  Definition, in FP64 and two plain passes over
+   the grid: the count and the mean, then the sum of the centred outer
+   products divided by the count.  n_inside = 0 leaves mean and cov zero. */
+int oracle_moments(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                   int64_t* n_inside, double mean[3], double cov[9]) {
+  grid_t g;
+  int st = grid_init(&g, vol, dtype, dims, spacing);
+  if (st) return st;
+  int64_t n = 0;
+  double sum[3] = {0.0, 0.0, 0.0};
+  int64_t u[3];
+  for (u[0] = 0; u[0] < g.d[0]; ++u[0])
+    for (u[1] = 0; u[1] < g.d[1]; ++u[1])
+      for (u[2] = 0; u[2] < g.d[2]; ++u[2])
+        if (inside_at(&g, u)) {
+          ++n;
+          for (int k = 0; k < 3; ++k) sum[k] += (double)u[k] * g.s[k];
+        }
+  *n_inside = n;
+  for (int k = 0; k < 3; ++k) mean[k] = n ? sum[k] / (double)n : 0.0;
+  double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (u[0] = 0; u[0] < g.d[0]; ++u[0])
+    for (u[1] = 0; u[1] < g.d[1]; ++u[1])
+      for (u[2] = 0; u[2] < g.d[2]; ++u[2])
+        if (inside_at(&g, u)) {
+          double x[3];
+          for (int k = 0; k < 3; ++k) x[k] = (double)u[k] * g.s[k] - mean[k];
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) c[3 * k + l] += x[k] * x[l];
+        }
+  for (int k = 0; k < 9; ++k) cov[k] = n ? c[k] / (double)n : 0.0;
+  return n ? OR_OK : OR_EMPTY;
+}
+
+int oracle_version(void) { return 2; }
