@@ -9,10 +9,15 @@ ellipsoids (semi-axes 20-90 voxels) thresholded after Gaussian smoothing
 (sigma 3).  Four copies of the mask rotate through the steps so the 256 MB
 Infinity Cache does not hold the input.
 
-Prints one JSON line: value = 3D diameter vertex pairs V(V-1)/2 per second of
-whole-call time; roofline of the dominant kernel (the MFMA pair pass) from HIP
-events recorded around it inside the library; cpu_baseline = the FP64 oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line.  value = 3D diameter vertex pairs V(V-1)/2 per second of
+whole-call time with every vertex pair evaluated (the pair pass's pruning
+switched off); roofline of that call's dominant kernel (the MFMA pair pass),
+8 algorithmic flops per vertex pair (3D and in-plane) over its time from HIP
+events recorded around it inside the library, against the peak of the
+contraction's dtype.  `effective` gives the library's default call on the same
+masks, which skips pair tiles that cannot hold the diameter (identical
+results), as V(V-1)/2 per second.  cpu_baseline = the FP64 oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
 """
@@ -33,11 +38,16 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PEAK_F16_MFMA_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
-# Gram form on the matrix cores, flops per vertex pair as executed:
-# kernel 0: v_mfma_f32_16x16x4_f32, 2048 flops per 256 pairs;
-# kernel 1: v_mfma_f32_32x32x16_f16 (split f16), 32768 flops per 1024 pairs.
-FLOPS_PER_PAIR = {0: 8, 1: 32}
+# Algorithmic work of the all-pairs maximum: 8 flops per vertex pair (3 sub,
+# 3 mul, 2 add of |x_i - x_j|^2; the compare is not counted).
+ALG_FLOPS_PER_PAIR = 8
+# Flops the matrix cores execute per vertex pair (the Gram form, padding and
+# split terms included): kernel 0 v_mfma_f32_16x16x4_f32, 2048 flops per 256
+# pairs; kernel 1 v_mfma_f32_32x32x16_f16 (split f16), 32768 per 1024 pairs.
+MFMA_FLOPS_PER_PAIR = {0: 8, 1: 32}
 PEAK_TFLOPS = {0: PEAK_FP32_MFMA_TFLOPS, 1: PEAK_F16_MFMA_TFLOPS}
+DTYPE_LABEL = {0: "fp32 MFMA filter + fp64 exact maxima; int64/fp64 area and volume",
+               1: "split-f16 MFMA filter + fp64 exact maxima; int64/fp64 area and volume"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -390,31 +400,58 @@ def main():
     def step(i):
         return S.features(vols[i % len(vols)], spacing, stats=True, timing=True)
 
-    for i in range(args.warmup):
-        f, st, rc = step(i)
-        log("warmup %d: %.3f ms total, V=%d" % (i, st["ms"]["total"], st["V"]))
-    torch.cuda.synchronize()
-    phases = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        f, st, rc = step(i)
-        phases.append(st["ms"])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
+    def timed(label):
+        for i in range(args.warmup):
+            f, st, rc = step(i)
+            log("%s warmup %d: %.3f ms total, V=%d" % (label, i, st["ms"]["total"], st["V"]))
+        torch.cuda.synchronize()
+        phases = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            f, st, rc = step(i)
+            phases.append(st["ms"])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+        log("%s: %.3f ms per call; phases (ms): %s" % (label, ms, ", ".join("%s %.4f" % kv for kv in avg.items())))
+        return f, st, ms, avg, phases
+
+    # the library's default call (exact; the 3D pair tiles that cannot hold
+    # the diameter are skipped), then every vertex pair evaluated
+    prune_default = S.get_prune()
+    f_eff, st_eff, ms_eff, avg_eff, _ = timed("default call")
+    S.set_prune(0)
+    try:
+        f, st, ms_per_step, avg, phases = timed("all pairs")
+    finally:
+        S.set_prune(prune_default)
+    assert np.array_equal(f, f_eff) and np.array_equal(st["pair_ids"], st_eff["pair_ids"]), \
+        "pruned and all-pairs calls differ"
     V = st["V"]
     pairs3 = V * (V - 1) // 2
     pairs2 = st["pairs_2d"]
-    avg = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
-    log("phases (ms): " + ", ".join("%s %.4f" % kv for kv in avg.items()))
 
     t_pair = avg["pair_maxima"] * 1e-3
     kern = int(tiles[3])
-    achieved = FLOPS_PER_PAIR[kern] * (pairs3 + pairs2) / t_pair / 1e12
+    achieved = ALG_FLOPS_PER_PAIR * (pairs3 + pairs2) / t_pair / 1e12
     traffic = measured_traffic("k_pair_maxima_h" if kern == 1 else "k_pair_maxima", tiles)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[kern], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[kern], "traffic": traffic,
-                "kernel": "split-f16 v_mfma_f32_32x32x16_f16" if kern == 1 else "fp32 v_mfma_f32_16x16x4_f32"}
+                "kernel": "split-f16 v_mfma_f32_32x32x16_f16" if kern == 1 else "fp32 v_mfma_f32_16x16x4_f32",
+                "work": "%d algorithmic flops per vertex pair x (V(V-1)/2 + in-plane pairs) = %.4g flops per launch"
+                        % (ALG_FLOPS_PER_PAIR, ALG_FLOPS_PER_PAIR * float(pairs3 + pairs2)),
+                "kernel_ms": avg["pair_maxima"]}
+    # share of the matrix pipe's peak that the kernel's executed MFMA flops reach
+    # (dense Gram operands, split terms and padding included): not a roofline
+    mfma_occupancy = MFMA_FLOPS_PER_PAIR[kern] * (pairs3 + pairs2) / t_pair / 1e12 / PEAK_TFLOPS[kern]
+    effective = {
+        "what": "the library's default call on the same masks: exact pruned 3D pairs (tiles whose bounding-box "
+                "distance bound is below a vertex-pair distance are skipped); identical results",
+        "effective_pairs_per_s": pairs3 / (ms_eff * 1e-3),
+        "ms_per_step": ms_eff,
+        "phases_ms": avg_eff,
+        "speedup_vs_all_pairs": ms_per_step / ms_eff,
+    }
     N = int(np.prod(mask.shape))
     t_mesh = (avg["mesh_count"] + avg["mesh_emit"]) * 1e-3
     tc, te = measured_traffic("k_mesh_count"), measured_traffic("k_mesh_emit")
@@ -444,7 +481,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16" if kern == 1 else "f32",
+        "dtype": DTYPE_LABEL[kern],
         "data": "synthetic",
         "config": {
             "workload": "large ROI: uint8 mask 300x512x512 (axis0 = slices), spacing (1.25,0.7,0.7) mm, "
@@ -457,6 +494,8 @@ def main():
             "pairs_in_plane": pairs2,
         },
         "roofline": roofline,
+        "mfma_pipe_occupancy": mfma_occupancy,
+        "effective": effective,
         "cpu_baseline": cpu,
         "tiles": list(tiles),
         "phases_ms": avg,

@@ -134,6 +134,51 @@ int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_
                     int* status, int flags, void* stream);
 
 /*
+ * The whole Shape class.  The paper's feature list (Sec. 2) is the six
+ * features above; PyRadiomics' Shape class, which the paper accelerates,
+ * also has members that are closed forms of MeshVolume V, SurfaceArea A and
+ * the number n of inside voxels, and members from the principal axes of the
+ * inside voxels.  With the covariance C of the inside voxels' physical
+ * coordinates (index * spacing; population covariance, divisor n) and its
+ * eigenvalues l_least <= l_minor <= l_major (negative rounding clamped to 0),
+ * the SHAPE3D_N_CLASS outputs are, in order:
+ *   0-5  the six features above;
+ *   6    VoxelVolume            = n s0 s1 s2
+ *   7    SurfaceVolumeRatio     = A / V
+ *   8    Sphericity             = (36 pi V^2)^(1/3) / A
+ *   9    Compactness1           = V / (sqrt(pi) A^(3/2))
+ *   10   Compactness2           = 36 pi V^2 / A^3
+ *   11   SphericalDisproportion = A / (36 pi V^2)^(1/3)
+ *   12   MajorAxisLength        = 4 sqrt(l_major)
+ *   13   MinorAxisLength        = 4 sqrt(l_minor)
+ *   14   LeastAxisLength        = 4 sqrt(l_least)
+ *   15   Elongation             = sqrt(l_minor / l_major)  (0 if l_major = 0)
+ *   16   Flatness               = sqrt(l_least / l_major)  (0 if l_major = 0)
+ * all 0 for an empty ROI.  The moments are summed exactly in integers in the
+ * mesh pass (the same read of the volume), the eigenvalues come from Jacobi
+ * rotations in FP64.
+ *
+ * shape3d_class -- the SHAPE3D_N_CLASS members for one ROI (arguments as
+ *   shape3d_ex; out: HOST double[SHAPE3D_N_CLASS]; stats: HOST or NULL).
+ *   Synchronous on `stream`.
+ *
+ * shape3d_batched_ex -- shape3d_batched with per-ROI statistics and flags.
+ *   stats: HOST shape3d_stats[n_rois] or NULL: V, T, maximising pairs,
+ *          in-plane pair counts and candidate rows of every ROI (ms fields 0).
+ *   flags: SHAPE3D_BATCH_GRAPH as shape3d_batched, plus SHAPE3D_SHAPE_CLASS:
+ *          out is then HOST double[SHAPE3D_N_CLASS * n_rois] (ROI r's members
+ *          at out[SHAPE3D_N_CLASS r ...]); without it double[6 * n_rois].
+ *   Other arguments and errors as shape3d_batched.
+ */
+#define SHAPE3D_SHAPE_CLASS 2
+#define SHAPE3D_N_CLASS 17
+
+int shape3d_class(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                  double out[SHAPE3D_N_CLASS], shape3d_stats* stats, void* stream);
+int shape3d_batched_ex(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out,
+                       int* status, shape3d_stats* stats, int flags, void* stream);
+
+/*
  * shape3d_vertices -- the mesh vertex set, for verification.
  *   ids:  DEVICE int64[cap]; receives the canonical ids of all V vertices
  *         (in the library's emission order, which is deterministic).
@@ -330,7 +375,8 @@ int shape3d_ex_async(const void* vol, int dtype, const int64_t dims[3], const do
  *             launches and buffers).  An entry that is out of bounds, reaches
  *             past the allocation holding base, or is otherwise invalid gets
  *             status SHAPE3D_EINVAL; the other ROIs are unaffected.
- *   out:      DEVICE double[6 n_rois]; status: DEVICE int[n_rois].
+ *   out:      DEVICE double[6 n_rois], or double[SHAPE3D_N_CLASS n_rois] with
+ *             SHAPE3D_SHAPE_CLASS in flags; status: DEVICE int[n_rois].
  *   workspace: DEVICE or NULL.  With a workspace: as shape3d_ex_async (no
  *             host synchronisation; shape3d_batched_workspace_size).  With
  *             NULL the library's workspace is used: the call reads the vertex
@@ -340,6 +386,8 @@ int shape3d_ex_async(const void* vol, int dtype, const int64_t dims[3], const do
  *             n_rois, max_dims and output pointers; a replay whose meshes
  *             exceed the recorded capacity sets every status to
  *             SHAPE3D_ECAPACITY (call without the flag once to resize).
+ *             SHAPE3D_SHAPE_CLASS: the whole Shape class per ROI (see
+ *             shape3d_class).
  * Enqueued on `stream`; returns without waiting for the results.
  */
 typedef struct {

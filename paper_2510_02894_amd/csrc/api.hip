@@ -268,7 +268,9 @@ struct Batch {
   int max_G = 1;
   bool planned = false;
   long long max_d[3] = {0, 0, 0};  // planned: every ROI's dims are at most these
+  bool moments = false;  // also the inside-voxel moments and the whole Shape class
   int n() const { return n_rois; }
+  int nf() const { return moments ? SHAPE3D_N_CLASS : 6; }  // features per ROI in out
 };
 
 void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double spacing[3], long long stride0 = 0,
@@ -497,6 +499,7 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   B.cand_nch = P.as<long long>(W_CAND_NCH);
   B.cand_chbase = P.as<long long>(W_CAND_CHBASE);
   B.cu_count = cu_count;
+  B.moments = Bt.moments;
   B.prune = false;
   B.blkrec = P.as<BlkRec>(W_BLKREC);
   B.rseed = P.as<RoiSeed>(W_RSEED);
@@ -509,9 +512,10 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
 int launch_head(const Ptrs& P, const Batch& Bt, int dtype, hipStream_t st) {
   HIPCK(launch_fill_u32(P.as<unsigned int>(W_COUNTERS), 0u, kCounterWords, st));
   HIPCK(launch_mesh_count(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<double>(W_CASE_AREA),
-                          P.as<BrickPart>(W_PART), st));
+                          P.as<BrickPart>(W_PART), Bt.moments ? 1 : 0, st));
   HIPCK(launch_mesh_totals(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, dtype, P.as<const BrickPart>(W_PART),
-                           P.as<long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS), st));
+                           P.as<long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
+                           Bt.moments ? 1 : 0, st));
   return SHAPE3D_OK;
 }
 
@@ -622,7 +626,7 @@ int run_fixed(const Batch& Bt, int dtype, const Roi* one_roi, const DevTable* dt
   }
   if ((rc = launch_head(P, Bt, dtype, st))) return rc;
   if ((rc = launch_tail(P, Bt, dtype, L.S, cu_count, st, nullptr, cap))) return rc;
-  HIPCK(launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, st));
+  HIPCK(launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, Bt.nf(), st));
   return SHAPE3D_OK;
 }
 
@@ -642,8 +646,9 @@ void fill_stats(shape3d_stats* stats, const RoiResult& R, const float* ms) {
     for (int k = 0; k < 7; ++k) stats->ms[k] = ms[k];
 }
 
-int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double out[6],
-                 shape3d_stats* stats, int timing, hipStream_t st, RoiResult* raw = nullptr) {
+// out: the six features, or with `moments` the SHAPE3D_N_CLASS Shape-class members.
+int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double* out,
+                 shape3d_stats* stats, int timing, hipStream_t st, RoiResult* raw = nullptr, bool moments = false) {
   int rc = check_args(vol, dtype, dims, spacing);
   if (rc) return rc;
   if (!out) return fail(SHAPE3D_EINVAL, "null out");
@@ -651,6 +656,7 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   if ((rc = get_workspace(&wp))) return rc;
   Workspace& w = *wp;
   Batch Bt;
+  Bt.moments = moments;
   batch_add(Bt, vol, dims, spacing);
   if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
   RoiResult* hres = host_results(w, Bt);
@@ -658,6 +664,8 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   if ((rc = run_eager(w, Bt, dtype, st, hres, timing, ms))) return rc;
   if (hres->status < 0) return fail(hres->status, "an internal capacity was exceeded");
   for (int f = 0; f < 6; ++f) out[f] = hres->out[f];
+  if (moments)
+    for (int f = 6; f < SHAPE3D_N_CLASS; ++f) out[f] = hres->shape[f - 6];
   if (raw) *raw = *hres;
   fill_stats(stats, *hres, timing ? ms : nullptr);
   g_err.clear();
@@ -702,7 +710,7 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
   if (!rc) rc = launch_head(P, Bt, dtype, st);
   if (!rc) rc = launch_tail(P, Bt, dtype, S, w.cu_count, st, nullptr, w.last_vmax);
   if (!rc) {
-    const hipError_t e = dt ? launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, st)
+    const hipError_t e = dt ? launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, Bt.nf(), st)
                             : hipMemcpyAsync(rec.host_res, P.p[W_RES], sizeof(RoiResult) * Bt.n(),
                                              hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) rc = fail(SHAPE3D_EHIP, std::string("results: ") + hipGetErrorString(e));
@@ -768,6 +776,7 @@ int make_batch(const void* base, int dtype, const shape3d_roi* rois, int64_t n_r
 int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, int flags, hipStream_t st,
                  const RoiResult** hres_out) {
   Batch Bt;
+  Bt.moments = (flags & SHAPE3D_SHAPE_CLASS) != 0;
   int rc = make_batch(base, dtype, rois, n_rois, Bt);
   if (rc) return rc;
   Workspace* wp = nullptr;
@@ -775,8 +784,10 @@ int batched_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t n
   Workspace& w = *wp;
   if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
   const bool use_graph = (flags & SHAPE3D_BATCH_GRAPH) != 0;
-  const std::string sig =
-      use_graph ? layout_signature(base, dtype, rois, sizeof(shape3d_roi) * (size_t)n_rois) : std::string();
+  const int sig_flags = flags & SHAPE3D_SHAPE_CLASS;
+  const std::string sig = use_graph ? layout_signature(base, dtype, rois, sizeof(shape3d_roi) * (size_t)n_rois,
+                                                       &sig_flags, sizeof(sig_flags))
+                                    : std::string();
   const RoiResult* hres = nullptr;
   bool done = false;
   if (use_graph) {
@@ -834,6 +845,7 @@ int batched_dev_impl(const void* base, int dtype, const shape3d_roi_ex* rois, in
   Batch Bt;
   int rc = batch_bounds(Bt, n_rois, max_dims);
   if (rc) return rc;
+  Bt.moments = (flags & SHAPE3D_SHAPE_CLASS) != 0;
   const char* abase;
   size_t asize;
   if ((rc = device_range(base, &abase, &asize))) return rc;
@@ -841,7 +853,7 @@ int batched_dev_impl(const void* base, int dtype, const shape3d_roi_ex* rois, in
   const size_t elem = dtype == SHAPE3D_U8 ? 1 : 4;
   if ((uintptr_t)base % elem) return fail(SHAPE3D_EINVAL, "misaligned base");
   if ((rc = check_device_span(rois, sizeof(shape3d_roi_ex) * (size_t)n_rois, "ROI table"))) return rc;
-  if ((rc = check_device_span(out, sizeof(double) * 6 * (size_t)n_rois, "out"))) return rc;
+  if ((rc = check_device_span(out, sizeof(double) * Bt.nf() * (size_t)n_rois, "out"))) return rc;
   if ((rc = check_device_span(status, sizeof(int) * (size_t)n_rois, "status"))) return rc;
   DevTable dt;
   dt.rois = (const RoiDesc*)rois;
@@ -865,6 +877,8 @@ int batched_dev_impl(const void* base, int dtype, const shape3d_roi_ex* rois, in
     const void* extra[3] = {rois, out, status};
     sig = layout_signature(base, dtype, max_dims, sizeof(int64_t) * 3, extra, sizeof(extra));
     sig.append((const char*)&n_rois, sizeof(n_rois));
+    const int sig_flags = flags & SHAPE3D_SHAPE_CLASS;
+    sig.append((const char*)&sig_flags, sizeof(sig_flags));
     auto it = w.graphs.find(sig);
     if (it != w.graphs.end() && it->second.generation == w.generation && it->second.exec) {
       hipStream_t gs = w.graph_stream;
@@ -879,7 +893,7 @@ int batched_dev_impl(const void* base, int dtype, const shape3d_roi_ex* rois, in
     }
   }
   if ((rc = run_eager(w, Bt, dtype, st, nullptr, 0, nullptr, &dt))) return rc;
-  HIPCK(launch_results_out(w.ptrs().as<const RoiResult>(W_RES), Bt.n(), out, status, st));
+  HIPCK(launch_results_out(w.ptrs().as<const RoiResult>(W_RES), Bt.n(), out, status, Bt.nf(), st));
   if (use_graph) {
     graph_slot(w, sig);
     GraphRec rec;
@@ -1149,18 +1163,34 @@ int shape3d_ex(const void* vol, int dtype, const int64_t dims[3], const double s
 
 int shape3d_batched(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out, int* status,
                     int flags, void* stream) {
+  return shape3d_batched_ex(base, dtype, rois, n_rois, out, status, nullptr, flags & SHAPE3D_BATCH_GRAPH, stream);
+}
+
+int shape3d_batched_ex(const void* base, int dtype, const shape3d_roi* rois, int64_t n_rois, double* out,
+                       int* status, shape3d_stats* stats, int flags, void* stream) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!out || !status) return fail(SHAPE3D_EINVAL, "null output");
+  if (flags & ~(SHAPE3D_BATCH_GRAPH | SHAPE3D_SHAPE_CLASS)) return fail(SHAPE3D_EINVAL, "unknown flags");
   const RoiResult* hres = nullptr;
   const int rc = batched_impl(base, dtype, rois, n_rois, flags, (hipStream_t)stream, &hres);
   if (rc < 0 && !hres) return rc;
+  const bool cls = (flags & SHAPE3D_SHAPE_CLASS) != 0;
+  const int nf = cls ? SHAPE3D_N_CLASS : 6;
   for (int64_t r = 0; r < n_rois; ++r) {
-    for (int f = 0; f < 6; ++f) out[6 * r + f] = hres[r].out[f];
+    for (int f = 0; f < 6; ++f) out[nf * r + f] = hres[r].out[f];
+    for (int f = 6; f < nf; ++f) out[nf * r + f] = hres[r].shape[f - 6];
     status[r] = hres[r].status;
+    if (stats) fill_stats(&stats[r], hres[r], nullptr);
   }
   if (rc < 0) return rc;
   g_err.clear();
   return SHAPE3D_OK;
+}
+
+int shape3d_class(const void* vol, int dtype, const int64_t dims[3], const double spacing[3],
+                  double out[SHAPE3D_N_CLASS], shape3d_stats* stats, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return shape3d_impl(vol, dtype, dims, spacing, out, stats, 0, (hipStream_t)stream, nullptr, true);
 }
 
 int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], int64_t* ids,
@@ -1358,6 +1388,7 @@ int shape3d_batched_dev(const void* base, int dtype, const shape3d_roi_ex* rois,
                         const int64_t max_dims[3], double* out, int* status, void* workspace, size_t ws_bytes,
                         int flags, void* stream) {
   std::lock_guard<std::mutex> lk(g_mu);
+  if (flags & ~(SHAPE3D_BATCH_GRAPH | SHAPE3D_SHAPE_CLASS)) return fail(SHAPE3D_EINVAL, "unknown flags");
   return batched_dev_impl(base, dtype, rois, n_rois, max_dims, out, status, workspace, ws_bytes, flags,
                           (hipStream_t)stream);
 }

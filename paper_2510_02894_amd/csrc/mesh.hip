@@ -15,6 +15,14 @@
 // an integer in units of s0*s1*s2/48 (see gen_mc_table.py).  The binary pass
 // therefore accumulates the volume exactly in int64 and the area as FP64
 // sums in a fixed order.  Soft masks evaluate every triangle in FP64.
+//
+// Inside-voxel moments (the principal-axis members of the Shape class, asked
+// for per call): every voxel is the far corner (1, 1, 1) of exactly one cube,
+// so the thread that owns that cube counts it, from the voxel-row word it
+// already holds.  A word's count, sum of bit positions and sum of squared bit
+// positions come from popcounts of the word under fixed bit patterns; the
+// thread, brick and ROI sums are integers, so the second moments are exact
+// and independent of the order of the work.
 #include <hip/hip_runtime.h>
 
 #define MC_TABLE_QUAL __constant__ const
@@ -278,6 +286,43 @@ __device__ inline Corners tile_corners(const uint32_t* s_bits, const Tile& T, co
   return make_corners(r[0][0], x[0][0], r[0][1], x[0][1], r[1][0], x[1][0], r[1][1], x[1][1]);
 }
 
+// Count, sum of bit positions b and sum of b^2 over the set bits of w.  With
+// M_k the bits whose position has bit k set, b = sum_k 2^k [b in M_k], so
+// sum b = sum_k 2^k popc(w & M_k) and sum b^2 = sum_k 4^k popc(w & M_k)
+// + sum_{k<l} 2^(k+l+1) popc(w & M_k & M_l).
+struct WordMom {
+  int c, b1, b2;
+};
+
+__device__ inline WordMom word_moments(uint32_t w) {
+  WordMom m;
+  if (w == 0u) {
+    m.c = m.b1 = m.b2 = 0;
+    return m;
+  }
+  if (w == 0xffffffffu) {  // 32 bits: sum b = 496, sum b^2 = 10416
+    m.c = 32;
+    m.b1 = 496;
+    m.b2 = 10416;
+    return m;
+  }
+  const uint32_t M[5] = {0xaaaaaaaau, 0xccccccccu, 0xf0f0f0f0u, 0xff00ff00u, 0xffff0000u};
+  m.c = __popc(w);
+  int b1 = 0, b2 = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const uint32_t wk = w & M[k];
+    const int pk = __popc(wk);
+    b1 += pk << k;
+    b2 += pk << (2 * k);
+#pragma unroll
+    for (int l = k + 1; l < 5; ++l) b2 += __popc(wk & M[l]) << (k + l + 1);
+  }
+  m.b1 = b1;
+  m.b2 = b2;
+  return m;
+}
+
 __device__ inline int case_of(const Corners& C, int k) {
   int cas = 0;
 #pragma unroll
@@ -309,7 +354,7 @@ __global__ __launch_bounds__(256) void k_case_area(const Roi* __restrict__ rois,
 template <int DT>
 __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restrict__ rois, int n_rois,
                                                               long long nbricks, const double* __restrict__ case_area,
-                                                              BrickPart* __restrict__ part) {
+                                                              BrickPart* __restrict__ part, int moments) {
   extern __shared__ uint32_t s_bits[];
   __shared__ double s_area[256];
   __shared__ int s_tk[256];
@@ -320,6 +365,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   __shared__ double s_rd[2][4];
   __shared__ long long s_rl[4];
   __shared__ int s_ri[8][4];
+  __shared__ long long s_mom[10][4];
 
   const long long brick = xcd_remap(blockIdx.x, nbricks);
   const int roi = find_roi(rois, n_rois, brick);
@@ -358,6 +404,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   static_assert(kTZ <= 8, "an item holds the plane in 3 bits");
   uint32_t act[kTZ];
   int cnt = 0;
+  long long mom[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     uint32_t rr[kTZ + 1][2], xx[kTZ + 1][2];
 #pragma unroll
@@ -399,6 +446,36 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
         act[p] = active;
       }
       cnt += __popc(act[p]);
+    }
+    if (moments && L.valid) {
+      // voxel row (z, y) = (pz0 + p, L.y + 1), x = 32 l + bit, is word rr[p + 1][1]
+      // (the far corner row of plane pair p); rows past the array read as 0
+      long long n = 0, sz = 0, szz = 0, sb1 = 0, sb2 = 0, szb = 0;
+#pragma unroll
+      for (int p = 0; p < kTZ; ++p) {
+        if (p + 1 < T.np) {
+          const WordMom wm = word_moments(rr[p + 1][1]);
+          const long long z = T.pz0 + p;
+          n += wm.c;
+          sz += z * wm.c;
+          szz += z * z * wm.c;
+          sb1 += wm.b1;
+          sb2 += wm.b2;
+          szb += z * wm.b1;
+        }
+      }
+      const long long y = L.y + 1, x0 = 32ll * L.l;
+      const long long sx = x0 * n + sb1;
+      mom[0] = n;
+      mom[1] = sz;
+      mom[2] = y * n;
+      mom[3] = sx;
+      mom[4] = szz;
+      mom[5] = y * y * n;
+      mom[6] = x0 * x0 * n + 2 * x0 * sb1 + sb2;
+      mom[7] = y * sz;
+      mom[8] = x0 * sz + szb;
+      mom[9] = y * sx;
     }
   }
   int total;
@@ -484,6 +561,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
     bb[k] = wave_min(bb[k]);
     bb[3 + k] = wave_max(bb[3 + k]);
   }
+  if (moments)
+    for (int k = 0; k < 10; ++k) mom[k] = wave_sum(mom[k]);
   if (lane == 0) {
     s_ri[0][wid] = nv;
     s_ri[1][wid] = nt;
@@ -491,6 +570,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
     s_rd[0][wid] = area;
     s_rd[1][wid] = vol_d;
     s_rl[wid] = vol_i;
+    for (int k = 0; k < 10; ++k) s_mom[k][wid] = mom[k];
   }
   __syncthreads();
   if (tid == 0) {
@@ -504,6 +584,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
     P.area = ((s_rd[0][0] + s_rd[0][1]) + s_rd[0][2]) + s_rd[0][3];
     P.vol_d = ((s_rd[1][0] + s_rd[1][1]) + s_rd[1][2]) + s_rd[1][3];
     P.vol_i = s_rl[0] + s_rl[1] + s_rl[2] + s_rl[3];
+    for (int k = 0; k < 10; ++k) P.mom[k] = s_mom[k][0] + s_mom[k][1] + s_mom[k][2] + s_mom[k][3];
     part[brick] = P;
   }
 }
@@ -512,12 +593,42 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
 // Per-ROI totals: exclusive scan of brick vertex counts, fixed-order sums.
 // One 1024-thread workgroup per ROI.
 
+// 128-bit sum over a wave (two's complement halves, carry from the low half).
+__device__ inline __int128 wave_sum_i128(__int128 v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long lo = (unsigned long long)v, hi = (unsigned long long)(v >> 64);
+    const unsigned long long olo = __shfl_xor(lo, m, 64), ohi = __shfl_xor(hi, m, 64);
+    const unsigned long long slo = lo + olo;
+    const unsigned long long shi = hi + ohi + (slo < lo ? 1ull : 0ull);
+    v = (__int128)(((unsigned __int128)shi << 64) | (unsigned __int128)slo);
+  }
+  return v;
+}
+
+// Covariance of the inside voxels' physical coordinates from exact integer
+// moments: cov_ij = s_i s_j (n S_ij - S_i S_j) / n^2, the numerator exact in
+// 128 bits (n < 2^40 voxels and coordinates < 2^20 keep it below 2^120).
+__device__ inline void moments_to_cov(const __int128* S, const double* sp, RoiMeta& M) {
+  const __int128 n = S[0];
+  M.n_in = (long long)n;
+  const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+  const int sij[6] = {4, 5, 6, 7, 8, 9};
+  const double n2 = (double)n * (double)n;
+  for (int k = 0; k < 6; ++k) {
+    const __int128 c = n * S[sij[k]] - S[1 + ii[k]] * S[1 + jj[k]];
+    M.cov[k] = n > 0 ? (double)c / n2 * (sp[ii[k]] * sp[jj[k]]) : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ rois, int n_rois, long long nbricks,
                                                       int dtype, const BrickPart* __restrict__ part,
-                                                      long long* __restrict__ brick_voff, RoiMeta* __restrict__ meta) {
+                                                      long long* __restrict__ brick_voff, RoiMeta* __restrict__ meta,
+                                                      int moments) {
   __shared__ long long s_l[2][1024];
   __shared__ double s_d[2][1024];
   __shared__ int s_b[6][1024];
+  __shared__ __int128 s_m[10][16];
   const int r = blockIdx.x, tid = threadIdx.x;
   const Roi R = rois[r];
   const long long b0 = R.brick_begin, b1 = R.brick_end;
@@ -538,6 +649,16 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
       bb[k] = min(bb[k], P.bb[k]);
       bb[3 + k] = max(bb[3 + k], P.bb[3 + k]);
     }
+  }
+  if (moments) {
+    // exact moment sums: 128-bit per thread, per wave, then over the 16 waves
+    __int128 m[10];
+    for (int k = 0; k < 10; ++k) m[k] = 0;
+    for (long long b = lo; b < hi; ++b)
+      for (int k = 0; k < 10; ++k) m[k] += (__int128)part[b].mom[k];
+    for (int k = 0; k < 10; ++k) m[k] = wave_sum_i128(m[k]);
+    if ((tid & 63) == 0)
+      for (int k = 0; k < 10; ++k) s_m[k][tid >> 6] = m[k];
   }
   // exclusive scan of nv over threads (Hillis-Steele in shared memory)
   s_l[0][tid] = nv;
@@ -598,6 +719,16 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
       }
     }
     M.R2 = R2;
+    M.n_in = 0;
+    for (int k = 0; k < 6; ++k) M.cov[k] = 0.0;
+    if (moments) {
+      __int128 S[10];
+      for (int k = 0; k < 10; ++k) {
+        S[k] = 0;
+        for (int w = 0; w < 16; ++w) S[k] += s_m[k][w];
+      }
+      moments_to_cov(S, R.s, M);
+    }
     meta[r] = M;
   }
 }
@@ -911,24 +1042,24 @@ __global__ void k_set_roi(Roi R, Roi* __restrict__ out) {
 size_t mesh_lds_bytes(int max_G) { return sizeof(uint32_t) * (size_t)(kTZ + 1) * (kBrickThreads + 1 + max_G); }
 
 hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
-                             double* case_area, BrickPart* part, hipStream_t st) {
+                             double* case_area, BrickPart* part, int moments, hipStream_t st) {
   if (nbricks <= 0) return hipSuccess;
   const size_t lds = mesh_lds_bytes(max_G);
   if (dtype == 0) {
     hipLaunchKernelGGL(k_case_area, dim3((unsigned)n_rois), dim3(256), 0, st, rois, case_area);
     hipLaunchKernelGGL(k_mesh_count<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part);
+                       case_area, part, moments);
   } else {
     hipLaunchKernelGGL(k_mesh_count<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part);
+                       case_area, part, moments);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
-                              long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st) {
+                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, hipStream_t st) {
   hipLaunchKernelGGL(k_mesh_totals, dim3(n_rois), dim3(1024), 0, st, rois, n_rois, nbricks, dtype, part, brick_voff,
-                     meta);
+                     meta, moments);
   hipLaunchKernelGGL(k_roi_rows, dim3(1), dim3(1024), 0, st, n_rois, meta, totals);
   return hipGetLastError();
 }

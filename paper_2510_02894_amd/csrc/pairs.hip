@@ -844,10 +844,70 @@ __global__ void k_init_groups(GroupRes* gres, long long n, unsigned int* counter
   }
 }
 
+// Eigenvalues (ascending) of the symmetric 3x3 matrix with entries
+// c = (a00, a11, a22, a01, a02, a12), by cyclic Jacobi rotations (Golub and
+// Van Loan, Matrix Computations, Sec. 8.5): each rotation in plane (p, q)
+// uses t = sign(th) / (|th| + sqrt(1 + th^2)), th = (a_qq - a_pp) / (2 a_pq),
+// the smaller root, which zeroes a_pq; sweeps converge quadratically, and 12
+// sweeps leave the off-diagonal entries at rounding level.
+__device__ inline void sym3_eigenvalues(const double* c, double* lam) {
+  double a[3][3] = {{c[0], c[3], c[4]}, {c[3], c[1], c[5]}, {c[4], c[5], c[2]}};
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = fabs(a[0][1]) + fabs(a[0][2]) + fabs(a[1][2]);
+    if (off == 0.0) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2, r = 3 - p - q;
+      const double apq = a[p][q];
+      if (apq == 0.0) continue;
+      const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+      const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+      const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+      a[p][p] -= t * apq;
+      a[q][q] += t * apq;
+      a[p][q] = a[q][p] = 0.0;
+      const double arp = a[r][p], arq = a[r][q];
+      a[r][p] = a[p][r] = cs * arp - sn * arq;
+      a[r][q] = a[q][r] = sn * arp + cs * arq;
+    }
+  }
+  double e0 = a[0][0], e1 = a[1][1], e2 = a[2][2], tmp;
+  if (e0 > e1) { tmp = e0; e0 = e1; e1 = tmp; }
+  if (e1 > e2) { tmp = e1; e1 = e2; e2 = tmp; }
+  if (e0 > e1) { tmp = e0; e0 = e1; e1 = tmp; }
+  lam[0] = e0;
+  lam[1] = e1;
+  lam[2] = e2;
+}
+
+// The Shape-class members that follow from MeshVolume V, SurfaceArea A, the
+// inside-voxel count and the covariance eigenvalues (PyRadiomics' Shape class
+// definitions): VoxelVolume, SurfaceVolumeRatio, Sphericity, Compactness1,
+// Compactness2, SphericalDisproportion, Major/Minor/LeastAxisLength (4 sqrt
+// of the largest, middle and smallest eigenvalue, negative rounding clamped
+// to 0), Elongation and Flatness (0 when the largest eigenvalue is 0).
+__device__ inline void shape_class_members(const RoiMeta& M, const Roi& R, double V, double A, double* f) {
+  const double pi = 3.14159265358979323846;
+  f[0] = (double)M.n_in * (R.s[0] * R.s[1] * R.s[2]);
+  f[1] = A / V;
+  const double k = cbrt(36.0 * pi * V * V);
+  f[2] = k / A;
+  f[3] = V / (sqrt(pi) * A * sqrt(A));
+  f[4] = 36.0 * pi * V * V / (A * A * A);
+  f[5] = A / k;
+  double lam[3];
+  sym3_eigenvalues(M.cov, lam);
+  for (int i = 0; i < 3; ++i) lam[i] = lam[i] > 0.0 ? lam[i] : 0.0;
+  f[6] = 4.0 * sqrt(lam[2]);
+  f[7] = 4.0 * sqrt(lam[1]);
+  f[8] = 4.0 * sqrt(lam[0]);
+  f[9] = lam[2] > 0.0 ? sqrt(lam[1] / lam[2]) : 0.0;
+  f[10] = lam[2] > 0.0 ? sqrt(lam[0] / lam[2]) : 0.0;
+}
+
 __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const GroupRes* __restrict__ gres,
                            const unsigned int* __restrict__ ncand, const unsigned long long* __restrict__ key,
                            const Roi* __restrict__ rois, const long long* __restrict__ pairs2d,
-                           RoiResult* __restrict__ res, long long cand_cap) {
+                           RoiResult* __restrict__ res, long long cand_cap, int moments) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
     const RoiMeta M = meta[r];
     RoiResult Q;
@@ -872,18 +932,24 @@ __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const G
     if ((long long)*ncand > cand_cap || ncand[1] != 0u) Q.status = -4;
     if (rois[r].status != 0) Q.status = rois[r].status;
     Q.pad_ = 0;
+    Q.n_in = moments ? M.n_in : 0;
+    for (int f = 0; f < 11; ++f) Q.shape[f] = 0.0;
+    if (moments && Q.status == 0) shape_class_members(M, rois[r], Q.out[0], Q.out[1], Q.shape);
     res[r] = Q;
   }
 }
 
-// Per-ROI results to the caller's device arrays: out[6 r .. 6 r + 5] (left
+// Per-ROI results to the caller's device arrays: out[nf r .. nf r + nf - 1]
+// (the six features, then with nf = 17 the other Shape-class members; left
 // untouched for a negative status) and status[r].
 __global__ void k_results_out(const RoiResult* __restrict__ res, int n_rois, double* __restrict__ out,
-                              int* __restrict__ status) {
+                              int* __restrict__ status, int nf) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
     const int st = res[r].status;
-    if (st >= 0)
-      for (int f = 0; f < 6; ++f) out[6 * r + f] = res[r].out[f];
+    if (st >= 0) {
+      for (int f = 0; f < 6; ++f) out[(long long)nf * r + f] = res[r].out[f];
+      for (int f = 6; f < nf; ++f) out[(long long)nf * r + f] = res[r].shape[f - 6];
+    }
     if (status) status[r] = st;
   }
 }
@@ -1044,12 +1110,12 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
 
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(B.n_rois)), dim3(256), 0, st, B.n_rois, B.meta, B.gres,
-                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res, B.cand_cap);
+                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res, B.cand_cap, B.moments ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_results_out(const RoiResult* res, int n_rois, double* out, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_results_out, dim3(grid_for(n_rois, 1024)), dim3(256), 0, st, res, n_rois, out, status);
+hipError_t launch_results_out(const RoiResult* res, int n_rois, double* out, int* status, int nf, hipStream_t st) {
+  hipLaunchKernelGGL(k_results_out, dim3(grid_for(n_rois, 1024)), dim3(256), 0, st, res, n_rois, out, status, nf);
   return hipGetLastError();
 }
 

@@ -128,6 +128,9 @@ struct BrickPart {
   double area;
   double vol_d;      // soft: signed volume partial
   long long vol_i;   // binary: signed volume partial in units of s0*s1*s2/48
+  // inside-voxel moments in voxel indices (only when the call asks for them):
+  // count, sums of z, y, x, of zz, yy, xx, and of zy, zx, yx
+  long long mom[10];
 };
 
 struct RoiMeta {
@@ -140,6 +143,8 @@ struct RoiMeta {
   double R2;          // bound on |centred FP32 position|^2
   int bb[6];
   long long sb_off;   // first 1024-row column of the ROI's 3D segment in the pruning pass
+  long long n_in;     // inside voxels (when moments are asked for)
+  double cov[6];      // covariance of their physical coordinates: zz, yy, xx, zy, zx, yx
 };
 
 struct Seg {

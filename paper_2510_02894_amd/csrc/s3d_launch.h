@@ -9,6 +9,8 @@ namespace s3d {
 // Per-ROI result record written by the finalisation kernel.
 struct RoiResult {
   double out[6];
+  double shape[11];  // the other Shape-class members (when moments were summed), order of SHAPE3D_CLASS_*
+  long long n_in;    // inside voxels (when moments were summed)
   double vol_signed;
   long long V, T;
   long long ids[4][2];
@@ -23,10 +25,11 @@ struct RoiResult {
 // Dynamic LDS of the mesh kernels for ROIs with at most max_G row-groups per row.
 size_t mesh_lds_bytes(int max_G);
 // case_area: [n_rois * 256] scratch for the binary masks' per-case areas.
+// moments: also sum the inside voxels' moments (BrickPart.mom, RoiMeta.n_in/cov).
 hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
-                             double* case_area, BrickPart* part, hipStream_t st);
+                             double* case_area, BrickPart* part, int moments, hipStream_t st);
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
-                              long long* brick_voff, RoiMeta* meta, long long* totals, hipStream_t st);
+                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, hipStream_t st);
 hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
                                  unsigned int* overflow, hipStream_t st);
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
@@ -102,6 +105,7 @@ struct PairBufs {
   RoiResult* res;          // [n_rois]
   long long* pairs2d;      // [n_rois] in-plane pairs n*(n-1)/2 summed over buckets
   int cu_count;
+  bool moments;            // RoiMeta holds inside-voxel moments: finalise the whole Shape class
   // 3D pruning (prune.hip), kernel 1 only: when `prune` is set the 3D
   // segments run from the pruned item list instead of the work list
   bool prune;
@@ -166,8 +170,9 @@ hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st);   // MFMA pass
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st);   // reset group results, pair-pass counters, row maxima
 hipError_t launch_refine(const PairBufs& B, hipStream_t st);        // candidates + exact FP64 passes
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st);      // per-ROI results
-// res -> out[6 * n_rois] (not written for a negative status) and status[n_rois] (may be null), on the device
-hipError_t launch_results_out(const RoiResult* res, int n_rois, double* out, int* status, hipStream_t st);
+// res -> out[nf * n_rois] (nf = 6, or 17 for the whole Shape class; not written for a negative
+// status) and status[n_rois] (may be null), on the device
+hipError_t launch_results_out(const RoiResult* res, int n_rois, double* out, int* status, int nf, hipStream_t st);
 hipError_t launch_export_vertices(const unsigned long long* key, const double* tsoft, const RoiMeta* meta,
                                   const Roi* rois, long long* ids, double* pos, long long V, hipStream_t st);
 

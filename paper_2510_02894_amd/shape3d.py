@@ -27,6 +27,23 @@ FEATURES = (
     "Maximum2DDiameterColumn",
     "Maximum2DDiameterRow",
 )
+# The whole Shape class (shape3d_class): the six features, then the members
+# that follow from the mesh volume, surface area, inside-voxel count and the
+# principal axes of the inside voxels.
+SHAPE_FEATURES = FEATURES + (
+    "VoxelVolume",
+    "SurfaceVolumeRatio",
+    "Sphericity",
+    "Compactness1",
+    "Compactness2",
+    "SphericalDisproportion",
+    "MajorAxisLength",
+    "MinorAxisLength",
+    "LeastAxisLength",
+    "Elongation",
+    "Flatness",
+)
+N_CLASS = len(SHAPE_FEATURES)
 PHASES = ("mesh_count", "mesh_emit", "buckets", "pair_maxima", "refine", "finalize", "total")
 
 
@@ -83,6 +100,7 @@ class RoiEx(ctypes.Structure):
 
 
 BATCH_GRAPH = 1
+SHAPE_CLASS = 2
 
 
 class Shape3DError(RuntimeError):
@@ -121,6 +139,13 @@ def load():
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                         ctypes.c_void_p]
         lib.shape3d_batched.restype = ctypes.c_int
+        lib.shape3d_batched_ex.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(Roi), ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(Stats), ctypes.c_int, ctypes.c_void_p]
+        lib.shape3d_batched_ex.restype = ctypes.c_int
+        lib.shape3d_class.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, f64p, ctypes.POINTER(Stats),
+                                      ctypes.c_void_p]
+        lib.shape3d_class.restype = ctypes.c_int
         lib.shape3d_batched_soft_forward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Roi), ctypes.c_int64, f64p,
                                                      ctypes.POINTER(SoftSaved), ctypes.c_int, ctypes.c_void_p]
         lib.shape3d_batched_soft_forward.restype = ctypes.c_int
@@ -210,6 +235,25 @@ def features(vol, spacing: Sequence[float] = (1.0, 1.0, 1.0), stats: bool = Fals
     st = Stats()
     rc = lib.shape3d_ex(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, out, ctypes.byref(st), 1 if timing else 0,
                         _stream())
+    _check(rc)
+    f = np.array(out[:], dtype=np.float64)
+    if stats:
+        d = st.as_dict()
+        if rc == EMPTY:
+            d["pair_ids"][:] = -1
+        return f, d, rc
+    return f
+
+
+def shape_class(vol, spacing: Sequence[float] = (1.0, 1.0, 1.0), stats: bool = False):
+    """The whole Shape class (float64 numpy array [17], order of
+    ``SHAPE_FEATURES``); with ``stats=True`` returns ``(features, stats_dict, status)``."""
+    lib = load()
+    dt = _volume(vol)
+    dims, sp = _dims_spacing(vol.shape, spacing)
+    out = (ctypes.c_double * N_CLASS)()
+    st = Stats()
+    rc = lib.shape3d_class(ctypes.c_void_p(vol.data_ptr()), dt, dims, sp, out, ctypes.byref(st), _stream())
     _check(rc)
     f = np.array(out[:], dtype=np.float64)
     if stats:
@@ -362,10 +406,12 @@ def table_to_device(table, device="cuda"):
     return torch.from_numpy(raw).to(device)
 
 
-def batched_dev(base, table_dev, n_rois: int, max_dims, workspace=None, graph: bool = False, out=None, status=None):
+def batched_dev(base, table_dev, n_rois: int, max_dims, workspace=None, graph: bool = False, out=None, status=None,
+                shape_class: bool = False):
     """shape3d_batched_dev: features of n_rois ROIs described by the
     shape3d_roi_ex table held in the GPU tensor ``table_dev``; returns
-    (out float64 tensor [n, 6], status int32 tensor [n]) on the GPU."""
+    (out float64 tensor [n, 6] or [n, 17] with ``shape_class``, status int32
+    tensor [n]) on the GPU."""
     import torch
 
     lib = load()
@@ -376,23 +422,28 @@ def batched_dev(base, table_dev, n_rois: int, max_dims, workspace=None, graph: b
         raise TypeError("base dtype must be uint8 or float32")
     if table_dev.numel() * table_dev.element_size() < n_rois * ctypes.sizeof(RoiEx):
         raise ValueError("table_dev holds fewer than n_rois descriptors")
+    nf = N_CLASS if shape_class else 6
     if out is None:
-        out = torch.zeros((n_rois, 6), dtype=torch.float64, device=base.device)
+        out = torch.zeros((n_rois, nf), dtype=torch.float64, device=base.device)
+    elif out.numel() < n_rois * nf or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of n_rois x %d" % nf)
     if status is None:
         status = torch.full((n_rois,), -100, dtype=torch.int32, device=base.device)
     md = (ctypes.c_int64 * 3)(*[int(x) for x in max_dims])
     wp, wb = (None, 0) if workspace is None else _workspace(workspace)
     _check(lib.shape3d_batched_dev(ctypes.c_void_p(base.data_ptr()), dt, ctypes.c_void_p(table_dev.data_ptr()),
                                    int(n_rois), md, ctypes.c_void_p(out.data_ptr()),
-                                   ctypes.c_void_p(status.data_ptr()), wp, wb, BATCH_GRAPH if graph else 0,
-                                   _stream()))
+                                   ctypes.c_void_p(status.data_ptr()), wp, wb,
+                                   (BATCH_GRAPH if graph else 0) | (SHAPE_CLASS if shape_class else 0), _stream()))
     return out, status
 
 
-def batched(base, table, graph: bool = False):
+def batched(base, table, graph: bool = False, stats: bool = False, shape_class: bool = False):
     """Features of a batch of ROIs packed in the 1-D GPU tensor ``base``
     (uint8 or float32); ``table`` from ``roi_table``.  Returns
-    (features float64[n, 6], status int32[n])."""
+    (features float64[n, 6], status int32[n]), with ``shape_class`` the whole
+    Shape class (float64[n, 17]), and with ``stats`` also a list of per-ROI
+    statistics dicts (V, T, pair_ids, ...)."""
     import torch
 
     lib = load()
@@ -406,14 +457,29 @@ def batched(base, table, graph: bool = False):
         raise TypeError("base dtype must be uint8 or float32")
     n = len(table)
     _check_extents(table, base.numel())
-    out = np.zeros((n, 6), dtype=np.float64)
+    out = np.zeros((n, N_CLASS if shape_class else 6), dtype=np.float64)
     status = np.zeros(n, dtype=np.int32)
-    rc = lib.shape3d_batched(ctypes.c_void_p(base.data_ptr()), dt, table, n,
-                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                             status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), BATCH_GRAPH if graph else 0,
-                             _stream())
+    flags = (BATCH_GRAPH if graph else 0) | (SHAPE_CLASS if shape_class else 0)
+    if not stats and not shape_class:
+        rc = lib.shape3d_batched(ctypes.c_void_p(base.data_ptr()), dt, table, n,
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), flags, _stream())
+        _check(rc)
+        return out, status
+    st = (Stats * n)() if stats else None
+    rc = lib.shape3d_batched_ex(ctypes.c_void_p(base.data_ptr()), dt, table, n,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), st, flags, _stream())
     _check(rc)
-    return out, status
+    if not stats:
+        return out, status
+    dicts = []
+    for r in range(n):
+        d = st[r].as_dict()
+        if status[r] == EMPTY:
+            d["pair_ids"][:] = -1
+        dicts.append(d)
+    return out, status, dicts
 
 
 def soft_forward(p, spacing=(1.0, 1.0, 1.0)):

@@ -102,3 +102,52 @@ def max_pairs(vol, spacing):
     for k in range(3):
         out.append(max_pair(ids, pos, key[:, k]))
     return out
+
+
+def max_pair_chunked(ids, pos, chunk=1024):
+    """As max_pair (no groups), in row chunks so that large point sets fit in
+    memory: (max d2, (id_lo, id_hi)) with the lexicographically smallest pair
+    of canonical ids among the pairs at the maximum."""
+    ids = np.asarray(ids, dtype=np.int64)
+    pos = np.asarray(pos, dtype=np.float64)
+    n = len(ids)
+    if n < 2:
+        return 0.0, (-1, -1)
+    best = -1.0
+    pair = (-1, -1)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        dx = pos[s:e, None, 0] - pos[None, :, 0]
+        dy = pos[s:e, None, 1] - pos[None, :, 1]
+        dz = pos[s:e, None, 2] - pos[None, :, 2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        d2[np.arange(e - s), np.arange(s, e)] = -1.0
+        m = float(d2.max())
+        if m < best:
+            continue
+        ii, jj = np.nonzero(d2 == m)
+        lo = np.minimum(ids[s + ii], ids[jj])
+        hi = np.maximum(ids[s + ii], ids[jj])
+        k = np.lexsort((hi, lo))[0]
+        cand = (int(lo[k]), int(hi[k]))
+        if m > best or cand < pair:
+            best, pair = m, cand
+    return best, pair
+
+
+def hull_max_pair(ids, pos):
+    """The exact maximum squared distance and its smallest-id pair, searched
+    over the extreme points only: a farthest pair of a point set consists of
+    two extreme points of its convex hull (|x - q|^2 is strictly convex along
+    a segment, so a point that is a proper convex combination of others is
+    strictly closer to q than one of them).  Candidates are qhull's vertices
+    together with the points it reports as coplanar with a facet, so that an
+    extreme point that the hull merged into a facet within rounding is kept."""
+    from scipy.spatial import ConvexHull
+
+    h = ConvexHull(pos)
+    cand = [h.vertices]
+    if len(h.coplanar):
+        cand.append(h.coplanar[:, 0])
+    c = np.unique(np.concatenate(cand))
+    return max_pair_chunked(np.asarray(ids)[c], np.asarray(pos)[c])

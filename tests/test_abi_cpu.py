@@ -22,8 +22,23 @@ def test_header_declares_entry_points():
               "shape3d_soft_backward", "shape3d_batched_soft_forward", "shape3d_batched_soft_backward",
               "shape3d_get_tuning", "shape3d_set_tuning", "shape3d_autotune", "shape3d_last_error", "shape3d_release",
               "shape3d_version", "shape3d_workspace_size", "shape3d_workspace_size_v", "shape3d_batched_workspace_size",
-              "shape3d_ex_async", "shape3d_batched_dev"):
+              "shape3d_ex_async", "shape3d_batched_dev", "shape3d_noalloc", "shape3d_class", "shape3d_batched_ex"):
         assert n in names
+
+
+def test_header_constants_match_binding():
+    """Flag and size constants of the header equal the binding's copies."""
+    from paper_2510_02894_amd import shape3d as S
+
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"^#define (SHAPE3D_[A-Z0-9_]+) \(?(-?[0-9]+)\)?\s*(?:/\*.*)?$", text, flags=re.M))
+    assert int(defs["SHAPE3D_N_CLASS"]) == S.N_CLASS == len(S.SHAPE_FEATURES) == 17
+    assert int(defs["SHAPE3D_SHAPE_CLASS"]) == S.SHAPE_CLASS
+    assert int(defs["SHAPE3D_BATCH_GRAPH"]) == S.BATCH_GRAPH
+    assert int(defs["SHAPE3D_U8"]) == S.U8 and int(defs["SHAPE3D_F32"]) == S.F32
+    for name, val in (("OK", S.OK), ("EMPTY", S.EMPTY), ("EINVAL", S.EINVAL), ("ENODEV", S.ENODEV),
+                      ("EHIP", S.EHIP), ("ECAPACITY", S.ECAPACITY), ("ENOMEM", S.ENOMEM), ("EINTERNAL", S.EINTERNAL)):
+        assert int(defs["SHAPE3D_" + name]) == val, name
 
 
 def test_library_exports_every_declared_symbol():

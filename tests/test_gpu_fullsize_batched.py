@@ -1,24 +1,39 @@
 """Full-size parity of the batched workloads, in the configuration bench.py
-times (graph replay, default pair-pass setting): every ROI of the 4096-ROI
-uint8 batch against the single-ROI entry point (bit for bit), a sample of
-ROIs against the oracle, and the 256-ROI batched soft forward and backward
-against single-ROI calls and, on its smallest ROIs, against the oracle's FP64
-features and gradient."""
+times (graph replay, default pair-pass setting), against the oracle on every
+ROI:
+
+* the 4,096-ROI uint8 batch: V and T equal; area and volume within relative
+  1e-9; the in-plane diameters and their maximising pairs equal to the
+  oracle's; the 3D diameter and its pair equal to the oracle's all-pairs
+  maximum (ROIs of up to 20,000 vertices) or to the exact maximum over the
+  extreme points of the oracle's vertex set (larger ROIs; the farthest pair
+  of a point set lies on its convex hull);
+* the 256-ROI float32 soft batch: the same for the forward features, and the
+  batched backward's dL/dp against the oracle's FP64 gradient on 32 ROIs
+  spread over the size range.
+
+The oracle runs in a pool of worker processes (tests/oracle_pool.py)."""
 import os
 import sys
 
 import numpy as np
 import pytest
 
-from oracle import oracle as O
 from paper_2510_02894_amd import synth
+from tests import oracle_pool
 
 pytestmark = pytest.mark.gpu
+
+BRUTE_MAX = 20000
 
 
 def say(msg):
     print("[case] " + msg, flush=True)
     sys.stdout.flush()
+
+
+def pool_workers():
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 @pytest.fixture(scope="module")
@@ -33,49 +48,46 @@ def S():
     return shape3d
 
 
-def check_features(got, exp, name):
-    np.testing.assert_allclose(got[:2], exp[:2], rtol=1e-9, err_msg=name)   # volume, area
-    np.testing.assert_allclose(got[2:], exp[2:], rtol=1e-6, err_msg=name)   # diameters
+def check_roi(r, got, st, status, ref):
+    name = "ROI %d" % r
+    assert st["V"] == ref["V"], name
+    assert st["T"] == ref["T"], name
+    if ref["V"] == 0:
+        assert status == 1, name
+        np.testing.assert_array_equal(got, np.zeros(6), err_msg=name)
+        return
+    assert status == 0, name
+    np.testing.assert_allclose(got[0], abs(ref["signed_volume"]), rtol=1e-9, atol=0, err_msg=name)
+    np.testing.assert_allclose(got[1], ref["area"], rtol=1e-9, atol=0, err_msg=name)
+    np.testing.assert_array_equal(got[2:], np.sqrt(ref["d2"]), err_msg=name)
+    np.testing.assert_array_equal(st["pair_ids"], ref["pair_ids"], err_msg=name)
 
 
 def test_batched_4096_rois_full_size(S):
-    import torch
-
     say("batched 4096 ROIs: generate")
     buf, offs, shapes, sps = synth.batched_rois_torch(4096, 0)
     table = S.roi_table(offs, shapes, sps)
     say("batched 4096 ROIs: record + replay")
     out, status = S.batched(buf, table, graph=True)
-    out2, _ = S.batched(buf, table, graph=True)
-    assert np.array_equal(out, out2)
-    assert np.all(status == 0)
-    say("batched 4096 ROIs: single-ROI calls")
-    V = np.zeros(len(offs), np.int64)
-    for r in range(len(offs)):
-        n = int(np.prod(shapes[r]))
-        f, st, _ = S.features(buf[int(offs[r]):int(offs[r]) + n].view(shapes[r]), sps[r], stats=True)
-        assert np.array_equal(f, out2[r]), r
-        V[r] = st["V"]
-    # oracle on a sample spanning the vertex counts (up to 60k vertices)
-    order = np.argsort(V)
-    small = order[V[order] <= 60000]
-    picks = small[np.linspace(0, len(small) - 1, 8).astype(int)]
+    out2, status2 = S.batched(buf, table, graph=True)
+    assert np.array_equal(out, out2) and np.array_equal(status, status2)
+    say("batched 4096 ROIs: per-ROI statistics")
+    out3, status3, stats = S.batched(buf, table, stats=True)
+    assert np.array_equal(out3, out2) and np.array_equal(status3, status2)
     host = buf.cpu().numpy()
-    for r in picks:
-        n = int(np.prod(shapes[r]))
-        m = host[int(offs[r]):int(offs[r]) + n].reshape(shapes[r])
-        say("batched 4096 ROIs: oracle on ROI %d (V=%d)" % (r, V[r]))
-        exp = O.shape3d(m, sps[r])
-        check_features(out2[r], exp["features"], "ROI %d" % r)
-    del torch
+    say("batched 4096 ROIs: oracle on every ROI (%d workers)" % pool_workers())
+    ref = oracle_pool.run(host, offs, shapes, sps, brute_max=BRUTE_MAX, workers=pool_workers())
+    n3 = sum(1 for x in ref if x["method3d"] == "extreme points")
+    say("batched 4096 ROIs: compare (%d ROIs with the 3D diameter from extreme points)" % n3)
+    for r in range(len(offs)):
+        check_roi(r, out2[r], stats[r], status2[r], ref[r])
 
 
 def test_batched_soft_256_rois_full_size(S):
     import torch
 
     say("batched soft 256 ROIs: generate")
-    workers = max(1, min(16, os.cpu_count() or 1))
-    buf, offs, shapes, sps = synth.soft_batch(256, 0, workers=workers)
+    buf, offs, shapes, sps = synth.soft_batch(256, 0, workers=pool_workers())
     base = torch.from_numpy(buf).cuda()
     table = S.roi_table(offs, shapes, sps)
     say("batched soft 256 ROIs: forward (record + replay) and backward")
@@ -84,25 +96,24 @@ def test_batched_soft_256_rois_full_size(S):
     assert np.array_equal(out, out2)
     gout = np.ones((len(offs), 6))
     grad = S.batched_soft_backward(base, table, saved2, gout).cpu().numpy()
+    say("batched soft 256 ROIs: per-ROI statistics")
+    out3, status3, stats = S.batched(base, table, stats=True)
+    assert np.array_equal(out3, out2)
     sizes = np.array([int(np.prod(s)) for s in shapes])
     order = np.argsort(sizes)
-    # single-ROI calls on a sample: identical features and gradients
-    for r in order[np.linspace(0, len(order) - 1, 6).astype(int)]:
+    sample = set(int(r) for r in order[np.linspace(0, len(order) - 1, 32).astype(int)])
+    gjobs = {}
+    for r in sample:
+        pid = np.array([[saved2[r].pair_ids[f][0], saved2[r].pair_ids[f][1]] for f in range(4)], dtype=np.int64)
+        gjobs[r] = (gout[r], pid)
+    say("batched soft 256 ROIs: oracle on every ROI, gradients on %d (%d workers)" % (len(sample), pool_workers()))
+    ref = oracle_pool.run(buf, offs, shapes, sps, brute_max=BRUTE_MAX, workers=pool_workers(), grad=gjobs)
+    for r in range(len(offs)):
+        assert saved2[r].n_vertices == stats[r]["V"] and saved2[r].status == status3[r], r
+        np.testing.assert_array_equal(gjobs[r][1] if r in gjobs else stats[r]["pair_ids"], stats[r]["pair_ids"])
+        check_roi(r, out2[r], stats[r], status3[r], ref[r])
+    for r in sorted(sample):
         n = sizes[r]
-        p = buf[offs[r]:offs[r] + n].reshape(shapes[r])
-        pt = torch.from_numpy(np.ascontiguousarray(p)).cuda()
-        say("batched soft: single-ROI calls on ROI %d %s" % (r, shapes[r]))
-        f1, s1 = S.soft_forward(pt, sps[r])
-        assert np.array_equal(f1, out2[r]), r
-        g1 = S.soft_backward(pt, s1, gout[r]).cpu().numpy()
-        assert np.array_equal(g1.reshape(-1), grad[offs[r]:offs[r] + n]), r
-    # oracle features and FP64 gradient on the two smallest ROIs
-    for r in order[:2]:
-        n = sizes[r]
-        p = buf[offs[r]:offs[r] + n].reshape(shapes[r])
-        say("batched soft: oracle on ROI %d %s" % (r, shapes[r]))
-        exp = O.shape3d(p, sps[r])
-        check_features(out2[r], exp["features"], "soft ROI %d" % r)
-        eg = O.soft_grad(p, sps[r], gout[r])
+        eg = ref[r]["grad"]
         got = grad[offs[r]:offs[r] + n].reshape(shapes[r]).astype(np.float64)
         np.testing.assert_allclose(got, eg, rtol=2e-6, atol=2e-6 * np.abs(eg).max(), err_msg="soft ROI %d" % r)
