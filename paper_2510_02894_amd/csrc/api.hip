@@ -123,6 +123,10 @@ void* g_scratch[kMaxScratchDevices] = {};
 // Tile sizes of the pair pass for every device (results do not depend on them).
 Tuning g_tune = {8, 1024, 0, 1, 1};
 
+// Vertex count from which a ROI's 3D pairs are pruned: kPruneMinV for prune = 1,
+// every ROI with pairs for prune = 2.
+int prune_min_v() { return g_tune.prune == 2 ? 2 : kPruneMinV; }
+
 bool valid_tuning(const Tuning& t) {
   return (t.itile == 2 || t.itile == 4 || t.itile == 8) &&
          (t.jchunk == 64 || t.jchunk == 128 || t.jchunk == 256 || t.jchunk == 512 || t.jchunk == 1024) && t.blocks_per_cu >= 0 &&
@@ -501,6 +505,7 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   B.cu_count = cu_count;
   B.moments = Bt.moments;
   B.prune = false;
+  B.prune_min_v = prune_min_v();
   B.blkrec = P.as<BlkRec>(W_BLKREC);
   B.rseed = P.as<RoiSeed>(W_RSEED);
   B.pitems = P.as<PItem>(W_PITEM);
@@ -515,7 +520,7 @@ int launch_head(const Ptrs& P, const Batch& Bt, int dtype, hipStream_t st) {
                           P.as<BrickPart>(W_PART), Bt.moments ? 1 : 0, st));
   HIPCK(launch_mesh_totals(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, dtype, P.as<const BrickPart>(W_PART),
                            P.as<long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
-                           Bt.moments ? 1 : 0, st));
+                           Bt.moments ? 1 : 0, prune_min_v(), st));
   return SHAPE3D_OK;
 }
 
@@ -530,6 +535,7 @@ int launch_tail(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, int c
   PairBufs B = pair_bufs(P, Bt, dtype, S, cu_count);
   B.prune = g_tune.kernel == 1 &&
             (g_tune.prune == 2 || (g_tune.prune == 1 && (vmax_hint < 0 || vmax_hint >= kPruneMinV)));
+  B.prune_min_v = prune_min_v();
   HIPCK(launch_check_capacity(Bt.n(), S.rows0, P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
                               P.as<unsigned int>(W_COUNTERS) + 2, st));
   if (ev) HIPCK(hipEventRecord(ev[0], st));

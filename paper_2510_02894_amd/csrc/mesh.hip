@@ -606,19 +606,18 @@ __device__ inline __int128 wave_sum_i128(__int128 v) {
   return v;
 }
 
-// Covariance of the inside voxels' physical coordinates from exact integer
-// moments: cov_ij = s_i s_j (n S_ij - S_i S_j) / n^2, the numerator exact in
-// 128 bits (n < 2^40 voxels and coordinates < 2^20 keep it below 2^120).
-__device__ inline void moments_to_cov(const __int128* S, const double* sp, RoiMeta& M) {
+// Covariance entry k (zz, yy, xx, zy, zx, yx) of the inside voxels' physical
+// coordinates from exact integer moments S = (n, sums of z, y, x, of zz, yy,
+// xx, of zy, zx, yx): cov_ij = s_i s_j (n S_ij - S_i S_j) / n^2, the
+// numerator exact in 128 bits (n < 2^40 voxels and coordinates < 2^20 keep it
+// below 2^120).
+__device__ inline double cov_entry(const __int128* S, const double* sp, int k) {
+  const int i = k < 3 ? k : (k == 5 ? 1 : 0);
+  const int j = k < 3 ? k : (k == 3 ? 1 : 2);
   const __int128 n = S[0];
-  M.n_in = (long long)n;
-  const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-  const int sij[6] = {4, 5, 6, 7, 8, 9};
-  const double n2 = (double)n * (double)n;
-  for (int k = 0; k < 6; ++k) {
-    const __int128 c = n * S[sij[k]] - S[1 + ii[k]] * S[1 + jj[k]];
-    M.cov[k] = n > 0 ? (double)c / n2 * (sp[ii[k]] * sp[jj[k]]) : 0.0;
-  }
+  if (n <= 0) return 0.0;
+  const __int128 c = n * S[4 + k] - S[1 + i] * S[1 + j];
+  return (double)c / ((double)n * (double)n) * (sp[i] * sp[j]);
 }
 
 __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ rois, int n_rois, long long nbricks,
@@ -629,6 +628,7 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
   __shared__ double s_d[2][1024];
   __shared__ int s_b[6][1024];
   __shared__ __int128 s_m[10][16];
+  __shared__ __int128 s_S[10];
   const int r = blockIdx.x, tid = threadIdx.x;
   const Roi R = rois[r];
   const long long b0 = R.brick_begin, b1 = R.brick_end;
@@ -649,16 +649,6 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
       bb[k] = min(bb[k], P.bb[k]);
       bb[3 + k] = max(bb[3 + k], P.bb[3 + k]);
     }
-  }
-  if (moments) {
-    // exact moment sums: 128-bit per thread, per wave, then over the 16 waves
-    __int128 m[10];
-    for (int k = 0; k < 10; ++k) m[k] = 0;
-    for (long long b = lo; b < hi; ++b)
-      for (int k = 0; k < 10; ++k) m[k] += (__int128)part[b].mom[k];
-    for (int k = 0; k < 10; ++k) m[k] = wave_sum_i128(m[k]);
-    if ((tid & 63) == 0)
-      for (int k = 0; k < 10; ++k) s_m[k][tid >> 6] = m[k];
   }
   // exclusive scan of nv over threads (Hillis-Steele in shared memory)
   s_l[0][tid] = nv;
@@ -721,37 +711,61 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
     M.R2 = R2;
     M.n_in = 0;
     for (int k = 0; k < 6; ++k) M.cov[k] = 0.0;
-    if (moments) {
-      __int128 S[10];
-      for (int k = 0; k < 10; ++k) {
-        S[k] = 0;
-        for (int w = 0; w < 16; ++w) S[k] += s_m[k][w];
-      }
-      moments_to_cov(S, R.s, M);
-    }
     meta[r] = M;
   }
+  if (!moments) return;
+  // exact moment sums, last (few registers are live): 128-bit per thread, per
+  // wave, then over the 16 waves
+  {
+    __int128 m[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = 0;
+    for (long long b = lo; b < hi; ++b)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) m[k] += (__int128)part[b].mom[k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = wave_sum_i128(m[k]);
+    if ((tid & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < 10; ++k) s_m[k][tid >> 6] = m[k];
+  }
+  __syncthreads();
+  // thread k < 10 sums moment k over the waves, then thread k < 6 forms
+  // covariance entry k (one 128-bit product pair per thread)
+  if (tid < 10) {
+    __int128 v = 0;
+    for (int w = 0; w < 16; ++w) v += s_m[tid][w];
+    s_S[tid] = v;
+  }
+  __syncthreads();
+  if (tid < 6) meta[r].cov[tid] = cov_entry(s_S, rois[r].s, tid);
+  if (tid == 6) meta[r].n_in = (long long)s_S[0];
 }
 
 // Layout-0 row offsets of the ROIs (exclusive scan of V_pad) and the first
-// 1024-row column of each ROI's 3D segment in the pruning pass (exclusive
-// scan of ceil(V_pad / 1024) over ROIs with two or more vertices), one
-// workgroup.  totals: [0] layout-0 rows, [1] largest V, [7] pruning columns.
+// column pair of each pruned ROI (at least prune_min_v vertices) in the 3D
+// pruning pass (exclusive scan of ncol^2, ncol = ceil(V_pad / 1024)), one
+// workgroup.  totals: [0] layout-0 rows, [1] largest V, [7] column pairs.
 __global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restrict__ meta,
-                                                   long long* __restrict__ totals) {
+                                                   long long* __restrict__ totals, int prune_min_v) {
   __shared__ long long s[2][2][1024];
   const int tid = threadIdx.x;
   const int chunk = (n_rois + 1023) / 1024;
   const int lo = min(n_rois, chunk * tid), hi = min(n_rois, chunk * (tid + 1));
-  long long sum = 0, nsb = 0, vmax = 0;
+  auto npair = [&](const RoiMeta& M) -> long long {
+    if (M.V < 2 || M.V < prune_min_v) return 0;
+    const long long nc = (M.V_pad + kPruneSB * 32 - 1) / (kPruneSB * 32);
+    return nc * nc;
+  };
+  long long sum = 0, np = 0, vmax = 0;
   for (int r = lo; r < hi; ++r) {
     const RoiMeta& M = meta[r];
     sum += M.V_pad;
-    nsb += M.V >= 2 ? (M.V_pad + kPruneSB * 32 - 1) / (kPruneSB * 32) : 0;
+    np += npair(M);
     vmax = max(vmax, M.V);
   }
   s[0][0][tid] = sum;
-  s[1][0][tid] = nsb;
+  s[1][0][tid] = np;
   __syncthreads();
   int src = 0;
   for (int d = 1; d < 1024; d <<= 1) {
@@ -763,15 +777,15 @@ __global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restri
     __syncthreads();
     src = 1 - src;
   }
-  long long off = s[0][src][tid] - sum, soff = s[1][src][tid] - nsb;
+  long long off = s[0][src][tid] - sum, poff = s[1][src][tid] - np;
   for (int r = lo; r < hi; ++r) {
     RoiMeta& M = meta[r];
     M.row_off = off;
-    M.sb_off = soff;
+    M.prune_off = poff;
     off += M.V_pad;
-    soff += M.V >= 2 ? (M.V_pad + kPruneSB * 32 - 1) / (kPruneSB * 32) : 0;
+    poff += npair(M);
   }
-  const long long rows0 = s[0][src][1023], nsb_total = s[1][src][1023];
+  const long long rows0 = s[0][src][1023], np_total = s[1][src][1023];
   __syncthreads();
   s[0][0][tid] = vmax;
   __syncthreads();
@@ -782,7 +796,7 @@ __global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restri
   if (tid == 0) {
     totals[0] = rows0;
     totals[1] = s[0][0][0];
-    totals[7] = nsb_total;
+    totals[7] = np_total;
   }
 }
 
@@ -1057,10 +1071,11 @@ hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long n
 }
 
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
-                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, hipStream_t st) {
+                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, int prune_min_v,
+                              hipStream_t st) {
   hipLaunchKernelGGL(k_mesh_totals, dim3(n_rois), dim3(1024), 0, st, rois, n_rois, nbricks, dtype, part, brick_voff,
                      meta, moments);
-  hipLaunchKernelGGL(k_roi_rows, dim3(1), dim3(1024), 0, st, n_rois, meta, totals);
+  hipLaunchKernelGGL(k_roi_rows, dim3(1), dim3(1024), 0, st, n_rois, meta, totals, prune_min_v);
   return hipGetLastError();
 }
 

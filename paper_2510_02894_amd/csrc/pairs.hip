@@ -206,11 +206,12 @@ __global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long l
 
 // Columns (chunks of jchunk row blocks) per segment; also clears the item
 // counts of all col_cap columns (k_col_fill sets those of the real ones).
-// With prune set, the 3D segments are left out (the pruned item list covers
-// them) unless that list overflowed (counters[4]).
+// With prune set, the pruned ROIs' 3D segments are left out (the pruned item
+// list covers them) unless that list overflowed (counters[4]).
 __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __restrict__ totals,
-                           const Seg* __restrict__ segs, long long* __restrict__ ncol, int jchunk, int small_rows,
-                           long long* __restrict__ nitem, long long col_cap, int prune,
+                           const Seg* __restrict__ segs, const RoiMeta* __restrict__ meta,
+                           long long* __restrict__ ncol, int jchunk, int small_rows,
+                           long long* __restrict__ nitem, long long col_cap, int prune, int prune_min_v,
                            const unsigned int* __restrict__ counters) {
   const long long nseg = n_rois + totals[T_NSEG2D];
   const bool skip3d = prune && counters[4] == 0u;
@@ -221,7 +222,7 @@ __global__ void k_seg_cols(int n_rois, long long seg_cap, const long long* __res
        s += (long long)gridDim.x * blockDim.x) {
     long long rows = s < nseg ? segs[s].n_rows : 0;
     if (s >= n_rois && rows <= small_rows) rows = 0;  // a small bucket: k_pair_small_h
-    if (s < n_rois && skip3d) rows = 0;               // a 3D segment: k_pair_list_h
+    if (s < n_rois && skip3d && meta[s].V >= prune_min_v) rows = 0;  // a pruned 3D segment: k_pair_list_h
     ncol[s] = (rows + (long long)jchunk * kBlk - 1) / ((long long)jchunk * kBlk);
   }
 }
@@ -1006,8 +1007,9 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
                      B.pairs2d);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(std::max(B.seg_cap, B.col_cap))), dim3(256), 0, st, B.n_rois,
-                     B.seg_cap, B.totals, B.segs, B.ncol, B.tune.jchunk, small_buckets(B) ? kSmallBlocks * 32 : 0,
-                     B.nitem, B.col_cap, B.prune ? 1 : 0, B.counters);
+                     B.seg_cap, B.totals, B.segs, B.meta, B.ncol, B.tune.jchunk,
+                     small_buckets(B) ? kSmallBlocks * 32 : 0, B.nitem, B.col_cap, B.prune ? 1 : 0, B.prune_min_v,
+                     B.counters);
   if ((e = launch_scan(B.ncol, B.colbase, B.seg_cap, B.totals + T_NCOL, B.scan_tmp, st))) return e;
   hipLaunchKernelGGL(k_col_fill, dim3(grid_for(B.seg_cap)), dim3(256), 0, st, B.n_rois, B.seg_cap, B.totals, B.segs,
                      B.meta, B.ncol, B.colbase, B.cols, B.nitem, B.tune.itile, B.tune.jchunk);

@@ -3,28 +3,38 @@
 // The paper computes the maximum vertex distance by brute force over all
 // pairs (Sec. 2, "Parallel diameter calculation").  The maximum itself is all
 // that is needed, so a pair whose distance provably stays below a distance
-// that some pair reaches can be skipped.  Per ROI:
+// that some pair reaches can be skipped.  Per ROI with at least `min_v`
+// vertices (smaller ROIs stay with the all-pairs work list):
 //   1. bounds: every 32-row block of the ROI's vertex rows gets the bounding
-//      box of its (centred FP32) positions;
+//      box of its (centred FP32) positions, and so does every row tile (the
+//      pair pass's IT blocks) and every 1024-row column (kPruneSB blocks);
 //   2. a lower bound L on the diameter: seven seed vertices (the extremes
 //      along +-x, +-y, +-z and the vertex farthest from the box centre), the
 //      vertex farthest from each seed, and the vertex farthest from each of
 //      those (two farthest-point sweeps); L^2 is the largest squared distance
 //      met, i.e. the distance of an actual vertex pair, so L <= D;
-//   3. work items: for each row tile (IT blocks) and each column of 32 blocks
-//      of the upper triangle, the tile's box is tested against the column's
-//      box, then against each block's box; the largest distance between two
-//      boxes bounds every pair between them, and tiles whose bound is below
-//      L^2 (1 - 2^-10) are dropped.  Each surviving (tile, column) becomes
-//      one item covering its first to last surviving block.
+//   3. work items: every pair of columns (i <= j) is tested by the largest
+//      distance between their boxes; for a pair that can reach
+//      thr = L^2 (1 - 2^-10), each row tile of column i is tested against each
+//      block of column j (the largest distance between two boxes bounds every
+//      pair between them), and each tile with a surviving block becomes one
+//      item covering its first to last surviving block.
 // The matrix-core pair pass then runs only these items.  Every pair at the
-// maximum distance D >= L lies in a surviving item, so the row maxima of the
-// rows that hold a maximising pair, the group maximum, and hence the rows
-// handed to the exact FP64 refinement, which rescans them against all vertices,
-// are those of the full pass: the result is the exact maximum and the same
-// canonical pair.  The margin 2^-10 covers the FP32 rounding of positions,
-// boxes and L^2 (about 2^-20 relative) many times over.
+// maximum distance D >= L lies in a surviving item (a column pair's boxes
+// contain its tiles' and blocks' boxes, so the coarse test never drops a tile
+// that the fine test keeps), so the row maxima of the rows that hold a
+// maximising pair, the group maximum, and hence the rows handed to the exact
+// FP64 refinement, which rescans them against all vertices, are those of the
+// full pass: the result is the exact maximum and the same canonical pair.
+// The margin 2^-10 covers the FP32 rounding of positions, boxes and L^2
+// (about 2^-20 relative) many times over.
+//
+// Seed keys are reduced in block-major chunks (one atomic per wave, ROI and
+// key), and the column-pair tests run in a persistent grid over all pruned
+// ROIs' column pairs.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "s3d_device.h"
 #include "s3d_launch.h"
@@ -33,7 +43,7 @@ namespace s3d {
 
 namespace {
 
-enum { T_ROWS0 = 0, T_NSB = 7 };
+enum { T_ROWS0 = 0, T_NPAIR = 7 };
 
 // Monotone map of a float to an unsigned int (larger float, larger integer).
 __device__ inline unsigned int ord_bits(float v) {
@@ -71,28 +81,6 @@ __device__ inline void row_pos(const float* __restrict__ pos, const uint4* __res
   }
 }
 
-// Maximum over the 32 lanes of a half wave.
-__device__ inline float half_max(float v) {
-#pragma unroll
-  for (int m = 1; m < 32; m <<= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
-  return v;
-}
-
-__device__ inline float half_min(float v) {
-#pragma unroll
-  for (int m = 1; m < 32; m <<= 1) v = fminf(v, __shfl_xor(v, m, 64));
-  return v;
-}
-
-__device__ inline unsigned long long half_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int m = 1; m < 32; m <<= 1) {
-    const unsigned long long o = __shfl_xor(v, m, 64);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
 // Largest squared distance between a point of box a and a point of box b.
 __device__ inline float box_far2(const float* a, const float* b) {
   float s = 0.0f;
@@ -104,237 +92,350 @@ __device__ inline float box_far2(const float* a, const float* b) {
   return s;
 }
 
-// The ROI of a layout-0 row, and whether its 3D segment has pairs.
+// Whether a ROI's 3D pairs are pruned (else they stay in the all-pairs work list).
+__device__ inline bool pruned_roi(const RoiMeta& M, int min_v) { return M.V >= 2 && M.V >= min_v; }
+
+// The ROI of a layout-0 row, and whether it is pruned.
 struct RowRoi {
   int roi;
   bool on;
 };
 
-__device__ inline RowRoi row_roi(const int* __restrict__ blkseg, const RoiMeta* __restrict__ meta, long long row) {
+__device__ inline RowRoi row_roi(const int* __restrict__ blkseg, const RoiMeta* __restrict__ meta, long long row,
+                                 int min_v) {
   RowRoi r;
   r.roi = blkseg[row >> 4];
-  r.on = meta[r.roi].V >= 2;
+  r.on = pruned_roi(meta[r.roi], min_v);
   return r;
 }
 
+// Rows per lane in the row passes: a 32-row block is held by 4 lanes, so its
+// box and keys need two shuffle steps (a wave covers 512 rows).
+constexpr int kRowsPerLane = 8;
+
+__device__ inline float quad_min(float v) {
+  v = fminf(v, __shfl_xor(v, 1, 64));
+  return fminf(v, __shfl_xor(v, 2, 64));
+}
+
+__device__ inline float quad_max(float v) {
+  v = fmaxf(v, __shfl_xor(v, 1, 64));
+  return fmaxf(v, __shfl_xor(v, 2, 64));
+}
+
+__device__ inline unsigned long long quad_max_u64(unsigned long long v) {
+  unsigned long long o = __shfl_xor(v, 1, 64);
+  v = o > v ? o : v;
+  o = __shfl_xor(v, 2, 64);
+  return o > v ? o : v;
+}
+
 // Pass 1: per 32-row block, its box and its seed keys (largest x, y, z, -x,
-// -y, -z and |p|^2).  The first row of each ROI also clears its seed record.
+// -y, -z and |p|^2).  The first row of each pruned ROI also clears its seed
+// record (the reduction passes take atomic maxima into it).
 __global__ __launch_bounds__(256) void k_prune_box(const float* __restrict__ pos, const uint4* __restrict__ posh,
                                                    const RoiMeta* __restrict__ meta, const int* __restrict__ blkseg,
-                                                   const long long* __restrict__ totals, BlkRec* __restrict__ rec,
-                                                   RoiSeed* __restrict__ seed) {
+                                                   const long long* __restrict__ totals, int min_v,
+                                                   BlkRec* __restrict__ rec, RoiSeed* __restrict__ seed) {
   const long long rows0 = totals[T_ROWS0];
   const int lane = threadIdx.x & 63;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < rows0;
-       base += nwaves * 64) {
-    const long long row = base + lane;
-    const bool valid = row < rows0;  // uniform per half wave (rows0 is a multiple of 32)
+  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kRowsPerLane);
+       base < rows0; base += nwaves * 64 * kRowsPerLane) {
+    const long long r0 = base + (long long)lane * kRowsPerLane;  // this lane's rows (one 32-row block)
     RowRoi rr = {0, false};
-    if (valid) rr = row_roi(blkseg, meta, row);
-    float p[3] = {0.0f, 0.0f, 0.0f};
+    if (r0 < rows0) rr = row_roi(blkseg, meta, r0, min_v);  // uniform per block (rows0 is a multiple of 32)
+    float box[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
+    unsigned long long key[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     if (rr.on) {
       const RoiMeta& M = meta[rr.roi];
-      row_pos(pos, posh, row, h_scale_exp(M.R2), p);
-      if (row == M.row_off) {
-        RoiSeed z;
-        for (int s = 0; s < 3; ++s)
-          for (int c = 0; c < 7; ++c) z.key[s][c] = 0ull;
-        seed[rr.roi] = z;
+      const int e = h_scale_exp(M.R2);
+      if (r0 == M.row_off) {
+        for (int q = 0; q < 3; ++q)
+          for (int c = 0; c < 7; ++c) seed[rr.roi].key[q][c] = 0ull;
+      }
+      float p[kRowsPerLane][3];
+#pragma unroll
+      for (int i = 0; i < kRowsPerLane; ++i) row_pos(pos, posh, r0 + i, e, p[i]);
+#pragma unroll
+      for (int i = 0; i < kRowsPerLane; ++i) {
+        const float val[7] = {p[i][0], p[i][1], p[i][2], -p[i][0], -p[i][1], -p[i][2],
+                              p[i][0] * p[i][0] + p[i][1] * p[i][1] + p[i][2] * p[i][2]};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          box[c] = fminf(box[c], p[i][c]);
+          box[3 + c] = fmaxf(box[3 + c], p[i][c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          const unsigned long long k = vkey(val[c], r0 + i);
+          key[c] = k > key[c] ? k : key[c];
+        }
       }
     }
-    float box[6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      box[c] = half_min(rr.on ? p[c] : 3.0e38f);
-      box[3 + c] = half_max(rr.on ? p[c] : -3.0e38f);
+      box[c] = quad_min(box[c]);
+      box[3 + c] = quad_max(box[3 + c]);
     }
-    const float val[7] = {p[0], p[1], p[2], -p[0], -p[1], -p[2], p[0] * p[0] + p[1] * p[1] + p[2] * p[2]};
-    unsigned long long key[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) key[c] = half_max_u64(rr.on ? vkey(val[c], row) : 0ull);
-    if (rr.on && (lane & 31) == 0) {
-      BlkRec R;
+    for (int c = 0; c < 7; ++c) key[c] = quad_max_u64(key[c]);
+    if (rr.on && (lane & 3) == 0) {
+      BlkRec& R = rec[r0 >> 5];
 #pragma unroll
       for (int c = 0; c < 6; ++c) R.box[c] = box[c];
-      R.pad_[0] = R.pad_[1] = 0;
 #pragma unroll
       for (int c = 0; c < 7; ++c) R.key[c] = key[c];
-      rec[row >> 5] = R;
     }
   }
 }
 
-// Passes 2, 4, 6: per ROI, the maximum of each block key into seed slot
-// `slot`.  A wave takes 64 consecutive blocks and issues one atomic per key
-// and per distinct ROI among them (usually one).
-__global__ __launch_bounds__(256) void k_prune_reduce(const BlkRec* __restrict__ rec, const RoiMeta* __restrict__ meta,
+// Passes 2, 4, 6: the maxima of the blocks' keys per ROI into seed slot
+// `slot`.  A wave takes 512 consecutive blocks (8 per lane); each lane keeps
+// the maxima of its blocks per ROI (a pruned ROI has at least 512 blocks
+// unless pruning is forced, so a lane meets at most two), and the lanes that
+// end on the same ROI combine theirs before one atomic per key.  With BOXES
+// (pass 2) the lanes also write the box of every row tile (it_blocks blocks)
+// and every column (kPruneSB blocks) that starts among their blocks.
+constexpr int kRedPerLane = 8;
+
+__device__ inline void seed_max(RoiSeed* seed, int roi, int slot, const unsigned long long* k) {
+#pragma unroll
+  for (int c = 0; c < 7; ++c)
+    if (k[c]) atomicMax(&seed[roi].key[slot][c], k[c]);
+}
+
+template <bool BOXES>
+__global__ __launch_bounds__(256) void k_prune_reduce(BlkRec* __restrict__ rec, const RoiMeta* __restrict__ meta,
                                                       const int* __restrict__ blkseg,
-                                                      const long long* __restrict__ totals, RoiSeed* __restrict__ seed,
-                                                      int slot) {
+                                                      const long long* __restrict__ totals, int min_v,
+                                                      RoiSeed* __restrict__ seed, int slot, int it_blocks) {
   const long long nblk = totals[T_ROWS0] / 32;
   const int lane = threadIdx.x & 63;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < nblk;
-       base += nwaves * 64) {
-    const long long blk = base + lane;
-    int g = -1;
-    if (blk < nblk) {
-      const RowRoi rr = row_roi(blkseg, meta, blk * 32);
-      if (rr.on) g = rr.roi;
-    }
-    unsigned long long todo = __ballot(g >= 0);
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int gl = __shfl(g, leader, 64);
-      const unsigned long long same = __ballot(g == gl) & todo;
+  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kRedPerLane);
+       base < nblk; base += nwaves * 64 * kRedPerLane) {
+    const long long b0 = base + (long long)lane * kRedPerLane;
+    int cur = -1;
+    unsigned long long k[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    for (int q = 0; q < kRedPerLane; ++q) {
+      const long long blk = b0 + q;
+      if (blk >= nblk) break;
+      const int roi = blkseg[2 * blk];
+      const RoiMeta& M = meta[roi];
+      if (!pruned_roi(M, min_v)) continue;
+      if (roi != cur) {
+        if (cur >= 0) seed_max(seed, cur, slot, k);
+        cur = roi;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) k[c] = 0ull;
+      }
 #pragma unroll
       for (int c = 0; c < 7; ++c) {
-        unsigned long long v = g == gl ? rec[blk].key[c] : 0ull;
+        const unsigned long long v = rec[blk].key[c];
+        k[c] = v > k[c] ? v : k[c];
+      }
+      if (BOXES) {
+        const long long rb = M.row_off / 32;
+        const int nb = (int)(M.V_pad / 32), rel = (int)(blk - rb);
+        if (rel % it_blocks == 0 || rel % kPruneSB == 0) {
+          const int n = rel % kPruneSB == 0 ? kPruneSB : it_blocks;
+          float tb[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
+          float cb[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
+          for (int u = 0; u < n && rel + u < nb; ++u) {
+            float* bx = u < it_blocks ? tb : cb;
+            for (int c = 0; c < 3; ++c) {
+              const float lo = rec[blk + u].box[c], hi = rec[blk + u].box[3 + c];
+              bx[c] = fminf(bx[c], lo);
+              bx[3 + c] = fmaxf(bx[3 + c], hi);
+            }
+          }
+          // the column box also covers the tile's blocks
+          for (int c = 0; c < 3; ++c) {
+            cb[c] = fminf(cb[c], tb[c]);
+            cb[3 + c] = fmaxf(cb[3 + c], tb[3 + c]);
+          }
+          if (rel % it_blocks == 0)
+            for (int c = 0; c < 6; ++c) rec[blk].tbox[c] = tb[c];
+          if (rel % kPruneSB == 0)
+            for (int c = 0; c < 6; ++c) rec[blk].cbox[c] = cb[c];
+        }
+      }
+    }
+    // lanes ending on the same ROI combine their maxima (one atomic per key)
+    unsigned long long todo = __ballot(cur >= 0);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int gl = __shfl(cur, leader, 64);
+      const unsigned long long same = __ballot(cur == gl) & todo;
+      unsigned long long v[7];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) {
+        v[c] = cur == gl ? k[c] : 0ull;
 #pragma unroll
         for (int m = 1; m < 64; m <<= 1) {
-          const unsigned long long o = __shfl_xor(v, m, 64);
-          v = o > v ? o : v;
+          const unsigned long long o = __shfl_xor(v[c], m, 64);
+          v[c] = o > v[c] ? o : v[c];
         }
-        if (lane == leader) atomicMax(&seed[gl].key[slot][c], v);
       }
+      if (lane == leader) seed_max(seed, gl, slot, v);
       todo &= ~same;
     }
   }
+}
+
+// Threshold of the tile test for ROI r: L^2 (1 - 2^-10), L^2 the largest
+// squared distance the two farthest-point sweeps met (seed slots 1 and 2).
+__device__ inline float prune_threshold(const RoiSeed* __restrict__ seed, int r) {
+  float L2 = 0.0f;
+#pragma unroll
+  for (int q = 1; q < 3; ++q)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) L2 = fmaxf(L2, ord_float((unsigned int)(seed[r].key[q][c] >> 32)));
+  return L2 * (1.0f - 0.0009765625f);
 }
 
 // Passes 3, 5: per block, the packed maxima over its rows of the squared
 // distance to each of the seven vertices in seed slot `src` of its ROI.
 __global__ __launch_bounds__(256) void k_prune_far(const float* __restrict__ pos, const uint4* __restrict__ posh,
                                                    const RoiMeta* __restrict__ meta, const int* __restrict__ blkseg,
-                                                   const long long* __restrict__ totals,
+                                                   const long long* __restrict__ totals, int min_v,
                                                    const RoiSeed* __restrict__ seed, int src,
                                                    BlkRec* __restrict__ rec) {
   const long long rows0 = totals[T_ROWS0];
   const int lane = threadIdx.x & 63;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < rows0;
-       base += nwaves * 64) {
-    const long long row = base + lane;
+  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kRowsPerLane);
+       base < rows0; base += nwaves * 64 * kRowsPerLane) {
+    const long long r0 = base + (long long)lane * kRowsPerLane;
     RowRoi rr = {0, false};
-    if (row < rows0) rr = row_roi(blkseg, meta, row);
-    unsigned long long key[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) key[c] = 0ull;
+    if (r0 < rows0) rr = row_roi(blkseg, meta, r0, min_v);
+    unsigned long long key[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     if (rr.on) {
       const int e = h_scale_exp(meta[rr.roi].R2);
-      float p[3];
-      row_pos(pos, posh, row, e, p);
+      float q[7][3];
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        float q[3];
-        row_pos(pos, posh, key_row(seed[rr.roi].key[src][c]), e, q);
-        const float dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
-        key[c] = vkey(dx * dx + dy * dy + dz * dz, row);
-      }
+      for (int c = 0; c < 7; ++c) row_pos(pos, posh, key_row(seed[rr.roi].key[src][c]), e, q[c]);
+      float p[kRowsPerLane][3];
+#pragma unroll
+      for (int i = 0; i < kRowsPerLane; ++i) row_pos(pos, posh, r0 + i, e, p[i]);
+#pragma unroll
+      for (int i = 0; i < kRowsPerLane; ++i)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          const float dx = p[i][0] - q[c][0], dy = p[i][1] - q[c][1], dz = p[i][2] - q[c][2];
+          const unsigned long long k = vkey(dx * dx + dy * dy + dz * dz, r0 + i);
+          key[c] = k > key[c] ? k : key[c];
+        }
     }
 #pragma unroll
-    for (int c = 0; c < 7; ++c) key[c] = half_max_u64(key[c]);
-    if (rr.on && (lane & 31) == 0) {
+    for (int c = 0; c < 7; ++c) key[c] = quad_max_u64(key[c]);
+    if (rr.on && (lane & 3) == 0) {
 #pragma unroll
-      for (int c = 0; c < 7; ++c) rec[row >> 5].key[c] = key[c];
+      for (int c = 0; c < 7; ++c) rec[r0 >> 5].key[c] = key[c];
     }
   }
 }
 
-// Pass 7: one wave per (ROI, column of kPruneSB blocks); lanes run over the
-// row tiles of the upper triangle that start before the column ends.
+// Pass 7: the work items.  A persistent grid runs over the column pairs
+// (i, j) of all pruned ROIs (ROI r owns ncol^2 consecutive indices from
+// meta[r].prune_off; pairs with i > j are skipped): each lane tests one
+// column pair by its columns' boxes, then every surviving pair is expanded by
+// the whole wave: lane l tests row tile l / LPT of column i against LPT
+// consecutive blocks of column j, and each tile with a surviving block
+// becomes an item over its first to last surviving block.
 template <int IT>
 __global__ __launch_bounds__(256) void k_prune_items(const BlkRec* __restrict__ rec, const RoiMeta* __restrict__ meta,
                                                      int n_rois, const long long* __restrict__ totals,
                                                      const RoiSeed* __restrict__ seed, PItem* __restrict__ items,
                                                      long long cap, unsigned int* __restrict__ counters) {
+  constexpr int TPC = kPruneSB / IT;   // row tiles per column
+  constexpr int LPT = 64 / TPC;        // lanes per tile
+  constexpr int BPL = kPruneSB / LPT;  // column blocks per lane
+  static_assert(TPC * IT == kPruneSB && LPT * TPC == 64 && BPL * LPT == kPruneSB, "tile and wave shapes");
+  const long long total = totals[T_NPAIR];
   const int lane = threadIdx.x & 63;
-  const long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= totals[T_NSB]) return;  // whole waves leave; the kernel has no barrier
-  int lo = 0, hi = n_rois - 1;     // the last ROI whose first column is <= w
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (meta[mid].sb_off <= w)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const RoiMeta& M = meta[lo];
-  const int nb = (int)(M.V_pad / 32);
-  const long long rb = M.row_off / 32;
-  const int c0 = (int)(w - M.sb_off) * kPruneSB;
-  const int c1 = min(c0 + kPruneSB, nb);
-  const int e = h_scale_exp(M.R2);
-  float L2 = 0.0f;
-  for (int s = 1; s < 3; ++s)
-    for (int c = 0; c < 7; ++c) L2 = fmaxf(L2, ord_float((unsigned int)(seed[lo].key[s][c] >> 32)));
-  const float thr = L2 * (1.0f - 0.0009765625f);  // 1 - 2^-10
-  // the column's box (its blocks' boxes are read again, from cache, by the
-  // tiles that pass the column test)
-  float cb[6];
-  {
-    float b[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
-    if (lane < c1 - c0) {
-      const BlkRec& R = rec[rb + c0 + lane];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) b[c] = R.box[c];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float mn = b[c], mx = b[3 + c];
-#pragma unroll
-      for (int m = 1; m < 64; m <<= 1) {
-        mn = fminf(mn, __shfl_xor(mn, m, 64));
-        mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  int thr_roi = -1;
+  float thr_val = 0.0f;
+  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < total;
+       base += nwaves * 64) {
+    const long long idx = base + lane;
+    bool pass = false;
+    int r = 0, ci = 0, cj = 0;
+    float thr_r = 0.0f;
+    if (idx < total) {
+      int lo = 0, hi = n_rois - 1;  // the last ROI whose first column pair is <= idx
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (meta[mid].prune_off <= idx)
+          lo = mid;
+        else
+          hi = mid - 1;
       }
-      cb[c] = mn;
-      cb[3 + c] = mx;
+      r = lo;
+      const RoiMeta& M = meta[r];
+      const int nb = (int)(M.V_pad / 32);
+      const int ncol = (nb + kPruneSB - 1) / kPruneSB;
+      const long long local = idx - M.prune_off;
+      ci = (int)(local / ncol);
+      cj = (int)(local - (long long)ci * ncol);
+      if (ci <= cj) {
+        if (r != thr_roi) {  // the threshold of the lane's last ROI is kept
+          thr_roi = r;
+          thr_val = prune_threshold(seed, r);
+        }
+        thr_r = thr_val;
+        const long long rb = M.row_off / 32;
+        pass = box_far2(rec[rb + ci * kPruneSB].cbox, rec[rb + cj * kPruneSB].cbox) >= thr_r;
+      }
     }
-  }
-  const int ntile = min((c1 + IT - 1) / IT, (nb + IT - 1) / IT);  // tiles with i0 < c1
-  for (int t0 = 0; t0 < ntile; t0 += 64) {
-    const int t = t0 + lane;
-    int jf = -1, jl = -1;
-    const int i0 = t * IT;
-    if (t < ntile) {
-      float tb[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
-      for (int r = 0; r < IT && i0 + r < nb; ++r) {
-        const BlkRec& R = rec[rb + i0 + r];
+    unsigned long long todo = __ballot(pass);
+    while (todo) {
+      const int srcl = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const int rr = __shfl(r, srcl, 64), i = __shfl(ci, srcl, 64), j = __shfl(cj, srcl, 64);
+      const float thr = __shfl(thr_r, srcl, 64);
+      const RoiMeta& M = meta[rr];
+      const int nb = (int)(M.V_pad / 32);
+      const long long rb = M.row_off / 32;
+      const int t = lane / LPT, g = lane % LPT;
+      const int i0 = i * kPruneSB + t * IT;     // the tile's first block
+      const int jb0 = j * kPruneSB + g * BPL;   // this lane's first block of column j
+      unsigned int bits = 0u;                   // surviving blocks of column j (bit = block - j * kPruneSB)
+      if (i0 < nb) {
+        float tb[6];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          tb[c] = fminf(tb[c], R.box[c]);
-          tb[3 + c] = fmaxf(tb[3 + c], R.box[3 + c]);
+        for (int c = 0; c < 6; ++c) tb[c] = rec[rb + i0].tbox[c];
+#pragma unroll
+        for (int q = 0; q < BPL; ++q) {
+          const int jj = jb0 + q;
+          if (jj < nb && jj >= i0 && box_far2(tb, rec[rb + jj].box) >= thr) bits |= 1u << (g * BPL + q);
         }
       }
-      if (box_far2(tb, cb) >= thr) {
-        for (int j = max(c0, i0); j < c1; ++j)
-          if (box_far2(tb, rec[rb + j].box) >= thr) {
-            if (jf < 0) jf = j;
-            jl = j;
-          }
-      }
-    }
-    const bool emit = jf >= 0;
-    const unsigned long long m = __ballot(emit);
-    if (!m) continue;
-    unsigned int first = 0;
-    if (lane == 0) first = atomicAdd(&counters[3], (unsigned int)__popcll(m));
-    first = __shfl(first, 0, 64);
-    if (emit) {
-      const long long idx = (long long)first + __popcll(m & ((1ull << lane) - 1ull));
-      if (idx < cap) {
-        PItem P;
-        P.rb = (int)rb;
-        P.nb = nb;
-        P.i0 = i0;
-        P.j0 = jf;
-        P.j1 = jl + 1;
-        P.e = e;
-        P.pad_[0] = P.pad_[1] = 0;
-        items[idx] = P;
-      } else {
-        counters[4] = 1u;  // the list is incomplete: the 3D pairs run unpruned
+#pragma unroll
+      for (int m = 1; m < LPT; m <<= 1) bits |= __shfl_xor(bits, m, 64);
+      const bool emit = g == 0 && bits != 0u;
+      const unsigned long long em = __ballot(emit);
+      if (!em) continue;
+      unsigned int first = 0;
+      if (lane == 0) first = atomicAdd(&counters[3], (unsigned int)__popcll(em));
+      first = __shfl(first, 0, 64);
+      if (emit) {
+        const long long slot = (long long)first + __popcll(em & ((1ull << lane) - 1ull));
+        if (slot < cap) {
+          PItem P;
+          P.rb = (int)rb;
+          P.nb = nb;
+          P.i0 = i0;
+          P.j0 = j * kPruneSB + (__ffs(bits) - 1);
+          P.j1 = j * kPruneSB + (32 - __clz(bits));
+          P.e = h_scale_exp(M.R2);
+          P.pad_[0] = P.pad_[1] = 0;
+          items[slot] = P;
+        } else {
+          counters[4] = 1u;  // the list is incomplete: the pruned ROIs' 3D pairs run unpruned
+        }
       }
     }
   }
@@ -352,19 +453,22 @@ unsigned grid_rows(long long n, long long cap = 4096) {
 hipError_t launch_prune(const PairBufs& B, hipStream_t st) {
   const float* pos = B.tune.kernel == 1 ? nullptr : B.pos;
   const uint4* posh = B.tune.kernel == 1 ? B.posh : nullptr;
-  const unsigned g = grid_rows(B.rows0);
-  hipLaunchKernelGGL(k_prune_box, dim3(g), dim3(256), 0, st, pos, posh, B.meta, B.blkseg, B.totals, B.blkrec, B.rseed);
-  const unsigned gb = grid_rows(B.rows0 / 32 + 1, 1024);
-  hipLaunchKernelGGL(k_prune_reduce, dim3(gb), dim3(256), 0, st, B.blkrec, B.meta, B.blkseg, B.totals, B.rseed, 0);
+  const int it_blocks = B.tune.itile == 8 ? 4 : 2;
+  const unsigned g = grid_rows((B.rows0 + kRowsPerLane - 1) / kRowsPerLane);
+  const unsigned gb = grid_rows((B.rows0 / 32 + kRedPerLane - 1) / kRedPerLane + 1, 1024);
+  hipLaunchKernelGGL(k_prune_box, dim3(g), dim3(256), 0, st, pos, posh, B.meta, B.blkseg, B.totals, B.prune_min_v,
+                     B.blkrec, B.rseed);
+  hipLaunchKernelGGL(k_prune_reduce<true>, dim3(gb), dim3(256), 0, st, B.blkrec, B.meta, B.blkseg, B.totals,
+                     B.prune_min_v, B.rseed, 0, it_blocks);
   for (int s = 1; s < 3; ++s) {
-    hipLaunchKernelGGL(k_prune_far, dim3(g), dim3(256), 0, st, pos, posh, B.meta, B.blkseg, B.totals, B.rseed, s - 1,
-                       B.blkrec);
-    hipLaunchKernelGGL(k_prune_reduce, dim3(gb), dim3(256), 0, st, B.blkrec, B.meta, B.blkseg, B.totals, B.rseed, s);
+    hipLaunchKernelGGL(k_prune_far, dim3(g), dim3(256), 0, st, pos, posh, B.meta, B.blkseg, B.totals, B.prune_min_v,
+                       B.rseed, s - 1, B.blkrec);
+    hipLaunchKernelGGL(k_prune_reduce<false>, dim3(gb), dim3(256), 0, st, B.blkrec, B.meta, B.blkseg, B.totals,
+                       B.prune_min_v, B.rseed, s, it_blocks);
   }
-  // waves: at most one column per 1024 rows plus one partial column per ROI
-  const long long waves = B.rows0 / (kPruneSB * 32) + B.n_rois + 1;
-  const unsigned gi = (unsigned)((waves + 3) / 4);
-  if (B.tune.itile == 8)
+  // a persistent grid over the column pairs (their count is known on the device only)
+  const unsigned gi = (unsigned)std::max(1, B.cu_count * 8);
+  if (it_blocks == 4)
     hipLaunchKernelGGL(k_prune_items<4>, dim3(gi), dim3(256), 0, st, B.blkrec, B.meta, B.n_rois, B.totals, B.rseed,
                        B.pitems, B.pitem_cap, B.counters);
   else

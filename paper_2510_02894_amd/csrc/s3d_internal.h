@@ -37,7 +37,7 @@ constexpr int kWorkStride = 32;     // words between two work counters (one 128-
 constexpr int kCounterWords = kWorkStride * (1 + 2 * kWorkParts);
 constexpr int kListCounters = kWorkStride * (1 + kWorkParts);  // first work counter of the pruned 3D pass
 constexpr int kPruneSB = 32;          // 32-row blocks per column of the 3D pruning pass (1024 rows)
-constexpr int kPruneMinV = 16384;     // below this largest vertex count a call runs the 3D pairs unpruned
+constexpr int kPruneMinV = 16384;     // ROIs with fewer vertices run their 3D pairs unpruned (prune = 1)
 
 // Key of a vertex: edge (u, u + e_a): bits 0..19 u2+1, 20..39 u1+1, 40..59 u0+1, 60..61 a.
 __host__ __device__ inline uint64_t pack_key(int u0, int u1, int u2, int a) {
@@ -142,7 +142,7 @@ struct RoiMeta {
   double center[3];   // subtracted from positions before rounding to FP32
   double R2;          // bound on |centred FP32 position|^2
   int bb[6];
-  long long sb_off;   // first 1024-row column of the ROI's 3D segment in the pruning pass
+  long long prune_off;  // first (column, column) pair of the ROI in the pruning pass (pruned ROIs)
   long long n_in;     // inside voxels (when moments are asked for)
   double cov[6];      // covariance of their physical coordinates: zz, yy, xx, zy, zx, yx
 };
@@ -169,6 +169,8 @@ struct BlkRec {
   float box[6];                 // lo x, y, z, hi x, y, z
   int pad_[2];
   unsigned long long key[7];    // (ordered float bits << 32) | (0xffffffff - row)
+  float tbox[6];                // the box of the row tile starting at this block (tile starts only)
+  float cbox[6];                // the box of the 1024-row column starting at this block (column starts only)
 };
 
 struct RoiSeed {

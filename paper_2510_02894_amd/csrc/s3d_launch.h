@@ -28,8 +28,10 @@ size_t mesh_lds_bytes(int max_G);
 // moments: also sum the inside voxels' moments (BrickPart.mom, RoiMeta.n_in/cov).
 hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                              double* case_area, BrickPart* part, int moments, hipStream_t st);
+// prune_min_v: ROIs with at least this many vertices get the pruning pass's column-pair offsets.
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
-                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, hipStream_t st);
+                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, int prune_min_v,
+                              hipStream_t st);
 hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
                                  unsigned int* overflow, hipStream_t st);
 hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
@@ -109,6 +111,7 @@ struct PairBufs {
   // 3D pruning (prune.hip), kernel 1 only: when `prune` is set the 3D
   // segments run from the pruned item list instead of the work list
   bool prune;
+  int prune_min_v;         // ROIs with at least this many vertices are pruned, the others run all pairs
   BlkRec* blkrec;          // [rows0 / 32] per 32-row block of layout 0
   RoiSeed* rseed;          // [n_rois]
   PItem* pitems;           // [pitem_cap]
