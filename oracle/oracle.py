@@ -304,3 +304,42 @@ def decode_ids(ids: np.ndarray, dims):
     u1 = lin % (d[1] + 2) - 1
     u0 = lin // (d[1] + 2) - 1
     return np.stack([u0, u1, u2], axis=1), a
+
+
+def label_rois(labels: np.ndarray, max_label: int, spacing=(1.0, 1.0, 1.0)):
+    """Input preprocessing of a uint8 label map (the paper's open problem of
+    staging inputs, Sec. 3 discussion; Table 2 transfer column), by its plain
+    definition: for each label l in 1..max_label, the smallest box holding
+    every voxel equal to l, that box's first voxel as a flat offset into the
+    map, and the number of such voxels.
+
+    Returns a list of dicts {label, count, lo (3,), dims (3,), offset,
+    strides (2,), spacing}; a label with no voxel gets count 0, a 1x1x1 box at
+    the origin and offset 0.  ``crop(labels, entry)`` gives the entry's mask.
+    """
+    lab = np.ascontiguousarray(labels)
+    if lab.dtype != np.uint8 or lab.ndim != 3:
+        raise ValueError("labels must be a 3-D uint8 array")
+    d = lab.shape
+    out = []
+    for l in range(1, int(max_label) + 1):
+        idx = np.nonzero(lab == l)
+        n = int(idx[0].size)
+        if n == 0:
+            lo = np.zeros(3, np.int64)
+            dims = np.ones(3, np.int64)
+        else:
+            lo = np.array([int(a.min()) for a in idx], np.int64)
+            hi = np.array([int(a.max()) for a in idx], np.int64)
+            dims = hi - lo + 1
+        out.append(dict(label=l, count=n, lo=lo, dims=dims,
+                        offset=int(lo[0] * d[1] * d[2] + lo[1] * d[2] + lo[2]),
+                        strides=(d[1] * d[2], d[2]), spacing=tuple(float(s) for s in spacing)))
+    return out
+
+
+def crop(labels: np.ndarray, entry) -> np.ndarray:
+    """The binary mask (uint8) of ``entry``'s label inside ``entry``'s box."""
+    lo, dims = entry["lo"], entry["dims"]
+    sub = labels[lo[0]:lo[0] + dims[0], lo[1]:lo[1] + dims[1], lo[2]:lo[2] + dims[2]]
+    return (sub == entry["label"]).astype(np.uint8)

@@ -238,3 +238,25 @@ def batched_rois_torch(n: int, seed: int = 0, lmin: float = 8.0, lmax: float = 1
             sub = view[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
             sub |= (rr <= 1.0).to(torch.uint8)
     return buf, offsets, [p[0] for p in params], [p[1] for p in params]
+
+
+def label_map(seed: int = 0, shape=(96, 128, 128), n_labels: int = 6, semi_lo: float = 3.0, semi_hi: float = 24.0,
+              noise: float = 0.0):
+    """A uint8 label map: label l = 1..n_labels painted as one rotated
+    ellipsoid each (later labels over earlier ones), semi-axes U[semi_lo,
+    semi_hi] voxels, centres uniform over the array (so some touch the
+    border), plus i.i.d. voxels of random labels 1..n_labels with probability
+    ``noise`` (stray voxels stretch a label's box).  A stand-in for organ and
+    tumour label maps (labels 1 and 2 in the paper's kidney data)."""
+    g = rng(6, seed)
+    lab = np.zeros(shape, dtype=np.uint8)
+    params = ellipsoid_params(g, n_labels, semi_lo, semi_hi, 0.0, 1.0)
+    for l, (c, s, r) in enumerate(params, start=1):
+        c = c * np.asarray(shape, dtype=np.float64)
+        sl, rr = _ellipsoid_field(shape, c, s, r)
+        if sl is not None:
+            lab[sl][rr <= 1.0] = l
+    if noise > 0.0:
+        hit = g.random(shape) < noise
+        lab[hit] = g.integers(1, n_labels + 1, size=int(hit.sum()), dtype=np.uint8)
+    return lab
