@@ -59,7 +59,7 @@ def log(*a):
 KERNEL_SOURCES = {
     "k_pair_maxima_h": ["pairs.hip"], "k_pair_maxima": ["pairs.hip"],
     "k_bucket_scatter": ["pairs.hip"], "k_bucket_hist": ["pairs.hip"],
-    "k_mesh_count": ["mesh.hip"], "k_mesh_emit": ["mesh.hip"],
+    "k_mesh_pass": ["mesh.hip"], "k_mesh_rows": ["mesh.hip"],
 }
 SHARED_HEADERS = ["mc_table.h", "s3d_device.h", "s3d_internal.h", "s3d_launch.h"]
 
@@ -142,6 +142,16 @@ def bench_single_roi(args, S):
         t0 = time.perf_counter()
         S.shape3d_u8(vol, sp)
         lat.append(1e6 * (time.perf_counter() - t0))
+    # the same calls through the general pipeline (small-mesh path off)
+    S.set_small_path(False)
+    for _ in range(5):
+        S.shape3d_u8(vol, sp)
+    lat_general = []
+    for _ in range(max(20, 5 * args.steps)):
+        t0 = time.perf_counter()
+        S.shape3d_u8(vol, sp)
+        lat_general.append(1e6 * (time.perf_counter() - t0))
+    S.set_small_path(True)
     _, st, _ = S.features(vol, sp, stats=True, timing=True)
     rec = {
         "workload": "single ROI: uint8 64^3, one ellipsoid (semi-axes 8-24 voxels), spacing (1,1,1) mm",
@@ -150,9 +160,11 @@ def bench_single_roi(args, S):
         "latency_us_median": float(np.median(lat)),
         "latency_us_p10": float(np.percentile(lat, 10)),
         "latency_us_p90": float(np.percentile(lat, 90)),
-        "device_phases_ms": st["ms"],
+        "latency_us_median_general_pipeline": float(np.median(lat_general)),
+        "device_phases_ms_general_pipeline": st["ms"],
     }
-    log("single ROI: median %.1f us host-to-host" % rec["latency_us_median"])
+    log("single ROI: median %.1f us host-to-host (general pipeline %.1f us)" % (
+        rec["latency_us_median"], rec["latency_us_median_general_pipeline"]))
     return rec
 
 
@@ -379,7 +391,8 @@ def main():
         log("copy calibration: 3 device copies of %d bytes" % nbytes)
         del src, dst
     if args.skip_large:
-        rec = {"batched": None if args.skip_batched else bench_batched(args, S),
+        rec = {"single_roi": None if args.skip_single else bench_single_roi(args, S),
+               "batched": None if args.skip_batched else bench_batched(args, S),
                "differentiable": None if args.skip_differentiable else bench_differentiable(args, S),
                "batched_soft": None if args.skip_batched_soft else bench_batched_soft(args, S)}
         print(json.dumps(rec), flush=True)
@@ -453,8 +466,8 @@ def main():
         "speedup_vs_all_pairs": ms_per_step / ms_eff,
     }
     N = int(np.prod(mask.shape))
-    t_mesh = (avg["mesh_count"] + avg["mesh_emit"]) * 1e-3
-    tc, te = measured_traffic("k_mesh_count"), measured_traffic("k_mesh_emit")
+    t_mesh = (avg["mesh_pass"] + avg["mesh_rows"]) * 1e-3
+    tc, te = measured_traffic("k_mesh_pass"), measured_traffic("k_mesh_rows")
     mesh_traffic = tc + te if tc is not None and te is not None else None
     mesh_bytes = N * 1 + 24 * V
     mesh = {"bound": "hbm", "achieved": mesh_bytes / t_mesh / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -75,7 +75,8 @@ typedef struct {
   int64_t pairs_2d;        /* sum over planes of n*(n-1)/2 */
   int64_t candidates[4];   /* rows re-examined in FP64 per diameter */
   float ms[8];             /* device time per phase (ms), filled when timing != 0:
-                              0 mesh count, 1 mesh emit, 2 plane bucketing (and split-f16 operands),
+                              0 mesh pass (one read of the volume) and per-ROI totals,
+                              1 vertex rows and pair-pass operands, 2 pruning and plane bucketing,
                               3 pair maxima (MFMA),
                               4 exact refinement, 5 finalisation, 6 whole call, 7 reserved */
 } shape3d_stats;
@@ -275,11 +276,15 @@ int shape3d_batched_soft_backward(const float* base, const shape3d_roi* rois, in
  *   prune:         (kernel 1) skip the 3D pair tiles whose largest possible
  *                  distance, from the bounding boxes of their vertex blocks,
  *                  stays below a vertex-pair distance found by two
- *                  farthest-point sweeps: 1 = for calls whose largest ROI may
- *                  have 16,384 vertices or more, 2 = always, 0 = never (all
- *                  pairs).  Exact: the maximising pairs are never skipped, and
- *                  the FP64 refinement rescans its candidate rows against all
- *                  vertices, so the results equal those of prune = 0.
+ *                  farthest-point sweeps, and the plane buckets whose box
+ *                  diagonal stays below the largest in-plane extent of any
+ *                  bucket of their family: 1 = in calls whose largest ROI may
+ *                  have 16,384 vertices or more (then the 3D pairs of every
+ *                  ROI with 1,024 or more), 2 = always (every ROI), 0 = never
+ *                  (all pairs).  Exact: the maximising pairs are never
+ *                  skipped, and the FP64 refinement rescans its candidate rows
+ *                  against all vertices of their segment, so the results equal
+ *                  those of prune = 0.
  * The setting is process-wide (all devices); the default is {8, 1024, 0, 1, 1}
  * (the autotuner's choice on one very large ROI; batches of small ROIs gain
  * about 1 % from jchunk 512).
@@ -310,6 +315,9 @@ typedef struct {
   int32_t blocks_per_cu;
   int32_t kernel;
   int32_t prune;  /* kernel 1: 1 (default) prune the 3D pair tiles of large ROIs, 2 always, 0 never */
+  int32_t small_path; /* 1 (default): single-ROI calls of at most 2^22 voxels and 16,384 vertices
+                         (six features, no phase timing) evaluate all pairs exactly in one kernel
+                         after the mesh pass; 0: always the general pipeline.  Results are identical. */
 } shape3d_tuning;
 
 int shape3d_get_tuning(shape3d_tuning* t);
@@ -402,6 +410,62 @@ typedef struct {
 int shape3d_batched_dev(const void* base, int dtype, const shape3d_roi_ex* rois, int64_t n_rois,
                         const int64_t max_dims[3], double* out, int* status, void* workspace, size_t ws_bytes,
                         int flags, void* stream);
+
+/*
+ * shape3d_host_stream -- the features of n volumes that start in HOST memory,
+ * with the host-to-device transfer of volume i + 1 overlapped with the
+ * computation of volume i.  The paper copies each input to the device before
+ * its kernels run and reports that transfer as a large share of its GPU time
+ * (Sec. 3, discussion of the results; Table 2, transfer column): here a
+ * staging thread of the library copies on a stream of its own while the
+ * calling thread runs the pipeline on `stream`, and two device volumes
+ * alternate.  Page-locked sources (hipHostMalloc) are copied by DMA
+ * directly; pageable ones pass through two pinned 32 MiB chunks of the
+ * library that alternate.
+ *   vols:    HOST array of n HOST pointers, each a C-contiguous volume of
+ *            dtype (as shape3d_ex) and dims[3 i .. 3 i + 2].
+ *   dims, spacing: HOST int64[3 n], double[3 n].
+ *   out:     HOST double[6 n], or double[SHAPE3D_N_CLASS n] with
+ *            SHAPE3D_SHAPE_CLASS in flags (the only flag).
+ *   status:  HOST int[n]: each volume's status (as shape3d_ex; out rows of a
+ *            failed volume are 0).
+ * Synchronous: returns when every result is in out.  The library keeps two
+ * device volumes of the largest size seen (and the pinned chunks) until
+ * shape3d_release.  Returns SHAPE3D_EINVAL for bad arguments (checked for
+ * every volume before any copy), SHAPE3D_ENOMEM, or SHAPE3D_EHIP if a copy
+ * failed.
+ */
+int shape3d_host_stream(const void* const* vols, int dtype, const int64_t* dims, const double* spacing, int64_t n,
+                        double* out, int* status, int flags, void* stream);
+
+/*
+ * shape3d_label_rois -- input preprocessing on the device for a label map:
+ * one read of the map gives, for every label 1..max_label, its bounding box
+ * and voxel count, written as the entry of a device ROI table that crops the
+ * map to the box and selects the label, ready for shape3d_batched_dev.  The
+ * paper stages and transfers every input from the host and names this step
+ * its open problem (Sec. 3, discussion of the results; Table 2, transfer
+ * column); here the map stays in HBM and the table never leaves the device.
+ *   labels:  DEVICE uint8, C-contiguous (dims[0], dims[1], dims[2]) label map
+ *            (0 = background).
+ *   dims, spacing: HOST, as shape3d.  spacing is copied into every entry.
+ *   max_label: 1..255.  Voxels with larger labels are ignored.
+ *   rois:    DEVICE shape3d_roi_ex[max_label], written: entry l - 1 has
+ *            offset = the box's first voxel, dims = the box's extent,
+ *            strides = the map's (dims[1] dims[2], dims[2]), label = l.  A
+ *            label with no voxel gets a 1 x 1 x 1 crop at the origin, which
+ *            then holds none of it (status SHAPE3D_EMPTY in the batch).  The
+ *            entries also hold the boxes while they are built: their
+ *            contents are defined once the call's work on `stream` is done.
+ *   voxel_counts: DEVICE int64[max_label] (voxels per label) or NULL.
+ *   max_dims: DEVICE int64[3] (the largest entry dims per axis, at least 1)
+ *            or NULL.  The whole map's dims also bound every entry.
+ * Enqueued on `stream` (no host synchronisation, no allocation).
+ * Returns SHAPE3D_EINVAL for bad arguments (null pointers, max_label out of
+ * range, buffers that are not device memory or are too small).
+ */
+int shape3d_label_rois(const uint8_t* labels, const int64_t dims[3], const double spacing[3], int32_t max_label,
+                       shape3d_roi_ex* rois, int64_t* voxel_counts, int64_t* max_dims, void* stream);
 
 /*
  * shape3d_noalloc -- shape3d_ex_async for callers that cannot allocate memory

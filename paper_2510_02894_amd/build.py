@@ -16,10 +16,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshape3d.so")
-SOURCES = ["mesh.hip", "scan.hip", "pairs.hip", "prune.hip", "soft.hip", "api.hip"]
-# per-file flags: the pair kernel's maxima never see NaNs (MFMA results), so
-# fmaxf needs no canonicalisation there
-EXTRA = {"pairs.hip": ["-fno-honor-nans"]}
+SOURCES = ["mesh.hip", "scan.hip", "pairs.hip", "prune.hip", "soft.hip", "labels.hip", "small.hip", "api.hip"]
+# per-file flags: the pair kernels' maxima never see NaNs (MFMA results, or
+# FP64 distances of finite positions), so fmax needs no canonicalisation there
+EXTRA = {"pairs.hip": ["-fno-honor-nans"], "small.hip": ["-fno-honor-nans"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -16,12 +16,15 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/shape3d.h"
@@ -59,10 +62,13 @@ struct Buf {
 // on demand; a caller's workspace is carved into all of them at once.
 enum WsId {
   W_ROIS, W_PLAN, W_PART, W_BRICK_VOFF, W_META, W_CASE_AREA, W_TOTALS, W_COUNTERS, W_GRES, W_RES, W_PAIRS2D,
-  W_BCNT, W_BCUR, W_BSZ, W_BFLAG, W_BROW, W_BSEG, W_BGROUP,
+  W_BCNT, W_BCUR, W_BSZ, W_BFLAG, W_BROW, W_BSEG, W_BGROUP, W_BBOX,
   W_FIRST_VERTEX_BUF,
   W_KEY = W_FIRST_VERTEX_BUF, W_TSOFT, W_POS, W_POSH, W_ORIG, W_ROWMAX, W_BLKSEG, W_SEGS, W_NCOL, W_COLBASE,
   W_COLS, W_NITEM, W_ITEMBASE, W_SCAN_TMP, W_CAND, W_CAND_NCH, W_CAND_CHBASE, W_BLKREC, W_RSEED, W_PITEM,
+  // the mesh pass's staging list (in the library's workspace sized on its own,
+  // before the vertex count is known)
+  W_TMPKEY, W_TMPT,
   W_NUM
 };
 
@@ -101,6 +107,13 @@ struct Workspace {
   long long last_vmax = 0;   // largest vertex count of the last eager run
   std::map<std::string, GraphRec> graphs;
   long long stamp = 0;
+  Buf small_slots;  // the small-mesh pair kernels' accumulators (SmallAcc)
+  // host-to-device streaming (shape3d_host_stream): two device volumes, two
+  // pinned chunks for pageable sources, the copy stream and its events
+  Buf hs_vol[2];
+  void* hs_pin[2] = {nullptr, nullptr};
+  hipStream_t hs_copy = nullptr;
+  hipEvent_t hs_ev[6] = {};  // 0, 1: a volume copied; 2, 3: a volume used; 4, 5: a pinned chunk free
 
   Ptrs ptrs() const {
     Ptrs P;
@@ -121,7 +134,7 @@ static __device__ __align__(256) unsigned char scratch[SHAPE3D_NOALLOC_SCRATCH_B
 void* g_scratch[kMaxScratchDevices] = {};
 
 // Tile sizes of the pair pass for every device (results do not depend on them).
-Tuning g_tune = {8, 1024, 0, 1, 1};
+Tuning g_tune = {8, 1024, 0, 1, 1, 1};
 
 // Vertex count from which a ROI's 3D pairs are pruned: kPruneMinV for prune = 1,
 // every ROI with pairs for prune = 2.
@@ -130,7 +143,8 @@ int prune_min_v() { return g_tune.prune == 2 ? 2 : kPruneMinV; }
 bool valid_tuning(const Tuning& t) {
   return (t.itile == 2 || t.itile == 4 || t.itile == 8) &&
          (t.jchunk == 64 || t.jchunk == 128 || t.jchunk == 256 || t.jchunk == 512 || t.jchunk == 1024) && t.blocks_per_cu >= 0 &&
-         t.blocks_per_cu <= 64 && (t.kernel == 0 || (t.kernel == 1 && t.itile >= 4)) && (t.prune >= 0 && t.prune <= 2);
+         t.blocks_per_cu <= 64 && (t.kernel == 0 || (t.kernel == 1 && t.itile >= 4)) && (t.prune >= 0 && t.prune <= 2) &&
+         (t.small_path == 0 || t.small_path == 1);
 }
 
 void drop_graphs(Workspace& w) {
@@ -278,11 +292,11 @@ struct Batch {
 };
 
 void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double spacing[3], long long stride0 = 0,
-               long long stride1 = 0, int label = 0) {
+               long long stride1 = 0, int label = 0, int tz = kTZ) {
   Roi R;
   memset(&R, 0, sizeof(R));
   const long long d[3] = {dims[0], dims[1], dims[2]};
-  const long long nb = roi_fill(R, vol, d, spacing, stride0, stride1, label);
+  const long long nb = roi_fill(R, vol, d, spacing, stride0, stride1, label, tz);
   R.brick_begin = B.nbricks;
   R.brick_end = B.nbricks + nb;
   roi_set_buckets(R, B.n_buckets);
@@ -349,7 +363,7 @@ int ws_layout(const Batch& B, int dtype, const Tuning& t, long long rows0_cap, L
   b[W_PART] = sizeof(BrickPart) * B.nbricks;
   b[W_BRICK_VOFF] = sizeof(long long) * B.nbricks;
   b[W_META] = sizeof(RoiMeta) * n;
-  b[W_CASE_AREA] = sizeof(double) * 256 * n;
+  b[W_CASE_AREA] = (sizeof(double) + sizeof(unsigned long long)) * 256 * n;  // areas, then counts
   b[W_TOTALS] = sizeof(long long) * 16;
   b[W_COUNTERS] = sizeof(unsigned int) * kCounterWords;
   b[W_GRES] = sizeof(GroupRes) * 4 * n;
@@ -358,6 +372,7 @@ int ws_layout(const Batch& B, int dtype, const Tuning& t, long long rows0_cap, L
   b[W_BCNT] = b[W_BCUR] = sizeof(unsigned int) * B.n_buckets;
   b[W_BSZ] = b[W_BFLAG] = b[W_BROW] = b[W_BSEG] = sizeof(long long) * B.n_buckets;
   b[W_BGROUP] = sizeof(int) * B.n_buckets;
+  b[W_BBOX] = t.kernel == 1 ? sizeof(int) * 4 * B.n_buckets : 0;
   const long long r0 = std::max<long long>(S.rows0, 1);
   b[W_KEY] = sizeof(unsigned long long) * r0;
   b[W_TSOFT] = dtype == SHAPE3D_F32 ? sizeof(double) * r0 : 0;
@@ -381,6 +396,8 @@ int ws_layout(const Batch& B, int dtype, const Tuning& t, long long rows0_cap, L
   b[W_BLKREC] = t.kernel == 1 ? sizeof(BlkRec) * (S.rows0 / 32 + 1) : 0;
   b[W_RSEED] = t.kernel == 1 ? sizeof(RoiSeed) * n : 0;
   b[W_PITEM] = t.kernel == 1 ? sizeof(PItem) * (S.rows0 / 8 + 64) : 0;
+  b[W_TMPKEY] = sizeof(unsigned long long) * r0;
+  b[W_TMPT] = dtype == SHAPE3D_F32 ? sizeof(double) * r0 : 0;
   L.S = S;
   return SHAPE3D_OK;
 }
@@ -453,11 +470,38 @@ int ensure_vertex_bufs(Workspace& w, const Batch& B, int dtype, long long rows0,
   Layout L, Lc;
   int rc = ws_layout(B, dtype, g_tune, rows0, Lc);
   if (!rc) rc = ws_layout(B, dtype, g_tune, std::max<long long>(rows0, w.rows0_cap), L);
-  if (!rc) rc = ensure_bufs(w, L, W_FIRST_VERTEX_BUF, W_NUM);
+  if (!rc) rc = ensure_bufs(w, L, W_FIRST_VERTEX_BUF, W_TMPKEY);
   if (rc) return rc;
   S_call = Lc.S;
   w.rows0_cap = L.S.rows0;
   return SHAPE3D_OK;
+}
+
+// The staging list of the mesh pass in the library's workspace: rows for at
+// least `rows` vertices.  Returns its capacity in rows in *cap.
+int ensure_staging(Workspace& w, int dtype, long long rows, long long* cap) {
+  rows = std::max<long long>(rows, 1);
+  int rc = ensure(w, w.buf[W_TMPKEY], sizeof(unsigned long long) * (size_t)rows);
+  if (!rc && dtype == SHAPE3D_F32) rc = ensure(w, w.buf[W_TMPT], sizeof(double) * (size_t)rows);
+  if (rc) return rc;
+  long long c = (long long)(w.buf[W_TMPKEY].cap / sizeof(unsigned long long));
+  if (dtype == SHAPE3D_F32) c = std::min<long long>(c, (long long)(w.buf[W_TMPT].cap / sizeof(double)));
+  *cap = c;
+  return SHAPE3D_OK;
+}
+
+// A first guess of a batch's vertex rows for the staging list (one per 16
+// voxels, within [2^16, 2^26]); a mesh with more is counted by a first mesh
+// pass and the pass runs again with a list of the right size.
+long long staging_guess(const Batch& Bt) {
+  double vox = 0.0;
+  if (Bt.planned) {
+    vox = (double)Bt.n() * (double)Bt.max_d[0] * (double)Bt.max_d[1] * (double)Bt.max_d[2];
+  } else {
+    for (const Roi& R : Bt.rois) vox += (double)R.d[0] * (double)R.d[1] * (double)R.d[2];
+  }
+  const double g = vox / 16.0 + 32.0 * Bt.n();
+  return (long long)std::min(std::max(g, 65536.0), (double)(1ll << 26));
 }
 
 PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, int cu_count) {
@@ -482,6 +526,7 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   B.bgroup = P.as<int>(W_BGROUP);
   B.brow = P.as<long long>(W_BROW);
   B.bseg = P.as<long long>(W_BSEG);
+  B.bbox = P.as<int4>(W_BBOX);
   B.seg_cap = S.seg_cap;
   B.ncol = P.as<long long>(W_NCOL);
   B.colbase = P.as<long long>(W_COLBASE);
@@ -513,14 +558,30 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   return B;
 }
 
-// Mesh count and per-ROI totals (launches only).
-int launch_head(const Ptrs& P, const Batch& Bt, int dtype, hipStream_t st) {
-  HIPCK(launch_fill_u32(P.as<unsigned int>(W_COUNTERS), 0u, kCounterWords, st));
-  HIPCK(launch_mesh_count(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<double>(W_CASE_AREA),
-                          P.as<BrickPart>(W_PART), Bt.moments ? 1 : 0, st));
-  HIPCK(launch_mesh_totals(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, dtype, P.as<const BrickPart>(W_PART),
+// The mesh pass (with the staging list's capacity in rows) and per-ROI
+// totals (launches only).
+int launch_head(const Ptrs& P, const Batch& Bt, int dtype, long long tmp_cap, hipStream_t st) {
+  HIPCK(launch_mesh_pass(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<double>(W_CASE_AREA),
+                         P.as<BrickPart>(W_PART), P.as<unsigned int>(W_COUNTERS), kCounterWords,
+                         P.as<unsigned long long>(W_TMPKEY), dtype == SHAPE3D_F32 ? P.as<double>(W_TMPT) : nullptr,
+                         tmp_cap, P.as<long long>(W_TOTALS), Bt.moments ? 1 : 0, st));
+  HIPCK(launch_mesh_totals(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, dtype, P.as<const double>(W_CASE_AREA),
+                           P.as<const BrickPart>(W_PART),
                            P.as<long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
                            Bt.moments ? 1 : 0, prune_min_v(), st));
+  return SHAPE3D_OK;
+}
+
+// The capacity check and layout 0 from the staging list of tmp_cap rows (launches only).
+int launch_rows(const Ptrs& P, const Batch& Bt, int dtype, long long rows0_cap, long long tmp_cap, uint4* posh,
+                hipStream_t st) {
+  HIPCK(launch_mesh_rows(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, P.as<const BrickPart>(W_PART),
+                         P.as<const long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
+                         rows0_cap, P.as<const unsigned long long>(W_TMPKEY),
+                         dtype == SHAPE3D_F32 ? P.as<const double>(W_TMPT) : nullptr, tmp_cap,
+                         P.as<unsigned long long>(W_KEY), dtype == SHAPE3D_F32 ? P.as<double>(W_TSOFT) : nullptr,
+                         posh ? nullptr : P.as<float>(W_POS), posh, P.as<int>(W_ORIG), P.as<int>(W_BLKSEG),
+                         P.as<Seg>(W_SEGS), P.as<unsigned int>(W_COUNTERS) + 2, st));
   return SHAPE3D_OK;
 }
 
@@ -528,22 +589,17 @@ int launch_head(const Ptrs& P, const Batch& Bt, int dtype, hipStream_t st) {
 // only).  ev: optional phase events recorded before emission, buckets, pairs,
 // refinement and finalisation.
 // vmax_hint: the largest vertex count of the batch (a bound), or -1 if unknown;
-// with prune = 1 the 3D pairs are pruned when it may reach kPruneMinV, with
-// prune = 2 always.
-int launch_tail(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, int cu_count, hipStream_t st,
-                hipEvent_t* ev, long long vmax_hint) {
+// with prune = 1 the call prunes when it may reach kPruneCallMinV (then every
+// ROI of at least kPruneMinV vertices), with prune = 2 always (every ROI).
+int launch_tail(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, long long tmp_cap, int cu_count,
+                hipStream_t st, hipEvent_t* ev, long long vmax_hint) {
   PairBufs B = pair_bufs(P, Bt, dtype, S, cu_count);
   B.prune = g_tune.kernel == 1 &&
-            (g_tune.prune == 2 || (g_tune.prune == 1 && (vmax_hint < 0 || vmax_hint >= kPruneMinV)));
+            (g_tune.prune == 2 || (g_tune.prune == 1 && (vmax_hint < 0 || vmax_hint >= kPruneCallMinV)));
   B.prune_min_v = prune_min_v();
-  HIPCK(launch_check_capacity(Bt.n(), S.rows0, P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
-                              P.as<unsigned int>(W_COUNTERS) + 2, st));
   if (ev) HIPCK(hipEventRecord(ev[0], st));
-  HIPCK(launch_mesh_emit(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<const BrickPart>(W_PART),
-                         P.as<const long long>(W_BRICK_VOFF), P.as<const RoiMeta>(W_META),
-                         P.as<const unsigned int>(W_COUNTERS) + 2, P.as<unsigned long long>(W_KEY),
-                         dtype == SHAPE3D_F32 ? P.as<double>(W_TSOFT) : nullptr, P.as<float>(W_POS), split_rows(B),
-                         P.as<int>(W_ORIG), P.as<int>(W_BLKSEG), P.as<Seg>(W_SEGS), st));
+  int rc = launch_rows(P, Bt, dtype, S.rows0, tmp_cap, split_rows(B), st);
+  if (rc) return rc;
   if (ev) HIPCK(hipEventRecord(ev[1], st));
   if (B.prune) HIPCK(launch_prune(B, st));
   HIPCK(launch_buckets(B, st));
@@ -584,20 +640,29 @@ int run_eager(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, RoiResul
               float* phase_ms, const DevTable* dt = nullptr) {
   int rc;
   char* h = (char*)w.host;
+  long long tcap = 0;
+  if ((rc = ensure_staging(w, dtype, staging_guess(Bt), &tcap))) return rc;
   Ptrs P = w.ptrs();
   if ((rc = upload_rois(w, P, Bt, dtype, dt, st))) return rc;
-  if (timing) HIPCK(hipEventRecord(w.ev[0], st));
-  if ((rc = launch_head(P, Bt, dtype, st))) return rc;
-  if (timing) HIPCK(hipEventRecord(w.ev[1], st));
   long long* th = (long long*)h;
-  HIPCK(hipMemcpyAsync(th, P.p[W_TOTALS], sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
+  for (int pass = 0;; ++pass) {
+    if (timing) HIPCK(hipEventRecord(w.ev[0], st));
+    if ((rc = launch_head(P, Bt, dtype, tcap, st))) return rc;
+    if (timing) HIPCK(hipEventRecord(w.ev[1], st));
+    HIPCK(hipMemcpyAsync(th, P.p[W_TOTALS], sizeof(long long) * 9, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (th[8] <= tcap || pass > 0) break;
+    // more vertices than the staging list held: size it and run the mesh pass again
+    if ((rc = ensure_staging(w, dtype, th[8], &tcap))) return rc;
+    P = w.ptrs();
+  }
+  if (th[8] > tcap) return fail(SHAPE3D_EINTERNAL, "the mesh pass's staging list overflowed twice");
   Sizes S;
   if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
   P = w.ptrs();
   w.last_rows0 = th[0];
   w.last_vmax = th[1];
-  if ((rc = launch_tail(P, Bt, dtype, S, w.cu_count, st, timing ? &w.ev[2] : nullptr, th[1]))) return rc;
+  if ((rc = launch_tail(P, Bt, dtype, S, tcap, w.cu_count, st, timing ? &w.ev[2] : nullptr, th[1]))) return rc;
   if (host_res) HIPCK(hipMemcpyAsync(host_res, P.p[W_RES], sizeof(RoiResult) * Bt.n(), hipMemcpyDeviceToHost, st));
   if (timing) HIPCK(hipEventRecord(w.ev[7], st));
   HIPCK(hipStreamSynchronize(st));
@@ -630,8 +695,8 @@ int run_fixed(const Batch& Bt, int dtype, const Roi* one_roi, const DevTable* dt
   } else {
     HIPCK(launch_set_roi(*one_roi, P.as<Roi>(W_ROIS), st));
   }
-  if ((rc = launch_head(P, Bt, dtype, st))) return rc;
-  if ((rc = launch_tail(P, Bt, dtype, L.S, cu_count, st, nullptr, cap))) return rc;
+  if ((rc = launch_head(P, Bt, dtype, cap, st))) return rc;
+  if ((rc = launch_tail(P, Bt, dtype, L.S, cap, cu_count, st, nullptr, cap))) return rc;
   HIPCK(launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, Bt.nf(), st));
   return SHAPE3D_OK;
 }
@@ -652,6 +717,54 @@ void fill_stats(shape3d_stats* stats, const RoiResult& R, const float* ms) {
     for (int k = 0; k < 7; ++k) stats->ms[k] = ms[k];
 }
 
+// The small-mesh path of one ROI: the ROI record, the mesh pass into the
+// staging list and the exact all-pairs kernel (three launches), then the
+// result read back.  hres->status is kSmallOverflow when the mesh has more
+// than kSmallMaxV vertices (the general path must run instead).
+int run_small(Workspace& w, const void* vol, int dtype, const int64_t dims[3], const double spacing[3], hipStream_t st,
+              RoiResult* hres) {
+  // Binary masks: bricks of one cube plane, so that a small ROI still spreads
+  // over many workgroups (the area is summed from per-case counts, whatever
+  // the bricks).  Soft masks keep the general path's bricks: their area and
+  // volume partials are summed per brick, and the results must not change.
+  Batch Bt;
+  batch_add(Bt, vol, dims, spacing, 0, 0, 0, dtype == SHAPE3D_U8 ? 1 : kTZ);
+  int rc = ensure_layout_bufs(w, Bt, dtype);
+  if (rc) return rc;
+  long long tcap = 0;
+  if ((rc = ensure_staging(w, dtype, kSmallMaxV, &tcap))) return rc;
+  const int groups = 4 * w.cu_count;
+  if ((rc = ensure(w, w.small_slots, small_acc_bytes()))) return rc;
+  const Ptrs P = w.ptrs();
+  SmallAcc* acc = (SmallAcc*)w.small_slots.p;
+  const long long vmax = std::min(tcap, kSmallMaxV);
+  HIPCK(launch_small_head(dtype, Bt.rois[0], P.as<Roi>(W_ROIS), P.as<long long>(W_TOTALS), acc,
+                          P.as<double>(W_CASE_AREA), st));
+  HIPCK(launch_mesh_core(dtype, P.as<const Roi>(W_ROIS), 1, Bt.nbricks, Bt.max_G, P.as<double>(W_CASE_AREA),
+                         P.as<BrickPart>(W_PART), P.as<unsigned long long>(W_TMPKEY),
+                         dtype == SHAPE3D_F32 ? P.as<double>(W_TMPT) : nullptr, vmax, P.as<long long>(W_TOTALS), 0,
+                         st));
+  HIPCK(launch_small_pairs(dtype, P.as<const Roi>(W_ROIS), P.as<const BrickPart>(W_PART), Bt.nbricks,
+                           P.as<const double>(W_CASE_AREA), P.as<const unsigned long long>(W_TMPKEY),
+                           dtype == SHAPE3D_F32 ? P.as<const double>(W_TMPT) : nullptr,
+                           P.as<const long long>(W_TOTALS), vmax, acc, groups, P.as<RoiResult>(W_RES), st));
+  HIPCK(hipMemcpyAsync(hres, P.p[W_RES], sizeof(RoiResult), hipMemcpyDeviceToHost, st));
+  HIPCK(hipStreamSynchronize(st));
+  return SHAPE3D_OK;
+}
+
+// Whether a single-ROI call tries the small-mesh path first: six features,
+// no phase timing, a ROI small enough that a mesh beyond kSmallMaxV vertices
+// is unlikely (one that has more costs one extra mesh pass), and the
+// tuning's small-path switch on.
+bool small_path(const Batch& Bt, bool moments, int timing) {
+  if (moments || timing || !g_tune.small_path || Bt.n() != 1) return false;
+  const Roi& R = Bt.rois[0];
+  // the pair kernels pack two canonical ids, below 3 (d0 + 2) (d1 + 2) (d2 + 2), in 64 bits
+  const long long ids = 3ll * (R.d[0] + 2) * (R.d[1] + 2) * (R.d[2] + 2);
+  return (long long)R.d[0] * R.d[1] * R.d[2] <= kSmallMaxVoxels && ids < (1ll << 32);
+}
+
 // out: the six features, or with `moments` the SHAPE3D_N_CLASS Shape-class members.
 int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double spacing[3], double* out,
                  shape3d_stats* stats, int timing, hipStream_t st, RoiResult* raw = nullptr, bool moments = false) {
@@ -667,7 +780,12 @@ int shape3d_impl(const void* vol, int dtype, const int64_t dims[3], const double
   if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
   RoiResult* hres = host_results(w, Bt);
   float ms[8] = {0};
-  if ((rc = run_eager(w, Bt, dtype, st, hres, timing, ms))) return rc;
+  bool done = false;
+  if (!raw && small_path(Bt, moments, timing)) {
+    if ((rc = run_small(w, vol, dtype, dims, spacing, st, hres))) return rc;
+    done = hres->status != kSmallOverflow;
+  }
+  if (!done && (rc = run_eager(w, Bt, dtype, st, hres, timing, ms))) return rc;
   if (hres->status < 0) return fail(hres->status, "an internal capacity was exceeded");
   for (int f = 0; f < 6; ++f) out[f] = hres->out[f];
   if (moments)
@@ -704,6 +822,11 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
     }
   }
   const Sizes S = sizes_for(Bt, w.last_rows0);
+  // a staging list that holds the recorded row capacity, so that a replay
+  // within that capacity stages every vertex
+  long long tcap = 0;
+  int rc0 = ensure_staging(w, dtype, w.last_rows0, &tcap);
+  if (rc0) return rc0;
   const Ptrs P = w.ptrs();
   hipGraph_t graph = nullptr;
   HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -713,8 +836,8 @@ int capture_graph(Workspace& w, const Batch& Bt, int dtype, hipStream_t st, Grap
                                           P.as<Roi>(W_ROIS), P.as<long long>(W_PLAN), st);
     if (e != hipSuccess) rc = fail(SHAPE3D_EHIP, std::string("plan: ") + hipGetErrorString(e));
   }
-  if (!rc) rc = launch_head(P, Bt, dtype, st);
-  if (!rc) rc = launch_tail(P, Bt, dtype, S, w.cu_count, st, nullptr, w.last_vmax);
+  if (!rc) rc = launch_head(P, Bt, dtype, tcap, st);
+  if (!rc) rc = launch_tail(P, Bt, dtype, S, tcap, w.cu_count, st, nullptr, w.last_vmax);
   if (!rc) {
     const hipError_t e = dt ? launch_results_out(P.as<const RoiResult>(W_RES), Bt.n(), out, status, Bt.nf(), st)
                             : hipMemcpyAsync(rec.host_res, P.p[W_RES], sizeof(RoiResult) * Bt.n(),
@@ -1075,8 +1198,7 @@ bool tuning_cache_find(const char* path, const std::string& key, Tuning& t, doub
   char line[256], k[128];
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
-    Tuning c;
-    c.prune = g_tune.prune;  // the cache holds the tiles; pruning stays as set
+    Tuning c = g_tune;  // the cache holds the tiles; pruning and the small path stay as set
     double m;
     if (sscanf(line, "%127s %d %d %d %d %lf", k, &c.kernel, &c.itile, &c.jchunk, &c.blocks_per_cu, &m) == 6 &&
         key == k && valid_tuning(c)) {
@@ -1119,7 +1241,7 @@ int autotune_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t 
   static const int kCand[5][2] = {{0, 2}, {0, 4}, {0, 8}, {1, 4}, {1, 8}};  // (kernel, itile)
   for (const auto& kc : kCand)
     for (int jc : {64, 128, 256, 512, 1024}) {
-      g_tune = Tuning{kc[1], jc, 0, kc[0], saved.prune};
+      g_tune = Tuning{kc[1], jc, 0, kc[0], saved.prune, saved.small_path};
       double t = 1e300;
       for (int k = 0; k < reps; ++k) {
         if ((rc = run_eager(w, Bt, dtype, st, hres, 1, ms))) {
@@ -1150,6 +1272,181 @@ int autotune_impl(const void* base, int dtype, const shape3d_roi* rois, int64_t 
     fclose(f);
   }
   return SHAPE3D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Volumes that start in host memory (shape3d_host_stream).  A staging thread
+// copies volume i + 1 to the device on its own stream while the calling
+// thread computes volume i on the caller's stream; two device volumes
+// alternate.  Page-locked sources go to the device in one DMA copy; pageable
+// ones pass through two pinned chunks that alternate, so the host copy of one
+// chunk overlaps the DMA of the other.
+
+constexpr size_t kStreamChunk = 32ull << 20;
+
+int host_stream_buffers(Workspace& w, size_t vol_bytes, bool pageable) {
+  if (!w.hs_copy) {
+    HIPCK(hipStreamCreateWithFlags(&w.hs_copy, hipStreamNonBlocking));
+    for (hipEvent_t& e : w.hs_ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  for (int i = 0; i < 2; ++i) {
+    Buf& b = w.hs_vol[i];
+    if (b.cap < vol_bytes) {
+      HIPCK(hipDeviceSynchronize());
+      if (b.p) (void)hipFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+      const size_t want = (vol_bytes + 255) & ~(size_t)255;
+      if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(SHAPE3D_ENOMEM, "device allocation of a staging volume failed");
+      }
+      b.cap = want;
+    }
+    if (pageable && !w.hs_pin[i]) {
+      if (hipHostMalloc(&w.hs_pin[i], kStreamChunk, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        w.hs_pin[i] = nullptr;
+        return fail(SHAPE3D_ENOMEM, "pinned host allocation failed");
+      }
+    }
+  }
+  return SHAPE3D_OK;
+}
+
+bool host_pinned(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost;
+}
+
+// Handshake between the calling thread and the staging thread.
+struct StreamSync {
+  std::mutex mu;
+  std::condition_variable cv;
+  long long staged = -1;  // volumes whose copies are enqueued (and event recorded)
+  long long used = -1;    // volumes whose "used" event is recorded
+  int error = 0;          // a HIP failure of the staging thread
+  bool stop = false;      // the calling thread gave up
+};
+
+void host_stream_stager(Workspace* w, const void* const* vols, const size_t* bytes, const bool* pinned, int64_t n,
+                        StreamSync* S) {
+  (void)hipSetDevice(w->device);
+  auto ok = [&](hipError_t e) {
+    if (e == hipSuccess) return true;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->error = (int)e;
+    S->cv.notify_all();
+    return false;
+  };
+  bool chunk_used[2] = {false, false};
+  int chunk = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int b = (int)(i & 1);
+    {
+      // volume i reuses the device buffer of volume i - 2: its compute must be enqueued first
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || S->used >= i - 2; });
+      if (S->stop) return;
+    }
+    if (i >= 2 && !ok(hipStreamWaitEvent(w->hs_copy, w->hs_ev[2 + b], 0))) return;
+    char* dst = (char*)w->hs_vol[b].p;
+    if (pinned[i] || bytes[i] == 0) {
+      if (bytes[i] && !ok(hipMemcpyAsync(dst, vols[i], bytes[i], hipMemcpyHostToDevice, w->hs_copy))) return;
+    } else {
+      for (size_t off = 0; off < bytes[i]; off += kStreamChunk) {
+        const size_t len = std::min(kStreamChunk, bytes[i] - off);
+        if (chunk_used[chunk] && !ok(hipEventSynchronize(w->hs_ev[4 + chunk]))) return;
+        memcpy(w->hs_pin[chunk], (const char*)vols[i] + off, len);
+        if (!ok(hipMemcpyAsync(dst + off, w->hs_pin[chunk], len, hipMemcpyHostToDevice, w->hs_copy))) return;
+        if (!ok(hipEventRecord(w->hs_ev[4 + chunk], w->hs_copy))) return;
+        chunk_used[chunk] = true;
+        chunk ^= 1;
+      }
+    }
+    if (!ok(hipEventRecord(w->hs_ev[b], w->hs_copy))) return;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->staged = i;
+    S->cv.notify_all();
+  }
+}
+
+int host_stream_impl(const void* const* vols, int dtype, const int64_t* dims, const double* spacing, int64_t n,
+                     double* out, int* status, int flags, hipStream_t st) {
+  if (!vols || !dims || !spacing || !out || !status || n < 1) return fail(SHAPE3D_EINVAL, "null argument or no volume");
+  if (dtype != SHAPE3D_U8 && dtype != SHAPE3D_F32) return fail(SHAPE3D_EINVAL, "dtype must be SHAPE3D_U8 or SHAPE3D_F32");
+  const bool cls = (flags & SHAPE3D_SHAPE_CLASS) != 0;
+  const int nf = cls ? SHAPE3D_N_CLASS : 6;
+  std::vector<size_t> bytes((size_t)n, 0);
+  std::unique_ptr<bool[]> pinned(new bool[(size_t)n]);
+  size_t max_bytes = 0;
+  bool any_pageable = false;
+  int rc;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!vols[i]) return fail(SHAPE3D_EINVAL, "null volume " + std::to_string(i));
+    if ((rc = check_dims_spacing(dims + 3 * i, spacing + 3 * i))) return rc;
+    bytes[i] = (size_t)dims[3 * i] * (size_t)dims[3 * i + 1] * (size_t)dims[3 * i + 2] * (dtype == SHAPE3D_U8 ? 1 : 4);
+    pinned[i] = host_pinned(vols[i]);
+    any_pageable |= !pinned[i];
+    max_bytes = std::max(max_bytes, bytes[i]);
+  }
+  Workspace* wp = nullptr;
+  if ((rc = get_workspace(&wp))) return rc;
+  Workspace& w = *wp;
+  if ((rc = host_stream_buffers(w, max_bytes, any_pageable))) return rc;
+  StreamSync S;
+  std::thread stager(host_stream_stager, &w, vols, bytes.data(), pinned.get(), n, &S);
+  int result = SHAPE3D_OK;
+  for (int64_t i = 0; i < n; ++i) {
+    const int b = (int)(i & 1);
+    {
+      std::unique_lock<std::mutex> lk(S.mu);
+      S.cv.wait(lk, [&] { return S.error || S.staged >= i; });
+      if (S.error) {
+        result = fail(SHAPE3D_EHIP, std::string("HIP error while copying a volume: ") +
+                                        hipGetErrorString((hipError_t)S.error));
+        break;
+      }
+    }
+    hipError_t e = hipStreamWaitEvent(st, w.hs_ev[b], 0);
+    if (e != hipSuccess) {
+      result = fail(SHAPE3D_EHIP, hipGetErrorString(e));
+      break;
+    }
+    double* o = out + (size_t)nf * (size_t)i;
+    const int r = shape3d_impl(w.hs_vol[b].p, dtype, dims + 3 * i, spacing + 3 * i, o, nullptr, 0, st, nullptr, cls);
+    status[i] = r;
+    if (r < 0)
+      for (int f = 0; f < nf; ++f) o[f] = 0.0;
+    if (r == SHAPE3D_EHIP || r == SHAPE3D_ENOMEM) {
+      result = r;
+      break;
+    }
+    e = hipEventRecord(w.hs_ev[2 + b], st);
+    if (e != hipSuccess) {
+      result = fail(SHAPE3D_EHIP, hipGetErrorString(e));
+      break;
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.used = i;
+    S.cv.notify_all();
+  }
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+    S.cv.notify_all();
+  }
+  stager.join();
+  // the copy stream may still hold copies of volumes that were not computed
+  const hipError_t e = hipStreamSynchronize(w.hs_copy);
+  if (result == SHAPE3D_OK && e != hipSuccess) result = fail(SHAPE3D_EHIP, hipGetErrorString(e));
+  if (result == SHAPE3D_OK) g_err.clear();
+  return result;
 }
 
 }  // namespace
@@ -1212,15 +1509,23 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
   Batch Bt;
   batch_add(Bt, vol, dims, spacing);
   if ((rc = ensure_layout_bufs(w, Bt, dtype))) return rc;
+  long long tcap = 0;
+  if ((rc = ensure_staging(w, dtype, staging_guess(Bt), &tcap))) return rc;
   Ptrs P = w.ptrs();
   if ((rc = upload_rois(w, P, Bt, dtype, nullptr, st))) return rc;
-  if ((rc = launch_head(P, Bt, dtype, st))) return rc;
   char* h = (char*)w.host;
   long long* th = (long long*)h;
   RoiMeta* mh = (RoiMeta*)(h + 1024);
-  HIPCK(hipMemcpyAsync(th, P.p[W_TOTALS], sizeof(long long) * 2, hipMemcpyDeviceToHost, st));
-  HIPCK(hipMemcpyAsync(mh, P.p[W_META], sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
-  HIPCK(hipStreamSynchronize(st));
+  for (int pass = 0;; ++pass) {
+    if ((rc = launch_head(P, Bt, dtype, tcap, st))) return rc;
+    HIPCK(hipMemcpyAsync(th, P.p[W_TOTALS], sizeof(long long) * 9, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(mh, P.p[W_META], sizeof(RoiMeta), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (th[8] <= tcap || pass > 0) break;
+    if ((rc = ensure_staging(w, dtype, th[8], &tcap))) return rc;
+    P = w.ptrs();
+  }
+  if (th[8] > tcap) return fail(SHAPE3D_EINTERNAL, "the mesh pass's staging list overflowed twice");
   const long long V = mh->V;
   *n_out = V;
   if (V > cap) return fail(SHAPE3D_ECAPACITY, "vertex buffer too small");
@@ -1228,14 +1533,8 @@ int shape3d_vertices(const void* vol, int dtype, const int64_t dims[3], const do
   Sizes S;
   if ((rc = ensure_vertex_bufs(w, Bt, dtype, th[0], S))) return rc;
   P = w.ptrs();
-  HIPCK(launch_check_capacity(1, S.rows0, P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
-                              P.as<unsigned int>(W_COUNTERS) + 2, st));
-  HIPCK(launch_mesh_emit(dtype, P.as<const Roi>(W_ROIS), 1, Bt.nbricks, Bt.max_G, P.as<const BrickPart>(W_PART),
-                         P.as<const long long>(W_BRICK_VOFF), P.as<const RoiMeta>(W_META),
-                         P.as<const unsigned int>(W_COUNTERS) + 2, P.as<unsigned long long>(W_KEY),
-                         dtype == SHAPE3D_F32 ? P.as<double>(W_TSOFT) : nullptr, P.as<float>(W_POS),
-                         g_tune.kernel == 1 ? P.as<uint4>(W_POSH) : nullptr, P.as<int>(W_ORIG), P.as<int>(W_BLKSEG),
-                         P.as<Seg>(W_SEGS), st));
+  if ((rc = launch_rows(P, Bt, dtype, S.rows0, tcap, g_tune.kernel == 1 ? P.as<uint4>(W_POSH) : nullptr, st)))
+    return rc;
   HIPCK(launch_export_vertices(P.as<const unsigned long long>(W_KEY),
                                dtype == SHAPE3D_F32 ? P.as<const double>(W_TSOFT) : nullptr,
                                P.as<const RoiMeta>(W_META), P.as<const Roi>(W_ROIS), (long long*)ids, pos, V, st));
@@ -1399,6 +1698,34 @@ int shape3d_batched_dev(const void* base, int dtype, const shape3d_roi_ex* rois,
                           (hipStream_t)stream);
 }
 
+int shape3d_host_stream(const void* const* vols, int dtype, const int64_t* dims, const double* spacing, int64_t n,
+                        double* out, int* status, int flags, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (flags & ~SHAPE3D_SHAPE_CLASS) return fail(SHAPE3D_EINVAL, "unknown flags");
+  return host_stream_impl(vols, dtype, dims, spacing, n, out, status, flags, (hipStream_t)stream);
+}
+
+int shape3d_label_rois(const uint8_t* labels, const int64_t dims[3], const double spacing[3], int32_t max_label,
+                       shape3d_roi_ex* rois, int64_t* voxel_counts, int64_t* max_dims, void* stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (max_label < 1 || max_label > 255) return fail(SHAPE3D_EINVAL, "max_label must be in 1..255");
+  int rc = check_args(labels, SHAPE3D_U8, dims, spacing);
+  if (rc) return rc;
+  if ((rc = check_device_span(rois, sizeof(shape3d_roi_ex) * (size_t)max_label, "ROI table"))) return rc;
+  if ((uintptr_t)rois % 8) return fail(SHAPE3D_EINVAL, "misaligned ROI table");
+  if (voxel_counts && (rc = check_device_span(voxel_counts, sizeof(int64_t) * (size_t)max_label, "voxel_counts")))
+    return rc;
+  if (max_dims && (rc = check_device_span(max_dims, sizeof(int64_t) * 3, "max_dims"))) return rc;
+  int dev = 0, cu = 0;
+  HIPCK(hipGetDevice(&dev));
+  if ((rc = device_cu_count(dev, &cu))) return rc;
+  const long long d[3] = {dims[0], dims[1], dims[2]};
+  HIPCK(launch_label_rois(labels, d, spacing, max_label, (RoiDesc*)rois, (long long*)voxel_counts,
+                          (long long*)max_dims, cu, (hipStream_t)stream));
+  g_err.clear();
+  return SHAPE3D_OK;
+}
+
 const char* shape3d_last_error(void) { return g_err.c_str(); }
 
 int shape3d_release(void) {
@@ -1416,6 +1743,15 @@ int shape3d_release(void) {
     for (Buf* b : w->soft_bufs())
       if (b->p) (void)hipFree(b->p);
     if (w->host) (void)hipHostFree(w->host);
+    if (w->small_slots.p) (void)hipFree(w->small_slots.p);
+    for (int i = 0; i < 2; ++i) {
+      if (w->hs_vol[i].p) (void)hipFree(w->hs_vol[i].p);
+      if (w->hs_pin[i]) (void)hipHostFree(w->hs_pin[i]);
+    }
+    if (w->hs_copy) {
+      (void)hipStreamDestroy(w->hs_copy);
+      for (hipEvent_t e : w->hs_ev) (void)hipEventDestroy(e);
+    }
     for (int i = 0; i < 8; ++i)
       if (w->events) (void)hipEventDestroy(w->ev[i]);
     (void)hipSetDevice(cur);
@@ -1433,13 +1769,14 @@ int shape3d_get_tuning(shape3d_tuning* t) {
   t->blocks_per_cu = g_tune.blocks_per_cu;
   t->kernel = g_tune.kernel;
   t->prune = g_tune.prune;
+  t->small_path = g_tune.small_path;
   return SHAPE3D_OK;
 }
 
 int shape3d_set_tuning(const shape3d_tuning* t) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!t) return fail(SHAPE3D_EINVAL, "null argument");
-  const Tuning c{t->itile_blocks, t->jchunk_blocks, t->blocks_per_cu, t->kernel, t->prune};
+  const Tuning c{t->itile_blocks, t->jchunk_blocks, t->blocks_per_cu, t->kernel, t->prune, t->small_path};
   if (!valid_tuning(c)) return fail(SHAPE3D_EINVAL, "unsupported tile sizes");
   g_tune = c;
   for (auto& kv : g_ws) drop_graphs(*kv.second);  // recorded graphs hold the old tiles
@@ -1460,6 +1797,7 @@ int shape3d_autotune(const void* base, int dtype, const shape3d_roi* rois, int64
   best->blocks_per_cu = b.blocks_per_cu;
   best->kernel = b.kernel;
   best->prune = b.prune;
+  best->small_path = b.small_path;
   *best_ms = ms;
   g_err.clear();
   return SHAPE3D_OK;

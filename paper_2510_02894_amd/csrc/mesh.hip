@@ -25,6 +25,8 @@
 // and independent of the order of the work.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #define MC_TABLE_QUAL __constant__ const
 #include "mc_table.h"
 #include "s3d_device.h"
@@ -105,7 +107,7 @@ __device__ inline double soft_value(const Roi& R, int z, int y, int x) {
 }
 
 // A brick is kBrickThreads consecutive row-groups (rg = cube row * G + group)
-// times up to kTZ cube planes.  Its workgroup first loads, as bit masks, every
+// times up to R.tz (at most kTZ) cube planes.  Its workgroup first loads, as bit masks, every
 // voxel row-group it needs into LDS: planes pz0-1 .. pz1-1 and row-groups
 // rg0-1 .. rg0+kBrickThreads+G-1 (the row after each cube row, and the word
 // before the first group for the x-1 voxel).  All these loads are issued at
@@ -122,8 +124,8 @@ __device__ inline Tile tile_of(const Roi& R, long long local_brick) {
   Tile T;
   const int bx = (int)(local_brick / R.nzc), zc = (int)(local_brick % R.nzc);
   T.rg0 = bx * kBrickThreads;
-  T.pz0 = zc * kTZ;
-  T.pz1 = min(T.pz0 + kTZ, R.d[0] + 1);
+  T.pz0 = zc * R.tz;
+  T.pz1 = min(T.pz0 + R.tz, R.d[0] + 1);
   T.np = T.pz1 - T.pz0 + 1;
   T.nw = kBrickThreads + 1 + R.G;
   return T;
@@ -334,9 +336,7 @@ __device__ inline int case_of(const Corners& C, int k) {
 // Binary masks: area of each case's triangles for each ROI's spacing (one
 // workgroup per ROI, one thread per case), read by every brick of the ROI.
 
-__global__ __launch_bounds__(256) void k_case_area(const Roi* __restrict__ rois, double* __restrict__ case_area) {
-  const Roi& R = rois[blockIdx.x];
-  const int c = threadIdx.x;
+__device__ inline double case_area_of(const Roi& R, int c) {
   const int nt = MC_NTRI[c];
   double a = 0.0;
   for (int t = 0; t < nt; ++t) {
@@ -345,18 +345,59 @@ __global__ __launch_bounds__(256) void k_case_area(const Roi* __restrict__ rois,
     const double n2 = R.s[0] * R.s[1] * MC_TRI_N[c][t][2];
     a += 0.125 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
   }
-  case_area[(size_t)blockIdx.x * 256 + c] = a;
+  return a;
+}
+
+__global__ __launch_bounds__(256) void k_case_area(const Roi* __restrict__ rois, int n_rois,
+                                                   double* __restrict__ case_area) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  case_area[i] = case_area_of(rois[blockIdx.x], (int)threadIdx.x);
+  case_hist(case_area, n_rois)[i] = 0ull;
+}
+
+// The small-mesh path's first launch (one workgroup): the ROI record, the
+// cleared staged-row count and pair-kernel accumulators, and (binary masks)
+// the per-case areas and cleared case counts.
+__global__ __launch_bounds__(256) void k_small_head(Roi R, Roi* __restrict__ rois, long long* __restrict__ totals,
+                                                    SmallAcc* __restrict__ acc, double* __restrict__ case_area) {
+  if (threadIdx.x == 0) {
+    rois[0] = R;
+    totals[8] = 0;
+    SmallAcc A;
+    for (int g = 0; g < 4; ++g) {
+      A.gmax[g] = 0ull;
+      A.key[g] = ~0ull;
+    }
+    A.pairs2d = 0ull;
+    A.ticket = 0u;
+    A.pad_ = 0u;
+    *acc = A;
+  }
+  if (case_area) {
+    case_area[threadIdx.x] = case_area_of(R, (int)threadIdx.x);
+    case_hist(case_area, 1)[threadIdx.x] = 0ull;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Count pass.
+// The mesh pass: one read of the volume per brick gives its vertex and
+// triangle counts, area, volume, bounding box and moments, and writes the
+// canonical keys of its vertices (and soft masks' interpolation parameters)
+// to a staging list, at a range of rows the brick reserves with one atomic
+// (below `tmp_cap` rows; totals[8] counts them all).  Within a brick the order
+// is (thread, plane, axis, cube); the row pass then places each brick's rows
+// at its offset in brick order, so the final order does not depend on the
+// order of the reservations.
 
 template <int DT>
-__global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restrict__ rois, int n_rois,
-                                                              long long nbricks, const double* __restrict__ case_area,
-                                                              BrickPart* __restrict__ part, int moments) {
+__global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restrict__ rois, int n_rois,
+                                                             long long nbricks, double* __restrict__ case_area,
+                                                             BrickPart* __restrict__ part,
+                                                             unsigned long long* __restrict__ tmpkey,
+                                                             double* __restrict__ tmpt, long long tmp_cap,
+                                                             long long* __restrict__ totals, int moments) {
   extern __shared__ uint32_t s_bits[];
-  __shared__ double s_area[256];
+  __shared__ unsigned int s_hist[256];  // binary masks: active cubes per case
   __shared__ int s_tk[256];
   __shared__ int s_tm[256];
   __shared__ uint32_t s_items[kMeshItems];
@@ -366,6 +407,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   __shared__ long long s_rl[4];
   __shared__ int s_ri[8][4];
   __shared__ long long s_mom[10][4];
+  __shared__ long long s_base;
 
   const long long brick = xcd_remap(blockIdx.x, nbricks);
   const int roi = find_roi(rois, n_rois, brick);
@@ -376,7 +418,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   {
     const int c = tid;
     const int nt = MC_NTRI[c];
-    s_area[c] = DT == 0 ? case_area[(size_t)roi * 256 + c] : 0.0;
+    s_hist[c] = 0u;
     s_tk[c] = nt | ((MC_CASE_KAPPA[c] + 128) << 8);
     s_tm[c] = (MC_CASE_M[c][0] + 128) | ((MC_CASE_M[c][1] + 128) << 8) | ((MC_CASE_M[c][2] + 128) << 16);
   }
@@ -403,7 +445,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
   // brick takes a few barriers instead of a few per plane.
   static_assert(kTZ <= 8, "an item holds the plane in 3 bits");
   uint32_t act[kTZ];
-  int cnt = 0;
+  uint32_t ed[kTZ][3];  // crossing edges along axis 0, 1, 2 from each cube's corner 0
+  int cnt = 0, cnt_e = 0;
   long long mom[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
     uint32_t rr[kTZ + 1][2], xx[kTZ + 1][2];
@@ -422,6 +465,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
 #pragma unroll
     for (int p = 0; p < kTZ; ++p) {
       act[p] = 0u;
+      ed[p][0] = ed[p][1] = ed[p][2] = 0u;
       if (L.valid && p + 1 < T.np) {
         const Corners C = make_corners(rr[p][0], xx[p][0], rr[p][1], xx[p][1], rr[p + 1][0], xx[p + 1][0],
                                        rr[p + 1][1], xx[p + 1][1]);
@@ -431,8 +475,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
           any |= C.c[c];
           all &= C.c[c];
         }
-        nv += __popc((C.c[0] ^ C.c[4]) & L.vmask) + __popc((C.c[0] ^ C.c[2]) & L.vmask) +
-              __popc((C.c[0] ^ C.c[1]) & L.vmask);
+        ed[p][0] = (C.c[0] ^ C.c[4]) & L.vmask;
+        ed[p][1] = (C.c[0] ^ C.c[2]) & L.vmask;
+        ed[p][2] = (C.c[0] ^ C.c[1]) & L.vmask;
         const uint32_t active = any & ~all & L.vmask;
         if (active) {
           const int z = T.pz0 - 1 + p;
@@ -446,6 +491,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
         act[p] = active;
       }
       cnt += __popc(act[p]);
+      cnt_e += __popc(ed[p][0]) + __popc(ed[p][1]) + __popc(ed[p][2]);
     }
     if (moments && L.valid) {
       // voxel row (z, y) = (pz0 + p, L.y + 1), x = 32 l + bit, is word rr[p + 1][1]
@@ -478,6 +524,12 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
       mom[9] = y * sx;
     }
   }
+  // the brick's staged rows: one reservation
+  int total_e;
+  const int off_e = block_excl_scan256(cnt_e, s_scan, total_e);
+  nv = cnt_e;
+  if (tid == 0)
+    s_base = total_e ? (long long)atomicAdd((unsigned long long*)&totals[8], (unsigned long long)total_e) : 0;
   int total;
   const int off = block_excl_scan256(cnt, s_scan, total);
   for (int c0 = 0; c0 < total; c0 += kMeshItems) {
@@ -514,7 +566,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
       nt += tk & 0xff;
       if (DT == 0) {
         const int tm = s_tm[cas];
-        area += s_area[cas];
+        atomicAdd(&s_hist[cas], 1u);
         vol_i += (long long)((tk >> 8) - 128) +
                  2ll * ((long long)z * ((tm & 0xff) - 128) + (long long)y * (((tm >> 8) & 0xff) - 128) +
                         (long long)x * (((tm >> 16) & 0xff) - 128));
@@ -544,6 +596,49 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
           const double bcy = P[1][2] * P[2][0] - P[1][0] * P[2][2];
           const double bcz = P[1][0] * P[2][1] - P[1][1] * P[2][0];
           vol_d += (P[0][0] * bcx + P[0][1] * bcy + P[0][2] * bcz) / 6.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  __syncthreads();
+  const long long base = s_base;
+  for (int c0 = 0; c0 < total_e; c0 += kMeshItems) {
+    // this thread's edges with index in [c0, c0 + kMeshItems): (thread, plane, axis, cube)
+    int idx = off_e;
+#pragma unroll
+    for (int p = 0; p < kTZ; ++p)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        uint32_t m = ed[p][a];
+        const int nm = __popc(m);
+        if (idx + nm <= c0 || idx >= c0 + kMeshItems) {
+          idx += nm;
+          continue;
+        }
+        while (m && idx < c0 + kMeshItems) {
+          const int k = __ffs(m) - 1;
+          m &= m - 1u;
+          if (idx >= c0)
+            s_items[idx - c0] = ((uint32_t)tid << 10) | ((uint32_t)p << 7) | ((uint32_t)a << 5) | (uint32_t)k;
+          ++idx;
+        }
+      }
+    __syncthreads();
+    const int n = min(kMeshItems, total_e - c0);
+    for (int i = tid; i < n; i += kBrickThreads) {
+      const uint32_t it = s_items[i];
+      const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), p = (int)((it >> 7) & 7u), t = (int)(it >> 10);
+      const uint32_t ly = s_ly[t];
+      const int u0 = T.pz0 - 1 + p, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * (int)(ly >> 20) - 1 + k;
+      const long long row = base + c0 + i;
+      if (row < tmp_cap) {
+        tmpkey[row] = pack_key(u0, u1, u2, a);
+        if (DT == 1) {
+          const double pa = soft_value(R, u0, u1, u2);
+          const double pb = soft_value(R, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
+          tmpt[row] = (0.5 - pa) / (pb - pa);
         }
       }
     }
@@ -585,13 +680,20 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_count(const Roi* __restr
     P.vol_d = ((s_rd[1][0] + s_rd[1][1]) + s_rd[1][2]) + s_rd[1][3];
     P.vol_i = s_rl[0] + s_rl[1] + s_rl[2] + s_rl[3];
     for (int k = 0; k < 10; ++k) P.mom[k] = s_mom[k][0] + s_mom[k][1] + s_mom[k][2] + s_mom[k][3];
+    P.stage = base;
     part[brick] = P;
+  }
+  if (DT == 0) {
+    // the area follows from the case counts (summed per ROI in a fixed order
+    // later), so it does not depend on how the ROI is cut into bricks
+    const unsigned int h = s_hist[tid];
+    if (h) atomicAdd(&case_hist(case_area, n_rois)[(size_t)roi * 256 + tid], (unsigned long long)h);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Per-ROI totals: exclusive scan of brick vertex counts, fixed-order sums.
-// One 1024-thread workgroup per ROI.
+// Per-ROI totals: exclusive scan of brick vertex counts (each brick's first
+// row within its ROI), fixed-order sums.  One 1024-thread workgroup per ROI.
 
 // 128-bit sum over a wave (two's complement halves, carry from the low half).
 __device__ inline __int128 wave_sum_i128(__int128 v) {
@@ -621,10 +723,12 @@ __device__ inline double cov_entry(const __int128* S, const double* sp, int k) {
 }
 
 __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ rois, int n_rois, long long nbricks,
-                                                      int dtype, const BrickPart* __restrict__ part,
-                                                      long long* __restrict__ brick_voff, RoiMeta* __restrict__ meta,
-                                                      int moments) {
+                                                      int dtype, const double* __restrict__ case_area,
+                                                      const BrickPart* __restrict__ part,
+                                                      long long* __restrict__ brick_voff,
+                                                      RoiMeta* __restrict__ meta, int moments) {
   __shared__ long long s_l[2][1024];
+  __shared__ long long s_l2[1024];
   __shared__ double s_d[2][1024];
   __shared__ int s_b[6][1024];
   __shared__ __int128 s_m[10][16];
@@ -666,7 +770,7 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
     brick_voff[b] = off;
     off += part[b].nv;
   }
-  const long long V = s_l[src][1023];
+  s_l2[tid] = s_l[src][1023];
   __syncthreads();
   // fixed-order tree reductions
   s_l[0][tid] = nt;
@@ -688,13 +792,17 @@ __global__ __launch_bounds__(1024) void k_mesh_totals(const Roi* __restrict__ ro
     }
     __syncthreads();
   }
+  // binary masks: the area from the case counts (s_d[1] is free for them)
+  if (dtype == 0)
+    binary_area_tree(case_area + (size_t)r * 256, case_hist(case_area, n_rois) + (size_t)r * 256, s_d[1]);
   if (tid == 0) {
+    const long long V = s_l2[0];
     RoiMeta M;
     M.V = V;
     M.T = s_l[0][0];
     M.row_off = 0;
     M.V_pad = (V + kSegAlign - 1) / kSegAlign * kSegAlign;
-    M.area = s_d[0][0];
+    M.area = dtype == 0 ? s_d[1][0] : s_d[0][0];
     M.vol = dtype == 0 ? (double)s_l[1][0] * (R.s[0] * R.s[1] * R.s[2] / 48.0) : s_d[1][0];
     double R2 = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -803,15 +911,26 @@ __global__ __launch_bounds__(1024) void k_roi_rows(int n_rois, RoiMeta* __restri
 // Refuses a call whose vertex rows exceed the rows the buffers were sized for
 // (possible when a captured graph is replayed on new mask contents): raises
 // the overflow flag and empties every ROI, so all later kernels do no work.
+// Then writes each ROI's 3D segment (its layout-0 rows when it has pairs).
 __global__ void k_check_capacity(int n_rois, long long rows0_cap, RoiMeta* __restrict__ meta,
-                                 long long* __restrict__ totals, unsigned int* __restrict__ overflow) {
-  if (totals[0] <= rows0_cap) return;
+                                 long long* __restrict__ totals, unsigned int* __restrict__ overflow,
+                                 Seg* __restrict__ segs) {
+  const bool over = totals[0] > rows0_cap;
+  __syncthreads();
   for (int r = threadIdx.x; r < n_rois; r += blockDim.x) {
-    meta[r].V = 0;
-    meta[r].V_pad = 0;
-    meta[r].row_off = 0;
+    if (over) {
+      meta[r].V = 0;
+      meta[r].V_pad = 0;
+      meta[r].row_off = 0;
+    }
+    Seg S;
+    S.row_begin = meta[r].row_off;
+    S.n_rows = meta[r].V >= 2 ? (int)meta[r].V_pad : 0;
+    S.group = r * 4;
+    segs[r] = S;
   }
-  if (threadIdx.x == 0) {
+  __syncthreads();
+  if (over && threadIdx.x == 0) {
     *overflow = 1u;
     totals[0] = 0;
     totals[1] = 0;
@@ -820,148 +939,84 @@ __global__ void k_check_capacity(int n_rois, long long rows0_cap, RoiMeta* __res
 }
 
 // ---------------------------------------------------------------------------
-// Emission pass: the same classification, writing each crossing edge's vertex
-// at its deterministic row (brick order, then thread, plane, axis, cube).
+// Row layout: one workgroup per brick moves the brick's staged vertices to
+// layout 0, at the ROI's first row plus the brick's offset within its ROI
+// (rows in brick order, then the staging order within the brick), with the
+// pair pass's operands: the position minus the ROI's centre, rounded to FP32,
+// either as FP32 position blocks or as the split-f16 operand row; and the
+// 16-row block tags.  The brick that holds a ROI's last vertex pads the ROI
+// to a multiple of 32 rows with copies of that vertex.
 
-template <int DT>
-__global__ __launch_bounds__(kBrickThreads) void k_mesh_emit(const Roi* __restrict__ rois, int n_rois,
-                                                             long long nbricks, const BrickPart* __restrict__ part,
-                                                             const long long* __restrict__ brick_voff,
-                                                             const RoiMeta* __restrict__ meta,
-                                                             const unsigned int* __restrict__ overflow,
-                                                             unsigned long long* __restrict__ key,
-                                                             double* __restrict__ tsoft, float* __restrict__ pos,
-                                                             uint4* __restrict__ posh, int* __restrict__ orig) {
-  extern __shared__ uint32_t s_bits[];
-  __shared__ int s_scan[4];
-  __shared__ uint32_t s_items[kMeshItems];
-  __shared__ uint32_t s_ly[kBrickThreads];  // (y + 1) | l << 20 of each thread's row-group
-  const long long brick = xcd_remap(blockIdx.x, nbricks);
-  const int roi = find_roi(rois, n_rois, brick);
-  const Roi R = rois[roi];
-  if (brick >= R.brick_end || *overflow != 0u || part[brick].nv == 0) return;
-  const RoiMeta M = meta[roi];
-  const int tid = threadIdx.x;
-  const Tile T = tile_of(R, brick - R.brick_begin);
-  load_tile<DT>(R, T, s_bits);
-  __syncthreads();
-  const Lane L = lane_of(R, T, tid);
-  s_ly[tid] = (uint32_t)(L.y + 1) | ((uint32_t)L.l << 20);  // read back by the dense loop (after a barrier)
-  const long long base = M.row_off + brick_voff[brick];
-  const int e_split = h_scale_exp(M.R2);  // scale exponent of the split-f16 operands
-  // All planes at once, as in the count pass: each thread lists the crossing
-  // edges of its 32 cubes for every plane pair, one block scan places them,
-  // and the listed edges are written by consecutive threads to consecutive
-  // rows, so the stores of a wave are contiguous.
-  uint32_t e[kTZ][3];
-  int cnt = 0;
-  {
-    uint32_t rr[kTZ + 1][2], xx[kTZ + 1][2];
-#pragma unroll
-    for (int p = 0; p <= kTZ; ++p)
-#pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        rr[p][dy] = 0u;
-        xx[p][dy] = 0u;
-        if (L.valid && p < T.np) {
-          const int w = p * T.nw + tid + 1 + dy * R.G;
-          rr[p][dy] = s_bits[w];
-          xx[p][dy] = L.l > 0 ? (s_bits[w - 1] >> 31) : 0u;
-        }
-      }
-#pragma unroll
-    for (int p = 0; p < kTZ; ++p) {
-      // corner 0 of the cube is (rr[p][0] << 1 | xx[p][0]); its neighbours
-      // along axis 0, 1 and 2 are corners 4, 2 and 1
-      const uint32_t corner0 = (rr[p][0] << 1) | xx[p][0];
-      const bool on = L.valid && p + 1 < T.np;
-      e[p][0] = on ? (corner0 ^ ((rr[p + 1][0] << 1) | xx[p + 1][0])) & L.vmask : 0u;
-      e[p][1] = on ? (corner0 ^ ((rr[p][1] << 1) | xx[p][1])) & L.vmask : 0u;
-      e[p][2] = on ? (corner0 ^ rr[p][0]) & L.vmask : 0u;
-      cnt += __popc(e[p][0]) + __popc(e[p][1]) + __popc(e[p][2]);
-    }
+__device__ inline void put_row(const Roi& R, const RoiMeta& M, long long row, unsigned long long k, double tv,
+                               unsigned long long* __restrict__ key, double* __restrict__ tsoft,
+                               float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
+                               long long src_row) {
+  key[row] = k;
+  if (tsoft) tsoft[row] = tv;
+  const int u0 = (int)((k >> 40) & 0xFFFFF) - 1, u1 = (int)((k >> 20) & 0xFFFFF) - 1, u2 = (int)(k & 0xFFFFF) - 1;
+  const int a = (int)((k >> 60) & 3);
+  const double px = ((double)u0 + (a == 0 ? tv : 0.0)) * R.s[0] - M.center[0];
+  const double py = ((double)u1 + (a == 1 ? tv : 0.0)) * R.s[1] - M.center[1];
+  const double pz = ((double)u2 + (a == 2 ? tv : 0.0)) * R.s[2] - M.center[2];
+  const float fx = (float)px, fy = (float)py, fz = (float)pz;
+  const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
+  if (posh) {
+    write_split_row(posh, row, fx, fy, fz, fw, h_scale_exp(M.R2));
+  } else {
+    float* blk = pos + (row >> 4) * 64 + (row & 15);
+    blk[0] = fx;
+    blk[16] = fy;
+    blk[32] = fz;
+    blk[48] = fw;
   }
-  int total;
-  const int off = block_excl_scan256(cnt, s_scan, total);
-  for (int c0 = 0; c0 < total; c0 += kMeshItems) {
-    // this thread's items with index in [c0, c0 + kMeshItems): (thread, plane, axis, cube)
-    int idx = off;
-#pragma unroll
-    for (int p = 0; p < kTZ; ++p)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        uint32_t m = e[p][a];
-        const int nm = __popc(m);
-        if (idx + nm <= c0 || idx >= c0 + kMeshItems) {
-          idx += nm;
-          continue;
-        }
-        while (m && idx < c0 + kMeshItems) {
-          const int k = __ffs(m) - 1;
-          m &= m - 1u;
-          if (idx >= c0)
-            s_items[idx - c0] = ((uint32_t)tid << 10) | ((uint32_t)p << 7) | ((uint32_t)a << 5) | (uint32_t)k;
-          ++idx;
-        }
-      }
-    __syncthreads();
-    const int n = min(kMeshItems, total - c0);
-    for (int i = tid; i < n; i += kBrickThreads) {
-      const uint32_t it = s_items[i];
-      const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), p = (int)((it >> 7) & 7u), t = (int)(it >> 10);
-      const uint32_t ly = s_ly[t];
-      const int u0 = T.pz0 - 1 + p, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * (int)(ly >> 20) - 1 + k;
-      const long long row = base + c0 + i;
-      double tv = 0.5;
-      if (DT == 1) {
-        const double pa = soft_value(R, u0, u1, u2);
-        const double pb = soft_value(R, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
-        tv = (0.5 - pa) / (pb - pa);
-        tsoft[row] = tv;
-      }
-      key[row] = pack_key(u0, u1, u2, a);
-      const double px = ((double)u0 + (a == 0 ? tv : 0.0)) * R.s[0] - M.center[0];
-      const double py = ((double)u1 + (a == 1 ? tv : 0.0)) * R.s[1] - M.center[1];
-      const double pz = ((double)u2 + (a == 2 ? tv : 0.0)) * R.s[2] - M.center[2];
-      const float fx = (float)px, fy = (float)py, fz = (float)pz;
-      const float fw = (float)((double)fx * fx + (double)fy * fy + (double)fz * fz);
-      if (posh) {
-        write_split_row(posh, row, fx, fy, fz, fw, e_split);
-      } else {
-        float* blk = pos + (row >> 4) * 64 + (row & 15);
-        blk[0] = fx;
-        blk[16] = fy;
-        blk[32] = fz;
-        blk[48] = fw;
-      }
-      orig[row] = (int)row;
+  orig[row] = (int)src_row;
+}
+
+__global__ __launch_bounds__(256) void k_mesh_rows(const Roi* __restrict__ rois, int n_rois, long long nbricks,
+                                                   const BrickPart* __restrict__ part,
+                                                   const long long* __restrict__ brick_voff,
+                                                   const RoiMeta* __restrict__ meta,
+                                                   const unsigned long long* __restrict__ tmpkey,
+                                                   const double* __restrict__ tmpt, long long tmp_cap,
+                                                   unsigned long long* __restrict__ key, double* __restrict__ tsoft,
+                                                   float* __restrict__ pos, uint4* __restrict__ posh,
+                                                   int* __restrict__ orig, int* __restrict__ blkseg,
+                                                   unsigned int* __restrict__ overflow) {
+  const long long brick = blockIdx.x;
+  if (brick >= nbricks) return;
+  const int r = find_roi(rois, n_rois, brick);
+  const Roi& R = rois[r];
+  if (brick >= R.brick_end) return;
+  const RoiMeta& M = meta[r];
+  const long long cnt = part[brick].nv, first = brick_voff[brick];
+  // an emptied ROI (capacity exceeded), or a brick whose rows do not fit its ROI's count
+  if (cnt == 0 || M.V == 0 || first + cnt > M.V) return;
+  const long long src = part[brick].stage;
+  if (src + cnt > tmp_cap) {  // staged beyond the list (a replay on larger meshes): refused
+    if (threadIdx.x == 0) *overflow = 1u;
+    return;
+  }
+  const long long dst = M.row_off + first;
+  for (long long i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const long long row = dst + i;
+    put_row(R, M, row, tmpkey[src + i], tsoft ? tmpt[src + i] : 0.5, key, tsoft, pos, posh, orig, row);
+    if ((row & 15) == 0 || i == 0) blkseg[row >> 4] = r;  // a block shared with a neighbour gets the same tag
+  }
+  if (first + cnt == M.V) {  // the ROI's last vertex: pad to V_pad rows with copies of it
+    const long long last = M.row_off + M.V - 1;
+    const unsigned long long k = tmpkey[src + cnt - 1];
+    const double tv = tsoft ? tmpt[src + cnt - 1] : 0.5;
+    for (long long row = M.row_off + M.V + threadIdx.x; row < M.row_off + M.V_pad; row += blockDim.x) {
+      put_row(R, M, row, k, tv, key, tsoft, pos, posh, orig, last);
+      if ((row & 15) == 0) blkseg[row >> 4] = r;
     }
-    __syncthreads();
   }
 }
 
-// Pads each ROI's layout-0 rows to V_pad with copies of its first row and
-// tags the ROI's blocks with its 3D segment (segment id = roi).
-__global__ void k_pad_layout0(int n_rois, const RoiMeta* __restrict__ meta, float* __restrict__ pos,
-                              uint4* __restrict__ posh, int* __restrict__ orig, int* __restrict__ blkseg,
-                              Seg* __restrict__ segs) {
-  const int r = blockIdx.x;
-  if (r >= n_rois) return;
-  const RoiMeta M = meta[r];
-  const long long r0 = M.row_off;
-  if (threadIdx.x == 0) {
-    Seg S;
-    S.row_begin = r0;
-    S.n_rows = M.V >= 2 ? (int)M.V_pad : 0;
-    S.group = r * 4;
-    segs[r] = S;
-  }
-  for (long long i = threadIdx.x; i < M.V_pad / kBlk; i += blockDim.x) blkseg[r0 / kBlk + i] = r;
-  if (M.V == 0) return;
-  for (long long row = r0 + M.V + threadIdx.x; row < r0 + M.V_pad; row += blockDim.x) {
-    copy_row_operands(pos, posh, r0, row);
-    orig[row] = (int)r0;
-  }
+// Clears the call's counters and the staged-row count (totals[8]).
+__global__ void k_head_clear(unsigned int* __restrict__ counters, int n_counters, long long* __restrict__ totals) {
+  for (int i = threadIdx.x; i < n_counters; i += blockDim.x) counters[i] = 0u;
+  if (threadIdx.x == 0) totals[8] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,50 +1110,64 @@ __global__ void k_set_roi(Roi R, Roi* __restrict__ out) {
 
 size_t mesh_lds_bytes(int max_G) { return sizeof(uint32_t) * (size_t)(kTZ + 1) * (kBrickThreads + 1 + max_G); }
 
-hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
-                             double* case_area, BrickPart* part, int moments, hipStream_t st) {
-  if (nbricks <= 0) return hipSuccess;
+hipError_t launch_mesh_pass(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                            double* case_area, BrickPart* part, unsigned int* counters, int n_counters,
+                            unsigned long long* tmpkey, double* tmpt, long long tmp_cap, long long* totals,
+                            int moments, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_clear, dim3(1), dim3(1024), 0, st, counters, n_counters, totals);
+  if (nbricks <= 0) return hipGetLastError();
   const size_t lds = mesh_lds_bytes(max_G);
   if (dtype == 0) {
-    hipLaunchKernelGGL(k_case_area, dim3((unsigned)n_rois), dim3(256), 0, st, rois, case_area);
-    hipLaunchKernelGGL(k_mesh_count<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part, moments);
+    hipLaunchKernelGGL(k_case_area, dim3((unsigned)n_rois), dim3(256), 0, st, rois, n_rois, case_area);
+    hipLaunchKernelGGL(k_mesh_pass<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
   } else {
-    hipLaunchKernelGGL(k_mesh_count<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part, moments);
+    hipLaunchKernelGGL(k_mesh_pass<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
-                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, int prune_min_v,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_mesh_totals, dim3(n_rois), dim3(1024), 0, st, rois, n_rois, nbricks, dtype, part, brick_voff,
+hipError_t launch_small_head(int dtype, const Roi& R, Roi* rois, long long* totals, SmallAcc* acc,
+                             double* case_area, hipStream_t st) {
+  hipLaunchKernelGGL(k_small_head, dim3(1), dim3(256), 0, st, R, rois, totals, acc,
+                     dtype == 0 ? case_area : (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_core(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                            double* case_area, BrickPart* part, unsigned long long* tmpkey, double* tmpt,
+                            long long tmp_cap, long long* totals, int moments, hipStream_t st) {
+  if (nbricks <= 0) return hipGetLastError();
+  const size_t lds = mesh_lds_bytes(max_G);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_mesh_pass<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
+  else
+    hipLaunchKernelGGL(k_mesh_pass<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const double* case_area,
+                              const BrickPart* part, long long* brick_voff, RoiMeta* meta, long long* totals,
+                              int moments, int prune_min_v, hipStream_t st) {
+  hipLaunchKernelGGL(k_mesh_totals, dim3(n_rois), dim3(1024), 0, st, rois, n_rois, nbricks, dtype, case_area, part,
+                     brick_voff,
                      meta, moments);
   hipLaunchKernelGGL(k_roi_rows, dim3(1), dim3(1024), 0, st, n_rois, meta, totals, prune_min_v);
   return hipGetLastError();
 }
 
-hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
-                                 unsigned int* overflow, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(256), 0, st, n_rois, rows0_cap, meta, totals, overflow);
-  return hipGetLastError();
-}
-
-hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
-                            const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
-                            const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
-                            uint4* posh, int* orig, int* blkseg, Seg* segs, hipStream_t st) {
-  const size_t lds = mesh_lds_bytes(max_G);
-  if (nbricks > 0) {
-    if (dtype == 0)
-      hipLaunchKernelGGL(k_mesh_emit<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig);
-    else
-      hipLaunchKernelGGL(k_mesh_emit<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                         part, brick_voff, meta, overflow, key, tsoft, pos, posh, orig);
-  }
-  hipLaunchKernelGGL(k_pad_layout0, dim3(n_rois), dim3(256), 0, st, n_rois, meta, pos, posh, orig, blkseg, segs);
+hipError_t launch_mesh_rows(const Roi* rois, int n_rois, long long nbricks, const BrickPart* part,
+                            const long long* brick_voff, RoiMeta* meta, long long* totals, long long rows0_cap,
+                            const unsigned long long* tmpkey, const double* tmpt, long long tmp_cap,
+                            unsigned long long* key, double* tsoft, float* pos, uint4* posh, int* orig, int* blkseg,
+                            Seg* segs, unsigned int* overflow, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1024), 0, st, n_rois, rows0_cap, meta, totals, overflow, segs);
+  if (nbricks > 0)
+    hipLaunchKernelGGL(k_mesh_rows, dim3((unsigned)nbricks), dim3(256), 0, st, rois, n_rois, nbricks, part,
+                       brick_voff, meta, tmpkey, tmpt, tmp_cap, key, tsoft, pos, posh, orig, blkseg, overflow);
   return hipGetLastError();
 }
 

@@ -57,9 +57,63 @@ __device__ inline void wave_aggregated_inc(unsigned int* counter, long long b) {
   if (group) atomicAdd(&counter[b], group);
 }
 
-__global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
-                              const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
-                              const long long* __restrict__ totals, unsigned int* __restrict__ bcnt) {
+// As wave_aggregated_inc, and the bucket's box of in-plane key coordinates
+// (u, v) (half voxels): the lanes of a group combine their coordinates with
+// LDS atomics in a slot of their leader, which then widens the global box
+// where it has to.  slot: this wave's 64 x 4 ints of LDS.
+__device__ inline void wave_aggregated_inc_box(unsigned int* counter, int4* bbox, long long b, int cu, int cv,
+                                               int* slot) {
+  unsigned long long todo = __ballot(1);
+  const int lane = threadIdx.x & 63;
+  unsigned int group = 0;
+  int lead = lane;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const long long bl = __shfl(b, leader, 64);
+    const unsigned long long same = __ballot(b == bl) & todo;
+    if (b == bl) lead = leader;
+    if (lane == leader) group = (unsigned int)__popcll(same);
+    todo &= ~same;
+  }
+  int* s = slot + 4 * lead;
+  if (group) {
+    s[0] = INT_MAX;
+    s[1] = INT_MIN;
+    s[2] = INT_MAX;
+    s[3] = INT_MIN;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  atomicMin(&s[0], cu);
+  atomicMax(&s[1], cu);
+  atomicMin(&s[2], cv);
+  atomicMax(&s[3], cv);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (group) {
+    atomicAdd(&counter[b], group);
+    // The box only grows, so a bound that an earlier (possibly stale) read
+    // already covers needs no atomic: most groups of a plane skip all four.
+    int* g = (int*)&bbox[b];
+    int cur[4];
+    for (int j = 0; j < 4; ++j) cur[j] = __hip_atomic_load(&g[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (s[0] < cur[0]) atomicMin(&g[0], s[0]);
+    if (s[1] > cur[1]) atomicMax(&g[1], s[1]);
+    if (s[2] < cur[2]) atomicMin(&g[2], s[2]);
+    if (s[3] > cur[3]) atomicMax(&g[3], s[3]);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Bucket counts, and with bbox set the buckets' boxes in key coordinates: a
+// vertex on edge (u, u + e_a) has coordinate 2 u_j + [a == j] along axis j;
+// the box of a bucket of axis k holds the two other axes in increasing order.
+__global__ __launch_bounds__(256) void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
+                                                     const int* __restrict__ blkseg,
+                                                     const unsigned long long* __restrict__ key,
+                                                     const long long* __restrict__ totals,
+                                                     unsigned int* __restrict__ bcnt, int4* __restrict__ bbox) {
+  __shared__ int s_slot[4][64 * 4];
   const long long rows0 = totals[T_ROWS0];
   // the trip count is uniform per wave (rows0 is a multiple of the wave size)
   for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
@@ -70,21 +124,82 @@ __global__ void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __res
       const unsigned long long k = key[row];
       const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};  // u + 1
       const int a = (int)((k >> 60) & 3);
+      const int kc[3] = {2 * (p[0] - 1) + (a == 0), 2 * (p[1] - 1) + (a == 1), 2 * (p[2] - 1) + (a == 2)};
       for (int ax = 0; ax < 3; ++ax) {
-        const long long b = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
-        wave_aggregated_inc(bcnt, b);
+        const long long b = rois[roi].bucket_base[ax] + kc[ax] + 1;
+        if (bbox)
+          wave_aggregated_inc_box(bcnt, bbox, b, kc[ax == 0 ? 1 : 0], kc[ax == 2 ? 1 : 2], s_slot[threadIdx.x >> 6]);
+        else
+          wave_aggregated_inc(bcnt, b);
       }
     }
   }
 }
 
-// Clears the bucket counters and the per-ROI in-plane pair counts (one launch).
+// Whole plane buckets that cannot hold their family's planar diameter are
+// dropped before they are laid out (one workgroup per ROI).  For a family
+// (an axis k of a ROI) the two vertices of a bucket with the smallest and the
+// largest coordinate along an in-plane axis are a pair of the family, so the
+// largest such extent of any bucket, L, bounds the diameter from below; a
+// bucket whose box diagonal U satisfies U^2 < L^2 (1 - 2^-20) holds no pair
+// that reaches it.  Binary masks: positions are exactly the key coordinates
+// times half the spacing.  Soft masks: a vertex lies within half a voxel of
+// its key coordinate along its edge's axis, so L uses each extent less one
+// voxel, U each extent plus one voxel and, in a bucket of edges along k, one
+// voxel along k.  A dropped bucket's count is set to 0 (its in-plane pairs
+// still enter the pair statistics).
+__global__ __launch_bounds__(256) void k_bucket_prune(const Roi* __restrict__ rois, int soft,
+                                                      unsigned int* __restrict__ bcnt, const int4* __restrict__ bbox,
+                                                      long long* __restrict__ pairs2d) {
+  __shared__ double s_red[4];
+  const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const Roi& R = rois[r];
+  const double w = soft ? 1.0 : 0.0;
+  long long dropped_pairs = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int ju = ax == 0 ? 1 : 0, jv = ax == 2 ? 1 : 2;
+    const double su = R.s[ju], sv = R.s[jv], sk = R.s[ax];
+    const long long b0 = R.bucket_base[ax], nb = 2ll * R.d[ax] + 1;
+    double L2 = 0.0;
+    for (long long i = tid; i < nb; i += 256) {
+      if (bcnt[b0 + i] < 2u) continue;
+      const int4 q = bbox[b0 + i];
+      const double eu = fmax(0.0, 0.5 * (double)(q.y - q.x) - w) * su;
+      const double ev = fmax(0.0, 0.5 * (double)(q.w - q.z) - w) * sv;
+      L2 = fmax(L2, fmax(eu * eu, ev * ev));
+    }
+    for (int m = 32; m >= 1; m >>= 1) L2 = fmax(L2, __shfl_xor(L2, m, 64));
+    if (lane == 0) s_red[wid] = L2;
+    __syncthreads();
+    L2 = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+    __syncthreads();
+    const double thr = L2 * (1.0 - 9.5367431640625e-07);  // 1 - 2^-20
+    for (long long i = tid; i < nb; i += 256) {
+      const unsigned int c = bcnt[b0 + i];
+      if (c < 2u) continue;
+      const int4 q = bbox[b0 + i];
+      const double uu = (0.5 * (double)(q.y - q.x) + w) * su;
+      const double vv = (0.5 * (double)(q.w - q.z) + w) * sv;
+      const double kk = (soft && (i & 1) == 0) ? sk : 0.0;  // bucket index i = key + 1: odd key <=> even i
+      if (uu * uu + vv * vv + kk * kk < thr) {
+        bcnt[b0 + i] = 0u;
+        dropped_pairs += (long long)c * (c - 1) / 2;
+      }
+    }
+  }
+  dropped_pairs = wave_sum(dropped_pairs);
+  if (lane == 0 && dropped_pairs) atomicAdd((unsigned long long*)&pairs2d[r], (unsigned long long)dropped_pairs);
+}
+
+// Clears the bucket counters, boxes (if any) and the per-ROI in-plane pair
+// counts (one launch).
 __global__ void k_zero_buckets(unsigned int* __restrict__ bcnt, unsigned int* __restrict__ bcur, long long nb,
-                               long long* __restrict__ pairs2d, long long n_rois) {
+                               long long* __restrict__ pairs2d, long long n_rois, int4* __restrict__ bbox) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) {
     bcnt[i] = 0u;
     bcur[i] = 0u;
+    if (bbox) bbox[i] = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
   }
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n_rois; i += stride) pairs2d[i] = 0;
 }
@@ -992,10 +1107,19 @@ uint4* split_rows(const PairBufs& B) { return B.tune.kernel == 1 ? B.posh : null
 
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipError_t e;
+  // Whole plane buckets are pruned with the pair tiles in calls with many
+  // buckets: their boxes cost the histogram pass four more atomics per group
+  // of lanes, which the pruned scatter and pair work repay on a batch of
+  // small ROIs (4,096 ROIs: 19.3 -> 19.0 ms) but not on one large ROI
+  // (2,651 buckets: 0.83 -> 0.95 ms).
+  int4* bbox = B.prune && B.n_buckets >= kSmallMinBuckets ? B.bbox : nullptr;
   hipLaunchKernelGGL(k_zero_buckets, dim3(grid_for(std::max<long long>(B.n_buckets, B.n_rois), 4096)), dim3(256), 0,
-                     st, B.bcnt, B.bcur, B.n_buckets, B.pairs2d, (long long)B.n_rois);
+                     st, B.bcnt, B.bcur, B.n_buckets, B.pairs2d, (long long)B.n_rois, bbox);
   hipLaunchKernelGGL(k_bucket_hist, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.totals, B.bcnt);
+                     B.totals, B.bcnt, bbox);
+  if (bbox)
+    hipLaunchKernelGGL(k_bucket_prune, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.tsoft ? 1 : 0, B.bcnt,
+                       bbox, B.pairs2d);
   hipLaunchKernelGGL(k_bucket_sizes, dim3(grid_for(B.n_buckets)), dim3(256), 0, st, B.bcnt, B.n_buckets, B.bsz,
                      B.bflag);
   if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;

@@ -337,6 +337,43 @@ __global__ __launch_bounds__(256) void k_prune_far(const float* __restrict__ pos
   }
 }
 
+// A wave's staging buffer for work items in LDS: items are collected there
+// and appended to the global list 64 at a time with one atomic, so that the
+// many waves that emit a few items each do not all contend for the list's
+// counter.  Every lane of the wave must call push and flush alike.
+struct ItemStage {
+  PItem* buf;  // this wave's 64 LDS slots
+  int n;       // wave-uniform count of staged items
+
+  __device__ void flush(int lane, PItem* __restrict__ items, long long cap, unsigned int* __restrict__ counters) {
+    if (n == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    unsigned int first = 0;
+    if (lane == 0) first = atomicAdd(&counters[3], (unsigned int)n);
+    first = __shfl(first, 0, 64);
+    for (int i = lane; i < n; i += 64) {
+      const long long slot = (long long)first + i;
+      if (slot < cap)
+        items[slot] = buf[i];
+      else
+        counters[4] = 1u;  // the list is incomplete: the pruned ROIs' 3D pairs run unpruned
+    }
+    __builtin_amdgcn_wave_barrier();
+    n = 0;
+  }
+  // Stages the item of every lane with `emit` set (at most 32 per call).
+  __device__ void push(bool emit, const PItem& P, int lane, PItem* __restrict__ items, long long cap,
+                       unsigned int* __restrict__ counters) {
+    const unsigned long long em = __ballot(emit);
+    const int k = __popcll(em);
+    if (k == 0) return;
+    if (n + k > 64) flush(lane, items, cap, counters);
+    if (emit) buf[n + __popcll(em & ((1ull << lane) - 1ull))] = P;
+    n += k;
+  }
+};
+
 // Pass 7: the work items.  A persistent grid runs over the column pairs
 // (i, j) of all pruned ROIs (ROI r owns ncol^2 consecutive indices from
 // meta[r].prune_off; pairs with i > j are skipped): each lane tests one
@@ -358,6 +395,8 @@ __global__ __launch_bounds__(256) void k_prune_items(const BlkRec* __restrict__ 
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   int thr_roi = -1;
   float thr_val = 0.0f;
+  __shared__ PItem s_stage[4][64];
+  ItemStage stage{s_stage[threadIdx.x >> 6], 0};
   for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < total;
        base += nwaves * 64) {
     const long long idx = base + lane;
@@ -415,30 +454,18 @@ __global__ __launch_bounds__(256) void k_prune_items(const BlkRec* __restrict__ 
       }
 #pragma unroll
       for (int m = 1; m < LPT; m <<= 1) bits |= __shfl_xor(bits, m, 64);
-      const bool emit = g == 0 && bits != 0u;
-      const unsigned long long em = __ballot(emit);
-      if (!em) continue;
-      unsigned int first = 0;
-      if (lane == 0) first = atomicAdd(&counters[3], (unsigned int)__popcll(em));
-      first = __shfl(first, 0, 64);
-      if (emit) {
-        const long long slot = (long long)first + __popcll(em & ((1ull << lane) - 1ull));
-        if (slot < cap) {
-          PItem P;
-          P.rb = (int)rb;
-          P.nb = nb;
-          P.i0 = i0;
-          P.j0 = j * kPruneSB + (__ffs(bits) - 1);
-          P.j1 = j * kPruneSB + (32 - __clz(bits));
-          P.e = h_scale_exp(M.R2);
-          P.pad_[0] = P.pad_[1] = 0;
-          items[slot] = P;
-        } else {
-          counters[4] = 1u;  // the list is incomplete: the pruned ROIs' 3D pairs run unpruned
-        }
-      }
+      PItem P;
+      P.rb = (int)rb;
+      P.nb = nb;
+      P.i0 = i0;
+      P.j0 = j * kPruneSB + (bits ? __ffs(bits) - 1 : 0);
+      P.j1 = j * kPruneSB + (32 - __clz(bits));
+      P.e = h_scale_exp(M.R2);
+      P.pad_[0] = P.pad_[1] = 0;
+      stage.push(g == 0 && bits != 0u, P, lane, items, cap, counters);
     }
   }
+  stage.flush(lane, items, cap, counters);
 }
 
 unsigned grid_rows(long long n, long long cap = 4096) {

@@ -37,7 +37,8 @@ constexpr int kWorkStride = 32;     // words between two work counters (one 128-
 constexpr int kCounterWords = kWorkStride * (1 + 2 * kWorkParts);
 constexpr int kListCounters = kWorkStride * (1 + kWorkParts);  // first work counter of the pruned 3D pass
 constexpr int kPruneSB = 32;          // 32-row blocks per column of the 3D pruning pass (1024 rows)
-constexpr int kPruneMinV = 16384;     // ROIs with fewer vertices run their 3D pairs unpruned (prune = 1)
+constexpr int kPruneMinV = 1024;      // ROIs with fewer vertices run their 3D pairs unpruned (prune = 1)
+constexpr int kPruneCallMinV = 16384; // a call prunes (prune = 1) when its largest ROI may have this many vertices
 
 // Key of a vertex: edge (u, u + e_a): bits 0..19 u2+1, 20..39 u1+1, 40..59 u0+1, 60..61 a.
 __host__ __device__ inline uint64_t pack_key(int u0, int u1, int u2, int a) {
@@ -55,7 +56,7 @@ struct Roi {
   long long stride0;      // elements between consecutive voxels along axis 0
   long long stride1;      // ... along axis 1 (axis 2 is contiguous)
   int nrg;                // (d1 + 1) * G
-  int nzc;                // z-chunks: ceil((d0 + 1) / kTZ)
+  int nzc;                // z-chunks: ceil((d0 + 1) / tz)
   int bpz;                // bricks per z-chunk: ceil(nrg / kBrickThreads)
   int shG;                // floor(n / G) = (n * mG) >> shG for 0 <= n < 2^31
   unsigned int mG;
@@ -63,7 +64,7 @@ struct Roi {
   int shNW;
   int label;              // uint8 only: 0 = a voxel is inside iff nonzero; else iff it equals label
   int status;             // 0, or a negative status for a rejected table entry (then it has no bricks)
-  int pad_;
+  int tz;                 // cube planes per brick (kTZ, or fewer for a small ROI on its own)
   long long bucket_base[3];  // first global plane bucket of each axis
 };
 
@@ -77,6 +78,14 @@ struct RoiDesc {
   int reserved;
 };
 
+// A label's bounding box (inclusive voxel indices; lo = INT_MAX, hi = -1 when
+// empty) and voxel count, accumulated by the label pass.
+struct LabelAcc {
+  int lo[3];
+  int hi[3];
+  unsigned long long n;
+};
+
 // Magic numbers of the kernels' 32-bit division by D (numerators < 2^31):
 // floor(n / D) = (n * m) >> sh, sh = 31 + ceil(log2 D), m = floor(2^sh / D) + 1.
 __host__ __device__ inline void magic_div(unsigned int D, unsigned int& m, int& sh) {
@@ -88,9 +97,10 @@ __host__ __device__ inline void magic_div(unsigned int D, unsigned int& m, int& 
 
 // Fills the mesh-pass geometry of a ROI (everything but its brick and bucket
 // offsets) and returns its brick count.  Strides of 0 mean a dense layout.
+// tz: cube planes per brick (1..kTZ).
 __host__ __device__ inline long long roi_fill(Roi& R, const void* vol, const long long dims[3],
                                               const double spacing[3], long long stride0, long long stride1,
-                                              int label) {
+                                              int label, int tz = kTZ) {
   R.vol = vol;
   for (int k = 0; k < 3; ++k) {
     R.d[k] = (int)dims[k];
@@ -100,10 +110,10 @@ __host__ __device__ inline long long roi_fill(Roi& R, const void* vol, const lon
   R.stride0 = stride0 > 0 ? stride0 : (long long)R.d[1] * R.d[2];
   R.label = label;
   R.status = 0;
-  R.pad_ = 0;
+  R.tz = tz;
   R.G = (R.d[2] + 1 + 31) / 32;
   R.nrg = (R.d[1] + 1) * R.G;
-  R.nzc = (R.d[0] + 1 + kTZ - 1) / kTZ;
+  R.nzc = (R.d[0] + 1 + tz - 1) / tz;
   R.bpz = (R.nrg + kBrickThreads - 1) / kBrickThreads;
   magic_div((unsigned int)R.G, R.mG, R.shG);
   magic_div((unsigned int)(kBrickThreads + 1 + R.G), R.mNW, R.shNW);
@@ -122,15 +132,40 @@ __host__ __device__ inline void roi_set_buckets(Roi& R, long long b0) {
   R.bucket_base[2] = R.bucket_base[1] + 2ll * R.d[1] + 1;
 }
 
+// Per-ROI case data of binary masks in one buffer: 256 case areas (FP64) per
+// ROI, then 256 active-cube counts (uint64) per ROI.
+__host__ __device__ inline unsigned long long* case_hist(double* case_area, long long n_rois) {
+  return reinterpret_cast<unsigned long long*>(case_area + 256 * n_rois);
+}
+__host__ __device__ inline const unsigned long long* case_hist(const double* case_area, long long n_rois) {
+  return reinterpret_cast<const unsigned long long*>(case_area + 256 * n_rois);
+}
+
+// Surface area of a binary mask's ROI from its per-case areas and active-cube
+// counts: the 256 products n_c a_c summed by a fixed halving tree (so the
+// result does not depend on the order in which the cubes were visited).
+// Called by threads 0..255 of a workgroup (all of them, or none: it holds
+// barriers); s: 256 doubles of shared memory.  The sum is in s[0] afterwards.
+__device__ inline void binary_area_tree(const double* area, const unsigned long long* count, double* s) {
+  const int c = threadIdx.x;
+  if (c < 256) s[c] = count[c] ? __dmul_rn((double)count[c], area[c]) : 0.0;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (c < w) s[c] = __dadd_rn(s[c], s[c + w]);
+    __syncthreads();
+  }
+}
+
 struct BrickPart {
   int nv, nt;
   int bb[6];         // min corner (z, y, x) min / max of active cubes
-  double area;
+  double area;       // soft: area partial (binary masks: counted per case instead)
   double vol_d;      // soft: signed volume partial
   long long vol_i;   // binary: signed volume partial in units of s0*s1*s2/48
   // inside-voxel moments in voxel indices (only when the call asks for them):
   // count, sums of z, y, x, of zz, yy, xx, and of zy, zx, yx
   long long mom[10];
+  long long stage;   // first row of the brick's vertices in the mesh pass's staging list
 };
 
 struct RoiMeta {

@@ -21,23 +21,73 @@ struct RoiResult {
   int pad_;
 };
 
+// The small-mesh path (single ROIs): the four maximum squared distances
+// (FP64 bits), the smallest id pair at each (id_lo * 2^32 + id_hi), the
+// in-plane pair count and the ticket that finds the pair kernels' last
+// workgroup.
+struct SmallAcc {
+  unsigned long long gmax[4];
+  unsigned long long key[4];
+  unsigned long long pairs2d;
+  unsigned int ticket;
+  unsigned int pad_;
+};
+constexpr long long kSmallMaxV = 16384;         // largest mesh the small path evaluates
+constexpr long long kSmallMaxVoxels = 1ll << 22; // larger ROIs go straight to the general path
+constexpr int kSmallOverflow = -100;             // status: more vertices than kSmallMaxV
+
 // mesh.hip
 // Dynamic LDS of the mesh kernels for ROIs with at most max_G row-groups per row.
 size_t mesh_lds_bytes(int max_G);
-// case_area: [n_rois * 256] scratch for the binary masks' per-case areas.
-// moments: also sum the inside voxels' moments (BrickPart.mom, RoiMeta.n_in/cov).
-hipError_t launch_mesh_count(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
-                             double* case_area, BrickPart* part, int moments, hipStream_t st);
+// The small path's head (ROI record, cleared counts, case areas) and the
+// mesh pass alone (no clearing, no case areas).
+hipError_t launch_small_head(int dtype, const Roi& R, Roi* rois, long long* totals, SmallAcc* acc,
+                             double* case_area, hipStream_t st);
+hipError_t launch_mesh_core(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                            double* case_area, BrickPart* part, unsigned long long* tmpkey, double* tmpt,
+                            long long tmp_cap, long long* totals, int moments, hipStream_t st);
+// small.hip: every pair of the staged vertices exactly (vmax at most, at
+// most kSmallMaxV), in two persistent kernels of n_groups workgroups, then
+// the ROI's result in res[0].  acc: small_acc_bytes() of device memory (the
+// accumulators, then per-tile maxima).
+size_t small_acc_bytes();
+hipError_t launch_small_pairs(int dtype, const Roi* rois, const BrickPart* part, long long nbricks,
+                              const double* case_area, const unsigned long long* tmpkey, const double* tmpt,
+                              const long long* totals, long long vmax, SmallAcc* acc, int n_groups,
+                              RoiResult* res, hipStream_t st);
+
+// The mesh pass (one read of the volume): clears counters[0, n_counters),
+// then per brick its BrickPart and its vertices' keys (and soft t) in the
+// staging list (rows below tmp_cap are written; totals[8] counts all).
+// case_area: [n_rois * 512] scratch for the binary masks' per-case areas and
+// active-cube counts (case_hist);
+// moments: also the inside-voxel moments.
+hipError_t launch_mesh_pass(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
+                            double* case_area, BrickPart* part, unsigned int* counters, int n_counters,
+                            unsigned long long* tmpkey, double* tmpt, long long tmp_cap, long long* totals,
+                            int moments, hipStream_t st);
+// Per-ROI totals and each brick's first row within its ROI (brick_voff);
 // prune_min_v: ROIs with at least this many vertices get the pruning pass's column-pair offsets.
-hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const BrickPart* part,
-                              long long* brick_voff, RoiMeta* meta, long long* totals, int moments, int prune_min_v,
-                              hipStream_t st);
-hipError_t launch_check_capacity(int n_rois, long long rows0_cap, RoiMeta* meta, long long* totals,
-                                 unsigned int* overflow, hipStream_t st);
-hipError_t launch_mesh_emit(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
-                            const BrickPart* part, const long long* brick_voff, const RoiMeta* meta,
-                            const unsigned int* overflow, unsigned long long* key, double* tsoft, float* pos,
-                            uint4* posh, int* orig, int* blkseg, Seg* segs, hipStream_t st);
+hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const double* case_area,
+                              const BrickPart* part, long long* brick_voff, RoiMeta* meta, long long* totals,
+                              int moments, int prune_min_v, hipStream_t st);
+// The capacity check (rows0_cap rows; *overflow raised and every ROI emptied
+// beyond it), the 3D segments, and layout 0 from the staging list (tmp_cap
+// rows): keys, soft t, pair-pass operands (pos, or posh when set), orig and
+// block tags.
+hipError_t launch_mesh_rows(const Roi* rois, int n_rois, long long nbricks, const BrickPart* part,
+                            const long long* brick_voff, RoiMeta* meta, long long* totals, long long rows0_cap,
+                            const unsigned long long* tmpkey, const double* tmpt, long long tmp_cap,
+                            unsigned long long* key, double* tsoft, float* pos, uint4* posh, int* orig, int* blkseg,
+                            Seg* segs, unsigned int* overflow, hipStream_t st);
+
+// labels.hip: the ROI table of labels 1..max_label of a dense uint8 label map
+// (crop to each label's box, select the label), the voxel counts (counts,
+// may be null) and the largest crop (max_dims, may be null).  The table's
+// entries also hold the boxes while they are built.
+hipError_t launch_label_rois(const unsigned char* lab, const long long dims[3], const double spacing[3],
+                             int max_label, RoiDesc* rois, long long* counts, long long* max_dims, int cu_count,
+                             hipStream_t st);
 
 // ROI tables on the device: a caller's descriptors planned and validated in
 // one workgroup (plan[0] = bricks, plan[1] = buckets), or one ROI by value.
@@ -62,6 +112,7 @@ struct Tuning {
   int blocks_per_cu;  // persistent workgroups per CU (0: as many as fit)
   int kernel;         // 0: FP32 16x16x4 MFMA; 1: split-f16 32x32x16 MFMA
   int prune;          // 1: skip 3D pair tiles that cannot reach the diameter (kernel 1); 0: all pairs
+  int small_path;     // 1: small single ROIs take the exact all-pairs kernel after the mesh pass
 };
 
 // Buffers of the diameter passes.
@@ -85,6 +136,7 @@ struct PairBufs {
   long long* bflag;     // [n_buckets]
   long long* brow;      // [n_buckets]
   long long* bseg;      // [n_buckets]
+  int4* bbox;           // [n_buckets] key-coordinate boxes of the plane buckets (pruning)
   int* bgroup;          // [n_buckets] group roi * 4 + 1 + axis of each plane bucket
   long long seg_cap;    // n_rois + n_buckets
   long long* ncol;      // [seg_cap]

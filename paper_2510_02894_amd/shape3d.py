@@ -44,7 +44,7 @@ SHAPE_FEATURES = FEATURES + (
     "Flatness",
 )
 N_CLASS = len(SHAPE_FEATURES)
-PHASES = ("mesh_count", "mesh_emit", "buckets", "pair_maxima", "refine", "finalize", "total")
+PHASES = ("mesh_pass", "mesh_rows", "buckets", "pair_maxima", "refine", "finalize", "total")
 
 
 class Stats(ctypes.Structure):
@@ -84,7 +84,7 @@ class SoftSaved(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("itile_blocks", ctypes.c_int32), ("jchunk_blocks", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("prune", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("prune", ctypes.c_int32), ("small_path", ctypes.c_int32)]
 
     def as_tuple(self):
         return (self.itile_blocks, self.jchunk_blocks, self.blocks_per_cu, self.kernel)
@@ -178,6 +178,13 @@ def load():
         lib.shape3d_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, f64p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]
         lib.shape3d_noalloc.restype = ctypes.c_int
+        lib.shape3d_label_rois.argtypes = [ctypes.c_void_p, i64p, f64p, ctypes.c_int32, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.shape3d_label_rois.restype = ctypes.c_int
+        lib.shape3d_host_stream.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, i64p, f64p,
+                                            ctypes.c_int64, f64p, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                            ctypes.c_void_p]
+        lib.shape3d_host_stream.restype = ctypes.c_int
         lib.shape3d_last_error.argtypes = []
         lib.shape3d_last_error.restype = ctypes.c_char_p
         lib.shape3d_release.argtypes = []
@@ -438,6 +445,83 @@ def batched_dev(base, table_dev, n_rois: int, max_dims, workspace=None, graph: b
     return out, status
 
 
+def host_stream(vols, spacings, shape_class: bool = False):
+    """shape3d_host_stream: features of volumes held in HOST memory (numpy
+    arrays or CPU torch tensors, pinned or not, all uint8 or all float32,
+    C-contiguous), each copied to the GPU while the previous one is computed.
+    Returns (out float64[n, 6] or [n, 17], status int32[n]) as numpy arrays."""
+    import torch
+
+    lib = load()
+    n = len(vols)
+    if n < 1 or len(spacings) != n:
+        raise ValueError("need one spacing per volume")
+    ptrs = (ctypes.c_void_p * n)()
+    dims = (ctypes.c_int64 * (3 * n))()
+    sp = (ctypes.c_double * (3 * n))()
+    dt = None
+    for i, v in enumerate(vols):
+        if isinstance(v, torch.Tensor):
+            if v.is_cuda or not v.is_contiguous() or v.dim() != 3:
+                raise ValueError("host volumes must be 3-D contiguous CPU tensors")
+            d = U8 if v.dtype == torch.uint8 else (F32 if v.dtype == torch.float32 else None)
+            ptrs[i] = v.data_ptr()
+        else:
+            v = np.asarray(v)
+            if v.ndim != 3 or not v.flags["C_CONTIGUOUS"]:
+                raise ValueError("host volumes must be 3-D C-contiguous arrays")
+            d = U8 if v.dtype == np.uint8 else (F32 if v.dtype == np.float32 else None)
+            ptrs[i] = v.ctypes.data
+        if d is None or (dt is not None and d != dt):
+            raise TypeError("volumes must all be uint8 or all float32")
+        dt = d
+        for k in range(3):
+            dims[3 * i + k] = int(v.shape[k])
+            sp[3 * i + k] = float(spacings[i][k])
+    nf = N_CLASS if shape_class else 6
+    out = np.zeros((n, nf))
+    status = np.zeros(n, dtype=np.int32)
+    _check(lib.shape3d_host_stream(ptrs, dt, dims, sp, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   SHAPE_CLASS if shape_class else 0, _stream()))
+    return out, status
+
+
+def label_rois(labels, spacing=(1.0, 1.0, 1.0), max_label: int = 255, counts: bool = True):
+    """shape3d_label_rois: the device ROI table of labels 1..max_label of the
+    C-contiguous uint8 GPU label map ``labels`` (each entry crops the map to
+    the label's box and selects the label).  Returns (table uint8 GPU tensor
+    of max_label descriptors, voxel counts int64 GPU tensor or None, largest
+    crop dims int64 GPU tensor [3]); nothing is read back to the host."""
+    import torch
+
+    lib = load()
+    if _volume(labels) != U8:
+        raise TypeError("labels must be a uint8 tensor")
+    dims, sp = _dims_spacing(labels.shape, spacing)
+    table = torch.empty(int(max_label) * ctypes.sizeof(RoiEx), dtype=torch.uint8, device=labels.device)
+    cnt = torch.empty(int(max_label), dtype=torch.int64, device=labels.device) if counts else None
+    maxd = torch.empty(3, dtype=torch.int64, device=labels.device)
+    _check(lib.shape3d_label_rois(ctypes.c_void_p(labels.data_ptr()), dims, sp, int(max_label),
+                                  ctypes.c_void_p(table.data_ptr()),
+                                  ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
+                                  ctypes.c_void_p(maxd.data_ptr()), _stream()))
+    return table, cnt, maxd
+
+
+def label_features(labels, spacing=(1.0, 1.0, 1.0), max_label: int = 255, shape_class: bool = False,
+                   graph: bool = False):
+    """Features of every label 1..max_label of a GPU label map, each in its
+    own bounding box: shape3d_label_rois, then shape3d_batched_dev on the
+    map.  The batch is sized by the largest crop, read back once; the
+    features and statuses stay on the GPU (out [max_label, 6 or 17], status
+    [max_label]; a label with no voxel has status EMPTY)."""
+    table, _, maxd = label_rois(labels, spacing, max_label, counts=False)
+    md = [int(x) for x in maxd.cpu().tolist()]
+    base = labels.view(-1)
+    return batched_dev(base, table, int(max_label), md, graph=graph, shape_class=shape_class)
+
+
 def batched(base, table, graph: bool = False, stats: bool = False, shape_class: bool = False):
     """Features of a batch of ROIs packed in the 1-D GPU tensor ``base``
     (uint8 or float32); ``table`` from ``roi_table``.  Returns
@@ -637,7 +721,7 @@ def set_tuning(itile_blocks: int, jchunk_blocks: int, blocks_per_cu: int = 0, ke
     t = Tuning()
     _check(load().shape3d_get_tuning(ctypes.byref(t)))
     t = Tuning(int(itile_blocks), int(jchunk_blocks), int(blocks_per_cu), int(kernel),
-               int(t.prune if prune is None else prune))
+               int(t.prune if prune is None else prune), int(t.small_path))
     _check(load().shape3d_set_tuning(ctypes.byref(t)))
 
 
@@ -646,6 +730,21 @@ def set_prune(mode: int):
     t = Tuning()
     _check(load().shape3d_get_tuning(ctypes.byref(t)))
     t.prune = int(mode)
+    _check(load().shape3d_set_tuning(ctypes.byref(t)))
+
+
+def get_small_path() -> bool:
+    """Whether small single ROIs take the exact all-pairs kernel (default True)."""
+    t = Tuning()
+    _check(load().shape3d_get_tuning(ctypes.byref(t)))
+    return bool(t.small_path)
+
+
+def set_small_path(on: bool):
+    """Switch the small single-ROI path on or off (results are identical)."""
+    t = Tuning()
+    _check(load().shape3d_get_tuning(ctypes.byref(t)))
+    t.small_path = 1 if on else 0
     _check(load().shape3d_set_tuning(ctypes.byref(t)))
 
 

@@ -22,7 +22,8 @@ def test_header_declares_entry_points():
               "shape3d_soft_backward", "shape3d_batched_soft_forward", "shape3d_batched_soft_backward",
               "shape3d_get_tuning", "shape3d_set_tuning", "shape3d_autotune", "shape3d_last_error", "shape3d_release",
               "shape3d_version", "shape3d_workspace_size", "shape3d_workspace_size_v", "shape3d_batched_workspace_size",
-              "shape3d_ex_async", "shape3d_batched_dev", "shape3d_noalloc", "shape3d_class", "shape3d_batched_ex"):
+              "shape3d_ex_async", "shape3d_batched_dev", "shape3d_noalloc", "shape3d_class", "shape3d_batched_ex",
+              "shape3d_label_rois", "shape3d_host_stream"):
         assert n in names
 
 

@@ -1,7 +1,10 @@
 """GPU parity of the pruned 3D diameter pass: with pruning forced on, every
 result (features and maximising pairs) equals the all-pairs pass and the
 oracle, on tie-rich shapes (boxes, single voxels), a sphere (the least
-prunable shape), random masks, ellipsoid unions and batches."""
+prunable shape), random masks, ellipsoid unions and batches, including a
+batch with more than 2^16 plane buckets, where whole buckets are pruned too.
+The single-ROI cases switch the small-ROI path off, so that they run the
+general pipeline that prunes."""
 import sys
 
 import numpy as np
@@ -28,7 +31,9 @@ def S():
 
     shape3d.load()
     before = shape3d.get_prune()
+    shape3d.set_small_path(False)
     yield shape3d
+    shape3d.set_small_path(True)
     shape3d.set_prune(before)
 
 
@@ -89,3 +94,32 @@ def test_pruned_batch(S):
         m = buf[offs[r]:offs[r] + int(np.prod(shapes[r]))].reshape(shapes[r])
         ref = O.shape3d(m, sps[r])
         np.testing.assert_array_equal(o2[r, 2:], ref["features"][2:])
+
+
+def test_pruned_buckets(S):
+    """More than 2^16 plane buckets: buckets whose box cannot hold their
+    family's planar diameter are dropped before the pair pass."""
+    buf, offs, shapes, sps = synth.batched_rois_torch(400, 11, lmin=40.0, lmax=64.0)
+    assert sum(2 * (d[0] + d[1] + d[2]) + 3 for d in shapes) >= 1 << 16
+    table = S.roi_table(offs, shapes, sps)
+    say("bucket pruning: 400 ROIs")
+    S.set_prune(0)
+    o0, s0, st0 = S.batched(buf, table, stats=True)
+    S.set_prune(2)
+    o2, s2, st2 = S.batched(buf, table, stats=True)
+    o2g, _ = S.batched(buf, table, graph=True)
+    o2r, _ = S.batched(buf, table, graph=True)
+    np.testing.assert_array_equal(o2, o0)
+    np.testing.assert_array_equal(s2, s0)
+    np.testing.assert_array_equal(o2g, o0)
+    np.testing.assert_array_equal(o2r, o0)
+    for r in range(len(offs)):
+        np.testing.assert_array_equal(st2[r]["pair_ids"], st0[r]["pair_ids"], err_msg="ROI %d" % r)
+        # the in-plane pair count covers the dropped buckets' pairs too
+        assert st2[r]["pairs_2d"] == st0[r]["pairs_2d"], r
+    host = buf.cpu().numpy()
+    for r in range(0, len(offs), 50):
+        m = host[offs[r]:offs[r] + int(np.prod(shapes[r]))].reshape(shapes[r])
+        ref = O.shape3d(m, sps[r])
+        np.testing.assert_array_equal(o2[r, 2:], ref["features"][2:])
+        np.testing.assert_array_equal(st2[r]["pair_ids"], ref["pair_ids"])

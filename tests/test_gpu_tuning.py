@@ -29,7 +29,10 @@ def S():
     from paper_2510_02894_amd import shape3d
 
     shape3d.load()
+    # single-ROI calls run the general pipeline (the one the tiles belong to)
+    shape3d.set_small_path(False)
     yield shape3d
+    shape3d.set_small_path(True)
     shape3d.set_tuning(8, 1024, 0, 1)
 
 
