@@ -24,7 +24,6 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -55,26 +54,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Sources that define each profiled kernel (the shared headers count for all).
-KERNEL_SOURCES = {
-    "k_pair_maxima_h": ["pairs.hip"], "k_pair_maxima": ["pairs.hip"],
-    "k_bucket_scatter": ["pairs.hip"], "k_bucket_hist": ["pairs.hip"],
-    "k_mesh_pass": ["mesh.hip"], "k_mesh_rows": ["mesh.hip"],
-}
-SHARED_HEADERS = ["mc_table.h", "s3d_device.h", "s3d_internal.h", "s3d_launch.h"]
-
-
 def source_hash(files=None):
     """Hash of the kernel sources (all of csrc, or the given files plus the shared headers)."""
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2510_02894_amd", "csrc")
-    names = sorted(os.listdir(csrc)) if files is None else sorted(set(files) | set(SHARED_HEADERS))
-    for name in names:
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2510_02894_amd.profiling import source_hash as h
+
+    return h(files)
 
 
 def measured_traffic(kernel: str, tiles=None):
@@ -87,6 +71,8 @@ def measured_traffic(kernel: str, tiles=None):
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
+    from paper_2510_02894_amd.profiling import KERNEL_SOURCES
+
     if not k or k.get("source_hash") != source_hash(KERNEL_SOURCES.get(kernel)):
         return None
     if tiles is not None and list(rec.get("tiles", [])) != list(tiles):
