@@ -391,10 +391,19 @@ def main():
     vols = [torch.from_numpy(mask).to(dev) for _ in range(max(1, args.copies))]
     torch.cuda.synchronize()
 
-    tiles = S.get_tuning()
+    # pair-pass tiles: tuned separately for the default call (pruned 3D
+    # pairs) and for the call that evaluates every pair
+    prune_default = S.get_prune()
+    table1 = S.roi_table([0], [mask.shape], [spacing])
+    tiles = tiles_eff = S.get_tuning()
     if not args.no_autotune:
-        tiles, _ = S.autotune(vols[0].view(-1), S.roi_table([0], [mask.shape], [spacing]), reps=2)
-        log("large ROI: autotuned pair-pass tiles %s" % (tiles,))
+        tiles_eff, _ = S.autotune(vols[0].view(-1), table1, reps=2)
+        S.set_prune(0)
+        try:
+            tiles, _ = S.autotune(vols[0].view(-1), table1, reps=2)
+        finally:
+            S.set_prune(prune_default)
+        log("large ROI: autotuned pair-pass tiles %s (default call), %s (every pair)" % (tiles_eff, tiles))
 
     def step(i):
         return S.features(vols[i % len(vols)], spacing, stats=True, timing=True)
@@ -417,9 +426,10 @@ def main():
 
     # the library's default call (exact; the 3D pair tiles that cannot hold
     # the diameter are skipped), then every vertex pair evaluated
-    prune_default = S.get_prune()
+    S.set_tuning(*tiles_eff)
     f_eff, st_eff, ms_eff, avg_eff, _ = timed("default call")
     S.set_prune(0)
+    S.set_tuning(*tiles)
     try:
         f, st, ms_per_step, avg, phases = timed("all pairs")
     finally:
@@ -450,6 +460,7 @@ def main():
         "ms_per_step": ms_eff,
         "phases_ms": avg_eff,
         "speedup_vs_all_pairs": ms_per_step / ms_eff,
+        "tiles": list(tiles_eff),
     }
     N = int(np.prod(mask.shape))
     t_mesh = (avg["mesh_pass"] + avg["mesh_rows"]) * 1e-3
