@@ -77,6 +77,16 @@ __device__ inline double sel8(const double* v, int k) {
   return (k & 4) ? ce : ab;
 }
 
+// 1 / x in FP64 from the hardware reciprocal estimate and two Newton steps
+// (each squares the relative error, which ends far below a unit in the last
+// place of a double for the estimate's accuracy); x != 0.
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Position (relative to o) of the vertex on cube edge e of the cube with min
 // corner (c0, c1, c2) and corner values pc.  Edge e = 4 axis + 2 o_b + o_c runs
 // from corner k0 (bits dz dy dx) along its axis.
@@ -85,16 +95,17 @@ __device__ inline D3 cube_vertex(const double* pc, int e, int c0, int c1, int c2
   const int k0 = ea == 0 ? (e & 3) : (ea == 1 ? 4 * ((e >> 1) & 1) + (e & 1) : 4 * ((e >> 1) & 1) + 2 * (e & 1));
   const int k1 = k0 | (4 >> ea);
   const double p0 = sel8(pc, k0), p1 = sel8(pc, k1);
-  const double tt = (0.5 - p0) / (p1 - p0);
+  const double tt = (0.5 - p0) * rcp64(p1 - p0);
   const int w0 = c0 + ((k0 >> 2) & 1), w1 = c1 + ((k0 >> 1) & 1), w2 = c2 + (k0 & 1);
   return {((double)w0 + (ea == 0 ? tt : 0.0)) * s[0] - o[0], ((double)w1 + (ea == 1 ? tt : 0.0)) * s[1] - o[1],
           ((double)w2 + (ea == 2 ? tt : 0.0)) * s[2] - o[2]};
 }
 
-// dL/dx of the vertex on edge (u, a) from the area and volume terms; ntri and
-// tri are the case table's triangle counts and edge triples (in LDS).
+// dL/dx of the vertex on edge (u, a) from the area and volume terms; tri is
+// the case table's edge triples and tmask[12 case + e] the set of the case's
+// triangles that hold edge e (both in LDS).
 __device__ inline void vertex_grad_mesh(const float* p, const int* d, const double* s, const double* o, int u0, int u1,
-                                        int u2, int a, double g_area, double g_vol_signed, const uint8_t* ntri,
+                                        int u2, int a, double g_area, double g_vol_signed, const uint8_t* tmask,
                                         const uint8_t* tri, double* gx) {
   // per-edge factors of the two terms (divisions hoisted out of the triangle loop)
   const double ga = 0.5 * g_area, gv = g_vol_signed / 6.0;
@@ -112,11 +123,11 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
     int cas = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) cas |= (int)(pc[k] > 0.5) << k;
-    const int nt = ntri[cas];
-    for (int t = 0; t < nt; ++t) {
+    // only the triangles that hold this vertex
+    for (unsigned int m = tmask[cas * 12 + le]; m; m &= m - 1u) {
+      const int t = __ffs(m) - 1;
       const uint8_t* tr = tri + (cas * MC_MAX_TRI + t) * 3;
       const int e0 = tr[0], e1 = tr[1], e2 = tr[2];
-      if (e0 != le && e1 != le && e2 != le) continue;
       const D3 P0 = cube_vertex(pc, e0, c0, c1, c2, s, o);
       const D3 P1 = cube_vertex(pc, e1, c0, c1, c2, s, o);
       const D3 P2 = cube_vertex(pc, e2, c0, c1, c2, s, o);
@@ -126,7 +137,7 @@ __device__ inline void vertex_grad_mesh(const float* p, const int* d, const doub
       const D3 n = cross3(sub3(P1, P0), sub3(P2, P0));
       const double len = sqrt(n.x * n.x + n.y * n.y + n.z * n.z);
       if (len > 0.0) {
-        const double il = 1.0 / len;
+        const double il = rcp64(len);
         const D3 nh = {n.x * il, n.y * il, n.z * il};
         const D3 r = cross3(nh, sub3(C, B));
         gx[0] += ga * r.x;
@@ -229,12 +240,19 @@ __global__ __launch_bounds__(256) void k_soft_edges(SoftBwdBufs B) {
   }
 }
 
-__global__ __launch_bounds__(256, 4) void k_soft_vertex_grad(SoftBwdBufs B) {
-  // the case table in LDS: its lookups depend on one another (case, then triangle, then edge)
-  __shared__ uint8_t s_ntri[256];
+__global__ __launch_bounds__(256, 3) void k_soft_vertex_grad(SoftBwdBufs B) {
+  // the case table in LDS: its lookups depend on one another (case, then
+  // triangle, then edge); per case and edge, the triangles that hold the edge
+  __shared__ uint8_t s_tmask[256 * 12];
   __shared__ uint8_t s_tri[256 * MC_MAX_TRI * 3];
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) s_ntri[i] = MC_NTRI[i];
   for (int i = threadIdx.x; i < 256 * MC_MAX_TRI * 3; i += blockDim.x) s_tri[i] = (&MC_TRI[0][0][0])[i];
+  for (int i = threadIdx.x; i < 256 * 12; i += blockDim.x) {
+    const int c = i / 12, e = i - 12 * c;
+    unsigned int m = 0u;
+    for (int t = 0; t < MC_NTRI[c]; ++t)
+      if (MC_TRI[c][t][0] == e || MC_TRI[c][t][1] == e || MC_TRI[c][t][2] == e) m |= 1u << t;
+    s_tmask[i] = (uint8_t)m;
+  }
   __syncthreads();
   const long long n = min(B.counters[0], B.cap);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -257,7 +275,7 @@ __global__ __launch_bounds__(256, 4) void k_soft_vertex_grad(SoftBwdBufs B) {
     const unsigned int c1 = fdiv(r, R->m_c2, R->sh_c2);
     const int u0 = (int)c0 - 1, u1 = (int)c1 - 1, u2 = (int)(r - c1 * (unsigned int)(R->d[2] + 1)) - 1;
     double gx[3] = {0.0, 0.0, 0.0};
-    vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, s_ntri, s_tri, gx);
+    vertex_grad_mesh(R->p, R->d, R->s, R->o, u0, u1, u2, a, R->g_area, R->g_vol_signed, s_tmask, s_tri, gx);
     const long long id = 3ll * ((((long long)(u0 + 1)) * (R->d[1] + 2) + (u1 + 1)) * (long long)(R->d[2] + 2) +
                                 (u2 + 1)) +
                          a;

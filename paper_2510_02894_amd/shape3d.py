@@ -592,6 +592,20 @@ def soft_backward(p, saved: SoftSaved, grad_out):
     return grad
 
 
+def _uncovered(table, numel: int):
+    """The element ranges [a, b) of a packed buffer of numel elements that no
+    ROI of the table covers."""
+    spans = sorted((int(r.offset), int(r.offset) + int(r.dims[0]) * int(r.dims[1]) * int(r.dims[2])) for r in table)
+    out, pos = [], 0
+    for a, b in spans:
+        if a > pos:
+            out.append((pos, min(a, numel)))
+        pos = max(pos, b)
+    if pos < numel:
+        out.append((pos, numel))
+    return [(a, b) for a, b in out if b > a]
+
+
 def _soft_base(base):
     import torch
 
@@ -625,7 +639,11 @@ def batched_soft_backward(base, table, saved, grad_out, grad=None):
     n = len(table)
     g = np.ascontiguousarray(np.asarray(grad_out, dtype=np.float64).reshape(n, 6))
     if grad is None:
-        grad = torch.zeros_like(base)
+        # every element of every ROI is written by the call: only the elements
+        # outside all ROIs need their zeros
+        grad = torch.empty_like(base)
+        for a, b in _uncovered(table, base.numel()):
+            grad[a:b].zero_()
     _check(lib.shape3d_batched_soft_backward(ctypes.c_void_p(base.data_ptr()), table, n, saved,
                                              g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                              ctypes.c_void_p(grad.data_ptr()), _stream()))

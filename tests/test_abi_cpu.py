@@ -176,3 +176,16 @@ def test_batch_extent_check_in_binding():
         S._check_extents(t, 127)
     with pytest.raises(ValueError):
         S._check_extents(S.roi_table([-1], [(1, 1, 1)], [(1, 1, 1)]), 10)
+
+
+def test_uncovered_ranges_of_a_packed_buffer():
+    """The batched soft backward zeroes only the elements outside every ROI:
+    the ranges come from the table (overlaps, gaps, a tail, back-to-back ROIs)."""
+    from paper_2510_02894_amd import shape3d as S
+
+    t = S.roi_table([3, 20, 10], [(1, 2, 3), (2, 2, 2), (1, 1, 5)], [(1, 1, 1)] * 3)
+    assert S._uncovered(t, 40) == [(0, 3), (9, 10), (15, 20), (28, 40)]
+    t = S.roi_table([0, 6], [(1, 2, 3), (1, 1, 4)], [(1, 1, 1)] * 2)
+    assert S._uncovered(t, 10) == []
+    t = S.roi_table([0, 2], [(1, 1, 5), (1, 1, 2)], [(1, 1, 1)] * 2)  # the second inside the first
+    assert S._uncovered(t, 8) == [(5, 8)]
