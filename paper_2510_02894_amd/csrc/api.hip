@@ -61,7 +61,7 @@ struct Buf {
 // the layout-0 row capacity.  The library's own workspace grows each buffer
 // on demand; a caller's workspace is carved into all of them at once.
 enum WsId {
-  W_ROIS, W_PLAN, W_PART, W_BRICK_VOFF, W_META, W_CASE_AREA, W_TOTALS, W_COUNTERS, W_GRES, W_RES, W_PAIRS2D,
+  W_ROIS, W_PLAN, W_PART, W_BRICK_VOFF, W_BRICK_ROI, W_META, W_CASE_AREA, W_TOTALS, W_COUNTERS, W_GRES, W_RES, W_PAIRS2D,
   W_BCNT, W_BCUR, W_BSZ, W_BFLAG, W_BROW, W_BSEG, W_BGROUP, W_BBOX,
   W_FIRST_VERTEX_BUF,
   W_KEY = W_FIRST_VERTEX_BUF, W_TSOFT, W_POS, W_POSH, W_ORIG, W_ROWMAX, W_BLKSEG, W_SEGS, W_NCOL, W_COLBASE,
@@ -362,6 +362,7 @@ int ws_layout(const Batch& B, int dtype, const Tuning& t, long long rows0_cap, L
   b[W_PLAN] = sizeof(long long) * 4;
   b[W_PART] = sizeof(BrickPart) * B.nbricks;
   b[W_BRICK_VOFF] = sizeof(long long) * B.nbricks;
+  b[W_BRICK_ROI] = B.n() > 1 ? sizeof(int) * B.nbricks : 0;
   b[W_META] = sizeof(RoiMeta) * n;
   b[W_CASE_AREA] = (sizeof(double) + sizeof(unsigned long long)) * 256 * n;  // areas, then counts
   b[W_TOTALS] = sizeof(long long) * 16;
@@ -564,7 +565,7 @@ int launch_head(const Ptrs& P, const Batch& Bt, int dtype, long long tmp_cap, hi
   HIPCK(launch_mesh_pass(dtype, P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, Bt.max_G, P.as<double>(W_CASE_AREA),
                          P.as<BrickPart>(W_PART), P.as<unsigned int>(W_COUNTERS), kCounterWords,
                          P.as<unsigned long long>(W_TMPKEY), dtype == SHAPE3D_F32 ? P.as<double>(W_TMPT) : nullptr,
-                         tmp_cap, P.as<long long>(W_TOTALS), Bt.moments ? 1 : 0, st));
+                         tmp_cap, P.as<long long>(W_TOTALS), Bt.moments ? 1 : 0, P.as<int>(W_BRICK_ROI), st));
   HIPCK(launch_mesh_totals(P.as<const Roi>(W_ROIS), Bt.n(), Bt.nbricks, dtype, P.as<const double>(W_CASE_AREA),
                            P.as<const BrickPart>(W_PART),
                            P.as<long long>(W_BRICK_VOFF), P.as<RoiMeta>(W_META), P.as<long long>(W_TOTALS),
@@ -581,7 +582,7 @@ int launch_rows(const Ptrs& P, const Batch& Bt, int dtype, long long rows0_cap, 
                          dtype == SHAPE3D_F32 ? P.as<const double>(W_TMPT) : nullptr, tmp_cap,
                          P.as<unsigned long long>(W_KEY), dtype == SHAPE3D_F32 ? P.as<double>(W_TSOFT) : nullptr,
                          posh ? nullptr : P.as<float>(W_POS), posh, P.as<int>(W_ORIG), P.as<int>(W_BLKSEG),
-                         P.as<Seg>(W_SEGS), P.as<unsigned int>(W_COUNTERS) + 2, st));
+                         P.as<Seg>(W_SEGS), P.as<unsigned int>(W_COUNTERS) + 2, P.as<const int>(W_BRICK_ROI), st));
   return SHAPE3D_OK;
 }
 

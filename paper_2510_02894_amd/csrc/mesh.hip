@@ -35,8 +35,7 @@
 namespace s3d {
 
 // ---------------------------------------------------------------------------
-// Row loader: bits of voxels [32l, 32l + 32) of row (z, y); voxels outside the
-// array read as outside.
+// Voxel bytes to inside bits, four at a time.
 
 __device__ inline uint32_t nz4(uint32_t w) {
   // high bit of each byte set iff the byte is nonzero, then gathered to bits 0..3
@@ -50,48 +49,93 @@ __device__ inline uint32_t in4(uint32_t w, uint32_t label4) {
   return label4 ? (~nz4(w ^ label4) & 0xfu) : nz4(w);
 }
 
-template <int DT>
-__device__ inline uint32_t row_bits(const Roi& R, int z, int y, int l) {
-  uint32_t bits = 0u;
-  if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1]) return 0u;
-  const int x0 = 32 * l;
-  int n = R.d[2] - x0;
-  if (n <= 0) return 0u;
-  const size_t off = (size_t)z * (size_t)R.stride0 + (size_t)y * (size_t)R.stride1 + (size_t)x0;
-  if (DT == 0) {
-    const uint8_t* p = (const uint8_t*)R.vol + off;
-    const uint32_t label4 = (uint32_t)(R.label & 0xff) * 0x01010101u;
-    if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
-      const uint4 a = *(const uint4*)p;
-      const uint4 b = *(const uint4*)(p + 16);
-      bits = in4(a.x, label4) | (in4(a.y, label4) << 4) | (in4(a.z, label4) << 8) | (in4(a.w, label4) << 12) |
-             (in4(b.x, label4) << 16) | (in4(b.y, label4) << 20) | (in4(b.z, label4) << 24) |
-             (in4(b.w, label4) << 28);
-    } else {
-      if (n > 32) n = 32;
-      const int lab = R.label;
-      for (int i = 0; i < n; ++i) bits |= (uint32_t)(lab ? p[i] == lab : p[i] != 0) << i;
-    }
-  } else {
-    const float* p = (const float*)R.vol + off;
-    if (n >= 32 && (((uintptr_t)p) & 15u) == 0) {
+// Slots per chunk of a brick's dense enumeration of active cubes or crossing
+// edges (8 per thread).
+constexpr int kMeshItems = 2048;
+static_assert(kMeshItems == 8 * kBrickThreads, "the slot scan gives each thread 8 slots");
+
+// Position of the r-th set bit (r = 0 for the lowest) of w; r < popc(w).
+__device__ inline int nth_set_bit(uint32_t w, int r) {
+  int pos = 0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float4 v = ((const float4*)p)[i];
-        bits |= ((uint32_t)(v.x > 0.5f) | ((uint32_t)(v.y > 0.5f) << 1) | ((uint32_t)(v.z > 0.5f) << 2) |
-                 ((uint32_t)(v.w > 0.5f) << 3))
-                << (4 * i);
-      }
-    } else {
-      if (n > 32) n = 32;
-      for (int i = 0; i < n; ++i) bits |= (uint32_t)(p[i] > 0.5f) << i;
-    }
+  for (int h = 16; h >= 1; h >>= 1) {
+    const int c = __popc(w & ((1u << h) - 1u));
+    const bool up = r >= c;
+    r = up ? r - c : r;
+    w = up ? w >> h : w;
+    pos = up ? pos + h : pos;
   }
-  return bits;
+  return pos;
 }
 
-// Capacity of the per-plane list of compacted cubes or edges of a brick.
-constexpr int kMeshItems = 2048;
+// Inclusive max-scan of s[0, n) by the workgroup, 8 consecutive slots per
+// thread (slots >= n read as 0).  s_mx holds 4 words.  Contains barriers.
+__device__ inline void block_max_scan(uint32_t* s, int n, uint32_t* s_mx) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int b = 8 * tid;
+  const uint4 q0 = *(const uint4*)(s + b), q1 = *(const uint4*)(s + b + 4);
+  const uint32_t in[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+  uint32_t v[8], m = 0u;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    m = max(m, b + j < n ? in[j] : 0u);
+    v[j] = m;
+  }
+  uint32_t x = m;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x = max(x, y);
+  }
+  const uint32_t prev = __shfl_up(x, 1, 64);
+  if (lane == 63) s_mx[wid] = x;
+  __syncthreads();
+  uint32_t pre = lane > 0 ? prev : 0u;
+  for (int w = 0; w < wid; ++w) pre = max(pre, s_mx[w]);
+  *(uint4*)(s + b) = make_uint4(max(pre, v[0]), max(pre, v[1]), max(pre, v[2]), max(pre, v[3]));
+  *(uint4*)(s + b + 4) = make_uint4(max(pre, v[4]), max(pre, v[5]), max(pre, v[6]), max(pre, v[7]));
+  __syncthreads();
+}
+
+// Dense enumeration of the set bits of the brick's per-thread words: thread t
+// holds NW words (their bit counts are passed, one per byte of `counts`), item
+// numbers run over threads, then words, then bits, and `off` is the thread's
+// first item.  For the chunk of items [c0, c0 + n), each
+// nonempty word writes a marker at the slot where it begins (slot 0 for a word
+// that began in an earlier chunk), (slot << 21) | (bits before the chunk << 16)
+// | (t << 8) | word; the max-scan then leaves in every slot i the marker of the
+// word that holds item c0 + i, which is that word's
+// (i - (marker >> 21) + ((marker >> 16) & 31))-th set bit.  Every lane does
+// the same amount of work however the bits fall among the threads.
+template <int NW>
+__device__ inline void mark_words(const uint32_t* counts, int off, int c0, int n, uint32_t* s, uint32_t* s_mx) {
+  static_assert(NW <= 256, "the word index takes 8 bits");
+  for (int i = threadIdx.x; i < n; i += kBrickThreads) s[i] = 0u;
+  // The counts pass through an empty asm statement so that the compiler does
+  // not hoist the NW word offsets out of the caller's chunk loop, which would
+  // hold NW more registers through the whole kernel.
+  uint32_t cc[(NW + 3) / 4];
+#pragma unroll
+  for (int q = 0; q < (NW + 3) / 4; ++q) {
+    cc[q] = counts[q];
+    asm volatile("" : "+v"(cc[q]));
+  }
+  __syncthreads();
+  int o = off - c0;  // first item of word j, relative to the chunk
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int c = (int)((cc[j >> 2] >> (8 * (j & 3))) & 0xffu);
+    if (c > 0 && o + c > 0 && o < n) {
+      const int ls = max(o, 0);
+      s[ls] = ((uint32_t)ls << 21) | ((uint32_t)(ls - o) << 16) | ((uint32_t)threadIdx.x << 8) | (uint32_t)j;
+    }
+    o += c;
+  }
+  __syncthreads();
+  block_max_scan(s, n, s_mx);
+}
+
+__device__ inline int marker_rank(uint32_t mk, int i) { return i - (int)(mk >> 21) + (int)((mk >> 16) & 31u); }
 
 // v[k] of an 8-entry register array for a run-time k (selects, no scratch).
 __device__ inline double sel8d(const double* v, int k) {
@@ -131,105 +175,122 @@ __device__ inline Tile tile_of(const Roi& R, long long local_brick) {
   return T;
 }
 
-// Address of voxel row-group vrg of voxel plane p of the tile, or null when it
-// lies outside the array or is not a full aligned 32-voxel run (then the slow
-// per-voxel path of row_bits is used).
+// Voxel row-group vrg of voxel plane p of the tile: the address of its first
+// voxel and the number of its 32 voxels that lie inside the array (0 when the
+// row-group lies outside it; then the address is not used).
 template <int DT>
-__device__ inline const void* fast_row_ptr(const Roi& R, const Tile& T, int p, int vrg) {
+__device__ inline const char* row_span(const Roi& R, const Tile& T, int p, int vrg, int& nvox) {
+  nvox = 0;
   if (vrg < 0) return nullptr;
   const int ry = (int)fdiv((unsigned int)vrg, R.mG, R.shG);
   const int z = T.pz0 - 1 + p, y = ry - 1, x0 = 32 * (vrg - ry * R.G);
-  if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1] || x0 + 32 > R.d[2]) return nullptr;
+  if (z < 0 || z >= R.d[0] || y < 0 || y >= R.d[1] || x0 >= R.d[2]) return nullptr;
+  nvox = min(32, R.d[2] - x0);
   const size_t off = (size_t)z * (size_t)R.stride0 + (size_t)y * (size_t)R.stride1 + (size_t)x0;
-  const char* ptr = (const char*)R.vol + off * (DT == 0 ? 1 : 4);
-  return (((uintptr_t)ptr) & 15u) == 0 ? ptr : nullptr;
-}
-
-template <int DT>
-__device__ inline uint32_t slow_row_bits(const Roi& R, const Tile& T, int p, int vrg) {
-  if (vrg < 0) return 0u;
-  const int ry = (int)fdiv((unsigned int)vrg, R.mG, R.shG);
-  return row_bits<DT>(R, T.pz0 - 1 + p, ry - 1, vrg - ry * R.G);
+  return (const char*)R.vol + off * (DT == 0 ? 1 : 4);
 }
 
 // Stages the tile's voxel row-groups in LDS.  Each thread issues the loads of
-// kLoadBatch row-groups before converting any of them, so a workgroup keeps
-// its whole tile in flight instead of one row-group per thread at a time.
+// several row-groups before converting any of them, so a workgroup keeps its
+// whole tile in flight instead of one row-group per thread at a time.  A full
+// row-group at a 16-byte aligned address is read with 16-byte loads; any other
+// (rows of packed ROIs start anywhere, row ends) with loads of the aligned
+// dwords (uint8) or floats that hold its voxels inside the array, and never
+// past them, since an aligned dword holding a valid byte lies on a mapped page.
 template <int DT>
 __device__ inline void load_tile(const Roi& R, const Tile& T, uint32_t* s_bits) {
-  constexpr int kLoadBatch = 5;
   const int n = T.np * T.nw;
-  const uint32_t label4 = (uint32_t)(R.label & 0xff) * 0x01010101u;
-  for (int base = threadIdx.x; base < n; base += kBrickThreads * kLoadBatch) {
-    if (DT == 0) {
-      uint4 a[kLoadBatch], b[kLoadBatch];
-      bool fast[kLoadBatch];
+  if (DT == 0) {
+    constexpr int kLoadBatch = 5;
+    const uint32_t label4 = (uint32_t)(R.label & 0xff) * 0x01010101u;
+    for (int base = threadIdx.x; base < n; base += kBrickThreads * kLoadBatch) {
+      uint32_t d[kLoadBatch][9];
+      int nv[kLoadBatch], sh[kLoadBatch];
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
         const int idx = base + u * kBrickThreads;
-        const void* ptr = nullptr;
+        const char* ptr = nullptr;
+        nv[u] = 0;
+        sh[u] = 0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) d[u][j] = 0u;
         if (idx < n) {
           const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
-          ptr = fast_row_ptr<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+          ptr = row_span<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw, nv[u]);
         }
-        fast[u] = ptr != nullptr;
-        if (fast[u]) {
-          a[u] = *(const uint4*)ptr;
-          b[u] = *((const uint4*)ptr + 1);
+        if (nv[u] == 32 && (((uintptr_t)ptr) & 15u) == 0) {
+          const uint4 a = *(const uint4*)ptr, b = *((const uint4*)ptr + 1);
+          d[u][0] = a.x;
+          d[u][1] = a.y;
+          d[u][2] = a.z;
+          d[u][3] = a.w;
+          d[u][4] = b.x;
+          d[u][5] = b.y;
+          d[u][6] = b.z;
+          d[u][7] = b.w;
+        } else if (nv[u] > 0) {
+          const uintptr_t a = (uintptr_t)ptr;
+          const uint32_t* q = (const uint32_t*)(a & ~(uintptr_t)3);
+          sh[u] = (int)(a & 3u);
+          const int last = (sh[u] + nv[u] - 1) >> 2;  // last dword holding a voxel of the row-group
+#pragma unroll
+          for (int j = 0; j < 9; ++j)
+            if (j <= last) d[u][j] = q[j];
         }
       }
 #pragma unroll
       for (int u = 0; u < kLoadBatch; ++u) {
         const int idx = base + u * kBrickThreads;
         if (idx >= n) continue;
-        uint32_t bits;
-        if (fast[u]) {
-          bits = in4(a[u].x, label4) | (in4(a[u].y, label4) << 4) | (in4(a[u].z, label4) << 8) |
-                 (in4(a[u].w, label4) << 12) | (in4(b[u].x, label4) << 16) | (in4(b[u].y, label4) << 20) |
-                 (in4(b[u].z, label4) << 24) | (in4(b[u].w, label4) << 28);
-        } else {
-          const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
-          bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
-        }
-        s_bits[idx] = bits;
+        uint32_t bits = 0u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          bits |= in4(__builtin_amdgcn_alignbyte(d[u][j + 1], d[u][j], (uint32_t)sh[u]), label4) << (4 * j);
+        s_bits[idx] = nv[u] >= 32 ? bits : bits & ((1u << nv[u]) - 1u);
       }
-    } else {
-      // float32: a row-group is 128 B; two of them (sixteen float4 loads) are
-      // in flight per thread before any is converted
-      for (int u0 = 0; u0 < kLoadBatch; u0 += 2) {
-        float4 v[2][8];
-        bool fast[2];
+    }
+  } else {
+    // float32: a row-group is 128 B; two of them are in flight per thread
+    // before either is converted
+    constexpr int kLoadBatch = 2;
+    for (int base = threadIdx.x; base < n; base += kBrickThreads * kLoadBatch) {
+      float v[kLoadBatch][32];
+      int nv[kLoadBatch];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int idx = base + (u0 + h) * kBrickThreads;
-          const void* ptr = nullptr;
-          if (u0 + h < kLoadBatch && idx < n) {
-            const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
-            ptr = fast_row_ptr<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
-          }
-          fast[h] = ptr != nullptr;
-          if (fast[h]) {
+      for (int h = 0; h < kLoadBatch; ++h) {
+        const int idx = base + h * kBrickThreads;
+        const char* ptr = nullptr;
+        nv[h] = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[h][i] = ((const float4*)ptr)[i];
-          }
+        for (int i = 0; i < 32; ++i) v[h][i] = 0.0f;
+        if (idx < n) {
+          const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
+          ptr = row_span<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw, nv[h]);
         }
+        const float* f = (const float*)ptr;
+        if (nv[h] == 32 && (((uintptr_t)ptr) & 15u) == 0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int idx = base + (u0 + h) * kBrickThreads;
-          if (u0 + h >= kLoadBatch || idx >= n) continue;
-          uint32_t bits = 0u;
-          if (fast[h]) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-              bits |= ((uint32_t)(v[h][i].x > 0.5f) | ((uint32_t)(v[h][i].y > 0.5f) << 1) |
-                       ((uint32_t)(v[h][i].z > 0.5f) << 2) | ((uint32_t)(v[h][i].w > 0.5f) << 3))
-                      << (4 * i);
-          } else {
-            const int p = (int)fdiv((unsigned int)idx, R.mNW, R.shNW);
-            bits = slow_row_bits<DT>(R, T, p, T.rg0 - 1 + idx - p * T.nw);
+          for (int i = 0; i < 8; ++i) {
+            const float4 q = ((const float4*)f)[i];
+            v[h][4 * i] = q.x;
+            v[h][4 * i + 1] = q.y;
+            v[h][4 * i + 2] = q.z;
+            v[h][4 * i + 3] = q.w;
           }
-          s_bits[idx] = bits;
+        } else if (nv[h] > 0) {
+#pragma unroll
+          for (int i = 0; i < 32; ++i)
+            if (i < nv[h]) v[h][i] = f[i];
         }
+      }
+#pragma unroll
+      for (int h = 0; h < kLoadBatch; ++h) {
+        const int idx = base + h * kBrickThreads;
+        if (idx >= n) continue;
+        uint32_t bits = 0u;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) bits |= (uint32_t)(v[h][i] > 0.5f) << i;
+        s_bits[idx] = bits;
       }
     }
   }
@@ -242,6 +303,13 @@ struct Lane {
   bool valid;
 };
 
+// Cubes of 32-cube group l inside the ROI: cube x = 32l - 1 + k is valid iff
+// k <= d2 - 32l.
+__device__ inline uint32_t lane_vmask(const Roi& R, int l) {
+  const int kmax = R.d[2] - 32 * l;
+  return kmax >= 31 ? 0xffffffffu : ((1u << (kmax + 1)) - 1u);
+}
+
 __device__ inline Lane lane_of(const Roi& R, const Tile& T, int tid) {
   Lane L;
   const int rg = T.rg0 + tid;
@@ -249,8 +317,7 @@ __device__ inline Lane lane_of(const Roi& R, const Tile& T, int tid) {
   const int ry = L.valid ? (int)fdiv((unsigned int)rg, R.mG, R.shG) : 0;
   L.l = L.valid ? rg - ry * R.G : 0;
   L.y = ry - 1;
-  const int kmax = R.d[2] - 32 * L.l;  // cube x = 32l - 1 + k valid iff k <= kmax
-  L.vmask = kmax >= 31 ? 0xffffffffu : ((1u << (kmax + 1)) - 1u);
+  L.vmask = lane_vmask(R, L.l);
   return L;
 }
 
@@ -395,14 +462,16 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
                                                              BrickPart* __restrict__ part,
                                                              unsigned long long* __restrict__ tmpkey,
                                                              double* __restrict__ tmpt, long long tmp_cap,
-                                                             long long* __restrict__ totals, int moments) {
+                                                             long long* __restrict__ totals, int moments,
+                                                             const int* __restrict__ bmap) {
   extern __shared__ uint32_t s_bits[];
   __shared__ unsigned int s_hist[256];  // binary masks: active cubes per case
   __shared__ int s_tk[256];
   __shared__ int s_tm[256];
-  __shared__ uint32_t s_items[kMeshItems];
+  __shared__ __align__(16) uint32_t s_items[kMeshItems];
   __shared__ uint32_t s_ly[kBrickThreads];  // (y + 1) | l << 20 of each thread's row-group
   __shared__ int s_scan[4];
+  __shared__ uint32_t s_mx[4];
   __shared__ double s_rd[2][4];
   __shared__ long long s_rl[4];
   __shared__ int s_ri[8][4];
@@ -410,7 +479,8 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
   __shared__ long long s_base;
 
   const long long brick = xcd_remap(blockIdx.x, nbricks);
-  const int roi = find_roi(rois, n_rois, brick);
+  const int roi = bmap ? bmap[brick] : find_roi(rois, n_rois, brick);
+  if (roi < 0) return;
   const Roi R = rois[roi];
   // a grid sized by a bound (ROI table planned on the device) ends past the last brick
   if (brick >= R.brick_end) return;
@@ -438,14 +508,16 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
 
   // All planes of the brick at once: each thread first classifies its 32
   // cubes of every plane pair (voxel rows held in registers, each read from
-  // LDS once), counting crossing edges and collecting the active cubes per
-  // plane; one block scan then places every active cube of the brick in
-  // s_items, and the whole workgroup processes them densely, so that a lane
-  // whose cubes all touch the surface does not hold up its wave and the
-  // brick takes a few barriers instead of a few per plane.
-  static_assert(kTZ <= 8, "an item holds the plane in 3 bits");
-  uint32_t act[kTZ];
-  uint32_t ed[kTZ][3];  // crossing edges along axis 0, 1, 2 from each cube's corner 0
+  // LDS once) into a word of active cubes and three words of crossing edges
+  // per plane; the brick's active cubes, then its crossing edges, are then
+  // enumerated densely over the whole workgroup (mark_words), so that a lane
+  // whose cubes all touch the surface does not hold up its wave and the brick
+  // takes a few barriers instead of a few per plane.
+  // bit counts of the words (active cubes of plane p: byte p of actc; edges
+  // along axis a of plane p, from each cube's corner 0: byte 3p + a of edc);
+  // the words themselves are recomputed from the tile when they are listed
+  uint32_t actc[(kTZ + 3) / 4] = {};
+  uint32_t edc[(3 * kTZ + 3) / 4] = {};
   int cnt = 0, cnt_e = 0;
   long long mom[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
@@ -464,8 +536,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
       }
 #pragma unroll
     for (int p = 0; p < kTZ; ++p) {
-      act[p] = 0u;
-      ed[p][0] = ed[p][1] = ed[p][2] = 0u;
+      uint32_t act = 0u, ed[3] = {0u, 0u, 0u};
       if (L.valid && p + 1 < T.np) {
         const Corners C = make_corners(rr[p][0], xx[p][0], rr[p][1], xx[p][1], rr[p + 1][0], xx[p + 1][0],
                                        rr[p + 1][1], xx[p + 1][1]);
@@ -475,9 +546,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
           any |= C.c[c];
           all &= C.c[c];
         }
-        ed[p][0] = (C.c[0] ^ C.c[4]) & L.vmask;
-        ed[p][1] = (C.c[0] ^ C.c[2]) & L.vmask;
-        ed[p][2] = (C.c[0] ^ C.c[1]) & L.vmask;
+        ed[0] = (C.c[0] ^ C.c[4]) & L.vmask;
+        ed[1] = (C.c[0] ^ C.c[2]) & L.vmask;
+        ed[2] = (C.c[0] ^ C.c[1]) & L.vmask;
         const uint32_t active = any & ~all & L.vmask;
         if (active) {
           const int z = T.pz0 - 1 + p;
@@ -488,10 +559,17 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
           bb[4] = max(bb[4], L.y);
           bb[5] = max(bb[5], 32 * L.l - 1 + (31 - __clz(active)));
         }
-        act[p] = active;
+        act = active;
       }
-      cnt += __popc(act[p]);
-      cnt_e += __popc(ed[p][0]) + __popc(ed[p][1]) + __popc(ed[p][2]);
+      const uint32_t ca = (uint32_t)__popc(act);
+      actc[p >> 2] |= ca << (8 * (p & 3));
+      cnt += (int)ca;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const uint32_t ce = (uint32_t)__popc(ed[a]);
+        edc[(3 * p + a) >> 2] |= ce << (8 * ((3 * p + a) & 3));
+        cnt_e += (int)ce;
+      }
     }
     if (moments && L.valid) {
       // voxel row (z, y) = (pz0 + p, L.y + 1), x = 32 l + bit, is word rr[p + 1][1]
@@ -533,34 +611,25 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
   int total;
   const int off = block_excl_scan256(cnt, s_scan, total);
   for (int c0 = 0; c0 < total; c0 += kMeshItems) {
-    // this thread's items with index in [c0, c0 + kMeshItems): (thread, plane, cube)
-    int idx = off;
-#pragma unroll
-    for (int p = 0; p < kTZ; ++p) {
-      uint32_t m = act[p];
-      const int np = __popc(m);
-      if (idx + np <= c0 || idx >= c0 + kMeshItems) {
-        idx += np;
-        continue;
-      }
-      while (m && idx < c0 + kMeshItems) {
-        const int k = __ffs(m) - 1;
-        m &= m - 1u;
-        if (idx >= c0) s_items[idx - c0] = ((uint32_t)tid << 8) | ((uint32_t)p << 5) | (uint32_t)k;
-        ++idx;
-      }
-    }
-    __syncthreads();
     const int n = min(kMeshItems, total - c0);
+    mark_words<kTZ>(actc, off, c0, n, s_items, s_mx);
     for (int i = tid; i < n; i += kBrickThreads) {
-      const uint32_t it = s_items[i];
-      const int k = (int)(it & 31u), p = (int)((it >> 5) & 7u), t = (int)(it >> 8);
+      const uint32_t mk = s_items[i];
+      const int p = (int)(mk & 255u), t = (int)((mk >> 8) & 255u);
       const int z = T.pz0 - 1 + p;
       const uint32_t ly = s_ly[t];
       Lane Lt;
       Lt.y = (int)(ly & 0xfffffu) - 1;
       Lt.l = (int)(ly >> 20);
-      const int cas = case_of(tile_corners(s_bits, T, Lt, p, t, R.G), k);
+      const Corners C = tile_corners(s_bits, T, Lt, p, t, R.G);
+      uint32_t any = 0u, all = 0xffffffffu;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        any |= C.c[c];
+        all &= C.c[c];
+      }
+      const int k = nth_set_bit(any & ~all & lane_vmask(R, Lt.l), marker_rank(mk, i));
+      const int cas = case_of(C, k);
       const int y = Lt.y, x = 32 * Lt.l - 1 + k;
       const int tk = s_tk[cas];
       nt += tk & 0xff;
@@ -605,33 +674,22 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
   __syncthreads();
   const long long base = s_base;
   for (int c0 = 0; c0 < total_e; c0 += kMeshItems) {
-    // this thread's edges with index in [c0, c0 + kMeshItems): (thread, plane, axis, cube)
-    int idx = off_e;
-#pragma unroll
-    for (int p = 0; p < kTZ; ++p)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        uint32_t m = ed[p][a];
-        const int nm = __popc(m);
-        if (idx + nm <= c0 || idx >= c0 + kMeshItems) {
-          idx += nm;
-          continue;
-        }
-        while (m && idx < c0 + kMeshItems) {
-          const int k = __ffs(m) - 1;
-          m &= m - 1u;
-          if (idx >= c0)
-            s_items[idx - c0] = ((uint32_t)tid << 10) | ((uint32_t)p << 7) | ((uint32_t)a << 5) | (uint32_t)k;
-          ++idx;
-        }
-      }
-    __syncthreads();
     const int n = min(kMeshItems, total_e - c0);
+    mark_words<3 * kTZ>(edc, off_e, c0, n, s_items, s_mx);
     for (int i = tid; i < n; i += kBrickThreads) {
-      const uint32_t it = s_items[i];
-      const int k = (int)(it & 31u), a = (int)((it >> 5) & 3u), p = (int)((it >> 7) & 7u), t = (int)(it >> 10);
+      const uint32_t mk = s_items[i];
+      const int j = (int)(mk & 255u), t = (int)((mk >> 8) & 255u);
+      const int p = j / 3, a = j - 3 * p;
       const uint32_t ly = s_ly[t];
-      const int u0 = T.pz0 - 1 + p, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * (int)(ly >> 20) - 1 + k;
+      const int l = (int)(ly >> 20);
+      // the thread's edge word (corner 0 against the corner one step along a)
+      const int w0 = p * T.nw + t + 1;
+      const int wq = a == 0 ? w0 + T.nw : (a == 1 ? w0 + R.G : w0);
+      const uint32_t r0 = s_bits[w0], rq = s_bits[wq];
+      const uint32_t x0 = l > 0 ? (s_bits[w0 - 1] >> 31) : 0u, xq = l > 0 ? (s_bits[wq - 1] >> 31) : 0u;
+      const uint32_t cq = a == 2 ? r0 : ((rq << 1) | xq);
+      const int k = nth_set_bit((((r0 << 1) | x0) ^ cq) & lane_vmask(R, l), marker_rank(mk, i));
+      const int u0 = T.pz0 - 1 + p, u1 = (int)(ly & 0xfffffu) - 1, u2 = 32 * l - 1 + k;
       const long long row = base + c0 + i;
       if (row < tmp_cap) {
         tmpkey[row] = pack_key(u0, u1, u2, a);
@@ -981,10 +1039,11 @@ __global__ __launch_bounds__(256) void k_mesh_rows(const Roi* __restrict__ rois,
                                                    unsigned long long* __restrict__ key, double* __restrict__ tsoft,
                                                    float* __restrict__ pos, uint4* __restrict__ posh,
                                                    int* __restrict__ orig, int* __restrict__ blkseg,
-                                                   unsigned int* __restrict__ overflow) {
+                                                   unsigned int* __restrict__ overflow, const int* __restrict__ bmap) {
   const long long brick = blockIdx.x;
   if (brick >= nbricks) return;
-  const int r = find_roi(rois, n_rois, brick);
+  const int r = bmap ? bmap[brick] : find_roi(rois, n_rois, brick);
+  if (r < 0) return;
   const Roi& R = rois[r];
   if (brick >= R.brick_end) return;
   const RoiMeta& M = meta[r];
@@ -1011,6 +1070,29 @@ __global__ __launch_bounds__(256) void k_mesh_rows(const Roi* __restrict__ rois,
       if ((row & 15) == 0) blkseg[row >> 4] = r;
     }
   }
+}
+
+// Brick -> ROI map of a batch, so that a brick's workgroup finds its ROI with
+// one load instead of a search of the ROI table.  Workgroup r < n_rois writes r
+// over its ROI's bricks; the others write -1 over the bricks past the last ROI
+// (the grid of a call planned on the device is sized by a bound).
+constexpr int kBrickMapTailGroups = 64;
+
+__global__ __launch_bounds__(256) void k_brick_map(const Roi* __restrict__ rois, int n_rois, long long nbricks,
+                                                   int* __restrict__ bmap) {
+  long long b0, b1, step = blockDim.x;
+  int v;
+  if ((int)blockIdx.x < n_rois) {
+    v = (int)blockIdx.x;
+    b0 = rois[v].brick_begin + threadIdx.x;
+    b1 = min(rois[v].brick_end, nbricks);
+  } else {
+    v = -1;
+    b0 = rois[n_rois - 1].brick_end + (long long)(blockIdx.x - n_rois) * blockDim.x + threadIdx.x;
+    b1 = nbricks;
+    step = (long long)kBrickMapTailGroups * blockDim.x;
+  }
+  for (long long b = b0; b < b1; b += step) bmap[b] = v;
 }
 
 // Clears the call's counters and the staged-row count (totals[8]).
@@ -1113,17 +1195,21 @@ size_t mesh_lds_bytes(int max_G) { return sizeof(uint32_t) * (size_t)(kTZ + 1) *
 hipError_t launch_mesh_pass(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             double* case_area, BrickPart* part, unsigned int* counters, int n_counters,
                             unsigned long long* tmpkey, double* tmpt, long long tmp_cap, long long* totals,
-                            int moments, hipStream_t st) {
+                            int moments, int* bmap, hipStream_t st) {
   hipLaunchKernelGGL(k_head_clear, dim3(1), dim3(1024), 0, st, counters, n_counters, totals);
   if (nbricks <= 0) return hipGetLastError();
+  if (n_rois < 2) bmap = nullptr;  // one ROI: the search is free
+  if (bmap)
+    hipLaunchKernelGGL(k_brick_map, dim3((unsigned)(n_rois + kBrickMapTailGroups)), dim3(256), 0, st, rois, n_rois,
+                       nbricks, bmap);
   const size_t lds = mesh_lds_bytes(max_G);
   if (dtype == 0) {
     hipLaunchKernelGGL(k_case_area, dim3((unsigned)n_rois), dim3(256), 0, st, rois, n_rois, case_area);
     hipLaunchKernelGGL(k_mesh_pass<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments, (const int*)bmap);
   } else {
     hipLaunchKernelGGL(k_mesh_pass<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments, (const int*)bmap);
   }
   return hipGetLastError();
 }
@@ -1142,10 +1228,10 @@ hipError_t launch_mesh_core(int dtype, const Roi* rois, int n_rois, long long nb
   const size_t lds = mesh_lds_bytes(max_G);
   if (dtype == 0)
     hipLaunchKernelGGL(k_mesh_pass<0>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments, (const int*)nullptr);
   else
     hipLaunchKernelGGL(k_mesh_pass<1>, dim3((unsigned)nbricks), dim3(kBrickThreads), lds, st, rois, n_rois, nbricks,
-                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments);
+                       case_area, part, tmpkey, tmpt, tmp_cap, totals, moments, (const int*)nullptr);
   return hipGetLastError();
 }
 
@@ -1163,11 +1249,12 @@ hipError_t launch_mesh_rows(const Roi* rois, int n_rois, long long nbricks, cons
                             const long long* brick_voff, RoiMeta* meta, long long* totals, long long rows0_cap,
                             const unsigned long long* tmpkey, const double* tmpt, long long tmp_cap,
                             unsigned long long* key, double* tsoft, float* pos, uint4* posh, int* orig, int* blkseg,
-                            Seg* segs, unsigned int* overflow, hipStream_t st) {
+                            Seg* segs, unsigned int* overflow, const int* bmap, hipStream_t st) {
   hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1024), 0, st, n_rois, rows0_cap, meta, totals, overflow, segs);
   if (nbricks > 0)
     hipLaunchKernelGGL(k_mesh_rows, dim3((unsigned)nbricks), dim3(256), 0, st, rois, n_rois, nbricks, part,
-                       brick_voff, meta, tmpkey, tmpt, tmp_cap, key, tsoft, pos, posh, orig, blkseg, overflow);
+                       brick_voff, meta, tmpkey, tmpt, tmp_cap, key, tsoft, pos, posh, orig, blkseg, overflow,
+                       n_rois < 2 ? nullptr : bmap);
   return hipGetLastError();
 }
 

@@ -61,11 +61,13 @@ hipError_t launch_small_pairs(int dtype, const Roi* rois, const BrickPart* part,
 // staging list (rows below tmp_cap are written; totals[8] counts all).
 // case_area: [n_rois * 512] scratch for the binary masks' per-case areas and
 // active-cube counts (case_hist);
-// moments: also the inside-voxel moments.
+// moments: also the inside-voxel moments;
+// bmap: [nbricks] scratch for the brick -> ROI map of a batch (unused, and may
+// be null, for one ROI).
 hipError_t launch_mesh_pass(int dtype, const Roi* rois, int n_rois, long long nbricks, int max_G,
                             double* case_area, BrickPart* part, unsigned int* counters, int n_counters,
                             unsigned long long* tmpkey, double* tmpt, long long tmp_cap, long long* totals,
-                            int moments, hipStream_t st);
+                            int moments, int* bmap, hipStream_t st);
 // Per-ROI totals and each brick's first row within its ROI (brick_voff);
 // prune_min_v: ROIs with at least this many vertices get the pruning pass's column-pair offsets.
 hipError_t launch_mesh_totals(const Roi* rois, int n_rois, long long nbricks, int dtype, const double* case_area,
@@ -79,7 +81,7 @@ hipError_t launch_mesh_rows(const Roi* rois, int n_rois, long long nbricks, cons
                             const long long* brick_voff, RoiMeta* meta, long long* totals, long long rows0_cap,
                             const unsigned long long* tmpkey, const double* tmpt, long long tmp_cap,
                             unsigned long long* key, double* tsoft, float* pos, uint4* posh, int* orig, int* blkseg,
-                            Seg* segs, unsigned int* overflow, hipStream_t st);
+                            Seg* segs, unsigned int* overflow, const int* bmap, hipStream_t st);
 
 // labels.hip: the ROI table of labels 1..max_label of a dense uint8 label map
 // (crop to each label's box, select the label), the voxel counts (counts,
