@@ -285,7 +285,7 @@ struct Batch {
   long long n_buckets = 0;  // plane buckets (a bound when planned)
   int max_G = 1;
   bool planned = false;
-  long long max_d[3] = {0, 0, 0};  // planned: every ROI's dims are at most these
+  long long max_d[3] = {0, 0, 0};  // every ROI's dims are at most these
   bool moments = false;  // also the inside-voxel moments and the whole Shape class
   int n() const { return n_rois; }
   int nf() const { return moments ? SHAPE3D_N_CLASS : 6; }  // features per ROI in out
@@ -303,6 +303,7 @@ void batch_add(Batch& B, const void* vol, const int64_t dims[3], const double sp
   B.nbricks += nb;
   B.n_buckets += roi_buckets(R.d);
   B.max_G = std::max(B.max_G, R.G);
+  for (int k = 0; k < 3; ++k) B.max_d[k] = std::max(B.max_d[k], d[k]);
   B.rois.push_back(R);
   B.n_rois = (int)B.rois.size();
 }
@@ -509,6 +510,10 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   PairBufs B;
   B.rois = P.as<const Roi>(W_ROIS);
   B.n_rois = Bt.n();
+  B.nbricks = Bt.nbricks;
+  B.part = P.as<const BrickPart>(W_PART);
+  B.brick_voff = P.as<const long long>(W_BRICK_VOFF);
+  B.bmap = Bt.n() > 1 ? P.as<const int>(W_BRICK_ROI) : nullptr;
   B.meta = P.as<const RoiMeta>(W_META);
   B.key = P.as<const unsigned long long>(W_KEY);
   B.tsoft = dtype == SHAPE3D_F32 ? P.as<const double>(W_TSOFT) : nullptr;
@@ -550,6 +555,8 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   B.cand_chbase = P.as<long long>(W_CAND_CHBASE);
   B.cu_count = cu_count;
   B.moments = Bt.moments;
+  // canonical ids 3 lin(u) + a, lin over the padded (d + 2)^3 grid
+  B.ids32 = 3.0 * (double)(Bt.max_d[0] + 2) * (double)(Bt.max_d[1] + 2) * (double)(Bt.max_d[2] + 2) < 4294967295.0;
   B.prune = false;
   B.prune_min_v = prune_min_v();
   B.blkrec = P.as<BlkRec>(W_BLKREC);

@@ -105,30 +105,163 @@ __device__ inline void wave_aggregated_inc_box(unsigned int* counter, int4* bbox
   __builtin_amdgcn_wave_barrier();
 }
 
-// Bucket counts, and with bbox set the buckets' boxes in key coordinates: a
-// vertex on edge (u, u + e_a) has coordinate 2 u_j + [a == j] along axis j;
-// the box of a bucket of axis k holds the two other axes in increasing order.
-__global__ __launch_bounds__(256) void k_bucket_hist(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
-                                                     const int* __restrict__ blkseg,
-                                                     const unsigned long long* __restrict__ key,
-                                                     const long long* __restrict__ totals,
-                                                     unsigned int* __restrict__ bcnt, int4* __restrict__ bbox) {
+// Bucket-index windows of a brick held in LDS (all three axes together).
+constexpr int kBrickWin = 2048;
+
+// A brick's vertices: its rows of layout 0 (consecutive, in the mesh pass's
+// order) and its ROI.  False for a brick with no vertex, past the last ROI, or
+// of an emptied ROI.
+struct BrickRows {
+  long long row0, n;
+  int roi;
+};
+
+__device__ inline bool brick_rows(const BrickArgs& A, long long brick, BrickRows& out) {
+  if (brick >= A.nbricks) return false;
+  const int r = A.bmap ? A.bmap[brick] : find_roi(A.rois, A.n_rois, brick);
+  if (r < 0 || brick >= A.rois[r].brick_end) return false;
+  const RoiMeta& M = A.meta[r];
+  const long long cnt = A.part[brick].nv, first = A.brick_voff[brick];
+  if (cnt == 0 || M.V == 0 || first + cnt > M.V) return false;
+  out.row0 = M.row_off + first;
+  out.n = cnt;
+  out.roi = r;
+  return true;
+}
+
+// Plane keys of a vertex: along axis j, 2 u_j + [a == j] for the edge
+// (u, u + e_a), as bucket indices key + 1 within the ROI's 2 d_j + 1 buckets of
+// axis j (a key outside them, which only a stale row could hold, gives -1).
+__device__ inline void vertex_buckets(unsigned long long k, const int* d, int* bi, int* kc) {
+  const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};  // u + 1
+  const int a = (int)((k >> 60) & 3);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    kc[j] = 2 * (p[j] - 1) + (a == j);
+    bi[j] = kc[j] + 1;
+    if (bi[j] < 0 || bi[j] > 2 * d[j]) bi[j] = -1;
+  }
+}
+
+// The brick's window of bucket indices [lo_j, hi_j] per axis (LDS s_lo,
+// s_hi); returns the windows' total width, or a value above kBrickWin when
+// they do not fit the LDS tables.  Contains barriers.
+__device__ inline int brick_windows(const unsigned long long* __restrict__ key, const BrickRows& W, const int* d,
+                                    int* s_lo, int* s_hi, int* off) {
+  const int tid = threadIdx.x;
+  if (tid < 3) {
+    s_lo[tid] = INT_MAX;
+    s_hi[tid] = INT_MIN;
+  }
+  __syncthreads();
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  for (long long i = tid; i < W.n; i += blockDim.x) {
+    int bi[3], kc[3];
+    vertex_buckets(key[W.row0 + i], d, bi, kc);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (bi[j] >= 0) {
+        lo[j] = min(lo[j], bi[j]);
+        hi[j] = max(hi[j], bi[j]);
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = wave_min(lo[j]);
+    hi[j] = wave_max(hi[j]);
+  }
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      atomicMin(&s_lo[j], lo[j]);
+      atomicMax(&s_hi[j], hi[j]);
+    }
+  __syncthreads();
+  int total = 0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    off[j] = total;
+    total += s_hi[j] >= s_lo[j] ? s_hi[j] - s_lo[j] + 1 : 0;
+  }
+  return total;
+}
+
+// Bucket counts, and with bbox set the buckets' boxes in key coordinates (the
+// box of a bucket of axis k holds the two other axes in increasing order).
+// One workgroup per brick: a brick's vertices lie on few planes of each axis,
+// so they are counted per plane in LDS windows and each plane the brick
+// touches costs one global atomic (plus the box's, where it grows).  A brick
+// whose windows exceed kBrickWin planes uses wave-aggregated global atomics
+// per vertex instead.
+__global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned long long* __restrict__ key,
+                                                    unsigned int* __restrict__ bcnt, int4* __restrict__ bbox) {
+  extern __shared__ int s_win[];  // kBrickWin counts, then with bbox kBrickWin boxes
+  __shared__ int s_lo[3], s_hi[3];
   __shared__ int s_slot[4][64 * 4];
-  const long long rows0 = totals[T_ROWS0];
-  // the trip count is uniform per wave (rows0 is a multiple of the wave size)
-  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
-       row += (long long)gridDim.x * blockDim.x) {
-    const int roi = blkseg[row >> 4];
-    const RoiMeta& M = meta[roi];
-    if (row - M.row_off < M.V) {
-      const unsigned long long k = key[row];
-      const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};  // u + 1
-      const int a = (int)((k >> 60) & 3);
-      const int kc[3] = {2 * (p[0] - 1) + (a == 0), 2 * (p[1] - 1) + (a == 1), 2 * (p[2] - 1) + (a == 2)};
-      for (int ax = 0; ax < 3; ++ax) {
-        const long long b = rois[roi].bucket_base[ax] + kc[ax] + 1;
+  BrickRows W;
+  if (!brick_rows(A, blockIdx.x, W)) return;
+  const Roi& R = A.rois[W.roi];
+  const int tid = threadIdx.x;
+  int off[3];
+  const int total = brick_windows(key, W, R.d, s_lo, s_hi, off);
+  int* s_box = s_win + kBrickWin;
+  if (total <= kBrickWin) {
+    for (int w = tid; w < total; w += blockDim.x) {
+      s_win[w] = 0;
+      if (bbox) {
+        s_box[4 * w] = INT_MAX;
+        s_box[4 * w + 1] = INT_MIN;
+        s_box[4 * w + 2] = INT_MAX;
+        s_box[4 * w + 3] = INT_MIN;
+      }
+    }
+    __syncthreads();
+    for (long long i = tid; i < W.n; i += blockDim.x) {
+      int bi[3], kc[3];
+      vertex_buckets(key[W.row0 + i], R.d, bi, kc);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (bi[j] < 0) continue;
+        const int w = off[j] + bi[j] - s_lo[j];
+        atomicAdd(&s_win[w], 1);
+        if (bbox) {
+          const int cu = kc[j == 0 ? 1 : 0], cv = kc[j == 2 ? 1 : 2];
+          atomicMin(&s_box[4 * w], cu);
+          atomicMax(&s_box[4 * w + 1], cu);
+          atomicMin(&s_box[4 * w + 2], cv);
+          atomicMax(&s_box[4 * w + 3], cv);
+        }
+      }
+    }
+    __syncthreads();
+    for (int w = tid; w < total; w += blockDim.x) {
+      const int c = s_win[w];
+      if (!c) continue;
+      const int j = w >= off[2] ? 2 : (w >= off[1] ? 1 : 0);
+      const long long b = R.bucket_base[j] + s_lo[j] + (w - off[j]);
+      atomicAdd(&bcnt[b], (unsigned int)c);
+      if (bbox) {
+        // the box only grows: a bound that a (possibly stale) read already
+        // covers needs no atomic
+        int* g = (int*)&bbox[b];
+        const int* q = s_box + 4 * w;
+        int cur[4];
+        for (int e = 0; e < 4; ++e) cur[e] = __hip_atomic_load(&g[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (q[0] < cur[0]) atomicMin(&g[0], q[0]);
+        if (q[1] > cur[1]) atomicMax(&g[1], q[1]);
+        if (q[2] < cur[2]) atomicMin(&g[2], q[2]);
+        if (q[3] > cur[3]) atomicMax(&g[3], q[3]);
+      }
+    }
+  } else {
+    for (long long i = tid; i < W.n; i += blockDim.x) {
+      int bi[3], kc[3];
+      vertex_buckets(key[W.row0 + i], R.d, bi, kc);
+      for (int j = 0; j < 3; ++j) {
+        if (bi[j] < 0) continue;  // lanes with an invalid key sit out of the grouping
+        const long long b = R.bucket_base[j] + bi[j];
         if (bbox)
-          wave_aggregated_inc_box(bcnt, bbox, b, kc[ax == 0 ? 1 : 0], kc[ax == 2 ? 1 : 2], s_slot[threadIdx.x >> 6]);
+          wave_aggregated_inc_box(bcnt, bbox, b, kc[j == 0 ? 1 : 0], kc[j == 2 ? 1 : 2], s_slot[tid >> 6]);
         else
           wave_aggregated_inc(bcnt, b);
       }
@@ -213,59 +346,112 @@ __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long 
   }
 }
 
-__global__ void k_bucket_scatter(const Roi* __restrict__ rois, const RoiMeta* __restrict__ meta,
-                                 const int* __restrict__ blkseg, const unsigned long long* __restrict__ key,
-                                 const long long* __restrict__ totals, const unsigned int* __restrict__ bcnt,
-                                 unsigned int* __restrict__ bcur, const long long* __restrict__ brow,
-                                 float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig) {
+// Copies every vertex's operand row into its three plane buckets (those with
+// at least two vertices after pruning), at rows0 + brow[b] + slot.  One
+// workgroup per brick: the brick counts its vertices per plane in LDS, takes
+// its slots of each plane with one global atomic, and hands them out with LDS
+// atomics.  A brick whose windows exceed kBrickWin planes groups the lanes of
+// a wave per bucket and issues one global atomic per group instead.
+__global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsigned long long* __restrict__ key,
+                                                       const long long* __restrict__ totals,
+                                                       const unsigned int* __restrict__ bcnt,
+                                                       unsigned int* __restrict__ bcur,
+                                                       const long long* __restrict__ brow, float* __restrict__ pos,
+                                                       uint4* __restrict__ posh, int* __restrict__ orig) {
+  extern __shared__ int s_win[];  // kBrickWin counts (then ranks), then kBrickWin slot bases
+  __shared__ int s_lo[3], s_hi[3];
+  BrickRows W;
+  if (!brick_rows(A, blockIdx.x, W)) return;
+  const Roi& R = A.rois[W.roi];
   const long long rows0 = totals[T_ROWS0];
-  const int lane = threadIdx.x & 63;
-  for (long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x; row < rows0;
-       row += (long long)gridDim.x * blockDim.x) {
-    const int roi = blkseg[row >> 4];
-    const RoiMeta& M = meta[roi];
-    long long b[3] = {0, 0, 0};
-    bool on[3] = {false, false, false};
-    if (row - M.row_off < M.V) {
-      const unsigned long long k = key[row];
-      const int p[3] = {(int)((k >> 40) & 0xFFFFF), (int)((k >> 20) & 0xFFFFF), (int)(k & 0xFFFFF)};
-      const int a = (int)((k >> 60) & 3);
+  const int tid = threadIdx.x, lane = tid & 63;
+  int off[3];
+  const int total = brick_windows(key, W, R.d, s_lo, s_hi, off);
+  unsigned int* s_base = (unsigned int*)(s_win + kBrickWin);
+  if (total <= kBrickWin) {
+    for (int w = tid; w < total; w += blockDim.x) s_win[w] = 0;
+    __syncthreads();
+    for (long long i = tid; i < W.n; i += blockDim.x) {
+      int bi[3], kc[3];
+      vertex_buckets(key[W.row0 + i], R.d, bi, kc);
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        b[ax] = rois[roi].bucket_base[ax] + 2 * (p[ax] - 1) + (a == ax) + 1;
-        on[ax] = bcnt[b[ax]] >= 2;
+      for (int j = 0; j < 3; ++j)
+        if (bi[j] >= 0) atomicAdd(&s_win[off[j] + bi[j] - s_lo[j]], 1);
+    }
+    __syncthreads();
+    for (int w = tid; w < total; w += blockDim.x) {
+      const int c = s_win[w];
+      unsigned int base = UINT_MAX;
+      if (c) {
+        const int j = w >= off[2] ? 2 : (w >= off[1] ? 1 : 0);
+        const long long b = R.bucket_base[j] + s_lo[j] + (w - off[j]);
+        if (bcnt[b] >= 2u) base = atomicAdd(&bcur[b], (unsigned int)c);
+      }
+      s_base[w] = base;
+      s_win[w] = 0;  // from here on: slots handed out
+    }
+    __syncthreads();
+    for (long long i = tid; i < W.n; i += blockDim.x) {
+      const long long row = W.row0 + i;
+      int bi[3], kc[3];
+      vertex_buckets(key[row], R.d, bi, kc);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (bi[j] < 0) continue;
+        const int w = off[j] + bi[j] - s_lo[j];
+        const unsigned int base = s_base[w];
+        if (base == UINT_MAX) continue;
+        const unsigned int slot = base + (unsigned int)atomicAdd(&s_win[w], 1);
+        const long long dst_row = rows0 + brow[R.bucket_base[j] + bi[j]] + slot;
+        copy_row_operands(pos, posh, row, dst_row);
+        orig[dst_row] = (int)row;
       }
     }
-    // The three buckets' slots: lanes are grouped per axis by bucket (ALU
-    // only) and the leaders' three atomics are all issued before any result
-    // is used, so a wave waits for one atomic round trip per row batch.
-    unsigned int base[3] = {0u, 0u, 0u}, rank[3] = {0u, 0u, 0u};
-    int lead[3] = {lane, lane, lane};
+  } else {
+    for (long long i0 = 0; i0 < W.n; i0 += blockDim.x) {
+      const long long i = i0 + tid;
+      const long long row = W.row0 + i;
+      long long b[3] = {0, 0, 0};
+      bool on[3] = {false, false, false};
+      if (i < W.n) {
+        int bi[3], kc[3];
+        vertex_buckets(key[row], R.d, bi, kc);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      unsigned long long todo = __ballot(on[ax]);
-      unsigned int group = 0;
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const long long bl = __shfl(b[ax], leader, 64);
-        const bool mine = on[ax] && b[ax] == bl;
-        const unsigned long long same = __ballot(mine) & todo;
-        if (mine) {
-          lead[ax] = leader;
-          rank[ax] = (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+        for (int j = 0; j < 3; ++j) {
+          b[j] = R.bucket_base[j] + bi[j];
+          on[j] = bi[j] >= 0 && bcnt[b[j]] >= 2u;
         }
-        if (lane == leader) group = (unsigned int)__popcll(same);
-        todo &= ~same;
       }
-      if (group) base[ax] = atomicAdd(&bcur[b[ax]], group);
-    }
+      // the three buckets' slots: lanes are grouped per axis by bucket (ALU
+      // only) and the leaders' atomics are all issued before any result is used
+      unsigned int base[3] = {0u, 0u, 0u}, rank[3] = {0u, 0u, 0u};
+      int lead[3] = {lane, lane, lane};
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const unsigned int slot = __shfl(base[ax], lead[ax], 64) + rank[ax];
-      if (!on[ax]) continue;
-      const long long dst_row = rows0 + brow[b[ax]] + slot;
-      copy_row_operands(pos, posh, row, dst_row);
-      orig[dst_row] = (int)row;
+      for (int j = 0; j < 3; ++j) {
+        unsigned long long todo = __ballot(on[j]);
+        unsigned int group = 0;
+        while (todo) {
+          const int leader = __ffsll((long long)todo) - 1;
+          const long long bl = __shfl(b[j], leader, 64);
+          const bool mine = on[j] && b[j] == bl;
+          const unsigned long long same = __ballot(mine) & todo;
+          if (mine) {
+            lead[j] = leader;
+            rank[j] = (unsigned int)__popcll(same & ((1ull << lane) - 1ull));
+          }
+          if (lane == leader) group = (unsigned int)__popcll(same);
+          todo &= ~same;
+        }
+        if (group) base[j] = atomicAdd(&bcur[b[j]], group);
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const unsigned int slot = __shfl(base[j], lead[j], 64) + rank[j];
+        if (!on[j]) continue;
+        const long long dst_row = rows0 + brow[b[j]] + slot;
+        copy_row_operands(pos, posh, row, dst_row);
+        orig[dst_row] = (int)row;
+      }
     }
   }
 }
@@ -851,20 +1037,112 @@ __global__ void k_candidates(const float* __restrict__ rowmax, const int* __rest
   }
 }
 
+// Rows of a segment rescanned by one wave (16 per lane).
+constexpr int kExactWave = 1024;
+
 // Chunks of each candidate's segment, for the candidates found (the scan that
 // follows reads no further).
 __global__ void k_cand_chunks(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
                               const int* __restrict__ blkseg, const Seg* __restrict__ segs,
                               long long* __restrict__ nch, long long cand_cap) {
   const long long nc = min((long long)*ncand_p, cand_cap);
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x)
-    nch[c] = (segs[blkseg[cand[c] >> 4]].n_rows + kExactChunk - 1) / kExactChunk;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride) {
+    // a segment of at most kExactWave rows is rescanned by a wave of its own
+    // (k_exact, first phase) and gets no work items
+    const long long n = segs[blkseg[cand[c] >> 4]].n_rows;
+    nch[c] = n > kExactWave ? (n + kExactChunk - 1) / kExactChunk : 0;
+  }
 }
 
 // Exact FP64 rescans of candidate rows.  Work item = (candidate, chunk of its
 // segment) from the prefix sum chbase.  PASS 0: maximum squared distance;
 // PASS 1: smallest id of the pairs that reach it; PASS 2: smallest partner id
-// of those; PASS 3: the rows of the chosen pair.
+// of those; PASS 3: the rows of the chosen pair (only items whose candidate
+// is one of its two vertices scan their chunk).  With ids32 (every id of the
+// call below 2^32) PASS 1 takes the smallest id_lo * 2^32 + id_hi at once
+// into id_lo, and PASS 2 is not run.
+// One candidate row against rows [jb, je) of its segment: the pass's value
+// over those pairs, reduced over the lanes that take part (lane, step).
+template <int PASS>
+__device__ inline unsigned long long exact_scan(long long jb, long long je, int lane, int step, int vi,
+                                                const double* pi, unsigned long long idi, const Roi& R,
+                                                double target, unsigned long long lo_ref,
+                                                unsigned long long hi_ref, int ids32, int g,
+                                                const int* __restrict__ orig,
+                                                const unsigned long long* __restrict__ key,
+                                                const double* __restrict__ tsoft, GroupRes* __restrict__ gres) {
+  unsigned long long red = PASS == 0 ? 0ull : ~0ull;
+  for (long long j = jb + lane; j < je; j += step) {
+    const int vj = orig[j];
+    const unsigned long long kj = key[vj];
+    double pj[3];
+    key_position(kj, tsoft ? tsoft[vj] : 0.5, R.s, pj);
+    const double d2 = dist2_exact(pi, pj);
+    if (PASS == 0) {
+      red = max(red, (unsigned long long)__double_as_longlong(d2));
+    } else if (vi != vj && d2 == target) {
+      const unsigned long long idj = key_canonical_id(kj, R.d);
+      const unsigned long long lo_id = min(idi, idj), hi_id = max(idi, idj);
+      if (PASS == 1) red = min(red, ids32 ? (lo_id << 32) | hi_id : lo_id);
+      if (PASS == 2 && lo_id == lo_ref) red = min(red, hi_id);
+      if (PASS == 3 && lo_id == lo_ref && hi_id == hi_ref) {
+        gres[g].row_i = idi == lo_id ? vi : vj;
+        gres[g].row_j = idi == lo_id ? vj : vi;
+      }
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long o = __shfl_xor(red, m, 64);
+    red = PASS == 0 ? max(red, o) : min(red, o);
+  }
+  return red;
+}
+
+template <int PASS>
+__device__ inline void exact_commit(GroupRes* __restrict__ gres, int g, unsigned long long red) {
+  if (red == (PASS == 0 ? 0ull : ~0ull)) return;
+  if (PASS == 0) atomicMax(&gres[g].best_bits, red);
+  if (PASS == 1) atomicMin(&gres[g].id_lo, red);
+  if (PASS == 2) atomicMin(&gres[g].id_hi, red);
+}
+
+// The candidate row, its group and the group's references for the pass.
+struct ExactRow {
+  int vi, g;
+  long long row_begin, n_rows;
+  double pi[3];
+  unsigned long long idi, lo_ref, hi_ref;
+  double target;
+};
+
+__device__ inline ExactRow exact_row(int row_i, const int* __restrict__ blkseg, const Seg* __restrict__ segs,
+                                     const int* __restrict__ orig, const unsigned long long* __restrict__ key,
+                                     const double* __restrict__ tsoft, const Roi* __restrict__ rois,
+                                     const GroupRes* __restrict__ gres, int ids32) {
+  ExactRow E;
+  const Seg S = segs[blkseg[row_i >> 4]];
+  E.g = S.group;
+  E.row_begin = S.row_begin;
+  E.n_rows = S.n_rows;
+  const Roi& R = rois[E.g >> 2];
+  E.vi = orig[row_i];
+  const unsigned long long ki = key[E.vi];
+  key_position(ki, tsoft ? tsoft[E.vi] : 0.5, R.s, E.pi);
+  E.idi = key_canonical_id(ki, R.d);
+  E.target = __longlong_as_double((long long)gres[E.g].best_bits);
+  const unsigned long long gl = gres[E.g].id_lo;
+  E.lo_ref = ids32 ? gl >> 32 : gl;
+  E.hi_ref = ids32 ? gl & 0xffffffffull : gres[E.g].id_hi;
+  return E;
+}
+
+// Two phases: first every candidate whose segment holds at most kExactWave
+// rows, a wave each (most candidates lie in plane buckets of tens to hundreds
+// of rows, where a workgroup per candidate would leave most lanes idle and a
+// search of chbase per item would cost more than the scan); then the work
+// items (candidate, chunk) of the longer segments from the prefix sum
+// chbase, a workgroup each.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, const unsigned int* __restrict__ ncand_p,
                                                const long long* __restrict__ chbase,
@@ -872,11 +1150,22 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
                                                const int* __restrict__ blkseg, const Seg* __restrict__ segs,
                                                const int* __restrict__ orig, const unsigned long long* __restrict__ key,
                                                const double* __restrict__ tsoft, const Roi* __restrict__ rois,
-                                               GroupRes* __restrict__ gres, long long cand_cap) {
+                                               GroupRes* __restrict__ gres, long long cand_cap, int ids32) {
   __shared__ unsigned long long sh[4];
   const int nc = (int)min((long long)*ncand_p, cand_cap);
   const long long n_work = *n_work_p;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long c = ((long long)blockIdx.x * blockDim.x + tid) >> 6; c < nc; c += nwaves) {
+    const int row_i = cand[c];
+    if (segs[blkseg[row_i >> 4]].n_rows > kExactWave) continue;
+    const ExactRow E = exact_row(row_i, blkseg, segs, orig, key, tsoft, rois, gres, ids32);
+    if (PASS == 3 && E.idi != E.lo_ref && E.idi != E.hi_ref) continue;
+    const unsigned long long red =
+        exact_scan<PASS>(E.row_begin, E.row_begin + E.n_rows, lane, 64, E.vi, E.pi, E.idi, rois[E.g >> 2],
+                         E.target, E.lo_ref, E.hi_ref, ids32, E.g, orig, key, tsoft, gres);
+    if (PASS != 3 && lane == 0) exact_commit<PASS>(gres, E.g, red);
+  }
   for (long long w = blockIdx.x; w < n_work; w += gridDim.x) {
     int lo = 0, hi = nc - 1;
     while (lo < hi) {
@@ -886,53 +1175,19 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
       else
         hi = mid - 1;
     }
-    const int row_i = cand[lo];
-    const long long chunk = w - chbase[lo];
-    const Seg S = segs[blkseg[row_i >> 4]];
-    const long long jb = S.row_begin + chunk * kExactChunk;
-    const long long je = min(jb + (long long)kExactChunk, S.row_begin + (long long)S.n_rows);
-    const int g = S.group;
-    const Roi& R = rois[g >> 2];
-    const int vi = orig[row_i];
-    const unsigned long long ki = key[vi];
-    double pi[3];
-    key_position(ki, tsoft ? tsoft[vi] : 0.5, R.s, pi);
-    const unsigned long long idi = key_canonical_id(ki, R.d);
-    const double target = __longlong_as_double((long long)gres[g].best_bits);
-    const unsigned long long lo_ref = gres[g].id_lo, hi_ref = gres[g].id_hi;
-    unsigned long long red = PASS == 0 ? 0ull : ~0ull;
-    for (long long j = jb + tid; j < je; j += 256) {
-      const int vj = orig[j];
-      const unsigned long long kj = key[vj];
-      double pj[3];
-      key_position(kj, tsoft ? tsoft[vj] : 0.5, R.s, pj);
-      const double d2 = dist2_exact(pi, pj);
-      if (PASS == 0) {
-        red = max(red, (unsigned long long)__double_as_longlong(d2));
-      } else if (vi != vj && d2 == target) {
-        const unsigned long long idj = key_canonical_id(kj, R.d);
-        const unsigned long long lo_id = min(idi, idj), hi_id = max(idi, idj);
-        if (PASS == 1) red = min(red, lo_id);
-        if (PASS == 2 && lo_id == lo_ref) red = min(red, hi_id);
-        if (PASS == 3 && lo_id == lo_ref && hi_id == hi_ref) {
-          gres[g].row_i = idi == lo_id ? vi : vj;
-          gres[g].row_j = idi == lo_id ? vj : vi;
-        }
-      }
-    }
+    const ExactRow E = exact_row(cand[lo], blkseg, segs, orig, key, tsoft, rois, gres, ids32);
+    if (PASS == 3 && E.idi != E.lo_ref && E.idi != E.hi_ref) continue;  // uniform over the workgroup
+    const long long jb = E.row_begin + (w - chbase[lo]) * kExactChunk;
+    const long long je = min(jb + (long long)kExactChunk, E.row_begin + E.n_rows);
+    unsigned long long red = exact_scan<PASS>(jb, je, tid, 256, E.vi, E.pi, E.idi, rois[E.g >> 2], E.target,
+                                              E.lo_ref, E.hi_ref, ids32, E.g, orig, key, tsoft, gres);
     if (PASS == 3) continue;
-    for (int m = 32; m >= 1; m >>= 1) {
-      const unsigned long long o = __shfl_xor(red, m, 64);
-      red = PASS == 0 ? max(red, o) : min(red, o);
-    }
     __syncthreads();
     if (lane == 0) sh[wid] = red;
     __syncthreads();
     if (tid == 0) {
       for (int k = 0; k < 4; ++k) red = PASS == 0 ? max(red, sh[k]) : min(red, sh[k]);
-      if (PASS == 0) atomicMax(&gres[g].best_bits, red);
-      if (PASS == 1) atomicMin(&gres[g].id_lo, red);
-      if (PASS == 2) atomicMin(&gres[g].id_hi, red);
+      exact_commit<PASS>(gres, E.g, red);
     }
   }
 }
@@ -1023,7 +1278,7 @@ __device__ inline void shape_class_members(const RoiMeta& M, const Roi& R, doubl
 __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const GroupRes* __restrict__ gres,
                            const unsigned int* __restrict__ ncand, const unsigned long long* __restrict__ key,
                            const Roi* __restrict__ rois, const long long* __restrict__ pairs2d,
-                           RoiResult* __restrict__ res, long long cand_cap, int moments) {
+                           RoiResult* __restrict__ res, long long cand_cap, int moments, int ids32) {
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_rois; r += gridDim.x * blockDim.x) {
     const RoiMeta M = meta[r];
     RoiResult Q;
@@ -1038,8 +1293,9 @@ __global__ void k_finalize(int n_rois, const RoiMeta* __restrict__ meta, const G
       const double d2 = __longlong_as_double((long long)G.best_bits);
       Q.out[2 + f] = sqrt(d2);
       const bool have = G.id_lo != ~0ull;
-      Q.ids[f][0] = have ? (long long)G.id_lo : -1;
-      Q.ids[f][1] = have ? (long long)G.id_hi : -1;
+      const unsigned long long lo = ids32 ? G.id_lo >> 32 : G.id_lo, hi = ids32 ? G.id_lo & 0xffffffffull : G.id_hi;
+      Q.ids[f][0] = have ? (long long)lo : -1;
+      Q.ids[f][1] = have ? (long long)hi : -1;
       Q.rows[f][0] = have ? G.row_i : -1;
       Q.rows[f][1] = have ? G.row_j : -1;
       Q.cand[f] = G.n_cand;
@@ -1105,6 +1361,18 @@ static bool small_buckets(const PairBufs& B) { return B.tune.kernel == 1 && B.n_
 // written in place of the FP32 positions), else null.
 uint4* split_rows(const PairBufs& B) { return B.tune.kernel == 1 ? B.posh : nullptr; }
 
+static BrickArgs brick_args(const PairBufs& B) {
+  BrickArgs A;
+  A.rois = B.rois;
+  A.n_rois = B.n_rois;
+  A.meta = B.meta;
+  A.part = B.part;
+  A.brick_voff = B.brick_voff;
+  A.bmap = B.n_rois > 1 ? B.bmap : nullptr;
+  A.nbricks = B.nbricks;
+  return A;
+}
+
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipError_t e;
   // Whole plane buckets are pruned with the pair tiles in calls with many
@@ -1115,8 +1383,10 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   int4* bbox = B.prune && B.n_buckets >= kSmallMinBuckets ? B.bbox : nullptr;
   hipLaunchKernelGGL(k_zero_buckets, dim3(grid_for(std::max<long long>(B.n_buckets, B.n_rois), 4096)), dim3(256), 0,
                      st, B.bcnt, B.bcur, B.n_buckets, B.pairs2d, (long long)B.n_rois, bbox);
-  hipLaunchKernelGGL(k_bucket_hist, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.totals, B.bcnt, bbox);
+  const BrickArgs A = brick_args(B);
+  if (B.nbricks > 0)
+    hipLaunchKernelGGL(k_brick_hist, dim3((unsigned)B.nbricks), dim3(256), sizeof(int) * kBrickWin * (bbox ? 5 : 1),
+                       st, A, B.key, B.bcnt, bbox);
   if (bbox)
     hipLaunchKernelGGL(k_bucket_prune, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.tsoft ? 1 : 0, B.bcnt,
                        bbox, B.pairs2d);
@@ -1124,8 +1394,9 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
                      B.bflag);
   if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(grid_for(B.rows0)), dim3(256), 0, st, B.rois, B.meta, B.blkseg, B.key,
-                     B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig);
+  if (B.nbricks > 0)
+    hipLaunchKernelGGL(k_brick_scatter, dim3((unsigned)B.nbricks), dim3(256), sizeof(int) * kBrickWin * 2, st, A,
+                       B.key, B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig);
   hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
@@ -1225,10 +1496,11 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
   const unsigned grid = (unsigned)(B.cu_count * 8);
 #define S3D_EXACT(P)                                                                                             \
   hipLaunchKernelGGL(k_exact<P>, dim3(grid), dim3(256), 0, st, B.cand, B.counters + 1, B.cand_chbase,             \
-                     B.totals + T_NEXACT, B.blkseg, B.segs, B.orig, B.key, B.tsoft, B.rois, B.gres, B.cand_cap)
+                     B.totals + T_NEXACT, B.blkseg, B.segs, B.orig, B.key, B.tsoft, B.rois, B.gres, B.cand_cap,    \
+                     B.ids32 ? 1 : 0)
   S3D_EXACT(0);
   S3D_EXACT(1);
-  S3D_EXACT(2);
+  if (!B.ids32) S3D_EXACT(2);
   S3D_EXACT(3);
 #undef S3D_EXACT
   return hipGetLastError();
@@ -1236,7 +1508,7 @@ hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
 
 hipError_t launch_finalize(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(B.n_rois)), dim3(256), 0, st, B.n_rois, B.meta, B.gres,
-                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res, B.cand_cap, B.moments ? 1 : 0);
+                     B.counters + 1, B.key, B.rois, B.pairs2d, B.res, B.cand_cap, B.moments ? 1 : 0, B.ids32 ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -118,9 +118,24 @@ struct Tuning {
 };
 
 // Buffers of the diameter passes.
+// What a per-brick kernel needs to find a brick's vertices in layout 0.
+struct BrickArgs {
+  const Roi* rois;
+  int n_rois;
+  const RoiMeta* meta;
+  const BrickPart* part;       // [nbricks] the mesh pass's per-brick records
+  const long long* brick_voff;  // [nbricks] each brick's first vertex within its ROI
+  const int* bmap;             // [nbricks] brick -> ROI map, or null (then the ROI table is searched)
+  long long nbricks;
+};
+
 struct PairBufs {
   const Roi* rois;
   int n_rois;
+  long long nbricks;            // bricks of the mesh pass (its grid)
+  const BrickPart* part;        // [nbricks]
+  const long long* brick_voff;  // [nbricks]
+  const int* bmap;              // [nbricks] or null
   const RoiMeta* meta;
   const unsigned long long* key;
   const double* tsoft;  // null for binary masks
@@ -162,6 +177,7 @@ struct PairBufs {
   long long* pairs2d;      // [n_rois] in-plane pairs n*(n-1)/2 summed over buckets
   int cu_count;
   bool moments;            // RoiMeta holds inside-voxel moments: finalise the whole Shape class
+  bool ids32;              // every canonical vertex id of the call is below 2^32 (packed tie-break)
   // 3D pruning (prune.hip), kernel 1 only: when `prune` is set the 3D
   // segments run from the pruned item list instead of the work list
   bool prune;

@@ -220,7 +220,7 @@ def source_hash(files=None) -> str:
 
 KERNEL_SOURCES = {
     "k_pair_maxima_h": ["pairs.hip"], "k_pair_maxima": ["pairs.hip"],
-    "k_bucket_scatter": ["pairs.hip"], "k_bucket_hist": ["pairs.hip"],
+    "k_brick_scatter": ["pairs.hip"], "k_brick_hist": ["pairs.hip"],
     "k_mesh_pass": ["mesh.hip"], "k_mesh_rows": ["mesh.hip"],
 }
 
