@@ -456,8 +456,11 @@ __global__ __launch_bounds__(256) void k_small_head(Roi R, Roi* __restrict__ roi
 // at its offset in brick order, so the final order does not depend on the
 // order of the reservations.
 
+// Binary masks: at most 80 VGPRs, so that six bricks share a CU and the
+// 1,330 bricks of a 300 x 512 x 512 volume run in one round on 256 CUs (a few
+// registers spill; measured faster than 96 VGPRs and five bricks per CU).
 template <int DT>
-__global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restrict__ rois, int n_rois,
+__global__ __launch_bounds__(kBrickThreads, DT == 0 ? 6 : 1) void k_mesh_pass(const Roi* __restrict__ rois, int n_rois,
                                                              long long nbricks, double* __restrict__ case_area,
                                                              BrickPart* __restrict__ part,
                                                              unsigned long long* __restrict__ tmpkey,
@@ -521,25 +524,29 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
   int cnt = 0, cnt_e = 0;
   long long mom[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   {
-    uint32_t rr[kTZ + 1][2], xx[kTZ + 1][2];
-#pragma unroll
-    for (int p = 0; p <= kTZ; ++p)
+    // voxel rows y and y + 1 (and the bit before each) of the current voxel
+    // plane and the next one, read from the tile one plane at a time
+    uint32_t r0[2] = {0u, 0u}, x0[2] = {0u, 0u};
+    auto plane_rows = [&](int p, uint32_t* r, uint32_t* x) {
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy) {
-        rr[p][dy] = 0u;
-        xx[p][dy] = 0u;
+        r[dy] = 0u;
+        x[dy] = 0u;
         if (L.valid && p < T.np) {
           const int w = p * T.nw + tid + 1 + dy * R.G;
-          rr[p][dy] = s_bits[w];
-          xx[p][dy] = L.l > 0 ? (s_bits[w - 1] >> 31) : 0u;
+          r[dy] = s_bits[w];
+          x[dy] = L.l > 0 ? (s_bits[w - 1] >> 31) : 0u;
         }
       }
+    };
+    plane_rows(0, r0, x0);
 #pragma unroll
     for (int p = 0; p < kTZ; ++p) {
+      uint32_t r1[2], x1[2];
+      plane_rows(p + 1, r1, x1);
       uint32_t act = 0u, ed[3] = {0u, 0u, 0u};
       if (L.valid && p + 1 < T.np) {
-        const Corners C = make_corners(rr[p][0], xx[p][0], rr[p][1], xx[p][1], rr[p + 1][0], xx[p + 1][0],
-                                       rr[p + 1][1], xx[p + 1][1]);
+        const Corners C = make_corners(r0[0], x0[0], r0[1], x0[1], r1[0], x1[0], r1[1], x1[1]);
         uint32_t any = 0u, all = 0xffffffffu;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
@@ -570,36 +577,11 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
         edc[(3 * p + a) >> 2] |= ce << (8 * ((3 * p + a) & 3));
         cnt_e += (int)ce;
       }
-    }
-    if (moments && L.valid) {
-      // voxel row (z, y) = (pz0 + p, L.y + 1), x = 32 l + bit, is word rr[p + 1][1]
-      // (the far corner row of plane pair p); rows past the array read as 0
-      long long n = 0, sz = 0, szz = 0, sb1 = 0, sb2 = 0, szb = 0;
 #pragma unroll
-      for (int p = 0; p < kTZ; ++p) {
-        if (p + 1 < T.np) {
-          const WordMom wm = word_moments(rr[p + 1][1]);
-          const long long z = T.pz0 + p;
-          n += wm.c;
-          sz += z * wm.c;
-          szz += z * z * wm.c;
-          sb1 += wm.b1;
-          sb2 += wm.b2;
-          szb += z * wm.b1;
-        }
+      for (int dy = 0; dy < 2; ++dy) {
+        r0[dy] = r1[dy];
+        x0[dy] = x1[dy];
       }
-      const long long y = L.y + 1, x0 = 32ll * L.l;
-      const long long sx = x0 * n + sb1;
-      mom[0] = n;
-      mom[1] = sz;
-      mom[2] = y * n;
-      mom[3] = sx;
-      mom[4] = szz;
-      mom[5] = y * y * n;
-      mom[6] = x0 * x0 * n + 2 * x0 * sb1 + sb2;
-      mom[7] = y * sz;
-      mom[8] = x0 * sz + szb;
-      mom[9] = y * sx;
     }
   }
   // the brick's staged rows: one reservation
@@ -701,6 +683,40 @@ __global__ __launch_bounds__(kBrickThreads) void k_mesh_pass(const Roi* __restri
       }
     }
     __syncthreads();
+  }
+
+  if (moments && L.valid) {
+    // Inside-voxel moments, from the tile (still in LDS; computed here so that
+    // their registers are not held through the enumeration): voxel row
+    // (z, y) = (pz0 + p, L.y + 1), x = 32 l + bit, is the tile word of plane
+    // p + 1, row-group tid + G (the far corner row of plane pair p); rows past
+    // the array read as 0.
+    long long n = 0, sz = 0, szz = 0, sb1 = 0, sb2 = 0, szb = 0;
+#pragma unroll
+    for (int p = 0; p < kTZ; ++p) {
+      if (p + 1 < T.np) {
+        const WordMom wm = word_moments(s_bits[(p + 1) * T.nw + tid + 1 + R.G]);
+        const long long z = T.pz0 + p;
+        n += wm.c;
+        sz += z * wm.c;
+        szz += z * z * wm.c;
+        sb1 += wm.b1;
+        sb2 += wm.b2;
+        szb += z * wm.b1;
+      }
+    }
+    const long long y = L.y + 1, x0 = 32ll * L.l;
+    const long long sx = x0 * n + sb1;
+    mom[0] = n;
+    mom[1] = sz;
+    mom[2] = y * n;
+    mom[3] = sx;
+    mom[4] = szz;
+    mom[5] = y * y * n;
+    mom[6] = x0 * x0 * n + 2 * x0 * sb1 + sb2;
+    mom[7] = y * sz;
+    mom[8] = x0 * sz + szb;
+    mom[9] = y * sx;
   }
 
   // fixed-order block reduction
