@@ -107,6 +107,38 @@ __device__ inline void wave_aggregated_inc_box(unsigned int* counter, int4* bbox
 
 // Bucket-index windows of a brick held in LDS (all three axes together).
 constexpr int kBrickWin = 2048;
+// Row copies of a brick that the scatter orders by destination in LDS.
+constexpr int kScatterList = 3072;
+
+// Exclusive prefix sum of s[0, n) in place (n <= 8 * 256, 8 consecutive
+// slots per thread of a 256-thread workgroup); returns the sum.  s_w: 4 ints.
+// The caller's barrier must precede it; it ends with one.
+__device__ inline int block_scan_slots(int* s, int n, int* s_w) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int b = 8 * tid;
+  int e[8], sum = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    e[j] = sum;
+    sum += b + j < n ? s[b + j] : 0;
+  }
+  int inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) s_w[wid] = inc;
+  __syncthreads();
+  int base = inc - sum;
+  for (int w = 0; w < wid; ++w) base += s_w[w];
+  const int total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (b + j < n) s[b + j] = base + e[j];
+  __syncthreads();
+  return total;
+}
 
 // A brick's vertices: its rows of layout 0 (consecutive, in the mesh pass's
 // order) and its ROI.  False for a brick with no vertex, past the last ROI, or
@@ -143,6 +175,25 @@ __device__ inline void vertex_buckets(unsigned long long k, const int* d, int* b
   }
 }
 
+// Calls f(i, key) for every vertex i of the brick; each thread loads the keys
+// of four of its rows together, so that their latencies overlap.
+template <typename F>
+__device__ inline void for_brick_keys(const unsigned long long* __restrict__ key, const BrickRows& W, F&& f) {
+  for (long long i4 = threadIdx.x; i4 < W.n; i4 += 4ll * blockDim.x) {
+    unsigned long long k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = i4 + (long long)u * blockDim.x;
+      k[u] = i < W.n ? key[W.row0 + i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = i4 + (long long)u * blockDim.x;
+      if (i < W.n) f(i, k[u]);
+    }
+  }
+}
+
 // The brick's window of bucket indices [lo_j, hi_j] per axis (LDS s_lo,
 // s_hi); returns the windows' total width, or a value above kBrickWin when
 // they do not fit the LDS tables.  Contains barriers.
@@ -155,16 +206,16 @@ __device__ inline int brick_windows(const unsigned long long* __restrict__ key, 
   }
   __syncthreads();
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-  for (long long i = tid; i < W.n; i += blockDim.x) {
+  for_brick_keys(key, W, [&](long long, unsigned long long k) {
     int bi[3], kc[3];
-    vertex_buckets(key[W.row0 + i], d, bi, kc);
+    vertex_buckets(k, d, bi, kc);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       if (bi[j] >= 0) {
         lo[j] = min(lo[j], bi[j]);
         hi[j] = max(hi[j], bi[j]);
       }
-  }
+  });
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     lo[j] = wave_min(lo[j]);
@@ -216,9 +267,9 @@ __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned 
       }
     }
     __syncthreads();
-    for (long long i = tid; i < W.n; i += blockDim.x) {
+    for_brick_keys(key, W, [&](long long, unsigned long long k) {
       int bi[3], kc[3];
-      vertex_buckets(key[W.row0 + i], R.d, bi, kc);
+      vertex_buckets(k, R.d, bi, kc);
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         if (bi[j] < 0) continue;
@@ -232,7 +283,7 @@ __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned 
           atomicMax(&s_box[4 * w + 3], cv);
         }
       }
-    }
+    });
     __syncthreads();
     for (int w = tid; w < total; w += blockDim.x) {
       const int c = s_win[w];
@@ -349,8 +400,8 @@ __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long 
 // Copies every vertex's operand row into its three plane buckets (those with
 // at least two vertices after pruning), at rows0 + brow[b] + slot.  One
 // workgroup per brick: the brick counts its vertices per plane in LDS, takes
-// its slots of each plane with one global atomic, and hands them out with LDS
-// atomics.  A brick whose windows exceed kBrickWin planes groups the lanes of
+// its slots of each plane with one global atomic, and orders its copies by
+// destination in LDS (a counting sort) before writing them.  A brick whose windows exceed kBrickWin planes groups the lanes of
 // a wave per bucket and issues one global atomic per group instead.
 __global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsigned long long* __restrict__ key,
                                                        const long long* __restrict__ totals,
@@ -358,8 +409,8 @@ __global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsign
                                                        unsigned int* __restrict__ bcur,
                                                        const long long* __restrict__ brow, float* __restrict__ pos,
                                                        uint4* __restrict__ posh, int* __restrict__ orig) {
-  extern __shared__ int s_win[];  // kBrickWin counts (then ranks), then kBrickWin slot bases
-  __shared__ int s_lo[3], s_hi[3];
+  extern __shared__ int s_win[];  // kBrickWin counts, then kBrickWin offsets, then kScatterList entries
+  __shared__ int s_lo[3], s_hi[3], s_sw[4];
   BrickRows W;
   if (!brick_rows(A, blockIdx.x, W)) return;
   const Roi& R = A.rois[W.roi];
@@ -367,42 +418,67 @@ __global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsign
   const int tid = threadIdx.x, lane = tid & 63;
   int off[3];
   const int total = brick_windows(key, W, R.d, s_lo, s_hi, off);
-  unsigned int* s_base = (unsigned int*)(s_win + kBrickWin);
   if (total <= kBrickWin) {
+    int* s_rel = s_win + kBrickWin;
+    unsigned int* s_list = (unsigned int*)(s_win + 2 * kBrickWin);
     for (int w = tid; w < total; w += blockDim.x) s_win[w] = 0;
     __syncthreads();
-    for (long long i = tid; i < W.n; i += blockDim.x) {
+    for_brick_keys(key, W, [&](long long, unsigned long long k) {
       int bi[3], kc[3];
-      vertex_buckets(key[W.row0 + i], R.d, bi, kc);
+      vertex_buckets(k, R.d, bi, kc);
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         if (bi[j] >= 0) atomicAdd(&s_win[off[j] + bi[j] - s_lo[j]], 1);
-    }
+    });
     __syncthreads();
+    // the brick's slots in each plane bucket (kept ones only): rows brow[b] + base ...
     for (int w = tid; w < total; w += blockDim.x) {
       const int c = s_win[w];
-      unsigned int base = UINT_MAX;
+      int rel = INT_MIN;
       if (c) {
         const int j = w >= off[2] ? 2 : (w >= off[1] ? 1 : 0);
         const long long b = R.bucket_base[j] + s_lo[j] + (w - off[j]);
-        if (bcnt[b] >= 2u) base = atomicAdd(&bcur[b], (unsigned int)c);
+        if (bcnt[b] >= 2u) rel = (int)(brow[b] + (long long)atomicAdd(&bcur[b], (unsigned int)c));
       }
-      s_base[w] = base;
-      s_win[w] = 0;  // from here on: slots handed out
+      s_rel[w] = rel;
+      s_win[w] = rel == INT_MIN ? 0 : c;
     }
     __syncthreads();
-    for (long long i = tid; i < W.n; i += blockDim.x) {
-      const long long row = W.row0 + i;
+    // ... and the brick's copies listed by destination: window w's copies take
+    // list positions [pre_w, pre_w + c_w), and position q goes to row
+    // rows0 + brow[b] + base + (q - pre_w) = rows0 + s_rel[w] + q
+    const int n_copy = block_scan_slots(s_win, total, s_sw);
+    for (int w = tid; w < total; w += blockDim.x)
+      if (s_rel[w] != INT_MIN) s_rel[w] -= s_win[w];
+    __syncthreads();
+    // Listed, the copies are written in destination order, so neighbouring
+    // lanes fill neighbouring rows (whole cache lines) instead of one row of
+    // a different bucket each; a brick with more copies than the list holds
+    // writes them directly.
+    const bool listed = n_copy <= kScatterList && W.n < (1ll << 21);
+    for_brick_keys(key, W, [&](long long i, unsigned long long k) {
       int bi[3], kc[3];
-      vertex_buckets(key[row], R.d, bi, kc);
+      vertex_buckets(k, R.d, bi, kc);
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         if (bi[j] < 0) continue;
         const int w = off[j] + bi[j] - s_lo[j];
-        const unsigned int base = s_base[w];
-        if (base == UINT_MAX) continue;
-        const unsigned int slot = base + (unsigned int)atomicAdd(&s_win[w], 1);
-        const long long dst_row = rows0 + brow[R.bucket_base[j] + bi[j]] + slot;
+        if (s_rel[w] == INT_MIN) continue;
+        const int q = atomicAdd(&s_win[w], 1);
+        if (listed) {
+          s_list[q] = ((unsigned int)w << 21) | (unsigned int)i;
+        } else {
+          const long long row = W.row0 + i, dst_row = rows0 + s_rel[w] + q;
+          copy_row_operands(pos, posh, row, dst_row);
+          orig[dst_row] = (int)row;
+        }
+      }
+    });
+    if (listed) {
+      __syncthreads();
+      for (int q = tid; q < n_copy; q += blockDim.x) {
+        const unsigned int e = s_list[q];
+        const long long row = W.row0 + (e & 0x1fffffu), dst_row = rows0 + s_rel[e >> 21] + q;
         copy_row_operands(pos, posh, row, dst_row);
         orig[dst_row] = (int)row;
       }
@@ -1395,7 +1471,8 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.bsz, B.brow, B.n_buckets, B.totals + T_ROWS2D, B.scan_tmp, st))) return e;
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   if (B.nbricks > 0)
-    hipLaunchKernelGGL(k_brick_scatter, dim3((unsigned)B.nbricks), dim3(256), sizeof(int) * kBrickWin * 2, st, A,
+    hipLaunchKernelGGL(k_brick_scatter, dim3((unsigned)B.nbricks), dim3(256),
+                       sizeof(int) * (2 * kBrickWin + kScatterList), st, A,
                        B.key, B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig);
   hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
