@@ -19,10 +19,12 @@
 //      its rows with one atomic;
 //   2. k_soft_vertex_grad: one thread per crossing edge (the surface is sparse,
 //      so a thread per voxel would leave most lanes idle around the FP64 work)
-//      computes (dL/dx_v)_a * s_a into the edge's field slot;
-//   3. k_soft_gather: one wave per voxel row sums, for each voxel, the terms of
-//      its (at most six) incident crossing edges, read directly from their
-//      field slots, and writes dL/dp densely (0 away from the surface).
+//      computes (dL/dx_v)_a * s_a / (p_b - p_u)^2 into the edge's field slot;
+//   3. k_soft_gather: for each voxel, the terms of its (at most six) incident
+//      crossing edges, the field value times (0.5 - p_b) or -(0.5 - p_u), read
+//      directly from their field slots, summed, and dL/dp written densely (0
+//      away from the surface).  The division by (p_b - p_u)^2 is thus done once
+//      per crossing edge, not once per end point over whole waves.
 // Only slots of crossing edges are written and read, so the field is never
 // cleared.  No float atomics: the result does not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -297,7 +299,10 @@ __global__ __launch_bounds__(256, 3) void k_soft_vertex_grad(SoftBwdBufs B) {
       // dD/dx_v = (x_v - x_other) / D for either end point
       for (int c = 0; c < 3; ++c) gx[c] += gd * (xv[c] - xo[c]);
     }
-    B.field[slot] = (float)(gx[a] * R->s[a]);
+    const double pu = pval(R->p, R->d, u0, u1, u2);
+    const double pb = pval(R->p, R->d, u0 + (a == 0), u1 + (a == 1), u2 + (a == 2));
+    const double den = pb - pu;  // at least one float ulp at 0.5: a crossing edge straddles it
+    B.field[slot] = (float)(gx[a] * R->s[a] / (den * den));
   }
 }
 
@@ -329,9 +334,8 @@ __device__ inline double voxel_grad(const float* __restrict__ field, long long s
     for (int j = 0; j < 6; ++j) {
       if (!cross[j]) continue;
       const bool up = j & 1;  // the neighbour is w + e_a (w is the edge's lower end)
-      const double pu = up ? (double)vc : (double)nv[j], pb = up ? (double)nv[j] : (double)vc;
-      const double den = pb - pu;
-      g += (double)q[j] * (up ? (0.5 - pb) / (den * den) : -(0.5 - pu) / (den * den));
+      // the field holds (dL/dx_v)_a s_a / (p_b - p_u)^2; times dt/dp_w (p_b - p_u)^2
+      g += (double)q[j] * (up ? 0.5 - (double)nv[j] : -(0.5 - (double)nv[j]));
     }
   }
   return g;
