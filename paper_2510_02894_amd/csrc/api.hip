@@ -514,6 +514,13 @@ PairBufs pair_bufs(const Ptrs& P, const Batch& Bt, int dtype, const Sizes& S, in
   B.part = P.as<const BrickPart>(W_PART);
   B.brick_voff = P.as<const long long>(W_BRICK_VOFF);
   B.bmap = Bt.n() > 1 ? P.as<const int>(W_BRICK_ROI) : nullptr;
+  {
+    // plane keys a brick can touch: 2 tz + 3 along axis 0, at most 2 (256 + 2) + 1
+    // along axis 1 (256 row-groups of at least one group per row) and
+    // 2 (d2 + 1) + 1 along axis 2; smaller windows keep more workgroups per CU
+    const long long w = (2ll * kTZ + 3) + (2ll * (kBrickThreads + 2) + 1) + (2ll * (Bt.max_d[2] + 1) + 1);
+    B.brick_win = (int)std::min<long long>(2048, (w + 255) / 256 * 256);
+  }
   B.meta = P.as<const RoiMeta>(W_META);
   B.key = P.as<const unsigned long long>(W_KEY);
   B.tsoft = dtype == SHAPE3D_F32 ? P.as<const double>(W_TSOFT) : nullptr;

@@ -105,8 +105,6 @@ __device__ inline void wave_aggregated_inc_box(unsigned int* counter, int4* bbox
   __builtin_amdgcn_wave_barrier();
 }
 
-// Bucket-index windows of a brick held in LDS (all three axes together).
-constexpr int kBrickWin = 2048;
 // Row copies of a brick that the scatter orders by destination in LDS.
 constexpr int kScatterList = 3072;
 
@@ -195,8 +193,8 @@ __device__ inline void for_brick_keys(const unsigned long long* __restrict__ key
 }
 
 // The brick's window of bucket indices [lo_j, hi_j] per axis (LDS s_lo,
-// s_hi); returns the windows' total width, or a value above kBrickWin when
-// they do not fit the LDS tables.  Contains barriers.
+// s_hi); returns the windows' total width (the caller compares it with the
+// size of its LDS tables).  Contains barriers.
 __device__ inline int brick_windows(const unsigned long long* __restrict__ key, const BrickRows& W, const int* d,
                                     int* s_lo, int* s_hi, int* off) {
   const int tid = threadIdx.x;
@@ -242,11 +240,11 @@ __device__ inline int brick_windows(const unsigned long long* __restrict__ key, 
 // One workgroup per brick: a brick's vertices lie on few planes of each axis,
 // so they are counted per plane in LDS windows and each plane the brick
 // touches costs one global atomic (plus the box's, where it grows).  A brick
-// whose windows exceed kBrickWin planes uses wave-aggregated global atomics
+// whose windows exceed `win` planes uses wave-aggregated global atomics
 // per vertex instead.
 __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned long long* __restrict__ key,
-                                                    unsigned int* __restrict__ bcnt, int4* __restrict__ bbox) {
-  extern __shared__ int s_win[];  // kBrickWin counts, then with bbox kBrickWin boxes
+                                                    unsigned int* __restrict__ bcnt, int4* __restrict__ bbox, int win) {
+  extern __shared__ int s_win[];  // win counts, then with bbox win boxes
   __shared__ int s_lo[3], s_hi[3];
   __shared__ int s_slot[4][64 * 4];
   BrickRows W;
@@ -255,8 +253,8 @@ __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned 
   const int tid = threadIdx.x;
   int off[3];
   const int total = brick_windows(key, W, R.d, s_lo, s_hi, off);
-  int* s_box = s_win + kBrickWin;
-  if (total <= kBrickWin) {
+  int* s_box = s_win + win;
+  if (total <= win) {
     for (int w = tid; w < total; w += blockDim.x) {
       s_win[w] = 0;
       if (bbox) {
@@ -276,11 +274,15 @@ __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned 
         const int w = off[j] + bi[j] - s_lo[j];
         atomicAdd(&s_win[w], 1);
         if (bbox) {
+          // the box only grows: an atomic that a (possibly stale) read shows
+          // cannot change it is skipped, which spares most vertices the
+          // same-address LDS atomics of a wave's lanes
           const int cu = kc[j == 0 ? 1 : 0], cv = kc[j == 2 ? 1 : 2];
-          atomicMin(&s_box[4 * w], cu);
-          atomicMax(&s_box[4 * w + 1], cu);
-          atomicMin(&s_box[4 * w + 2], cv);
-          atomicMax(&s_box[4 * w + 3], cv);
+          int* q = s_box + 4 * w;
+          if (cu < q[0]) atomicMin(&q[0], cu);
+          if (cu > q[1]) atomicMax(&q[1], cu);
+          if (cv < q[2]) atomicMin(&q[2], cv);
+          if (cv > q[3]) atomicMax(&q[3], cv);
         }
       }
     });
@@ -292,16 +294,14 @@ __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned 
       const long long b = R.bucket_base[j] + s_lo[j] + (w - off[j]);
       atomicAdd(&bcnt[b], (unsigned int)c);
       if (bbox) {
-        // the box only grows: a bound that a (possibly stale) read already
-        // covers needs no atomic
+        // no read of the global box first: the atomics' results are not
+        // waited for, so the workgroup ends without a round trip
         int* g = (int*)&bbox[b];
         const int* q = s_box + 4 * w;
-        int cur[4];
-        for (int e = 0; e < 4; ++e) cur[e] = __hip_atomic_load(&g[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (q[0] < cur[0]) atomicMin(&g[0], q[0]);
-        if (q[1] > cur[1]) atomicMax(&g[1], q[1]);
-        if (q[2] < cur[2]) atomicMin(&g[2], q[2]);
-        if (q[3] > cur[3]) atomicMax(&g[3], q[3]);
+        atomicMin(&g[0], q[0]);
+        atomicMax(&g[1], q[1]);
+        atomicMin(&g[2], q[2]);
+        atomicMax(&g[3], q[3]);
       }
     }
   } else {
@@ -401,15 +401,16 @@ __global__ void k_bucket_sizes(const unsigned int* __restrict__ bcnt, long long 
 // at least two vertices after pruning), at rows0 + brow[b] + slot.  One
 // workgroup per brick: the brick counts its vertices per plane in LDS, takes
 // its slots of each plane with one global atomic, and orders its copies by
-// destination in LDS (a counting sort) before writing them.  A brick whose windows exceed kBrickWin planes groups the lanes of
+// destination in LDS (a counting sort) before writing them.  A brick whose
+// windows exceed `win` planes groups the lanes of
 // a wave per bucket and issues one global atomic per group instead.
 __global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsigned long long* __restrict__ key,
                                                        const long long* __restrict__ totals,
                                                        const unsigned int* __restrict__ bcnt,
                                                        unsigned int* __restrict__ bcur,
                                                        const long long* __restrict__ brow, float* __restrict__ pos,
-                                                       uint4* __restrict__ posh, int* __restrict__ orig) {
-  extern __shared__ int s_win[];  // kBrickWin counts, then kBrickWin offsets, then kScatterList entries
+                                                       uint4* __restrict__ posh, int* __restrict__ orig, int win) {
+  extern __shared__ int s_win[];  // win counts, then win offsets, then kScatterList entries
   __shared__ int s_lo[3], s_hi[3], s_sw[4];
   BrickRows W;
   if (!brick_rows(A, blockIdx.x, W)) return;
@@ -418,9 +419,9 @@ __global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsign
   const int tid = threadIdx.x, lane = tid & 63;
   int off[3];
   const int total = brick_windows(key, W, R.d, s_lo, s_hi, off);
-  if (total <= kBrickWin) {
-    int* s_rel = s_win + kBrickWin;
-    unsigned int* s_list = (unsigned int*)(s_win + 2 * kBrickWin);
+  if (total <= win) {
+    int* s_rel = s_win + win;
+    unsigned int* s_list = (unsigned int*)(s_win + 2 * win);
     for (int w = tid; w < total; w += blockDim.x) s_win[w] = 0;
     __syncthreads();
     for_brick_keys(key, W, [&](long long, unsigned long long k) {
@@ -1461,8 +1462,8 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
                      st, B.bcnt, B.bcur, B.n_buckets, B.pairs2d, (long long)B.n_rois, bbox);
   const BrickArgs A = brick_args(B);
   if (B.nbricks > 0)
-    hipLaunchKernelGGL(k_brick_hist, dim3((unsigned)B.nbricks), dim3(256), sizeof(int) * kBrickWin * (bbox ? 5 : 1),
-                       st, A, B.key, B.bcnt, bbox);
+    hipLaunchKernelGGL(k_brick_hist, dim3((unsigned)B.nbricks), dim3(256), sizeof(int) * B.brick_win * (bbox ? 5 : 1),
+                       st, A, B.key, B.bcnt, bbox, B.brick_win);
   if (bbox)
     hipLaunchKernelGGL(k_bucket_prune, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.tsoft ? 1 : 0, B.bcnt,
                        bbox, B.pairs2d);
@@ -1472,8 +1473,8 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   if ((e = launch_scan(B.bflag, B.bseg, B.n_buckets, B.totals + T_NSEG2D, B.scan_tmp, st))) return e;
   if (B.nbricks > 0)
     hipLaunchKernelGGL(k_brick_scatter, dim3((unsigned)B.nbricks), dim3(256),
-                       sizeof(int) * (2 * kBrickWin + kScatterList), st, A,
-                       B.key, B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig);
+                       sizeof(int) * (2 * B.brick_win + kScatterList), st, A,
+                       B.key, B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig, B.brick_win);
   hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup);
   hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
                      B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,

@@ -136,6 +136,7 @@ struct PairBufs {
   const BrickPart* part;        // [nbricks]
   const long long* brick_voff;  // [nbricks]
   const int* bmap;              // [nbricks] or null
+  int brick_win;                // LDS plane-key windows of the per-brick bucket kernels (at most 2,048)
   const RoiMeta* meta;
   const unsigned long long* key;
   const double* tsoft;  // null for binary masks
