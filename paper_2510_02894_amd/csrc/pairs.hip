@@ -533,16 +533,31 @@ __global__ __launch_bounds__(256) void k_brick_scatter(BrickArgs A, const unsign
   }
 }
 
-// The group (roi * 4 + 1 + axis) of every plane bucket: one workgroup per ROI
-// over its contiguous bucket range (so the segment pass needs no search of
-// the ROI table).
-__global__ void k_bucket_groups(const Roi* __restrict__ rois, int* __restrict__ bgroup) {
+// The group (roi * 4 + 1 + axis) of every plane bucket, and the ROI's
+// in-plane pair count n (n - 1) / 2 summed over its kept buckets (one atomic
+// per ROI: the pruning pass adds the dropped buckets' pairs): one workgroup
+// per ROI over its contiguous bucket range (so the segment pass needs no
+// search of the ROI table).
+__global__ __launch_bounds__(256) void k_bucket_groups(const Roi* __restrict__ rois, int* __restrict__ bgroup,
+                                                       const unsigned int* __restrict__ bcnt,
+                                                       long long* __restrict__ pairs2d) {
+  __shared__ long long s_sum[4];
   const Roi& R = rois[blockIdx.x];
   const long long b0 = R.bucket_base[0];
   const long long b1 = R.bucket_base[2] + 2ll * R.d[2] + 1;
+  long long pairs = 0;
   for (long long b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
     const int axis = b >= R.bucket_base[2] ? 2 : (b >= R.bucket_base[1] ? 1 : 0);
     bgroup[b] = (int)blockIdx.x * 4 + 1 + axis;
+    const long long c = bcnt[b];
+    if (c >= 2) pairs += c * (c - 1) / 2;
+  }
+  pairs = wave_sum(pairs);
+  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = pairs;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long t = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+    if (t) atomicAdd((unsigned long long*)&pairs2d[blockIdx.x], (unsigned long long)t);
   }
 }
 
@@ -552,8 +567,7 @@ __global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long l
                               const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                               const long long* __restrict__ brow, const long long* __restrict__ bseg,
                               float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
-                              int* __restrict__ blkseg, Seg* __restrict__ segs,
-                              long long* __restrict__ pairs2d) {
+                              int* __restrict__ blkseg, Seg* __restrict__ segs) {
   // one wave per bucket: its lanes tag the blocks and fill the pad rows
   const long long rows0 = totals[T_ROWS0];
   const int lane = threadIdx.x & 63;
@@ -566,7 +580,6 @@ __global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long l
     const long long n = bsz[b];
     if (lane == 0) {
       const int group = bgroup[b];
-      atomicAdd((unsigned long long*)&pairs2d[group >> 2], (unsigned long long)c * (c - 1) / 2);
       Seg S;
       S.row_begin = r0;
       S.n_rows = (int)n;
@@ -1021,18 +1034,27 @@ __global__ __launch_bounds__(256) void k_pair_small_h(const uint4* __restrict__ 
 __global__ void k_group_max(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
                             const Seg* __restrict__ segs, const long long* __restrict__ totals,
                             GroupRes* __restrict__ gres) {
+  // A wave takes a contiguous range of 16-row blocks, 64 at a time, and keeps
+  // the maximum of the group it last met: a group (a ROI's 3D rows, or one
+  // axis's plane buckets) covers long runs of blocks, so it costs one atomic
+  // per wave that meets it, instead of one per wave and 64 blocks (the
+  // atomics of a group serialise on its one address).
   const long long nblk = (totals[T_ROWS0] + totals[T_ROWS2D]) / kBlk;
   const int lane = threadIdx.x & 63;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long base = wave * 64; base < nblk; base += nwaves * 64) {
+  const long long per = (nblk + nwaves - 1) / nwaves;
+  const long long b0 = wave * per, b1 = min(b0 + per, nblk);
+  int cg = -1;  // the group whose maximum cm the wave holds (uniform over the wave)
+  float cm = 0.0f;
+  for (long long base = b0; base < b1; base += 64) {
     const long long blk = base + lane;
     int g = -1;
     float m = 0.0f;
-    if (blk < nblk) {
-      const int s = blkseg[blk];
-      if (s >= 0) {
-        g = segs[s].group;
+    if (blk < b1) {
+      const int sg = blkseg[blk];
+      if (sg >= 0) {
+        g = segs[sg].group;
         const float4* p = (const float4*)(rowmax + blk * kBlk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -1048,10 +1070,17 @@ __global__ void k_group_max(const float* __restrict__ rowmax, const int* __restr
       const unsigned long long same = __ballot(g == gl) & todo;
       float v = g == gl ? m : 0.0f;
       for (int k = 32; k >= 1; k >>= 1) v = fmaxf(v, __shfl_xor(v, k, 64));
-      if (lane == leader) atomicMax((int*)&gres[gl].gmax, __float_as_int(v));
+      if (gl == cg) {
+        cm = fmaxf(cm, v);
+      } else {
+        if (cg >= 0 && lane == 0) atomicMax((int*)&gres[cg].gmax, __float_as_int(cm));
+        cg = gl;
+        cm = v;
+      }
       todo &= ~same;
     }
   }
+  if (cg >= 0 && lane == 0) atomicMax((int*)&gres[cg].gmax, __float_as_int(cm));
 }
 
 __global__ void k_candidates(const float* __restrict__ rowmax, const int* __restrict__ blkseg,
@@ -1475,10 +1504,10 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
     hipLaunchKernelGGL(k_brick_scatter, dim3((unsigned)B.nbricks), dim3(256),
                        sizeof(int) * (2 * B.brick_win + kScatterList), st, A,
                        B.key, B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig, B.brick_win);
-  hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup);
-  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
-                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs,
+  hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup, B.bcnt,
                      B.pairs2d);
+  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
+                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs);
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(std::max(B.seg_cap, B.col_cap))), dim3(256), 0, st, B.n_rois,
                      B.seg_cap, B.totals, B.segs, B.meta, B.ncol, B.tune.jchunk,
                      small_buckets(B) ? kSmallBlocks * 32 : 0, B.nitem, B.col_cap, B.prune ? 1 : 0, B.prune_min_v,
@@ -1562,7 +1591,8 @@ hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
 
 hipError_t launch_refine(const PairBufs& B, hipStream_t st) {
   hipError_t e;
-  hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound / kBlk, 1024)), dim3(256), 0, st, B.rowmax, B.blkseg,
+  // about 8 chunks of 64 blocks per wave (a few waves per group on one large ROI)
+  hipLaunchKernelGGL(k_group_max, dim3(grid_for(B.rows_bound / kBlk / 8, 1024)), dim3(256), 0, st, B.rowmax, B.blkseg,
                      B.segs, B.totals, B.gres);
   hipLaunchKernelGGL(k_candidates, dim3(grid_for(B.rows_bound / kBlk)), dim3(256), 0, st, B.rowmax, B.blkseg, B.segs,
                      B.meta, B.totals, B.gres, B.counters + 1, B.cand, B.cand_cap,
