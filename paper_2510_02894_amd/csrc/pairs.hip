@@ -1481,11 +1481,12 @@ static BrickArgs brick_args(const PairBufs& B) {
 
 hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
   hipError_t e;
-  // Whole plane buckets are pruned with the pair tiles: their boxes cost the
-  // per-brick histogram LDS work and larger windows, which the pruned
-  // scatter, segments and pair work repay (4,096 ROIs: 15.4 -> 14.0 ms; one
-  // 300 x 512 x 512 ROI: 0.692 -> 0.680 ms).
-  int4* bbox = B.prune ? B.bbox : nullptr;
+  // Whole plane buckets are pruned with the pair tiles in calls with many
+  // buckets: their boxes cost the histogram pass four more atomics per group
+  // of lanes, which the pruned scatter and pair work repay on a batch of
+  // small ROIs (4,096 ROIs: 19.3 -> 19.0 ms) but not on one large ROI
+  // (2,651 buckets: 0.83 -> 0.95 ms).
+  int4* bbox = B.prune && B.n_buckets >= kSmallMinBuckets ? B.bbox : nullptr;
   hipLaunchKernelGGL(k_zero_buckets, dim3(grid_for(std::max<long long>(B.n_buckets, B.n_rois), 4096)), dim3(256), 0,
                      st, B.bcnt, B.bcur, B.n_buckets, B.pairs2d, (long long)B.n_rois, bbox);
   const BrickArgs A = brick_args(B);
