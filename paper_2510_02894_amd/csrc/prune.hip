@@ -429,40 +429,73 @@ __global__ __launch_bounds__(256) void k_prune_items(const BlkRec* __restrict__ 
         pass = box_far2(rec[rb + ci * kPruneSB].cbox, rec[rb + cj * kPruneSB].cbox) >= thr_r;
       }
     }
+    // Surviving column pairs, two at a time: the box loads of both are issued
+    // before either is tested (one memory round trip per two pairs).
     unsigned long long todo = __ballot(pass);
     while (todo) {
-      const int srcl = __ffsll((long long)todo) - 1;
-      todo &= todo - 1ull;
-      const int rr = __shfl(r, srcl, 64), i = __shfl(ci, srcl, 64), j = __shfl(cj, srcl, 64);
-      const float thr = __shfl(thr_r, srcl, 64);
-      const RoiMeta& M = meta[rr];
-      const int nb = (int)(M.V_pad / 32);
-      const long long rb = M.row_off / 32;
-      const int t = lane / LPT, g = lane % LPT;
-      const int i0 = i * kPruneSB + t * IT;     // the tile's first block
-      const int jb0 = j * kPruneSB + g * BPL;   // this lane's first block of column j
-      unsigned int bits = 0u;                   // surviving blocks of column j (bit = block - j * kPruneSB)
-      if (i0 < nb) {
-        float tb[6];
+      int srcl[2];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) tb[c] = rec[rb + i0].tbox[c];
+      for (int u = 0; u < 2; ++u) {
+        srcl[u] = todo ? __ffsll((long long)todo) - 1 : -1;
+        if (todo) todo &= todo - 1ull;
+      }
+      const int t = lane / LPT, g = lane % LPT;
+      float tb[2][6], jbx[2][BPL][6];
+      int nb[2], rb[2], i0[2], j[2];
+      float thr[2];
+      double r2[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        nb[u] = 0;
+        rb[u] = 0;
+        i0[u] = 0;
+        j[u] = 0;
+        thr[u] = 0.0f;
+        r2[u] = 0.0;
+        if (srcl[u] < 0) continue;  // uniform over the wave
+        const int rr = __shfl(r, srcl[u], 64), i = __shfl(ci, srcl[u], 64);
+        j[u] = __shfl(cj, srcl[u], 64);
+        thr[u] = __shfl(thr_r, srcl[u], 64);
+        const RoiMeta& M = meta[rr];
+        nb[u] = (int)(M.V_pad / 32);
+        rb[u] = (int)(M.row_off / 32);
+        r2[u] = M.R2;
+        i0[u] = i * kPruneSB + t * IT;  // the tile's first block
+        const int jb0 = j[u] * kPruneSB + g * BPL;  // this lane's first block of column j
+        const int ic = min(i0[u], nb[u] - 1);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tb[u][c] = rec[rb[u] + ic].tbox[c];
 #pragma unroll
         for (int q = 0; q < BPL; ++q) {
-          const int jj = jb0 + q;
-          if (jj < nb && jj >= i0 && box_far2(tb, rec[rb + jj].box) >= thr) bits |= 1u << (g * BPL + q);
+          const int jj = min(jb0 + q, nb[u] - 1);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) jbx[u][q][c] = rec[rb[u] + jj].box[c];
         }
       }
 #pragma unroll
-      for (int m = 1; m < LPT; m <<= 1) bits |= __shfl_xor(bits, m, 64);
-      PItem P;
-      P.rb = (int)rb;
-      P.nb = nb;
-      P.i0 = i0;
-      P.j0 = j * kPruneSB + (bits ? __ffs(bits) - 1 : 0);
-      P.j1 = j * kPruneSB + (32 - __clz(bits));
-      P.e = h_scale_exp(M.R2);
-      P.pad_[0] = P.pad_[1] = 0;
-      stage.push(g == 0 && bits != 0u, P, lane, items, cap, counters);
+      for (int u = 0; u < 2; ++u) {
+        if (srcl[u] < 0) continue;
+        const int jb0 = j[u] * kPruneSB + g * BPL;
+        unsigned int bits = 0u;  // surviving blocks of column j (bit = block - j * kPruneSB)
+        if (i0[u] < nb[u]) {
+#pragma unroll
+          for (int q = 0; q < BPL; ++q) {
+            const int jj = jb0 + q;
+            if (jj < nb[u] && jj >= i0[u] && box_far2(tb[u], jbx[u][q]) >= thr[u]) bits |= 1u << (g * BPL + q);
+          }
+        }
+#pragma unroll
+        for (int m = 1; m < LPT; m <<= 1) bits |= __shfl_xor(bits, m, 64);
+        PItem P;
+        P.rb = rb[u];
+        P.nb = nb[u];
+        P.i0 = i0[u];
+        P.j0 = j[u] * kPruneSB + (bits ? __ffs(bits) - 1 : 0);
+        P.j1 = j[u] * kPruneSB + (32 - __clz(bits));
+        P.e = h_scale_exp(r2[u]);
+        P.pad_[0] = P.pad_[1] = 0;
+        stage.push(g == 0 && bits != 0u, P, lane, items, cap, counters);
+      }
     }
   }
   stage.flush(lane, items, cap, counters);
