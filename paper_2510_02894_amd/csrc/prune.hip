@@ -191,18 +191,42 @@ __global__ __launch_bounds__(256) void k_prune_box(const float* __restrict__ pos
 }
 
 // Passes 2, 4, 6: the maxima of the blocks' keys per ROI into seed slot
-// `slot`.  A wave takes 512 consecutive blocks (8 per lane); each lane keeps
-// the maxima of its blocks per ROI (a pruned ROI has at least 512 blocks
-// unless pruning is forced, so a lane meets at most two), and the lanes that
-// end on the same ROI combine theirs before one atomic per key.  With BOXES
-// (pass 2) the lanes also write the box of every row tile (it_blocks blocks)
-// and every column (kPruneSB blocks) that starts among their blocks.
-constexpr int kRedPerLane = 8;
+// `slot`.  A wave walks a contiguous range of blocks, 64 kRedPerLane at a time
+// (kRedPerLane per lane, their loads issued together); each lane keeps the
+// maxima of its blocks per ROI, and the lanes that end on the same ROI combine
+// theirs into the wave's maxima of its last ROI.  With BOXES (pass 2) the lanes
+// also write the box of every row tile (it_blocks blocks) and every column
+// (kPruneSB blocks) that starts among their blocks.
+constexpr int kRedPerLane = 4;
 
 __device__ inline void seed_max(RoiSeed* seed, int roi, int slot, const unsigned long long* k) {
 #pragma unroll
   for (int c = 0; c < 7; ++c)
     if (k[c]) atomicMax(&seed[roi].key[slot][c], k[c]);
+}
+
+// Box of blocks [b, b + n) of a ROI's rows (n <= kPruneSB), eight blocks'
+// loads in flight at a time.
+__device__ inline void blocks_box(const BlkRec* __restrict__ rec, long long b, int n, float* bx) {
+  for (int u0 = 0; u0 < n; u0 += 8) {
+    float lo[8][3], hi[8][3];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const long long bb = b + min(u0 + u, n - 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lo[u][c] = rec[bb].box[c];
+        hi[u][c] = rec[bb].box[3 + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        bx[c] = fminf(bx[c], lo[u][c]);
+        bx[3 + c] = fmaxf(bx[3 + c], hi[u][c]);
+      }
+  }
 }
 
 template <bool BOXES>
@@ -213,15 +237,34 @@ __global__ __launch_bounds__(256) void k_prune_reduce(BlkRec* __restrict__ rec, 
   const long long nblk = totals[T_ROWS0] / 32;
   const int lane = threadIdx.x & 63;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kRedPerLane);
-       base < nblk; base += nwaves * 64 * kRedPerLane) {
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // a contiguous range of blocks per wave, so that its iterations mostly meet
+  // the same ROI: the wave keeps the maxima of the last ROI it met (wroi,
+  // wk) and issues atomics only when the ROI changes
+  constexpr long long kStep = 64 * kRedPerLane;
+  const long long per = (nblk + nwaves - 1) / nwaves;
+  const long long w0 = wave * ((per + kStep - 1) / kStep * kStep);
+  const long long w1 = min(w0 + (per + kStep - 1) / kStep * kStep, nblk);
+  int wroi = -1;
+  unsigned long long wk[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+  for (long long base = w0; base < w1; base += kStep) {
     const long long b0 = base + (long long)lane * kRedPerLane;
+    int roiq[kRedPerLane];
+    unsigned long long kq[kRedPerLane][7];
+#pragma unroll
+    for (int q = 0; q < kRedPerLane; ++q) {
+      const long long blk = min(b0 + q, nblk - 1);
+      roiq[q] = blkseg[2 * blk];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) kq[q][c] = rec[blk].key[c];
+    }
     int cur = -1;
     unsigned long long k[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+#pragma unroll
     for (int q = 0; q < kRedPerLane; ++q) {
       const long long blk = b0 + q;
-      if (blk >= nblk) break;
-      const int roi = blkseg[2 * blk];
+      if (blk >= w1) break;
+      const int roi = roiq[q];
       const RoiMeta& M = meta[roi];
       if (!pruned_roi(M, min_v)) continue;
       if (roi != cur) {
@@ -231,38 +274,25 @@ __global__ __launch_bounds__(256) void k_prune_reduce(BlkRec* __restrict__ rec, 
         for (int c = 0; c < 7; ++c) k[c] = 0ull;
       }
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        const unsigned long long v = rec[blk].key[c];
-        k[c] = v > k[c] ? v : k[c];
-      }
+      for (int c = 0; c < 7; ++c) k[c] = kq[q][c] > k[c] ? kq[q][c] : k[c];
       if (BOXES) {
         const long long rb = M.row_off / 32;
         const int nb = (int)(M.V_pad / 32), rel = (int)(blk - rb);
         if (rel % it_blocks == 0 || rel % kPruneSB == 0) {
-          const int n = rel % kPruneSB == 0 ? kPruneSB : it_blocks;
           float tb[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
-          float cb[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
-          for (int u = 0; u < n && rel + u < nb; ++u) {
-            float* bx = u < it_blocks ? tb : cb;
-            for (int c = 0; c < 3; ++c) {
-              const float lo = rec[blk + u].box[c], hi = rec[blk + u].box[3 + c];
-              bx[c] = fminf(bx[c], lo);
-              bx[3 + c] = fmaxf(bx[3 + c], hi);
-            }
-          }
-          // the column box also covers the tile's blocks
-          for (int c = 0; c < 3; ++c) {
-            cb[c] = fminf(cb[c], tb[c]);
-            cb[3 + c] = fmaxf(cb[3 + c], tb[3 + c]);
-          }
+          blocks_box(rec, blk, min(it_blocks, nb - rel), tb);
           if (rel % it_blocks == 0)
             for (int c = 0; c < 6; ++c) rec[blk].tbox[c] = tb[c];
-          if (rel % kPruneSB == 0)
+          if (rel % kPruneSB == 0) {
+            // the column box also covers the tile's blocks
+            float cb[6] = {tb[0], tb[1], tb[2], tb[3], tb[4], tb[5]};
+            if (nb - rel > it_blocks) blocks_box(rec, blk + it_blocks, min(kPruneSB, nb - rel) - it_blocks, cb);
             for (int c = 0; c < 6; ++c) rec[blk].cbox[c] = cb[c];
+          }
         }
       }
     }
-    // lanes ending on the same ROI combine their maxima (one atomic per key)
+    // lanes ending on the same ROI combine their maxima into the wave's
     unsigned long long todo = __ballot(cur >= 0);
     while (todo) {
       const int leader = __ffsll((long long)todo) - 1;
@@ -278,8 +308,41 @@ __global__ __launch_bounds__(256) void k_prune_reduce(BlkRec* __restrict__ rec, 
           v[c] = o > v[c] ? o : v[c];
         }
       }
-      if (lane == leader) seed_max(seed, gl, slot, v);
+      if (gl != wroi) {
+        if (wroi >= 0 && lane == 0) seed_max(seed, wroi, slot, wk);
+        wroi = gl;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) wk[c] = 0ull;
+      }
+#pragma unroll
+      for (int c = 0; c < 7; ++c) wk[c] = v[c] > wk[c] ? v[c] : wk[c];
       todo &= ~same;
+    }
+  }
+  // the waves' last ROIs: one atomic per key and ROI for the workgroup
+  __shared__ int s_roi[4];
+  __shared__ unsigned long long s_key[4][7];
+  const int wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_roi[wid] = wroi;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) s_key[wid][c] = wk[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < 4; ++w) {
+      const int r = s_roi[w];
+      if (r < 0) continue;
+      unsigned long long v[7];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) v[c] = s_key[w][c];
+      for (int w2 = w + 1; w2 < 4; ++w2) {
+        if (s_roi[w2] != r) continue;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = s_key[w2][c] > v[c] ? s_key[w2][c] : v[c];
+        s_roi[w2] = -1;
+      }
+      seed_max(seed, r, slot, v);
     }
   }
 }
