@@ -459,8 +459,10 @@ __global__ __launch_bounds__(256) void k_small_head(Roi R, Roi* __restrict__ roi
 // Binary masks: at most 80 VGPRs, so that six bricks share a CU and the
 // 1,330 bricks of a 300 x 512 x 512 volume run in one round on 256 CUs (a few
 // registers spill; measured faster than 96 VGPRs and five bricks per CU).
+// Soft masks: at most 128 VGPRs (four bricks per CU instead of three; a few
+// registers spill, measured slightly faster).
 template <int DT>
-__global__ __launch_bounds__(kBrickThreads, DT == 0 ? 6 : 1) void k_mesh_pass(const Roi* __restrict__ rois, int n_rois,
+__global__ __launch_bounds__(kBrickThreads, DT == 0 ? 6 : 4) void k_mesh_pass(const Roi* __restrict__ rois, int n_rois,
                                                              long long nbricks, double* __restrict__ case_area,
                                                              BrickPart* __restrict__ part,
                                                              unsigned long long* __restrict__ tmpkey,
@@ -633,7 +635,10 @@ __global__ __launch_bounds__(kBrickThreads, DT == 0 ? 6 : 1) void k_mesh_pass(co
             const int e = MC_TRI[cas][tr][v];
             const int ax = MC_EDGE_AXIS[e], k0 = MC_EDGE_C0[e];
             const int k1 = k0 | (4 >> ax);
-            const double tt = (0.5 - sel8d(pc, k0)) / (sel8d(pc, k1) - sel8d(pc, k0));
+            // the area and volume terms only (the vertex rows take the edge
+            // pass's correctly rounded quotient): a reciprocal estimate refined
+            // by Newton steps is within a unit in the last place
+            const double tt = (0.5 - sel8d(pc, k0)) * rcp64(sel8d(pc, k1) - sel8d(pc, k0));
             const int u0 = z + ((k0 >> 2) & 1), u1 = y + ((k0 >> 1) & 1), u2 = x + (k0 & 1);
             P[v][0] = ((double)u0 + (ax == 0 ? tt : 0.0)) * R.s[0] - o0;
             P[v][1] = ((double)u1 + (ax == 1 ? tt : 0.0)) * R.s[1] - o1;

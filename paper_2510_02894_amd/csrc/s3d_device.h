@@ -74,6 +74,17 @@ __device__ inline int block_excl_scan256(int v, int* sh, int& total) {
   return base + inc - v;
 }
 
+// 1 / x in FP64 from the hardware reciprocal estimate and two Newton steps
+// (each squares the relative error, which ends far below a unit in the last
+// place of a double for the estimate's accuracy; the result may differ from the
+// correctly rounded quotient in its last bit); x != 0.
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Exact FP64 squared distance in a fixed operation order (no contraction).
 __device__ inline double dist2_exact(const double* p, const double* q) {
   double dx = __dsub_rn(p[0], q[0]), dy = __dsub_rn(p[1], q[1]), dz = __dsub_rn(p[2], q[2]);

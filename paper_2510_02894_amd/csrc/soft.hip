@@ -79,16 +79,6 @@ __device__ inline double sel8(const double* v, int k) {
   return (k & 4) ? ce : ab;
 }
 
-// 1 / x in FP64 from the hardware reciprocal estimate and two Newton steps
-// (each squares the relative error, which ends far below a unit in the last
-// place of a double for the estimate's accuracy); x != 0.
-__device__ inline double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-
 // Position (relative to o) of the vertex on cube edge e of the cube with min
 // corner (c0, c1, c2) and corner values pc.  Edge e = 4 axis + 2 o_b + o_c runs
 // from corner k0 (bits dz dy dx) along its axis.
