@@ -1077,10 +1077,25 @@ __global__ __launch_bounds__(256) void k_mesh_rows(const Roi* __restrict__ rois,
     return;
   }
   const long long dst = M.row_off + first;
-  for (long long i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const long long row = dst + i;
-    put_row(R, M, row, tmpkey[src + i], tsoft ? tmpt[src + i] : 0.5, key, tsoft, pos, posh, orig, row);
-    if ((row & 15) == 0 || i == 0) blkseg[row >> 4] = r;  // a block shared with a neighbour gets the same tag
+  // four rows per thread at a time, their staged keys loaded together (a load
+  // after a row's stores would wait for them)
+  for (long long i0 = threadIdx.x; i0 < cnt; i0 += 4ll * blockDim.x) {
+    unsigned long long kk[4];
+    double tt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = min(i0 + (long long)u * blockDim.x, cnt - 1);
+      kk[u] = tmpkey[src + i];
+      tt[u] = tsoft ? tmpt[src + i] : 0.5;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = i0 + (long long)u * blockDim.x;
+      if (i >= cnt) break;
+      const long long row = dst + i;
+      put_row(R, M, row, kk[u], tt[u], key, tsoft, pos, posh, orig, row);
+      if ((row & 15) == 0 || i == 0) blkseg[row >> 4] = r;  // a block shared with a neighbour gets the same tag
+    }
   }
   if (first + cnt == M.V) {  // the ROI's last vertex: pad to V_pad rows with copies of it
     const long long last = M.row_off + M.V - 1;
