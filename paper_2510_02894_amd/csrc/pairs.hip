@@ -567,30 +567,46 @@ __global__ void k_bucket_segs(const int* __restrict__ bgroup, int n_rois, long l
                               const unsigned int* __restrict__ bcnt, const long long* __restrict__ bsz,
                               const long long* __restrict__ brow, const long long* __restrict__ bseg,
                               float* __restrict__ pos, uint4* __restrict__ posh, int* __restrict__ orig,
-                              int* __restrict__ blkseg, Seg* __restrict__ segs) {
-  // one wave per bucket: its lanes tag the blocks and fill the pad rows
+                              int* __restrict__ blkseg, Seg* __restrict__ segs, int per_wave) {
+  // A wave takes per_wave buckets at a time (64 in calls with many buckets,
+  // most of them empty or pruned; else 1), a lane each, and loads their counts
+  // and offsets together; then the whole wave serves each bucket of two or
+  // more vertices in turn: its lanes tag the blocks and fill the pad rows.
   const long long rows0 = totals[T_ROWS0];
   const int lane = threadIdx.x & 63;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long b = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < nb; b += nwaves) {
-    const unsigned int c = bcnt[b];
-    if (c < 2) continue;
-    const long long sid = n_rois + bseg[b];
-    const long long r0 = rows0 + brow[b];
-    const long long n = bsz[b];
-    if (lane == 0) {
-      const int group = bgroup[b];
-      Seg S;
-      S.row_begin = r0;
-      S.n_rows = (int)n;
-      S.group = group;
-      segs[sid] = S;
+  for (long long b0 = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * per_wave; b0 < nb;
+       b0 += nwaves * per_wave) {
+    const long long bl = b0 + lane;
+    const unsigned int cl = lane < per_wave && bl < nb ? bcnt[bl] : 0u;
+    long long sidl = 0, r0l = 0, nl = 0;
+    int groupl = 0, ol = 0;
+    if (cl >= 2u) {
+      sidl = n_rois + bseg[bl];
+      r0l = rows0 + brow[bl];
+      nl = bsz[bl];
+      groupl = bgroup[bl];
+      ol = orig[r0l];
     }
-    for (long long i = lane; i < n / kBlk; i += 64) blkseg[r0 / kBlk + i] = (int)sid;
-    const int o = orig[r0];
-    for (long long row = r0 + c + lane; row < r0 + n; row += 64) {
-      copy_row_operands(pos, posh, r0, row);
-      orig[row] = o;
+    unsigned long long todo = __ballot(cl >= 2u);
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const unsigned int c = (unsigned int)__shfl((int)cl, src, 64);
+      const long long sid = __shfl(sidl, src, 64), r0 = __shfl(r0l, src, 64), n = __shfl(nl, src, 64);
+      const int group = __shfl(groupl, src, 64), o = __shfl(ol, src, 64);
+      if (lane == 0) {
+        Seg S;
+        S.row_begin = r0;
+        S.n_rows = (int)n;
+        S.group = group;
+        segs[sid] = S;
+      }
+      for (long long i = lane; i < n / kBlk; i += 64) blkseg[r0 / kBlk + i] = (int)sid;
+      for (long long row = r0 + c + lane; row < r0 + n; row += 64) {
+        copy_row_operands(pos, posh, r0, row);
+        orig[row] = o;
+      }
     }
   }
 }
@@ -1506,8 +1522,12 @@ hipError_t launch_buckets(const PairBufs& B, hipStream_t st) {
                        B.key, B.totals, B.bcnt, B.bcur, B.brow, B.pos, split_rows(B), B.orig, B.brick_win);
   hipLaunchKernelGGL(k_bucket_groups, dim3((unsigned)B.n_rois), dim3(256), 0, st, B.rois, B.bgroup, B.bcnt,
                      B.pairs2d);
-  hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets)), dim3(256), 0, st, B.bgroup, B.n_rois, B.n_buckets,
-                     B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig, B.blkseg, B.segs);
+  {
+    const int per_wave = B.n_buckets >= kSmallMinBuckets ? 64 : 1;
+    hipLaunchKernelGGL(k_bucket_segs, dim3(grid_for(64 * B.n_buckets / per_wave)), dim3(256), 0, st, B.bgroup,
+                       B.n_rois, B.n_buckets, B.totals, B.bcnt, B.bsz, B.brow, B.bseg, B.pos, split_rows(B), B.orig,
+                       B.blkseg, B.segs, per_wave);
+  }
   hipLaunchKernelGGL(k_seg_cols, dim3(grid_for(std::max(B.seg_cap, B.col_cap))), dim3(256), 0, st, B.n_rois,
                      B.seg_cap, B.totals, B.segs, B.meta, B.ncol, B.tune.jchunk,
                      small_buckets(B) ? kSmallBlocks * 32 : 0, B.nitem, B.col_cap, B.prune ? 1 : 0, B.prune_min_v,
