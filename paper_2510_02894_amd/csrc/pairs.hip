@@ -265,27 +265,55 @@ __global__ __launch_bounds__(256) void k_brick_hist(BrickArgs A, const unsigned 
       }
     }
     __syncthreads();
-    for_brick_keys(key, W, [&](long long, unsigned long long k) {
-      int bi[3], kc[3];
-      vertex_buckets(k, R.d, bi, kc);
+    // Each thread takes four consecutive vertices at a time and merges runs of
+    // equal buckets before its LDS atomics: a brick lists its vertices by
+    // row-group, then plane, so their axis-0 and axis-1 buckets repeat, and
+    // the same-address atomics of a wave's lanes are serialised.  The box only
+    // grows: an atomic that a (possibly stale) read shows cannot change it is
+    // skipped.
+    auto flush = [&](int w, int c, const int* bx) {
+      if (w < 0) return;
+      atomicAdd(&s_win[w], c);
+      if (bbox) {
+        int* q = s_box + 4 * w;
+        if (bx[0] < q[0]) atomicMin(&q[0], bx[0]);
+        if (bx[1] > q[1]) atomicMax(&q[1], bx[1]);
+        if (bx[2] < q[2]) atomicMin(&q[2], bx[2]);
+        if (bx[3] > q[3]) atomicMax(&q[3], bx[3]);
+      }
+    };
+    for (long long b0 = 4ll * tid; b0 < W.n; b0 += 4ll * blockDim.x) {
+      unsigned long long k[4];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        if (bi[j] < 0) continue;
-        const int w = off[j] + bi[j] - s_lo[j];
-        atomicAdd(&s_win[w], 1);
-        if (bbox) {
-          // the box only grows: an atomic that a (possibly stale) read shows
-          // cannot change it is skipped, which spares most vertices the
-          // same-address LDS atomics of a wave's lanes
+      for (int u = 0; u < 4; ++u) k[u] = b0 + u < W.n ? key[W.row0 + b0 + u] : 0ull;
+      int cw[3] = {-1, -1, -1}, cc[3] = {0, 0, 0}, bx[3][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (b0 + u >= W.n) continue;
+        int bi[3], kc[3];
+        vertex_buckets(k[u], R.d, bi, kc);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (bi[j] < 0) continue;
+          const int w = off[j] + bi[j] - s_lo[j];
           const int cu = kc[j == 0 ? 1 : 0], cv = kc[j == 2 ? 1 : 2];
-          int* q = s_box + 4 * w;
-          if (cu < q[0]) atomicMin(&q[0], cu);
-          if (cu > q[1]) atomicMax(&q[1], cu);
-          if (cv < q[2]) atomicMin(&q[2], cv);
-          if (cv > q[3]) atomicMax(&q[3], cv);
+          if (w != cw[j]) {
+            flush(cw[j], cc[j], bx[j]);
+            cw[j] = w;
+            cc[j] = 0;
+            bx[j][0] = bx[j][1] = cu;
+            bx[j][2] = bx[j][3] = cv;
+          }
+          ++cc[j];
+          bx[j][0] = min(bx[j][0], cu);
+          bx[j][1] = max(bx[j][1], cu);
+          bx[j][2] = min(bx[j][2], cv);
+          bx[j][3] = max(bx[j][3], cv);
         }
       }
-    });
+#pragma unroll
+      for (int j = 0; j < 3; ++j) flush(cw[j], cc[j], bx[j]);
+    }
     __syncthreads();
     for (int w = tid; w < total; w += blockDim.x) {
       const int c = s_win[w];
