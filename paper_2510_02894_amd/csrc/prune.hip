@@ -142,21 +142,23 @@ __global__ __launch_bounds__(256) void k_prune_box(const float* __restrict__ pos
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kRowsPerLane);
        base < rows0; base += nwaves * 64 * kRowsPerLane) {
-    const long long r0 = base + (long long)lane * kRowsPerLane;  // this lane's rows (one 32-row block)
+    // four lanes per 32-row block, each taking its rows (lane & 3) + 4 i, so
+    // that a load instruction of the wave reads whole cache lines
+    const long long blk = base + (long long)(lane >> 2) * 32, r0 = blk + (lane & 3);
     RowRoi rr = {0, false};
-    if (r0 < rows0) rr = row_roi(blkseg, meta, r0, min_v);  // uniform per block (rows0 is a multiple of 32)
+    if (blk < rows0) rr = row_roi(blkseg, meta, blk, min_v);  // uniform per block (rows0 is a multiple of 32)
     float box[6] = {3.0e38f, 3.0e38f, 3.0e38f, -3.0e38f, -3.0e38f, -3.0e38f};
     unsigned long long key[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     if (rr.on) {
       const RoiMeta& M = meta[rr.roi];
       const int e = h_scale_exp(M.R2);
-      if (r0 == M.row_off) {
+      if (blk == M.row_off && (lane & 3) == 0) {
         for (int q = 0; q < 3; ++q)
           for (int c = 0; c < 7; ++c) seed[rr.roi].key[q][c] = 0ull;
       }
       float p[kRowsPerLane][3];
 #pragma unroll
-      for (int i = 0; i < kRowsPerLane; ++i) row_pos(pos, posh, r0 + i, e, p[i]);
+      for (int i = 0; i < kRowsPerLane; ++i) row_pos(pos, posh, r0 + 4 * i, e, p[i]);
 #pragma unroll
       for (int i = 0; i < kRowsPerLane; ++i) {
         const float val[7] = {p[i][0], p[i][1], p[i][2], -p[i][0], -p[i][1], -p[i][2],
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(256) void k_prune_box(const float* __restrict__ pos
         }
 #pragma unroll
         for (int c = 0; c < 7; ++c) {
-          const unsigned long long k = vkey(val[c], r0 + i);
+          const unsigned long long k = vkey(val[c], r0 + 4 * i);
           key[c] = k > key[c] ? k : key[c];
         }
       }
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void k_prune_box(const float* __restrict__ pos
 #pragma unroll
     for (int c = 0; c < 7; ++c) key[c] = quad_max_u64(key[c]);
     if (rr.on && (lane & 3) == 0) {
-      BlkRec& R = rec[r0 >> 5];
+      BlkRec& R = rec[blk >> 5];
 #pragma unroll
       for (int c = 0; c < 6; ++c) R.box[c] = box[c];
 #pragma unroll
@@ -370,9 +372,9 @@ __global__ __launch_bounds__(256) void k_prune_far(const float* __restrict__ pos
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long base = (((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kRowsPerLane);
        base < rows0; base += nwaves * 64 * kRowsPerLane) {
-    const long long r0 = base + (long long)lane * kRowsPerLane;
+    const long long blk = base + (long long)(lane >> 2) * 32, r0 = blk + (lane & 3);  // as in k_prune_box
     RowRoi rr = {0, false};
-    if (r0 < rows0) rr = row_roi(blkseg, meta, r0, min_v);
+    if (blk < rows0) rr = row_roi(blkseg, meta, blk, min_v);
     unsigned long long key[7] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     if (rr.on) {
       const int e = h_scale_exp(meta[rr.roi].R2);
@@ -381,13 +383,13 @@ __global__ __launch_bounds__(256) void k_prune_far(const float* __restrict__ pos
       for (int c = 0; c < 7; ++c) row_pos(pos, posh, key_row(seed[rr.roi].key[src][c]), e, q[c]);
       float p[kRowsPerLane][3];
 #pragma unroll
-      for (int i = 0; i < kRowsPerLane; ++i) row_pos(pos, posh, r0 + i, e, p[i]);
+      for (int i = 0; i < kRowsPerLane; ++i) row_pos(pos, posh, r0 + 4 * i, e, p[i]);
 #pragma unroll
       for (int i = 0; i < kRowsPerLane; ++i)
 #pragma unroll
         for (int c = 0; c < 7; ++c) {
           const float dx = p[i][0] - q[c][0], dy = p[i][1] - q[c][1], dz = p[i][2] - q[c][2];
-          const unsigned long long k = vkey(dx * dx + dy * dy + dz * dz, r0 + i);
+          const unsigned long long k = vkey(dx * dx + dy * dy + dz * dz, r0 + 4 * i);
           key[c] = k > key[c] ? k : key[c];
         }
     }
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(256) void k_prune_far(const float* __restrict__ pos
     for (int c = 0; c < 7; ++c) key[c] = quad_max_u64(key[c]);
     if (rr.on && (lane & 3) == 0) {
 #pragma unroll
-      for (int c = 0; c < 7; ++c) rec[r0 >> 5].key[c] = key[c];
+      for (int c = 0; c < 7; ++c) rec[blk >> 5].key[c] = key[c];
     }
   }
 }
