@@ -1345,11 +1345,14 @@ __global__ __launch_bounds__(256) void k_exact(const int* __restrict__ cand, con
 // Also clears the candidate counter, the pair-pass work counters and the row
 // maxima of every row the layouts can hold (one launch before the pair pass).
 __global__ void k_init_groups(GroupRes* gres, long long n, unsigned int* counters, unsigned int* rowmax_bits,
-                              long long n_rows) {
+                              long long n_rows, const long long* __restrict__ totals) {
   if (blockIdx.x == 0) {
     for (int i = kWorkStride + threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0u;
     if (threadIdx.x == 0) counters[1] = 0u;
   }
+  // only the rows laid out by this call (layout 0 and the plane buckets) are
+  // written by the pair passes and read after them
+  n_rows = min(n_rows, totals[T_ROWS0] + totals[T_ROWS2D]);
   for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += (long long)gridDim.x * blockDim.x)
     rowmax_bits[r] = 0u;
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (long long)gridDim.x * blockDim.x) {
@@ -1633,7 +1636,7 @@ hipError_t launch_pair_maxima(const PairBufs& B, hipStream_t st) {
 
 hipError_t launch_init_groups(const PairBufs& B, hipStream_t st) {
   hipLaunchKernelGGL(k_init_groups, dim3(grid_for(std::max<long long>(4ll * B.n_rois, B.rows_bound), 4096)), dim3(256), 0,
-                     st, B.gres, 4ll * B.n_rois, B.counters, (unsigned int*)B.rowmax, B.rows_bound);
+                     st, B.gres, 4ll * B.n_rois, B.counters, (unsigned int*)B.rowmax, B.rows_bound, B.totals);
   return hipGetLastError();
 }
 
